@@ -1,0 +1,236 @@
+"""Seeded synthetic inputs for the latent-GP RMHMC workloads.
+
+This module only *draws inputs*: covariates, labels, the hyperparameter
+layout of each model, momentum normals and Metropolis uniforms.  It holds
+none of the sampler's arithmetic (no Hessian, metric, integrator or chain
+code).  The one piece of kernel arithmetic here is the GP prior draw of the
+synthetic ground-truth function, which is part of the data recipe: the
+Gram matrix is written out directly below for that purpose only.
+
+Both the GPU path and the FP64 reference use these generators, so the two
+always see bit-identical inputs.
+
+Model conventions (the paper's experiments use a reduced-rank basis model;
+these workloads sample the latent GP values f at the N inputs instead, the
+parameterisation the paper's Discussion attributes to earlier work):
+
+* q = (f_1..f_N, eta_1..eta_P); f first, then the log-hyperparameters.
+* K(eta) = sum of kernel terms + jitter * I (jitter fixed, not sampled).
+* Kernel terms (parameters are consumed in term order):
+    SE_ISO(cols):      s^2 exp(-|x-x'|^2 / (2 l^2)),    eta = (log s, log l)
+    SE_ARD(cols):      s^2 exp(-sum_d r_d^2/(2 l_d^2)), eta = (log s, log l_d...)
+    LINEAR_ARD(cols):  sum_d v_d x_d x'_d,              eta = (log v_d...)
+    BINARY_SAME(col):  s^2 [x_c == x'_c],               eta = (log s,)
+* Priors: eta ~ N(0, I); f | eta ~ N(0, K(eta)).
+* Likelihood: Bernoulli-logit (y in {0,1}) scaled by an inverse temperature
+  beta (power posterior), or Gaussian with known noise variance (tests only).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+SE_ISO = 0
+SE_ARD = 1
+LINEAR_ARD = 2
+BINARY_SAME = 3
+
+LIK_BERNOULLI_LOGIT = 0
+LIK_GAUSSIAN = 1
+
+KIND_NAMES = {SE_ISO: "se_iso", SE_ARD: "se_ard", LINEAR_ARD: "linear_ard",
+              BINARY_SAME: "binary_same"}
+
+
+def term_nparams(kind: int, cols: Sequence[int]) -> int:
+    if kind == SE_ISO:
+        return 2
+    if kind == SE_ARD:
+        return 1 + len(cols)
+    if kind == LINEAR_ARD:
+        return len(cols)
+    if kind == BINARY_SAME:
+        if len(cols) != 1:
+            raise ValueError("BINARY_SAME takes exactly one column")
+        return 1
+    raise ValueError(f"unknown kernel kind {kind}")
+
+
+@dataclasses.dataclass
+class ModelSpec:
+    """Plain description of one latent-GP model (host arrays, FP64)."""
+    X: np.ndarray                     # N x dx covariates
+    y: np.ndarray                     # N labels ({0,1}) or targets (Gaussian)
+    terms: List[Tuple[int, Tuple[int, ...]]]
+    lik: int = LIK_BERNOULLI_LOGIT
+    noise_var: float = 1.0            # Gaussian likelihood only
+    jitter: float = 1e-6
+    beta: float = 1.0                 # inverse temperature on the likelihood
+
+    def __post_init__(self):
+        self.X = np.ascontiguousarray(np.asarray(self.X, dtype=np.float64))
+        if self.X.ndim != 2:
+            raise ValueError("X must be N x dx")
+        self.y = np.ascontiguousarray(np.asarray(self.y, dtype=np.float64))
+        self.terms = [(int(k), tuple(int(c) for c in cols)) for k, cols in self.terms]
+        for k, cols in self.terms:
+            term_nparams(k, cols)
+            for c in cols:
+                if not 0 <= c < self.X.shape[1]:
+                    raise ValueError("kernel column out of range")
+
+    @property
+    def N(self) -> int:
+        return self.X.shape[0]
+
+    @property
+    def dx(self) -> int:
+        return self.X.shape[1]
+
+    @property
+    def P(self) -> int:
+        return sum(term_nparams(k, c) for k, c in self.terms)
+
+    @property
+    def D(self) -> int:
+        return self.N + self.P
+
+
+def _gram_for_data(X, terms, eta, jitter):
+    """Kernel Gram matrix used only to draw the synthetic ground truth."""
+    N = X.shape[0]
+    K = np.zeros((N, N))
+    i = 0
+    for kind, cols in terms:
+        if kind in (SE_ISO, SE_ARD):
+            s = math.exp(eta[i])
+            r2 = np.zeros((N, N))
+            for j, c in enumerate(cols):
+                ell = math.exp(eta[i + 1] if kind == SE_ISO else eta[i + 1 + j])
+                r2 += (X[:, c, None] - X[None, :, c]) ** 2 / ell ** 2
+            K += s * s * np.exp(-0.5 * r2)
+        elif kind == LINEAR_ARD:
+            for j, c in enumerate(cols):
+                K += math.exp(eta[i + j]) * np.outer(X[:, c], X[:, c])
+        elif kind == BINARY_SAME:
+            c = cols[0]
+            K += math.exp(2 * eta[i]) * (X[:, c, None] == X[None, :, c])
+        i += term_nparams(kind, cols)
+    return K + jitter * np.eye(N)
+
+
+def _finish(rng, X, terms, jitter=1e-6, beta=1.0):
+    """Draw eta_true ~ N(0, I), f_true ~ GP, labels ~ Bernoulli(sigmoid(f))."""
+    P = sum(term_nparams(k, c) for k, c in terms)
+    eta_true = rng.standard_normal(P)
+    L = np.linalg.cholesky(_gram_for_data(X, terms, eta_true, jitter))
+    f_true = L @ rng.standard_normal(X.shape[0])
+    y = (rng.uniform(size=X.shape[0]) < 1.0 / (1.0 + np.exp(-f_true))).astype(np.float64)
+    spec = ModelSpec(X=X, y=y, terms=list(terms), jitter=jitter, beta=beta)
+    return spec, eta_true, f_true
+
+
+def gp_logistic_2d(N: int, seed: int = 0, beta: float = 1.0):
+    """GP classification on 2-D inputs x ~ U[-1,1]^2 with an isotropic SE kernel."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1.0, 1.0, size=(N, 2))
+    return _finish(rng, X, [(SE_ISO, (0, 1))], beta=beta)
+
+
+def gp_logistic_ard4(N: int = 256, seed: int = 0):
+    """GP classification on 4-D inputs x ~ N(0, I) with an SE-ARD kernel."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((N, 4))
+    return _finish(rng, X, [(SE_ARD, (0, 1, 2, 3))])
+
+
+def propensity_mkl(N: int = 1024, seed: int = 0):
+    """Binary-treatment propensity model with a multiple-kernel sum.
+
+    8 covariates: 5 continuous N(0,1) and 3 binary Bernoulli(0.3).  Kernel =
+    SE-ARD(5 continuous) + linear-ARD(5 continuous) + one same-value kernel per
+    binary covariate: 6 + 5 + 3 = 14 hyperparameters.  Synthetic stand-in for
+    the shape of the paper's medical-expenditure propensity analysis.
+    """
+    rng = np.random.default_rng(seed)
+    Xc = rng.standard_normal((N, 5))
+    Xb = (rng.uniform(size=(N, 3)) < 0.3).astype(np.float64)
+    X = np.concatenate([Xc, Xb], axis=1)
+    terms = [(SE_ARD, (0, 1, 2, 3, 4)), (LINEAR_ARD, (0, 1, 2, 3, 4)),
+             (BINARY_SAME, (5,)), (BINARY_SAME, (6,)), (BINARY_SAME, (7,))]
+    return _finish(rng, X, terms)
+
+
+def gaussian_gp(N: int, noise_var: float = 0.1, seed: int = 0):
+    """GP regression with a Gaussian likelihood (test target)."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1.0, 1.0, size=(N, 2))
+    terms = [(SE_ISO, (0, 1))]
+    P = 2
+    eta_true = rng.standard_normal(P)
+    L = np.linalg.cholesky(_gram_for_data(X, terms, eta_true, 1e-6))
+    f_true = L @ rng.standard_normal(N)
+    y = f_true + math.sqrt(noise_var) * rng.standard_normal(N)
+    spec = ModelSpec(X=X, y=y, terms=terms, lik=LIK_GAUSSIAN, noise_var=noise_var)
+    return spec, eta_true, f_true
+
+
+@dataclasses.dataclass
+class ChainSettings:
+    eps: float
+    n_leapfrog: int       # C
+    n_fixed_point: int    # K
+    n_samples: int        # kept moves
+    n_burnin: int         # A0
+    alpha: float = 1e6
+
+    @property
+    def n_moves(self) -> int:
+        return self.n_samples + self.n_burnin
+
+
+def chain_randoms(D: int, n_moves: int, seed: int = 0, stream: int = 0):
+    """Momentum normals z (n_moves x D) and MH uniforms u in (0,1) (n_moves)."""
+    rng = np.random.default_rng([seed, stream, 0x524D48])
+    z = rng.standard_normal((n_moves, D))
+    u = rng.uniform(size=n_moves)
+    u = np.where(u <= 0.0, np.nextafter(0.0, 1.0), u)
+    return z, u
+
+
+# Named workloads ------------------------------------------------------------
+
+def workload(name: str, seed: int = 0):
+    """Return (spec, settings) for a named workload."""
+    if name == "gp_logistic_d34":
+        spec, _, _ = gp_logistic_2d(32, seed)
+        return spec, ChainSettings(eps=0.1, n_leapfrog=10, n_fixed_point=6,
+                                   n_samples=200, n_burnin=67)
+    if name == "gp_logistic_ard_d261":
+        spec, _, _ = gp_logistic_ard4(256, seed)
+        return spec, ChainSettings(eps=0.05, n_leapfrog=20, n_fixed_point=6,
+                                   n_samples=1000, n_burnin=334)
+    if name == "propensity_mkl_d1038":
+        spec, _, _ = propensity_mkl(1024, seed)
+        return spec, ChainSettings(eps=0.05, n_leapfrog=20, n_fixed_point=6,
+                                   n_samples=200, n_burnin=67)
+    raise KeyError(name)
+
+
+def tempered_ladder(n_chains: int = 64, seed: int = 0):
+    """Tempered chains for evidence estimation: beta_k = (k/(n-1))^5 and a
+    chain dimension drawn uniformly from {66,130,258,514} (one dataset per D)."""
+    rng = np.random.default_rng(seed)
+    dims = rng.choice(np.array([66, 130, 258, 514]), size=n_chains)
+    betas = (np.arange(n_chains) / (n_chains - 1)) ** 5
+    data = {}
+    for D in sorted(set(int(d) for d in dims)):
+        data[D], _, _ = gp_logistic_2d(D - 2, seed)
+    specs = []
+    for k in range(n_chains):
+        base = data[int(dims[k])]
+        specs.append(dataclasses.replace(base, beta=float(betas[k])))
+    return specs, dims, betas

@@ -1,0 +1,203 @@
+"""Pins of the reference Hamiltonian gradient (Eq. d_Hamiltonian, sign as
+derived from Eq. Hamiltonian), the generalized leapfrog (Eq. leapfrog) and the
+chain (Algorithm 1)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2511_06407_amd import workloads as wl
+from oracle import model, softabs
+from oracle import hamiltonian as ham
+from oracle.integrator import glf_step, trajectory
+from oracle.chain import run_chain, momentum
+from tests.targets import Quadratic, Quartic
+
+
+def gp_target(N=6, seed=3, jitter=1e-2):
+    spec, _, _ = wl.gp_logistic_2d(N, seed)
+    return ham.GPTarget(dataclasses.replace(spec, jitter=jitter))
+
+
+def richardson_grad(fun, x, h):
+    E = np.eye(x.size)
+
+    def cd(hh):
+        return np.array([(fun(x + hh * E[i]) - fun(x - hh * E[i])) / (2 * hh) for i in range(x.size)])
+    return (4 * cd(h / 2) - cd(h)) / 3
+
+
+@pytest.mark.parametrize("alpha", [1e6, 3.0])
+def test_dHdq_matches_finite_differences(alpha):
+    T = gp_target()
+    rng = np.random.default_rng(2)
+    q = 0.4 * rng.standard_normal(T.D)
+    p = rng.standard_normal(T.D)
+    st = ham.State(T, q, alpha)
+    assert np.any(st.eig["lam"] < 0)          # indefinite Hessian on purpose
+    got = ham.grad_q(st, p)
+    fd = richardson_grad(lambda z: ham.hamiltonian(ham.State(T, z, alpha), p), q, 1e-3)
+    assert np.linalg.norm(got - fd) / np.linalg.norm(fd) < 1e-8
+    # the printed sign of the two metric terms does not match the derivative
+    W1, W2, _, _ = softabs.w_matrices(st.eig, p, alpha)
+    flipped = st.grad - 0.5 * T.contract(q, W2) + 0.5 * T.contract(q, W1)
+    assert np.linalg.norm(flipped - fd) / np.linalg.norm(fd) > 1e-3
+
+
+def test_dHdp_matches_finite_differences():
+    T = gp_target()
+    rng = np.random.default_rng(3)
+    q = 0.3 * rng.standard_normal(T.D)
+    p = rng.standard_normal(T.D)
+    st = ham.State(T, q, 1e6)
+    fd = richardson_grad(lambda z: ham.hamiltonian(st, z), p, 1e-3)
+    assert np.allclose(ham.grad_p(st, p), fd, rtol=1e-8, atol=1e-10)
+
+
+def test_brute_force_per_coordinate_traces():
+    """D <= 8: form dH/dq_i for every i by complex step of the Hessian, then
+    tr(G^-1 dG_i) and p'G^-1 dG_i G^-1 p from their definitions with the
+    per-coordinate Psi' dH_i Psi (no W caching, no structured contraction)."""
+    T = gp_target(N=5, seed=7)
+    D = T.D
+    assert D <= 8
+    alpha = 50.0
+    rng = np.random.default_rng(4)
+    q = 0.5 * rng.standard_normal(D)
+    p = rng.standard_normal(D)
+    st = ham.State(T, q, alpha)
+    Psi, lam, g = st.eig["Psi"], st.eig["lam"], st.eig["g"]
+    Tm = softabs.divided_differences(lam, alpha)
+    Gi = (Psi / g) @ Psi.T
+    tr1 = np.empty(D)
+    tr2 = np.empty(D)
+    E = np.eye(D)
+    for i in range(D):
+        dH = np.imag(model.hessian(T.spec, q + 1j * 1e-30 * E[i])[2]) / 1e-30
+        dG = Psi @ (Tm * (Psi.T @ dH @ Psi)) @ Psi.T
+        tr2[i] = np.trace(Gi @ dG)
+        tr1[i] = p @ Gi @ dG @ Gi @ p
+    W1, W2, _, _ = softabs.w_matrices(st.eig, p, alpha)
+    assert np.allclose(T.contract(q, W2), tr2, rtol=1e-10, atol=1e-12)
+    assert np.allclose(T.contract(q, W1), tr1, rtol=1e-10, atol=1e-12)
+
+
+def test_constant_metric_is_textbook_leapfrog():
+    rng = np.random.default_rng(6)
+    M = rng.standard_normal((5, 5))
+    A = M @ M.T + 5 * np.eye(5)
+    T = Quadratic(A)
+    q = rng.standard_normal(5)
+    p = rng.standard_normal(5)
+    eps = 0.2
+    st, pn = glf_step(ham.State(T, q, 1e6), p, eps, 6)
+    ph = p - eps / 2 * A @ q
+    qn = q + eps * np.linalg.solve(A, ph)
+    pw = ph - eps / 2 * A @ qn
+    assert np.allclose(st.q, qn, rtol=1e-13, atol=1e-13)
+    assert np.allclose(pn, pw, rtol=1e-13, atol=1e-13)
+
+
+def test_harmonic_oscillator_closed_form():
+    """U = q'Aq/2 with G = A: every mode obeys x'' = -x, and n leapfrogs of step
+    e give q_n = cos(n th) q_0 + sin(n th)/s A^-1 p_0 with cos th = 1 - e^2/2,
+    s = sqrt(1 - e^2/4)."""
+    rng = np.random.default_rng(7)
+    M = rng.standard_normal((4, 4))
+    A = M @ M.T + 2 * np.eye(4)
+    T = Quadratic(A)
+    q0 = rng.standard_normal(4)
+    p0 = rng.standard_normal(4)
+    eps, n = 0.3, 17
+    st, pn = trajectory(ham.State(T, q0, 1e6), p0, eps, n, 3)
+    th = np.arccos(1 - eps ** 2 / 2)
+    s = np.sqrt(1 - eps ** 2 / 4)
+    v0 = np.linalg.solve(A, p0)
+    want = np.cos(n * th) * q0 + np.sin(n * th) / s * v0
+    assert np.allclose(st.q, want, rtol=1e-12, atol=1e-12)
+
+
+def test_reversibility_gp():
+    T = gp_target(N=6, seed=8)
+    rng = np.random.default_rng(8)
+    q = 0.3 * rng.standard_normal(T.D)
+    st0 = ham.State(T, q, 1e6)
+    p0 = momentum(st0, rng.standard_normal(T.D))       # p ~ N(0, G(q))
+    st1, p1 = trajectory(st0, p0, 0.02, 5, 12)
+    assert np.linalg.norm(st1.q - q) > 0.1                  # it did move
+    st2, p2 = trajectory(st1, -p1, 0.02, 5, 12)
+    assert np.linalg.norm(st2.q - q) < 1e-11 * max(1, np.linalg.norm(q))
+    assert np.linalg.norm(p2 + p0) < 1e-11 * np.linalg.norm(p0)
+
+
+def test_energy_error_is_second_order():
+    T = gp_target(N=6, seed=9)
+    rng = np.random.default_rng(9)
+    q = 0.3 * rng.standard_normal(T.D)
+    st = ham.State(T, q, 1e6)
+    p = momentum(st, rng.standard_normal(T.D))
+    h0 = ham.hamiltonian(st, p)
+    errs = []
+    for eps, n in ((0.02, 4), (0.01, 8), (0.005, 16)):
+        s1, p1 = trajectory(st, p, eps, n, 12)
+        errs.append(abs(ham.hamiltonian(s1, p1) - h0))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.0 < r1 < 5.5 and 3.0 < r2 < 5.5, errs
+
+
+def test_volume_preservation_2d():
+    """det of the finite-difference Jacobian of one generalized leapfrog is 1
+    (indefinite quartic target, D = 2)."""
+    T = Quartic(2, c4=1.0, c2=-0.5)
+    q0 = np.array([0.3, -0.8])
+    p0 = np.array([0.4, 0.1])
+    eps, K = 0.05, 30
+
+    def step(z):
+        st, pn = glf_step(ham.State(T, z[:2], 5.0), z[2:], eps, K)
+        return np.concatenate([st.q, pn])
+    z0 = np.concatenate([q0, p0])
+    J = np.empty((4, 4))
+    h = 1e-6
+    for i in range(4):
+        e = np.zeros(4)
+        e[i] = h
+        J[:, i] = (step(z0 + e) - step(z0 - e)) / (2 * h)
+    assert abs(np.linalg.det(J) - 1.0) < 1e-7
+
+
+def test_chain_gaussian_moments():
+    """Correlated 3-D Gaussian target: sample mean and covariance agree with
+    the exact moments within Monte Carlo error."""
+    rng = np.random.default_rng(10)
+    M = rng.standard_normal((3, 3))
+    Sigma = M @ M.T + 0.5 * np.eye(3)
+    mu = np.array([1.0, -2.0, 0.5])
+    T = Quadratic(np.linalg.inv(Sigma), mu)
+    n = 3000
+    z = rng.standard_normal((n, 3))
+    u = rng.uniform(size=n)
+    samples, logpost, acc, h0, h1 = run_chain(T, np.zeros(3), 0.35, 4, 2, 1e6, z, u)
+    xs = samples[300:]
+    se = np.sqrt(np.diag(Sigma) / xs.shape[0]) * 3.0    # generous: ESS/n >= ~0.1
+    assert np.all(np.abs(xs.mean(0) - mu) < 5 * se)
+    C = np.cov(xs.T)
+    assert np.allclose(C, Sigma, rtol=0.15, atol=0.15 * np.max(np.diag(Sigma)))
+    assert acc.mean() > 0.8
+
+
+def test_chain_mh_rule_and_restore():
+    T = gp_target(N=5, seed=11)
+    rng = np.random.default_rng(11)
+    n = 6
+    z = rng.standard_normal((n, T.D))
+    u = rng.uniform(size=n)
+    u[2] = 1.0 - 1e-16            # forces a rejection unless H drops
+    q0 = np.zeros(T.D)
+    samples, logpost, acc, h0, h1 = run_chain(T, q0, 0.3, 3, 4, 1e6, z, u)
+    prev = q0
+    for ell in range(n):
+        assert bool(acc[ell]) == bool(np.log(u[ell]) < h0[ell] - h1[ell])
+        if not acc[ell]:
+            assert np.array_equal(samples[ell], prev)
+        prev = samples[ell]

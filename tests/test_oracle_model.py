@@ -1,0 +1,116 @@
+"""Pins of the reference U, grad U, H and v(W) = grad tr(W H) by the complex-step
+derivative (Squire & Trapp 1998), which is exact to rounding for analytic code.
+
+Models: every kernel kind (isotropic SE, SE-ARD, linear-ARD, same-value binary),
+both likelihoods, a tempered likelihood (beta != 1) and random points q.
+Jitter 1e-2 keeps K well conditioned so the bar can be near machine precision.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2511_06407_amd import workloads as wl
+from oracle import model
+
+H_CS = 1e-30
+
+
+def small_models():
+    a, _, _ = wl.gp_logistic_2d(10, seed=1)
+    b, _, _ = wl.gp_logistic_ard4(9, seed=2)
+    c, _, _ = wl.propensity_mkl(12, seed=3)
+    d, _, _ = wl.gaussian_gp(8, noise_var=0.3, seed=4)
+    out = []
+    for s, beta in ((a, 0.7), (b, 1.0), (c, 0.35), (d, 1.0)):
+        out.append(dataclasses.replace(s, jitter=1e-2, beta=beta))
+    return out
+
+
+MODELS = small_models()
+
+
+def rand_q(spec, seed):
+    rng = np.random.default_rng(seed)
+    q = 0.6 * rng.standard_normal(spec.D)
+    return q
+
+
+def cs_jacobian(fun, q):
+    E = np.eye(q.size)
+    return np.array([np.imag(fun(q + 1j * H_CS * E[i])) / H_CS for i in range(q.size)])
+
+
+@pytest.mark.parametrize("k", range(len(MODELS)))
+def test_kernel_derivatives_complex_step(k):
+    spec = MODELS[k]
+    eta = rand_q(spec, 10 + k)[spec.N:]
+    kd = model.KernelDerivs(spec, eta)
+    P = spec.P
+    E = np.eye(P)
+    for l in range(P):
+        want = np.imag(model.gram(spec, eta + 1j * H_CS * E[l])) / H_CS
+        got = kd.d((l,))
+        assert np.allclose(got, want, rtol=1e-13, atol=1e-14)
+        for m in range(P):
+            kd_c = model.KernelDerivs(spec, eta + 1j * H_CS * E[m])
+            d1 = kd_c.d((l,))
+            want2 = np.zeros_like(got) if d1 is None else np.imag(d1) / H_CS
+            got2 = kd.d((l, m))
+            got2 = np.zeros_like(want2) if got2 is None else got2
+            assert np.allclose(got2, want2, rtol=1e-13, atol=1e-14)
+            for n in range(P):
+                d2 = kd_c.d((l, n))
+                want3 = np.zeros_like(got) if d2 is None else np.imag(d2) / H_CS
+                got3 = kd.d((l, n, m))
+                got3 = np.zeros_like(want3) if got3 is None else got3
+                assert np.allclose(got3, want3, rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("k", range(len(MODELS)))
+def test_gradient_complex_step(k):
+    spec = MODELS[k]
+    q = rand_q(spec, k)
+    g = model.gradient(spec, q)
+    want = cs_jacobian(lambda z: model.neg_log_post(spec, z), q)
+    assert np.linalg.norm(g - want) / np.linalg.norm(want) < 1e-13
+    U, g2, _ = model.hessian(spec, q)
+    assert abs(U - model.neg_log_post(spec, q)) < 1e-12 * max(1.0, abs(U))
+    assert np.allclose(g2, g, rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("k", range(len(MODELS)))
+def test_hessian_complex_step(k):
+    spec = MODELS[k]
+    q = rand_q(spec, 20 + k)
+    H = model.hessian(spec, q)[2]
+    want = cs_jacobian(lambda z: model.gradient(spec, z), q)
+    assert np.linalg.norm(H - want) / np.linalg.norm(want) < 1e-13
+    assert np.array_equal(H, H.T)
+
+
+@pytest.mark.parametrize("k", range(len(MODELS)))
+def test_contraction_complex_step(k):
+    spec = MODELS[k]
+    q = rand_q(spec, 30 + k)
+    rng = np.random.default_rng(40 + k)
+    W = rng.standard_normal((spec.D, spec.D))
+    W = W + W.T
+    v = model.contract(spec, q, W)
+    want = cs_jacobian(lambda z: np.sum(W * model.hessian(spec, z)[2]), q)
+    assert np.linalg.norm(v - want) / np.linalg.norm(want) < 1e-12
+
+
+def test_gaussian_likelihood_fixed_eta_textbook():
+    """With a Gaussian likelihood the f-block of H is K^-1 + I/s2 and the
+    f-gradient vanishes at the textbook posterior mean K (K + s2 I)^-1 y
+    (Rasmussen & Williams, Sec. 2.2)."""
+    spec = MODELS[3]
+    eta = np.array([0.2, -0.3])
+    K = model.gram(spec, eta)
+    s2 = spec.noise_var
+    mean = K @ np.linalg.solve(K + s2 * np.eye(spec.N), spec.y)
+    q = np.concatenate([mean, eta])
+    U, g, H = model.hessian(spec, q)
+    assert np.max(np.abs(g[:spec.N])) < 1e-10
+    assert np.allclose(H[:spec.N, :spec.N], np.linalg.inv(K) + np.eye(spec.N) / s2, rtol=1e-12)
