@@ -1,0 +1,185 @@
+"""Benchmark: generalized-leapfrog throughput of softabs RMHMC at D = 1038.
+
+One step = one generalized leapfrog (Eq. leapfrog of the paper) on the
+device-resident state: K Hessian assemblies and warm-started Jacobi
+eigendecompositions for the implicit position update, the per-point
+contraction precompute at the new point, and K + 2 structured
+third-derivative contractions for the two momentum half steps.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+Prints one JSON line.  Only one GPU is used; --gpus above 1 is refused.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f64_tflops": 78.6, "f32_tflops": 157.3, "hbm_gbs": 8000.0}
+# FP64 MFMA GEMMs carry the bulk of the algorithmic flops of a leapfrog at
+# this size (A_l = K^-1 K_l, B_l = A_l K^-1, Y_lm = A_l A_m, Psi products)
+DOMINANT = "gemm_f64"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="propensity_mkl_d1038")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true",
+                    help="skip the per-kernel event timing (use under a profiler)")
+    ap.add_argument("--ess-moves", type=int, default=0,
+                    help="also run a chain of this many moves and report ESS/s")
+    return ap.parse_args()
+
+
+def file_hash(*paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_src_hash):
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    summary, only if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "gemm_f64_propensity_mkl_d1038_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_src_hash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(spec, cfg):
+    """The FP64 reference timed on the host cores on a bounded sample: one
+    metric evaluation at a point (Hessian + eigendecomposition) and one
+    third-derivative contraction, scaled to a leapfrog
+    (K evaluations + (K + 2) contractions)."""
+    import numpy as np
+    from oracle import hamiltonian as oham
+    from oracle.chain import momentum
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    T = oham.GPTarget(spec)
+    q = np.zeros(spec.D)
+    t0 = time.perf_counter()
+    st = oham.State(T, q, cfg.alpha)
+    t1 = time.perf_counter()
+    p = momentum(st, np.random.default_rng(0).standard_normal(spec.D))
+    st.v_w2()
+    t2 = time.perf_counter()
+    K = cfg.n_fixed_point
+    per_leapfrog = K * (t1 - t0) + (K + 2) * (t2 - t1)
+    return {"value": 1.0 / per_leapfrog, "unit": "leapfrog steps/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": (f"1 Hessian+eigh ({t1 - t0:.2f} s) and 1 contraction ({t2 - t1:.2f} s) "
+                       f"at q=0 of {spec.D}-dim workload, scaled to K={K} evaluations + "
+                       f"{K + 2} contractions per leapfrog"),
+            "seconds": t2 - t0}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py: this build runs on one GPU only; --gpus above 1 is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2511_06407_amd import rmhmc, workloads as wl
+
+    spec, cfg = wl.workload(args.workload, args.seed)
+    model = rmhmc.Model(spec)
+    dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")  # noqa
+    z, u = wl.chain_randoms(spec.D, max(args.ess_moves, 1) + 1, seed=args.seed)
+    q0 = np.zeros(spec.D)
+    S = rmhmc.State(model, dev(q0), dev(np.zeros(spec.D)), cfg.alpha)
+    S.draw_momentum(dev(z[0]))
+    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)  # noqa: E731
+    log(f"state ready D={spec.D}")
+    for k in range(args.warmup):
+        S.step(cfg.eps, cfg.n_fixed_point)
+        torch.cuda.synchronize()
+        log(f"warmup step {k} done")
+
+    if not args.no_timing:
+        rmhmc.timing_enable((DOMINANT,))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        S.step(cfg.eps, cfg.n_fixed_point)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log(f"timed {args.steps} steps in {t1 - t0:.3f} s")
+    elapsed = t1 - t0
+    value = args.steps / elapsed
+
+    roofline = None
+    if not args.no_timing:
+        n, ms, flops, byts = rmhmc.timing_read(DOMINANT)
+        rmhmc.timing_enable(())
+        if n > 0 and ms > 0:
+            achieved = flops / (ms * 1e-3) / 1e12
+            src_hash = file_hash("paper_2511_06407_amd/csrc/gemm.hip")
+            roofline = {"bound": "mfma", "kernel": "gemm_kernel<double> (v_mfma_f64_16x16x4f64)",
+                        "achieved": round(achieved, 3), "peak": PEAK["f64_tflops"],
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64_tflops"], 4),
+                        "traffic": traffic_from_profile(src_hash),
+                        "launches": n, "avg_launch_us": round(ms * 1e3 / n, 2),
+                        "algorithmic_flops_per_launch": flops / n,
+                        "kernel_time_share": round(ms * 1e-3 / elapsed, 3)}
+
+    ess_block = None
+    if args.ess_moves > 0:
+        from paper_2511_06407_amd.analysis import ess_summary
+        nm = args.ess_moves
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        samples, logpost, acc, stats = model.chain(dev(q0), dev(z[:nm]), dev(u[:nm]), cfg.eps,
+                                                   cfg.n_leapfrog, cfg.n_fixed_point, cfg.alpha)
+        torch.cuda.synchronize()
+        c1 = time.perf_counter()
+        burn = nm // 4
+        es = ess_summary(samples.cpu().numpy()[burn:], logpost.cpu().numpy()[burn:])
+        kept_time = (c1 - c0) * (nm - burn) / nm
+        ess_block = {"moves": nm, "burn_in": burn, "accept_rate": float(acc.float().mean()),
+                     "ess_min": es["min"], "ess_median": es["median"], "ess_logpost": es["logpost"],
+                     "ess_min_per_sec": es["min"] / kept_time,
+                     "ess_logpost_per_sec": es["logpost"] / kept_time,
+                     "chain_leapfrogs_per_sec": stats.leapfrogs / (c1 - c0)}
+
+    out = {"metric": "leapfrog steps/sec + ESS/sec at D=1036; p50/p99 request latency",
+           "value": value, "unit": "leapfrog steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": args.workload, "D": spec.D, "N": spec.N, "P": spec.P,
+                      "eps": cfg.eps, "n_fixed_point": cfg.n_fixed_point, "alpha": cfg.alpha,
+                      "precision": "fp64", "parallelism": "single GPU"},
+           "roofline": roofline}
+    if ess_block is not None:
+        out["ess"] = ess_block
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,216 @@
+/*
+ * rmhmc.h -- C ABI of librmhmc.so: softabs Riemannian-manifold HMC for
+ * latent Gaussian-process models on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Hayakawa & Asai, "Fast Riemannian-manifold Hamiltonian Monte
+ * Carlo for hierarchical Gaussian-process models" (arXiv 2511.06407).
+ * Each entry point names the passage of the paper that defines what it
+ * computes.
+ *
+ * Conventions shared by every call
+ *   - Parameter vector q = (f_1..f_N, eta_1..eta_P), D = N + P: latent GP
+ *     values first, then log-hyperparameters in kernel-term order.
+ *   - Matrices are column-major FP64 with a leading dimension >= rows.
+ *   - Pointers marked [device] must be device memory on the current HIP
+ *     device (e.g. torch.Tensor.data_ptr() of a CUDA tensor); [host] marks
+ *     host memory.  The caller owns every array it passes; the library owns
+ *     rmhmc_model and rmhmc_state and everything they hold.
+ *   - Calls are asynchronous on the given stream unless they return a value
+ *     through a [host] pointer or say otherwise; those synchronise the
+ *     stream before returning.
+ *   - Errors: every call returns an rmhmc_status; nothing throws across the
+ *     ABI.  Argument errors are found on the host before any launch.  After
+ *     a non-OK status, rmhmc_last_error() gives a message (thread-local) and
+ *     the contents of output arrays are undefined.
+ */
+#ifndef RMHMC_H
+#define RMHMC_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RMHMC_OK = 0,
+  RMHMC_E_ARG = -1,        /* invalid argument (detected on the host)        */
+  RMHMC_E_NOT_PD = -2,     /* kernel matrix K not positive definite          */
+  RMHMC_E_EIG_NOCONV = -3, /* Jacobi sweeps exhausted before tolerance       */
+  RMHMC_E_NONFINITE = -4,  /* NaN/Inf in an input or a computed quantity     */
+  RMHMC_E_NOMEM = -5,      /* device allocation failed (create calls only)  */
+  RMHMC_E_HIP = -6         /* a HIP runtime call failed                      */
+} rmhmc_status;
+
+typedef enum { RMHMC_FP64 = 0, RMHMC_MIXED = 1 } rmhmc_precision;
+
+typedef enum { RMHMC_LIK_BERNOULLI_LOGIT = 0, RMHMC_LIK_GAUSSIAN = 1 } rmhmc_lik;
+
+/* Kernel terms of the multiple-kernel prior f ~ GP(0, sum_c k_c) (Sec. 2.1,
+ * Eq. BMKL).  Parameters are consumed in term order:
+ *   SE_ISO(cols)     s^2 exp(-|x-x'|^2 / (2 l^2))         eta = (log s, log l)
+ *   SE_ARD(cols)     s^2 exp(-sum_d r_d^2 / (2 l_d^2))    eta = (log s, log l_d..)
+ *   LINEAR_ARD(cols) sum_d v_d x_d x'_d                   eta = (log v_d..)
+ *   BINARY_SAME(col) s^2 [x_c == x'_c]                    eta = (log s)          */
+typedef enum {
+  RMHMC_K_SE_ISO = 0,
+  RMHMC_K_SE_ARD = 1,
+  RMHMC_K_LINEAR_ARD = 2,
+  RMHMC_K_BINARY_SAME = 3
+} rmhmc_kernel_kind;
+
+#define RMHMC_MAX_TERM_COLS 8
+
+typedef struct {
+  int kind;                          /* rmhmc_kernel_kind                  */
+  int ncols;                         /* 1..RMHMC_MAX_TERM_COLS              */
+  int cols[RMHMC_MAX_TERM_COLS];     /* covariate columns used by the term  */
+} rmhmc_kernel_term;
+
+typedef struct {
+  int N, dx;                 /* data points, covariates                        */
+  const double* X;           /* [host] N x dx, row-major (X[i*dx + c])         */
+  const double* y;           /* [host] N labels in {0,1} (logit) or targets    */
+  int lik;                   /* rmhmc_lik                                      */
+  double noise_var;          /* Gaussian likelihood only                       */
+  int nterms;
+  const rmhmc_kernel_term* terms; /* [host] nterms entries                     */
+  double jitter;             /* fixed diagonal added to K (> 0)                */
+  double beta;               /* inverse temperature on the likelihood, >= 0   */
+} rmhmc_model_desc;
+
+typedef struct rmhmc_model rmhmc_model;
+typedef struct rmhmc_state rmhmc_state;
+
+/* Build a model: copies X and y to the device and allocates every workspace
+ * the calls below need for this N, P and D (no allocation happens later).
+ * The prior is eta ~ N(0, I), f | eta ~ N(0, K(eta)); the likelihood of
+ * Sec. 2.1 Eq. (data_likelihood), raised to the power beta (power posterior
+ * of the evidence appendix).  Returns RMHMC_E_ARG for an invalid descriptor,
+ * RMHMC_E_NOMEM if device memory runs out. */
+rmhmc_status rmhmc_model_create(const rmhmc_model_desc* desc, rmhmc_precision prec,
+                                rmhmc_model** out);
+rmhmc_status rmhmc_model_dims(const rmhmc_model* m, int* N, int* P, int* D); /* [host] outs */
+rmhmc_status rmhmc_model_destroy(rmhmc_model* m);
+
+/* U(q) = -ln P(q) (constants included), grad U and the Hessian H of U at q
+ * (H is the matrix the softabs map of Sec. 2.2 is applied to).
+ *   q [device] D; U [device] 1; gradU [device] D; H [device] D x D, ldh >= D.
+ * RMHMC_E_NOT_PD if the Cholesky factorisation of K fails (the check reads
+ * one device flag and synchronises the stream). */
+rmhmc_status rmhmc_hessian(rmhmc_model* m, const double* q, double* U, double* gradU,
+                           double* H, int ldh, hipStream_t stream);
+
+/* Softabs eigendecomposition (Sec. 2.2; dynamic form Sec. 2.4).
+ * H = Q diag(lam) Q' by cyclic two-sided Jacobi.  Q_warm == NULL: static
+ * solve from the identity.  Q_warm != NULL: the dynamic update of Sec. 2.4,
+ * Jacobi on Q_warm' H Q_warm, then Q = Q_warm * (its rotations).  Stops when
+ * off(M)_F <= zeta ||M||_F (zeta <= 0 selects 1e-13).
+ *   H [device] D x D (ldh); Q_warm, Q [device] D x D (ld = D);
+ *   lam, g, gp [device] D: eigenvalues, g = lam coth(alpha lam) and g';
+ *   logdetG [device] 1 = sum log g;  sweeps [host, nullable].
+ * Eigenvalues are not sorted.  Synchronises the stream once per sweep.
+ * RMHMC_E_EIG_NOCONV if max_sweeps (<= 0 selects 60) runs out. */
+rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, double zeta,
+                               int max_sweeps, const double* Q_warm, double* Q, double* lam,
+                               double* g, double* gp, double* logdetG, int* sweeps,
+                               hipStream_t stream);
+
+/* Hamiltonian and its gradients at (q, p) for a given eigen-state (Q, lam)
+ * of H(q) (Sec. 2.2, Eq. Hamiltonian and Eq. d_Hamiltonian, with the metric
+ * terms signed as the derivative of Eq. Hamiltonian gives:
+ *   dH/dq = grad U + 1/2 tr(W2 dH/dq) - 1/2 tr(W1 dH/dq), dH/dp = G^-1 p),
+ * where the traces use the cached W1, W2 of Eq. (Betancourt_formula) and the
+ * structure-ordered contraction of Sec. 2.3.
+ *   q, p [device] D; Q [device] D x D (ld D); lam [device] D;
+ *   dHdq, dHdp [device] D; ham [device] 1. */
+rmhmc_status rmhmc_metric_grad(rmhmc_model* m, const double* q, const double* p,
+                               const double* Q, const double* lam, double alpha,
+                               double* dHdq, double* dHdp, double* ham, hipStream_t stream);
+
+/* Device-resident integrator state (q, p, eigen-state and per-point caches).
+ * q0, p0 [device] D.  The first eigendecomposition is static; later ones
+ * are warm-started (Sec. 2.4).  Synchronises `stream`. */
+rmhmc_status rmhmc_state_create(rmhmc_model* m, const double* q0, const double* p0,
+                                double alpha, hipStream_t stream, rmhmc_state** out);
+rmhmc_status rmhmc_state_get(const rmhmc_state* s, double* q, double* p, double* ham,
+                             hipStream_t stream);   /* [device] outs, ham nullable */
+rmhmc_status rmhmc_state_set_momentum(rmhmc_state* s, const double* p, hipStream_t stream);
+rmhmc_status rmhmc_state_destroy(rmhmc_state* s);
+/* Momentum draw of Algorithm 1 at the state's current point:
+ * p = Q diag(sqrt g) z, i.e. p ~ N(0, G(q)) for z ~ N(0, I).  z [device] D. */
+rmhmc_status rmhmc_state_draw_momentum(rmhmc_state* s, const double* z, hipStream_t stream);
+
+/* One generalized leapfrog (Sec. 2.2, Eq. leapfrog).  Both implicit
+ * equations are solved by n_fixed_point plain fixed-point iterations
+ * started at p(t) and q(t) (no early exit).  Metric evaluations at new
+ * points are warm-started Jacobi updates (Sec. 2.4). */
+rmhmc_status rmhmc_glf_step(rmhmc_model* m, rmhmc_state* s, double eps, int n_fixed_point,
+                            hipStream_t stream);
+
+typedef struct {
+  double eps;            /* leapfrog step size epsilon                        */
+  double alpha;          /* softabs sharpness (g = lam coth(alpha lam))       */
+  double zeta;           /* Jacobi tolerance (<= 0: 1e-13)                    */
+  int n_leapfrog;        /* C, leapfrogs per move                             */
+  int n_moves;           /* A, moves (burn-in included)                       */
+  int n_fixed_point;     /* K, fixed-point iterations per implicit equation   */
+  int max_sweeps;        /* Jacobi sweep cap per eigendecomposition (<=0: 60) */
+  int reorth_every;      /* re-orthogonalise Q every this many updates (<=0: 10) */
+} rmhmc_chain_cfg;
+
+typedef struct {
+  int accepted;          /* moves accepted                                    */
+  int failures;          /* moves rejected because a step failed              */
+  long long leapfrogs;   /* generalized leapfrogs completed                   */
+  long long eig_calls;   /* eigendecompositions                               */
+  long long sweeps;      /* Jacobi sweeps over all eigendecompositions        */
+} rmhmc_chain_stats;
+
+/* RMHMC chain, Algorithm 1: per move p = Q diag(sqrt g) z (p ~ N(0, G(q))),
+ * C generalized leapfrogs, then Metropolis-Hastings: accept iff
+ * log u < H_old - H_new, else restore q and its eigen-state (the printed
+ * algorithm restores on the opposite event).  A failure inside a move
+ * counts as a rejection.
+ *   q0 [device] D; z [device] n_moves x D (row-major: move-major);
+ *   u [device] n_moves in (0,1); samples [device] n_moves x D (row-major);
+ *   logpost [device] n_moves (= -U(q) after each move);
+ *   accepted [device] n_moves (int32 0/1); stats [host, nullable].
+ * Synchronises once per move (the accept decision is read on the host). */
+rmhmc_status rmhmc_chain(rmhmc_model* m, const rmhmc_chain_cfg* cfg, const double* q0,
+                         const double* z, const double* u, double* samples, double* logpost,
+                         int* accepted, rmhmc_chain_stats* stats, hipStream_t stream);
+
+/* Building block exposed for tests and benchmarks: the MFMA GEMM every
+ * dense product above runs on.  C = alpha op(A) op(B) + beta C, column-major,
+ * op(X) = X' when the trans flag is non-zero; A, B, C [device].
+ * rmhmc_gemm_f64 uses v_mfma_f64_16x16x4f64, rmhmc_gemm_f32
+ * v_mfma_f32_16x16x4f32 (FP32 accumulation).  Asynchronous on `stream`. */
+rmhmc_status rmhmc_gemm_f64(int m, int n, int k, double alpha, const double* A, int lda, int transA,
+                            const double* B, int ldb, int transB, double beta, double* C, int ldc,
+                            hipStream_t stream);
+rmhmc_status rmhmc_gemm_f32(int m, int n, int k, float alpha, const float* A, int lda, int transA,
+                            const float* B, int ldb, int transB, float beta, float* C, int ldc,
+                            hipStream_t stream);
+
+/* Live per-kernel timing (instrumentation, off by default).  When enabled,
+ * the launches of each kernel family below are bracketed by HIP events on
+ * their own stream and their algorithmic work is tallied:
+ *   0 FP64 MFMA GEMM, 1 FP32 MFMA GEMM, 2 Jacobi subproblem solve,
+ *   3 Jacobi rotation apply, 4 kernel-derivative weighted sums,
+ *   5 kernel-derivative mat-vec, 6 Cholesky diagonal block.
+ * rmhmc_timing_enable(mask) clears the tallies and times the families whose
+ * bit (1 << family) is set, 0 switches timing off (synchronises the device);
+ * rmhmc_timing_read waits for the recorded events and returns the launch
+ * count, summed kernel milliseconds, algorithmic flops and bytes [host]. */
+rmhmc_status rmhmc_timing_enable(unsigned mask);
+rmhmc_status rmhmc_timing_read(int kind, long long* launches, double* ms, double* flops,
+                               double* bytes);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char* rmhmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RMHMC_H */

@@ -1,0 +1,37 @@
+// Softabs eigendecomposition: block Jacobi workspace and helpers.
+#pragma once
+#include "common.h"
+
+namespace rmhmc {
+
+struct EigWork {
+  double* M = nullptr;     // Dp x Dp working matrix (ld Dp)
+  double* M2 = nullptr;    // second buffer
+  double* Psi = nullptr;   // Dp x Dp eigenvectors (columns), identity-padded
+  double* V = nullptr;     // per-slot 64 x 64 rotations
+  double* part = nullptr;  // reduction partials
+  double* ctrl = nullptr;  // device: ||M||_F, converged, ratio, checks
+  double* ctrl_host = nullptr;  // pinned host mirror of ctrl
+};
+
+int eig_padded_dim(int D);
+void eig_workspace_sizes(int D, long* doubles);
+// Copy H (D x D, ldh) into w.M (symmetrised, zero-padded).
+void eig_load_matrix(int D, const double* H, long ldh, EigWork& w, hipStream_t st);
+// w.Psi = diag(Q, I) (Q == nullptr: identity).
+void eig_load_basis(int D, const double* Q, long ldq, EigWork& w, hipStream_t st);
+// Jacobi on w.M, rotations accumulated into w.Psi; converged matrix left in w.M.
+void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int* sweeps_out, hipStream_t st);
+void softabs_finalize(int D, const double* M, long ldm, double alpha, double* lam, double* g,
+                      double* gp, double* logdetG, hipStream_t st);
+// M1(j,k) = T_jk b_j b_k with T the divided differences of g.
+void t_bb(int D, const double* lam, const double* b, double alpha, double* M1, long ld,
+          hipStream_t st);
+// B(:, j) = A(:, j) * num[j] / den[j]  (either may be null)
+void scale_cols(int m, int n, const double* A, long lda, const double* num, const double* den,
+                double* B, long ldb, hipStream_t st);
+// y = x * (sqrt)num / den elementwise (either may be null)
+void vec_scale(int n, const double* x, const double* num, const double* den, bool sqrt_num,
+               double* y, hipStream_t st);
+
+}  // namespace rmhmc

@@ -1,0 +1,507 @@
+// Softabs eigendecomposition (Sec. 2.2) by cyclic two-sided Jacobi, static
+// or warm-started (Sec. 2.4: Jacobi on Psi_prev' H Psi_prev, then
+// Psi = Psi_prev Q).
+//
+// Block Jacobi on the padded Dp x Dp matrix (Dp a multiple of 64): the
+// nb = Dp/32 column blocks play a round-robin tournament, nb-1 rounds per
+// sweep.  In a round every pair of blocks (I, J) forms a 64 x 64 symmetric
+// subproblem that one workgroup diagonalises in LDS with an inner cyclic
+// Jacobi (its own round-robin over 64 indices); the resulting 64 x 64
+// rotations are then applied to all of M (double-buffered, one 64 x 64
+// tile per workgroup) and to the columns of Psi.  Padding rows/columns are
+// zero and never rotate (their off-diagonal entries stay exactly zero).
+// Rotations use Rutishauser's formulas (|angle| <= pi/4).
+#include <cmath>
+#include <utility>
+
+#include "common.h"
+#include "eig.h"
+
+namespace rmhmc {
+namespace {
+
+constexpr int SB = 64;   // subproblem size (two 32-column blocks)
+constexpr int HB = 32;
+
+__device__ __forceinline__ int rr_player(int r, int k, int n) {
+  // round r of a round-robin over n players: player at seat k (seat 0 fixed)
+  return k == 0 ? 0 : 1 + ((k - 1 + r) % (n - 1));
+}
+
+__device__ __forceinline__ int slot_index(int r, int slot, int nb, int x) {
+  // global index of local index x (0..63) of slot `slot` in round r
+  const int I = rr_player(r, slot, nb), J = rr_player(r, nb - 1 - slot, nb);
+  return x < HB ? I * HB + x : J * HB + (x - HB);
+}
+
+__global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
+                                                           const double* __restrict__ M,
+                                                           double* __restrict__ Vbuf,
+                                                           const double* __restrict__ ctrl,
+                                                           int max_inner) {
+  // ctrl[0] = ||M||_F, ctrl[1] = converged flag
+  if (ctrl[1] != 0.0) return;
+  __shared__ double S[SB][SB + 1];
+  __shared__ double V[SB][SB + 1];
+  __shared__ double rc[SB / 2], rs[SB / 2], rt[SB / 2];
+  __shared__ int rp[SB / 2], rq[SB / 2];
+  __shared__ int any;
+  __shared__ double red[4];
+  const int nb = Dp / HB;
+  const int slot = blockIdx.x;
+  const int tid = threadIdx.x;
+  double ss = 0.0;
+  for (int e = tid; e < SB * SB; e += 256) {
+    const int x = e % SB, y = e / SB;
+    const double v = M[slot_index(round, slot, nb, x) + (long)slot_index(round, slot, nb, y) * Dp];
+    S[x][y] = v;
+    V[x][y] = (x == y) ? 1.0 : 0.0;
+    ss += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) ss += __shfl_down(ss, o, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = ss;
+  __syncthreads();
+  // Skip rotations whose off-diagonal entry is below 1e-15 ||S||_F: above the
+  // rounding noise the rotations themselves leave behind (~1e-16 ||S||), so
+  // the inner sweeps stop once the subproblem is diagonal to working accuracy.
+  const double thr = fmax(1e-15 * sqrt(red[0] + red[1] + red[2] + red[3]), 1e-300);
+  for (int sweep = 0; sweep < max_inner; ++sweep) {
+    if (tid == 0) any = 0;
+    __syncthreads();
+    for (int ir = 0; ir < SB - 1; ++ir) {
+      if (tid < SB / 2) {
+        const int p = rr_player(ir, tid, SB), q = rr_player(ir, SB - 1 - tid, SB);
+        const double app = S[p][p], aqq = S[q][q], apq = S[p][q];
+        double c = 1.0, s = 0.0, t = 0.0;
+        if (fabs(apq) > thr) {
+          const double zeta = (aqq - app) / (2.0 * apq);
+          t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+          any = 1;
+        }
+        rc[tid] = c; rs[tid] = s; rt[tid] = t; rp[tid] = p; rq[tid] = q;
+      }
+      __syncthreads();
+      for (int k = tid; k < (SB / 2) * (SB / 2); k += 256) {
+        const int u = k % (SB / 2), v = k / (SB / 2);
+        const int pu = rp[u], qu = rq[u], pv = rp[v], qv = rq[v];
+        if (u == v) {
+          if (rs[u] == 0.0) continue;   // pair not rotated this round
+          const double apq = S[pu][qu];
+          S[pu][pu] -= rt[u] * apq;
+          S[qu][qu] += rt[u] * apq;
+          S[pu][qu] = 0.0;
+          S[qu][pu] = 0.0;
+        } else {
+          const double cu = rc[u], su = rs[u], cv = rc[v], sv = rs[v];
+          const double x11 = S[pu][pv], x12 = S[pu][qv], x21 = S[qu][pv], x22 = S[qu][qv];
+          const double y11 = cu * x11 - su * x21, y12 = cu * x12 - su * x22;
+          const double y21 = su * x11 + cu * x21, y22 = su * x12 + cu * x22;
+          S[pu][pv] = cv * y11 - sv * y12;
+          S[pu][qv] = sv * y11 + cv * y12;
+          S[qu][pv] = cv * y21 - sv * y22;
+          S[qu][qv] = sv * y21 + cv * y22;
+        }
+      }
+      for (int k = tid; k < SB * (SB / 2); k += 256) {
+        const int row = k % SB, u = k / SB;
+        const int pu = rp[u], qu = rq[u];
+        const double cu = rc[u], su = rs[u];
+        const double vp = V[row][pu], vq = V[row][qu];
+        V[row][pu] = cu * vp - su * vq;
+        V[row][qu] = su * vp + cu * vq;
+      }
+      __syncthreads();
+    }
+    if (!any) break;
+  }
+  double* out = Vbuf + (long)slot * SB * SB;
+  for (int e = tid; e < SB * SB; e += 256) {
+    const int x = e % SB, y = e / SB;
+    out[e] = V[x][y];
+  }
+}
+
+// Apply the round's rotations: M_out[P,R] = V_P' M_in[P,R] V_R for all slot
+// pairs, and Psi[:, P] <- Psi[:, P] V_P for 64-row tiles.
+__global__ __launch_bounds__(256) void jacobi_apply_kernel(int Dp, int round,
+                                                           const double* __restrict__ Min,
+                                                           double* __restrict__ Mout,
+                                                           double* __restrict__ Psi,
+                                                           const double* __restrict__ Vbuf,
+                                                           const double* __restrict__ ctrl) {
+  if (ctrl[1] != 0.0) return;
+  __shared__ double X[SB][SB + 1];
+  __shared__ double VP[SB][SB + 1];
+  __shared__ double VR[SB][SB + 1];
+  const int nb = Dp / HB, ns = nb / 2;
+  const int tid = threadIdx.x;
+  const int bx = blockIdx.x;
+  const int a0 = 4 * (tid % 16), b0 = 4 * (tid / 16);
+  double acc[4][4];
+  if (bx < ns * ns) {
+    const int P = bx % ns, R = bx / ns;
+    for (int e = tid; e < SB * SB; e += 256) {
+      const int x = e % SB, y = e / SB;
+      X[x][y] = Min[slot_index(round, P, nb, x) + (long)slot_index(round, R, nb, y) * Dp];
+      VP[x][y] = Vbuf[(long)P * SB * SB + e];
+      VR[x][y] = Vbuf[(long)R * SB * SB + e];
+    }
+    __syncthreads();
+    // Y = VP' X
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int x = 0; x < SB; ++x) {
+      double va[4], xb[4];
+      for (int i = 0; i < 4; ++i) va[i] = VP[x][a0 + i];
+      for (int j = 0; j < 4; ++j) xb[j] = X[x][b0 + j];
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] += va[i] * xb[j];
+    }
+    __syncthreads();
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) X[a0 + i][b0 + j] = acc[i][j];
+    __syncthreads();
+    // Z = Y VR
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int y = 0; y < SB; ++y) {
+      double ya[4], vb[4];
+      for (int i = 0; i < 4; ++i) ya[i] = X[a0 + i][y];
+      for (int j = 0; j < 4; ++j) vb[j] = VR[y][b0 + j];
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] += ya[i] * vb[j];
+    }
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        Mout[slot_index(round, P, nb, a0 + i) + (long)slot_index(round, R, nb, b0 + j) * Dp] =
+            acc[i][j];
+  } else {
+    const int k = bx - ns * ns;
+    const int P = k % ns, rt = k / ns;
+    const int row0 = rt * SB;
+    for (int e = tid; e < SB * SB; e += 256) {
+      const int x = e % SB, y = e / SB;
+      X[x][y] = Psi[(row0 + x) + (long)slot_index(round, P, nb, y) * Dp];
+      VP[x][y] = Vbuf[(long)P * SB * SB + e];
+    }
+    __syncthreads();
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int y = 0; y < SB; ++y) {
+      double xa[4], vb[4];
+      for (int i = 0; i < 4; ++i) xa[i] = X[a0 + i][y];
+      for (int j = 0; j < 4; ++j) vb[j] = VP[y][b0 + j];
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] += xa[i] * vb[j];
+    }
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        Psi[(row0 + a0 + i) + (long)slot_index(round, P, nb, b0 + j) * Dp] = acc[i][j];
+  }
+}
+
+// Partial sums of (off-diagonal squares, all squares) per 64-column chunk.
+__global__ __launch_bounds__(256) void offnorm_kernel(int Dp, const double* __restrict__ M,
+                                                      double* __restrict__ part) {
+  __shared__ double sh[2][4];
+  const int c0 = blockIdx.x * 64;
+  double off = 0.0, tot = 0.0;
+  for (int j = c0; j < c0 + 64; ++j)
+    for (int i = threadIdx.x; i < Dp; i += 256) {
+      const double v = M[i + (long)j * Dp];
+      tot += v * v;
+      if (i != j) off += v * v;
+    }
+  for (int o = 32; o > 0; o >>= 1) {
+    off += __shfl_down(off, o, 64);
+    tot += __shfl_down(tot, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = off;
+    sh[1][threadIdx.x >> 6] = tot;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    part[2 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+  }
+}
+
+// ctrl[0] = ||M||_F (set on the first check), ctrl[1] = converged flag,
+// ctrl[2] = last off/||M|| ratio, ctrl[3] = number of checks.
+__global__ void offnorm_finish_kernel(int nparts, const double* __restrict__ part, double zeta,
+                                      double* __restrict__ ctrl, int first) {
+  if (threadIdx.x != 0) return;
+  double off = 0.0, tot = 0.0;
+  for (int p = 0; p < nparts; ++p) {
+    off += part[2 * p];
+    tot += part[2 * p + 1];
+  }
+  const double nrm = sqrt(tot);
+  if (first) ctrl[0] = nrm;
+  const double r = nrm > 0.0 ? sqrt(off) / nrm : 0.0;
+  ctrl[2] = r;
+  ctrl[3] += 1.0;
+  ctrl[1] = (sqrt(off) <= zeta * nrm || !(nrm > 0.0)) ? 1.0 : 0.0;
+}
+
+// ------------------------------------------------------------ softabs g, g'
+// h(x) = x coth x with x = alpha * lambda; g = h / alpha, g' = h'(x).
+// |x| >= 20: h = |x| (coth 20 - 1 < 2^-53); |x| < 1/2: Taylor series in x^2
+// (radius pi) with 12 terms; otherwise the closed forms.
+__device__ const double kCoth[12] = {1.0,
+                                     1.0 / 3.0,
+                                     -1.0 / 45.0,
+                                     2.0 / 945.0,
+                                     -1.0 / 4725.0,
+                                     2.0 / 93555.0,
+                                     -1382.0 / 638512875.0,
+                                     4.0 / 18243225.0,
+                                     -3617.0 / 162820783125.0,
+                                     87734.0 / 38979295480125.0,
+                                     -349222.0 / 1531329465290625.0,
+                                     310732.0 / 13447856940643125.0};
+
+__device__ double h0(double x) {
+  const double ax = fabs(x);
+  if (ax >= 20.0) return ax;
+  if (ax < 0.5) {
+    const double z = x * x;
+    double s = kCoth[11];
+    for (int n = 10; n >= 0; --n) s = s * z + kCoth[n];
+    return s;
+  }
+  return x / tanh(x);
+}
+
+__device__ double h1(double x) {
+  const double ax = fabs(x);
+  if (ax >= 20.0) return x > 0 ? 1.0 : -1.0;
+  if (ax < 0.5) {
+    const double z = x * x;
+    double s = 22.0 * kCoth[11];
+    for (int n = 10; n >= 1; --n) s = s * z + 2.0 * n * kCoth[n];
+    return s * x;
+  }
+  const double sh = sinh(x);
+  return (0.5 * sinh(2.0 * x) - x) / (sh * sh);
+}
+
+__device__ double h3(double x) {
+  const double ax = fabs(x);
+  if (ax >= 20.0) return 0.0;
+  if (ax < 0.5) {
+    const double z = x * x;
+    double s = 0.0;
+    for (int n = 11; n >= 2; --n) {
+      const double k = 2.0 * n;
+      s = s * z + k * (k - 1.0) * (k - 2.0) * kCoth[n];
+    }
+    return s * x;
+  }
+  const double sh = sinh(x), ct = 1.0 / tanh(x);
+  return 2.0 / (sh * sh) * (3.0 * ct - 3.0 * x * ct * ct + x);
+}
+
+}  // namespace
+
+__device__ double divided_difference(double lj, double ll, double alpha) {
+  const double xj = alpha * lj, xl = alpha * ll;
+  if (fabs(xj) >= 20.0 && fabs(xl) >= 20.0) {
+    if ((xj > 0) == (xl > 0)) return xj > 0 ? 1.0 : -1.0;
+    return (fabs(lj) - fabs(ll)) / (lj - ll);
+  }
+  const double d = xj - xl;
+  if (fabs(d) < 1e-3) {
+    const double m = 0.5 * (xj + xl);
+    return h1(m) + h3(m) * d * d / 24.0;
+  }
+  return (h0(xj) - h0(xl)) / d;
+}
+
+namespace {
+
+__global__ __launch_bounds__(256) void softabs_finalize_kernel(int D, const double* __restrict__ M,
+                                                               long ldm, double alpha,
+                                                               double* __restrict__ lam,
+                                                               double* __restrict__ g,
+                                                               double* __restrict__ gp,
+                                                               double* __restrict__ logdetG) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < D; i += 256) {
+    const double l = M[i + (long)i * ldm];
+    const double x = alpha * l;
+    const double gi = h0(x) / alpha;
+    lam[i] = l;
+    g[i] = gi;
+    gp[i] = h1(x);
+    s += log(gi);
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) logdetG[0] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// M1(j,k) = T_jk b_j b_k  (T from Eq. d3_transform), D x D with ld.
+__global__ void t_bb_kernel(int D, const double* __restrict__ lam, const double* __restrict__ b,
+                            double alpha, double* __restrict__ M1, long ld) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)D * D) return;
+  const int j = (int)(e % D), k = (int)(e / D);
+  const double t = (j == k) ? h1(alpha * lam[j]) : divided_difference(lam[j], lam[k], alpha);
+  M1[j + (long)k * ld] = t * b[j] * b[k];
+}
+
+__global__ void scale_cols_kernel(int m, int n, const double* __restrict__ A, long lda,
+                                  const double* __restrict__ num, const double* __restrict__ den,
+                                  double* __restrict__ B, long ldb) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)m * n) return;
+  const int i = (int)(e % m), j = (int)(e / m);
+  double s = num ? num[j] : 1.0;
+  if (den) s /= den[j];
+  B[i + (long)j * ldb] = A[i + (long)j * lda] * s;
+}
+
+__global__ void vec_scale_kernel(int n, const double* __restrict__ x, const double* __restrict__ num,
+                                 const double* __restrict__ den, int sqrt_num, double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = x[i];
+  if (num) s *= sqrt_num ? sqrt(num[i]) : num[i];
+  if (den) s /= den[i];
+  y[i] = s;
+}
+
+__global__ void pad_copy_kernel(int D, int Dp, const double* __restrict__ H, long ldh,
+                                double* __restrict__ M) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)Dp * Dp) return;
+  const int i = (int)(e % Dp), j = (int)(e / Dp);
+  M[e] = (i < D && j < D) ? 0.5 * (H[i + (long)j * ldh] + H[j + (long)i * ldh]) : 0.0;
+}
+
+__global__ void pad_identity_kernel(int D, int Dp, const double* __restrict__ Q, long ldq,
+                                    double* __restrict__ Psi) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)Dp * Dp) return;
+  const int i = (int)(e % Dp), j = (int)(e / Dp);
+  double v;
+  if (i < D && j < D) v = Q ? Q[i + (long)j * ldq] : (i == j ? 1.0 : 0.0);
+  else v = (i == j) ? 1.0 : 0.0;
+  Psi[e] = v;
+}
+
+}  // namespace
+
+int eig_padded_dim(int D) { return ((D + SB - 1) / SB) * SB; }
+
+void eig_workspace_sizes(int D, long* doubles) {
+  const int Dp = eig_padded_dim(D);
+  const int nb = Dp / HB;
+  *doubles = 3L * Dp * Dp + (long)(nb / 2) * SB * SB + 2L * (Dp / 64 + 1) + 8;
+}
+
+void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int* sweeps_out, hipStream_t st) {
+  // Input: w.M (Dp x Dp symmetric, padded) and w.Psi (Dp x Dp, padded with identity).
+  const int Dp = eig_padded_dim(D);
+  const int nb = Dp / HB, ns = nb / 2;
+  const int nparts = Dp / 64;
+  double* Min = w.M;
+  double* Mout = w.M2;
+  RM_HIP(hipMemsetAsync(w.ctrl, 0, 4 * sizeof(double), st));
+  hipLaunchKernelGGL(offnorm_kernel, dim3(nparts), dim3(256), 0, st, Dp, (const double*)Min, w.part);
+  RM_CHECK_LAUNCH();
+  hipLaunchKernelGGL(offnorm_finish_kernel, dim3(1), dim3(64), 0, st, nparts, (const double*)w.part,
+                     zeta, w.ctrl, 1);
+  RM_CHECK_LAUNCH();
+  int sw = 0;
+  bool conv = false;
+  for (;;) {
+    RM_HIP(hipMemcpyAsync(w.ctrl_host, w.ctrl, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    RM_HIP(hipStreamSynchronize(st));
+    if (!std::isfinite(w.ctrl_host[0]))
+      throw Error(RMHMC_E_NONFINITE, "softabs_eig: non-finite entries in the matrix");
+    if (w.ctrl_host[1] != 0.0) { conv = true; break; }
+    if (sw >= max_sweeps) break;
+    for (int r = 0; r < nb - 1; ++r) {
+      int slot = timing_begin(TK_JACOBI_SOLVE, st);
+      hipLaunchKernelGGL(jacobi_solve_kernel, dim3(ns), dim3(256), 0, st, Dp, r,
+                         (const double*)Min, w.V, (const double*)w.ctrl, 12);
+      RM_CHECK_LAUNCH();
+      // one inner sweep of a 64x64 subproblem: 63 rounds x (1024 2x2 blocks x 24
+      // flops + 2048 V row pairs x 6 flops); bytes: subproblems in, rotations out
+      timing_end(slot, st, (double)ns * 63.0 * (1024.0 * 24.0 + 2048.0 * 6.0),
+                 2.0 * ns * SB * SB * sizeof(double));
+      slot = timing_begin(TK_JACOBI_APPLY, st);
+      hipLaunchKernelGGL(jacobi_apply_kernel, dim3(ns * ns + (Dp / SB) * ns), dim3(256), 0, st, Dp,
+                         r, (const double*)Min, Mout, w.Psi, (const double*)w.V,
+                         (const double*)w.ctrl);
+      RM_CHECK_LAUNCH();
+      timing_end(slot, st, 4.0 * (double)SB * SB * SB * ns * ns + 2.0 * (double)SB * SB * SB * (Dp / SB) * ns,
+                 4.0 * (double)Dp * Dp * sizeof(double));
+      std::swap(Min, Mout);
+    }
+    ++sw;
+    hipLaunchKernelGGL(offnorm_kernel, dim3(nparts), dim3(256), 0, st, Dp, (const double*)Min, w.part);
+    RM_CHECK_LAUNCH();
+    hipLaunchKernelGGL(offnorm_finish_kernel, dim3(1), dim3(64), 0, st, nparts,
+                       (const double*)w.part, zeta, w.ctrl, 0);
+    RM_CHECK_LAUNCH();
+  }
+  if (Min != w.M) {
+    // keep the converged matrix in w.M
+    RM_HIP(hipMemcpyAsync(w.M, Min, (size_t)Dp * Dp * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  if (sweeps_out) *sweeps_out = sw;
+  if (!conv) throw Error(RMHMC_E_EIG_NOCONV, "softabs_eig: Jacobi did not converge");
+}
+
+void eig_load_matrix(int D, const double* H, long ldh, EigWork& w, hipStream_t st) {
+  const int Dp = eig_padded_dim(D);
+  const long n = (long)Dp * Dp;
+  hipLaunchKernelGGL(pad_copy_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, D, Dp, H, ldh, w.M);
+  RM_CHECK_LAUNCH();
+}
+
+void eig_load_basis(int D, const double* Q, long ldq, EigWork& w, hipStream_t st) {
+  const int Dp = eig_padded_dim(D);
+  const long n = (long)Dp * Dp;
+  hipLaunchKernelGGL(pad_identity_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, D, Dp, Q, ldq, w.Psi);
+  RM_CHECK_LAUNCH();
+}
+
+void softabs_finalize(int D, const double* M, long ldm, double alpha, double* lam, double* g,
+                      double* gp, double* logdetG, hipStream_t st) {
+  hipLaunchKernelGGL(softabs_finalize_kernel, dim3(1), dim3(256), 0, st, D, M, ldm, alpha, lam, g,
+                     gp, logdetG);
+  RM_CHECK_LAUNCH();
+}
+
+void t_bb(int D, const double* lam, const double* b, double alpha, double* M1, long ld,
+          hipStream_t st) {
+  const long n = (long)D * D;
+  hipLaunchKernelGGL(t_bb_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, D, lam, b, alpha, M1, ld);
+  RM_CHECK_LAUNCH();
+}
+
+void scale_cols(int m, int n, const double* A, long lda, const double* num, const double* den,
+                double* B, long ldb, hipStream_t st) {
+  const long mn = (long)m * n;
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(cdiv(mn, 256)), dim3(256), 0, st, m, n, A, lda, num,
+                     den, B, ldb);
+  RM_CHECK_LAUNCH();
+}
+
+void vec_scale(int n, const double* x, const double* num, const double* den, bool sqrt_num,
+               double* y, hipStream_t st) {
+  hipLaunchKernelGGL(vec_scale_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, n, x, num, den,
+                     (int)sqrt_num, y);
+  RM_CHECK_LAUNCH();
+}
+
+}  // namespace rmhmc

@@ -1,0 +1,266 @@
+// Dense GEMM on the CDNA4 matrix cores (v_mfma_f64_16x16x4f64 and
+// v_mfma_f32_16x16x4f32), column-major, with strided / pointer-array
+// batches and split-K for the very tall inner products used by the
+// trace terms.
+//
+// Tiling: 256 threads (4 wave64), a 64x64 output tile per workgroup, each
+// wave owns a 32x32 quadrant = 2x2 MFMA tiles of 16x16; k advances 16 per
+// LDS stage with register double-buffering of the next stage.  The MFMA
+// "row" operand is fed from the B tile and the "column" operand from the A
+// tile, so each lane's accumulators hold consecutive rows m of C and the
+// column-major stores coalesce.
+#include "common.h"
+
+namespace rmhmc {
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16, PADL = 4;
+
+template <typename T> struct Mfma;
+// Accumulator layout of a 16x16 output tile: lane l, register r holds
+// D[row(l, r)][l % 16].  The FP32 instruction keeps four consecutive rows
+// per lane; the FP64 one interleaves them (row = l/16 + 4r).
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename T>
+struct Params {
+  int m, n, k;
+  T alpha, beta;
+  const T* A; long lda; long sA;
+  const T* B; long ldb; long sB;
+  T* C; long ldc; long sC;
+  T* C2; long ldc2; long sC2;
+  const T* const* Ap; const T* const* Bp; T* const* Cp; T* const* C2p;
+  int ksplit; long kchunk;
+  T* part;          // split-K partials: part[kc * m * n + i + j * m]
+};
+
+template <typename T, bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
+  typedef typename Mfma<T>::v4 v4;
+  const int bz = blockIdx.z;
+  const int batch = bz / p.ksplit, kc = bz % p.ksplit;
+  const T* __restrict__ A = p.Ap ? p.Ap[batch] : p.A + (long)batch * p.sA;
+  const T* __restrict__ B = p.Bp ? p.Bp[batch] : p.B + (long)batch * p.sB;
+  const long kbeg = (long)kc * p.kchunk;
+  const long kend = min((long)p.k, kbeg + p.kchunk);
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int M = p.m, N = p.n;
+  const long lda = p.lda, ldb = p.ldb;
+
+  __shared__ T As[2][BK][BM + PADL];
+  __shared__ T Bs[2][BK][BN + PADL];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+
+  v4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
+
+  T ra[4], rb[4];
+  auto loadA = [&](long k0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int ml, kl;
+      if (!TA) { ml = tid & 63; kl = (tid >> 6) + 4 * r; }
+      else     { kl = tid & 15; ml = (tid >> 4) + 16 * r; }
+      const long gm = m0 + ml, gk = k0 + kl;
+      T v = 0;
+      if (gm < M && gk < kend) v = TA ? A[gk + gm * lda] : A[gm + gk * lda];
+      ra[r] = v;
+    }
+  };
+  auto loadB = [&](long k0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int nl, kl;
+      if (!TB) { kl = tid & 15; nl = (tid >> 4) + 16 * r; }
+      else     { nl = tid & 63; kl = (tid >> 6) + 4 * r; }
+      const long gn = n0 + nl, gk = k0 + kl;
+      T v = 0;
+      if (gn < N && gk < kend) v = TB ? B[gn + gk * ldb] : B[gk + gn * ldb];
+      rb[r] = v;
+    }
+  };
+  auto storeAB = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int ml, kl;
+      if (!TA) { ml = tid & 63; kl = (tid >> 6) + 4 * r; }
+      else     { kl = tid & 15; ml = (tid >> 4) + 16 * r; }
+      As[buf][kl][ml] = ra[r];
+      int nl, kl2;
+      if (!TB) { kl2 = tid & 15; nl = (tid >> 4) + 16 * r; }
+      else     { nl = tid & 63; kl2 = (tid >> 6) + 4 * r; }
+      Bs[buf][kl2][nl] = rb[r];
+    }
+  };
+
+  if (kbeg < kend) {
+    loadA(kbeg);
+    loadB(kbeg);
+    storeAB(0);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (long k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) { loadA(k0 + BK); loadB(k0 + BK); }
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int kr = 4 * kk + (lane >> 4);
+      T av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = As[cur][kr][wm * 32 + t * 16 + (lane & 15)];
+        bv[t] = Bs[cur][kr][wn * 32 + t * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = Mfma<T>::op(bv[tj], av[ti], acc[ti][tj]);
+    }
+    if (more) storeAB(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  // Epilogue.  acc[ti][tj][r] = C(m, n) with m = mbase + lane%16,
+  // n = nbase + row(lane, r) (the MFMA row index is our n).
+  if (p.ksplit > 1) {
+    T* part = p.part + (long)kc * M * N;
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gm = m0 + wm * 32 + ti * 16 + (lane & 15);
+          const int gn = n0 + wn * 32 + tj * 16 + Mfma<T>::row(lane, r);
+          if (gm < M && gn < N) part[gm + (long)gn * M] = acc[ti][tj][r];
+        }
+    return;
+  }
+  T* C = p.Cp ? p.Cp[batch] : (p.C ? p.C + (long)batch * p.sC : nullptr);
+  T* C2 = p.C2p ? p.C2p[batch] : (p.C2 ? p.C2 + (long)batch * p.sC2 : nullptr);
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm * 32 + ti * 16 + (lane & 15);
+        const int gn = n0 + wn * 32 + tj * 16 + Mfma<T>::row(lane, r);
+        if (gm < M && gn < N) {
+          T v = p.alpha * acc[ti][tj][r];
+          if (C) {
+            T* c = C + gm + (long)gn * p.ldc;
+            if (p.beta != T(0)) v += p.beta * *c;
+            *c = v;
+          }
+          if (C2) C2[gn + (long)gm * p.ldc2] = v;
+        }
+      }
+}
+
+template <typename T>
+__global__ void splitk_reduce(int m, int n, int splits, const T* __restrict__ part,
+                              double* __restrict__ C, long ldc) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)m * n) return;
+  double s = 0;
+  for (int kc = 0; kc < splits; ++kc) s += (double)part[(long)kc * m * n + idx];
+  const int i = (int)(idx % m), j = (int)(idx / m);
+  C[i + (long)j * ldc] = s;
+}
+
+template <typename T>
+void launch(const Params<T>& p, bool tA, bool tB, int batch, hipStream_t st) {
+  dim3 grid(cdiv(p.m, BM), cdiv(p.n, BN), batch * p.ksplit);
+  RM_REQUIRE(grid.z <= 65535, "gemm: batch*ksplit too large");
+  const int slot = timing_begin(sizeof(T) == 8 ? TK_GEMM_F64 : TK_GEMM_F32, st);
+  if (!tA && !tB) hipLaunchKernelGGL((gemm_kernel<T, false, false>), grid, dim3(256), 0, st, p);
+  else if (!tA && tB) hipLaunchKernelGGL((gemm_kernel<T, false, true>), grid, dim3(256), 0, st, p);
+  else if (tA && !tB) hipLaunchKernelGGL((gemm_kernel<T, true, false>), grid, dim3(256), 0, st, p);
+  else hipLaunchKernelGGL((gemm_kernel<T, true, true>), grid, dim3(256), 0, st, p);
+  RM_CHECK_LAUNCH();
+  if (slot >= 0) {
+    const double mnk = (double)p.m * p.n * p.k * batch;
+    const double io = ((double)p.m * p.k + (double)p.k * p.n + (double)p.m * p.n) * batch * sizeof(T);
+    timing_end(slot, st, 2.0 * mnk, io);
+  }
+}
+
+template <typename T>
+void gemm_impl(const Gemm<T>& g, hipStream_t st) {
+  if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return;
+  Params<T> p{};
+  p.m = g.m; p.n = g.n; p.k = g.k; p.alpha = g.alpha; p.beta = g.beta;
+  p.A = g.A; p.lda = g.lda; p.sA = g.sA;
+  p.B = g.B; p.ldb = g.ldb; p.sB = g.sB;
+  p.C = g.C; p.ldc = g.ldc; p.sC = g.sC;
+  p.C2 = g.C2; p.ldc2 = g.ldc2; p.sC2 = g.sC2;
+  p.Ap = g.Ap; p.Bp = g.Bp; p.Cp = g.Cp; p.C2p = g.C2p;
+  p.ksplit = 1; p.kchunk = g.k > 0 ? g.k : 1; p.part = nullptr;
+  launch(p, g.tA, g.tB, g.batch, st);
+}
+
+template <typename T>
+void tallk_impl(int m, int n, long k, const T* A, long lda, const T* B, long ldb, double* C,
+                long ldc, double* work, int splits, hipStream_t st) {
+  if (m <= 0 || n <= 0) return;
+  Params<T> p{};
+  p.m = m; p.n = n; p.k = (int)k; p.alpha = 1; p.beta = 0;
+  RM_REQUIRE(k < (1L << 31), "gemm_tallk: k too large");
+  p.A = A; p.lda = lda; p.B = B; p.ldb = ldb;
+  long chunk = ((k + splits - 1) / splits + BK - 1) / BK * BK;
+  if (chunk < BK) chunk = BK;
+  int sp = (int)((k + chunk - 1) / chunk);
+  if (sp < 1) sp = 1;
+  p.ksplit = sp; p.kchunk = chunk;
+  p.part = reinterpret_cast<T*>(work);
+  launch(p, true, false, 1, st);
+  const long mn = (long)m * n;
+  hipLaunchKernelGGL((splitk_reduce<T>), dim3(cdiv(mn, 256)), dim3(256), 0, st, m, n, sp,
+                     (const T*)p.part, C, ldc);
+  RM_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+void gemm(const Gemm<double>& g, hipStream_t st) { gemm_impl(g, st); }
+void gemm(const Gemm<float>& g, hipStream_t st) { gemm_impl(g, st); }
+
+int tallk_splits(long k) {
+  long s = k / 2048;
+  if (s < 1) s = 1;
+  if (s > 1024) s = 1024;
+  return (int)s;
+}
+
+void gemm_tallk(int m, int n, long k, const double* A, long lda, const double* B, long ldb,
+                double* C, long ldc, double* work, int splits, hipStream_t st) {
+  tallk_impl<double>(m, n, k, A, lda, B, ldb, C, ldc, work, splits, st);
+}
+void gemm_tallk(int m, int n, long k, const float* A, long lda, const float* B, long ldb,
+                double* C, long ldc, double* work, int splits, hipStream_t st) {
+  tallk_impl<float>(m, n, k, A, lda, B, ldb, C, ldc, work, splits, st);
+}
+
+}  // namespace rmhmc

@@ -1,0 +1,54 @@
+// Latent-GP model pieces on the device: kernel matrix and hyperparameter
+// derivatives generated on the fly, likelihood derivatives, and the small
+// reductions the Hessian and the third-derivative contraction need.
+#pragma once
+#include "common.h"
+
+namespace rmhmc {
+
+constexpr int MAX_TERMS = 8;
+constexpr int MAX_P = 24;
+constexpr int MAX_TUPLES = 64;
+
+struct TermDev {
+  int kind, ncols, p0, np;
+  int cols[RMHMC_MAX_TERM_COLS];
+};
+
+// Everything a kernel needs to evaluate K(eta) and its derivatives at (i, j).
+struct ModelDev {
+  int N, dx, P, nterms;
+  double jitter;
+  const double* X;     // dx x N: X[c * N + i]
+  TermDev terms[MAX_TERMS];
+  int param_term[MAX_P];
+};
+
+// A derivative index tuple (order 1..3), all indices in one kernel term.
+struct Tuple {
+  int ord, l, m, n;
+};
+
+// K and K_l (materialised), jitter on the diagonal of K.
+void kgen(const ModelDev& md, const double* eta, double* K, double* K1, hipStream_t st);
+
+// out[w * nt + t] = sum_ij Wgt_w(i,j) * d^ord K / d eta_tuple(i,j).
+// mode 0: one weight Phi = (K^-1 - alpha alpha')/2 built from Kinv and alpha;
+// mode 1: nw weights from a stack (stride N*N).
+void kd_wsum(const ModelDev& md, const double* eta, const Tuple* tuples, int nt, int mode,
+             const double* Kinv, const double* alpha, const double* Wstack, int nw, double* out,
+             double* work, hipStream_t st);
+
+// y[(x * nt + t) * N + i] = sum_j d K_tuple(i,j) x_x(j), for nx vectors x (stride N).
+void kd_matvec(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
+               const double* x, int nx, double* y, hipStream_t st);
+
+// l, l', l'', l''' of the per-sample negative log likelihood: out[0..4N).
+void lik_derivs(int N, int lik, double noise_var, const double* f, const double* y, double* out,
+                hipStream_t st);
+
+// out[a * ny + b] = x_a . y_b  (length n, x stride sx, y stride sy)
+void pair_dots(int n, const double* x, long sx, int nx, const double* y, long sy, int ny,
+               double* out, hipStream_t st);
+
+}  // namespace rmhmc

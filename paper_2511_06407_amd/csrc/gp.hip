@@ -1,0 +1,282 @@
+// Kernel matrix K(eta) = sum of kernel terms + jitter I (Sec. 2.1,
+// Eq. BMKL) and its hyperparameter derivatives, evaluated element by
+// element from the covariates so that only K and the first derivatives are
+// ever stored.  Squared-exponential terms differentiate exp(log K):
+//   K_l = K c_l,  K_lm = K (c_l c_m + c_lm),
+//   K_lmn = K (c_l c_m c_n + c_lm c_n + c_ln c_m + c_mn c_l + c_lmn),
+// with log K = 2 eta_s - sum_g u_g / 2, u_g = r_g^2 exp(-2 eta_g), so
+// c_s = 2, c_g = u_g, c_gg = -2 u_g, c_ggg = 4 u_g and all other entries 0.
+#include "gp.h"
+
+namespace rmhmc {
+namespace {
+
+struct TermVals {
+  double Kt;
+  double u[RMHMC_MAX_TERM_COLS];
+};
+
+__device__ __forceinline__ void term_eval(const ModelDev& md, const double* __restrict__ eta,
+                                          int t, int i, int j, TermVals& tv) {
+  const TermDev& T = md.terms[t];
+  const double* X = md.X;
+  const int N = md.N;
+  if (T.kind == RMHMC_K_SE_ISO) {
+    double r2 = 0.0;
+    for (int c = 0; c < T.ncols; ++c) {
+      const double d = X[(long)T.cols[c] * N + i] - X[(long)T.cols[c] * N + j];
+      r2 += d * d;
+    }
+    const double u = r2 * exp(-2.0 * eta[T.p0 + 1]);
+    tv.u[0] = u;
+    tv.Kt = exp(2.0 * eta[T.p0] - 0.5 * u);
+  } else if (T.kind == RMHMC_K_SE_ARD) {
+    double su = 0.0;
+    for (int c = 0; c < T.ncols; ++c) {
+      const double d = X[(long)T.cols[c] * N + i] - X[(long)T.cols[c] * N + j];
+      const double u = d * d * exp(-2.0 * eta[T.p0 + 1 + c]);
+      tv.u[c] = u;
+      su += u;
+    }
+    tv.Kt = exp(2.0 * eta[T.p0] - 0.5 * su);
+  } else if (T.kind == RMHMC_K_LINEAR_ARD) {
+    double s = 0.0;
+    for (int c = 0; c < T.ncols; ++c) {
+      const double v = exp(eta[T.p0 + c]) * X[(long)T.cols[c] * N + i] * X[(long)T.cols[c] * N + j];
+      tv.u[c] = v;
+      s += v;
+    }
+    tv.Kt = s;
+  } else {  // RMHMC_K_BINARY_SAME
+    const long c = T.cols[0];
+    tv.Kt = (X[c * N + i] == X[c * N + j]) ? exp(2.0 * eta[T.p0]) : 0.0;
+  }
+}
+
+// Derivative of one term with respect to local parameter indices a, b, c
+// (ord = 1, 2 or 3; unused indices ignored).
+__device__ __forceinline__ double term_deriv(const TermDev& T, const TermVals& tv, int ord, int a,
+                                             int b, int c) {
+  if (T.kind == RMHMC_K_SE_ISO || T.kind == RMHMC_K_SE_ARD) {
+    auto c1 = [&](int x) { return x == 0 ? 2.0 : tv.u[x - 1]; };
+    auto c2 = [&](int x, int y) { return (x == y && x > 0) ? -2.0 * tv.u[x - 1] : 0.0; };
+    if (ord == 1) return tv.Kt * c1(a);
+    if (ord == 2) return tv.Kt * (c1(a) * c1(b) + c2(a, b));
+    const double c3 = (a == b && b == c && a > 0) ? 4.0 * tv.u[a - 1] : 0.0;
+    return tv.Kt * (c1(a) * c1(b) * c1(c) + c2(a, b) * c1(c) + c2(a, c) * c1(b) +
+                    c2(b, c) * c1(a) + c3);
+  }
+  if (T.kind == RMHMC_K_LINEAR_ARD) {
+    if (ord >= 2 && a != b) return 0.0;
+    if (ord == 3 && a != c) return 0.0;
+    return tv.u[a];
+  }
+  return (ord == 1 ? 2.0 : (ord == 2 ? 4.0 : 8.0)) * tv.Kt;
+}
+
+__device__ __forceinline__ double tuple_val(const ModelDev& md, const TermVals* tv, const Tuple& tp) {
+  const int t = md.param_term[tp.l];
+  const int p0 = md.terms[t].p0;
+  return term_deriv(md.terms[t], tv[t], tp.ord, tp.l - p0, tp.m - p0, tp.n - p0);
+}
+
+__global__ __launch_bounds__(256) void kgen_kernel(ModelDev md, const double* __restrict__ eta,
+                                                   double* __restrict__ K, double* __restrict__ K1) {
+  const long NN = (long)md.N * md.N;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NN) return;
+  const int i = (int)(e % md.N), j = (int)(e / md.N);
+  double k = (i == j) ? md.jitter : 0.0;
+  for (int t = 0; t < md.nterms; ++t) {
+    TermVals tv;
+    term_eval(md, eta, t, i, j, tv);
+    k += tv.Kt;
+    const TermDev& T = md.terms[t];
+    for (int a = 0; a < T.np; ++a) K1[(long)(T.p0 + a) * NN + e] = term_deriv(T, tv, 1, a, 0, 0);
+  }
+  K[e] = k;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void kd_wsum_kernel(ModelDev md, const double* __restrict__ eta,
+                                                      const Tuple* __restrict__ tuples, int nt,
+                                                      int mode, const double* __restrict__ Kinv,
+                                                      const double* __restrict__ alpha,
+                                                      const double* __restrict__ Wstack,
+                                                      double* __restrict__ part) {
+  __shared__ double sh[4][MAX_TUPLES];
+  __shared__ Tuple stup[MAX_TUPLES];
+  const long NN = (long)md.N * md.N;
+  const int w = blockIdx.y;
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) stup[t] = tuples[t];
+  __syncthreads();
+  double acc[MAX_TUPLES];
+#pragma unroll
+  for (int t = 0; t < MAX_TUPLES; ++t) acc[t] = 0.0;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < NN; e += stride) {
+    const int i = (int)(e % md.N), j = (int)(e / md.N);
+    const double wgt = mode == 0 ? 0.5 * (Kinv[e] - alpha[i] * alpha[j]) : Wstack[(long)w * NN + e];
+    TermVals tv[MAX_TERMS];
+    for (int t = 0; t < md.nterms; ++t) term_eval(md, eta, t, i, j, tv[t]);
+#pragma unroll
+    for (int t = 0; t < MAX_TUPLES; ++t)
+      if (t < nt) acc[t] += wgt * tuple_val(md, tv, stup[t]);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < MAX_TUPLES; ++t) {
+    if (t < nt) {
+      const double s = wave_sum(acc[t]);
+      if (lane == 0) sh[wave][t] = s;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nt; t += blockDim.x)
+    part[((long)w * gridDim.x + blockIdx.x) * nt + t] = sh[0][t] + sh[1][t] + sh[2][t] + sh[3][t];
+}
+
+__global__ void kd_wsum_reduce(int nblk, int nt, int nw, const double* __restrict__ part,
+                               double* __restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nt * nw) return;
+  const int w = idx / nt, t = idx % nt;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[((long)w * nblk + b) * nt + t];
+  out[idx] = s;
+}
+
+__global__ __launch_bounds__(256) void kd_matvec_kernel(ModelDev md, const double* __restrict__ eta,
+                                                        const Tuple* __restrict__ tuples, int nt,
+                                                        const double* __restrict__ x,
+                                                        double* __restrict__ y) {
+  __shared__ double sh[4][64];
+  __shared__ Tuple stup[MAX_TUPLES];
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) stup[t] = tuples[t];
+  __syncthreads();
+  const int N = md.N;
+  const int xi = blockIdx.y;
+  const double* xv = x + (long)xi * N;
+  const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + r;
+  double acc[MAX_TUPLES];
+#pragma unroll
+  for (int t = 0; t < MAX_TUPLES; ++t) acc[t] = 0.0;
+  if (i < N) {
+    for (int j = g; j < N; j += 4) {
+      TermVals tv[MAX_TERMS];
+      for (int t = 0; t < md.nterms; ++t) term_eval(md, eta, t, i, j, tv[t]);
+      const double xj = xv[j];
+#pragma unroll
+      for (int t = 0; t < MAX_TUPLES; ++t)
+        if (t < nt) acc[t] += tuple_val(md, tv, stup[t]) * xj;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < MAX_TUPLES; ++t) {
+    if (t < nt) {
+      sh[g][r] = acc[t];
+      __syncthreads();
+      if (g == 0 && i < N) y[((long)xi * nt + t) * N + i] = sh[0][r] + sh[1][r] + sh[2][r] + sh[3][r];
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void lik_kernel(int N, int lik, double noise_var, const double* __restrict__ f,
+                           const double* __restrict__ y, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double fi = f[i], yi = y[i];
+  double l0, l1, l2, l3;
+  if (lik == RMHMC_LIK_BERNOULLI_LOGIT) {
+    // l = log(1 + e^f) - y f, written to avoid overflow for large |f|
+    const double s = fi >= 0 ? 1.0 / (1.0 + exp(-fi)) : exp(fi) / (1.0 + exp(fi));
+    l0 = (fi > 0 ? fi + log1p(exp(-fi)) : log1p(exp(fi))) - yi * fi;
+    l1 = s - yi;
+    l2 = s * (1.0 - s);
+    l3 = l2 * (1.0 - 2.0 * s);
+  } else {
+    const double r = fi - yi;
+    l0 = 0.5 * r * r / noise_var + 0.5 * log(2.0 * M_PI * noise_var);
+    l1 = r / noise_var;
+    l2 = 1.0 / noise_var;
+    l3 = 0.0;
+  }
+  out[i] = l0;
+  out[N + i] = l1;
+  out[2 * N + i] = l2;
+  out[3 * N + i] = l3;
+}
+
+__global__ __launch_bounds__(256) void pair_dots_kernel(int n, const double* __restrict__ x, long sx,
+                                                        int nx, const double* __restrict__ y, long sy,
+                                                        int ny, double* __restrict__ out) {
+  __shared__ double sh[4];
+  const int a = blockIdx.x / ny, b = blockIdx.x % ny;
+  const double* xa = x + (long)a * sx;
+  const double* yb = y + (long)b * sy;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += xa[i] * yb[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+}  // namespace
+
+void kgen(const ModelDev& md, const double* eta, double* K, double* K1, hipStream_t st) {
+  const long NN = (long)md.N * md.N;
+  hipLaunchKernelGGL(kgen_kernel, dim3(cdiv(NN, 256)), dim3(256), 0, st, md, eta, K, K1);
+  RM_CHECK_LAUNCH();
+}
+
+void kd_wsum(const ModelDev& md, const double* eta, const Tuple* tuples, int nt, int mode,
+             const double* Kinv, const double* alpha, const double* Wstack, int nw, double* out,
+             double* work, hipStream_t st) {
+  if (nt <= 0 || nw <= 0) return;
+  RM_REQUIRE(nt <= MAX_TUPLES, "kd_wsum: too many derivative tuples");
+  const long NN = (long)md.N * md.N;
+  int nblk = cdiv(NN, 256 * 16);
+  if (nblk > 512) nblk = 512;
+  if (nblk < 1) nblk = 1;
+  const int slot = timing_begin(TK_KD_WSUM, st);
+  hipLaunchKernelGGL(kd_wsum_kernel, dim3(nblk, nw), dim3(256), 0, st, md, eta, tuples, nt, mode,
+                     Kinv, alpha, Wstack, work);
+  RM_CHECK_LAUNCH();
+  timing_end(slot, st, 2.0 * (double)NN * nt * nw, (double)NN * nw * sizeof(double));
+  hipLaunchKernelGGL(kd_wsum_reduce, dim3(cdiv(nt * nw, 256)), dim3(256), 0, st, nblk, nt, nw,
+                     (const double*)work, out);
+  RM_CHECK_LAUNCH();
+}
+
+void kd_matvec(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
+               const double* x, int nx, double* y, hipStream_t st) {
+  if (nt <= 0 || nx <= 0) return;
+  RM_REQUIRE(nt <= MAX_TUPLES, "kd_matvec: too many derivative tuples");
+  const int slot = timing_begin(TK_KD_MATVEC, st);
+  hipLaunchKernelGGL(kd_matvec_kernel, dim3(cdiv(md.N, 64), nx), dim3(256), 0, st, md, eta,
+                     tuples, nt, x, y);
+  RM_CHECK_LAUNCH();
+  timing_end(slot, st, 2.0 * (double)md.N * md.N * nt * nx, (double)md.N * nx * (1.0 + nt) * sizeof(double));
+}
+
+void lik_derivs(int N, int lik, double noise_var, const double* f, const double* y, double* out,
+                hipStream_t st) {
+  hipLaunchKernelGGL(lik_kernel, dim3(cdiv(N, 256)), dim3(256), 0, st, N, lik, noise_var, f, y, out);
+  RM_CHECK_LAUNCH();
+}
+
+void pair_dots(int n, const double* x, long sx, int nx, const double* y, long sy, int ny,
+               double* out, hipStream_t st) {
+  if (nx <= 0 || ny <= 0) return;
+  hipLaunchKernelGGL(pair_dots_kernel, dim3(nx * ny), dim3(256), 0, st, n, x, sx, nx, y, sy, ny, out);
+  RM_CHECK_LAUNCH();
+}
+
+}  // namespace rmhmc

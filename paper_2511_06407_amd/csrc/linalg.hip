@@ -1,0 +1,434 @@
+// Small dense linear-algebra building blocks: GEMV, multi-dot reductions,
+// blocked Cholesky with explicit inverse, and vector utilities.  Every
+// reduction runs in a fixed order (no atomics), so results are bitwise
+// reproducible run to run.
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+namespace rmhmc {
+
+// ---------------------------------------------------------------- timing
+namespace {
+struct TRec {
+  int kind;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+std::mutex g_tmu;
+unsigned g_tmask = 0;
+std::vector<TRec> g_recs;
+std::vector<hipEvent_t> g_evpool;
+hipEvent_t take_event() {
+  if (!g_evpool.empty()) {
+    hipEvent_t e = g_evpool.back();
+    g_evpool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  RM_HIP(hipEventCreate(&e));
+  return e;
+}
+}  // namespace
+
+bool timing_enabled() { return g_tmask != 0; }
+
+int timing_begin(int kind, hipStream_t st) {
+  if (!((g_tmask >> kind) & 1u)) return -1;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  TRec r{kind, take_event(), take_event(), 0.0, 0.0};
+  RM_HIP(hipEventRecord(r.a, st));
+  g_recs.push_back(r);
+  return (int)g_recs.size() - 1;
+}
+
+void timing_end(int slot, hipStream_t st, double flops, double bytes) {
+  if (slot < 0) return;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  TRec& r = g_recs[slot];
+  RM_HIP(hipEventRecord(r.b, st));
+  r.flops = flops;
+  r.bytes = bytes;
+}
+
+void timing_set(unsigned mask) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (auto& r : g_recs) {
+    g_evpool.push_back(r.a);
+    g_evpool.push_back(r.b);
+  }
+  g_recs.clear();
+  g_tmask = mask;
+}
+
+void timing_read(int kind, long long* launches, double* ms, double* flops, double* bytes) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  long long n = 0;
+  double t = 0, f = 0, b = 0;
+  for (auto& r : g_recs) {
+    if (r.kind != kind) continue;
+    RM_HIP(hipEventSynchronize(r.b));
+    float e = 0.f;
+    RM_HIP(hipEventElapsedTime(&e, r.a, r.b));
+    ++n;
+    t += e;
+    f += r.flops;
+    b += r.bytes;
+  }
+  *launches = n;
+  *ms = t;
+  *flops = f;
+  *bytes = b;
+}
+
+namespace {
+
+constexpr int CB = 64;   // Cholesky block
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  // 256-thread deterministic sum (tree in LDS)
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------- GEMV
+// y = alpha A x + beta y: 64 rows x 4 column groups per workgroup.
+__global__ __launch_bounds__(256) void gemv_n_kernel(int m, int n, double alpha, const double* A,
+                                                     long lda, long sA, const double* x, long sx,
+                                                     double beta, double* y, long sy) {
+  __shared__ double sh[4][64];
+  const int b = blockIdx.y;
+  A += (long)b * sA; x += (long)b * sx; y += (long)b * sy;
+  const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + r;
+  double s = 0;
+  if (i < m)
+    for (int j = g; j < n; j += 4) s += A[i + (long)j * lda] * x[j];
+  sh[g][r] = s;
+  __syncthreads();
+  if (g == 0 && i < m) {
+    double t = sh[0][r] + sh[1][r] + sh[2][r] + sh[3][r];
+    y[i] = alpha * t + (beta != 0.0 ? beta * y[i] : 0.0);
+  }
+}
+
+// y = alpha A' x + beta y: one wave per output column.
+__global__ __launch_bounds__(256) void gemv_t_kernel(int m, int n, double alpha, const double* A,
+                                                     long lda, long sA, const double* x, long sx,
+                                                     double beta, double* y, long sy) {
+  const int b = blockIdx.y;
+  A += (long)b * sA; x += (long)b * sx; y += (long)b * sy;
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;
+  double s = 0;
+  for (int i = lane; i < m; i += 64) s += A[i + (long)j * lda] * x[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) y[j] = alpha * s + (beta != 0.0 ? beta * y[j] : 0.0);
+}
+
+// ---------------------------------------------------------------- multi-dot
+constexpr int MD_MAX = 32;
+__global__ __launch_bounds__(256) void multi_dot_kernel(int m, int n, const double* A, long lda,
+                                                        const double* B, long ldb, long sB,
+                                                        int nb, int cols_per_block, double* part) {
+  __shared__ double sh[256];
+  double acc[MD_MAX];
+#pragma unroll
+  for (int b = 0; b < MD_MAX; ++b) acc[b] = 0;
+  const int c0 = blockIdx.x * cols_per_block;
+  const int c1 = min(n, c0 + cols_per_block);
+  for (int j = c0; j < c1; ++j)
+    for (int i = threadIdx.x; i < m; i += 256) {
+      const double a = A[i + (long)j * lda];
+#pragma unroll
+      for (int b = 0; b < MD_MAX; ++b)
+        if (b < nb) acc[b] += a * B[(long)b * sB + i + (long)j * ldb];
+    }
+  for (int b = 0; b < nb; ++b) {
+    double s = block_sum(acc[b], sh);
+    if (threadIdx.x == 0) part[(long)blockIdx.x * nb + b] = s;
+  }
+}
+
+__global__ void reduce_parts_kernel(int nparts, int nb, const double* part, double* out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  double s = 0;
+  for (int p = 0; p < nparts; ++p) s += part[(long)p * nb + b];
+  out[b] = s;
+}
+
+// ---------------------------------------------------------------- Cholesky
+// Factor the diagonal block in LDS (right-looking, one barrier per column),
+// then invert the triangle by forward substitution, one thread per column.
+__global__ __launch_bounds__(256) void potrf_diag_kernel(int n, int k0, double* L, long ldl,
+                                                         double* Linv, double* diagLogs,
+                                                         int* info) {
+  __shared__ double S[CB][CB + 1];
+  __shared__ double X[CB][CB + 1];
+  __shared__ int bad;
+  const int w = min(CB, n - k0);
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int i = e % CB, j = e / CB;
+    S[i][j] = (i < w && j < w) ? L[(k0 + i) + (long)(k0 + j) * ldl] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    const double d = S[j][j];
+    if (!(d > 0.0)) {
+      if (tid == 0) bad = 1;
+    }
+    // trailing update with the unscaled column j: S_ik -= S_ij S_kj / d
+    for (int e = tid; e < CB * CB; e += 256) {
+      const int i = e % CB, k = e / CB;
+      if (k > j && i >= k && i < w) S[i][k] -= S[i][j] * S[k][j] / d;
+    }
+    __syncthreads();
+  }
+  // scale: L_ij = S_ij / sqrt(S_jj), L_jj = sqrt(S_jj)
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int i = e % CB, j = e / CB;
+    double v = 0.0;
+    if (i < w && j < w && i >= j) v = (i == j) ? sqrt(S[j][j]) : S[i][j] / sqrt(S[j][j]);
+    X[i][j] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int i = e % CB, j = e / CB;
+    S[i][j] = X[i][j];
+  }
+  __syncthreads();
+  // invert lower-triangular S: column c of X = S^-1 e_c
+  if (tid < w) {
+    const int c = tid;
+    for (int i = 0; i < w; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= S[i][k] * X[k][c];
+      X[i][c] = (i < c) ? 0.0 : s / S[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int i = e % CB, j = e / CB;
+    if (i < w && j < w) {
+      L[(k0 + i) + (long)(k0 + j) * ldl] = S[i][j];
+      Linv[(k0 + i) + (long)(k0 + j) * ldl] = X[i][j];
+    }
+  }
+  if (tid < w) diagLogs[k0 + tid] = log(S[tid][tid]);
+  if (tid == 0 && bad) *info = k0 + 1;
+}
+
+__global__ void zero_upper_kernel(int n, double* A, long lda) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * n) return;
+  const int i = (int)(e % n), j = (int)(e / n);
+  if (j > i) A[i + (long)j * lda] = 0.0;
+}
+
+__global__ void fill_kernel(double* x, long n, double v) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+__global__ void copy_kernel(double* d, const double* s, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+__global__ void axpby_kernel(long n, double a, const double* x, double b, double* y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + b * y[i];
+}
+__global__ void lincomb3_kernel(long n, const double* base, double c1, const double* x, double c2,
+                                const double* y, double* dst) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = base[i] + c1 * x[i] + c2 * y[i];
+}
+__global__ void symmetrize_kernel(int n, double* A, long lda) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * n) return;
+  const int i = (int)(e % n), j = (int)(e / n);
+  if (i > j) {
+    const double v = 0.5 * (A[i + (long)j * lda] + A[j + (long)i * lda]);
+    A[i + (long)j * lda] = v;
+    A[j + (long)i * lda] = v;
+  }
+}
+__global__ __launch_bounds__(256) void vsum_kernel(long n, const double* x, const double* y,
+                                                   double* out) {
+  __shared__ double sh[256];
+  double s = 0;
+  for (long i = threadIdx.x; i < n; i += 256) s += y ? x[i] * y[i] : x[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[0] = s;
+}
+__global__ void set_identity_kernel(int n, double* A, long lda) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * n) return;
+  const int i = (int)(e % n), j = (int)(e / n);
+  A[i + (long)j * lda] = (i == j) ? 1.0 : 0.0;
+}
+__global__ void copy_matrix_kernel(int m, int n, const double* A, long lda, double* B, long ldb) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)m * n) return;
+  const int i = (int)(e % m), j = (int)(e / m);
+  B[i + (long)j * ldb] = A[i + (long)j * lda];
+}
+__global__ void cast_kernel(long n, const double* x, float* y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+
+}  // namespace
+
+void gemv(int m, int n, double alpha, const double* A, long lda, bool tA, long sA,
+          const double* x, long sx, double beta, double* y, long sy, int batch, hipStream_t st) {
+  if (m <= 0 || n <= 0 || batch <= 0) return;
+  if (!tA)
+    hipLaunchKernelGGL(gemv_n_kernel, dim3(cdiv(m, 64), batch), dim3(256), 0, st, m, n, alpha, A,
+                       lda, sA, x, sx, beta, y, sy);
+  else
+    hipLaunchKernelGGL(gemv_t_kernel, dim3(cdiv(n, 4), batch), dim3(256), 0, st, m, n, alpha, A,
+                       lda, sA, x, sx, beta, y, sy);
+  RM_CHECK_LAUNCH();
+}
+
+void multi_dot(int m, int n, const double* A, long lda, const double* B, long ldb, long sB,
+               int nb, double* out, double* work, hipStream_t st) {
+  if (nb <= 0) return;
+  RM_REQUIRE(nb <= MD_MAX, "multi_dot: too many matrices");
+  const int cpb = 4;
+  const int nblocks = cdiv(n, cpb);
+  hipLaunchKernelGGL(multi_dot_kernel, dim3(nblocks), dim3(256), 0, st, m, n, A, lda, B, ldb, sB,
+                     nb, cpb, work);
+  RM_CHECK_LAUNCH();
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, st, nblocks, nb,
+                     (const double*)work, out);
+  RM_CHECK_LAUNCH();
+}
+
+void chol_inverse(int n, const double* K, double* Kinv, double* logdet, CholWork& w,
+                  double* redwork, hipStream_t st) {
+  const long nn = (long)n * n;
+  RM_HIP(hipMemcpyAsync(w.L, K, nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+  fill(w.Linv, nn, 0.0, st);
+  RM_HIP(hipMemsetAsync(w.info, 0, sizeof(int), st));
+  const int nb = cdiv(n, CB);
+  for (int kb = 0; kb < nb; ++kb) {
+    const int k0 = kb * CB, bw = std::min(CB, n - k0), r0 = k0 + bw, rm = n - r0;
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, n, k0, w.L, (long)n, w.Linv,
+                       w.diagLogs, w.info);
+    RM_CHECK_LAUNCH();
+    if (rm <= 0) break;
+    // panel: tmp = L[r0:, k0:k0+bw] * Linv_kk'
+    Gemm<double> g;
+    g.m = rm; g.n = bw; g.k = bw;
+    g.A = w.L + r0 + (long)k0 * n; g.lda = n;
+    g.B = w.Linv + k0 + (long)k0 * n; g.ldb = n; g.tB = true;
+    g.C = w.tmp + r0 + (long)k0 * n; g.ldc = n;
+    gemm(g, st);
+    copy_matrix(rm, bw, w.tmp + r0 + (long)k0 * n, n, w.L + r0 + (long)k0 * n, n, st);
+    // trailing: L[r0:, r0:] -= P P'
+    Gemm<double> t;
+    t.m = rm; t.n = rm; t.k = bw; t.alpha = -1.0; t.beta = 1.0;
+    t.A = w.L + r0 + (long)k0 * n; t.lda = n;
+    t.B = w.L + r0 + (long)k0 * n; t.ldb = n; t.tB = true;
+    t.C = w.L + r0 + (long)r0 * n; t.ldc = n;
+    gemm(t, st);
+  }
+  hipLaunchKernelGGL(zero_upper_kernel, dim3(cdiv(nn, 256)), dim3(256), 0, st, n, w.L, (long)n);
+  RM_CHECK_LAUNCH();
+  // Linv block rows: Linv[i, :i] = -Linv_ii (L[i, :i] Linv[:i, :i])
+  for (int ib = 1; ib < nb; ++ib) {
+    const int i0 = ib * CB, bw = std::min(CB, n - i0);
+    Gemm<double> a;
+    a.m = bw; a.n = i0; a.k = i0;
+    a.A = w.L + i0; a.lda = n;
+    a.B = w.Linv; a.ldb = n;
+    a.C = w.tmp + i0; a.ldc = n;
+    gemm(a, st);
+    Gemm<double> b;
+    b.m = bw; b.n = i0; b.k = bw; b.alpha = -1.0;
+    b.A = w.Linv + i0 + (long)i0 * n; b.lda = n;
+    b.B = w.tmp + i0; b.ldb = n;
+    b.C = w.Linv + i0; b.ldc = n;
+    gemm(b, st);
+  }
+  // K^-1 = Linv' Linv
+  Gemm<double> c;
+  c.m = n; c.n = n; c.k = n;
+  c.A = w.Linv; c.lda = n; c.tA = true;
+  c.B = w.Linv; c.ldb = n;
+  c.C = Kinv; c.ldc = n;
+  gemm(c, st);
+  symmetrize(n, Kinv, n, st);
+  vsum(n, w.diagLogs, logdet, st);
+  axpby(1, 0.0, logdet, 2.0, logdet, st);  // log|K| = 2 sum log L_ii
+  (void)redwork;
+}
+
+void fill(double* x, long n, double v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, x, n, v);
+  RM_CHECK_LAUNCH();
+}
+void copy(double* dst, const double* src, long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(copy_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, dst, src, n);
+  RM_CHECK_LAUNCH();
+}
+void axpby(long n, double a, const double* x, double b, double* y, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(axpby_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, n, a, x, b, y);
+  RM_CHECK_LAUNCH();
+}
+void lincomb3(long n, const double* base, double c1, const double* x, double c2, const double* y,
+              double* dst, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(lincomb3_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, n, base, c1, x, c2, y,
+                     dst);
+  RM_CHECK_LAUNCH();
+}
+void symmetrize(int n, double* A, long lda, hipStream_t st) {
+  const long nn = (long)n * n;
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(cdiv(nn, 256)), dim3(256), 0, st, n, A, lda);
+  RM_CHECK_LAUNCH();
+}
+void vsum(long n, const double* x, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(vsum_kernel, dim3(1), dim3(256), 0, st, n, x, (const double*)nullptr, out);
+  RM_CHECK_LAUNCH();
+}
+void vdot(long n, const double* x, const double* y, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(vsum_kernel, dim3(1), dim3(256), 0, st, n, x, y, out);
+  RM_CHECK_LAUNCH();
+}
+void set_identity(int n, double* A, long lda, hipStream_t st) {
+  const long nn = (long)n * n;
+  hipLaunchKernelGGL(set_identity_kernel, dim3(cdiv(nn, 256)), dim3(256), 0, st, n, A, lda);
+  RM_CHECK_LAUNCH();
+}
+void copy_matrix(int m, int n, const double* A, long lda, double* B, long ldb, hipStream_t st) {
+  const long mn = (long)m * n;
+  if (mn <= 0) return;
+  hipLaunchKernelGGL(copy_matrix_kernel, dim3(cdiv(mn, 256)), dim3(256), 0, st, m, n, A, lda, B,
+                     ldb);
+  RM_CHECK_LAUNCH();
+}
+void cast_to_float(long n, const double* x, float* y, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(cast_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, n, x, y);
+  RM_CHECK_LAUNCH();
+}
+
+}  // namespace rmhmc

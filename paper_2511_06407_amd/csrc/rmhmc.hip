@@ -1,0 +1,1162 @@
+// librmhmc: softabs RMHMC for latent-GP models on one MI355X.
+//
+// Host orchestration of the device kernels behind the C ABI in rmhmc.h:
+//   hessian      U, grad U and H at q                      (Sec. 2.2 input)
+//   softabs_eig  H = Psi diag(lam) Psi', g, g', log|G|     (Sec. 2.2, 2.4)
+//   metric_grad  dH/dq, dH/dp and H(q,p)                   (Eq. d_Hamiltonian,
+//                with W1, W2 of Eq. Betancourt_formula and the ordered
+//                contraction of Sec. 2.3)
+//   glf_step     generalized leapfrog                      (Eq. leapfrog)
+//   chain        RMHMC moves with Metropolis-Hastings      (Algorithm 1)
+//
+// Notation: q = (f, eta), K = K(eta) + jitter I, alpha = K^-1 f, K_l = dK/deta_l,
+// A_l = K^-1 K_l, B_l = A_l K^-1, Phi = (K^-1 - alpha alpha')/2.
+// Everything a point q needs is cached in a Point; a leapfrog moves between
+// three Points (move start, and two alternating trial points).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "eig.h"
+#include "gp.h"
+
+namespace rmhmc {
+
+static thread_local std::string g_last_error;
+void timing_set(unsigned mask);
+void timing_read(int kind, long long* launches, double* ms, double* flops, double* bytes);
+
+namespace {
+
+const double kLog2Pi = 1.8378770664093453;
+
+struct Pool {
+  std::vector<void*> ptrs;
+  std::vector<void*> host;
+  template <class T>
+  T* alloc(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(RMHMC_E_NOMEM, "device allocation of " + std::to_string(n * sizeof(T)) +
+                                     " bytes failed");
+    }
+    ptrs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  template <class T>
+  T* alloc_host(size_t n) {
+    void* p = nullptr;
+    RM_HIP(hipHostMalloc(&p, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault));
+    host.push_back(p);
+    return static_cast<T*>(p);
+  }
+  ~Pool() {
+    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : host) (void)hipHostFree(p);
+  }
+};
+
+// ------------------------------------------------------------ small kernels
+
+// H (Dp x Dp, padded with zeros): H_ff = K^-1 + beta diag(l''), H_fl = -A_l alpha,
+// H_lm = k_l.a_m + <Phi, K_lm> - tr(A_l A_m)/2 + delta_lm (symmetrised).
+__global__ void assemble_H_kernel(int N, int P, int Dp, double beta, const double* __restrict__ Kinv,
+                                  const double* __restrict__ lik, const double* __restrict__ a,
+                                  const double* __restrict__ kla, const double* __restrict__ phiK2,
+                                  const double* __restrict__ trAA, const int* __restrict__ pidx,
+                                  double* __restrict__ H) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)Dp * Dp) return;
+  const int i = (int)(e % Dp), j = (int)(e / Dp);
+  const int D = N + P;
+  double v = 0.0;
+  if (i < N && j < N) {
+    v = Kinv[i + (long)j * N];
+    if (i == j) v += beta * lik[2 * N + i];
+  } else if (i < N && j < D) {
+    v = -a[(long)(j - N) * N + i];
+  } else if (j < N && i < D) {
+    v = -a[(long)(i - N) * N + j];
+  } else if (i < D && j < D) {
+    const int l = i - N, m = j - N;
+    v = 0.5 * (kla[l * P + m] + kla[m * P + l]) - 0.25 * (trAA[l + m * P] + trAA[m + l * P]);
+    const int pi = pidx[l * P + m];
+    if (pi >= 0) v += phiK2[pi];
+    if (l == m) v += 1.0;
+  }
+  H[e] = v;
+}
+
+// grad U and U.  scal: [0] log|K|, [1] U (out), [3] sum l_i, [4] f.alpha.
+__global__ void grad_U_kernel(int N, int P, double beta, const double* __restrict__ q,
+                              const double* __restrict__ alpha, const double* __restrict__ lik,
+                              const double* __restrict__ ak, const double* __restrict__ trK1,
+                              double* __restrict__ gradU, double* __restrict__ scal) {
+  const int D = N + P;
+  for (int i = threadIdx.x; i < D; i += blockDim.x) {
+    if (i < N) {
+      gradU[i] = beta * lik[N + i] + alpha[i];
+    } else {
+      const int l = i - N;
+      gradU[i] = -0.5 * ak[l] + 0.5 * trK1[l] + q[i];
+    }
+  }
+  if (threadIdx.x == 0) {
+    double ee = 0.0;
+    for (int l = 0; l < P; ++l) ee += q[N + l] * q[N + l];
+    scal[1] = beta * scal[3] + 0.5 * scal[4] + 0.5 * scal[0] + 0.5 * ee + 0.5 * D * kLog2Pi;
+  }
+}
+
+// d H_lm / d eta_n for all n, l, m (W-independent part of the contraction).
+__global__ void dHe_kernel(int P, const double* __restrict__ D1, const double* __restrict__ D2,
+                           const double* __restrict__ D3, const double* __restrict__ t3,
+                           const double* __restrict__ tB, const double* __restrict__ tau,
+                           const int* __restrict__ pidx, const int* __restrict__ tidx,
+                           const int* __restrict__ yidx, int npairs, int nyy,
+                           double* __restrict__ dHe) {
+  const int P2 = P * P, P3 = P2 * P;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < P3; e += gridDim.x * blockDim.x) {
+    const int n = e / P2, l = (e / P) % P, m = e % P;
+    double v = -D1[n * P2 + l * P + m] - D1[l * P2 + n * P + m] - D1[l * P2 + m * P + n];
+    const int pln = pidx[l * P + n], pmn = pidx[m * P + n], plm = pidx[l * P + m];
+    if (pln >= 0) v += D2[pln * P + m] - 0.5 * tB[m * npairs + pln];
+    if (pmn >= 0) v += D3[l * npairs + pmn] - 0.5 * tB[l * npairs + pmn];
+    if (plm >= 0) v += D3[n * npairs + plm] - 0.5 * tB[n * npairs + plm];
+    const int t = tidx[(l * P + m) * P + n];
+    if (t >= 0) v += t3[t];
+    v += tau[n + yidx[l * P + m] * P];
+    dHe[e] = v;
+  }
+}
+
+// z = sum_lm W_lm (2 K_l a_m - K_lm alpha)
+__global__ void zvec_kernel(int N, int P, int Dp, const double* __restrict__ W,
+                            const double* __restrict__ c1a, const double* __restrict__ k2a,
+                            const int* __restrict__ pidx, double* __restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double s = 0.0;
+  for (int l = 0; l < P; ++l)
+    for (int m = 0; m < P; ++m) {
+      const double wlm = W[(N + l) + (long)(N + m) * Dp];
+      double t = 2.0 * c1a[(long)(l * P + m) * N + i];
+      const int pi = pidx[l * P + m];
+      if (pi >= 0) t -= k2a[(long)pi * N + i];
+      s += wlm * t;
+    }
+  z[i] = s;
+}
+
+// v = tr(W dH/dq) assembled from the pieces (f-part and eta-part).
+__global__ void contract_final_kernel(int N, int P, int Dp, double beta, const double* __restrict__ W,
+                                      const double* __restrict__ lik, const double* __restrict__ Au,
+                                      const double* __restrict__ Kz, const double* __restrict__ wB,
+                                      const double* __restrict__ E1, const double* __restrict__ E2,
+                                      const double* __restrict__ dHe, const int* __restrict__ pidx,
+                                      int npairs, double* __restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int D = N + P;
+  if (i >= D) return;
+  if (i < N) {
+    double s = beta * W[i + (long)i * Dp] * lik[3 * N + i] + Kz[i];
+    for (int l = 0; l < P; ++l) s -= 2.0 * Au[(long)l * N + i];
+    v[i] = s;
+  } else {
+    const int n = i - N, P2 = P * P;
+    double s = -wB[n];
+    for (int l = 0; l < P; ++l) {
+      s += 2.0 * (E1[l * P2 + n * P + l] + E1[l * P2 + l * P + n]);
+      const int pln = pidx[l * P + n];
+      if (pln >= 0) s -= 2.0 * E2[l * npairs + pln];
+    }
+    for (int l = 0; l < P; ++l)
+      for (int m = 0; m < P; ++m) s += W[(N + l) + (long)(N + m) * Dp] * dHe[n * P2 + l * P + m];
+    v[i] = s;
+  }
+}
+
+// H(q,p) = U + log|G|/2 + sum c^2/g / 2 + D log(2 pi)/2, c = Psi' p.
+__global__ void ham_kernel(int D, const double* __restrict__ c, const double* __restrict__ g,
+                           const double* __restrict__ U, const double* __restrict__ logdetG,
+                           double* __restrict__ out) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < D; i += 256) s += c[i] * c[i] / g[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    out[0] = U[0] + 0.5 * logdetG[0] + 0.5 * (sh[0] + sh[1] + sh[2] + sh[3]) + 0.5 * D * kLog2Pi;
+}
+
+__global__ void store_sample_kernel(int D, const double* __restrict__ q, const double* __restrict__ U,
+                                    double* __restrict__ sample, double* __restrict__ logpost,
+                                    int* __restrict__ acc, int accepted) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < D) sample[i] = q[i];
+  if (i == 0) {
+    logpost[0] = -U[0];
+    acc[0] = accepted;
+  }
+}
+
+__global__ void any_nonfinite_kernel(long n, const double* __restrict__ x, int* __restrict__ flag) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(x[i])) flag[0] = 1;
+}
+
+// Newton-Schulz polishing step  Psi <- Psi (3I - Psi'Psi) / 2  on the D x D block.
+__global__ void ns_coeff_kernel(int D, int Dp, double* __restrict__ G) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)D * D) return;
+  const int i = (int)(e % D), j = (int)(e / D);
+  double* x = G + i + (long)j * Dp;
+  *x = (i == j ? 1.5 : 0.0) - 0.5 * *x;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ model
+
+struct Model {
+  int N = 0, dx = 0, P = 0, D = 0, Dp = 0;
+  int lik = 0;
+  double noise_var = 1.0, jitter = 1e-6, beta = 1.0;
+  rmhmc_precision prec = RMHMC_FP64;
+  ModelDev md{};
+  Pool pool;
+  double* y = nullptr;
+  std::vector<Tuple> pairs_h, triples_h;
+  Tuple* pairs = nullptr;
+  Tuple* triples = nullptr;
+  int npairs = 0, ntriples = 0, nyy = 0;
+  std::vector<int> pidx_h, tidx_h, yidx_h;
+  int *pidx = nullptr, *tidx = nullptr, *yidx = nullptr;
+  // scratch
+  CholWork chol;
+  EigWork eig;
+  double *tallwork = nullptr, *kdwork = nullptr, *mdwork = nullptr;
+  double *W = nullptr, *Wt1 = nullptr, *Wt2 = nullptr;
+  double *vc = nullptr, *vb = nullptr, *vtmp = nullptr, *vtmp2 = nullptr, *v1 = nullptr;
+  double *u = nullptr, *Au = nullptr, *z = nullptr, *Kz = nullptr, *wB = nullptr;
+  double *E1 = nullptr, *E2 = nullptr, *D1 = nullptr, *D2 = nullptr, *D3 = nullptr;
+  double *t3 = nullptr, *tB = nullptr, *tau = nullptr;
+  double* dscal = nullptr;     // device scalars for API outputs
+  double* hscal = nullptr;     // pinned host mirror
+  int* dflag = nullptr;
+  int* hflag = nullptr;
+  struct Point* api_pt = nullptr;
+  std::unique_ptr<struct Point> api_pt_own;
+  long reorth_every = 10;
+};
+
+struct Point {
+  Pool pool;
+  int N, P, D, Dp;
+  double *q, *K, *Kinv, *K1, *A, *At, *alpha, *lik, *scal, *k1a, *a, *gradU, *H;
+  double *Psi, *lam, *g, *gp;
+  double *B, *Yt, *k2a, *ik2a, *c1a, *Aam, *dHe, *vW2;
+  double *trK1, *kla, *phiK2, *trAA, *ak;
+  const double **Yap, **Ybp;
+  double** Ycp;
+  bool have_pre = false, have_vW2 = false, have_eig = false;
+  long updates_since_reorth = 0;
+  // scal: [0] log|K|, [1] U, [2] log|G|, [3] sum l, [4] f.alpha, [5] ham
+};
+
+namespace {
+
+std::unique_ptr<Point> new_point(Model& m) {
+  auto pt = std::make_unique<Point>();
+  Point& p = *pt;
+  const long N = m.N, P = m.P, NN = N * N, Dp = m.Dp;
+  p.N = m.N; p.P = m.P; p.D = m.D; p.Dp = m.Dp;
+  Pool& pl = p.pool;
+  p.q = pl.alloc<double>(m.D);
+  p.K = pl.alloc<double>(NN);
+  p.Kinv = pl.alloc<double>(NN);
+  p.K1 = pl.alloc<double>(P * NN);
+  p.A = pl.alloc<double>(P * NN);
+  p.At = pl.alloc<double>(P * NN);
+  p.alpha = pl.alloc<double>(N);
+  p.lik = pl.alloc<double>(4 * N);
+  p.scal = pl.alloc<double>(8);
+  p.k1a = pl.alloc<double>(P * N);
+  p.a = pl.alloc<double>(P * N);
+  p.gradU = pl.alloc<double>(m.D);
+  p.H = pl.alloc<double>(Dp * Dp);
+  p.Psi = pl.alloc<double>(Dp * Dp);
+  p.lam = pl.alloc<double>(Dp);
+  p.g = pl.alloc<double>(Dp);
+  p.gp = pl.alloc<double>(Dp);
+  p.B = pl.alloc<double>(P * NN);
+  p.Yt = pl.alloc<double>((long)m.nyy * NN);
+  p.k2a = pl.alloc<double>((long)std::max(m.npairs, 1) * N);
+  p.ik2a = pl.alloc<double>((long)std::max(m.npairs, 1) * N);
+  p.c1a = pl.alloc<double>(P * P * N);
+  p.Aam = pl.alloc<double>(P * P * N);
+  p.dHe = pl.alloc<double>(P * P * P);
+  p.vW2 = pl.alloc<double>(m.D);
+  p.trK1 = pl.alloc<double>(P);
+  p.kla = pl.alloc<double>(P * P);
+  p.phiK2 = pl.alloc<double>(std::max(m.npairs, 1));
+  p.trAA = pl.alloc<double>(P * P);
+  p.ak = pl.alloc<double>(P);
+  // pointer arrays for the Y_lm = A_l A_m batch (l <= m)
+  std::vector<const double*> ya, yb;
+  std::vector<double*> yc;
+  for (int l = 0; l < m.P; ++l)
+    for (int mm = l; mm < m.P; ++mm) {
+      ya.push_back(p.A + l * NN);
+      yb.push_back(p.A + mm * NN);
+      yc.push_back(p.Yt + (long)m.yidx_h[l * m.P + mm] * NN);
+    }
+  p.Yap = (const double**)pl.alloc<double*>(ya.size());
+  p.Ybp = (const double**)pl.alloc<double*>(yb.size());
+  p.Ycp = pl.alloc<double*>(yc.size());
+  RM_HIP(hipMemcpy((void*)p.Yap, ya.data(), ya.size() * sizeof(void*), hipMemcpyHostToDevice));
+  RM_HIP(hipMemcpy((void*)p.Ybp, yb.data(), yb.size() * sizeof(void*), hipMemcpyHostToDevice));
+  RM_HIP(hipMemcpy((void*)p.Ycp, yc.data(), yc.size() * sizeof(void*), hipMemcpyHostToDevice));
+  RM_HIP(hipMemset(p.scal, 0, 8 * sizeof(double)));
+  return pt;
+}
+
+void check_flag_nonfinite(Model& m, const double* x, long n, hipStream_t st, const char* what) {
+  RM_HIP(hipMemsetAsync(m.dflag, 0, sizeof(int), st));
+  hipLaunchKernelGGL(any_nonfinite_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, n, x, m.dflag);
+  RM_CHECK_LAUNCH();
+  RM_HIP(hipMemcpyAsync(m.hflag, m.dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+  RM_HIP(hipStreamSynchronize(st));
+  if (*m.hflag) throw Error(RMHMC_E_NONFINITE, std::string("non-finite values in ") + what);
+}
+
+// U, grad U, H at pt.q.
+void compute_hessian(Model& m, Point& pt, hipStream_t st) {
+  const int N = m.N, P = m.P;
+  const long NN = (long)N * N;
+  const double* eta = pt.q + N;
+  pt.have_pre = pt.have_vW2 = pt.have_eig = false;
+  kgen(m.md, eta, pt.K, pt.K1, st);
+  chol_inverse(N, pt.K, pt.Kinv, pt.scal + 0, m.chol, nullptr, st);
+  gemv(N, N, 1.0, pt.Kinv, N, false, 0, pt.q, 0, 0.0, pt.alpha, 0, 1, st);
+  lik_derivs(N, m.lik, m.noise_var, pt.q, m.y, pt.lik, st);
+  {  // A_l = K^-1 K_l, and the transposed copies
+    Gemm<double> g;
+    g.m = N; g.n = N; g.k = N;
+    g.A = pt.Kinv; g.lda = N;
+    g.B = pt.K1; g.ldb = N; g.sB = NN;
+    g.C = pt.A; g.ldc = N; g.sC = NN;
+    g.C2 = pt.At; g.ldc2 = N; g.sC2 = NN;
+    g.batch = P;
+    gemm(g, st);
+  }
+  gemv(N, N, 1.0, pt.A, N, false, NN, pt.alpha, 0, 0.0, pt.a, N, P, st);
+  gemv(N, N, 1.0, pt.K1, N, false, NN, pt.alpha, 0, 0.0, pt.k1a, N, P, st);
+  multi_dot(N, N, pt.Kinv, N, pt.K1, N, NN, P, pt.trK1, m.mdwork, st);
+  pair_dots(N, pt.k1a, N, P, pt.a, N, P, pt.kla, st);
+  pair_dots(N, pt.alpha, 0, 1, pt.k1a, N, P, pt.ak, st);
+  kd_wsum(m.md, eta, m.pairs, m.npairs, 0, pt.Kinv, pt.alpha, nullptr, 1, pt.phiK2, m.kdwork, st);
+  gemm_tallk(P, P, NN, pt.A, NN, pt.At, NN, pt.trAA, P, m.tallwork, tallk_splits(NN), st);
+  vsum(N, pt.lik, pt.scal + 3, st);
+  vdot(N, pt.q, pt.alpha, pt.scal + 4, st);
+  hipLaunchKernelGGL(assemble_H_kernel, dim3(cdiv((long)m.Dp * m.Dp, 256)), dim3(256), 0, st, N, P,
+                     m.Dp, m.beta, (const double*)pt.Kinv, (const double*)pt.lik,
+                     (const double*)pt.a, (const double*)pt.kla, (const double*)pt.phiK2,
+                     (const double*)pt.trAA, (const int*)m.pidx, pt.H);
+  RM_CHECK_LAUNCH();
+  hipLaunchKernelGGL(grad_U_kernel, dim3(1), dim3(256), 0, st, N, P, m.beta, (const double*)pt.q,
+                     (const double*)pt.alpha, (const double*)pt.lik, (const double*)pt.ak,
+                     (const double*)pt.trK1, pt.gradU, pt.scal);
+  RM_CHECK_LAUNCH();
+  RM_HIP(hipMemcpyAsync(m.hflag, m.chol.info, sizeof(int), hipMemcpyDeviceToHost, st));
+  RM_HIP(hipStreamSynchronize(st));
+  if (*m.hflag) throw Error(RMHMC_E_NOT_PD, "kernel matrix K is not positive definite");
+  (void)NN;
+}
+
+void reorthogonalise(Model& m, double* Psi, hipStream_t st) {
+  // Psi <- Psi (3I - Psi'Psi)/2 on the D x D block (one Newton-Schulz step).
+  const int D = m.D, Dp = m.Dp;
+  Gemm<double> g;
+  g.m = D; g.n = D; g.k = D;
+  g.A = Psi; g.lda = Dp; g.tA = true;
+  g.B = Psi; g.ldb = Dp;
+  g.C = m.Wt1; g.ldc = Dp;
+  gemm(g, st);
+  hipLaunchKernelGGL(ns_coeff_kernel, dim3(cdiv((long)D * D, 256)), dim3(256), 0, st, D, Dp, m.Wt1);
+  RM_CHECK_LAUNCH();
+  Gemm<double> h;
+  h.m = D; h.n = D; h.k = D;
+  h.A = Psi; h.lda = Dp;
+  h.B = m.Wt1; h.ldb = Dp;
+  h.C = m.Wt2; h.ldc = Dp;
+  gemm(h, st);
+  copy_matrix(D, D, m.Wt2, Dp, Psi, Dp, st);
+}
+
+// Softabs eigen-state of pt.H; warm == nullptr: static, else dynamic from warm->Psi.
+int compute_eig(Model& m, Point& pt, Point* warm, double alpha, double zeta, int max_sweeps,
+                hipStream_t st) {
+  const int D = m.D, Dp = m.Dp;
+  if (!warm) {
+    eig_load_matrix(D, pt.H, Dp, m.eig, st);
+    eig_load_basis(D, nullptr, Dp, m.eig, st);
+    pt.updates_since_reorth = 0;
+  } else {
+    long cnt = warm->updates_since_reorth + 1;
+    if (cnt >= m.reorth_every) {
+      reorthogonalise(m, warm->Psi, st);
+      cnt = 0;
+    }
+    // M = Psi_w' H Psi_w
+    Gemm<double> g;
+    g.m = Dp; g.n = Dp; g.k = Dp;
+    g.A = pt.H; g.lda = Dp;
+    g.B = warm->Psi; g.ldb = Dp;
+    g.C = m.Wt1; g.ldc = Dp;
+    gemm(g, st);
+    Gemm<double> h;
+    h.m = Dp; h.n = Dp; h.k = Dp;
+    h.A = warm->Psi; h.lda = Dp; h.tA = true;
+    h.B = m.Wt1; h.ldb = Dp;
+    h.C = m.eig.M; h.ldc = Dp;
+    gemm(h, st);
+    symmetrize(Dp, m.eig.M, Dp, st);
+    copy(m.eig.Psi, warm->Psi, (long)Dp * Dp, st);
+    pt.updates_since_reorth = cnt;
+  }
+  int sweeps = 0;
+  jacobi_eig(D, m.eig, zeta, max_sweeps, &sweeps, st);
+  copy(pt.Psi, m.eig.Psi, (long)Dp * Dp, st);
+  softabs_finalize(D, m.eig.M, Dp, alpha, pt.lam, pt.g, pt.gp, pt.scal + 2, st);
+  pt.have_eig = true;
+  pt.have_vW2 = false;
+  return sweeps;
+}
+
+// W-independent pieces of v(W) at pt (needs compute_hessian first).
+void compute_precompute(Model& m, Point& pt, hipStream_t st) {
+  if (pt.have_pre) return;
+  const int N = m.N, P = m.P;
+  const long NN = (long)N * N;
+  const double* eta = pt.q + N;
+  {  // B_l = A_l K^-1
+    Gemm<double> g;
+    g.m = N; g.n = N; g.k = N;
+    g.A = pt.A; g.lda = N; g.sA = NN;
+    g.B = pt.Kinv; g.ldb = N;
+    g.C = pt.B; g.ldc = N; g.sC = NN;
+    g.batch = P;
+    gemm(g, st);
+  }
+  {  // Y_lm = A_l A_m (l <= m), stored transposed
+    Gemm<double> g;
+    g.m = N; g.n = N; g.k = N;
+    g.Ap = pt.Yap; g.lda = N;
+    g.Bp = pt.Ybp; g.ldb = N;
+    g.C2p = pt.Ycp; g.ldc2 = N;
+    g.batch = m.nyy;
+    gemm(g, st);
+  }
+  // tau[n, (l,m)] = tr(A_n A_l A_m) = <A_n, Y_lm'>
+  gemm_tallk(P, m.nyy, NN, pt.A, NN, pt.Yt, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
+  kd_matvec(m.md, eta, m.pairs, m.npairs, pt.alpha, 1, pt.k2a, st);
+  {
+    Gemm<double> g;  // ik2a = K^-1 [K_lm alpha]
+    g.m = N; g.n = m.npairs; g.k = N;
+    g.A = pt.Kinv; g.lda = N;
+    g.B = pt.k2a; g.ldb = N;
+    g.C = pt.ik2a; g.ldc = N;
+    gemm(g, st);
+  }
+  {
+    Gemm<double> g;  // c1a[l] = K_l [a_0 .. a_P-1]
+    g.m = N; g.n = P; g.k = N;
+    g.A = pt.K1; g.lda = N; g.sA = NN;
+    g.B = pt.a; g.ldb = N;
+    g.C = pt.c1a; g.ldc = N; g.sC = (long)N * P;
+    g.batch = P;
+    gemm(g, st);
+    Gemm<double> h = g;  // Aam[l] = A_l [a_0 .. a_P-1]
+    h.A = pt.A;
+    h.C = pt.Aam;
+    gemm(h, st);
+  }
+  kd_wsum(m.md, eta, m.pairs, m.npairs, 1, nullptr, nullptr, pt.B, P, m.tB, m.kdwork, st);
+  kd_wsum(m.md, eta, m.triples, m.ntriples, 0, pt.Kinv, pt.alpha, nullptr, 1, m.t3, m.kdwork, st);
+  pair_dots(N, pt.k1a, N, P, pt.Aam, N, P * P, m.D1, st);
+  pair_dots(N, pt.k2a, N, m.npairs, pt.a, N, P, m.D2, st);
+  pair_dots(N, pt.k1a, N, P, pt.ik2a, N, m.npairs, m.D3, st);
+  hipLaunchKernelGGL(dHe_kernel, dim3(cdiv(P * P * P, 256)), dim3(256), 0, st, P,
+                     (const double*)m.D1, (const double*)m.D2, (const double*)m.D3,
+                     (const double*)m.t3, (const double*)m.tB, (const double*)m.tau,
+                     (const int*)m.pidx, (const int*)m.tidx, (const int*)m.yidx, m.npairs, m.nyy,
+                     pt.dHe);
+  RM_CHECK_LAUNCH();
+  pt.have_pre = true;
+}
+
+// v = tr(W dH/dq_i) for a symmetric W (Dp x Dp, ld Dp).
+void contract(Model& m, Point& pt, const double* W, double* v, hipStream_t st) {
+  compute_precompute(m, pt, st);
+  const int N = m.N, P = m.P, Dp = m.Dp;
+  const long NN = (long)N * N;
+  multi_dot(N, N, W, Dp, pt.B, N, NN, P, m.wB, m.mdwork, st);
+  {
+    Gemm<double> g;  // u = K^-1 W[f, eta]
+    g.m = N; g.n = P; g.k = N;
+    g.A = pt.Kinv; g.lda = N;
+    g.B = W + (long)N * Dp; g.ldb = Dp;
+    g.C = m.u; g.ldc = N;
+    gemm(g, st);
+  }
+  gemv(N, N, 1.0, pt.A, N, false, NN, m.u, N, 0.0, m.Au, N, P, st);
+  pair_dots(N, m.u, N, P, pt.c1a, N, P * P, m.E1, st);
+  pair_dots(N, m.u, N, P, pt.k2a, N, m.npairs, m.E2, st);
+  hipLaunchKernelGGL(zvec_kernel, dim3(cdiv(N, 256)), dim3(256), 0, st, N, P, Dp, W,
+                     (const double*)pt.c1a, (const double*)pt.k2a, (const int*)m.pidx, m.z);
+  RM_CHECK_LAUNCH();
+  gemv(N, N, 1.0, pt.Kinv, N, false, 0, m.z, 0, 0.0, m.Kz, 0, 1, st);
+  hipLaunchKernelGGL(contract_final_kernel, dim3(cdiv(m.D, 256)), dim3(256), 0, st, N, P, Dp,
+                     m.beta, W, (const double*)pt.lik, (const double*)m.Au, (const double*)m.Kz,
+                     (const double*)m.wB, (const double*)m.E1, (const double*)m.E2,
+                     (const double*)pt.dHe, (const int*)m.pidx, m.npairs, v);
+  RM_CHECK_LAUNCH();
+}
+
+void compute_vW2(Model& m, Point& pt, hipStream_t st) {
+  if (pt.have_vW2) return;
+  const int D = m.D, Dp = m.Dp;
+  fill(m.W, (long)Dp * Dp, 0.0, st);
+  scale_cols(D, D, pt.Psi, Dp, pt.gp, pt.g, m.Wt1, Dp, st);   // Psi diag(g'/g)
+  Gemm<double> g;
+  g.m = D; g.n = D; g.k = D;
+  g.A = m.Wt1; g.lda = Dp;
+  g.B = pt.Psi; g.ldb = Dp; g.tB = true;
+  g.C = m.W; g.ldc = Dp;
+  gemm(g, st);
+  contract(m, pt, m.W, pt.vW2, st);
+  pt.have_vW2 = true;
+}
+
+// c = Psi'p, b = c / g, dHdp = Psi b (= G^-1 p), ham (optional, device scalar)
+void metric_vectors(Model& m, Point& pt, const double* p, double* dHdp, double* ham, hipStream_t st) {
+  const int D = m.D, Dp = m.Dp;
+  gemv(D, D, 1.0, pt.Psi, Dp, true, 0, p, 0, 0.0, m.vc, 0, 1, st);
+  vec_scale(D, m.vc, nullptr, pt.g, false, m.vb, st);
+  if (dHdp) gemv(D, D, 1.0, pt.Psi, Dp, false, 0, m.vb, 0, 0.0, dHdp, 0, 1, st);
+  if (ham) {
+    hipLaunchKernelGGL(ham_kernel, dim3(1), dim3(256), 0, st, D, (const double*)m.vc,
+                       (const double*)pt.g, (const double*)(pt.scal + 1),
+                       (const double*)(pt.scal + 2), ham);
+    RM_CHECK_LAUNCH();
+  }
+}
+
+// dH/dq = grad U + v(W2)/2 - v(W1)/2 at pt for momentum p.  Also dH/dp, ham.
+void grad_q(Model& m, Point& pt, const double* p, double alpha, double* dHdq, double* dHdp,
+            double* ham, hipStream_t st) {
+  const int D = m.D, Dp = m.Dp;
+  compute_vW2(m, pt, st);
+  metric_vectors(m, pt, p, dHdp, ham, st);
+  fill(m.W, (long)Dp * Dp, 0.0, st);
+  t_bb(D, pt.lam, m.vb, alpha, m.Wt1, Dp, st);             // T o b b'
+  Gemm<double> g;                                            // Wt2 = (T o bb') Psi'
+  g.m = D; g.n = D; g.k = D;
+  g.A = m.Wt1; g.lda = Dp;
+  g.B = pt.Psi; g.ldb = Dp; g.tB = true;
+  g.C = m.Wt2; g.ldc = Dp;
+  gemm(g, st);
+  Gemm<double> h;                                            // W1 = Psi Wt2
+  h.m = D; h.n = D; h.k = D;
+  h.A = pt.Psi; h.lda = Dp;
+  h.B = m.Wt2; h.ldb = Dp;
+  h.C = m.W; h.ldc = Dp;
+  gemm(h, st);
+  contract(m, pt, m.W, m.v1, st);
+  lincomb3(D, pt.gradU, 0.5, pt.vW2, -0.5, m.v1, dHdq, st);
+}
+
+void full_point(Model& m, Point& pt, Point* warm, double alpha, double zeta, int max_sweeps,
+                hipStream_t st, int* sweeps) {
+  compute_hessian(m, pt, st);
+  const int s = compute_eig(m, pt, warm, alpha, zeta, max_sweeps, st);
+  if (sweeps) *sweeps += s;
+}
+
+void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
+  RM_REQUIRE(d != nullptr, "model descriptor is NULL");
+  RM_REQUIRE(d->N >= 2 && d->dx >= 1, "need N >= 2 and dx >= 1");
+  RM_REQUIRE(d->X && d->y, "X and y are required");
+  RM_REQUIRE(d->nterms >= 1 && d->nterms <= MAX_TERMS && d->terms, "1..8 kernel terms required");
+  RM_REQUIRE(d->jitter > 0.0 && std::isfinite(d->jitter), "jitter must be positive");
+  RM_REQUIRE(d->beta >= 0.0 && std::isfinite(d->beta), "beta must be finite and >= 0");
+  RM_REQUIRE(d->lik == RMHMC_LIK_BERNOULLI_LOGIT || d->lik == RMHMC_LIK_GAUSSIAN, "unknown likelihood");
+  if (d->lik == RMHMC_LIK_GAUSSIAN) RM_REQUIRE(d->noise_var > 0.0, "noise_var must be positive");
+  RM_REQUIRE(prec == RMHMC_FP64 || prec == RMHMC_MIXED, "unknown precision");
+  m.N = d->N; m.dx = d->dx; m.lik = d->lik; m.noise_var = d->noise_var;
+  m.jitter = d->jitter; m.beta = d->beta; m.prec = prec;
+  int P = 0;
+  ModelDev& md = m.md;
+  md.N = m.N; md.dx = m.dx; md.nterms = d->nterms; md.jitter = d->jitter;
+  for (int t = 0; t < d->nterms; ++t) {
+    const rmhmc_kernel_term& tt = d->terms[t];
+    RM_REQUIRE(tt.ncols >= 1 && tt.ncols <= RMHMC_MAX_TERM_COLS, "term ncols out of range");
+    for (int c = 0; c < tt.ncols; ++c)
+      RM_REQUIRE(tt.cols[c] >= 0 && tt.cols[c] < d->dx, "term column out of range");
+    int np;
+    switch (tt.kind) {
+      case RMHMC_K_SE_ISO: np = 2; break;
+      case RMHMC_K_SE_ARD: np = 1 + tt.ncols; break;
+      case RMHMC_K_LINEAR_ARD: np = tt.ncols; break;
+      case RMHMC_K_BINARY_SAME:
+        RM_REQUIRE(tt.ncols == 1, "BINARY_SAME takes one column");
+        np = 1;
+        break;
+      default: throw Error(RMHMC_E_ARG, "unknown kernel kind");
+    }
+    TermDev& T = md.terms[t];
+    T.kind = tt.kind; T.ncols = tt.ncols; T.p0 = P; T.np = np;
+    for (int c = 0; c < RMHMC_MAX_TERM_COLS; ++c) T.cols[c] = c < tt.ncols ? tt.cols[c] : 0;
+    RM_REQUIRE(P + np <= MAX_P, "too many hyperparameters");
+    for (int a = 0; a < np; ++a) md.param_term[P + a] = t;
+    P += np;
+  }
+  m.P = P; md.P = P;
+  m.D = m.N + P;
+  m.Dp = eig_padded_dim(m.D);
+  for (long i = 0; i < (long)m.N * m.dx; ++i)
+    RM_REQUIRE(std::isfinite(d->X[i]), "X contains a non-finite value");
+  for (int i = 0; i < m.N; ++i) RM_REQUIRE(std::isfinite(d->y[i]), "y contains a non-finite value");
+  // derivative tuples: pairs l <= m and triples l <= m <= n within a term
+  m.pidx_h.assign(P * P, -1);
+  m.tidx_h.assign(P * P * P, -1);
+  m.yidx_h.assign(P * P, -1);
+  for (int l = 0; l < P; ++l)
+    for (int mm = l; mm < P; ++mm) {
+      const int y = (int)(l * P - l * (l - 1) / 2 + (mm - l));
+      m.yidx_h[l * P + mm] = m.yidx_h[mm * P + l] = y;
+      if (md.param_term[l] != md.param_term[mm]) continue;
+      const int idx = (int)m.pairs_h.size();
+      m.pairs_h.push_back({2, l, mm, 0});
+      m.pidx_h[l * P + mm] = m.pidx_h[mm * P + l] = idx;
+    }
+  m.nyy = P * (P + 1) / 2;
+  for (int l = 0; l < P; ++l)
+    for (int mm = l; mm < P; ++mm)
+      for (int n = mm; n < P; ++n) {
+        if (md.param_term[l] != md.param_term[mm] || md.param_term[l] != md.param_term[n]) continue;
+        const int idx = (int)m.triples_h.size();
+        m.triples_h.push_back({3, l, mm, n});
+        const int perm[6][3] = {{l, mm, n}, {l, n, mm}, {mm, l, n}, {mm, n, l}, {n, l, mm}, {n, mm, l}};
+        for (auto& pp : perm) m.tidx_h[(pp[0] * P + pp[1]) * P + pp[2]] = idx;
+      }
+  m.npairs = (int)m.pairs_h.size();
+  m.ntriples = (int)m.triples_h.size();
+  RM_REQUIRE(m.npairs <= MAX_TUPLES && m.ntriples <= MAX_TUPLES,
+             "kernel terms with too many hyperparameters for the on-the-fly derivative kernels");
+  Pool& pl = m.pool;
+  const long N = m.N, NN = N * N, Dp = m.Dp;
+  // data, column-major on the device
+  std::vector<double> Xc((size_t)m.dx * m.N);
+  for (int i = 0; i < m.N; ++i)
+    for (int c = 0; c < m.dx; ++c) Xc[(size_t)c * m.N + i] = d->X[(size_t)i * m.dx + c];
+  double* Xd = pl.alloc<double>(Xc.size());
+  RM_HIP(hipMemcpy(Xd, Xc.data(), Xc.size() * sizeof(double), hipMemcpyHostToDevice));
+  md.X = Xd;
+  m.y = pl.alloc<double>(N);
+  RM_HIP(hipMemcpy(m.y, d->y, N * sizeof(double), hipMemcpyHostToDevice));
+  m.pairs = pl.alloc<Tuple>(std::max(m.npairs, 1));
+  m.triples = pl.alloc<Tuple>(std::max(m.ntriples, 1));
+  if (m.npairs) RM_HIP(hipMemcpy(m.pairs, m.pairs_h.data(), m.npairs * sizeof(Tuple), hipMemcpyHostToDevice));
+  if (m.ntriples) RM_HIP(hipMemcpy(m.triples, m.triples_h.data(), m.ntriples * sizeof(Tuple), hipMemcpyHostToDevice));
+  m.pidx = pl.alloc<int>(P * P);
+  m.tidx = pl.alloc<int>(P * P * P);
+  m.yidx = pl.alloc<int>(P * P);
+  RM_HIP(hipMemcpy(m.pidx, m.pidx_h.data(), P * P * sizeof(int), hipMemcpyHostToDevice));
+  RM_HIP(hipMemcpy(m.tidx, m.tidx_h.data(), P * P * P * sizeof(int), hipMemcpyHostToDevice));
+  RM_HIP(hipMemcpy(m.yidx, m.yidx_h.data(), P * P * sizeof(int), hipMemcpyHostToDevice));
+  // scratch
+  m.chol.L = pl.alloc<double>(NN);
+  m.chol.Linv = pl.alloc<double>(NN);
+  m.chol.tmp = pl.alloc<double>(NN);
+  m.chol.diagLogs = pl.alloc<double>(N);
+  m.chol.info = pl.alloc<int>(1);
+  m.eig.M = pl.alloc<double>(Dp * Dp);
+  m.eig.M2 = pl.alloc<double>(Dp * Dp);
+  m.eig.Psi = pl.alloc<double>(Dp * Dp);
+  m.eig.V = pl.alloc<double>((Dp / 64) * 64 * 64);
+  m.eig.part = pl.alloc<double>(2 * (Dp / 64 + 1));
+  m.eig.ctrl = pl.alloc<double>(4);
+  m.eig.ctrl_host = pl.alloc_host<double>(4);
+  const int spl = tallk_splits(NN);
+  m.tallwork = pl.alloc<double>((long)spl * P * std::max(P, m.nyy) + 64);
+  m.kdwork = pl.alloc<double>(512L * std::max(P, 1) * MAX_TUPLES);
+  m.mdwork = pl.alloc<double>((long)(std::max<long>(N, Dp) / 4 + 2) * 32);
+  m.W = pl.alloc<double>(Dp * Dp);
+  m.Wt1 = pl.alloc<double>(Dp * Dp);
+  m.Wt2 = pl.alloc<double>(Dp * Dp);
+  m.vc = pl.alloc<double>(Dp);
+  m.vb = pl.alloc<double>(Dp);
+  m.vtmp = pl.alloc<double>(Dp);
+  m.vtmp2 = pl.alloc<double>(Dp);
+  m.v1 = pl.alloc<double>(Dp);
+  m.u = pl.alloc<double>(N * P);
+  m.Au = pl.alloc<double>(N * P);
+  m.z = pl.alloc<double>(N);
+  m.Kz = pl.alloc<double>(N);
+  m.wB = pl.alloc<double>(P);
+  m.E1 = pl.alloc<double>(P * P * P);
+  m.E2 = pl.alloc<double>(P * std::max(m.npairs, 1));
+  m.D1 = pl.alloc<double>(P * P * P);
+  m.D2 = pl.alloc<double>(std::max(m.npairs, 1) * P);
+  m.D3 = pl.alloc<double>(P * std::max(m.npairs, 1));
+  m.t3 = pl.alloc<double>(std::max(m.ntriples, 1));
+  m.tB = pl.alloc<double>(P * std::max(m.npairs, 1));
+  m.tau = pl.alloc<double>(P * m.nyy);
+  m.dscal = pl.alloc<double>(8);
+  m.hscal = pl.alloc_host<double>(8);
+  m.dflag = pl.alloc<int>(1);
+  m.hflag = pl.alloc_host<int>(1);
+  m.api_pt_own = new_point(m);
+  m.api_pt = m.api_pt_own.get();
+}
+
+// ------------------------------------------------------------ integrator state
+
+struct State {
+  Pool pool;
+  Model* m;
+  std::unique_ptr<Point> own[3];
+  Point* pts[3];     // pts[0] = current point
+  double alpha, zeta;
+  int max_sweeps;
+  double *p, *ph, *v0, *vk, *gq, *qk, *ham;
+  long leapfrogs = 0, eig_calls = 0, sweeps = 0;
+};
+
+std::unique_ptr<State> make_state(Model& m, double alpha) {
+  auto s = std::make_unique<State>();
+  s->m = &m;
+  s->alpha = alpha;
+  s->zeta = 1e-13;
+  s->max_sweeps = 60;
+  for (int i = 0; i < 3; ++i) {
+    s->own[i] = new_point(m);
+    s->pts[i] = s->own[i].get();
+  }
+  Pool& pl = s->pool;
+  s->p = pl.alloc<double>(m.D);
+  s->ph = pl.alloc<double>(m.D);
+  s->v0 = pl.alloc<double>(m.D);
+  s->vk = pl.alloc<double>(m.D);
+  s->gq = pl.alloc<double>(m.D);
+  s->qk = pl.alloc<double>(m.D);
+  s->ham = pl.alloc<double>(2);
+  return s;
+}
+
+// One generalized leapfrog from cur with momentum s.p; trial points alternate
+// among the two non-current Points, never touching `keep` (if given).
+Point* leapfrog(State& s, Point* cur, Point* keep, double eps, int K, hipStream_t st) {
+  Model& m = *s.m;
+  const int D = m.D;
+  Point* trial = nullptr;
+  for (int i = 0; i < 3; ++i)
+    if (s.pts[i] != cur && s.pts[i] != keep) { trial = s.pts[i]; break; }
+  // implicit momentum half step at fixed q
+  copy(s.ph, s.p, D, st);
+  for (int k = 0; k < K; ++k) {
+    grad_q(m, *cur, s.ph, s.alpha, s.gq, nullptr, nullptr, st);
+    lincomb3(D, s.p, -0.5 * eps, s.gq, 0.0, s.gq, s.ph, st);
+  }
+  // implicit position step
+  metric_vectors(m, *cur, s.ph, s.v0, nullptr, st);
+  lincomb3(D, cur->q, eps, s.v0, 0.0, s.v0, s.qk, st);   // k = 0: G(q) both times
+  Point* warm = cur;
+  for (int k = 1; k < K; ++k) {
+    copy(trial->q, s.qk, D, st);
+    int sw = 0;
+    full_point(m, *trial, warm, s.alpha, s.zeta, s.max_sweeps, st, &sw);
+    s.sweeps += sw;
+    s.eig_calls += 1;
+    warm = trial;
+    metric_vectors(m, *trial, s.ph, s.vk, nullptr, st);
+    lincomb3(D, cur->q, 0.5 * eps, s.v0, 0.5 * eps, s.vk, s.qk, st);
+  }
+  copy(trial->q, s.qk, D, st);
+  int sw = 0;
+  full_point(m, *trial, warm, s.alpha, s.zeta, s.max_sweeps, st, &sw);
+  s.sweeps += sw;
+  s.eig_calls += 1;
+  // explicit momentum half step
+  grad_q(m, *trial, s.ph, s.alpha, s.gq, nullptr, nullptr, st);
+  lincomb3(D, s.ph, -0.5 * eps, s.gq, 0.0, s.gq, s.p, st);
+  s.leapfrogs += 1;
+  return trial;
+}
+
+}  // namespace
+}  // namespace rmhmc
+
+// ================================================================ C ABI
+
+using namespace rmhmc;
+
+struct rmhmc_model {
+  Model impl;
+};
+struct rmhmc_state {
+  std::unique_ptr<State> impl;
+};
+
+namespace {
+
+template <class F>
+rmhmc_status guard(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return RMHMC_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return RMHMC_E_NOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return RMHMC_E_HIP;
+  }
+}
+
+struct EigCache {
+  int Dp = 0;
+  Pool* pool = nullptr;
+  EigWork w;
+};
+EigCache& eig_cache() {
+  static EigCache c;
+  return c;
+}
+
+template <typename T>
+rmhmc_status gemm_entry(int m, int n, int k, T alpha, const T* A, int lda, int transA,
+                               const T* B, int ldb, int transB, T beta, T* C, int ldc,
+                               hipStream_t st) {
+  return guard([&] {
+    RM_REQUIRE(m >= 0 && n >= 0 && k >= 0, "negative dimension");
+    RM_REQUIRE(A && B && C, "NULL matrix");
+    RM_REQUIRE(lda >= std::max(1, transA ? k : m), "lda too small");
+    RM_REQUIRE(ldb >= std::max(1, transB ? n : k), "ldb too small");
+    RM_REQUIRE(ldc >= std::max(1, m), "ldc too small");
+    Gemm<T> g;
+    g.m = m; g.n = n; g.k = k; g.alpha = alpha; g.beta = beta;
+    g.A = A; g.lda = lda; g.tA = transA != 0;
+    g.B = B; g.ldb = ldb; g.tB = transB != 0;
+    g.C = C; g.ldc = ldc;
+    gemm(g, st);
+  });
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rmhmc_last_error(void) { return g_last_error.c_str(); }
+
+rmhmc_status rmhmc_gemm_f64(int m, int n, int k, double alpha, const double* A, int lda, int transA,
+                            const double* B, int ldb, int transB, double beta, double* C, int ldc,
+                            hipStream_t st) {
+  return gemm_entry<double>(m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc, st);
+}
+rmhmc_status rmhmc_gemm_f32(int m, int n, int k, float alpha, const float* A, int lda, int transA,
+                            const float* B, int ldb, int transB, float beta, float* C, int ldc,
+                            hipStream_t st) {
+  return gemm_entry<float>(m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc, st);
+}
+
+rmhmc_status rmhmc_model_create(const rmhmc_model_desc* desc, rmhmc_precision prec,
+                                rmhmc_model** out) {
+  return guard([&] {
+    RM_REQUIRE(out != nullptr, "out is NULL");
+    auto m = std::make_unique<rmhmc_model>();
+    build_model(m->impl, desc, prec);
+    RM_HIP(hipDeviceSynchronize());
+    *out = m.release();
+  });
+}
+
+rmhmc_status rmhmc_model_dims(const rmhmc_model* m, int* N, int* P, int* D) {
+  return guard([&] {
+    RM_REQUIRE(m != nullptr, "model is NULL");
+    if (N) *N = m->impl.N;
+    if (P) *P = m->impl.P;
+    if (D) *D = m->impl.D;
+  });
+}
+
+rmhmc_status rmhmc_model_destroy(rmhmc_model* m) {
+  return guard([&] {
+    if (m) {
+      (void)hipDeviceSynchronize();
+      delete m;
+    }
+  });
+}
+
+rmhmc_status rmhmc_hessian(rmhmc_model* mh, const double* q, double* U, double* gradU, double* H,
+                           int ldh, hipStream_t st) {
+  return guard([&] {
+    RM_REQUIRE(mh && q && U && gradU && H, "NULL argument");
+    Model& m = mh->impl;
+    RM_REQUIRE(ldh >= m.D, "ldh < D");
+    Point& pt = *m.api_pt;
+    copy(pt.q, q, m.D, st);
+    check_flag_nonfinite(m, pt.q, m.D, st, "q");
+    compute_hessian(m, pt, st);
+    copy(U, pt.scal + 1, 1, st);
+    copy(gradU, pt.gradU, m.D, st);
+    copy_matrix(m.D, m.D, pt.H, m.Dp, H, ldh, st);
+  });
+}
+
+rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, double zeta,
+                               int max_sweeps, const double* Q_warm, double* Q, double* lam,
+                               double* g, double* gp, double* logdetG, int* sweeps,
+                               hipStream_t st) {
+  return guard([&] {
+    RM_REQUIRE(D >= 1 && H && Q && lam && g && gp && logdetG, "bad argument");
+    RM_REQUIRE(ldh >= D, "ldh < D");
+    RM_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "alpha must be positive");
+    if (zeta <= 0.0) zeta = 1e-13;
+    if (max_sweeps <= 0) max_sweeps = 60;
+    EigCache& c = eig_cache();
+    const int Dp = eig_padded_dim(D);
+    if (c.Dp < Dp) {
+      RM_HIP(hipDeviceSynchronize());
+      delete c.pool;
+      c.pool = new Pool();
+      c.w.M = c.pool->alloc<double>((long)Dp * Dp);
+      c.w.M2 = c.pool->alloc<double>((long)Dp * Dp);
+      c.w.Psi = c.pool->alloc<double>((long)Dp * Dp);
+      c.w.V = c.pool->alloc<double>((long)(Dp / 64) * 64 * 64);
+      c.w.part = c.pool->alloc<double>(2 * (Dp / 64 + 1));
+      c.w.ctrl = c.pool->alloc<double>(4);
+      c.w.ctrl_host = c.pool->alloc_host<double>(4);
+      c.Dp = Dp;
+    }
+    eig_load_matrix(D, H, ldh, c.w, st);
+    if (Q_warm) {
+      // M = Qw' H Qw computed through padded copies
+      eig_load_basis(D, Q_warm, D, c.w, st);
+      Gemm<double> a;
+      a.m = Dp; a.n = Dp; a.k = Dp;
+      a.A = c.w.M; a.lda = Dp;
+      a.B = c.w.Psi; a.ldb = Dp;
+      a.C = c.w.M2; a.ldc = Dp;
+      gemm(a, st);
+      Gemm<double> b;
+      b.m = Dp; b.n = Dp; b.k = Dp;
+      b.A = c.w.Psi; b.lda = Dp; b.tA = true;
+      b.B = c.w.M2; b.ldb = Dp;
+      b.C = c.w.M; b.ldc = Dp;
+      gemm(b, st);
+      symmetrize(Dp, c.w.M, Dp, st);
+    } else {
+      eig_load_basis(D, nullptr, D, c.w, st);
+    }
+    int sw = 0;
+    jacobi_eig(D, c.w, zeta, max_sweeps, &sw, st);
+    copy_matrix(D, D, c.w.Psi, Dp, Q, D, st);
+    softabs_finalize(D, c.w.M, Dp, alpha, lam, g, gp, logdetG, st);
+    RM_HIP(hipStreamSynchronize(st));
+    if (sweeps) *sweeps = sw;
+  });
+}
+
+rmhmc_status rmhmc_metric_grad(rmhmc_model* mh, const double* q, const double* p, const double* Q,
+                               const double* lam, double alpha, double* dHdq, double* dHdp,
+                               double* ham, hipStream_t st) {
+  return guard([&] {
+    RM_REQUIRE(mh && q && p && Q && lam && dHdq && dHdp && ham, "NULL argument");
+    RM_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "alpha must be positive");
+    Model& m = mh->impl;
+    Point& pt = *m.api_pt;
+    copy(pt.q, q, m.D, st);
+    compute_hessian(m, pt, st);
+    // eigen-state supplied by the caller
+    eig_load_basis(m.D, Q, m.D, m.eig, st);
+    copy(pt.Psi, m.eig.Psi, (long)m.Dp * m.Dp, st);
+    fill(m.eig.M, (long)m.Dp * m.Dp, 0.0, st);
+    copy_matrix(1, m.D, lam, 1, m.eig.M, m.Dp + 1, st);   // diag(lam)
+    softabs_finalize(m.D, m.eig.M, m.Dp, alpha, pt.lam, pt.g, pt.gp, pt.scal + 2, st);
+    pt.have_eig = true;
+    grad_q(m, pt, p, alpha, dHdq, dHdp, ham, st);
+  });
+}
+
+rmhmc_status rmhmc_state_create(rmhmc_model* mh, const double* q0, const double* p0, double alpha,
+                                hipStream_t st, rmhmc_state** out) {
+  return guard([&] {
+    RM_REQUIRE(mh && q0 && p0 && out, "NULL argument");
+    RM_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "alpha must be positive");
+    Model& m = mh->impl;
+    auto s = std::make_unique<rmhmc_state>();
+    s->impl = make_state(m, alpha);
+    State& S = *s->impl;
+    copy(S.pts[0]->q, q0, m.D, st);
+    copy(S.p, p0, m.D, st);
+    check_flag_nonfinite(m, S.pts[0]->q, m.D, st, "q0");
+    int sw = 0;
+    full_point(m, *S.pts[0], nullptr, alpha, S.zeta, S.max_sweeps, st, &sw);
+    S.sweeps += sw;
+    S.eig_calls += 1;
+    RM_HIP(hipStreamSynchronize(st));
+    *out = s.release();
+  });
+}
+
+rmhmc_status rmhmc_state_get(const rmhmc_state* sh, double* q, double* p, double* ham,
+                             hipStream_t st) {
+  return guard([&] {
+    RM_REQUIRE(sh && q && p, "NULL argument");
+    State& S = *sh->impl;
+    Model& m = *S.m;
+    copy(q, S.pts[0]->q, m.D, st);
+    copy(p, S.p, m.D, st);
+    if (ham) metric_vectors(m, *S.pts[0], S.p, nullptr, ham, st);
+  });
+}
+
+rmhmc_status rmhmc_state_set_momentum(rmhmc_state* sh, const double* p, hipStream_t st) {
+  return guard([&] {
+    RM_REQUIRE(sh && p, "NULL argument");
+    copy(sh->impl->p, p, sh->impl->m->D, st);
+  });
+}
+
+rmhmc_status rmhmc_state_draw_momentum(rmhmc_state* sh, const double* z, hipStream_t st) {
+  return guard([&] {
+    RM_REQUIRE(sh && z, "NULL argument");
+    State& S = *sh->impl;
+    Model& m = *S.m;
+    vec_scale(m.D, z, S.pts[0]->g, nullptr, true, S.vk, st);
+    gemv(m.D, m.D, 1.0, S.pts[0]->Psi, m.Dp, false, 0, S.vk, 0, 0.0, S.p, 0, 1, st);
+  });
+}
+
+rmhmc_status rmhmc_timing_enable(unsigned mask) {
+  return guard([&] {
+    RM_HIP(hipDeviceSynchronize());
+    timing_set(mask);
+  });
+}
+
+rmhmc_status rmhmc_timing_read(int kind, long long* launches, double* ms, double* flops,
+                               double* bytes) {
+  return guard([&] {
+    RM_REQUIRE(kind >= 0 && kind < TK_COUNT, "unknown timer kind");
+    RM_REQUIRE(launches && ms && flops && bytes, "NULL argument");
+    timing_read(kind, launches, ms, flops, bytes);
+  });
+}
+
+rmhmc_status rmhmc_state_destroy(rmhmc_state* sh) {
+  return guard([&] {
+    (void)hipDeviceSynchronize();
+    delete sh;
+  });
+}
+
+rmhmc_status rmhmc_glf_step(rmhmc_model* mh, rmhmc_state* sh, double eps, int n_fixed_point,
+                            hipStream_t st) {
+  return guard([&] {
+    RM_REQUIRE(mh && sh, "NULL argument");
+    RM_REQUIRE(sh->impl->m == &mh->impl, "state belongs to another model");
+    RM_REQUIRE(n_fixed_point >= 1, "n_fixed_point must be >= 1");
+    RM_REQUIRE(std::isfinite(eps) && eps > 0.0, "eps must be positive");
+    State& S = *sh->impl;
+    Point* nxt = leapfrog(S, S.pts[0], nullptr, eps, n_fixed_point, st);
+    for (int i = 1; i < 3; ++i)
+      if (S.pts[i] == nxt) std::swap(S.pts[0], S.pts[i]);
+  });
+}
+
+rmhmc_status rmhmc_chain(rmhmc_model* mh, const rmhmc_chain_cfg* cfg, const double* q0,
+                         const double* z, const double* u, double* samples, double* logpost,
+                         int* accepted, rmhmc_chain_stats* stats, hipStream_t st) {
+  return guard([&] {
+    RM_REQUIRE(mh && cfg && q0 && z && u && samples && logpost && accepted, "NULL argument");
+    RM_REQUIRE(cfg->n_leapfrog >= 1 && cfg->n_moves >= 1 && cfg->n_fixed_point >= 1,
+               "n_leapfrog, n_moves and n_fixed_point must be >= 1");
+    RM_REQUIRE(std::isfinite(cfg->eps) && cfg->eps > 0.0, "eps must be positive");
+    RM_REQUIRE(std::isfinite(cfg->alpha) && cfg->alpha > 0.0, "alpha must be positive");
+    Model& m = mh->impl;
+    const int D = m.D;
+    if (cfg->reorth_every > 0) m.reorth_every = cfg->reorth_every;
+    auto Sp = make_state(m, cfg->alpha);
+    State& S = *Sp;
+    if (cfg->zeta > 0.0) S.zeta = cfg->zeta;
+    if (cfg->max_sweeps > 0) S.max_sweeps = cfg->max_sweeps;
+    std::vector<double> uh(cfg->n_moves);
+    RM_HIP(hipMemcpyAsync(uh.data(), u, cfg->n_moves * sizeof(double), hipMemcpyDeviceToHost, st));
+    copy(S.pts[0]->q, q0, D, st);
+    check_flag_nonfinite(m, S.pts[0]->q, D, st, "q0");
+    int sw = 0;
+    full_point(m, *S.pts[0], nullptr, cfg->alpha, S.zeta, S.max_sweeps, st, &sw);
+    S.sweeps += sw;
+    S.eig_calls += 1;
+    int n_acc = 0, n_fail = 0;
+    for (int ell = 0; ell < cfg->n_moves; ++ell) {
+      Point* start = S.pts[0];
+      // p = Psi diag(sqrt g) z   (p ~ N(0, G(q)))
+      vec_scale(D, z + (long)ell * D, start->g, nullptr, true, S.vk, st);
+      gemv(D, D, 1.0, start->Psi, m.Dp, false, 0, S.vk, 0, 0.0, S.p, 0, 1, st);
+      metric_vectors(m, *start, S.p, nullptr, S.ham, st);
+      bool ok = true;
+      Point* cur = start;
+      try {
+        for (int c = 0; c < cfg->n_leapfrog; ++c) cur = leapfrog(S, cur, start, cfg->eps, cfg->n_fixed_point, st);
+        metric_vectors(m, *cur, S.p, nullptr, S.ham + 1, st);
+      } catch (const Error& e) {
+        if (e.status == RMHMC_E_HIP || e.status == RMHMC_E_ARG || e.status == RMHMC_E_NOMEM) throw;
+        ok = false;
+      }
+      double h0 = 0, h1 = 0;
+      RM_HIP(hipMemcpyAsync(m.hscal, S.ham, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      RM_HIP(hipStreamSynchronize(st));
+      h0 = m.hscal[0];
+      h1 = m.hscal[1];
+      bool acc = ok && std::isfinite(h1) && std::isfinite(h0) && std::log(uh[ell]) < h0 - h1;
+      if (!ok) ++n_fail;
+      if (acc) {
+        ++n_acc;
+        for (int i = 1; i < 3; ++i)
+          if (S.pts[i] == cur) std::swap(S.pts[0], S.pts[i]);
+      }
+      hipLaunchKernelGGL(store_sample_kernel, dim3(cdiv(D, 256)), dim3(256), 0, st, D,
+                         (const double*)S.pts[0]->q, (const double*)(S.pts[0]->scal + 1),
+                         samples + (long)ell * D, logpost + ell, accepted + ell, acc ? 1 : 0);
+      RM_CHECK_LAUNCH();
+    }
+    RM_HIP(hipStreamSynchronize(st));
+    if (stats) {
+      stats->accepted = n_acc;
+      stats->failures = n_fail;
+      stats->leapfrogs = S.leapfrogs;
+      stats->eig_calls = S.eig_calls;
+      stats->sweeps = S.sweeps;
+    }
+  });
+}
+
+}  // extern "C"

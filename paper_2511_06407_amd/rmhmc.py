@@ -1,0 +1,279 @@
+"""ctypes binding of librmhmc.so (C ABI in include/rmhmc.h).
+
+Argument marshalling only: every step of the sampler runs in the HIP
+library.  Device arrays are torch CUDA tensors (float64, contiguous); streams
+are torch.cuda streams.  Importing this module loads the library and raises
+if it has not been built (``python -m paper_2511_06407_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import workloads as wl
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librmhmc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2511_06407_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+MAX_TERM_COLS = 8
+OK, E_ARG, E_NOT_PD, E_EIG_NOCONV, E_NONFINITE, E_NOMEM, E_HIP = 0, -1, -2, -3, -4, -5, -6
+FP64, MIXED = 0, 1
+
+EXPORTED = ["rmhmc_model_create", "rmhmc_model_dims", "rmhmc_model_destroy", "rmhmc_hessian",
+            "rmhmc_softabs_eig", "rmhmc_metric_grad", "rmhmc_state_create", "rmhmc_state_get",
+            "rmhmc_state_set_momentum", "rmhmc_state_destroy", "rmhmc_glf_step", "rmhmc_chain",
+            "rmhmc_gemm_f64", "rmhmc_gemm_f32", "rmhmc_last_error", "rmhmc_state_draw_momentum",
+            "rmhmc_timing_enable", "rmhmc_timing_read"]
+
+TIMER_KINDS = {"gemm_f64": 0, "gemm_f32": 1, "jacobi_solve": 2, "jacobi_apply": 3, "kd_wsum": 4,
+               "kd_matvec": 5, "potrf_diag": 6}
+
+
+class KernelTerm(C.Structure):
+    _fields_ = [("kind", C.c_int), ("ncols", C.c_int), ("cols", C.c_int * MAX_TERM_COLS)]
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("N", C.c_int), ("dx", C.c_int), ("X", C.POINTER(C.c_double)),
+                ("y", C.POINTER(C.c_double)), ("lik", C.c_int), ("noise_var", C.c_double),
+                ("nterms", C.c_int), ("terms", C.POINTER(KernelTerm)), ("jitter", C.c_double),
+                ("beta", C.c_double)]
+
+
+class ChainCfg(C.Structure):
+    _fields_ = [("eps", C.c_double), ("alpha", C.c_double), ("zeta", C.c_double),
+                ("n_leapfrog", C.c_int), ("n_moves", C.c_int), ("n_fixed_point", C.c_int),
+                ("max_sweeps", C.c_int), ("reorth_every", C.c_int)]
+
+
+class ChainStats(C.Structure):
+    _fields_ = [("accepted", C.c_int), ("failures", C.c_int), ("leapfrogs", C.c_longlong),
+                ("eig_calls", C.c_longlong), ("sweeps", C.c_longlong)]
+
+
+_vp = C.c_void_p
+_i, _d = C.c_int, C.c_double
+_sig = {
+    "rmhmc_model_create": [C.POINTER(ModelDesc), _i, C.POINTER(_vp)],
+    "rmhmc_model_dims": [_vp, C.POINTER(_i), C.POINTER(_i), C.POINTER(_i)],
+    "rmhmc_model_destroy": [_vp],
+    "rmhmc_hessian": [_vp, _vp, _vp, _vp, _vp, _i, _vp],
+    "rmhmc_softabs_eig": [_i, _vp, _i, _d, _d, _i, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_i), _vp],
+    "rmhmc_metric_grad": [_vp, _vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp],
+    "rmhmc_state_create": [_vp, _vp, _vp, _d, _vp, C.POINTER(_vp)],
+    "rmhmc_state_get": [_vp, _vp, _vp, _vp, _vp],
+    "rmhmc_state_set_momentum": [_vp, _vp, _vp],
+    "rmhmc_state_destroy": [_vp],
+    "rmhmc_state_draw_momentum": [_vp, _vp, _vp],
+    "rmhmc_timing_enable": [C.c_uint],
+    "rmhmc_timing_read": [_i, C.POINTER(C.c_longlong), C.POINTER(_d), C.POINTER(_d), C.POINTER(_d)],
+    "rmhmc_glf_step": [_vp, _vp, _d, _i, _vp],
+    "rmhmc_chain": [_vp, C.POINTER(ChainCfg), _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(ChainStats), _vp],
+    "rmhmc_gemm_f64": [_i, _i, _i, _d, _vp, _i, _i, _vp, _i, _i, _d, _vp, _i, _vp],
+    "rmhmc_gemm_f32": [_i, _i, _i, C.c_float, _vp, _i, _i, _vp, _i, _i, C.c_float, _vp, _i, _vp],
+}
+for _name, _args in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+_lib.rmhmc_last_error.restype = C.c_char_p
+_lib.rmhmc_last_error.argtypes = []
+
+
+class RmhmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"rmhmc status {status}: {msg}")
+        self.status = status
+
+
+def _check(status):
+    if status != OK:
+        raise RmhmcError(status, _lib.rmhmc_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t, dtype=None):
+    if t is None:
+        return None
+    torch = _torch()
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _f64(t):
+    return _ptr(t, _torch().float64)
+
+
+def gemm_colmajor(m, n, k, A, lda, tA, B, ldb, tB, Cm, ldc, alpha=1.0, beta=0.0, stream=None):
+    torch = _torch()
+    if A.dtype == torch.float64:
+        _check(_lib.rmhmc_gemm_f64(m, n, k, alpha, _f64(A), lda, int(tA), _f64(B), ldb, int(tB),
+                                   beta, _f64(Cm), ldc, _stream(stream)))
+    else:
+        f32 = torch.float32
+        _check(_lib.rmhmc_gemm_f32(m, n, k, alpha, _ptr(A, f32), lda, int(tA), _ptr(B, f32), ldb,
+                                   int(tB), beta, _ptr(Cm, f32), ldc, _stream(stream)))
+
+
+class Model:
+    """A latent-GP model resident on the device (rmhmc_model)."""
+
+    def __init__(self, spec: wl.ModelSpec, precision=FP64):
+        terms = (KernelTerm * len(spec.terms))()
+        for t, (kind, cols) in enumerate(spec.terms):
+            terms[t].kind = kind
+            terms[t].ncols = len(cols)
+            for c, col in enumerate(cols):
+                terms[t].cols[c] = col
+        X = np.ascontiguousarray(spec.X, dtype=np.float64)
+        y = np.ascontiguousarray(spec.y, dtype=np.float64)
+        self._keep = (X, y, terms)
+        desc = ModelDesc(spec.N, spec.dx, X.ctypes.data_as(C.POINTER(C.c_double)),
+                         y.ctypes.data_as(C.POINTER(C.c_double)), spec.lik, spec.noise_var,
+                         len(spec.terms), terms, spec.jitter, spec.beta)
+        h = C.c_void_p()
+        _check(_lib.rmhmc_model_create(C.byref(desc), precision, C.byref(h)))
+        self._h = h
+        N, P, D = C.c_int(), C.c_int(), C.c_int()
+        _check(_lib.rmhmc_model_dims(h, C.byref(N), C.byref(P), C.byref(D)))
+        self.N, self.P, self.D = N.value, P.value, D.value
+        self.spec = spec
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.rmhmc_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def hessian(self, q, stream=None):
+        torch = _torch()
+        U = torch.empty(1, dtype=torch.float64, device=q.device)
+        g = torch.empty(self.D, dtype=torch.float64, device=q.device)
+        H = torch.empty((self.D, self.D), dtype=torch.float64, device=q.device)
+        _check(_lib.rmhmc_hessian(self._h, _f64(q), _f64(U), _f64(g), _f64(H), self.D, _stream(stream)))
+        # H is symmetric, so the row-major view equals the column-major matrix
+        return U, g, H
+
+    def metric_grad(self, q, p, Q, lam, alpha, stream=None):
+        """Q: device tensor whose column-major layout holds the eigenvectors,
+        i.e. Q_t[j, i] = Q(i, j) (pass Q.T.contiguous() of a row-major matrix)."""
+        torch = _torch()
+        dq = torch.empty(self.D, dtype=torch.float64, device=q.device)
+        dp = torch.empty(self.D, dtype=torch.float64, device=q.device)
+        ham = torch.empty(1, dtype=torch.float64, device=q.device)
+        _check(_lib.rmhmc_metric_grad(self._h, _f64(q), _f64(p), _f64(Q), _f64(lam), alpha,
+                                      _f64(dq), _f64(dp), _f64(ham), _stream(stream)))
+        return dq, dp, ham
+
+    def chain(self, q0, z, u, eps, n_leapfrog, n_fixed_point, alpha=1e6, zeta=0.0,
+              max_sweeps=0, reorth_every=0, stream=None):
+        torch = _torch()
+        n_moves = z.shape[0]
+        samples = torch.empty((n_moves, self.D), dtype=torch.float64, device=q0.device)
+        logpost = torch.empty(n_moves, dtype=torch.float64, device=q0.device)
+        acc = torch.empty(n_moves, dtype=torch.int32, device=q0.device)
+        cfg = ChainCfg(eps, alpha, zeta, n_leapfrog, n_moves, n_fixed_point, max_sweeps, reorth_every)
+        stats = ChainStats()
+        _check(_lib.rmhmc_chain(self._h, C.byref(cfg), _f64(q0), _f64(z), _f64(u), _f64(samples),
+                                _f64(logpost), _ptr(acc, torch.int32), C.byref(stats),
+                                _stream(stream)))
+        return samples, logpost, acc, stats
+
+
+def softabs_eig(H, alpha, Q_warm=None, zeta=0.0, max_sweeps=0, stream=None):
+    """H: symmetric D x D device tensor.  Returns (Q_colmajor, lam, g, gp, logdetG, sweeps);
+    Q_colmajor[j] is the j-th eigenvector."""
+    torch = _torch()
+    D = H.shape[0]
+    Q = torch.empty((D, D), dtype=torch.float64, device=H.device)
+    lam = torch.empty(D, dtype=torch.float64, device=H.device)
+    g = torch.empty(D, dtype=torch.float64, device=H.device)
+    gp = torch.empty(D, dtype=torch.float64, device=H.device)
+    ld = torch.empty(1, dtype=torch.float64, device=H.device)
+    sw = C.c_int()
+    _check(_lib.rmhmc_softabs_eig(D, _f64(H), D, alpha, zeta, max_sweeps, _f64(Q_warm), _f64(Q),
+                                  _f64(lam), _f64(g), _f64(gp), _f64(ld), C.byref(sw),
+                                  _stream(stream)))
+    return Q, lam, g, gp, ld, sw.value
+
+
+class State:
+    """Device-resident integrator state (rmhmc_state)."""
+
+    def __init__(self, model: Model, q0, p0, alpha=1e6, stream=None):
+        h = C.c_void_p()
+        _check(_lib.rmhmc_state_create(model._h, _f64(q0), _f64(p0), alpha, _stream(stream),
+                                       C.byref(h)))
+        self._h, self.model = h, model
+
+    def step(self, eps, n_fixed_point, stream=None):
+        _check(_lib.rmhmc_glf_step(self.model._h, self._h, eps, n_fixed_point, _stream(stream)))
+
+    def get(self, stream=None):
+        torch = _torch()
+        D = self.model.D
+        q = torch.empty(D, dtype=torch.float64, device="cuda")
+        p = torch.empty(D, dtype=torch.float64, device="cuda")
+        ham = torch.empty(1, dtype=torch.float64, device="cuda")
+        _check(_lib.rmhmc_state_get(self._h, _f64(q), _f64(p), _f64(ham), _stream(stream)))
+        return q, p, ham
+
+    def draw_momentum(self, z, stream=None):
+        """p = Q diag(sqrt g) z at the current point (p ~ N(0, G(q)))."""
+        _check(_lib.rmhmc_state_draw_momentum(self._h, _f64(z), _stream(stream)))
+
+    def set_momentum(self, p, stream=None):
+        _check(_lib.rmhmc_state_set_momentum(self._h, _f64(p), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.rmhmc_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def timing_enable(kinds=("gemm_f64",)):
+    """Time the given kernel families (names of TIMER_KINDS); () switches off."""
+    mask = 0
+    for k in kinds:
+        mask |= 1 << (TIMER_KINDS[k] if isinstance(k, str) else int(k))
+    _check(_lib.rmhmc_timing_enable(mask))
+
+
+def timing_read(kind):
+    """(launches, kernel ms, algorithmic flops, algorithmic bytes) for a kernel family."""
+    n, ms, fl, by = C.c_longlong(), C.c_double(), C.c_double(), C.c_double()
+    _check(_lib.rmhmc_timing_read(TIMER_KINDS[kind] if isinstance(kind, str) else kind,
+                                  C.byref(n), C.byref(ms), C.byref(fl), C.byref(by)))
+    return n.value, ms.value, fl.value, by.value
