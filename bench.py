@@ -39,7 +39,53 @@ def parse():
                     help="skip the per-kernel event timing (use under a profiler)")
     ap.add_argument("--ess-moves", type=int, default=0,
                     help="also run a chain of this many moves and report ESS/s")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--mode", choices=["leapfrog", "tempered", "serve"], default="leapfrog",
+                    help="leapfrog: one chain at D=1038 (default); tempered: 64 power-posterior "
+                         "chains of uneven D on the worker pool; serve: Poisson request stream")
+    ap.add_argument("--chains", type=int, default=64)
+    ap.add_argument("--moves", type=int, default=4, help="moves per chain (tempered mode)")
+    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--rate", type=float, default=20.0, help="requests/s (serve mode)")
+    ap.add_argument("--duration", type=float, default=3.0, help="arrival window in s (serve)")
+    ap.add_argument("--max-moves", type=int, default=4, help="moves per request (serve)")
+    ap.add_argument("--hbm-gb", type=float, default=200.0, help="admission budget (serve)")
     return ap.parse_args()
+
+
+def run_tempered_mode(args):
+    from paper_2511_06407_amd.tempered import run_tempered
+    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)  # noqa: E731
+    out = run_tempered(n_chains=args.chains, n_moves=args.moves, n_leapfrog=10, n_fixed_point=6,
+                       eps=0.01, n_workers=args.workers, seed=args.seed, log=log)
+    dims = [c["D"] for c in out["chains"]]
+    return {"metric": "tempered chains: aggregate chain-leapfrogs/s", "value": out["chain_leapfrogs_per_s"],
+            "unit": "chain-leapfrogs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+            "data": "synthetic", "wall_s": out["wall_s"],
+            "config": {"workload": f"{args.chains} power-posterior chains, beta_k=(k/{args.chains - 1})^5, "
+                                   "D from {66,130,258,514}", "moves": args.moves, "n_leapfrog": 10,
+                       "workers": args.workers, "dims": dims},
+            "accept": [c["accepted"] for c in out["chains"]],
+            "failures": sum(c["failures"] for c in out["chains"])}
+
+
+def run_serve_mode(args):
+    from paper_2511_06407_amd import serving as sv
+    reqs = sv.make_requests(args.rate, args.duration, moves=(1, args.max_moves), seed=args.seed)
+    ex = sv.PoolExecutor(n_workers=args.workers, n_leapfrog=10)
+    sch = sv.Scheduler(ex, args.hbm_gb * 1e9, args.workers)
+    t0 = time.perf_counter()
+    sch.run(reqs)
+    wall = time.perf_counter() - t0
+    ex.close()
+    summ = sv.summarize(reqs, wall)
+    return {"metric": "serving: p50/p99 request latency", "value": summ["p99_latency_s"],
+            "unit": "s (p99 latency)", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
+            "data": "synthetic", **summ, "max_running": sch.max_running,
+            "config": {"workload": "Poisson arrivals, D log-uniform in [34,1038], GP-logistic or "
+                                   "multiple-kernel", "rate_per_s": args.rate,
+                       "duration_s": args.duration, "moves": [1, args.max_moves],
+                       "workers": args.workers, "hbm_budget_gb": args.hbm_gb}}
 
 
 def file_hash(*paths):
@@ -105,8 +151,14 @@ def main():
     import torch
     from paper_2511_06407_amd import rmhmc, workloads as wl
 
+    if args.mode == "tempered":
+        print(json.dumps(run_tempered_mode(args)), flush=True)
+        return
+    if args.mode == "serve":
+        print(json.dumps(run_serve_mode(args)), flush=True)
+        return
     spec, cfg = wl.workload(args.workload, args.seed)
-    model = rmhmc.Model(spec)
+    model = rmhmc.Model(spec, rmhmc.MIXED if args.precision == "mixed" else rmhmc.FP64)
     dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")  # noqa
     z, u = wl.chain_randoms(spec.D, max(args.ess_moves, 1) + 1, seed=args.seed)
     q0 = np.zeros(spec.D)
@@ -168,11 +220,12 @@ def main():
     out = {"metric": "leapfrog steps/sec + ESS/sec at D=1036; p50/p99 request latency",
            "value": value, "unit": "leapfrog steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.precision == "fp64" else "f32+f64",
            "data": "synthetic",
            "config": {"workload": args.workload, "D": spec.D, "N": spec.N, "P": spec.P,
                       "eps": cfg.eps, "n_fixed_point": cfg.n_fixed_point, "alpha": cfg.alpha,
-                      "precision": "fp64", "parallelism": "single GPU"},
+                      "precision": args.precision, "parallelism": "single GPU"},
            "roofline": roofline}
     if ess_block is not None:
         out["ess"] = ess_block

@@ -138,7 +138,9 @@ rmhmc_status rmhmc_state_get(const rmhmc_state* s, double* q, double* p, double*
 rmhmc_status rmhmc_state_set_momentum(rmhmc_state* s, const double* p, hipStream_t stream);
 rmhmc_status rmhmc_state_destroy(rmhmc_state* s);
 /* Momentum draw of Algorithm 1 at the state's current point:
- * p = Q diag(sqrt g) z, i.e. p ~ N(0, G(q)) for z ~ N(0, I).  z [device] D. */
+ * p = G^{1/2} z = Q diag(sqrt g) Q' z, i.e. p ~ N(0, G(q)) for z ~ N(0, I);
+ * the symmetric square root makes p a function of G alone (independent of
+ * eigenvector signs).  z [device] D. */
 rmhmc_status rmhmc_state_draw_momentum(rmhmc_state* s, const double* z, hipStream_t stream);
 
 /* One generalized leapfrog (Sec. 2.2, Eq. leapfrog).  Both implicit
@@ -167,7 +169,7 @@ typedef struct {
   long long sweeps;      /* Jacobi sweeps over all eigendecompositions        */
 } rmhmc_chain_stats;
 
-/* RMHMC chain, Algorithm 1: per move p = Q diag(sqrt g) z (p ~ N(0, G(q))),
+/* RMHMC chain, Algorithm 1: per move p = G^{1/2} z (p ~ N(0, G(q))),
  * C generalized leapfrogs, then Metropolis-Hastings: accept iff
  * log u < H_old - H_new, else restore q and its eigen-state (the printed
  * algorithm restores on the opposite event).  A failure inside a move
@@ -180,6 +182,34 @@ typedef struct {
 rmhmc_status rmhmc_chain(rmhmc_model* m, const rmhmc_chain_cfg* cfg, const double* q0,
                          const double* z, const double* u, double* samples, double* logpost,
                          int* accepted, rmhmc_chain_stats* stats, hipStream_t stream);
+
+/* Concurrent chains: a pool of worker threads, each with its own HIP stream
+ * (default priority), runs rmhmc_chain jobs side by side.  A job submitted
+ * while others run starts as soon as a worker is free and no running job
+ * uses the same model (a model's scratch memory serves one chain at a time),
+ * so requests are admitted continuously rather than in fixed batches.  This
+ * is how many independent chains, e.g. the tempered rungs of the
+ * power-posterior evidence estimate (appendix on model evidence), share the
+ * GPU.  Each job's results are bitwise identical to the same chain run
+ * alone: every kernel reduces in a fixed order.
+ *   rmhmc_pool_submit: same arguments as rmhmc_chain ([device] arrays owned by
+ *     the caller, kept alive until the job is done); *ticket [host] identifies
+ *     the job.  The model must not be destroyed before its jobs finish.
+ *   rmhmc_pool_poll: *done = 0 while queued/running, 1 on success, or the
+ *     job's negative rmhmc_status; wait != 0 blocks until done.  stats and
+ *     times_ms [host, nullable]: times_ms[0..2] = submit, start, end in ms
+ *     since the pool was created.  A finished ticket is released by the poll
+ *     that reports it.
+ *   rmhmc_pool_destroy: waits for running jobs, drops queued ones. */
+typedef struct rmhmc_pool rmhmc_pool;
+rmhmc_status rmhmc_pool_create(int n_workers, rmhmc_pool** out);
+rmhmc_status rmhmc_pool_submit(rmhmc_pool* pool, rmhmc_model* m, const rmhmc_chain_cfg* cfg,
+                               const double* q0, const double* z, const double* u,
+                               double* samples, double* logpost, int* accepted,
+                               long long* ticket);
+rmhmc_status rmhmc_pool_poll(rmhmc_pool* pool, long long ticket, int wait, int* done,
+                             rmhmc_chain_stats* stats, double* times_ms);
+rmhmc_status rmhmc_pool_destroy(rmhmc_pool* pool);
 
 /* Building block exposed for tests and benchmarks: the MFMA GEMM every
  * dense product above runs on.  C = alpha op(A) op(B) + beta C, column-major,

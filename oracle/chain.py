@@ -7,7 +7,10 @@ generalized leapfrogs, then a Metropolis-Hastings test.  The printed test
 restores the old q exactly when r < exp(H_old - H_new), i.e. on the event
 that should *accept*; the standard rule is used here: accept iff
 log r < H_old - H_new, otherwise restore q (and its eigen-state).
-The momentum draw p = Psi diag(sqrt g) z (z ~ N(0, I)) realises N(0, G).
+The momentum draw p = G^{1/2} z = Psi diag(sqrt g) Psi' z (z ~ N(0, I))
+realises N(0, G) with the symmetric square root, which depends on G alone
+(an eigenvector-based draw Psi diag(sqrt g) z would depend on the signs and
+in-cluster rotation of the computed eigenvectors).
 The normals z and uniforms r are inputs, drawn by the shared seeded input
 generator, so the GPU chain and this reference consume identical randomness.
 A failure inside a trajectory (non-finite value, non-positive-definite K)
@@ -22,8 +25,9 @@ from .integrator import glf_step
 
 
 def momentum(st, z):
+    """p = G^{1/2} z with the symmetric square root Psi diag(sqrt g) Psi'."""
     eig = st.eig
-    return eig["Psi"] @ (np.sqrt(eig["g"]) * z)
+    return eig["Psi"] @ (np.sqrt(eig["g"]) * (eig["Psi"].T @ z))
 
 
 def run_chain(target, q0, eps, n_leapfrog, n_fixed_point, alpha, z, u):

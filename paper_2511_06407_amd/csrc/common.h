@@ -115,5 +115,6 @@ void vdot(long n, const double* x, const double* y, double* out, hipStream_t st)
 void set_identity(int n, double* A, long lda, hipStream_t st);
 void copy_matrix(int m, int n, const double* A, long lda, double* B, long ldb, hipStream_t st);
 void cast_to_float(long n, const double* x, float* y, hipStream_t st);
+void widen_to_double(long n, const float* x, double* y, hipStream_t st);
 
 }  // namespace rmhmc

@@ -22,6 +22,9 @@ void eig_load_matrix(int D, const double* H, long ldh, EigWork& w, hipStream_t s
 void eig_load_basis(int D, const double* Q, long ldq, EigWork& w, hipStream_t st);
 // Jacobi on w.M, rotations accumulated into w.Psi; converged matrix left in w.M.
 void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int* sweeps_out, hipStream_t st);
+// Rayleigh quotients lam_i = psi_i' H psi_i of the converged basis against the
+// original H (D x D, ldh), written to diag(w.M); Z is Dp x Dp scratch.
+void rayleigh_refine(int D, const double* H, long ldh, EigWork& w, double* Z, hipStream_t st);
 void softabs_finalize(int D, const double* M, long ldm, double alpha, double* lam, double* g,
                       double* gp, double* logdetG, hipStream_t st);
 // M1(j,k) = T_jk b_j b_k with T the divided differences of g.

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
   __shared__ double V[SB][SB + 1];
   __shared__ double rc[SB / 2], rs[SB / 2], rt[SB / 2];
   __shared__ int rp[SB / 2], rq[SB / 2];
-  __shared__ int any;
+  __shared__ int any;   // a significant rotation happened in this inner sweep
   __shared__ double red[4];
   const int nb = Dp / HB;
   const int slot = blockIdx.x;
@@ -61,10 +61,12 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
   for (int o = 32; o > 0; o >>= 1) ss += __shfl_down(ss, o, 64);
   if ((tid & 63) == 0) red[tid >> 6] = ss;
   __syncthreads();
-  // Skip rotations whose off-diagonal entry is below 1e-15 ||S||_F: above the
-  // rounding noise the rotations themselves leave behind (~1e-16 ||S||), so
-  // the inner sweeps stop once the subproblem is diagonal to working accuracy.
-  const double thr = fmax(1e-15 * sqrt(red[0] + red[1] + red[2] + red[3]), 1e-300);
+  // Skip a rotation when |a_pq| <= 1e-16 sqrt(|a_pp a_qq|) (relative
+  // criterion, so eigenvectors of small eigenvalues stay accurate next to
+  // large ones), with an absolute floor of 1e-30 ||S||_F.  Rounding in the
+  // off-diagonal updates scales with the off-diagonal entries themselves, so
+  // the inner sweeps reach this test after a few quadratic steps.
+  const double thr = fmax(1e-30 * sqrt(red[0] + red[1] + red[2] + red[3]), 1e-300);
   for (int sweep = 0; sweep < max_inner; ++sweep) {
     if (tid == 0) any = 0;
     __syncthreads();
@@ -73,12 +75,13 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
         const int p = rr_player(ir, tid, SB), q = rr_player(ir, SB - 1 - tid, SB);
         const double app = S[p][p], aqq = S[q][q], apq = S[p][q];
         double c = 1.0, s = 0.0, t = 0.0;
-        if (fabs(apq) > thr) {
+        const double scale = sqrt(fabs(app * aqq));
+        if (fabs(apq) > fmax(thr, 1e-16 * scale)) {
           const double zeta = (aqq - app) / (2.0 * apq);
           t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           c = 1.0 / sqrt(1.0 + t * t);
           s = t * c;
-          any = 1;
+          if (fabs(apq) > fmax(thr, 1e-8 * scale)) any = 1;
         }
         rc[tid] = c; rs[tid] = s; rt[tid] = t; rp[tid] = p; rq[tid] = q;
       }
@@ -114,6 +117,8 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
       }
       __syncthreads();
     }
+    // start another inner sweep only after a significant rotation; residues
+    // below 1e-8 of the diagonal scale are removed by later outer sweeps
     if (!any) break;
   }
   double* out = Vbuf + (long)slot * SB * SB;
@@ -202,49 +207,67 @@ __global__ __launch_bounds__(256) void jacobi_apply_kernel(int Dp, int round,
   }
 }
 
-// Partial sums of (off-diagonal squares, all squares) per 64-column chunk.
+// Per 64-column chunk: off-diagonal squares, all squares, and the largest
+// relative off-diagonal |m_ij| / sqrt(|m_ii m_jj|).
 __global__ __launch_bounds__(256) void offnorm_kernel(int Dp, const double* __restrict__ M,
                                                       double* __restrict__ part) {
-  __shared__ double sh[2][4];
+  __shared__ double sh[3][4];
   const int c0 = blockIdx.x * 64;
-  double off = 0.0, tot = 0.0;
-  for (int j = c0; j < c0 + 64; ++j)
+  double off = 0.0, tot = 0.0, rel = 0.0;
+  for (int j = c0; j < c0 + 64; ++j) {
+    const double djj = fabs(M[j + (long)j * Dp]);
     for (int i = threadIdx.x; i < Dp; i += 256) {
       const double v = M[i + (long)j * Dp];
       tot += v * v;
-      if (i != j) off += v * v;
+      if (i != j && v != 0.0) {
+        off += v * v;
+        const double den = sqrt(fabs(M[i + (long)i * Dp]) * djj);
+        rel = fmax(rel, den > 0.0 ? fabs(v) / den : INFINITY);
+      }
     }
+  }
   for (int o = 32; o > 0; o >>= 1) {
     off += __shfl_down(off, o, 64);
     tot += __shfl_down(tot, o, 64);
+    rel = fmax(rel, __shfl_down(rel, o, 64));
   }
   if ((threadIdx.x & 63) == 0) {
     sh[0][threadIdx.x >> 6] = off;
     sh[1][threadIdx.x >> 6] = tot;
+    sh[2][threadIdx.x >> 6] = rel;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
-    part[2 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    part[3 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    part[3 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    part[3 * blockIdx.x + 2] = fmax(fmax(sh[2][0], sh[2][1]), fmax(sh[2][2], sh[2][3]));
   }
 }
 
 // ctrl[0] = ||M||_F (set on the first check), ctrl[1] = converged flag,
-// ctrl[2] = last off/||M|| ratio, ctrl[3] = number of checks.
+// ctrl[2] = last off/||M|| ratio, ctrl[3] = number of checks, ctrl[4] = 1 if
+// the norm-wise test already held at the previous check.
+// Converged: off(M)_F <= zeta ||M||_F (the stated tolerance) and either every
+// off-diagonal is below 1e-12 of the geometric mean of its diagonals or the
+// norm-wise test also held one sweep earlier (one polishing sweep at most).
 __global__ void offnorm_finish_kernel(int nparts, const double* __restrict__ part, double zeta,
                                       double* __restrict__ ctrl, int first) {
   if (threadIdx.x != 0) return;
-  double off = 0.0, tot = 0.0;
+  double off = 0.0, tot = 0.0, rel = 0.0;
   for (int p = 0; p < nparts; ++p) {
-    off += part[2 * p];
-    tot += part[2 * p + 1];
+    off += part[3 * p];
+    tot += part[3 * p + 1];
+    rel = fmax(rel, part[3 * p + 2]);
   }
   const double nrm = sqrt(tot);
   if (first) ctrl[0] = nrm;
   const double r = nrm > 0.0 ? sqrt(off) / nrm : 0.0;
   ctrl[2] = r;
   ctrl[3] += 1.0;
-  ctrl[1] = (sqrt(off) <= zeta * nrm || !(nrm > 0.0)) ? 1.0 : 0.0;
+  const bool normwise = sqrt(off) <= zeta * nrm || !(nrm > 0.0);
+  const bool done = normwise && (rel <= 1e-12 || off == 0.0 || ctrl[4] != 0.0);
+  ctrl[4] = normwise ? 1.0 : 0.0;
+  ctrl[1] = done ? 1.0 : 0.0;
 }
 
 // ------------------------------------------------------------ softabs g, g'
@@ -377,6 +400,20 @@ __global__ void vec_scale_kernel(int n, const double* __restrict__ x, const doub
   y[i] = s;
 }
 
+// lam_i = psi_i' H psi_i from Z = H Psi (column dots), overwriting diag(M).
+__global__ __launch_bounds__(256) void rayleigh_kernel(int D, int Dp, const double* __restrict__ Psi,
+                                                       const double* __restrict__ Z,
+                                                       double* __restrict__ M) {
+  __shared__ double sh[4];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < D; k += 256) s += Psi[k + (long)j * Dp] * Z[k + (long)j * Dp];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) M[j + (long)j * Dp] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
 __global__ void pad_copy_kernel(int D, int Dp, const double* __restrict__ H, long ldh,
                                 double* __restrict__ M) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -403,7 +440,7 @@ int eig_padded_dim(int D) { return ((D + SB - 1) / SB) * SB; }
 void eig_workspace_sizes(int D, long* doubles) {
   const int Dp = eig_padded_dim(D);
   const int nb = Dp / HB;
-  *doubles = 3L * Dp * Dp + (long)(nb / 2) * SB * SB + 2L * (Dp / 64 + 1) + 8;
+  *doubles = 3L * Dp * Dp + (long)(nb / 2) * SB * SB + 3L * (Dp / 64 + 1) + 8;
 }
 
 void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int* sweeps_out, hipStream_t st) {
@@ -413,7 +450,7 @@ void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int* sweeps_out,
   const int nparts = Dp / 64;
   double* Min = w.M;
   double* Mout = w.M2;
-  RM_HIP(hipMemsetAsync(w.ctrl, 0, 4 * sizeof(double), st));
+  RM_HIP(hipMemsetAsync(w.ctrl, 0, 8 * sizeof(double), st));
   hipLaunchKernelGGL(offnorm_kernel, dim3(nparts), dim3(256), 0, st, Dp, (const double*)Min, w.part);
   RM_CHECK_LAUNCH();
   hipLaunchKernelGGL(offnorm_finish_kernel, dim3(1), dim3(64), 0, st, nparts, (const double*)w.part,
@@ -431,7 +468,7 @@ void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int* sweeps_out,
     for (int r = 0; r < nb - 1; ++r) {
       int slot = timing_begin(TK_JACOBI_SOLVE, st);
       hipLaunchKernelGGL(jacobi_solve_kernel, dim3(ns), dim3(256), 0, st, Dp, r,
-                         (const double*)Min, w.V, (const double*)w.ctrl, 12);
+                         (const double*)Min, w.V, (const double*)w.ctrl, 4);
       RM_CHECK_LAUNCH();
       // one inner sweep of a 64x64 subproblem: 63 rounds x (1024 2x2 blocks x 24
       // flops + 2048 V row pairs x 6 flops); bytes: subproblems in, rotations out
@@ -472,6 +509,20 @@ void eig_load_basis(int D, const double* Q, long ldq, EigWork& w, hipStream_t st
   const int Dp = eig_padded_dim(D);
   const long n = (long)Dp * Dp;
   hipLaunchKernelGGL(pad_identity_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, D, Dp, Q, ldq, w.Psi);
+  RM_CHECK_LAUNCH();
+}
+
+void rayleigh_refine(int D, const double* H, long ldh, EigWork& w, double* Z, hipStream_t st) {
+  // Z = H Psi on the leading D x D block, then diag(M) <- column dots
+  const int Dp = eig_padded_dim(D);
+  Gemm<double> g;
+  g.m = D; g.n = D; g.k = D;
+  g.A = H; g.lda = ldh;
+  g.B = w.Psi; g.ldb = Dp;
+  g.C = Z; g.ldc = Dp;
+  gemm(g, st);
+  hipLaunchKernelGGL(rayleigh_kernel, dim3(D), dim3(256), 0, st, D, Dp, (const double*)w.Psi,
+                     (const double*)Z, w.M);
   RM_CHECK_LAUNCH();
 }
 

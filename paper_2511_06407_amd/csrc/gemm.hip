@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
 
   // Epilogue.  acc[ti][tj][r] = C(m, n) with m = mbase + lane%16,
   // n = nbase + row(lane, r) (the MFMA row index is our n).
-  if (p.ksplit > 1) {
+  if (p.part) {
     T* part = p.part + (long)kc * M * N;
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)

@@ -6,6 +6,8 @@
 //   K_lmn = K (c_l c_m c_n + c_lm c_n + c_ln c_m + c_mn c_l + c_lmn),
 // with log K = 2 eta_s - sum_g u_g / 2, u_g = r_g^2 exp(-2 eta_g), so
 // c_s = 2, c_g = u_g, c_gg = -2 u_g, c_ggg = 4 u_g and all other entries 0.
+#include <algorithm>
+
 #include "gp.h"
 
 namespace rmhmc {
@@ -236,11 +238,32 @@ void kgen(const ModelDev& md, const double* eta, double* K, double* K1, hipStrea
   RM_CHECK_LAUNCH();
 }
 
+static void kd_wsum_chunk(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
+                          int mode, const double* Kinv, const double* alpha, const double* Wstack,
+                          int nw, double* out, double* work, hipStream_t st);
+
 void kd_wsum(const ModelDev& md, const double* eta, const Tuple* tuples, int nt, int mode,
              const double* Kinv, const double* alpha, const double* Wstack, int nw, double* out,
              double* work, hipStream_t st) {
+  // out is nw x nt (row w); chunks of at most MAX_TUPLES tuples write their columns
+  if (nt <= MAX_TUPLES) {
+    kd_wsum_chunk(md, eta, tuples, nt, mode, Kinv, alpha, Wstack, nw, out, work, st);
+    return;
+  }
+  double* tmp = work + 512L * MAX_P * MAX_TUPLES;
+  for (int t0 = 0; t0 < nt; t0 += MAX_TUPLES) {
+    const int c = std::min(MAX_TUPLES, nt - t0);
+    kd_wsum_chunk(md, eta, tuples + t0, c, mode, Kinv, alpha, Wstack, nw, tmp, work, st);
+    for (int w = 0; w < nw; ++w)
+      RM_HIP(hipMemcpyAsync(out + (long)w * nt + t0, tmp + (long)w * c, c * sizeof(double),
+                            hipMemcpyDeviceToDevice, st));
+  }
+}
+
+static void kd_wsum_chunk(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
+                          int mode, const double* Kinv, const double* alpha, const double* Wstack,
+                          int nw, double* out, double* work, hipStream_t st) {
   if (nt <= 0 || nw <= 0) return;
-  RM_REQUIRE(nt <= MAX_TUPLES, "kd_wsum: too many derivative tuples");
   const long NN = (long)md.N * md.N;
   int nblk = cdiv(NN, 256 * 16);
   if (nblk > 512) nblk = 512;
@@ -258,7 +281,12 @@ void kd_wsum(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
 void kd_matvec(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
                const double* x, int nx, double* y, hipStream_t st) {
   if (nt <= 0 || nx <= 0) return;
-  RM_REQUIRE(nt <= MAX_TUPLES, "kd_matvec: too many derivative tuples");
+  RM_REQUIRE(nt <= MAX_TUPLES || nx == 1, "kd_matvec: chunked tuples need a single vector");
+  if (nt > MAX_TUPLES) {
+    for (int t0 = 0; t0 < nt; t0 += MAX_TUPLES)
+      kd_matvec(md, eta, tuples + t0, std::min(MAX_TUPLES, nt - t0), x, 1, y + (long)t0 * md.N, st);
+    return;
+  }
   const int slot = timing_begin(TK_KD_MATVEC, st);
   hipLaunchKernelGGL(kd_matvec_kernel, dim3(cdiv(md.N, 64), nx), dim3(256), 0, st, md, eta,
                      tuples, nt, x, y);

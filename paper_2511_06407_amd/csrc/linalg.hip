@@ -289,6 +289,10 @@ __global__ void cast_kernel(long n, const double* x, float* y) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = (float)x[i];
 }
+__global__ void widen_kernel(long n, const float* x, double* y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (double)x[i];
+}
 
 }  // namespace
 
@@ -428,6 +432,11 @@ void copy_matrix(int m, int n, const double* A, long lda, double* B, long ldb, h
 void cast_to_float(long n, const double* x, float* y, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(cast_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, n, x, y);
+  RM_CHECK_LAUNCH();
+}
+void widen_to_double(long n, const float* x, double* y, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(widen_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, n, x, y);
   RM_CHECK_LAUNCH();
 }
 

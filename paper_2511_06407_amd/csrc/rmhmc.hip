@@ -14,10 +14,16 @@
 // Everything a point q needs is cached in a Point; a leapfrog moves between
 // three Points (move start, and two alternating trial points).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -255,7 +261,9 @@ struct Model {
   int* hflag = nullptr;
   struct Point* api_pt = nullptr;
   std::unique_ptr<struct Point> api_pt_own;
+  std::unique_ptr<struct State> chain_state;
   long reorth_every = 10;
+  ~Model();
 };
 
 struct Point {
@@ -267,6 +275,11 @@ struct Point {
   double *trK1, *kla, *phiK2, *trAA, *ak;
   const double **Yap, **Ybp;
   double** Ycp;
+  // mixed precision: FP32 copies feeding the FP32 MFMA products
+  float *Kinvf = nullptr, *K1f = nullptr, *Af = nullptr, *Atf = nullptr, *Bf = nullptr,
+        *Ytf = nullptr;
+  const float **Yapf = nullptr, **Ybpf = nullptr;
+  float** Ycpf = nullptr;
   bool have_pre = false, have_vW2 = false, have_eig = false;
   long updates_since_reorth = 0;
   // scal: [0] log|K|, [1] U, [2] log|G|, [3] sum l, [4] f.alpha, [5] ham
@@ -298,7 +311,7 @@ std::unique_ptr<Point> new_point(Model& m) {
   p.g = pl.alloc<double>(Dp);
   p.gp = pl.alloc<double>(Dp);
   p.B = pl.alloc<double>(P * NN);
-  p.Yt = pl.alloc<double>((long)m.nyy * NN);
+  p.Yt = pl.alloc<double>(m.prec == RMHMC_MIXED ? 1 : (long)m.nyy * NN);
   p.k2a = pl.alloc<double>((long)std::max(m.npairs, 1) * N);
   p.ik2a = pl.alloc<double>((long)std::max(m.npairs, 1) * N);
   p.c1a = pl.alloc<double>(P * P * N);
@@ -317,7 +330,8 @@ std::unique_ptr<Point> new_point(Model& m) {
     for (int mm = l; mm < m.P; ++mm) {
       ya.push_back(p.A + l * NN);
       yb.push_back(p.A + mm * NN);
-      yc.push_back(p.Yt + (long)m.yidx_h[l * m.P + mm] * NN);
+      yc.push_back(m.prec == RMHMC_MIXED ? p.Yt
+                                         : p.Yt + (long)m.yidx_h[l * m.P + mm] * NN);
     }
   p.Yap = (const double**)pl.alloc<double*>(ya.size());
   p.Ybp = (const double**)pl.alloc<double*>(yb.size());
@@ -325,6 +339,28 @@ std::unique_ptr<Point> new_point(Model& m) {
   RM_HIP(hipMemcpy((void*)p.Yap, ya.data(), ya.size() * sizeof(void*), hipMemcpyHostToDevice));
   RM_HIP(hipMemcpy((void*)p.Ybp, yb.data(), yb.size() * sizeof(void*), hipMemcpyHostToDevice));
   RM_HIP(hipMemcpy((void*)p.Ycp, yc.data(), yc.size() * sizeof(void*), hipMemcpyHostToDevice));
+  if (m.prec == RMHMC_MIXED) {
+    p.Kinvf = pl.alloc<float>(NN);
+    p.K1f = pl.alloc<float>(P * NN);
+    p.Af = pl.alloc<float>(P * NN);
+    p.Atf = pl.alloc<float>(P * NN);
+    p.Bf = pl.alloc<float>(P * NN);
+    p.Ytf = pl.alloc<float>((long)m.nyy * NN);
+    std::vector<const float*> fa, fb;
+    std::vector<float*> fc;
+    for (int l = 0; l < m.P; ++l)
+      for (int mm = l; mm < m.P; ++mm) {
+        fa.push_back(p.Af + l * NN);
+        fb.push_back(p.Af + mm * NN);
+        fc.push_back(p.Ytf + (long)m.yidx_h[l * m.P + mm] * NN);
+      }
+    p.Yapf = (const float**)pl.alloc<float*>(fa.size());
+    p.Ybpf = (const float**)pl.alloc<float*>(fb.size());
+    p.Ycpf = pl.alloc<float*>(fc.size());
+    RM_HIP(hipMemcpy((void*)p.Yapf, fa.data(), fa.size() * sizeof(void*), hipMemcpyHostToDevice));
+    RM_HIP(hipMemcpy((void*)p.Ybpf, fb.data(), fb.size() * sizeof(void*), hipMemcpyHostToDevice));
+    RM_HIP(hipMemcpy((void*)p.Ycpf, fc.data(), fc.size() * sizeof(void*), hipMemcpyHostToDevice));
+  }
   RM_HIP(hipMemset(p.scal, 0, 8 * sizeof(double)));
   return pt;
 }
@@ -348,7 +384,8 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st) {
   chol_inverse(N, pt.K, pt.Kinv, pt.scal + 0, m.chol, nullptr, st);
   gemv(N, N, 1.0, pt.Kinv, N, false, 0, pt.q, 0, 0.0, pt.alpha, 0, 1, st);
   lik_derivs(N, m.lik, m.noise_var, pt.q, m.y, pt.lik, st);
-  {  // A_l = K^-1 K_l, and the transposed copies
+  const bool mixed = m.prec == RMHMC_MIXED;
+  if (!mixed) {  // A_l = K^-1 K_l, and the transposed copies
     Gemm<double> g;
     g.m = N; g.n = N; g.k = N;
     g.A = pt.Kinv; g.lda = N;
@@ -357,6 +394,18 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st) {
     g.C2 = pt.At; g.ldc2 = N; g.sC2 = NN;
     g.batch = P;
     gemm(g, st);
+  } else {       // the same products on the FP32 matrix cores, FP32 accumulation
+    cast_to_float(NN, pt.Kinv, pt.Kinvf, st);
+    cast_to_float(P * NN, pt.K1, pt.K1f, st);
+    Gemm<float> g;
+    g.m = N; g.n = N; g.k = N;
+    g.A = pt.Kinvf; g.lda = N;
+    g.B = pt.K1f; g.ldb = N; g.sB = NN;
+    g.C = pt.Af; g.ldc = N; g.sC = NN;
+    g.C2 = pt.Atf; g.ldc2 = N; g.sC2 = NN;
+    g.batch = P;
+    gemm(g, st);
+    widen_to_double(P * NN, pt.Af, pt.A, st);
   }
   gemv(N, N, 1.0, pt.A, N, false, NN, pt.alpha, 0, 0.0, pt.a, N, P, st);
   gemv(N, N, 1.0, pt.K1, N, false, NN, pt.alpha, 0, 0.0, pt.k1a, N, P, st);
@@ -364,7 +413,10 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st) {
   pair_dots(N, pt.k1a, N, P, pt.a, N, P, pt.kla, st);
   pair_dots(N, pt.alpha, 0, 1, pt.k1a, N, P, pt.ak, st);
   kd_wsum(m.md, eta, m.pairs, m.npairs, 0, pt.Kinv, pt.alpha, nullptr, 1, pt.phiK2, m.kdwork, st);
-  gemm_tallk(P, P, NN, pt.A, NN, pt.At, NN, pt.trAA, P, m.tallwork, tallk_splits(NN), st);
+  if (!mixed)
+    gemm_tallk(P, P, NN, pt.A, NN, pt.At, NN, pt.trAA, P, m.tallwork, tallk_splits(NN), st);
+  else
+    gemm_tallk(P, P, NN, pt.Af, NN, pt.Atf, NN, pt.trAA, P, m.tallwork, tallk_splits(NN), st);
   vsum(N, pt.lik, pt.scal + 3, st);
   vdot(N, pt.q, pt.alpha, pt.scal + 4, st);
   hipLaunchKernelGGL(assemble_H_kernel, dim3(cdiv((long)m.Dp * m.Dp, 256)), dim3(256), 0, st, N, P,
@@ -435,6 +487,7 @@ int compute_eig(Model& m, Point& pt, Point* warm, double alpha, double zeta, int
   }
   int sweeps = 0;
   jacobi_eig(D, m.eig, zeta, max_sweeps, &sweeps, st);
+  rayleigh_refine(D, pt.H, Dp, m.eig, m.Wt2, st);
   copy(pt.Psi, m.eig.Psi, (long)Dp * Dp, st);
   softabs_finalize(D, m.eig.M, Dp, alpha, pt.lam, pt.g, pt.gp, pt.scal + 2, st);
   pt.have_eig = true;
@@ -448,26 +501,49 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
   const int N = m.N, P = m.P;
   const long NN = (long)N * N;
   const double* eta = pt.q + N;
-  {  // B_l = A_l K^-1
-    Gemm<double> g;
-    g.m = N; g.n = N; g.k = N;
-    g.A = pt.A; g.lda = N; g.sA = NN;
-    g.B = pt.Kinv; g.ldb = N;
-    g.C = pt.B; g.ldc = N; g.sC = NN;
-    g.batch = P;
-    gemm(g, st);
+  if (m.prec != RMHMC_MIXED) {
+    {  // B_l = A_l K^-1
+      Gemm<double> g;
+      g.m = N; g.n = N; g.k = N;
+      g.A = pt.A; g.lda = N; g.sA = NN;
+      g.B = pt.Kinv; g.ldb = N;
+      g.C = pt.B; g.ldc = N; g.sC = NN;
+      g.batch = P;
+      gemm(g, st);
+    }
+    {  // Y_lm = A_l A_m (l <= m), stored transposed
+      Gemm<double> g;
+      g.m = N; g.n = N; g.k = N;
+      g.Ap = pt.Yap; g.lda = N;
+      g.Bp = pt.Ybp; g.ldb = N;
+      g.C2p = pt.Ycp; g.ldc2 = N;
+      g.batch = m.nyy;
+      gemm(g, st);
+    }
+    // tau[n, (l,m)] = tr(A_n A_l A_m) = <A_n, Y_lm'>
+    gemm_tallk(P, m.nyy, NN, pt.A, NN, pt.Yt, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
+  } else {
+    {
+      Gemm<float> g;
+      g.m = N; g.n = N; g.k = N;
+      g.A = pt.Af; g.lda = N; g.sA = NN;
+      g.B = pt.Kinvf; g.ldb = N;
+      g.C = pt.Bf; g.ldc = N; g.sC = NN;
+      g.batch = P;
+      gemm(g, st);
+      widen_to_double(P * NN, pt.Bf, pt.B, st);
+    }
+    {
+      Gemm<float> g;
+      g.m = N; g.n = N; g.k = N;
+      g.Ap = pt.Yapf; g.lda = N;
+      g.Bp = pt.Ybpf; g.ldb = N;
+      g.C2p = pt.Ycpf; g.ldc2 = N;
+      g.batch = m.nyy;
+      gemm(g, st);
+    }
+    gemm_tallk(P, m.nyy, NN, pt.Af, NN, pt.Ytf, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
   }
-  {  // Y_lm = A_l A_m (l <= m), stored transposed
-    Gemm<double> g;
-    g.m = N; g.n = N; g.k = N;
-    g.Ap = pt.Yap; g.lda = N;
-    g.Bp = pt.Ybp; g.ldb = N;
-    g.C2p = pt.Ycp; g.ldc2 = N;
-    g.batch = m.nyy;
-    gemm(g, st);
-  }
-  // tau[n, (l,m)] = tr(A_n A_l A_m) = <A_n, Y_lm'>
-  gemm_tallk(P, m.nyy, NN, pt.A, NN, pt.Yt, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
   kd_matvec(m.md, eta, m.pairs, m.npairs, pt.alpha, 1, pt.k2a, st);
   {
     Gemm<double> g;  // ik2a = K^-1 [K_lm alpha]
@@ -640,11 +716,20 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   m.pidx_h.assign(P * P, -1);
   m.tidx_h.assign(P * P * P, -1);
   m.yidx_h.assign(P * P, -1);
+  // a derivative tuple is structurally non-zero only within one term, and
+  // for linear-ARD and same-value terms only when all indices coincide
+  auto nonzero = [&](int a, int b, int c) {
+    const int t = md.param_term[a];
+    if (md.param_term[b] != t || md.param_term[c] != t) return false;
+    const int kind = md.terms[t].kind;
+    if (kind == RMHMC_K_SE_ISO || kind == RMHMC_K_SE_ARD) return true;
+    return a == b && b == c;
+  };
   for (int l = 0; l < P; ++l)
     for (int mm = l; mm < P; ++mm) {
       const int y = (int)(l * P - l * (l - 1) / 2 + (mm - l));
       m.yidx_h[l * P + mm] = m.yidx_h[mm * P + l] = y;
-      if (md.param_term[l] != md.param_term[mm]) continue;
+      if (!nonzero(l, mm, mm)) continue;
       const int idx = (int)m.pairs_h.size();
       m.pairs_h.push_back({2, l, mm, 0});
       m.pidx_h[l * P + mm] = m.pidx_h[mm * P + l] = idx;
@@ -653,7 +738,7 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   for (int l = 0; l < P; ++l)
     for (int mm = l; mm < P; ++mm)
       for (int n = mm; n < P; ++n) {
-        if (md.param_term[l] != md.param_term[mm] || md.param_term[l] != md.param_term[n]) continue;
+        if (!nonzero(l, mm, n)) continue;
         const int idx = (int)m.triples_h.size();
         m.triples_h.push_back({3, l, mm, n});
         const int perm[6][3] = {{l, mm, n}, {l, n, mm}, {mm, l, n}, {mm, n, l}, {n, l, mm}, {n, mm, l}};
@@ -661,8 +746,6 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
       }
   m.npairs = (int)m.pairs_h.size();
   m.ntriples = (int)m.triples_h.size();
-  RM_REQUIRE(m.npairs <= MAX_TUPLES && m.ntriples <= MAX_TUPLES,
-             "kernel terms with too many hyperparameters for the on-the-fly derivative kernels");
   Pool& pl = m.pool;
   const long N = m.N, NN = N * N, Dp = m.Dp;
   // data, column-major on the device
@@ -694,12 +777,12 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   m.eig.M2 = pl.alloc<double>(Dp * Dp);
   m.eig.Psi = pl.alloc<double>(Dp * Dp);
   m.eig.V = pl.alloc<double>((Dp / 64) * 64 * 64);
-  m.eig.part = pl.alloc<double>(2 * (Dp / 64 + 1));
-  m.eig.ctrl = pl.alloc<double>(4);
+  m.eig.part = pl.alloc<double>(3 * (Dp / 64 + 1));
+  m.eig.ctrl = pl.alloc<double>(8);
   m.eig.ctrl_host = pl.alloc_host<double>(4);
   const int spl = tallk_splits(NN);
   m.tallwork = pl.alloc<double>((long)spl * P * std::max(P, m.nyy) + 64);
-  m.kdwork = pl.alloc<double>(512L * std::max(P, 1) * MAX_TUPLES);
+  m.kdwork = pl.alloc<double>(512L * MAX_P * MAX_TUPLES + (long)MAX_P * std::max(m.ntriples, m.npairs) + 64);
   m.mdwork = pl.alloc<double>((long)(std::max<long>(N, Dp) / 4 + 2) * 32);
   m.W = pl.alloc<double>(Dp * Dp);
   m.Wt1 = pl.alloc<double>(Dp * Dp);
@@ -732,6 +815,8 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
 
 // ------------------------------------------------------------ integrator state
 
+}  // namespace
+
 struct State {
   Pool pool;
   Model* m;
@@ -742,6 +827,8 @@ struct State {
   double *p, *ph, *v0, *vk, *gq, *qk, *ham;
   long leapfrogs = 0, eig_calls = 0, sweeps = 0;
 };
+
+namespace {
 
 std::unique_ptr<State> make_state(Model& m, double alpha) {
   auto s = std::make_unique<State>();
@@ -762,6 +849,21 @@ std::unique_ptr<State> make_state(Model& m, double alpha) {
   s->qk = pl.alloc<double>(m.D);
   s->ham = pl.alloc<double>(2);
   return s;
+}
+
+}  // namespace
+
+Model::~Model() = default;
+
+namespace {
+
+// p = G^{1/2} z = Psi diag(sqrt g) Psi' z: p ~ N(0, G(q)) for z ~ N(0, I)
+// (Algorithm 1's momentum draw).  The symmetric square root depends on G
+// alone, not on the signs or the in-cluster rotation of the eigenvectors.
+void draw_momentum(Model& m, State& S, Point& pt, const double* z, hipStream_t st) {
+  gemv(m.D, m.D, 1.0, pt.Psi, m.Dp, true, 0, z, 0, 0.0, S.v0, 0, 1, st);
+  vec_scale(m.D, S.v0, pt.g, nullptr, true, S.vk, st);
+  gemv(m.D, m.D, 1.0, pt.Psi, m.Dp, false, 0, S.vk, 0, 0.0, S.p, 0, 1, st);
 }
 
 // One generalized leapfrog from cur with momentum s.p; trial points alternate
@@ -807,13 +909,182 @@ Point* leapfrog(State& s, Point* cur, Point* keep, double eps, int K, hipStream_
 }  // namespace
 }  // namespace rmhmc
 
+namespace rmhmc {
+namespace {
+
+// ------------------------------------------------------------ chain (Algorithm 1)
+
+void chain_impl(Model& m, const rmhmc_chain_cfg* cfg, const double* q0, const double* z,
+                const double* u, double* samples, double* logpost, int* accepted,
+                rmhmc_chain_stats* stats, hipStream_t st) {
+  RM_REQUIRE(cfg && q0 && z && u && samples && logpost && accepted, "NULL argument");
+  RM_REQUIRE(cfg->n_leapfrog >= 1 && cfg->n_moves >= 1 && cfg->n_fixed_point >= 1,
+             "n_leapfrog, n_moves and n_fixed_point must be >= 1");
+  RM_REQUIRE(std::isfinite(cfg->eps) && cfg->eps > 0.0, "eps must be positive");
+  RM_REQUIRE(std::isfinite(cfg->alpha) && cfg->alpha > 0.0, "alpha must be positive");
+  const int D = m.D;
+  m.reorth_every = cfg->reorth_every > 0 ? cfg->reorth_every : 10;
+  // the chain state (three Points) is allocated once per model and reused
+  if (!m.chain_state) m.chain_state = make_state(m, cfg->alpha);
+  State& S = *m.chain_state;
+  S.alpha = cfg->alpha;
+  S.zeta = cfg->zeta > 0.0 ? cfg->zeta : 1e-13;
+  S.max_sweeps = cfg->max_sweeps > 0 ? cfg->max_sweeps : 60;
+  S.leapfrogs = S.eig_calls = S.sweeps = 0;
+  std::vector<double> uh(cfg->n_moves);
+  RM_HIP(hipMemcpyAsync(uh.data(), u, cfg->n_moves * sizeof(double), hipMemcpyDeviceToHost, st));
+  copy(S.pts[0]->q, q0, D, st);
+  check_flag_nonfinite(m, S.pts[0]->q, D, st, "q0");
+  int sw = 0;
+  full_point(m, *S.pts[0], nullptr, cfg->alpha, S.zeta, S.max_sweeps, st, &sw);
+  S.sweeps += sw;
+  S.eig_calls += 1;
+  int n_acc = 0, n_fail = 0;
+  for (int ell = 0; ell < cfg->n_moves; ++ell) {
+    Point* start = S.pts[0];
+    draw_momentum(m, S, *start, z + (long)ell * D, st);
+    metric_vectors(m, *start, S.p, nullptr, S.ham, st);
+    bool ok = true;
+    Point* cur = start;
+    try {
+      for (int c = 0; c < cfg->n_leapfrog; ++c)
+        cur = leapfrog(S, cur, start, cfg->eps, cfg->n_fixed_point, st);
+      metric_vectors(m, *cur, S.p, nullptr, S.ham + 1, st);
+    } catch (const Error& e) {
+      if (e.status == RMHMC_E_HIP || e.status == RMHMC_E_ARG || e.status == RMHMC_E_NOMEM) throw;
+      ok = false;
+    }
+    RM_HIP(hipMemcpyAsync(m.hscal, S.ham, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    RM_HIP(hipStreamSynchronize(st));
+    const double h0 = m.hscal[0], h1 = m.hscal[1];
+    const bool acc = ok && std::isfinite(h1) && std::isfinite(h0) && std::log(uh[ell]) < h0 - h1;
+    if (!ok) ++n_fail;
+    if (acc) {
+      ++n_acc;
+      for (int i = 1; i < 3; ++i)
+        if (S.pts[i] == cur) std::swap(S.pts[0], S.pts[i]);
+    }
+    hipLaunchKernelGGL(store_sample_kernel, dim3(cdiv(D, 256)), dim3(256), 0, st, D,
+                       (const double*)S.pts[0]->q, (const double*)(S.pts[0]->scal + 1),
+                       samples + (long)ell * D, logpost + ell, accepted + ell, acc ? 1 : 0);
+    RM_CHECK_LAUNCH();
+  }
+  RM_HIP(hipStreamSynchronize(st));
+  if (stats) {
+    stats->accepted = n_acc;
+    stats->failures = n_fail;
+    stats->leapfrogs = S.leapfrogs;
+    stats->eig_calls = S.eig_calls;
+    stats->sweeps = S.sweeps;
+  }
+}
+
+}  // namespace
+}  // namespace rmhmc
+
+// ------------------------------------------------------------ worker pool
+// Chains (Algorithm 1) run concurrently on a fixed set of worker threads,
+// one HIP stream each.  A job submitted while others run starts as soon as
+// a worker is free and no other job holds its model (continuous admission);
+// results are read back with rmhmc_pool_poll.
+
+struct rmhmc_model {
+  rmhmc::Model impl;
+  std::mutex busy;    // one chain at a time per model (its scratch is shared)
+};
+
+namespace rmhmc {
+namespace {
+
+struct PoolJob {
+  long long id = 0;
+  rmhmc_model* m = nullptr;
+  rmhmc_chain_cfg cfg{};
+  const double *q0 = nullptr, *z = nullptr, *u = nullptr;
+  double *samples = nullptr, *logpost = nullptr;
+  int* accepted = nullptr;
+  rmhmc_chain_stats stats{};
+  rmhmc_status status = RMHMC_OK;
+  std::string err;
+  int state = 0;   // 0 queued, 1 running, 2 done
+  double t_submit = 0, t_start = 0, t_end = 0;
+};
+
+}  // namespace
+}  // namespace rmhmc
+
+struct rmhmc_pool {
+  std::vector<std::thread> workers;
+  std::vector<hipStream_t> streams;
+  std::deque<std::shared_ptr<rmhmc::PoolJob>> queue;
+  std::map<long long, std::shared_ptr<rmhmc::PoolJob>> jobs;
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  bool stop = false;
+  long long next_id = 0;
+  std::chrono::steady_clock::time_point t0;
+  double now_ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace rmhmc {
+namespace {
+
+void pool_worker(rmhmc_pool* pool, int w) {
+  hipStream_t st = pool->streams[w];
+  for (;;) {
+    std::shared_ptr<PoolJob> job;
+    {
+      std::unique_lock<std::mutex> lk(pool->mu);
+      for (;;) {
+        if (pool->stop) return;
+        // first queued job whose model is free
+        for (auto it = pool->queue.begin(); it != pool->queue.end(); ++it) {
+          if ((*it)->m->busy.try_lock()) {
+            job = *it;
+            pool->queue.erase(it);
+            break;
+          }
+        }
+        if (job) break;
+        pool->cv.wait_for(lk, std::chrono::milliseconds(2));
+      }
+      job->state = 1;
+      job->t_start = pool->now_ms();
+    }
+    rmhmc_status status = RMHMC_OK;
+    std::string err;
+    try {
+      chain_impl(job->m->impl, &job->cfg, job->q0, job->z, job->u, job->samples, job->logpost,
+                 job->accepted, &job->stats, st);
+    } catch (const Error& e) {
+      status = e.status;
+      err = e.what();
+    } catch (const std::exception& e) {
+      status = RMHMC_E_HIP;
+      err = e.what();
+    }
+    job->m->busy.unlock();
+    {
+      std::lock_guard<std::mutex> lk(pool->mu);
+      job->status = status;
+      job->err = err;
+      job->t_end = pool->now_ms();
+      job->state = 2;
+    }
+    pool->cv_done.notify_all();
+    pool->cv.notify_all();
+  }
+}
+
+}  // namespace
+}  // namespace rmhmc
+
 // ================================================================ C ABI
 
 using namespace rmhmc;
 
-struct rmhmc_model {
-  Model impl;
-};
 struct rmhmc_state {
   std::unique_ptr<State> impl;
 };
@@ -949,8 +1220,8 @@ rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, do
       c.w.M2 = c.pool->alloc<double>((long)Dp * Dp);
       c.w.Psi = c.pool->alloc<double>((long)Dp * Dp);
       c.w.V = c.pool->alloc<double>((long)(Dp / 64) * 64 * 64);
-      c.w.part = c.pool->alloc<double>(2 * (Dp / 64 + 1));
-      c.w.ctrl = c.pool->alloc<double>(4);
+      c.w.part = c.pool->alloc<double>(3 * (Dp / 64 + 1));
+      c.w.ctrl = c.pool->alloc<double>(8);
       c.w.ctrl_host = c.pool->alloc_host<double>(4);
       c.Dp = Dp;
     }
@@ -976,6 +1247,7 @@ rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, do
     }
     int sw = 0;
     jacobi_eig(D, c.w, zeta, max_sweeps, &sw, st);
+    rayleigh_refine(D, H, ldh, c.w, c.w.M2, st);
     copy_matrix(D, D, c.w.Psi, Dp, Q, D, st);
     softabs_finalize(D, c.w.M, Dp, alpha, lam, g, gp, logdetG, st);
     RM_HIP(hipStreamSynchronize(st));
@@ -1048,9 +1320,7 @@ rmhmc_status rmhmc_state_draw_momentum(rmhmc_state* sh, const double* z, hipStre
   return guard([&] {
     RM_REQUIRE(sh && z, "NULL argument");
     State& S = *sh->impl;
-    Model& m = *S.m;
-    vec_scale(m.D, z, S.pts[0]->g, nullptr, true, S.vk, st);
-    gemv(m.D, m.D, 1.0, S.pts[0]->Psi, m.Dp, false, 0, S.vk, 0, 0.0, S.p, 0, 1, st);
+    draw_momentum(*S.m, S, *S.pts[0], z, st);
   });
 }
 
@@ -1095,67 +1365,89 @@ rmhmc_status rmhmc_chain(rmhmc_model* mh, const rmhmc_chain_cfg* cfg, const doub
                          const double* z, const double* u, double* samples, double* logpost,
                          int* accepted, rmhmc_chain_stats* stats, hipStream_t st) {
   return guard([&] {
-    RM_REQUIRE(mh && cfg && q0 && z && u && samples && logpost && accepted, "NULL argument");
-    RM_REQUIRE(cfg->n_leapfrog >= 1 && cfg->n_moves >= 1 && cfg->n_fixed_point >= 1,
-               "n_leapfrog, n_moves and n_fixed_point must be >= 1");
-    RM_REQUIRE(std::isfinite(cfg->eps) && cfg->eps > 0.0, "eps must be positive");
-    RM_REQUIRE(std::isfinite(cfg->alpha) && cfg->alpha > 0.0, "alpha must be positive");
-    Model& m = mh->impl;
-    const int D = m.D;
-    if (cfg->reorth_every > 0) m.reorth_every = cfg->reorth_every;
-    auto Sp = make_state(m, cfg->alpha);
-    State& S = *Sp;
-    if (cfg->zeta > 0.0) S.zeta = cfg->zeta;
-    if (cfg->max_sweeps > 0) S.max_sweeps = cfg->max_sweeps;
-    std::vector<double> uh(cfg->n_moves);
-    RM_HIP(hipMemcpyAsync(uh.data(), u, cfg->n_moves * sizeof(double), hipMemcpyDeviceToHost, st));
-    copy(S.pts[0]->q, q0, D, st);
-    check_flag_nonfinite(m, S.pts[0]->q, D, st, "q0");
-    int sw = 0;
-    full_point(m, *S.pts[0], nullptr, cfg->alpha, S.zeta, S.max_sweeps, st, &sw);
-    S.sweeps += sw;
-    S.eig_calls += 1;
-    int n_acc = 0, n_fail = 0;
-    for (int ell = 0; ell < cfg->n_moves; ++ell) {
-      Point* start = S.pts[0];
-      // p = Psi diag(sqrt g) z   (p ~ N(0, G(q)))
-      vec_scale(D, z + (long)ell * D, start->g, nullptr, true, S.vk, st);
-      gemv(D, D, 1.0, start->Psi, m.Dp, false, 0, S.vk, 0, 0.0, S.p, 0, 1, st);
-      metric_vectors(m, *start, S.p, nullptr, S.ham, st);
-      bool ok = true;
-      Point* cur = start;
-      try {
-        for (int c = 0; c < cfg->n_leapfrog; ++c) cur = leapfrog(S, cur, start, cfg->eps, cfg->n_fixed_point, st);
-        metric_vectors(m, *cur, S.p, nullptr, S.ham + 1, st);
-      } catch (const Error& e) {
-        if (e.status == RMHMC_E_HIP || e.status == RMHMC_E_ARG || e.status == RMHMC_E_NOMEM) throw;
-        ok = false;
-      }
-      double h0 = 0, h1 = 0;
-      RM_HIP(hipMemcpyAsync(m.hscal, S.ham, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-      RM_HIP(hipStreamSynchronize(st));
-      h0 = m.hscal[0];
-      h1 = m.hscal[1];
-      bool acc = ok && std::isfinite(h1) && std::isfinite(h0) && std::log(uh[ell]) < h0 - h1;
-      if (!ok) ++n_fail;
-      if (acc) {
-        ++n_acc;
-        for (int i = 1; i < 3; ++i)
-          if (S.pts[i] == cur) std::swap(S.pts[0], S.pts[i]);
-      }
-      hipLaunchKernelGGL(store_sample_kernel, dim3(cdiv(D, 256)), dim3(256), 0, st, D,
-                         (const double*)S.pts[0]->q, (const double*)(S.pts[0]->scal + 1),
-                         samples + (long)ell * D, logpost + ell, accepted + ell, acc ? 1 : 0);
-      RM_CHECK_LAUNCH();
+    RM_REQUIRE(mh != nullptr, "NULL model");
+    std::lock_guard<std::mutex> lk(mh->busy);
+    chain_impl(mh->impl, cfg, q0, z, u, samples, logpost, accepted, stats, st);
+  });
+}
+
+rmhmc_status rmhmc_pool_create(int n_workers, rmhmc_pool** out) {
+  return guard([&] {
+    RM_REQUIRE(out != nullptr, "out is NULL");
+    RM_REQUIRE(n_workers >= 1 && n_workers <= 64, "n_workers must be in 1..64");
+    auto p = std::make_unique<rmhmc_pool>();
+    p->t0 = std::chrono::steady_clock::now();
+    for (int w = 0; w < n_workers; ++w) {
+      hipStream_t s;
+      RM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      p->streams.push_back(s);
     }
-    RM_HIP(hipStreamSynchronize(st));
-    if (stats) {
-      stats->accepted = n_acc;
-      stats->failures = n_fail;
-      stats->leapfrogs = S.leapfrogs;
-      stats->eig_calls = S.eig_calls;
-      stats->sweeps = S.sweeps;
+    rmhmc_pool* raw = p.get();
+    for (int w = 0; w < n_workers; ++w) raw->workers.emplace_back([raw, w] { pool_worker(raw, w); });
+    *out = p.release();
+  });
+}
+
+rmhmc_status rmhmc_pool_submit(rmhmc_pool* pool, rmhmc_model* m, const rmhmc_chain_cfg* cfg,
+                               const double* q0, const double* z, const double* u,
+                               double* samples, double* logpost, int* accepted,
+                               long long* ticket) {
+  return guard([&] {
+    RM_REQUIRE(pool && m && cfg && q0 && z && u && samples && logpost && accepted && ticket,
+               "NULL argument");
+    auto j = std::make_shared<PoolJob>();
+    j->m = m;
+    j->cfg = *cfg;
+    j->q0 = q0; j->z = z; j->u = u;
+    j->samples = samples; j->logpost = logpost; j->accepted = accepted;
+    {
+      std::lock_guard<std::mutex> lk(pool->mu);
+      j->id = ++pool->next_id;
+      j->t_submit = pool->now_ms();
+      pool->jobs[j->id] = j;
+      pool->queue.push_back(j);
     }
+    pool->cv.notify_all();
+    *ticket = j->id;
+  });
+}
+
+rmhmc_status rmhmc_pool_poll(rmhmc_pool* pool, long long ticket, int wait, int* done,
+                             rmhmc_chain_stats* stats, double* times_ms) {
+  return guard([&] {
+    RM_REQUIRE(pool && done, "NULL argument");
+    std::unique_lock<std::mutex> lk(pool->mu);
+    auto it = pool->jobs.find(ticket);
+    RM_REQUIRE(it != pool->jobs.end(), "unknown ticket");
+    std::shared_ptr<PoolJob> j = it->second;
+    if (wait) pool->cv_done.wait(lk, [&] { return j->state == 2; });
+    if (j->state != 2) {
+      *done = 0;
+      return;
+    }
+    *done = j->status == RMHMC_OK ? 1 : (int)j->status;
+    if (stats) *stats = j->stats;
+    if (times_ms) {
+      times_ms[0] = j->t_submit;
+      times_ms[1] = j->t_start;
+      times_ms[2] = j->t_end;
+    }
+    if (j->status != RMHMC_OK) g_last_error = j->err;
+    pool->jobs.erase(it);
+  });
+}
+
+rmhmc_status rmhmc_pool_destroy(rmhmc_pool* pool) {
+  return guard([&] {
+    if (!pool) return;
+    {
+      std::lock_guard<std::mutex> lk(pool->mu);
+      pool->stop = true;
+    }
+    pool->cv.notify_all();
+    for (auto& t : pool->workers) t.join();
+    for (hipStream_t s : pool->streams) (void)hipStreamDestroy(s);
+    delete pool;
   });
 }
 

@@ -29,7 +29,8 @@ EXPORTED = ["rmhmc_model_create", "rmhmc_model_dims", "rmhmc_model_destroy", "rm
             "rmhmc_softabs_eig", "rmhmc_metric_grad", "rmhmc_state_create", "rmhmc_state_get",
             "rmhmc_state_set_momentum", "rmhmc_state_destroy", "rmhmc_glf_step", "rmhmc_chain",
             "rmhmc_gemm_f64", "rmhmc_gemm_f32", "rmhmc_last_error", "rmhmc_state_draw_momentum",
-            "rmhmc_timing_enable", "rmhmc_timing_read"]
+            "rmhmc_timing_enable", "rmhmc_timing_read", "rmhmc_pool_create", "rmhmc_pool_submit",
+            "rmhmc_pool_poll", "rmhmc_pool_destroy"]
 
 TIMER_KINDS = {"gemm_f64": 0, "gemm_f32": 1, "jacobi_solve": 2, "jacobi_apply": 3, "kd_wsum": 4,
                "kd_matvec": 5, "potrf_diag": 6}
@@ -72,6 +73,12 @@ _sig = {
     "rmhmc_state_destroy": [_vp],
     "rmhmc_state_draw_momentum": [_vp, _vp, _vp],
     "rmhmc_timing_enable": [C.c_uint],
+    "rmhmc_pool_create": [_i, C.POINTER(_vp)],
+    "rmhmc_pool_submit": [_vp, _vp, C.POINTER(ChainCfg), _vp, _vp, _vp, _vp, _vp, _vp,
+                          C.POINTER(C.c_longlong)],
+    "rmhmc_pool_poll": [_vp, C.c_longlong, _i, C.POINTER(_i), C.POINTER(ChainStats),
+                        C.POINTER(_d)],
+    "rmhmc_pool_destroy": [_vp],
     "rmhmc_timing_read": [_i, C.POINTER(C.c_longlong), C.POINTER(_d), C.POINTER(_d), C.POINTER(_d)],
     "rmhmc_glf_step": [_vp, _vp, _d, _i, _vp],
     "rmhmc_chain": [_vp, C.POINTER(ChainCfg), _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(ChainStats), _vp],
@@ -277,3 +284,69 @@ def timing_read(kind):
     _check(_lib.rmhmc_timing_read(TIMER_KINDS[kind] if isinstance(kind, str) else kind,
                                   C.byref(n), C.byref(ms), C.byref(fl), C.byref(by)))
     return n.value, ms.value, fl.value, by.value
+
+
+class ChainJob:
+    """Device buffers of one submitted chain (kept alive until collected)."""
+
+    def __init__(self, model, q0, z, u, cfg):
+        torch = _torch()
+        n_moves = z.shape[0]
+        self.model, self.q0, self.z, self.u, self.cfg = model, q0, z, u, cfg
+        self.samples = torch.empty((n_moves, model.D), dtype=torch.float64, device=q0.device)
+        self.logpost = torch.empty(n_moves, dtype=torch.float64, device=q0.device)
+        self.accepted = torch.empty(n_moves, dtype=torch.int32, device=q0.device)
+        self.ticket = None
+        self.stats = None
+        self.times_ms = None
+
+
+class Pool:
+    """Worker pool running chains concurrently (rmhmc_pool)."""
+
+    def __init__(self, n_workers=4):
+        h = C.c_void_p()
+        _check(_lib.rmhmc_pool_create(n_workers, C.byref(h)))
+        self._h = h
+        self.n_workers = n_workers
+
+    def submit(self, model, q0, z, u, eps, n_leapfrog, n_fixed_point, alpha=1e6, zeta=0.0,
+               max_sweeps=0, reorth_every=0):
+        torch = _torch()
+        job = ChainJob(model, q0, z, u, ChainCfg(eps, alpha, zeta, n_leapfrog, z.shape[0],
+                                                 n_fixed_point, max_sweeps, reorth_every))
+        t = C.c_longlong()
+        _check(_lib.rmhmc_pool_submit(self._h, model._h, C.byref(job.cfg), _f64(q0), _f64(z),
+                                      _f64(u), _f64(job.samples), _f64(job.logpost),
+                                      _ptr(job.accepted, torch.int32), C.byref(t)))
+        job.ticket = t.value
+        return job
+
+    def poll(self, job, wait=False):
+        """True when the job has finished (raises if it failed)."""
+        done = C.c_int()
+        stats = ChainStats()
+        times = (C.c_double * 3)()
+        _check(_lib.rmhmc_pool_poll(self._h, job.ticket, int(wait), C.byref(done),
+                                    C.byref(stats), times))
+        if done.value == 0:
+            return False
+        if done.value < 0:
+            raise RmhmcError(done.value, _lib.rmhmc_last_error().decode())
+        job.stats = stats
+        job.times_ms = tuple(times)
+        return True
+
+    def wait(self, job):
+        return self.poll(job, wait=True)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.rmhmc_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

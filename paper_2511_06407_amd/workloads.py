@@ -222,7 +222,7 @@ def workload(name: str, seed: int = 0):
                                    n_samples=200, n_burnin=67)
     if name == "gp_logistic_ard_d261":
         spec, _, _ = gp_logistic_ard4(256, seed)
-        return spec, ChainSettings(eps=0.01, n_leapfrog=20, n_fixed_point=6,
+        return spec, ChainSettings(eps=0.003, n_leapfrog=20, n_fixed_point=6,
                                    n_samples=1000, n_burnin=334)
     if name == "propensity_mkl_d1038":
         spec, _, _ = propensity_mkl(1024, seed)

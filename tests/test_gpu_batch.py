@@ -1,0 +1,111 @@
+"""GPU: chains run concurrently (worker pool, tempered ladder, serving loop)
+give the same results as each chain run alone, and the tempered ladder's
+first moves match the FP64 reference."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2511_06407_amd import workloads as wl  # noqa: E402
+from oracle import hamiltonian as oham  # noqa: E402
+from oracle.chain import run_chain  # noqa: E402
+from tests.parity_util import rel, record  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_06407_amd import rmhmc
+    return rmhmc
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def specs_mix():
+    a, _ = wl.workload("gp_logistic_d34")
+    b, _, _ = wl.gp_logistic_2d(64, seed=5, beta=0.3)
+    c, _, _ = wl.propensity_mkl(60, seed=6)
+    return [(a, 0.01), (b, 0.01), (dataclasses.replace(c, jitter=1e-2), 0.003)]
+
+
+def test_pool_mix_equals_alone(rm):
+    n_moves, C_, K = 3, 2, 6
+    runs = []
+    for k, (spec, eps) in enumerate(specs_mix()):
+        z, u = wl.chain_randoms(spec.D, n_moves, seed=1, stream=k)
+        runs.append((spec, eps, dev(np.zeros(spec.D)), dev(z), dev(u)))
+    alone = []
+    for spec, eps, q0, z, u in runs:
+        s, l, a, st = rm.Model(spec).chain(q0, z, u, eps, C_, K)
+        torch.cuda.synchronize()
+        alone.append((s.cpu().numpy(), l.cpu().numpy(), a.cpu().numpy()))
+    pool = rm.Pool(3)
+    models = [rm.Model(spec) for spec, *_ in runs]
+    jobs = [pool.submit(m, q0, z, u, eps, C_, K) for m, (spec, eps, q0, z, u) in zip(models, runs)]
+    for j in jobs:
+        assert pool.wait(j)
+    torch.cuda.synchronize()
+    for k, j in enumerate(jobs):
+        s, l, a = j.samples.cpu().numpy(), j.logpost.cpu().numpy(), j.accepted.cpu().numpy()
+        record("pool_mix", chain=k, D=runs[k][0].D, samples=rel(s, alone[k][0]),
+               accepted=int(a.sum()), start_ms=j.times_ms[1], end_ms=j.times_ms[2])
+        assert np.array_equal(s, alone[k][0]) and np.array_equal(l, alone[k][1])
+        assert np.array_equal(a, alone[k][2])
+    # the jobs overlapped in time
+    starts = [j.times_ms[1] for j in jobs]
+    ends = [j.times_ms[2] for j in jobs]
+    assert max(starts) < min(ends)
+    pool.close()
+
+
+def test_tempered_ladder_runs_and_matches_reference(rm):
+    from paper_2511_06407_amd.tempered import run_tempered
+    out = run_tempered(n_chains=6, n_moves=2, n_leapfrog=2, n_workers=3, seed=0)
+    record("tempered", wall_s=out["wall_s"], leapfrogs=out["chain_leapfrogs"],
+           lf_per_s=out["chain_leapfrogs_per_s"])
+    assert out["chain_leapfrogs"] > 0
+    # reference for the smallest chain
+    k = int(np.argmin([c["D"] for c in out["chains"]]))
+    specs, dims, betas = wl.tempered_ladder(6, 0)
+    spec = specs[k]
+    z, u = wl.chain_randoms(spec.D, 2, seed=0, stream=k)
+    ref = run_chain(oham.GPTarget(spec), np.zeros(spec.D), 0.01, 2, 6, 1e6, z, u)
+    got = out["jobs"][k].samples.cpu().numpy()
+    e = rel(got, ref[0])
+    record("tempered_ref", chain=k, D=spec.D, beta=float(betas[k]), samples=e)
+    assert np.array_equal(out["jobs"][k].accepted.cpu().numpy(), ref[2])
+    assert e < 1e-7
+
+
+def test_serving_results_same_alone_and_in_mix(rm):
+    from paper_2511_06407_amd import serving as sv
+    reqs = sv.make_requests(8.0, 0.6, d_min=34, d_max=140, moves=(2, 3), seed=3)
+    assert len(reqs) >= 3
+    ex = sv.PoolExecutor(n_workers=3, n_leapfrog=2)
+    kept = {}
+    start = ex.start
+
+    def start_keep(r):
+        j = start(r)
+        kept[r.rid] = j
+        return j
+    ex.start = start_keep
+    sch = sv.Scheduler(ex, hbm_budget_bytes=60e9, n_slots=3)
+    sch.run(reqs)
+    summ = sv.summarize(reqs, max(r.done_s for r in reqs))
+    record("serving", **{k: v for k, v in summ.items()})
+    assert sch.max_running >= 2
+    for r in reqs[:3]:
+        spec, eps = sv.request_spec(r)
+        z, u = wl.chain_randoms(spec.D, r.n_moves, seed=r.seed)
+        s, l, a, st = rm.Model(spec).chain(dev(np.zeros(spec.D)), dev(z), dev(u), eps, 2, 6)
+        torch.cuda.synchronize()
+        assert np.array_equal(s.cpu().numpy(), kept[r.rid].samples.cpu().numpy())
+    ex.close()

@@ -1,0 +1,74 @@
+"""GPU mixed precision: FP32 MFMA products (A_l, B_l, Y_lm and the trace
+GEMMs) with FP64 Cholesky, eigensolver, softabs branch and log|G|.  Error
+against the FP64 reference must stay below 1e-4 (norm-wise relative)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2511_06407_amd import workloads as wl  # noqa: E402
+from oracle import model as omodel, hamiltonian as oham  # noqa: E402
+from oracle.integrator import glf_step as oglf  # noqa: E402
+from oracle.chain import momentum as omomentum  # noqa: E402
+from tests.parity_util import rel, record  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+BAR_MIXED = 1e-4
+
+
+@pytest.fixture(scope="module")
+def rm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_06407_amd import rmhmc
+    return rmhmc
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    "mkl_d104": wl.propensity_mkl(90, seed=2)[0],
+    "mkl_d270": wl.propensity_mkl(256, seed=0)[0],
+    "c1_d34": wl.workload("gp_logistic_d34")[0],
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mixed_hessian_and_gradient(rm, name):
+    spec = CASES[name]
+    q = 0.2 * np.random.default_rng(3).standard_normal(spec.D)
+    M = rm.Model(spec, precision=rm.MIXED)
+    U, g, H = M.hessian(dev(q))
+    ref = omodel.hessian(spec, q)
+    eU, eg, eH = rel(host(U), ref[0]), rel(host(g), ref[1]), rel(host(H), ref[2])
+    T = oham.GPTarget(spec)
+    st = oham.State(T, q, 1e6)
+    p = omomentum(st, np.random.default_rng(4).standard_normal(spec.D))
+    dq, dp, ham = M.metric_grad(dev(q), dev(p), dev(st.eig["Psi"].T), dev(st.eig["lam"]), 1e6)
+    e_dq = rel(host(dq), oham.grad_q(st, p))
+    e_h = rel(host(ham), oham.hamiltonian(st, p))
+    record("mixed", model=name, U=eU, grad=eg, H=eH, dHdq=e_dq, ham=e_h)
+    assert max(eU, eg, eH, e_dq, e_h) < BAR_MIXED
+
+
+def test_mixed_leapfrog(rm):
+    spec = CASES["mkl_d104"]
+    q = 0.2 * np.random.default_rng(5).standard_normal(spec.D)
+    st = oham.State(oham.GPTarget(spec), q, 1e6)
+    p = omomentum(st, np.random.default_rng(6).standard_normal(spec.D))
+    S = rm.State(rm.Model(spec, precision=rm.MIXED), dev(q), dev(p), 1e6)
+    S.step(0.003, 6)
+    ref_st, ref_p = oglf(st, p, 0.003, 6)
+    qg, pg, _ = S.get()
+    e_q, e_p = rel(host(qg), ref_st.q), rel(host(pg), ref_p)
+    record("mixed_glf", q=e_q, p=e_p)
+    assert e_q < BAR_MIXED and e_p < BAR_MIXED

@@ -123,9 +123,9 @@ def test_reversibility_gp():
     q = 0.3 * rng.standard_normal(T.D)
     st0 = ham.State(T, q, 1e6)
     p0 = momentum(st0, rng.standard_normal(T.D))       # p ~ N(0, G(q))
-    st1, p1 = trajectory(st0, p0, 0.02, 5, 12)
+    st1, p1 = trajectory(st0, p0, 0.005, 5, 12)
     assert np.linalg.norm(st1.q - q) > 0.1                  # it did move
-    st2, p2 = trajectory(st1, -p1, 0.02, 5, 12)
+    st2, p2 = trajectory(st1, -p1, 0.005, 5, 12)
     assert np.linalg.norm(st2.q - q) < 1e-11 * max(1, np.linalg.norm(q))
     assert np.linalg.norm(p2 + p0) < 1e-11 * np.linalg.norm(p0)
 
