@@ -180,6 +180,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log(f"timed {args.steps} steps in {t1 - t0:.3f} s")
+    st_stats = S.stats()
     elapsed = t1 - t0
     value = args.steps / elapsed
 
@@ -227,6 +228,9 @@ def main():
                       "eps": cfg.eps, "n_fixed_point": cfg.n_fixed_point, "alpha": cfg.alpha,
                       "precision": args.precision, "parallelism": "single GPU"},
            "roofline": roofline}
+    out["eig"] = {"eig_calls": st_stats.eig_calls, "sweeps": st_stats.sweeps,
+                  "sweeps_per_eig": st_stats.sweeps / max(st_stats.eig_calls, 1),
+                  "note": "counted since state creation (static first solve included)"}
     if ess_block is not None:
         out["ess"] = ess_block
     if not args.no_cpu_baseline:

@@ -82,6 +82,25 @@ typedef struct {
 typedef struct rmhmc_model rmhmc_model;
 typedef struct rmhmc_state rmhmc_state;
 
+typedef struct {
+  double eps;            /* leapfrog step size epsilon                        */
+  double alpha;          /* softabs sharpness (g = lam coth(alpha lam))       */
+  double zeta;           /* Jacobi tolerance (<= 0: 1e-13)                    */
+  int n_leapfrog;        /* C, leapfrogs per move                             */
+  int n_moves;           /* A, moves (burn-in included)                       */
+  int n_fixed_point;     /* K, fixed-point iterations per implicit equation   */
+  int max_sweeps;        /* Jacobi sweep cap per eigendecomposition (<=0: 60) */
+  int reorth_every;      /* re-orthogonalise Q every this many updates (<=0: 10) */
+} rmhmc_chain_cfg;
+
+typedef struct {
+  int accepted;          /* moves accepted                                    */
+  int failures;          /* moves rejected because a step failed              */
+  long long leapfrogs;   /* generalized leapfrogs completed                   */
+  long long eig_calls;   /* eigendecompositions                               */
+  long long sweeps;      /* Jacobi sweeps over all eigendecompositions        */
+} rmhmc_chain_stats;
+
 /* Build a model: copies X and y to the device and allocates every workspace
  * the calls below need for this N, P and D (no allocation happens later).
  * The prior is eta ~ N(0, I), f | eta ~ N(0, K(eta)); the likelihood of
@@ -137,6 +156,9 @@ rmhmc_status rmhmc_state_get(const rmhmc_state* s, double* q, double* p, double*
                              hipStream_t stream);   /* [device] outs, ham nullable */
 rmhmc_status rmhmc_state_set_momentum(rmhmc_state* s, const double* p, hipStream_t stream);
 rmhmc_status rmhmc_state_destroy(rmhmc_state* s);
+/* Counters of a state since creation: generalized leapfrogs, eigen-
+ * decompositions and Jacobi sweeps (accepted/failures are 0).  [host] out. */
+rmhmc_status rmhmc_state_stats(const rmhmc_state* s, rmhmc_chain_stats* out);
 /* Momentum draw of Algorithm 1 at the state's current point:
  * p = G^{1/2} z = Q diag(sqrt g) Q' z, i.e. p ~ N(0, G(q)) for z ~ N(0, I);
  * the symmetric square root makes p a function of G alone (independent of
@@ -150,24 +172,6 @@ rmhmc_status rmhmc_state_draw_momentum(rmhmc_state* s, const double* z, hipStrea
 rmhmc_status rmhmc_glf_step(rmhmc_model* m, rmhmc_state* s, double eps, int n_fixed_point,
                             hipStream_t stream);
 
-typedef struct {
-  double eps;            /* leapfrog step size epsilon                        */
-  double alpha;          /* softabs sharpness (g = lam coth(alpha lam))       */
-  double zeta;           /* Jacobi tolerance (<= 0: 1e-13)                    */
-  int n_leapfrog;        /* C, leapfrogs per move                             */
-  int n_moves;           /* A, moves (burn-in included)                       */
-  int n_fixed_point;     /* K, fixed-point iterations per implicit equation   */
-  int max_sweeps;        /* Jacobi sweep cap per eigendecomposition (<=0: 60) */
-  int reorth_every;      /* re-orthogonalise Q every this many updates (<=0: 10) */
-} rmhmc_chain_cfg;
-
-typedef struct {
-  int accepted;          /* moves accepted                                    */
-  int failures;          /* moves rejected because a step failed              */
-  long long leapfrogs;   /* generalized leapfrogs completed                   */
-  long long eig_calls;   /* eigendecompositions                               */
-  long long sweeps;      /* Jacobi sweeps over all eigendecompositions        */
-} rmhmc_chain_stats;
 
 /* RMHMC chain, Algorithm 1: per move p = G^{1/2} z (p ~ N(0, G(q))),
  * C generalized leapfrogs, then Metropolis-Hastings: accept iff

@@ -83,6 +83,11 @@ int tallk_splits(long k);
 void gemv(int m, int n, double alpha, const double* A, long lda, bool tA, long sA,
           const double* x, long sx, double beta, double* y, long sy, int batch, hipStream_t st);
 
+// y = alpha A x + beta y for one well-parallelised GEMV: columns split over
+// workgroups, partials (<= 64 m) in `work`, reduced in a fixed order.
+void gemv_split(int m, int n, double alpha, const double* A, long lda, const double* x,
+                double beta, double* y, double* work, hipStream_t st);
+
 // out[b] = sum_ij A(i,j) * B_b(i,j) for an m x n A (lda) and B_b = B + b*sB (ldb).
 void multi_dot(int m, int n, const double* A, long lda, const double* B, long ldb, long sB,
                int nb, double* out, double* work, hipStream_t st);

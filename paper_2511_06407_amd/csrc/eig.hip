@@ -46,6 +46,7 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
   __shared__ double rc[SB / 2], rs[SB / 2], rt[SB / 2];
   __shared__ int rp[SB / 2], rq[SB / 2];
   __shared__ int any;   // a significant rotation happened in this inner sweep
+  __shared__ int rot;   // some pair rotates in the current inner round
   __shared__ double red[4];
   const int nb = Dp / HB;
   const int slot = blockIdx.x;
@@ -71,21 +72,25 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
     if (tid == 0) any = 0;
     __syncthreads();
     for (int ir = 0; ir < SB - 1; ++ir) {
+      if (tid == 0) rot = 0;
+      __syncthreads();
       if (tid < SB / 2) {
         const int p = rr_player(ir, tid, SB), q = rr_player(ir, SB - 1 - tid, SB);
         const double app = S[p][p], aqq = S[q][q], apq = S[p][q];
         double c = 1.0, s = 0.0, t = 0.0;
         const double scale = sqrt(fabs(app * aqq));
-        if (fabs(apq) > fmax(thr, 1e-16 * scale)) {
+        if (fabs(apq) > fmax(thr, 1e-15 * scale)) {
           const double zeta = (aqq - app) / (2.0 * apq);
           t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + t * t);
+          c = rsqrt(1.0 + t * t);
           s = t * c;
+          rot = 1;
           if (fabs(apq) > fmax(thr, 1e-8 * scale)) any = 1;
         }
         rc[tid] = c; rs[tid] = s; rt[tid] = t; rp[tid] = p; rq[tid] = q;
       }
       __syncthreads();
+      if (!rot) continue;   // uniform: nothing to apply this round
       for (int k = tid; k < (SB / 2) * (SB / 2); k += 256) {
         const int u = k % (SB / 2), v = k / (SB / 2);
         const int pu = rp[u], qu = rq[u], pv = rp[v], qv = rq[v];
@@ -128,8 +133,105 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
   }
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// C (64 x 64) = sum_k A(m, k) B(k, n) on the FP64 matrix cores, operands in
+// LDS through accessors; each wave owns a 32 x 32 quadrant (2 x 2 tiles of
+// v_mfma_f64_16x16x4f64).  The MFMA row operand is fed from B and the column
+// operand from A, so lane l, register r holds C(m = mb + l%16, n = nb + l/16 + 4r).
+template <class FA, class FB>
+__device__ __forceinline__ void mm64_mfma(FA Aat, FB Bat, d4 acc[2][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < SB; k0 += 4) {
+    const int k = k0 + (lane >> 4);
+    double av[2], bv[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      av[t] = Aat(wm * 32 + t * 16 + (lane & 15), k);
+      bv[t] = Bat(k, wn * 32 + t * 16 + (lane & 15));
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
+  }
+}
+
+// Visit every (m, n, value) of an mm64_mfma result.
+template <class F>
+__device__ __forceinline__ void mm64_foreach(const d4 acc[2][2], F f) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        f(wm * 32 + ti * 16 + (lane & 15), wn * 32 + tj * 16 + (lane >> 4) + 4 * r, acc[ti][tj][r]);
+}
+
+// Apply the round's rotations on the matrix cores: M_out[P,R] = V_P' M_in[P,R] V_R
+// for all slot pairs, and Psi[:, P] <- Psi[:, P] V_P for 64-row tiles.
+__global__ __launch_bounds__(256) void jacobi_apply_mfma_kernel(int Dp, int round,
+                                                                const double* __restrict__ Min,
+                                                                double* __restrict__ Mout,
+                                                                double* __restrict__ Psi,
+                                                                const double* __restrict__ Vbuf,
+                                                                const double* __restrict__ ctrl) {
+  if (ctrl[1] != 0.0) return;
+  __shared__ double X[SB][SB + 1];
+  __shared__ double VP[SB][SB + 1];
+  __shared__ double VR[SB][SB + 1];
+  const int nb = Dp / HB, ns = nb / 2;
+  const int tid = threadIdx.x;
+  const int bx = blockIdx.x;
+  d4 acc[2][2];
+  if (bx < ns * ns) {
+    const int P = bx % ns, R = bx / ns;
+    for (int e = tid; e < SB * SB; e += 256) {
+      const int x = e % SB, y = e / SB;
+      X[x][y] = Min[slot_index(round, P, nb, x) + (long)slot_index(round, R, nb, y) * Dp];
+      VP[x][y] = Vbuf[(long)P * SB * SB + e];
+      VR[x][y] = Vbuf[(long)R * SB * SB + e];
+    }
+    __syncthreads();
+    // Y = VP' X
+    mm64_mfma([&](int m, int k) { return VP[k][m]; }, [&](int k, int n) { return X[k][n]; }, acc);
+    __syncthreads();
+    mm64_foreach(acc, [&](int m, int n, double v) { X[m][n] = v; });
+    __syncthreads();
+    // Z = Y VR
+    mm64_mfma([&](int m, int k) { return X[m][k]; }, [&](int k, int n) { return VR[k][n]; }, acc);
+    mm64_foreach(acc, [&](int m, int n, double v) {
+      Mout[slot_index(round, P, nb, m) + (long)slot_index(round, R, nb, n) * Dp] = v;
+    });
+  } else {
+    const int k = bx - ns * ns;
+    const int P = k % ns, rt = k / ns;
+    const int row0 = rt * SB;
+    for (int e = tid; e < SB * SB; e += 256) {
+      const int x = e % SB, y = e / SB;
+      X[x][y] = Psi[(row0 + x) + (long)slot_index(round, P, nb, y) * Dp];
+      VP[x][y] = Vbuf[(long)P * SB * SB + e];
+    }
+    __syncthreads();
+    mm64_mfma([&](int m, int kk) { return X[m][kk]; }, [&](int kk, int n) { return VP[kk][n]; }, acc);
+    mm64_foreach(acc, [&](int m, int n, double v) {
+      Psi[(row0 + m) + (long)slot_index(round, P, nb, n) * Dp] = v;
+    });
+  }
+}
+
 // Apply the round's rotations: M_out[P,R] = V_P' M_in[P,R] V_R for all slot
-// pairs, and Psi[:, P] <- Psi[:, P] V_P for 64-row tiles.
+// pairs, and Psi[:, P] <- Psi[:, P] V_P for 64-row tiles (vector-ALU form,
+// kept as the reference implementation of the tile update).
 __global__ __launch_bounds__(256) void jacobi_apply_kernel(int Dp, int round,
                                                            const double* __restrict__ Min,
                                                            double* __restrict__ Mout,
@@ -209,20 +311,28 @@ __global__ __launch_bounds__(256) void jacobi_apply_kernel(int Dp, int round,
 
 // Per 64-column chunk: off-diagonal squares, all squares, and the largest
 // relative off-diagonal |m_ij| / sqrt(|m_ii m_jj|).
+constexpr int OFF_COLS = 8;   // columns per workgroup of the convergence check
+constexpr int OFF_MAXDP = 4096;
+
 __global__ __launch_bounds__(256) void offnorm_kernel(int Dp, const double* __restrict__ M,
                                                       double* __restrict__ part) {
   __shared__ double sh[3][4];
-  const int c0 = blockIdx.x * 64;
+  __shared__ double rdg[OFF_MAXDP];   // 1 / sqrt|m_ii| (inf for a zero diagonal)
+  for (int i = threadIdx.x; i < Dp; i += 256) {
+    const double d = fabs(M[i + (long)i * Dp]);
+    rdg[i] = d > 0.0 ? rsqrt(d) : INFINITY;
+  }
+  __syncthreads();
+  const int c0 = blockIdx.x * OFF_COLS;
   double off = 0.0, tot = 0.0, rel = 0.0;
-  for (int j = c0; j < c0 + 64; ++j) {
-    const double djj = fabs(M[j + (long)j * Dp]);
+  for (int j = c0; j < c0 + OFF_COLS; ++j) {
+    const double rj = rdg[j];
     for (int i = threadIdx.x; i < Dp; i += 256) {
       const double v = M[i + (long)j * Dp];
       tot += v * v;
       if (i != j && v != 0.0) {
         off += v * v;
-        const double den = sqrt(fabs(M[i + (long)i * Dp]) * djj);
-        rel = fmax(rel, den > 0.0 ? fabs(v) / den : INFINITY);
+        rel = fmax(rel, fabs(v) * rdg[i] * rj);
       }
     }
   }
@@ -440,14 +550,15 @@ int eig_padded_dim(int D) { return ((D + SB - 1) / SB) * SB; }
 void eig_workspace_sizes(int D, long* doubles) {
   const int Dp = eig_padded_dim(D);
   const int nb = Dp / HB;
-  *doubles = 3L * Dp * Dp + (long)(nb / 2) * SB * SB + 3L * (Dp / 64 + 1) + 8;
+  *doubles = 3L * Dp * Dp + (long)(nb / 2) * SB * SB + 3L * (Dp / OFF_COLS + 1) + 8;
 }
 
 void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int* sweeps_out, hipStream_t st) {
   // Input: w.M (Dp x Dp symmetric, padded) and w.Psi (Dp x Dp, padded with identity).
   const int Dp = eig_padded_dim(D);
   const int nb = Dp / HB, ns = nb / 2;
-  const int nparts = Dp / 64;
+  RM_REQUIRE(Dp <= OFF_MAXDP, "softabs_eig: dimension too large for the convergence check");
+  const int nparts = Dp / OFF_COLS;
   double* Min = w.M;
   double* Mout = w.M2;
   RM_HIP(hipMemsetAsync(w.ctrl, 0, 8 * sizeof(double), st));
@@ -475,7 +586,7 @@ void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int* sweeps_out,
       timing_end(slot, st, (double)ns * 63.0 * (1024.0 * 24.0 + 2048.0 * 6.0),
                  2.0 * ns * SB * SB * sizeof(double));
       slot = timing_begin(TK_JACOBI_APPLY, st);
-      hipLaunchKernelGGL(jacobi_apply_kernel, dim3(ns * ns + (Dp / SB) * ns), dim3(256), 0, st, Dp,
+      hipLaunchKernelGGL(jacobi_apply_mfma_kernel, dim3(ns * ns + (Dp / SB) * ns), dim3(256), 0, st, Dp,
                          r, (const double*)Min, Mout, w.Psi, (const double*)w.V,
                          (const double*)w.ctrl);
       RM_CHECK_LAUNCH();

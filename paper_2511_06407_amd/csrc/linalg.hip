@@ -2,6 +2,7 @@
 // blocked Cholesky with explicit inverse, and vector utilities.  Every
 // reduction runs in a fixed order (no atomics), so results are bitwise
 // reproducible run to run.
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -121,6 +122,29 @@ __global__ __launch_bounds__(256) void gemv_n_kernel(int m, int n, double alpha,
   }
 }
 
+// y = alpha A x + beta y with the columns split over gridDim.y chunks:
+// each thread owns a row of a 256-row block and sums its column chunk;
+// partials are reduced in a fixed order by gemv_reduce_kernel.
+__global__ __launch_bounds__(256) void gemv_n_split_kernel(int m, int n, const double* A, long lda,
+                                                           const double* x, int chunk,
+                                                           double* part) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int c0 = blockIdx.y * chunk, c1 = min(n, c0 + chunk);
+  if (i >= m) return;
+  double s = 0.0;
+  for (int j = c0; j < c1; ++j) s += A[i + (long)j * lda] * x[j];
+  part[(long)blockIdx.y * m + i] = s;
+}
+
+__global__ void gemv_reduce_kernel(int m, int nsplit, const double* part, double alpha,
+                                   double beta, double* y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double s = 0.0;
+  for (int c = 0; c < nsplit; ++c) s += part[(long)c * m + i];
+  y[i] = alpha * s + (beta != 0.0 ? beta * y[i] : 0.0);
+}
+
 // y = alpha A' x + beta y: one wave per output column.
 __global__ __launch_bounds__(256) void gemv_t_kernel(int m, int n, double alpha, const double* A,
                                                      long lda, long sA, const double* x, long sx,
@@ -191,17 +215,21 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int n, int k0, double* 
       if (tid == 0) bad = 1;
     }
     // trailing update with the unscaled column j: S_ik -= S_ij S_kj / d
+    const double rd = 1.0 / d;
     for (int e = tid; e < CB * CB; e += 256) {
       const int i = e % CB, k = e / CB;
-      if (k > j && i >= k && i < w) S[i][k] -= S[i][j] * S[k][j] / d;
+      if (k > j && i >= k && i < w) S[i][k] -= S[i][j] * (S[k][j] * rd);
     }
     __syncthreads();
   }
   // scale: L_ij = S_ij / sqrt(S_jj), L_jj = sqrt(S_jj)
+  __shared__ double rs[CB];
+  if (tid < CB) rs[tid] = tid < w ? rsqrt(S[tid][tid]) : 0.0;
+  __syncthreads();
   for (int e = tid; e < CB * CB; e += 256) {
     const int i = e % CB, j = e / CB;
     double v = 0.0;
-    if (i < w && j < w && i >= j) v = (i == j) ? sqrt(S[j][j]) : S[i][j] / sqrt(S[j][j]);
+    if (i < w && j < w && i >= j) v = (i == j) ? sqrt(S[j][j]) : S[i][j] * rs[j];
     X[i][j] = v;
   }
   __syncthreads();
@@ -210,16 +238,27 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int n, int k0, double* 
     S[i][j] = X[i][j];
   }
   __syncthreads();
-  // invert lower-triangular S: column c of X = S^-1 e_c
-  if (tid < w) {
-    const int c = tid;
-    for (int i = 0; i < w; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) s -= S[i][k] * X[k][c];
-      X[i][c] = (i < c) ? 0.0 : s / S[i][i];
-    }
-  }
+  // invert lower-triangular S row by row: X[i][c] = (delta_ic - sum_{c<=k<i}
+  // S[i][k] X[k][c]) / S[i][i]; all columns c of row i in parallel, the k-sum
+  // split over four thread groups
+  __shared__ double part4[4][CB];
+  __shared__ double rdiag[CB];
+  if (tid < CB) rdiag[tid] = tid < w ? 1.0 / S[tid][tid] : 0.0;
+  for (int e = tid; e < CB * CB; e += 256) X[e % CB][e / CB] = 0.0;
   __syncthreads();
+  for (int i = 0; i < w; ++i) {
+    const int c = tid & (CB - 1), g = tid >> 6;
+    double acc = 0.0;
+    if (c < i)
+      for (int k = c + g; k < i; k += 4) acc += S[i][k] * X[k][c];
+    part4[g][c] = acc;
+    __syncthreads();
+    if (tid < CB && tid <= i) {
+      const double sum = part4[0][tid] + part4[1][tid] + part4[2][tid] + part4[3][tid];
+      X[i][tid] = ((tid == i ? 1.0 : 0.0) - sum) * rdiag[i];
+    }
+    __syncthreads();
+  }
   for (int e = tid; e < CB * CB; e += 256) {
     const int i = e % CB, j = e / CB;
     if (i < w && j < w) {
@@ -295,6 +334,19 @@ __global__ void widen_kernel(long n, const float* x, double* y) {
 }
 
 }  // namespace
+
+void gemv_split(int m, int n, double alpha, const double* A, long lda, const double* x,
+                double beta, double* y, double* work, hipStream_t st) {
+  if (m <= 0 || n <= 0) return;
+  const int nsplit = std::max(1, std::min(64, n / 16));
+  const int chunk = cdiv(n, nsplit);
+  hipLaunchKernelGGL(gemv_n_split_kernel, dim3(cdiv(m, 256), nsplit), dim3(256), 0, st, m, n, A,
+                     lda, x, chunk, work);
+  RM_CHECK_LAUNCH();
+  hipLaunchKernelGGL(gemv_reduce_kernel, dim3(cdiv(m, 256)), dim3(256), 0, st, m, nsplit,
+                     (const double*)work, alpha, beta, y);
+  RM_CHECK_LAUNCH();
+}
 
 void gemv(int m, int n, double alpha, const double* A, long lda, bool tA, long sA,
           const double* x, long sx, double beta, double* y, long sy, int batch, hipStream_t st) {

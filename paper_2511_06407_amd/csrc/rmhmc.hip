@@ -252,7 +252,8 @@ struct Model {
   double *tallwork = nullptr, *kdwork = nullptr, *mdwork = nullptr;
   double *W = nullptr, *Wt1 = nullptr, *Wt2 = nullptr;
   double *vc = nullptr, *vb = nullptr, *vtmp = nullptr, *vtmp2 = nullptr, *v1 = nullptr;
-  double *u = nullptr, *Au = nullptr, *z = nullptr, *Kz = nullptr, *wB = nullptr;
+  double *u = nullptr, *Au = nullptr, *Ku = nullptr, *z = nullptr, *Kz = nullptr, *wB = nullptr;
+  double* gvwork = nullptr;    // column-split GEMV partials
   double *E1 = nullptr, *E2 = nullptr, *D1 = nullptr, *D2 = nullptr, *D3 = nullptr;
   double *t3 = nullptr, *tB = nullptr, *tau = nullptr;
   double* dscal = nullptr;     // device scalars for API outputs
@@ -382,7 +383,9 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st) {
   pt.have_pre = pt.have_vW2 = pt.have_eig = false;
   kgen(m.md, eta, pt.K, pt.K1, st);
   chol_inverse(N, pt.K, pt.Kinv, pt.scal + 0, m.chol, nullptr, st);
-  gemv(N, N, 1.0, pt.Kinv, N, false, 0, pt.q, 0, 0.0, pt.alpha, 0, 1, st);
+  // K^-1 and K_l are symmetric: A x = A' x, and the column-dot kernel is the
+  // well-parallelised one
+  gemv(N, N, 1.0, pt.Kinv, N, true, 0, pt.q, 0, 0.0, pt.alpha, 0, 1, st);
   lik_derivs(N, m.lik, m.noise_var, pt.q, m.y, pt.lik, st);
   const bool mixed = m.prec == RMHMC_MIXED;
   if (!mixed) {  // A_l = K^-1 K_l, and the transposed copies
@@ -407,8 +410,8 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st) {
     gemm(g, st);
     widen_to_double(P * NN, pt.Af, pt.A, st);
   }
-  gemv(N, N, 1.0, pt.A, N, false, NN, pt.alpha, 0, 0.0, pt.a, N, P, st);
-  gemv(N, N, 1.0, pt.K1, N, false, NN, pt.alpha, 0, 0.0, pt.k1a, N, P, st);
+  gemv(N, N, 1.0, pt.K1, N, true, NN, pt.alpha, 0, 0.0, pt.k1a, N, P, st);
+  gemv(N, N, 1.0, pt.Kinv, N, true, 0, pt.k1a, N, 0.0, pt.a, N, P, st);   // A_l a = K^-1 (K_l a)
   multi_dot(N, N, pt.Kinv, N, pt.K1, N, NN, P, pt.trK1, m.mdwork, st);
   pair_dots(N, pt.k1a, N, P, pt.a, N, P, pt.kla, st);
   pair_dots(N, pt.alpha, 0, 1, pt.k1a, N, P, pt.ak, st);
@@ -594,13 +597,14 @@ void contract(Model& m, Point& pt, const double* W, double* v, hipStream_t st) {
     g.C = m.u; g.ldc = N;
     gemm(g, st);
   }
-  gemv(N, N, 1.0, pt.A, N, false, NN, m.u, N, 0.0, m.Au, N, P, st);
+  gemv(N, N, 1.0, pt.K1, N, true, NN, m.u, N, 0.0, m.Ku, N, P, st);      // K_l u_l
+  gemv(N, N, 1.0, pt.Kinv, N, true, 0, m.Ku, N, 0.0, m.Au, N, P, st);     // A_l u_l = K^-1 K_l u_l
   pair_dots(N, m.u, N, P, pt.c1a, N, P * P, m.E1, st);
   pair_dots(N, m.u, N, P, pt.k2a, N, m.npairs, m.E2, st);
   hipLaunchKernelGGL(zvec_kernel, dim3(cdiv(N, 256)), dim3(256), 0, st, N, P, Dp, W,
                      (const double*)pt.c1a, (const double*)pt.k2a, (const int*)m.pidx, m.z);
   RM_CHECK_LAUNCH();
-  gemv(N, N, 1.0, pt.Kinv, N, false, 0, m.z, 0, 0.0, m.Kz, 0, 1, st);
+  gemv(N, N, 1.0, pt.Kinv, N, true, 0, m.z, 0, 0.0, m.Kz, 0, 1, st);
   hipLaunchKernelGGL(contract_final_kernel, dim3(cdiv(m.D, 256)), dim3(256), 0, st, N, P, Dp,
                      m.beta, W, (const double*)pt.lik, (const double*)m.Au, (const double*)m.Kz,
                      (const double*)m.wB, (const double*)m.E1, (const double*)m.E2,
@@ -628,7 +632,7 @@ void metric_vectors(Model& m, Point& pt, const double* p, double* dHdp, double* 
   const int D = m.D, Dp = m.Dp;
   gemv(D, D, 1.0, pt.Psi, Dp, true, 0, p, 0, 0.0, m.vc, 0, 1, st);
   vec_scale(D, m.vc, nullptr, pt.g, false, m.vb, st);
-  if (dHdp) gemv(D, D, 1.0, pt.Psi, Dp, false, 0, m.vb, 0, 0.0, dHdp, 0, 1, st);
+  if (dHdp) gemv_split(D, D, 1.0, pt.Psi, Dp, m.vb, 0.0, dHdp, m.gvwork, st);
   if (ham) {
     hipLaunchKernelGGL(ham_kernel, dim3(1), dim3(256), 0, st, D, (const double*)m.vc,
                        (const double*)pt.g, (const double*)(pt.scal + 1),
@@ -777,7 +781,7 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   m.eig.M2 = pl.alloc<double>(Dp * Dp);
   m.eig.Psi = pl.alloc<double>(Dp * Dp);
   m.eig.V = pl.alloc<double>((Dp / 64) * 64 * 64);
-  m.eig.part = pl.alloc<double>(3 * (Dp / 64 + 1));
+  m.eig.part = pl.alloc<double>(3 * (Dp / 8 + 1));
   m.eig.ctrl = pl.alloc<double>(8);
   m.eig.ctrl_host = pl.alloc_host<double>(4);
   const int spl = tallk_splits(NN);
@@ -794,6 +798,8 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   m.v1 = pl.alloc<double>(Dp);
   m.u = pl.alloc<double>(N * P);
   m.Au = pl.alloc<double>(N * P);
+  m.Ku = pl.alloc<double>(N * P);
+  m.gvwork = pl.alloc<double>(64L * Dp);
   m.z = pl.alloc<double>(N);
   m.Kz = pl.alloc<double>(N);
   m.wB = pl.alloc<double>(P);
@@ -863,7 +869,7 @@ namespace {
 void draw_momentum(Model& m, State& S, Point& pt, const double* z, hipStream_t st) {
   gemv(m.D, m.D, 1.0, pt.Psi, m.Dp, true, 0, z, 0, 0.0, S.v0, 0, 1, st);
   vec_scale(m.D, S.v0, pt.g, nullptr, true, S.vk, st);
-  gemv(m.D, m.D, 1.0, pt.Psi, m.Dp, false, 0, S.vk, 0, 0.0, S.p, 0, 1, st);
+  gemv_split(m.D, m.D, 1.0, pt.Psi, m.Dp, S.vk, 0.0, S.p, m.gvwork, st);
 }
 
 // One generalized leapfrog from cur with momentum s.p; trial points alternate
@@ -1220,7 +1226,7 @@ rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, do
       c.w.M2 = c.pool->alloc<double>((long)Dp * Dp);
       c.w.Psi = c.pool->alloc<double>((long)Dp * Dp);
       c.w.V = c.pool->alloc<double>((long)(Dp / 64) * 64 * 64);
-      c.w.part = c.pool->alloc<double>(3 * (Dp / 64 + 1));
+      c.w.part = c.pool->alloc<double>(3 * (Dp / 8 + 1));
       c.w.ctrl = c.pool->alloc<double>(8);
       c.w.ctrl_host = c.pool->alloc_host<double>(4);
       c.Dp = Dp;
@@ -1321,6 +1327,17 @@ rmhmc_status rmhmc_state_draw_momentum(rmhmc_state* sh, const double* z, hipStre
     RM_REQUIRE(sh && z, "NULL argument");
     State& S = *sh->impl;
     draw_momentum(*S.m, S, *S.pts[0], z, st);
+  });
+}
+
+rmhmc_status rmhmc_state_stats(const rmhmc_state* sh, rmhmc_chain_stats* out) {
+  return guard([&] {
+    RM_REQUIRE(sh && out, "NULL argument");
+    const State& S = *sh->impl;
+    *out = rmhmc_chain_stats{};
+    out->leapfrogs = S.leapfrogs;
+    out->eig_calls = S.eig_calls;
+    out->sweeps = S.sweeps;
   });
 }
 

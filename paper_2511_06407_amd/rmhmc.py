@@ -30,7 +30,7 @@ EXPORTED = ["rmhmc_model_create", "rmhmc_model_dims", "rmhmc_model_destroy", "rm
             "rmhmc_state_set_momentum", "rmhmc_state_destroy", "rmhmc_glf_step", "rmhmc_chain",
             "rmhmc_gemm_f64", "rmhmc_gemm_f32", "rmhmc_last_error", "rmhmc_state_draw_momentum",
             "rmhmc_timing_enable", "rmhmc_timing_read", "rmhmc_pool_create", "rmhmc_pool_submit",
-            "rmhmc_pool_poll", "rmhmc_pool_destroy"]
+            "rmhmc_pool_poll", "rmhmc_pool_destroy", "rmhmc_state_stats"]
 
 TIMER_KINDS = {"gemm_f64": 0, "gemm_f32": 1, "jacobi_solve": 2, "jacobi_apply": 3, "kd_wsum": 4,
                "kd_matvec": 5, "potrf_diag": 6}
@@ -72,6 +72,7 @@ _sig = {
     "rmhmc_state_set_momentum": [_vp, _vp, _vp],
     "rmhmc_state_destroy": [_vp],
     "rmhmc_state_draw_momentum": [_vp, _vp, _vp],
+    "rmhmc_state_stats": [_vp, C.POINTER(ChainStats)],
     "rmhmc_timing_enable": [C.c_uint],
     "rmhmc_pool_create": [_i, C.POINTER(_vp)],
     "rmhmc_pool_submit": [_vp, _vp, C.POINTER(ChainCfg), _vp, _vp, _vp, _vp, _vp, _vp,
@@ -254,6 +255,11 @@ class State:
     def draw_momentum(self, z, stream=None):
         """p = Q diag(sqrt g) z at the current point (p ~ N(0, G(q)))."""
         _check(_lib.rmhmc_state_draw_momentum(self._h, _f64(z), _stream(stream)))
+
+    def stats(self):
+        st = ChainStats()
+        _check(_lib.rmhmc_state_stats(self._h, C.byref(st)))
+        return st
 
     def set_momentum(self, p, stream=None):
         _check(_lib.rmhmc_state_set_momentum(self._h, _f64(p), _stream(stream)))

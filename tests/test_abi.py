@@ -55,3 +55,16 @@ def test_argument_errors_are_host_side():
     cfg = rmhmc.ChainCfg()
     assert lib.rmhmc_chain(None, ctypes.byref(cfg), None, None, None, None, None, None, None,
                            None) == rmhmc.E_ARG
+
+
+def test_header_compiles_as_c():
+    """include/rmhmc.h is a plain C header (no C++ or torch types)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        import pytest
+        pytest.skip("no gcc")
+    src = f'#include "{HEADER}"\nint main(void) {{ return 0; }}\n'
+    r = subprocess.run(["gcc", "-std=c11", "-fsyntax-only", "-x", "c", "-I/opt/rocm/include",
+                        "-D__HIP_PLATFORM_AMD__", "-"], input=src, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
