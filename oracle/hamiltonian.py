@@ -28,15 +28,16 @@ LOG2PI = math.log(2.0 * math.pi)
 class GPTarget:
     """The latent-GP posterior as a sampling target."""
 
-    def __init__(self, spec):
+    def __init__(self, spec, operand_round=None):
         self.spec = spec
         self.D = spec.D
+        self.operand_round = operand_round   # rounding model of A_l, B_l (None: exact)
 
     def derivs(self, q):
-        return model.hessian(self.spec, q)
+        return model.hessian(self.spec, q, self.operand_round)
 
     def contract(self, q, W):
-        return model.contract(self.spec, q, W)
+        return model.contract(self.spec, q, W, self.operand_round)
 
 
 class State:

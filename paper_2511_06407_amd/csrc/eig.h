@@ -24,6 +24,11 @@ void eig_load_basis(int D, const double* Q, long ldq, EigWork& w, hipStream_t st
 void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int* sweeps_out, hipStream_t st);
 // Rayleigh quotients lam_i = psi_i' H psi_i of the converged basis against the
 // original H (D x D, ldh), written to diag(w.M); Z is Dp x Dp scratch.
+// One Newton-Schulz step Psi <- Psi (3I - Psi'Psi) / 2 on the D x D block of
+// a Dp-strided basis: removes the rounding drift from orthogonality to second
+// order.  T1, T2: Dp x Dp scratch.
+void orthonormalise(int D, int Dp, double* Psi, double* T1, double* T2, hipStream_t st);
+
 void rayleigh_refine(int D, const double* H, long ldh, EigWork& w, double* Z, hipStream_t st);
 void softabs_finalize(int D, const double* M, long ldm, double alpha, double* lam, double* g,
                       double* gp, double* logdetG, hipStream_t st);

@@ -22,10 +22,21 @@ namespace {
 
 constexpr int SB = 64;   // subproblem size (two 32-column blocks)
 constexpr int HB = 32;
+#ifndef RM_JACOBI_MAX_INNER
+#define RM_JACOBI_MAX_INNER 4
+#endif
+constexpr int MAX_INNER = RM_JACOBI_MAX_INNER;   // inner sweeps per subproblem
 
 __device__ __forceinline__ int rr_player(int r, int k, int n) {
   // round r of a round-robin over n players: player at seat k (seat 0 fixed)
   return k == 0 ? 0 : 1 + ((k - 1 + r) % (n - 1));
+}
+
+// rr_player for the 64 local indices of a subproblem, branch-free:
+// k - 1 + r <= 124, so one conditional subtraction replaces the modulo.
+__device__ __forceinline__ int rr64(int r, int k) {
+  const int x = k - 1 + r;
+  return k == 0 ? 0 : 1 + (x >= SB - 1 ? x - (SB - 1) : x);
 }
 
 __device__ __forceinline__ int slot_index(int r, int slot, int nb, int x) {
@@ -34,6 +45,17 @@ __device__ __forceinline__ int slot_index(int r, int slot, int nb, int x) {
   return x < HB ? I * HB + x : J * HB + (x - HB);
 }
 
+// One workgroup diagonalises the 64 x 64 subproblem of its slot with an inner
+// cyclic Jacobi (round-robin over 64 indices, 32 disjoint rotations a round,
+// at most max_inner sweeps) and writes the accumulated rotation V.
+//
+// Every wave computes the round's 32 rotations itself (lanes u and u+32 hold
+// pair u; the computation is identical in every wave, so the decisions taken
+// from it are uniform over the workgroup) and publishes them to its own LDS
+// slot, which only that wave reads back (a wave's LDS operations complete in
+// order, so no barrier is needed).  S is double-buffered: a round reads one
+// copy and writes the other, so one barrier per rotating round orders
+// everything.
 __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
                                                            const double* __restrict__ M,
                                                            double* __restrict__ Vbuf,
@@ -41,90 +63,114 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
                                                            int max_inner) {
   // ctrl[0] = ||M||_F, ctrl[1] = converged flag
   if (ctrl[1] != 0.0) return;
-  __shared__ double S[SB][SB + 1];
+  __shared__ double Sb[2][SB][SB + 1];
   __shared__ double V[SB][SB + 1];
-  __shared__ double rc[SB / 2], rs[SB / 2], rt[SB / 2];
-  __shared__ int rp[SB / 2], rq[SB / 2];
-  __shared__ int any;   // a significant rotation happened in this inner sweep
-  __shared__ int rot;   // some pair rotates in the current inner round
+  __shared__ double2 cs[4][SB / 2];   // per wave: (c, s) of the round's pairs
   __shared__ double red[4];
   const int nb = Dp / HB;
   const int slot = blockIdx.x;
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   double ss = 0.0;
   for (int e = tid; e < SB * SB; e += 256) {
     const int x = e % SB, y = e / SB;
     const double v = M[slot_index(round, slot, nb, x) + (long)slot_index(round, slot, nb, y) * Dp];
-    S[x][y] = v;
+    Sb[0][x][y] = v;
     V[x][y] = (x == y) ? 1.0 : 0.0;
     ss += v * v;
   }
   for (int o = 32; o > 0; o >>= 1) ss += __shfl_down(ss, o, 64);
-  if ((tid & 63) == 0) red[tid >> 6] = ss;
+  if (lane == 0) red[w] = ss;
   __syncthreads();
-  // Skip a rotation when |a_pq| <= 1e-16 sqrt(|a_pp a_qq|) (relative
+  // Skip a rotation when |a_pq| <= 1e-15 sqrt(|a_pp a_qq|) (relative
   // criterion, so eigenvectors of small eigenvalues stay accurate next to
-  // large ones), with an absolute floor of 1e-30 ||S||_F.  Rounding in the
-  // off-diagonal updates scales with the off-diagonal entries themselves, so
-  // the inner sweeps reach this test after a few quadratic steps.
+  // large ones), with an absolute floor of 1e-30 ||S||_F.
   const double thr = fmax(1e-30 * sqrt(red[0] + red[1] + red[2] + red[3]), 1e-300);
+  const int u = lane & 31, h = lane >> 5;
+  double2* const csw = cs[w];
+  int cur = 0;
   for (int sweep = 0; sweep < max_inner; ++sweep) {
-    if (tid == 0) any = 0;
-    __syncthreads();
+    bool significant = false;
     for (int ir = 0; ir < SB - 1; ++ir) {
-      if (tid == 0) rot = 0;
-      __syncthreads();
-      if (tid < SB / 2) {
-        const int p = rr_player(ir, tid, SB), q = rr_player(ir, SB - 1 - tid, SB);
-        const double app = S[p][p], aqq = S[q][q], apq = S[p][q];
-        double c = 1.0, s = 0.0, t = 0.0;
-        const double scale = sqrt(fabs(app * aqq));
-        if (fabs(apq) > fmax(thr, 1e-15 * scale)) {
-          const double zeta = (aqq - app) / (2.0 * apq);
-          t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = rsqrt(1.0 + t * t);
-          s = t * c;
-          rot = 1;
-          if (fabs(apq) > fmax(thr, 1e-8 * scale)) any = 1;
+      double(*S)[SB + 1] = Sb[cur];
+      double(*T)[SB + 1] = Sb[cur ^ 1];
+      // rotation of pair u (Rutishauser: |angle| <= pi/4)
+      const int pu = rr64(ir, u), qu = rr64(ir, SB - 1 - u);
+      const double app = S[pu][pu], aqq = S[qu][qu], apq = S[pu][qu];
+      double c = 1.0, sn = 0.0, t = 0.0;
+      if (fabs(apq) > fmax(thr, 1e-15 * sqrt(fabs(app * aqq)))) {
+        const double zeta = (aqq - app) / (2.0 * apq);
+        t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        c = rsqrt(1.0 + t * t);
+        sn = t * c;
+      }
+      if (__ballot(t != 0.0) == 0) continue;   // no pair rotates: S and V stay
+      // significant: an angle above 1e-8.  Inside a tight cluster the entries
+      // are tiny next to the diagonal but the angles are not, and the
+      // subproblem must still be diagonalised for the outer sweeps to
+      // converge quadratically.
+      significant = significant || (__ballot(fabs(t) > 1e-8) != 0);
+      if (h == 0) csw[u] = make_double2(c, sn);
+
+      // S' = J' S J by 2 x 2 blocks (u, v): v = 8j + 2w + h
+      double x[4][4];
+      int pv[4], qv[4];
+      double2 rv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int v = 8 * j + 2 * w + h;
+        pv[j] = rr64(ir, v);
+        qv[j] = rr64(ir, SB - 1 - v);
+        rv[j] = csw[v];
+        x[j][0] = S[pu][pv[j]];
+        x[j][1] = S[pu][qv[j]];
+        x[j][2] = S[qu][pv[j]];
+        x[j][3] = S[qu][qv[j]];
+      }
+      // V <- V J on rows: lane = row, pairs w + 4k
+      double vp[8], vq[8];
+      double2 r2[8];
+      int p2[8], q2[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int u2 = w + 4 * k;
+        p2[k] = rr64(ir, u2);
+        q2[k] = rr64(ir, SB - 1 - u2);
+        r2[k] = csw[u2];
+        vp[k] = V[lane][p2[k]];
+        vq[k] = V[lane][q2[k]];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double cv = rv[j].x, sv = rv[j].y;
+        const double y11 = c * x[j][0] - sn * x[j][2], y12 = c * x[j][1] - sn * x[j][3];
+        const double y21 = sn * x[j][0] + c * x[j][2], y22 = sn * x[j][1] + c * x[j][3];
+        double z11 = cv * y11 - sv * y12, z12 = sv * y11 + cv * y12;
+        double z21 = cv * y21 - sv * y22, z22 = sv * y21 + cv * y22;
+        if (8 * j + 2 * w + h == u && t != 0.0) {
+          // the pair's own block: exact annihilation (Rutishauser update)
+          z11 = x[j][0] - t * x[j][1];
+          z22 = x[j][3] + t * x[j][1];
+          z12 = 0.0;
+          z21 = 0.0;
         }
-        rc[tid] = c; rs[tid] = s; rt[tid] = t; rp[tid] = p; rq[tid] = q;
+        T[pu][pv[j]] = z11;
+        T[pu][qv[j]] = z12;
+        T[qu][pv[j]] = z21;
+        T[qu][qv[j]] = z22;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        V[lane][p2[k]] = r2[k].x * vp[k] - r2[k].y * vq[k];
+        V[lane][q2[k]] = r2[k].y * vp[k] + r2[k].x * vq[k];
       }
       __syncthreads();
-      if (!rot) continue;   // uniform: nothing to apply this round
-      for (int k = tid; k < (SB / 2) * (SB / 2); k += 256) {
-        const int u = k % (SB / 2), v = k / (SB / 2);
-        const int pu = rp[u], qu = rq[u], pv = rp[v], qv = rq[v];
-        if (u == v) {
-          if (rs[u] == 0.0) continue;   // pair not rotated this round
-          const double apq = S[pu][qu];
-          S[pu][pu] -= rt[u] * apq;
-          S[qu][qu] += rt[u] * apq;
-          S[pu][qu] = 0.0;
-          S[qu][pu] = 0.0;
-        } else {
-          const double cu = rc[u], su = rs[u], cv = rc[v], sv = rs[v];
-          const double x11 = S[pu][pv], x12 = S[pu][qv], x21 = S[qu][pv], x22 = S[qu][qv];
-          const double y11 = cu * x11 - su * x21, y12 = cu * x12 - su * x22;
-          const double y21 = su * x11 + cu * x21, y22 = su * x12 + cu * x22;
-          S[pu][pv] = cv * y11 - sv * y12;
-          S[pu][qv] = sv * y11 + cv * y12;
-          S[qu][pv] = cv * y21 - sv * y22;
-          S[qu][qv] = sv * y21 + cv * y22;
-        }
-      }
-      for (int k = tid; k < SB * (SB / 2); k += 256) {
-        const int row = k % SB, u = k / SB;
-        const int pu = rp[u], qu = rq[u];
-        const double cu = rc[u], su = rs[u];
-        const double vp = V[row][pu], vq = V[row][qu];
-        V[row][pu] = cu * vp - su * vq;
-        V[row][qu] = su * vp + cu * vq;
-      }
-      __syncthreads();
+      cur ^= 1;
     }
-    // start another inner sweep only after a significant rotation; residues
-    // below 1e-8 of the diagonal scale are removed by later outer sweeps
-    if (!any) break;
+    // start another inner sweep only after a significant rotation; smaller
+    // residues are removed by later outer sweeps
+    if (!significant) break;
   }
   double* out = Vbuf + (long)slot * SB * SB;
   for (int e = tid; e < SB * SB; e += 256) {
@@ -229,87 +275,7 @@ __global__ __launch_bounds__(256) void jacobi_apply_mfma_kernel(int Dp, int roun
   }
 }
 
-// Apply the round's rotations: M_out[P,R] = V_P' M_in[P,R] V_R for all slot
-// pairs, and Psi[:, P] <- Psi[:, P] V_P for 64-row tiles (vector-ALU form,
-// kept as the reference implementation of the tile update).
-__global__ __launch_bounds__(256) void jacobi_apply_kernel(int Dp, int round,
-                                                           const double* __restrict__ Min,
-                                                           double* __restrict__ Mout,
-                                                           double* __restrict__ Psi,
-                                                           const double* __restrict__ Vbuf,
-                                                           const double* __restrict__ ctrl) {
-  if (ctrl[1] != 0.0) return;
-  __shared__ double X[SB][SB + 1];
-  __shared__ double VP[SB][SB + 1];
-  __shared__ double VR[SB][SB + 1];
-  const int nb = Dp / HB, ns = nb / 2;
-  const int tid = threadIdx.x;
-  const int bx = blockIdx.x;
-  const int a0 = 4 * (tid % 16), b0 = 4 * (tid / 16);
-  double acc[4][4];
-  if (bx < ns * ns) {
-    const int P = bx % ns, R = bx / ns;
-    for (int e = tid; e < SB * SB; e += 256) {
-      const int x = e % SB, y = e / SB;
-      X[x][y] = Min[slot_index(round, P, nb, x) + (long)slot_index(round, R, nb, y) * Dp];
-      VP[x][y] = Vbuf[(long)P * SB * SB + e];
-      VR[x][y] = Vbuf[(long)R * SB * SB + e];
-    }
-    __syncthreads();
-    // Y = VP' X
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int x = 0; x < SB; ++x) {
-      double va[4], xb[4];
-      for (int i = 0; i < 4; ++i) va[i] = VP[x][a0 + i];
-      for (int j = 0; j < 4; ++j) xb[j] = X[x][b0 + j];
-      for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) acc[i][j] += va[i] * xb[j];
-    }
-    __syncthreads();
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) X[a0 + i][b0 + j] = acc[i][j];
-    __syncthreads();
-    // Z = Y VR
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int y = 0; y < SB; ++y) {
-      double ya[4], vb[4];
-      for (int i = 0; i < 4; ++i) ya[i] = X[a0 + i][y];
-      for (int j = 0; j < 4; ++j) vb[j] = VR[y][b0 + j];
-      for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) acc[i][j] += ya[i] * vb[j];
-    }
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j)
-        Mout[slot_index(round, P, nb, a0 + i) + (long)slot_index(round, R, nb, b0 + j) * Dp] =
-            acc[i][j];
-  } else {
-    const int k = bx - ns * ns;
-    const int P = k % ns, rt = k / ns;
-    const int row0 = rt * SB;
-    for (int e = tid; e < SB * SB; e += 256) {
-      const int x = e % SB, y = e / SB;
-      X[x][y] = Psi[(row0 + x) + (long)slot_index(round, P, nb, y) * Dp];
-      VP[x][y] = Vbuf[(long)P * SB * SB + e];
-    }
-    __syncthreads();
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int y = 0; y < SB; ++y) {
-      double xa[4], vb[4];
-      for (int i = 0; i < 4; ++i) xa[i] = X[a0 + i][y];
-      for (int j = 0; j < 4; ++j) vb[j] = VP[y][b0 + j];
-      for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) acc[i][j] += xa[i] * vb[j];
-    }
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j)
-        Psi[(row0 + a0 + i) + (long)slot_index(round, P, nb, b0 + j) * Dp] = acc[i][j];
-  }
-}
-
-// Per 64-column chunk: off-diagonal squares, all squares, and the largest
+// Per OFF_COLS-column chunk: off-diagonal squares, all squares, and the largest
 // relative off-diagonal |m_ij| / sqrt(|m_ii m_jj|).
 constexpr int OFF_COLS = 8;   // columns per workgroup of the convergence check
 constexpr int OFF_MAXDP = 4096;
@@ -579,7 +545,7 @@ void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int* sweeps_out,
     for (int r = 0; r < nb - 1; ++r) {
       int slot = timing_begin(TK_JACOBI_SOLVE, st);
       hipLaunchKernelGGL(jacobi_solve_kernel, dim3(ns), dim3(256), 0, st, Dp, r,
-                         (const double*)Min, w.V, (const double*)w.ctrl, 4);
+                         (const double*)Min, w.V, (const double*)w.ctrl, MAX_INNER);
       RM_CHECK_LAUNCH();
       // one inner sweep of a 64x64 subproblem: 63 rounds x (1024 2x2 blocks x 24
       // flops + 2048 V row pairs x 6 flops); bytes: subproblems in, rotations out
@@ -607,6 +573,35 @@ void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int* sweeps_out,
   }
   if (sweeps_out) *sweeps_out = sw;
   if (!conv) throw Error(RMHMC_E_EIG_NOCONV, "softabs_eig: Jacobi did not converge");
+}
+
+namespace {
+// G <- (3I - G) / 2 on the D x D block.
+__global__ void ns_coeff_kernel(int D, int Dp, double* __restrict__ G) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)D * D) return;
+  const int i = (int)(e % D), j = (int)(e / D);
+  double* x = G + i + (long)j * Dp;
+  *x = (i == j ? 1.5 : 0.0) - 0.5 * *x;
+}
+}  // namespace
+
+void orthonormalise(int D, int Dp, double* Psi, double* T1, double* T2, hipStream_t st) {
+  Gemm<double> g;
+  g.m = D; g.n = D; g.k = D;
+  g.A = Psi; g.lda = Dp; g.tA = true;
+  g.B = Psi; g.ldb = Dp;
+  g.C = T1; g.ldc = Dp;
+  gemm(g, st);
+  hipLaunchKernelGGL(ns_coeff_kernel, dim3(cdiv((long)D * D, 256)), dim3(256), 0, st, D, Dp, T1);
+  RM_CHECK_LAUNCH();
+  Gemm<double> h;
+  h.m = D; h.n = D; h.k = D;
+  h.A = Psi; h.lda = Dp;
+  h.B = T1; h.ldb = Dp;
+  h.C = T2; h.ldc = Dp;
+  gemm(h, st);
+  copy_matrix(D, D, T2, Dp, Psi, Dp, st);
 }
 
 void eig_load_matrix(int D, const double* H, long ldh, EigWork& w, hipStream_t st) {

@@ -193,80 +193,81 @@ __global__ void reduce_parts_kernel(int nparts, int nb, const double* part, doub
 }
 
 // ---------------------------------------------------------------- Cholesky
-// Factor the diagonal block in LDS (right-looking, one barrier per column),
-// then invert the triangle by forward substitution, one thread per column.
+// Factor one CB x CB diagonal block and invert its triangle in one workgroup.
+//
+// Factorisation (right-looking, unscaled columns): thread (row i = lane,
+// wave g) keeps S[i][k] for k = g + 4m in registers.  At step j the wave
+// owning column j publishes it to LDS (double-buffered, one barrier per
+// column) and every thread applies S_ik -= (S_ij / d_j) S_kj to its k > j.
+// Then L_ij = S_ij / sqrt(d_j), L_jj = sqrt(d_j).  Padding rows/columns of a
+// partial block start as the identity, so they factor trivially.
+//
+// Inverse: wave 0, one lane per column c, forward substitution
+// X[r][c] = (delta_rc - sum_{k<r} L[r][k] X[k][c]) / L[r][r] with X in
+// registers and L read from LDS (same address in every lane).
 __global__ __launch_bounds__(256) void potrf_diag_kernel(int n, int k0, double* L, long ldl,
                                                          double* Linv, double* diagLogs,
                                                          int* info) {
-  __shared__ double S[CB][CB + 1];
-  __shared__ double X[CB][CB + 1];
-  __shared__ int bad;
+  constexpr int NM = CB / 4;
+  __shared__ double col[2][CB];
+  __shared__ double dg[CB];
+  __shared__ double Ls[CB][CB + 1];
+  __shared__ double Xs[CB][CB + 1];
   const int w = min(CB, n - k0);
   const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
-  for (int e = tid; e < CB * CB; e += 256) {
-    const int i = e % CB, j = e / CB;
-    S[i][j] = (i < w && j < w) ? L[(k0 + i) + (long)(k0 + j) * ldl] : 0.0;
+  const int i = tid & (CB - 1);
+  const int g = __builtin_amdgcn_readfirstlane(tid >> 6);
+  __builtin_assume(g >= 0 && g < 4);
+  double sv[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    const int k = g + 4 * m;
+    sv[m] = (i < w && k < w) ? L[(k0 + i) + (long)(k0 + k) * ldl] : (i == k ? 1.0 : 0.0);
   }
-  __syncthreads();
-  for (int j = 0; j < w; ++j) {
-    const double d = S[j][j];
-    if (!(d > 0.0)) {
-      if (tid == 0) bad = 1;
-    }
-    // trailing update with the unscaled column j: S_ik -= S_ij S_kj / d
-    const double rd = 1.0 / d;
-    for (int e = tid; e < CB * CB; e += 256) {
-      const int i = e % CB, k = e / CB;
-      if (k > j && i >= k && i < w) S[i][k] -= S[i][j] * (S[k][j] * rd);
-    }
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const int b = j & 1;
+    if (g == (j & 3)) col[b][i] = sv[j >> 2];
     __syncthreads();
-  }
-  // scale: L_ij = S_ij / sqrt(S_jj), L_jj = sqrt(S_jj)
-  __shared__ double rs[CB];
-  if (tid < CB) rs[tid] = tid < w ? rsqrt(S[tid][tid]) : 0.0;
-  __syncthreads();
-  for (int e = tid; e < CB * CB; e += 256) {
-    const int i = e % CB, j = e / CB;
-    double v = 0.0;
-    if (i < w && j < w && i >= j) v = (i == j) ? sqrt(S[j][j]) : S[i][j] * rs[j];
-    X[i][j] = v;
+    const double d = col[b][j];
+    bad = bad || !(d > 0.0);
+    if (tid == 0) dg[j] = d;
+    const double f = col[b][i] * (1.0 / d);
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+      if (g + 4 * m > j) sv[m] -= f * col[b][g + 4 * m];
   }
   __syncthreads();
-  for (int e = tid; e < CB * CB; e += 256) {
-    const int i = e % CB, j = e / CB;
-    S[i][j] = X[i][j];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    const int k = g + 4 * m;
+    const double dk = dg[k];
+    Ls[i][k] = i > k ? sv[m] * rsqrt(dk) : (i == k ? sqrt(dk) : 0.0);
   }
   __syncthreads();
-  // invert lower-triangular S row by row: X[i][c] = (delta_ic - sum_{c<=k<i}
-  // S[i][k] X[k][c]) / S[i][i]; all columns c of row i in parallel, the k-sum
-  // split over four thread groups
-  __shared__ double part4[4][CB];
-  __shared__ double rdiag[CB];
-  if (tid < CB) rdiag[tid] = tid < w ? 1.0 / S[tid][tid] : 0.0;
-  for (int e = tid; e < CB * CB; e += 256) X[e % CB][e / CB] = 0.0;
-  __syncthreads();
-  for (int i = 0; i < w; ++i) {
-    const int c = tid & (CB - 1), g = tid >> 6;
-    double acc = 0.0;
-    if (c < i)
-      for (int k = c + g; k < i; k += 4) acc += S[i][k] * X[k][c];
-    part4[g][c] = acc;
-    __syncthreads();
-    if (tid < CB && tid <= i) {
-      const double sum = part4[0][tid] + part4[1][tid] + part4[2][tid] + part4[3][tid];
-      X[i][tid] = ((tid == i ? 1.0 : 0.0) - sum) * rdiag[i];
+  if (tid < CB) {
+    const int c = tid;
+    double x[CB];
+#pragma unroll
+    for (int r = 0; r < CB; ++r) {
+      double acc = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < r; ++k) acc -= Ls[r][k] * x[k];
+      x[r] = acc * rsqrt(dg[r]);
     }
-    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < CB; ++r) Xs[r][c] = x[r];
   }
+  __syncthreads();
   for (int e = tid; e < CB * CB; e += 256) {
-    const int i = e % CB, j = e / CB;
-    if (i < w && j < w) {
-      L[(k0 + i) + (long)(k0 + j) * ldl] = S[i][j];
-      Linv[(k0 + i) + (long)(k0 + j) * ldl] = X[i][j];
+    const int r = e % CB, c = e / CB;
+    if (r < w && c < w) {
+      L[(k0 + r) + (long)(k0 + c) * ldl] = Ls[r][c];
+      Linv[(k0 + r) + (long)(k0 + c) * ldl] = Xs[r][c];
     }
   }
-  if (tid < w) diagLogs[k0 + tid] = log(S[tid][tid]);
+  if (tid < w) diagLogs[k0 + tid] = log(Ls[tid][tid]);
   if (tid == 0 && bad) *info = k0 + 1;
 }
 

@@ -219,14 +219,6 @@ __global__ void any_nonfinite_kernel(long n, const double* __restrict__ x, int* 
   if (i < n && !isfinite(x[i])) flag[0] = 1;
 }
 
-// Newton-Schulz polishing step  Psi <- Psi (3I - Psi'Psi) / 2  on the D x D block.
-__global__ void ns_coeff_kernel(int D, int Dp, double* __restrict__ G) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long)D * D) return;
-  const int i = (int)(e % D), j = (int)(e / D);
-  double* x = G + i + (long)j * Dp;
-  *x = (i == j ? 1.5 : 0.0) - 0.5 * *x;
-}
 
 }  // namespace
 
@@ -438,23 +430,7 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st) {
 }
 
 void reorthogonalise(Model& m, double* Psi, hipStream_t st) {
-  // Psi <- Psi (3I - Psi'Psi)/2 on the D x D block (one Newton-Schulz step).
-  const int D = m.D, Dp = m.Dp;
-  Gemm<double> g;
-  g.m = D; g.n = D; g.k = D;
-  g.A = Psi; g.lda = Dp; g.tA = true;
-  g.B = Psi; g.ldb = Dp;
-  g.C = m.Wt1; g.ldc = Dp;
-  gemm(g, st);
-  hipLaunchKernelGGL(ns_coeff_kernel, dim3(cdiv((long)D * D, 256)), dim3(256), 0, st, D, Dp, m.Wt1);
-  RM_CHECK_LAUNCH();
-  Gemm<double> h;
-  h.m = D; h.n = D; h.k = D;
-  h.A = Psi; h.lda = Dp;
-  h.B = m.Wt1; h.ldb = Dp;
-  h.C = m.Wt2; h.ldc = Dp;
-  gemm(h, st);
-  copy_matrix(D, D, m.Wt2, Dp, Psi, Dp, st);
+  orthonormalise(m.D, m.Dp, Psi, m.Wt1, m.Wt2, st);
 }
 
 // Softabs eigen-state of pt.H; warm == nullptr: static, else dynamic from warm->Psi.
@@ -490,6 +466,9 @@ int compute_eig(Model& m, Point& pt, Point* warm, double alpha, double zeta, int
   }
   int sweeps = 0;
   jacobi_eig(D, m.eig, zeta, max_sweeps, &sweeps, st);
+  // a static solve accumulates one rounding per rotation into Psi: restore
+  // orthogonality before the eigenvalues are refined against H
+  if (!warm) reorthogonalise(m, m.eig.Psi, st);
   rayleigh_refine(D, pt.H, Dp, m.eig, m.Wt2, st);
   copy(pt.Psi, m.eig.Psi, (long)Dp * Dp, st);
   softabs_finalize(D, m.eig.M, Dp, alpha, pt.lam, pt.g, pt.gp, pt.scal + 2, st);
@@ -1253,6 +1232,8 @@ rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, do
     }
     int sw = 0;
     jacobi_eig(D, c.w, zeta, max_sweeps, &sw, st);
+    // static solve: restore orthogonality (M's off-diagonal part is free now)
+    if (!Q_warm) orthonormalise(D, Dp, c.w.Psi, c.w.M2, c.w.M, st);
     rayleigh_refine(D, H, ldh, c.w, c.w.M2, st);
     copy_matrix(D, D, c.w.Psi, Dp, Q, D, st);
     softabs_finalize(D, c.w.M, Dp, alpha, lam, g, gp, logdetG, st);

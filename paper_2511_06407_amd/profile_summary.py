@@ -12,8 +12,16 @@ import sys
 
 
 def short_name(name):
-    n = re.sub(r"\(.*\)$", "", name)
-    n = n.replace("rmhmc::(anonymous namespace)::", "").replace("rmhmc::", "")
+    n = name.replace("(anonymous namespace)::", "").replace("rmhmc::", "")
+    n = re.sub(r"^void ", "", n)
+    # drop the parameter list (the last balanced parenthesis group)
+    if n.endswith(")"):
+        depth = 0
+        for i in range(len(n) - 1, -1, -1):
+            depth += {")": 1, "(": -1}.get(n[i], 0)
+            if depth == 0:
+                n = n[:i]
+                break
     return n
 
 

@@ -114,3 +114,25 @@ def test_gaussian_likelihood_fixed_eta_textbook():
     U, g, H = model.hessian(spec, q)
     assert np.max(np.abs(g[:spec.N])) < 1e-10
     assert np.allclose(H[:spec.N, :spec.N], np.linalg.inv(K) + np.eye(spec.N) / s2, rtol=1e-12)
+
+
+def test_operand_rounding_model():
+    """The rounding model used to size the mixed-precision bar: an identity
+    rounding reproduces the exact result bit for bit, and float32 rounding of
+    the A_l, B_l products moves H and v(W) by a few float32 ulps relative to
+    their operands on a well-conditioned model (jitter 1e-2)."""
+    spec = MODELS[2]
+    q = rand_q(spec, 50)
+    W = np.random.default_rng(51).standard_normal((spec.D, spec.D))
+    W = W + W.T
+    H = model.hessian(spec, q)[2]
+    v = model.contract(spec, q, W)
+    ident = lambda X: X   # noqa: E731
+    assert np.array_equal(model.hessian(spec, q, ident)[2], H)
+    assert np.array_equal(model.contract(spec, q, W, ident), v)
+    f32 = lambda X: np.asarray(X, dtype=np.float32).astype(np.float64)   # noqa: E731
+    eH = np.linalg.norm(model.hessian(spec, q, f32)[2] - H) / np.linalg.norm(H)
+    ev = np.linalg.norm(model.contract(spec, q, W, f32) - v) / np.linalg.norm(v)
+    u32 = np.finfo(np.float32).eps / 2
+    assert u32 / 100 < eH < 1e3 * u32
+    assert u32 / 100 < ev < 1e3 * u32
