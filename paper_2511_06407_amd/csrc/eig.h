@@ -21,7 +21,14 @@ void eig_load_matrix(int D, const double* H, long ldh, EigWork& w, hipStream_t s
 // w.Psi = diag(Q, I) (Q == nullptr: identity).
 void eig_load_basis(int D, const double* Q, long ldq, EigWork& w, hipStream_t st);
 // Jacobi on w.M, rotations accumulated into w.Psi; converged matrix left in w.M.
-void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int* sweeps_out, hipStream_t st);
+// max_inner: inner Jacobi sweeps per 64 x 64 subproblem and round.  A
+// warm-started matrix is nearly diagonal and one inner sweep per round is
+// fastest; a static solve from the identity converges in fewer outer sweeps
+// with up to JACOBI_INNER_STATIC.
+constexpr int JACOBI_INNER_STATIC = 4;
+constexpr int JACOBI_INNER_DYNAMIC = 1;
+void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, int* sweeps_out,
+                hipStream_t st);
 // Rayleigh quotients lam_i = psi_i' H psi_i of the converged basis against the
 // original H (D x D, ldh), written to diag(w.M); Z is Dp x Dp scratch.
 // One Newton-Schulz step Psi <- Psi (3I - Psi'Psi) / 2 on the D x D block of

@@ -22,10 +22,6 @@ namespace {
 
 constexpr int SB = 64;   // subproblem size (two 32-column blocks)
 constexpr int HB = 32;
-#ifndef RM_JACOBI_MAX_INNER
-#define RM_JACOBI_MAX_INNER 4
-#endif
-constexpr int MAX_INNER = RM_JACOBI_MAX_INNER;   // inner sweeps per subproblem
 
 __device__ __forceinline__ int rr_player(int r, int k, int n) {
   // round r of a round-robin over n players: player at seat k (seat 0 fixed)
@@ -39,11 +35,24 @@ __device__ __forceinline__ int rr64(int r, int k) {
   return k == 0 ? 0 : 1 + (x >= SB - 1 ? x - (SB - 1) : x);
 }
 
-__device__ __forceinline__ int slot_index(int r, int slot, int nb, int x) {
-  // global index of local index x (0..63) of slot `slot` in round r
-  const int I = rr_player(r, slot, nb), J = rr_player(r, nb - 1 - slot, nb);
-  return x < HB ? I * HB + x : J * HB + (x - HB);
+// The 64 global indices of a slot in a round: local x < 32 in block I,
+// x >= 32 in block J (computed once per workgroup).
+struct SlotCols {
+  int I32, J32;
+  __device__ __forceinline__ int col(int x) const { return x < HB ? I32 + x : J32 + (x - HB); }
+};
+__device__ __forceinline__ SlotCols slot_cols(int r, int slot, int nb) {
+  return SlotCols{rr_player(r, slot, nb) * HB, rr_player(r, nb - 1 - slot, nb) * HB};
 }
+
+// A 64 x 64 rotation V is stored in MFMA operand order: element
+// (k, c) = (4 kq + l / 16, 16 cb + l % 16) sits at cb * 1024 + kq * 64 + l, so
+// the 64 lanes of a wave read the operand of one v_mfma_f64_16x16x4f64 step
+// (rows k0 .. k0+3, 16 columns) as 64 consecutive doubles.
+__device__ __forceinline__ int vfrag_index(int cb, int kq, int lane) {
+  return cb * 1024 + kq * 64 + lane;
+}
+
 
 // One workgroup diagonalises the 64 x 64 subproblem of its slot with an inner
 // cyclic Jacobi (round-robin over 64 indices, 32 disjoint rotations a round,
@@ -72,10 +81,11 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const SlotCols sc = slot_cols(round, slot, nb);
   double ss = 0.0;
   for (int e = tid; e < SB * SB; e += 256) {
     const int x = e % SB, y = e / SB;
-    const double v = M[slot_index(round, slot, nb, x) + (long)slot_index(round, slot, nb, y) * Dp];
+    const double v = M[sc.col(x) + (long)sc.col(y) * Dp];
     Sb[0][x][y] = v;
     V[x][y] = (x == y) ? 1.0 : 0.0;
     ss += v * v;
@@ -172,59 +182,24 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
     // residues are removed by later outer sweeps
     if (!significant) break;
   }
+  // V in MFMA operand order (see vfrag_index)
   double* out = Vbuf + (long)slot * SB * SB;
   for (int e = tid; e < SB * SB; e += 256) {
-    const int x = e % SB, y = e / SB;
-    out[e] = V[x][y];
+    const int l = e & 63, kq = (e >> 6) & 15, cb = e >> 10;
+    out[e] = V[4 * kq + (l >> 4)][16 * cb + (l & 15)];
   }
 }
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// C (64 x 64) = sum_k A(m, k) B(k, n) on the FP64 matrix cores, operands in
-// LDS through accessors; each wave owns a 32 x 32 quadrant (2 x 2 tiles of
-// v_mfma_f64_16x16x4f64).  The MFMA row operand is fed from B and the column
-// operand from A, so lane l, register r holds C(m = mb + l%16, n = nb + l/16 + 4r).
-template <class FA, class FB>
-__device__ __forceinline__ void mm64_mfma(FA Aat, FB Bat, d4 acc[2][2]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < SB; k0 += 4) {
-    const int k = k0 + (lane >> 4);
-    double av[2], bv[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      av[t] = Aat(wm * 32 + t * 16 + (lane & 15), k);
-      bv[t] = Bat(k, wn * 32 + t * 16 + (lane & 15));
-    }
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
-        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
-  }
-}
-
-// Visit every (m, n, value) of an mm64_mfma result.
-template <class F>
-__device__ __forceinline__ void mm64_foreach(const d4 acc[2][2], F f) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        f(wm * 32 + ti * 16 + (lane & 15), wn * 32 + tj * 16 + (lane >> 4) + 4 * r, acc[ti][tj][r]);
-}
-
-// Apply the round's rotations on the matrix cores: M_out[P,R] = V_P' M_in[P,R] V_R
-// for all slot pairs, and Psi[:, P] <- Psi[:, P] V_P for 64-row tiles.
+// Apply the round's rotations on the FP64 matrix cores.
+//   M tiles (P <= R): M_out[P,R] = V_P' M_in[P,R] V_R, stored with its mirror
+//   M_out[R,P] = M_out[P,R]' (M stays exactly symmetric; diagonal tiles are
+//   symmetrised);  Psi tiles: Psi[:, P] <- Psi[:, P] V_P for 64-row tiles.
+// Each wave owns a 32 x 32 quadrant (2 x 2 tiles of v_mfma_f64_16x16x4f64);
+// lane l, register r of a tile holds (m = 16 ti + l % 16, n = 16 tj + l / 16
+// + 4 r) within the quadrant.  V operands come straight from global memory
+// in their stored MFMA order; only the M / Psi tile is staged in LDS.
 __global__ __launch_bounds__(256) void jacobi_apply_mfma_kernel(int Dp, int round,
                                                                 const double* __restrict__ Min,
                                                                 double* __restrict__ Mout,
@@ -233,45 +208,132 @@ __global__ __launch_bounds__(256) void jacobi_apply_mfma_kernel(int Dp, int roun
                                                                 const double* __restrict__ ctrl) {
   if (ctrl[1] != 0.0) return;
   __shared__ double X[SB][SB + 1];
-  __shared__ double VP[SB][SB + 1];
-  __shared__ double VR[SB][SB + 1];
-  const int nb = Dp / HB, ns = nb / 2;
-  const int tid = threadIdx.x;
-  const int bx = blockIdx.x;
+  const int nb = Dp / HB, ns = nb / 2, ntri = ns * (ns + 1) / 2;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave & 1, wn = wave >> 1;
+  const int lm = lane & 15, lk = lane >> 4;
+  int bx = blockIdx.x;
   d4 acc[2][2];
-  if (bx < ns * ns) {
-    const int P = bx % ns, R = bx / ns;
+  auto zero = [&] {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
+  };
+  if (bx < ntri) {
+    // upper-triangle tile (P, R), P <= R, from the linear index bx
+    int P = 0, rowlen = ns;
+    while (bx >= rowlen) { bx -= rowlen; ++P; --rowlen; }
+    const int R = P + bx;
+    const SlotCols cp = slot_cols(round, P, nb), cr = slot_cols(round, R, nb);
     for (int e = tid; e < SB * SB; e += 256) {
       const int x = e % SB, y = e / SB;
-      X[x][y] = Min[slot_index(round, P, nb, x) + (long)slot_index(round, R, nb, y) * Dp];
-      VP[x][y] = Vbuf[(long)P * SB * SB + e];
-      VR[x][y] = Vbuf[(long)R * SB * SB + e];
+      X[x][y] = Min[cp.col(x) + (long)cr.col(y) * Dp];
+    }
+    const double* VP = Vbuf + (long)P * SB * SB;
+    const double* VR = Vbuf + (long)R * SB * SB;
+    __syncthreads();
+    // Y = VP' X:  A(m, k) = VP(k, m), B(k, n) = X(k, n)
+    zero();
+#pragma unroll 4
+    for (int kq = 0; kq < SB / 4; ++kq) {
+      const int k = 4 * kq + lk;
+      double av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = VP[vfrag_index(2 * wm + t, kq, lane)];
+        bv[t] = X[k][wn * 32 + t * 16 + lm];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
     }
     __syncthreads();
-    // Y = VP' X
-    mm64_mfma([&](int m, int k) { return VP[k][m]; }, [&](int k, int n) { return X[k][n]; }, acc);
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          X[wm * 32 + ti * 16 + lm][wn * 32 + tj * 16 + lk + 4 * r] = acc[ti][tj][r];
     __syncthreads();
-    mm64_foreach(acc, [&](int m, int n, double v) { X[m][n] = v; });
+    // Z = Y VR:  A(m, k) = Y(m, k), B(k, n) = VR(k, n)
+    zero();
+#pragma unroll 4
+    for (int kq = 0; kq < SB / 4; ++kq) {
+      const int k = 4 * kq + lk;
+      double av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = X[wm * 32 + t * 16 + lm][k];
+        bv[t] = VR[vfrag_index(2 * wn + t, kq, lane)];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
+    }
     __syncthreads();
-    // Z = Y VR
-    mm64_mfma([&](int m, int k) { return X[m][k]; }, [&](int k, int n) { return VR[k][n]; }, acc);
-    mm64_foreach(acc, [&](int m, int n, double v) {
-      Mout[slot_index(round, P, nb, m) + (long)slot_index(round, R, nb, n) * Dp] = v;
-    });
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          X[wm * 32 + ti * 16 + lm][wn * 32 + tj * 16 + lk + 4 * r] = acc[ti][tj][r];
+    __syncthreads();
+    if (P == R) {
+      for (int e = tid; e < SB * SB; e += 256) {
+        const int x = e % SB, y = e / SB;
+        Mout[cp.col(x) + (long)cp.col(y) * Dp] = 0.5 * (X[x][y] + X[y][x]);
+      }
+    } else {
+      for (int e = tid; e < SB * SB; e += 256) {
+        const int x = e % SB, y = e / SB;
+        Mout[cp.col(x) + (long)cr.col(y) * Dp] = X[x][y];
+        Mout[cr.col(x) + (long)cp.col(y) * Dp] = X[y][x];
+      }
+    }
   } else {
-    const int k = bx - ns * ns;
+    const int k = bx - ntri;
     const int P = k % ns, rt = k / ns;
     const int row0 = rt * SB;
+    const SlotCols cp = slot_cols(round, P, nb);
     for (int e = tid; e < SB * SB; e += 256) {
       const int x = e % SB, y = e / SB;
-      X[x][y] = Psi[(row0 + x) + (long)slot_index(round, P, nb, y) * Dp];
-      VP[x][y] = Vbuf[(long)P * SB * SB + e];
+      X[x][y] = Psi[(row0 + x) + (long)cp.col(y) * Dp];
     }
+    const double* VP = Vbuf + (long)P * SB * SB;
     __syncthreads();
-    mm64_mfma([&](int m, int kk) { return X[m][kk]; }, [&](int kk, int n) { return VP[kk][n]; }, acc);
-    mm64_foreach(acc, [&](int m, int n, double v) {
-      Psi[(row0 + m) + (long)slot_index(round, P, nb, n) * Dp] = v;
-    });
+    // Psi tile <- X VP:  A(m, k) = X(m, k), B(k, n) = VP(k, n)
+    zero();
+#pragma unroll 4
+    for (int kq = 0; kq < SB / 4; ++kq) {
+      const int kk = 4 * kq + lk;
+      double av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = X[wm * 32 + t * 16 + lm][kk];
+        bv[t] = VP[vfrag_index(2 * wn + t, kq, lane)];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          Psi[(row0 + wm * 32 + ti * 16 + lm) +
+              (long)cp.col(wn * 32 + tj * 16 + lk + 4 * r) * Dp] = acc[ti][tj][r];
   }
 }
 
@@ -519,7 +581,8 @@ void eig_workspace_sizes(int D, long* doubles) {
   *doubles = 3L * Dp * Dp + (long)(nb / 2) * SB * SB + 3L * (Dp / OFF_COLS + 1) + 8;
 }
 
-void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int* sweeps_out, hipStream_t st) {
+void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, int* sweeps_out,
+                hipStream_t st) {
   // Input: w.M (Dp x Dp symmetric, padded) and w.Psi (Dp x Dp, padded with identity).
   const int Dp = eig_padded_dim(D);
   const int nb = Dp / HB, ns = nb / 2;
@@ -545,18 +608,18 @@ void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int* sweeps_out,
     for (int r = 0; r < nb - 1; ++r) {
       int slot = timing_begin(TK_JACOBI_SOLVE, st);
       hipLaunchKernelGGL(jacobi_solve_kernel, dim3(ns), dim3(256), 0, st, Dp, r,
-                         (const double*)Min, w.V, (const double*)w.ctrl, MAX_INNER);
+                         (const double*)Min, w.V, (const double*)w.ctrl, max_inner);
       RM_CHECK_LAUNCH();
       // one inner sweep of a 64x64 subproblem: 63 rounds x (1024 2x2 blocks x 24
       // flops + 2048 V row pairs x 6 flops); bytes: subproblems in, rotations out
       timing_end(slot, st, (double)ns * 63.0 * (1024.0 * 24.0 + 2048.0 * 6.0),
                  2.0 * ns * SB * SB * sizeof(double));
       slot = timing_begin(TK_JACOBI_APPLY, st);
-      hipLaunchKernelGGL(jacobi_apply_mfma_kernel, dim3(ns * ns + (Dp / SB) * ns), dim3(256), 0, st, Dp,
+      hipLaunchKernelGGL(jacobi_apply_mfma_kernel, dim3(ns * (ns + 1) / 2 + (Dp / SB) * ns), dim3(256), 0, st, Dp,
                          r, (const double*)Min, Mout, w.Psi, (const double*)w.V,
                          (const double*)w.ctrl);
       RM_CHECK_LAUNCH();
-      timing_end(slot, st, 4.0 * (double)SB * SB * SB * ns * ns + 2.0 * (double)SB * SB * SB * (Dp / SB) * ns,
+      timing_end(slot, st, 4.0 * (double)SB * SB * SB * (ns * (ns + 1) / 2) + 2.0 * (double)SB * SB * SB * (Dp / SB) * ns,
                  4.0 * (double)Dp * Dp * sizeof(double));
       std::swap(Min, Mout);
     }

@@ -465,7 +465,8 @@ int compute_eig(Model& m, Point& pt, Point* warm, double alpha, double zeta, int
     pt.updates_since_reorth = cnt;
   }
   int sweeps = 0;
-  jacobi_eig(D, m.eig, zeta, max_sweeps, &sweeps, st);
+  jacobi_eig(D, m.eig, zeta, max_sweeps, warm ? JACOBI_INNER_DYNAMIC : JACOBI_INNER_STATIC,
+             &sweeps, st);
   // a static solve accumulates one rounding per rotation into Psi: restore
   // orthogonality before the eigenvalues are refined against H
   if (!warm) reorthogonalise(m, m.eig.Psi, st);
@@ -1231,7 +1232,8 @@ rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, do
       eig_load_basis(D, nullptr, D, c.w, st);
     }
     int sw = 0;
-    jacobi_eig(D, c.w, zeta, max_sweeps, &sw, st);
+    jacobi_eig(D, c.w, zeta, max_sweeps, Q_warm ? JACOBI_INNER_DYNAMIC : JACOBI_INNER_STATIC, &sw,
+               st);
     // static solve: restore orthogonality (M's off-diagonal part is free now)
     if (!Q_warm) orthonormalise(D, Dp, c.w.Psi, c.w.M2, c.w.M, st);
     rayleigh_refine(D, H, ldh, c.w, c.w.M2, st);
