@@ -20,68 +20,75 @@
 namespace rmhmc {
 namespace {
 
-constexpr int SB = 64;   // subproblem size (two 32-column blocks)
-constexpr int HB = 32;
-
 __device__ __forceinline__ int rr_player(int r, int k, int n) {
   // round r of a round-robin over n players: player at seat k (seat 0 fixed)
   return k == 0 ? 0 : 1 + ((k - 1 + r) % (n - 1));
 }
 
-// rr_player for the 64 local indices of a subproblem, branch-free:
-// k - 1 + r <= 124, so one conditional subtraction replaces the modulo.
-__device__ __forceinline__ int rr64(int r, int k) {
+// rr_player over the SB local indices of a subproblem, branch-free:
+// k - 1 + r <= 2 SB - 4, so one conditional subtraction replaces the modulo.
+template <int SB>
+__device__ __forceinline__ int rr_local(int r, int k) {
   const int x = k - 1 + r;
   return k == 0 ? 0 : 1 + (x >= SB - 1 ? x - (SB - 1) : x);
 }
 
-// The 64 global indices of a slot in a round: local x < 32 in block I,
-// x >= 32 in block J (computed once per workgroup).
+// The SB global indices of a slot in a round: local x < HB in block I,
+// x >= HB in block J (computed once per workgroup or wave).
+template <int HB>
 struct SlotCols {
-  int I32, J32;
-  __device__ __forceinline__ int col(int x) const { return x < HB ? I32 + x : J32 + (x - HB); }
+  int I0, J0;
+  __device__ __forceinline__ int col(int x) const { return x < HB ? I0 + x : J0 + (x - HB); }
 };
-__device__ __forceinline__ SlotCols slot_cols(int r, int slot, int nb) {
-  return SlotCols{rr_player(r, slot, nb) * HB, rr_player(r, nb - 1 - slot, nb) * HB};
+template <int HB>
+__device__ __forceinline__ SlotCols<HB> slot_cols(int r, int slot, int nb) {
+  return SlotCols<HB>{rr_player(r, slot, nb) * HB, rr_player(r, nb - 1 - slot, nb) * HB};
 }
 
-// A 64 x 64 rotation V is stored in MFMA operand order: element
-// (k, c) = (4 kq + l / 16, 16 cb + l % 16) sits at cb * 1024 + kq * 64 + l, so
+// An SB x SB rotation V is stored in MFMA operand order: element
+// (k, c) = (4 kq + l / 16, 16 cb + l % 16) sits at cb * 16 SB + kq * 64 + l, so
 // the 64 lanes of a wave read the operand of one v_mfma_f64_16x16x4f64 step
 // (rows k0 .. k0+3, 16 columns) as 64 consecutive doubles.
+template <int SB>
 __device__ __forceinline__ int vfrag_index(int cb, int kq, int lane) {
-  return cb * 1024 + kq * 64 + lane;
+  return cb * 16 * SB + kq * 64 + lane;
 }
 
-
-// One workgroup diagonalises the 64 x 64 subproblem of its slot with an inner
-// cyclic Jacobi (round-robin over 64 indices, 32 disjoint rotations a round,
+// One workgroup diagonalises the SB x SB subproblem of its slot with an inner
+// cyclic Jacobi (round-robin over SB indices, SB/2 disjoint rotations a round,
 // at most max_inner sweeps) and writes the accumulated rotation V.
 //
-// Every wave computes the round's 32 rotations itself (lanes u and u+32 hold
-// pair u; the computation is identical in every wave, so the decisions taken
-// from it are uniform over the workgroup) and publishes them to its own LDS
-// slot, which only that wave reads back (a wave's LDS operations complete in
-// order, so no barrier is needed).  S is double-buffered: a round reads one
+// Every wave computes the round's SB/2 rotations itself (lane l holds pair
+// l mod SB/2; the computation is identical in every wave, so the decisions
+// taken from it are uniform over the workgroup) and publishes them to its own
+// LDS slot, which only that wave reads back (a wave's LDS operations complete
+// in order, so no barrier is needed).  S is double-buffered: a round reads one
 // copy and writes the other, so one barrier per rotating round orders
-// everything.
+// everything.  Thread t updates the 2 x 2 blocks (u, v) = (t mod SB/2, ...)
+// of S, whose row pair u is the pair it computed itself, and SB/2 x SB / 256
+// (row, pair) entries of V.
+template <int SB>
 __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
                                                            const double* __restrict__ M,
                                                            double* __restrict__ Vbuf,
                                                            const double* __restrict__ ctrl,
                                                            int max_inner) {
+  constexpr int HB = SB / 2;                  // block width; also the number of pairs
+  constexpr int NBLK = HB * HB / 256;         // S 2 x 2 blocks per thread
+  constexpr int NVR = SB * HB / 256;          // V (row, pair) entries per thread
+  static_assert(NBLK >= 1 && NVR >= 1, "subproblem too small for 256 threads");
   // ctrl[0] = ||M||_F, ctrl[1] = converged flag
   if (ctrl[1] != 0.0) return;
   __shared__ double Sb[2][SB][SB + 1];
   __shared__ double V[SB][SB + 1];
-  __shared__ double2 cs[4][SB / 2];   // per wave: (c, s) of the round's pairs
+  __shared__ double2 cs[4][HB];   // per wave: (c, s) of the round's pairs
   __shared__ double red[4];
   const int nb = Dp / HB;
   const int slot = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const SlotCols sc = slot_cols(round, slot, nb);
+  const SlotCols<HB> sc = slot_cols<HB>(round, slot, nb);
   double ss = 0.0;
   for (int e = tid; e < SB * SB; e += 256) {
     const int x = e % SB, y = e / SB;
@@ -95,9 +102,11 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
   __syncthreads();
   // Skip a rotation when |a_pq| <= 1e-15 sqrt(|a_pp a_qq|) (relative
   // criterion, so eigenvectors of small eigenvalues stay accurate next to
-  // large ones), with an absolute floor of 1e-30 ||S||_F.
-  const double thr = fmax(1e-30 * sqrt(red[0] + red[1] + red[2] + red[3]), 1e-300);
-  const int u = lane & 31, h = lane >> 5;
+  // large ones), with an absolute floor of 1e-30 ||S||_F; entries below
+  // 1e-150 never rotate, so every square below stays a normal number.
+  const double thr = fmax(1e-30 * sqrt(red[0] + red[1] + red[2] + red[3]), 1e-150);
+  const double thr2 = thr * thr;
+  const int u = tid % HB;
   double2* const csw = cs[w];
   int cur = 0;
   for (int sweep = 0; sweep < max_inner; ++sweep) {
@@ -105,13 +114,18 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
     for (int ir = 0; ir < SB - 1; ++ir) {
       double(*S)[SB + 1] = Sb[cur];
       double(*T)[SB + 1] = Sb[cur ^ 1];
-      // rotation of pair u (Rutishauser: |angle| <= pi/4)
-      const int pu = rr64(ir, u), qu = rr64(ir, SB - 1 - u);
+      // rotation of pair u (the smaller angle, |angle| <= pi/4)
+      const int pu = rr_local<SB>(ir, u), qu = rr_local<SB>(ir, SB - 1 - u);
       const double app = S[pu][pu], aqq = S[qu][qu], apq = S[pu][qu];
       double c = 1.0, sn = 0.0, t = 0.0;
-      if (fabs(apq) > fmax(thr, 1e-15 * sqrt(fabs(app * aqq)))) {
-        const double zeta = (aqq - app) / (2.0 * apq);
-        t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      const double apq2 = apq * apq;
+      if (apq2 > fmax(thr2, 1e-30 * fabs(app * aqq))) {
+        // t = sgn(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)), d = a_qq - a_pp
+        // (sgn(0) = +1), with the root from one refined rsqrt
+        const double d = aqq - app;
+        const double r2 = d * d + 4.0 * apq2;
+        const double r = r2 * rsqrt(r2);
+        t = (d >= 0.0 ? 2.0 : -2.0) * apq / (fabs(d) + r);
         c = rsqrt(1.0 + t * t);
         sn = t * c;
       }
@@ -121,44 +135,46 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
       // subproblem must still be diagonalised for the outer sweeps to
       // converge quadratically.
       significant = significant || (__ballot(fabs(t) > 1e-8) != 0);
-      if (h == 0) csw[u] = make_double2(c, sn);
+      if (lane < HB) csw[u] = make_double2(c, sn);
 
-      // S' = J' S J by 2 x 2 blocks (u, v): v = 8j + 2w + h
-      double x[4][4];
-      int pv[4], qv[4];
-      double2 rv[4];
+      // S' = J' S J by 2 x 2 blocks (u, v)
+      double x[NBLK][4];
+      int pv[NBLK], qv[NBLK];
+      double2 rv[NBLK];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int v = 8 * j + 2 * w + h;
-        pv[j] = rr64(ir, v);
-        qv[j] = rr64(ir, SB - 1 - v);
+      for (int j = 0; j < NBLK; ++j) {
+        const int v = (tid + 256 * j) / HB;
+        pv[j] = rr_local<SB>(ir, v);
+        qv[j] = rr_local<SB>(ir, SB - 1 - v);
         rv[j] = csw[v];
         x[j][0] = S[pu][pv[j]];
         x[j][1] = S[pu][qv[j]];
         x[j][2] = S[qu][pv[j]];
         x[j][3] = S[qu][qv[j]];
       }
-      // V <- V J on rows: lane = row, pairs w + 4k
-      double vp[8], vq[8];
-      double2 r2[8];
-      int p2[8], q2[8];
+      // V <- V J: entries (row, pair u2)
+      double vp[NVR], vq[NVR];
+      double2 r2v[NVR];
+      int p2[NVR], q2[NVR], row[NVR];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int u2 = w + 4 * k;
-        p2[k] = rr64(ir, u2);
-        q2[k] = rr64(ir, SB - 1 - u2);
-        r2[k] = csw[u2];
-        vp[k] = V[lane][p2[k]];
-        vq[k] = V[lane][q2[k]];
+      for (int k = 0; k < NVR; ++k) {
+        const int e = tid + 256 * k;
+        const int u2 = e / SB;
+        row[k] = e % SB;
+        p2[k] = rr_local<SB>(ir, u2);
+        q2[k] = rr_local<SB>(ir, SB - 1 - u2);
+        r2v[k] = csw[u2];
+        vp[k] = V[row[k]][p2[k]];
+        vq[k] = V[row[k]][q2[k]];
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < NBLK; ++j) {
         const double cv = rv[j].x, sv = rv[j].y;
         const double y11 = c * x[j][0] - sn * x[j][2], y12 = c * x[j][1] - sn * x[j][3];
         const double y21 = sn * x[j][0] + c * x[j][2], y22 = sn * x[j][1] + c * x[j][3];
         double z11 = cv * y11 - sv * y12, z12 = sv * y11 + cv * y12;
         double z21 = cv * y21 - sv * y22, z22 = sv * y21 + cv * y22;
-        if (8 * j + 2 * w + h == u && t != 0.0) {
+        if ((tid + 256 * j) / HB == u && t != 0.0) {
           // the pair's own block: exact annihilation (Rutishauser update)
           z11 = x[j][0] - t * x[j][1];
           z22 = x[j][3] + t * x[j][1];
@@ -171,9 +187,9 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
         T[qu][qv[j]] = z22;
       }
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        V[lane][p2[k]] = r2[k].x * vp[k] - r2[k].y * vq[k];
-        V[lane][q2[k]] = r2[k].y * vp[k] + r2[k].x * vq[k];
+      for (int k = 0; k < NVR; ++k) {
+        V[row[k]][p2[k]] = r2v[k].x * vp[k] - r2v[k].y * vq[k];
+        V[row[k]][q2[k]] = r2v[k].y * vp[k] + r2v[k].x * vq[k];
       }
       __syncthreads();
       cur ^= 1;
@@ -185,14 +201,14 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
   // V in MFMA operand order (see vfrag_index)
   double* out = Vbuf + (long)slot * SB * SB;
   for (int e = tid; e < SB * SB; e += 256) {
-    const int l = e & 63, kq = (e >> 6) & 15, cb = e >> 10;
+    const int l = e & 63, kq = (e >> 6) % (SB / 4), cb = e / (16 * SB);
     out[e] = V[4 * kq + (l >> 4)][16 * cb + (l & 15)];
   }
 }
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Apply the round's rotations on the FP64 matrix cores.
+// Apply the round's rotations of 64 x 64 subproblems on the FP64 matrix cores.
 //   M tiles (P <= R): M_out[P,R] = V_P' M_in[P,R] V_R, stored with its mirror
 //   M_out[R,P] = M_out[P,R]' (M stays exactly symmetric; diagonal tiles are
 //   symmetrised);  Psi tiles: Psi[:, P] <- Psi[:, P] V_P for 64-row tiles.
@@ -200,12 +216,13 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // lane l, register r of a tile holds (m = 16 ti + l % 16, n = 16 tj + l / 16
 // + 4 r) within the quadrant.  V operands come straight from global memory
 // in their stored MFMA order; only the M / Psi tile is staged in LDS.
-__global__ __launch_bounds__(256) void jacobi_apply_mfma_kernel(int Dp, int round,
+__global__ __launch_bounds__(256) void jacobi_apply64_kernel(int Dp, int round,
                                                                 const double* __restrict__ Min,
                                                                 double* __restrict__ Mout,
                                                                 double* __restrict__ Psi,
                                                                 const double* __restrict__ Vbuf,
                                                                 const double* __restrict__ ctrl) {
+  constexpr int SB = 64, HB = 32;
   if (ctrl[1] != 0.0) return;
   __shared__ double X[SB][SB + 1];
   const int nb = Dp / HB, ns = nb / 2, ntri = ns * (ns + 1) / 2;
@@ -226,7 +243,7 @@ __global__ __launch_bounds__(256) void jacobi_apply_mfma_kernel(int Dp, int roun
     int P = 0, rowlen = ns;
     while (bx >= rowlen) { bx -= rowlen; ++P; --rowlen; }
     const int R = P + bx;
-    const SlotCols cp = slot_cols(round, P, nb), cr = slot_cols(round, R, nb);
+    const SlotCols cp = slot_cols<HB>(round, P, nb), cr = slot_cols<HB>(round, R, nb);
     for (int e = tid; e < SB * SB; e += 256) {
       const int x = e % SB, y = e / SB;
       X[x][y] = Min[cp.col(x) + (long)cr.col(y) * Dp];
@@ -242,7 +259,7 @@ __global__ __launch_bounds__(256) void jacobi_apply_mfma_kernel(int Dp, int roun
       double av[2], bv[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        av[t] = VP[vfrag_index(2 * wm + t, kq, lane)];
+        av[t] = VP[vfrag_index<SB>(2 * wm + t, kq, lane)];
         bv[t] = X[k][wn * 32 + t * 16 + lm];
       }
 #pragma unroll
@@ -269,7 +286,7 @@ __global__ __launch_bounds__(256) void jacobi_apply_mfma_kernel(int Dp, int roun
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         av[t] = X[wm * 32 + t * 16 + lm][k];
-        bv[t] = VR[vfrag_index(2 * wn + t, kq, lane)];
+        bv[t] = VR[vfrag_index<SB>(2 * wn + t, kq, lane)];
       }
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
@@ -302,7 +319,7 @@ __global__ __launch_bounds__(256) void jacobi_apply_mfma_kernel(int Dp, int roun
     const int k = bx - ntri;
     const int P = k % ns, rt = k / ns;
     const int row0 = rt * SB;
-    const SlotCols cp = slot_cols(round, P, nb);
+    const SlotCols cp = slot_cols<HB>(round, P, nb);
     for (int e = tid; e < SB * SB; e += 256) {
       const int x = e % SB, y = e / SB;
       X[x][y] = Psi[(row0 + x) + (long)cp.col(y) * Dp];
@@ -318,7 +335,7 @@ __global__ __launch_bounds__(256) void jacobi_apply_mfma_kernel(int Dp, int roun
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         av[t] = X[wm * 32 + t * 16 + lm][kk];
-        bv[t] = VP[vfrag_index(2 * wn + t, kq, lane)];
+        bv[t] = VP[vfrag_index<SB>(2 * wn + t, kq, lane)];
       }
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
@@ -334,6 +351,136 @@ __global__ __launch_bounds__(256) void jacobi_apply_mfma_kernel(int Dp, int roun
         for (int r = 0; r < 4; ++r)
           Psi[(row0 + wm * 32 + ti * 16 + lm) +
               (long)cp.col(wn * 32 + tj * 16 + lk + 4 * r) * Dp] = acc[ti][tj][r];
+  }
+}
+
+// Apply the round's rotations of 32 x 32 subproblems: one wave per 32 x 32
+// tile (2 x 2 tiles of v_mfma_f64_16x16x4f64, lane l, register r holding
+// (m = 16 ti + l % 16, n = 16 tj + l / 16 + 4 r)), four tiles per workgroup.
+// Each wave stages its tile in its own LDS region and needs no barrier.
+// Tiles 0 .. ntri-1 are the M tiles (P <= R) in row order, then the Psi tiles.
+__global__ __launch_bounds__(256) void jacobi_apply32_kernel(int Dp, int round,
+                                                             const double* __restrict__ Min,
+                                                             double* __restrict__ Mout,
+                                                             double* __restrict__ Psi,
+                                                             const double* __restrict__ Vbuf,
+                                                             const double* __restrict__ ctrl) {
+  constexpr int SB = 32, HB = 16;
+  if (ctrl[1] != 0.0) return;
+  __shared__ double Xs[4][SB][SB + 1];
+  const int nb = Dp / HB, ns = nb / 2, ntri = ns * (ns + 1) / 2;
+  const int ntiles = ntri + (Dp / SB) * ns;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int tile = blockIdx.x * 4 + wave;
+  if (tile >= ntiles) return;
+  double(*X)[SB + 1] = Xs[wave];
+  const int lm = lane & 15, lk = lane >> 4;
+  d4 acc[2][2];
+  auto zero = [&] {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
+  };
+  auto to_lds = [&] {
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) X[ti * 16 + lm][tj * 16 + lk + 4 * r] = acc[ti][tj][r];
+  };
+  if (tile < ntri) {
+    int P = 0, rowlen = ns;
+    while (tile >= rowlen) { tile -= rowlen; ++P; --rowlen; }
+    const int R = P + tile;
+    const SlotCols<HB> cp = slot_cols<HB>(round, P, nb), cr = slot_cols<HB>(round, R, nb);
+    for (int e = lane; e < SB * SB; e += 64) {
+      const int x = e % SB, y = e / SB;
+      X[x][y] = Min[cp.col(x) + (long)cr.col(y) * Dp];
+    }
+    const double* VP = Vbuf + (long)P * SB * SB;
+    const double* VR = Vbuf + (long)R * SB * SB;
+    // Y = VP' X
+    zero();
+#pragma unroll
+    for (int kq = 0; kq < SB / 4; ++kq) {
+      const int k = 4 * kq + lk;
+      double av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = VP[vfrag_index<SB>(t, kq, lane)];
+        bv[t] = X[k][t * 16 + lm];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
+    }
+    to_lds();
+    // Z = Y VR
+    zero();
+#pragma unroll
+    for (int kq = 0; kq < SB / 4; ++kq) {
+      const int k = 4 * kq + lk;
+      double av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = X[t * 16 + lm][k];
+        bv[t] = VR[vfrag_index<SB>(t, kq, lane)];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
+    }
+    to_lds();
+    if (P == R) {
+      for (int e = lane; e < SB * SB; e += 64) {
+        const int x = e % SB, y = e / SB;
+        Mout[cp.col(x) + (long)cp.col(y) * Dp] = 0.5 * (X[x][y] + X[y][x]);
+      }
+    } else {
+      for (int e = lane; e < SB * SB; e += 64) {
+        const int x = e % SB, y = e / SB;
+        Mout[cp.col(x) + (long)cr.col(y) * Dp] = X[x][y];
+        Mout[cr.col(x) + (long)cp.col(y) * Dp] = X[y][x];
+      }
+    }
+  } else {
+    const int k = tile - ntri;
+    const int P = k % ns, rt = k / ns;
+    const int row0 = rt * SB;
+    const SlotCols<HB> cp = slot_cols<HB>(round, P, nb);
+    for (int e = lane; e < SB * SB; e += 64) {
+      const int x = e % SB, y = e / SB;
+      X[x][y] = Psi[(row0 + x) + (long)cp.col(y) * Dp];
+    }
+    const double* VP = Vbuf + (long)P * SB * SB;
+    zero();
+#pragma unroll
+    for (int kq = 0; kq < SB / 4; ++kq) {
+      const int kk = 4 * kq + lk;
+      double av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = X[t * 16 + lm][kk];
+        bv[t] = VP[vfrag_index<SB>(t, kq, lane)];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
+    }
+    to_lds();
+    for (int e = lane; e < SB * SB; e += 64) {
+      const int x = e % SB, y = e / SB;
+      Psi[(row0 + x) + (long)cp.col(y) * Dp] = X[x][y];
+    }
   }
 }
 
@@ -573,19 +720,28 @@ __global__ void pad_identity_kernel(int D, int Dp, const double* __restrict__ Q,
 
 }  // namespace
 
-int eig_padded_dim(int D) { return ((D + SB - 1) / SB) * SB; }
+// padded to a multiple of 64 (whole 64 x 64 tiles for every kernel)
+int eig_padded_dim(int D) { return ((D + 63) / 64) * 64; }
+
+// Subproblem size of the block Jacobi: 32 x 32 (blocks of 16 columns) or 64 x 64.
+#ifndef RM_JACOBI_SB
+#define RM_JACOBI_SB 32
+#endif
+constexpr int JSB = RM_JACOBI_SB, JHB = JSB / 2;
+static_assert(JSB == 32 || JSB == 64, "subproblem size must be 32 or 64");
 
 void eig_workspace_sizes(int D, long* doubles) {
   const int Dp = eig_padded_dim(D);
-  const int nb = Dp / HB;
-  *doubles = 3L * Dp * Dp + (long)(nb / 2) * SB * SB + 3L * (Dp / OFF_COLS + 1) + 8;
+  const int nb = Dp / JHB;
+  *doubles = 3L * Dp * Dp + (long)(nb / 2) * JSB * JSB + 3L * (Dp / OFF_COLS + 1) + 8;
 }
 
 void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, int* sweeps_out,
                 hipStream_t st) {
   // Input: w.M (Dp x Dp symmetric, padded) and w.Psi (Dp x Dp, padded with identity).
   const int Dp = eig_padded_dim(D);
-  const int nb = Dp / HB, ns = nb / 2;
+  const int nb = Dp / JHB, ns = nb / 2;
+  RM_REQUIRE(Dp % JSB == 0 && nb % 2 == 0, "softabs_eig: padded dimension does not fit the blocks");
   RM_REQUIRE(Dp <= OFF_MAXDP, "softabs_eig: dimension too large for the convergence check");
   const int nparts = Dp / OFF_COLS;
   double* Min = w.M;
@@ -607,19 +763,29 @@ void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, i
     if (sw >= max_sweeps) break;
     for (int r = 0; r < nb - 1; ++r) {
       int slot = timing_begin(TK_JACOBI_SOLVE, st);
-      hipLaunchKernelGGL(jacobi_solve_kernel, dim3(ns), dim3(256), 0, st, Dp, r,
+      hipLaunchKernelGGL(jacobi_solve_kernel<JSB>, dim3(ns), dim3(256), 0, st, Dp, r,
                          (const double*)Min, w.V, (const double*)w.ctrl, max_inner);
       RM_CHECK_LAUNCH();
-      // one inner sweep of a 64x64 subproblem: 63 rounds x (1024 2x2 blocks x 24
-      // flops + 2048 V row pairs x 6 flops); bytes: subproblems in, rotations out
-      timing_end(slot, st, (double)ns * 63.0 * (1024.0 * 24.0 + 2048.0 * 6.0),
-                 2.0 * ns * SB * SB * sizeof(double));
+      // one inner sweep of an SB x SB subproblem: SB-1 rounds x ((SB/2)^2 2x2
+      // blocks x 24 flops + SB^2/2 V row pairs x 6 flops); bytes: subproblems
+      // in, rotations out
+      timing_end(slot, st,
+                 (double)ns * (JSB - 1) * (JHB * JHB * 24.0 + JSB * JHB * 6.0),
+                 2.0 * ns * JSB * JSB * sizeof(double));
       slot = timing_begin(TK_JACOBI_APPLY, st);
-      hipLaunchKernelGGL(jacobi_apply_mfma_kernel, dim3(ns * (ns + 1) / 2 + (Dp / SB) * ns), dim3(256), 0, st, Dp,
-                         r, (const double*)Min, Mout, w.Psi, (const double*)w.V,
-                         (const double*)w.ctrl);
+      const long ntri = (long)ns * (ns + 1) / 2, npsi = (long)(Dp / JSB) * ns;
+      if (JSB == 64) {
+        hipLaunchKernelGGL(jacobi_apply64_kernel, dim3(ntri + npsi), dim3(256), 0, st, Dp, r,
+                           (const double*)Min, Mout, w.Psi, (const double*)w.V,
+                           (const double*)w.ctrl);
+      } else {
+        hipLaunchKernelGGL(jacobi_apply32_kernel, dim3(cdiv(ntri + npsi, 4)), dim3(256), 0, st, Dp,
+                           r, (const double*)Min, Mout, w.Psi, (const double*)w.V,
+                           (const double*)w.ctrl);
+      }
       RM_CHECK_LAUNCH();
-      timing_end(slot, st, 4.0 * (double)SB * SB * SB * (ns * (ns + 1) / 2) + 2.0 * (double)SB * SB * SB * (Dp / SB) * ns,
+      const double sb3 = (double)JSB * JSB * JSB;
+      timing_end(slot, st, 4.0 * sb3 * ntri + 2.0 * sb3 * npsi,
                  4.0 * (double)Dp * Dp * sizeof(double));
       std::swap(Min, Mout);
     }
