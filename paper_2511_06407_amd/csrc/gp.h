@@ -39,9 +39,20 @@ void kd_wsum(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
              const double* Kinv, const double* alpha, const double* Wstack, int nw, double* out,
              double* work, hipStream_t st);
 
+// out[w * nt + t] = sum_ij W_w(i,j) * d^ord K / d eta_tuple(i,j) for nw weights
+// from a stack (stride N*N): the tuple derivatives are generated once into
+// KT (at most MAX_TUPLES x N*N values) and contracted with every weight by a
+// deterministic tall-K GEMM (`tallwork`: tallk_splits(N*N) * MAX_TUPLES * nw).
+void kd_wsum_stack(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
+                   const double* Wstack, int nw, double* out, double* KT, double* tallwork,
+                   hipStream_t st);
+
 // y[(x * nt + t) * N + i] = sum_j d K_tuple(i,j) x_x(j), for nx vectors x (stride N).
+// The j range is split over KD_MV_SPLIT workgroup columns; `work` holds
+// KD_MV_SPLIT * min(nt, MAX_TUPLES) * nx * N partial sums.
+constexpr int KD_MV_SPLIT = 16;
 void kd_matvec(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
-               const double* x, int nx, double* y, hipStream_t st);
+               const double* x, int nx, double* y, double* work, hipStream_t st);
 
 // l, l', l'', l''' of the per-sample negative log likelihood: out[0..4N).
 void lik_derivs(int N, int lik, double noise_var, const double* f, const double* y, double* out,

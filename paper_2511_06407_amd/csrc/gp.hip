@@ -152,24 +152,26 @@ __global__ void kd_wsum_reduce(int nblk, int nt, int nw, const double* __restric
   out[idx] = s;
 }
 
+// Partial sums of y = dK_tuple x over the j chunk blockIdx.z.
 __global__ __launch_bounds__(256) void kd_matvec_kernel(ModelDev md, const double* __restrict__ eta,
                                                         const Tuple* __restrict__ tuples, int nt,
-                                                        const double* __restrict__ x,
-                                                        double* __restrict__ y) {
+                                                        const double* __restrict__ x, int nx,
+                                                        int jchunk, double* __restrict__ part) {
   __shared__ double sh[4][64];
   __shared__ Tuple stup[MAX_TUPLES];
   for (int t = threadIdx.x; t < nt; t += blockDim.x) stup[t] = tuples[t];
   __syncthreads();
   const int N = md.N;
-  const int xi = blockIdx.y;
+  const int xi = blockIdx.y, jz = blockIdx.z;
   const double* xv = x + (long)xi * N;
   const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + r;
+  const int j0 = jz * jchunk, j1 = min(N, j0 + jchunk);
   double acc[MAX_TUPLES];
 #pragma unroll
   for (int t = 0; t < MAX_TUPLES; ++t) acc[t] = 0.0;
   if (i < N) {
-    for (int j = g; j < N; j += 4) {
+    for (int j = j0 + g; j < j1; j += 4) {
       TermVals tv[MAX_TERMS];
       for (int t = 0; t < md.nterms; ++t) term_eval(md, eta, t, i, j, tv[t]);
       const double xj = xv[j];
@@ -183,9 +185,37 @@ __global__ __launch_bounds__(256) void kd_matvec_kernel(ModelDev md, const doubl
     if (t < nt) {
       sh[g][r] = acc[t];
       __syncthreads();
-      if (g == 0 && i < N) y[((long)xi * nt + t) * N + i] = sh[0][r] + sh[1][r] + sh[2][r] + sh[3][r];
+      if (g == 0 && i < N)
+        part[(((long)jz * nx + xi) * nt + t) * N + i] = sh[0][r] + sh[1][r] + sh[2][r] + sh[3][r];
       __syncthreads();
     }
+  }
+}
+
+// y[(x * nt + t) * N + i] = sum over chunks in order.
+__global__ void kd_matvec_reduce(long n, int nsplit, const double* __restrict__ part,
+                                 double* __restrict__ y) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double s = 0.0;
+  for (int z = 0; z < nsplit; ++z) s += part[(long)z * n + e];
+  y[e] = s;
+}
+
+// KT[t * NN + e] = d^ord K / d eta_tuple at element e = i + j N.
+__global__ __launch_bounds__(256) void kd_gen_kernel(ModelDev md, const double* __restrict__ eta,
+                                                     const Tuple* __restrict__ tuples, int nt,
+                                                     double* __restrict__ KT) {
+  __shared__ Tuple stup[MAX_TUPLES];
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) stup[t] = tuples[t];
+  __syncthreads();
+  const long NN = (long)md.N * md.N;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < NN; e += stride) {
+    const int i = (int)(e % md.N), j = (int)(e / md.N);
+    TermVals tv[MAX_TERMS];
+    for (int t = 0; t < md.nterms; ++t) term_eval(md, eta, t, i, j, tv[t]);
+    for (int t = 0; t < nt; ++t) KT[(long)t * NN + e] = tuple_val(md, tv, stup[t]);
   }
 }
 
@@ -279,19 +309,44 @@ static void kd_wsum_chunk(const ModelDev& md, const double* eta, const Tuple* tu
 }
 
 void kd_matvec(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
-               const double* x, int nx, double* y, hipStream_t st) {
+               const double* x, int nx, double* y, double* work, hipStream_t st) {
   if (nt <= 0 || nx <= 0) return;
   RM_REQUIRE(nt <= MAX_TUPLES || nx == 1, "kd_matvec: chunked tuples need a single vector");
   if (nt > MAX_TUPLES) {
     for (int t0 = 0; t0 < nt; t0 += MAX_TUPLES)
-      kd_matvec(md, eta, tuples + t0, std::min(MAX_TUPLES, nt - t0), x, 1, y + (long)t0 * md.N, st);
+      kd_matvec(md, eta, tuples + t0, std::min(MAX_TUPLES, nt - t0), x, 1, y + (long)t0 * md.N,
+                work, st);
     return;
   }
+  const int N = md.N;
+  const int jchunk = cdiv(N, KD_MV_SPLIT);
+  const int nsplit = cdiv(N, jchunk);
+  const long n = (long)nt * nx * N;
   const int slot = timing_begin(TK_KD_MATVEC, st);
-  hipLaunchKernelGGL(kd_matvec_kernel, dim3(cdiv(md.N, 64), nx), dim3(256), 0, st, md, eta,
-                     tuples, nt, x, y);
+  hipLaunchKernelGGL(kd_matvec_kernel, dim3(cdiv(N, 64), nx, nsplit), dim3(256), 0, st, md, eta,
+                     tuples, nt, x, nx, jchunk, work);
   RM_CHECK_LAUNCH();
-  timing_end(slot, st, 2.0 * (double)md.N * md.N * nt * nx, (double)md.N * nx * (1.0 + nt) * sizeof(double));
+  hipLaunchKernelGGL(kd_matvec_reduce, dim3(cdiv(n, 256)), dim3(256), 0, st, n, nsplit,
+                     (const double*)work, y);
+  RM_CHECK_LAUNCH();
+  timing_end(slot, st, 2.0 * (double)N * N * nt * nx, (double)N * nx * (1.0 + nt) * sizeof(double));
+}
+
+void kd_wsum_stack(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
+                   const double* Wstack, int nw, double* out, double* KT, double* tallwork,
+                   hipStream_t st) {
+  if (nt <= 0 || nw <= 0) return;
+  const long NN = (long)md.N * md.N;
+  const int nblk = std::max(1, std::min(2048, cdiv(NN, 256 * 4)));
+  for (int t0 = 0; t0 < nt; t0 += MAX_TUPLES) {
+    const int c = std::min(MAX_TUPLES, nt - t0);
+    const int slot = timing_begin(TK_KD_WSUM, st);
+    hipLaunchKernelGGL(kd_gen_kernel, dim3(nblk), dim3(256), 0, st, md, eta, tuples + t0, c, KT);
+    RM_CHECK_LAUNCH();
+    timing_end(slot, st, 0.0, (double)NN * c * sizeof(double));
+    // out(t, w) at out[w * nt + t]: C = KT' W with ldc = nt, columns offset by t0
+    gemm_tallk(c, nw, NN, KT, NN, Wstack, NN, out + t0, nt, tallwork, tallk_splits(NN), st);
+  }
 }
 
 void lik_derivs(int N, int lik, double noise_var, const double* f, const double* y, double* out,

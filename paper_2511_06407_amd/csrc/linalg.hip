@@ -202,9 +202,11 @@ __global__ void reduce_parts_kernel(int nparts, int nb, const double* part, doub
 // Then L_ij = S_ij / sqrt(d_j), L_jj = sqrt(d_j).  Padding rows/columns of a
 // partial block start as the identity, so they factor trivially.
 //
-// Inverse: wave 0, one lane per column c, forward substitution
-// X[r][c] = (delta_rc - sum_{k<r} L[r][k] X[k][c]) / L[r][r] with X in
-// registers and L read from LDS (same address in every lane).
+// Inverse: wave 0, one lane per column c, right-looking forward
+// substitution: once X[r][c] is final (scaled by 1/L[r][r]) it is removed
+// from every later row, a[i] -= L[i][r] X[r][c], so the updates of a step are
+// independent of each other.  a stays in registers; L is read from LDS at
+// the same address in every lane.
 __global__ __launch_bounds__(256) void potrf_diag_kernel(int n, int k0, double* L, long ldl,
                                                          double* Linv, double* diagLogs,
                                                          int* info) {
@@ -213,6 +215,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int n, int k0, double* 
   __shared__ double dg[CB];
   __shared__ double Ls[CB][CB + 1];
   __shared__ double Xs[CB][CB + 1];
+  __shared__ double rl[CB];   // 1 / L[k][k]
   const int w = min(CB, n - k0);
   const int tid = threadIdx.x;
   const int i = tid & (CB - 1);
@@ -245,19 +248,21 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int n, int k0, double* 
     const double dk = dg[k];
     Ls[i][k] = i > k ? sv[m] * rsqrt(dk) : (i == k ? sqrt(dk) : 0.0);
   }
+  if (tid < CB) rl[tid] = rsqrt(dg[tid]);
   __syncthreads();
   if (tid < CB) {
     const int c = tid;
-    double x[CB];
+    double a[CB];
+#pragma unroll
+    for (int r = 0; r < CB; ++r) a[r] = (r == c) ? 1.0 : 0.0;
 #pragma unroll
     for (int r = 0; r < CB; ++r) {
-      double acc = (r == c) ? 1.0 : 0.0;
+      a[r] *= rl[r];
 #pragma unroll
-      for (int k = 0; k < r; ++k) acc -= Ls[r][k] * x[k];
-      x[r] = acc * rsqrt(dg[r]);
+      for (int i = r + 1; i < CB; ++i) a[i] -= Ls[i][r] * a[r];
     }
 #pragma unroll
-    for (int r = 0; r < CB; ++r) Xs[r][c] = x[r];
+    for (int r = 0; r < CB; ++r) Xs[r][c] = a[r];
   }
   __syncthreads();
   for (int e = tid; e < CB * CB; e += 256) {

@@ -242,6 +242,8 @@ struct Model {
   CholWork chol;
   EigWork eig;
   double *tallwork = nullptr, *kdwork = nullptr, *mdwork = nullptr;
+  double *mvwork = nullptr;   // column-split partials of kd_matvec
+  double *ktbuf = nullptr;    // generated second derivatives of K (<= MAX_TUPLES x N*N)
   double *W = nullptr, *Wt1 = nullptr, *Wt2 = nullptr;
   double *vc = nullptr, *vb = nullptr, *vtmp = nullptr, *vtmp2 = nullptr, *v1 = nullptr;
   double *u = nullptr, *Au = nullptr, *Ku = nullptr, *z = nullptr, *Kz = nullptr, *wB = nullptr;
@@ -527,7 +529,7 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
     }
     gemm_tallk(P, m.nyy, NN, pt.Af, NN, pt.Ytf, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
   }
-  kd_matvec(m.md, eta, m.pairs, m.npairs, pt.alpha, 1, pt.k2a, st);
+  kd_matvec(m.md, eta, m.pairs, m.npairs, pt.alpha, 1, pt.k2a, m.mvwork, st);
   {
     Gemm<double> g;  // ik2a = K^-1 [K_lm alpha]
     g.m = N; g.n = m.npairs; g.k = N;
@@ -549,7 +551,7 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
     h.C = pt.Aam;
     gemm(h, st);
   }
-  kd_wsum(m.md, eta, m.pairs, m.npairs, 1, nullptr, nullptr, pt.B, P, m.tB, m.kdwork, st);
+  kd_wsum_stack(m.md, eta, m.pairs, m.npairs, pt.B, P, m.tB, m.ktbuf, m.tallwork, st);
   kd_wsum(m.md, eta, m.triples, m.ntriples, 0, pt.Kinv, pt.alpha, nullptr, 1, m.t3, m.kdwork, st);
   pair_dots(N, pt.k1a, N, P, pt.Aam, N, P * P, m.D1, st);
   pair_dots(N, pt.k2a, N, m.npairs, pt.a, N, P, m.D2, st);
@@ -767,6 +769,8 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   const int spl = tallk_splits(NN);
   m.tallwork = pl.alloc<double>((long)spl * P * std::max(P, m.nyy) + 64);
   m.kdwork = pl.alloc<double>(512L * MAX_P * MAX_TUPLES + (long)MAX_P * std::max(m.ntriples, m.npairs) + 64);
+  m.mvwork = pl.alloc<double>((long)KD_MV_SPLIT * std::min(m.npairs, MAX_TUPLES) * N + 64);
+  m.ktbuf = pl.alloc<double>((long)std::min(m.npairs, MAX_TUPLES) * N * N + 64);
   m.mdwork = pl.alloc<double>((long)(std::max<long>(N, Dp) / 4 + 2) * 32);
   m.W = pl.alloc<double>(Dp * Dp);
   m.Wt1 = pl.alloc<double>(Dp * Dp);
