@@ -8,7 +8,7 @@ struct EigWork {
   double* M = nullptr;     // Dp x Dp working matrix (ld Dp)
   double* M2 = nullptr;    // second buffer
   double* Psi = nullptr;   // Dp x Dp eigenvectors (columns), identity-padded
-  double* V = nullptr;     // per-slot 64 x 64 rotations
+  double* V = nullptr;     // per-slot 32 x 32 rotations, two sets (eig_rotation_doubles)
   double* part = nullptr;  // reduction partials
   double* ctrl = nullptr;  // device: ||M||_F, converged, ratio, checks
   double* ctrl_host = nullptr;  // pinned host mirror of ctrl
@@ -27,6 +27,10 @@ void eig_load_basis(int D, const double* Q, long ldq, EigWork& w, hipStream_t st
 // with up to JACOBI_INNER_STATIC.
 constexpr int JACOBI_INNER_STATIC = 4;
 constexpr int JACOBI_INNER_DYNAMIC = 1;
+// Doubles of EigWork::V for a padded dimension Dp: two sets of 32 x 32
+// rotations, one per slot (double-buffered across rounds).
+inline long eig_rotation_doubles(int Dp) { return 2L * (Dp / 32) * 32 * 32; }
+
 void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, int* sweeps_out,
                 hipStream_t st);
 // Rayleigh quotients lam_i = psi_i' H psi_i of the converged basis against the

@@ -3,14 +3,16 @@
 // Psi = Psi_prev Q).
 //
 // Block Jacobi on the padded Dp x Dp matrix (Dp a multiple of 64): the
-// nb = Dp/32 column blocks play a round-robin tournament, nb-1 rounds per
-// sweep.  In a round every pair of blocks (I, J) forms a 64 x 64 symmetric
+// nb = Dp/16 column blocks play a round-robin tournament, nb-1 rounds per
+// sweep.  In a round every pair of blocks (I, J) forms a 32 x 32 symmetric
 // subproblem that one workgroup diagonalises in LDS with an inner cyclic
-// Jacobi (its own round-robin over 64 indices); the resulting 64 x 64
-// rotations are then applied to all of M (double-buffered, one 64 x 64
-// tile per workgroup) and to the columns of Psi.  Padding rows/columns are
-// zero and never rotate (their off-diagonal entries stay exactly zero).
-// Rotations use Rutishauser's formulas (|angle| <= pi/4).
+// Jacobi (its own round-robin over 32 indices); the resulting 32 x 32
+// rotations are then applied to M (one wave per 32 x 32 tile on the FP64
+// matrix cores, double-buffered M) and to the columns of Psi (fused into
+// the next round's solve launch).  Padding rows/columns are zero and never
+// rotate (their off-diagonal entries stay exactly zero).  Each rotation
+// takes the smaller angle (|angle| <= pi/4) and annihilates its pair
+// exactly (Rutishauser's update of the diagonal).
 #include <cmath>
 #include <utility>
 
@@ -68,34 +70,36 @@ __device__ __forceinline__ int vfrag_index(int cb, int kq, int lane) {
 // of S, whose row pair u is the pair it computed itself, and SB/2 x SB / 256
 // (row, pair) entries of V.
 template <int SB>
-__global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
-                                                           const double* __restrict__ M,
-                                                           double* __restrict__ Vbuf,
-                                                           const double* __restrict__ ctrl,
-                                                           int max_inner) {
+__device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
+                                                   const double* __restrict__ M,
+                                                   double* __restrict__ Vbuf, int max_inner) {
   constexpr int HB = SB / 2;                  // block width; also the number of pairs
   constexpr int NBLK = HB * HB / 256;         // S 2 x 2 blocks per thread
   constexpr int NVR = SB * HB / 256;          // V (row, pair) entries per thread
   static_assert(NBLK >= 1 && NVR >= 1, "subproblem too small for 256 threads");
-  // ctrl[0] = ||M||_F, ctrl[1] = converged flag
-  if (ctrl[1] != 0.0) return;
   __shared__ double Sb[2][SB][SB + 1];
   __shared__ double V[SB][SB + 1];
   __shared__ double2 cs[4][HB];   // per wave: (c, s) of the round's pairs
   __shared__ double red[4];
   const int nb = Dp / HB;
-  const int slot = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const SlotCols<HB> sc = slot_cols<HB>(round, slot, nb);
+  constexpr int NLD = SB * SB / 256;
+  double ld[NLD];
+#pragma unroll
+  for (int i = 0; i < NLD; ++i) {
+    const int e = tid + 256 * i, x = e % SB, y = e / SB;
+    ld[i] = M[sc.col(x) + (long)sc.col(y) * Dp];
+  }
   double ss = 0.0;
-  for (int e = tid; e < SB * SB; e += 256) {
-    const int x = e % SB, y = e / SB;
-    const double v = M[sc.col(x) + (long)sc.col(y) * Dp];
-    Sb[0][x][y] = v;
+#pragma unroll
+  for (int i = 0; i < NLD; ++i) {
+    const int e = tid + 256 * i, x = e % SB, y = e / SB;
+    Sb[0][x][y] = ld[i];
     V[x][y] = (x == y) ? 1.0 : 0.0;
-    ss += v * v;
+    ss += ld[i] * ld[i];
   }
   for (int o = 32; o > 0; o >>= 1) ss += __shfl_down(ss, o, 64);
   if (lane == 0) red[w] = ss;
@@ -208,280 +212,180 @@ __global__ __launch_bounds__(256) void jacobi_solve_kernel(int Dp, int round,
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Apply the round's rotations of 64 x 64 subproblems on the FP64 matrix cores.
-//   M tiles (P <= R): M_out[P,R] = V_P' M_in[P,R] V_R, stored with its mirror
-//   M_out[R,P] = M_out[P,R]' (M stays exactly symmetric; diagonal tiles are
-//   symmetrised);  Psi tiles: Psi[:, P] <- Psi[:, P] V_P for 64-row tiles.
-// Each wave owns a 32 x 32 quadrant (2 x 2 tiles of v_mfma_f64_16x16x4f64);
-// lane l, register r of a tile holds (m = 16 ti + l % 16, n = 16 tj + l / 16
-// + 4 r) within the quadrant.  V operands come straight from global memory
-// in their stored MFMA order; only the M / Psi tile is staged in LDS.
-__global__ __launch_bounds__(256) void jacobi_apply64_kernel(int Dp, int round,
-                                                                const double* __restrict__ Min,
-                                                                double* __restrict__ Mout,
-                                                                double* __restrict__ Psi,
-                                                                const double* __restrict__ Vbuf,
-                                                                const double* __restrict__ ctrl) {
-  constexpr int SB = 64, HB = 32;
-  if (ctrl[1] != 0.0) return;
-  __shared__ double X[SB][SB + 1];
-  const int nb = Dp / HB, ns = nb / 2, ntri = ns * (ns + 1) / 2;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = wave & 1, wn = wave >> 1;
-  const int lm = lane & 15, lk = lane >> 4;
-  int bx = blockIdx.x;
-  d4 acc[2][2];
-  auto zero = [&] {
+constexpr int JSB = 32, JHB = 16;   // subproblem size of the block Jacobi and its block width
+
+// C (32 x 32, one wave) = sum_k A(m, k) B(k, n) on v_mfma_f64_16x16x4f64:
+// 2 x 2 tiles, lane l, register r of tile (ti, tj) holding
+// (m = 16 ti + l % 16, n = 16 tj + l / 16 + 4 r).  Aat(t, kq) returns this
+// lane's A(16 t + l % 16, 4 kq + l / 16), Bat(kq, t) its B(4 kq + l / 16,
+// 16 t + l % 16).
+template <class FA, class FB>
+__device__ __forceinline__ void mm32_wave(FA Aat, FB Bat, d4 acc[2][2]) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
-  };
-  if (bx < ntri) {
-    // upper-triangle tile (P, R), P <= R, from the linear index bx
-    int P = 0, rowlen = ns;
-    while (bx >= rowlen) { bx -= rowlen; ++P; --rowlen; }
-    const int R = P + bx;
-    const SlotCols cp = slot_cols<HB>(round, P, nb), cr = slot_cols<HB>(round, R, nb);
-    for (int e = tid; e < SB * SB; e += 256) {
-      const int x = e % SB, y = e / SB;
-      X[x][y] = Min[cp.col(x) + (long)cr.col(y) * Dp];
-    }
-    const double* VP = Vbuf + (long)P * SB * SB;
-    const double* VR = Vbuf + (long)R * SB * SB;
-    __syncthreads();
-    // Y = VP' X:  A(m, k) = VP(k, m), B(k, n) = X(k, n)
-    zero();
-#pragma unroll 4
-    for (int kq = 0; kq < SB / 4; ++kq) {
-      const int k = 4 * kq + lk;
-      double av[2], bv[2];
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        av[t] = VP[vfrag_index<SB>(2 * wm + t, kq, lane)];
-        bv[t] = X[k][wn * 32 + t * 16 + lm];
-      }
+  for (int kq = 0; kq < JSB / 4; ++kq) {
+    double av[2], bv[2];
 #pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
-          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          X[wm * 32 + ti * 16 + lm][wn * 32 + tj * 16 + lk + 4 * r] = acc[ti][tj][r];
-    __syncthreads();
-    // Z = Y VR:  A(m, k) = Y(m, k), B(k, n) = VR(k, n)
-    zero();
-#pragma unroll 4
-    for (int kq = 0; kq < SB / 4; ++kq) {
-      const int k = 4 * kq + lk;
-      double av[2], bv[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        av[t] = X[wm * 32 + t * 16 + lm][k];
-        bv[t] = VR[vfrag_index<SB>(2 * wn + t, kq, lane)];
-      }
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
-          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          X[wm * 32 + ti * 16 + lm][wn * 32 + tj * 16 + lk + 4 * r] = acc[ti][tj][r];
-    __syncthreads();
-    if (P == R) {
-      for (int e = tid; e < SB * SB; e += 256) {
-        const int x = e % SB, y = e / SB;
-        Mout[cp.col(x) + (long)cp.col(y) * Dp] = 0.5 * (X[x][y] + X[y][x]);
-      }
-    } else {
-      for (int e = tid; e < SB * SB; e += 256) {
-        const int x = e % SB, y = e / SB;
-        Mout[cp.col(x) + (long)cr.col(y) * Dp] = X[x][y];
-        Mout[cr.col(x) + (long)cp.col(y) * Dp] = X[y][x];
-      }
-    }
-  } else {
-    const int k = bx - ntri;
-    const int P = k % ns, rt = k / ns;
-    const int row0 = rt * SB;
-    const SlotCols cp = slot_cols<HB>(round, P, nb);
-    for (int e = tid; e < SB * SB; e += 256) {
-      const int x = e % SB, y = e / SB;
-      X[x][y] = Psi[(row0 + x) + (long)cp.col(y) * Dp];
-    }
-    const double* VP = Vbuf + (long)P * SB * SB;
-    __syncthreads();
-    // Psi tile <- X VP:  A(m, k) = X(m, k), B(k, n) = VP(k, n)
-    zero();
-#pragma unroll 4
-    for (int kq = 0; kq < SB / 4; ++kq) {
-      const int kk = 4 * kq + lk;
-      double av[2], bv[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        av[t] = X[wm * 32 + t * 16 + lm][kk];
-        bv[t] = VP[vfrag_index<SB>(2 * wn + t, kq, lane)];
-      }
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
-          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
+    for (int t = 0; t < 2; ++t) {
+      av[t] = Aat(t, kq);
+      bv[t] = Bat(kq, t);
     }
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          Psi[(row0 + wm * 32 + ti * 16 + lm) +
-              (long)cp.col(wn * 32 + tj * 16 + lk + 4 * r) * Dp] = acc[ti][tj][r];
+        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
   }
 }
 
-// Apply the round's rotations of 32 x 32 subproblems: one wave per 32 x 32
-// tile (2 x 2 tiles of v_mfma_f64_16x16x4f64, lane l, register r holding
-// (m = 16 ti + l % 16, n = 16 tj + l / 16 + 4 r)), four tiles per workgroup.
-// Each wave stages its tile in its own LDS region and needs no barrier.
-// Tiles 0 .. ntri-1 are the M tiles (P <= R) in row order, then the Psi tiles.
-__global__ __launch_bounds__(256) void jacobi_apply32_kernel(int Dp, int round,
+__device__ __forceinline__ void mm32_to_lds(const d4 acc[2][2], double (*X)[JSB + 1]) {
+  const int lane = threadIdx.x & 63, lm = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) X[ti * 16 + lm][tj * 16 + lk + 4 * r] = acc[ti][tj][r];
+}
+
+// This lane's operand fragments of a stored rotation (all JSB/4 k-steps, both
+// 16-column halves), loaded together so their latencies overlap.
+__device__ __forceinline__ void load_vfrag(const double* __restrict__ V, double f[JSB / 4][2]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int kq = 0; kq < JSB / 4; ++kq)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) f[kq][t] = V[vfrag_index<JSB>(t, kq, lane)];
+}
+
+// A 32 x 32 tile (rows from rowcol, columns from colcol) into registers:
+// element e = lane + 64 i, x = e % 32, y = e / 32.
+template <class FR, class FC>
+__device__ __forceinline__ void load_tile32(const double* __restrict__ A, long lda, FR rowidx,
+                                            FC colidx, double v[JSB * JSB / 64]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < JSB * JSB / 64; ++i) {
+    const int e = lane + 64 * i, x = e % JSB, y = e / JSB;
+    v[i] = A[rowidx(x) + (long)colidx(y) * lda];
+  }
+}
+
+__device__ __forceinline__ void tile32_to_lds(const double v[JSB * JSB / 64], double (*X)[JSB + 1]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < JSB * JSB / 64; ++i) {
+    const int e = lane + 64 * i;
+    X[e % JSB][e / JSB] = v[i];
+  }
+}
+
+// M tiles of a round (one wave per 32 x 32 tile (P, R), P <= R, in row order,
+// four per workgroup): M_out[P,R] = V_P' M_in[P,R] V_R, stored with its mirror
+// M_out[R,P] = M_out[P,R]' (M stays exactly symmetric; diagonal tiles are
+// symmetrised).  Every global load of a wave (its tile and both rotations in
+// their stored MFMA order) is issued before the first is used; each wave
+// stages its tile in its own LDS region and needs no barrier (a wave's LDS
+// operations complete in order).
+__global__ __launch_bounds__(256) void jacobi_apply_m_kernel(int Dp, int round,
                                                              const double* __restrict__ Min,
                                                              double* __restrict__ Mout,
-                                                             double* __restrict__ Psi,
                                                              const double* __restrict__ Vbuf,
                                                              const double* __restrict__ ctrl) {
-  constexpr int SB = 32, HB = 16;
   if (ctrl[1] != 0.0) return;
-  __shared__ double Xs[4][SB][SB + 1];
-  const int nb = Dp / HB, ns = nb / 2, ntri = ns * (ns + 1) / 2;
-  const int ntiles = ntri + (Dp / SB) * ns;
-  const int lane = threadIdx.x & 63;
+  __shared__ double Xs[4][JSB][JSB + 1];
+  const int nb = Dp / JHB, ns = nb / 2, ntri = ns * (ns + 1) / 2;
+  const int lane = threadIdx.x & 63, lm = lane & 15, lk = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int tile = blockIdx.x * 4 + wave;
-  if (tile >= ntiles) return;
-  double(*X)[SB + 1] = Xs[wave];
-  const int lm = lane & 15, lk = lane >> 4;
+  if (tile >= ntri) return;
+  double(*X)[JSB + 1] = Xs[wave];
+  int P = 0, rowlen = ns;
+  while (tile >= rowlen) { tile -= rowlen; ++P; --rowlen; }
+  const int R = P + tile;
+  const SlotCols<JHB> cp = slot_cols<JHB>(round, P, nb), cr = slot_cols<JHB>(round, R, nb);
+  double tv[JSB * JSB / 64], vp[JSB / 4][2], vr[JSB / 4][2];
+  load_tile32(Min, Dp, [&](int x) { return cp.col(x); }, [&](int y) { return cr.col(y); }, tv);
+  load_vfrag(Vbuf + (long)P * JSB * JSB, vp);
+  load_vfrag(Vbuf + (long)R * JSB * JSB, vr);
+  __builtin_amdgcn_sched_barrier(0);   // keep every load issued before the first use
+  tile32_to_lds(tv, X);
   d4 acc[2][2];
-  auto zero = [&] {
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
-  };
-  auto to_lds = [&] {
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) X[ti * 16 + lm][tj * 16 + lk + 4 * r] = acc[ti][tj][r];
-  };
-  if (tile < ntri) {
-    int P = 0, rowlen = ns;
-    while (tile >= rowlen) { tile -= rowlen; ++P; --rowlen; }
-    const int R = P + tile;
-    const SlotCols<HB> cp = slot_cols<HB>(round, P, nb), cr = slot_cols<HB>(round, R, nb);
-    for (int e = lane; e < SB * SB; e += 64) {
-      const int x = e % SB, y = e / SB;
-      X[x][y] = Min[cp.col(x) + (long)cr.col(y) * Dp];
-    }
-    const double* VP = Vbuf + (long)P * SB * SB;
-    const double* VR = Vbuf + (long)R * SB * SB;
-    // Y = VP' X
-    zero();
-#pragma unroll
-    for (int kq = 0; kq < SB / 4; ++kq) {
-      const int k = 4 * kq + lk;
-      double av[2], bv[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        av[t] = VP[vfrag_index<SB>(t, kq, lane)];
-        bv[t] = X[k][t * 16 + lm];
-      }
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
-          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
-    }
-    to_lds();
-    // Z = Y VR
-    zero();
-#pragma unroll
-    for (int kq = 0; kq < SB / 4; ++kq) {
-      const int k = 4 * kq + lk;
-      double av[2], bv[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        av[t] = X[t * 16 + lm][k];
-        bv[t] = VR[vfrag_index<SB>(t, kq, lane)];
-      }
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
-          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
-    }
-    to_lds();
-    if (P == R) {
-      for (int e = lane; e < SB * SB; e += 64) {
-        const int x = e % SB, y = e / SB;
-        Mout[cp.col(x) + (long)cp.col(y) * Dp] = 0.5 * (X[x][y] + X[y][x]);
-      }
-    } else {
-      for (int e = lane; e < SB * SB; e += 64) {
-        const int x = e % SB, y = e / SB;
-        Mout[cp.col(x) + (long)cr.col(y) * Dp] = X[x][y];
-        Mout[cr.col(x) + (long)cp.col(y) * Dp] = X[y][x];
-      }
+  // Y = VP' X:  A(m, k) = VP(k, m)
+  mm32_wave([&](int t, int kq) { return vp[kq][t]; },
+            [&](int kq, int t) { return X[4 * kq + lk][16 * t + lm]; }, acc);
+  mm32_to_lds(acc, X);
+  // Z = Y VR
+  mm32_wave([&](int t, int kq) { return X[16 * t + lm][4 * kq + lk]; },
+            [&](int kq, int t) { return vr[kq][t]; }, acc);
+  mm32_to_lds(acc, X);
+  if (P == R) {
+#pragma unroll 4
+    for (int e = lane; e < JSB * JSB; e += 64) {
+      const int x = e % JSB, y = e / JSB;
+      Mout[cp.col(x) + (long)cp.col(y) * Dp] = 0.5 * (X[x][y] + X[y][x]);
     }
   } else {
-    const int k = tile - ntri;
-    const int P = k % ns, rt = k / ns;
-    const int row0 = rt * SB;
-    const SlotCols<HB> cp = slot_cols<HB>(round, P, nb);
-    for (int e = lane; e < SB * SB; e += 64) {
-      const int x = e % SB, y = e / SB;
-      X[x][y] = Psi[(row0 + x) + (long)cp.col(y) * Dp];
-    }
-    const double* VP = Vbuf + (long)P * SB * SB;
-    zero();
-#pragma unroll
-    for (int kq = 0; kq < SB / 4; ++kq) {
-      const int kk = 4 * kq + lk;
-      double av[2], bv[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        av[t] = X[t * 16 + lm][kk];
-        bv[t] = VP[vfrag_index<SB>(t, kq, lane)];
-      }
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
-          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
-    }
-    to_lds();
-    for (int e = lane; e < SB * SB; e += 64) {
-      const int x = e % SB, y = e / SB;
-      Psi[(row0 + x) + (long)cp.col(y) * Dp] = X[x][y];
+#pragma unroll 4
+    for (int e = lane; e < JSB * JSB; e += 64) {
+      const int x = e % JSB, y = e / JSB;
+      Mout[cp.col(x) + (long)cr.col(y) * Dp] = X[x][y];
+      Mout[cr.col(x) + (long)cp.col(y) * Dp] = X[y][x];
     }
   }
+}
+
+// Psi tile k of a round (one wave): rows 32 (k / ns) .., columns of slot
+// k mod ns:  Psi[:, P] <- Psi[:, P] V_P.
+__device__ __forceinline__ void jacobi_psi_tile(int Dp, int round, int k, double* __restrict__ Psi,
+                                                const double* __restrict__ Vbuf,
+                                                double (*X)[JSB + 1]) {
+  const int nb = Dp / JHB, ns = nb / 2;
+  const int lane = threadIdx.x & 63, lm = lane & 15, lk = lane >> 4;
+  const int P = k % ns, row0 = (k / ns) * JSB;
+  const SlotCols<JHB> cp = slot_cols<JHB>(round, P, nb);
+  double tv[JSB * JSB / 64], vp[JSB / 4][2];
+  load_tile32(Psi, Dp, [&](int x) { return row0 + x; }, [&](int y) { return cp.col(y); }, tv);
+  load_vfrag(Vbuf + (long)P * JSB * JSB, vp);
+  __builtin_amdgcn_sched_barrier(0);   // keep every load issued before the first use
+  tile32_to_lds(tv, X);
+  d4 acc[2][2];
+  mm32_wave([&](int t, int kq) { return X[16 * t + lm][4 * kq + lk]; },
+            [&](int kq, int t) { return vp[kq][t]; }, acc);
+  mm32_to_lds(acc, X);
+#pragma unroll 4
+  for (int e = lane; e < JSB * JSB; e += 64) {
+    const int x = e % JSB, y = e / JSB;
+    Psi[(row0 + x) + (long)cp.col(y) * Dp] = X[x][y];
+  }
+}
+
+// One launch per round: workgroups [0, nsolve) solve the subproblems of
+// round solve_round (writing Vsolve); the rest update Psi with the rotations
+// of the previous round (Vpsi), four 32 x 32 tiles per workgroup.  The Psi
+// update does not feed the next solve, so it runs beside it on the CUs the
+// few solve workgroups leave idle.
+__global__ __launch_bounds__(256) void jacobi_round_kernel(int Dp, int solve_round, int nsolve,
+                                                           const double* __restrict__ M,
+                                                           double* __restrict__ Vsolve,
+                                                           const double* __restrict__ ctrl,
+                                                           int max_inner, int psi_round, int npsi,
+                                                           double* __restrict__ Psi,
+                                                           const double* __restrict__ Vpsi) {
+  if ((int)blockIdx.x < nsolve) {
+    // ctrl[1]: converged flag (uniform over the workgroup)
+    if (ctrl[1] != 0.0) return;
+    jacobi_solve_block<JSB>(Dp, solve_round, blockIdx.x, M, Vsolve, max_inner);
+    return;
+  }
+  __shared__ double Xs[4][JSB][JSB + 1];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int k = ((int)blockIdx.x - nsolve) * 4 + wave;
+  if (k >= npsi) return;
+  jacobi_psi_tile(Dp, psi_round, k, Psi, Vpsi, Xs[wave]);
 }
 
 // Per OFF_COLS-column chunk: off-diagonal squares, all squares, and the largest
@@ -723,17 +627,11 @@ __global__ void pad_identity_kernel(int D, int Dp, const double* __restrict__ Q,
 // padded to a multiple of 64 (whole 64 x 64 tiles for every kernel)
 int eig_padded_dim(int D) { return ((D + 63) / 64) * 64; }
 
-// Subproblem size of the block Jacobi: 32 x 32 (blocks of 16 columns) or 64 x 64.
-#ifndef RM_JACOBI_SB
-#define RM_JACOBI_SB 32
-#endif
-constexpr int JSB = RM_JACOBI_SB, JHB = JSB / 2;
-static_assert(JSB == 32 || JSB == 64, "subproblem size must be 32 or 64");
-
 void eig_workspace_sizes(int D, long* doubles) {
   const int Dp = eig_padded_dim(D);
   const int nb = Dp / JHB;
-  *doubles = 3L * Dp * Dp + (long)(nb / 2) * JSB * JSB + 3L * (Dp / OFF_COLS + 1) + 8;
+  // M, M2, Psi; two rotation sets (double-buffered); convergence partials; ctrl
+  *doubles = 3L * Dp * Dp + 2L * (nb / 2) * JSB * JSB + 3L * (Dp / OFF_COLS + 1) + 8;
 }
 
 void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, int* sweeps_out,
@@ -761,33 +659,36 @@ void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, i
       throw Error(RMHMC_E_NONFINITE, "softabs_eig: non-finite entries in the matrix");
     if (w.ctrl_host[1] != 0.0) { conv = true; break; }
     if (sw >= max_sweeps) break;
+    // round r: solve (V[r & 1]), M tiles, then Psi tiles fused into the
+    // launch that solves round r + 1
+    const long ntri = (long)ns * (ns + 1) / 2;
+    const int npsi = (Dp / JSB) * ns;
+    double* Vb[2] = {w.V, w.V + (long)ns * JSB * JSB};
+    const double solve_flops = (double)ns * (JSB - 1) * (JHB * JHB * 24.0 + JSB * JHB * 6.0);
+    const double sb3 = (double)JSB * JSB * JSB;
+    int slot = timing_begin(TK_JACOBI_SOLVE, st);
+    hipLaunchKernelGGL(jacobi_round_kernel, dim3(ns), dim3(256), 0, st, Dp, 0, ns,
+                       (const double*)Min, Vb[0], (const double*)w.ctrl, max_inner, 0, 0, w.Psi,
+                       (const double*)Vb[1]);
+    RM_CHECK_LAUNCH();
+    timing_end(slot, st, solve_flops, 2.0 * ns * JSB * JSB * sizeof(double));
     for (int r = 0; r < nb - 1; ++r) {
-      int slot = timing_begin(TK_JACOBI_SOLVE, st);
-      hipLaunchKernelGGL(jacobi_solve_kernel<JSB>, dim3(ns), dim3(256), 0, st, Dp, r,
-                         (const double*)Min, w.V, (const double*)w.ctrl, max_inner);
-      RM_CHECK_LAUNCH();
-      // one inner sweep of an SB x SB subproblem: SB-1 rounds x ((SB/2)^2 2x2
-      // blocks x 24 flops + SB^2/2 V row pairs x 6 flops); bytes: subproblems
-      // in, rotations out
-      timing_end(slot, st,
-                 (double)ns * (JSB - 1) * (JHB * JHB * 24.0 + JSB * JHB * 6.0),
-                 2.0 * ns * JSB * JSB * sizeof(double));
       slot = timing_begin(TK_JACOBI_APPLY, st);
-      const long ntri = (long)ns * (ns + 1) / 2, npsi = (long)(Dp / JSB) * ns;
-      if (JSB == 64) {
-        hipLaunchKernelGGL(jacobi_apply64_kernel, dim3(ntri + npsi), dim3(256), 0, st, Dp, r,
-                           (const double*)Min, Mout, w.Psi, (const double*)w.V,
-                           (const double*)w.ctrl);
-      } else {
-        hipLaunchKernelGGL(jacobi_apply32_kernel, dim3(cdiv(ntri + npsi, 4)), dim3(256), 0, st, Dp,
-                           r, (const double*)Min, Mout, w.Psi, (const double*)w.V,
-                           (const double*)w.ctrl);
-      }
+      hipLaunchKernelGGL(jacobi_apply_m_kernel, dim3(cdiv(ntri, 4)), dim3(256), 0, st, Dp, r,
+                         (const double*)Min, Mout, (const double*)Vb[r & 1],
+                         (const double*)w.ctrl);
       RM_CHECK_LAUNCH();
-      const double sb3 = (double)JSB * JSB * JSB;
-      timing_end(slot, st, 4.0 * sb3 * ntri + 2.0 * sb3 * npsi,
-                 4.0 * (double)Dp * Dp * sizeof(double));
+      timing_end(slot, st, 4.0 * sb3 * ntri, 3.0 * (double)Dp * Dp * sizeof(double));
       std::swap(Min, Mout);
+      const bool more = r + 1 < nb - 1;
+      slot = timing_begin(TK_JACOBI_SOLVE, st);
+      hipLaunchKernelGGL(jacobi_round_kernel, dim3((more ? ns : 0) + cdiv(npsi, 4)), dim3(256), 0,
+                         st, Dp, r + 1, more ? ns : 0, (const double*)Min, Vb[(r + 1) & 1],
+                         (const double*)w.ctrl, max_inner, r, npsi, w.Psi,
+                         (const double*)Vb[r & 1]);
+      RM_CHECK_LAUNCH();
+      timing_end(slot, st, (more ? solve_flops : 0.0) + 2.0 * sb3 * npsi,
+                 2.0 * (double)Dp * Dp * sizeof(double));
     }
     ++sw;
     hipLaunchKernelGGL(offnorm_kernel, dim3(nparts), dim3(256), 0, st, Dp, (const double*)Min, w.part);

@@ -762,7 +762,7 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   m.eig.M = pl.alloc<double>(Dp * Dp);
   m.eig.M2 = pl.alloc<double>(Dp * Dp);
   m.eig.Psi = pl.alloc<double>(Dp * Dp);
-  m.eig.V = pl.alloc<double>((Dp / 64) * 64 * 64);
+  m.eig.V = pl.alloc<double>(eig_rotation_doubles(Dp));
   m.eig.part = pl.alloc<double>(3 * (Dp / 8 + 1));
   m.eig.ctrl = pl.alloc<double>(8);
   m.eig.ctrl_host = pl.alloc_host<double>(4);
@@ -1209,7 +1209,7 @@ rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, do
       c.w.M = c.pool->alloc<double>((long)Dp * Dp);
       c.w.M2 = c.pool->alloc<double>((long)Dp * Dp);
       c.w.Psi = c.pool->alloc<double>((long)Dp * Dp);
-      c.w.V = c.pool->alloc<double>((long)(Dp / 64) * 64 * 64);
+      c.w.V = c.pool->alloc<double>(eig_rotation_doubles(Dp));
       c.w.part = c.pool->alloc<double>(3 * (Dp / 8 + 1));
       c.w.ctrl = c.pool->alloc<double>(8);
       c.w.ctrl_host = c.pool->alloc_host<double>(4);
