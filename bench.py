@@ -22,9 +22,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"f64_tflops": 78.6, "f32_tflops": 157.3, "hbm_gbs": 8000.0}
-# FP64 MFMA GEMMs carry the bulk of the algorithmic flops of a leapfrog at
-# this size (A_l = K^-1 K_l, B_l = A_l K^-1, Y_lm = A_l A_m, Psi products)
-DOMINANT = "gemm_f64"
+# The dominant kernel by time is the Jacobi round kernel (subproblem solves of
+# round r+1 beside the Psi update of round r).  Its algorithmic intensity,
+# about 4.5 flop/byte, is below the FP64 ridge point of 78.6 TFLOP/s over
+# 8 TB/s (~10 flop/byte), so its roofline is HBM.  The FP64 MFMA GEMMs, which
+# carry most of the flops, are reported beside it.
+DOMINANT = "jacobi_solve"
+DOMINANT_KERNEL = "jacobi_round_kernel<1>"   # warm-started (one inner sweep)
+GEMM = "gemm_f64"
+TRAFFIC_FILE = "profiles/jacobi_round_kernel_dynamic_propensity_mkl_d1038_traffic.json"
+TRAFFIC_SOURCES = ("paper_2511_06407_amd/csrc/eig.hip",)
 
 
 def parse():
@@ -40,6 +47,14 @@ def parse():
     ap.add_argument("--ess-moves", type=int, default=0,
                     help="also run a chain of this many moves and report ESS/s")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--traj", type=int, default=5,
+                    help="leapfrogs per trajectory: the state restarts from q0 with the same "
+                         "momentum draw every TRAJ steps, outside the timed region (longer "
+                         "trajectories without Metropolis-Hastings drift out of the stable "
+                         "region of this posterior)")
+    ap.add_argument("--calib-copy-mb", type=float, default=0.0,
+                    help="run one device-to-device copy of this many MB before the timed "
+                         "steps (a kernel of known traffic for scaling PMC byte counters)")
     ap.add_argument("--mode", choices=["leapfrog", "tempered", "serve"], default="leapfrog",
                     help="leapfrog: one chain at D=1038 (default); tempered: 64 power-posterior "
                          "chains of uneven D on the worker pool; serve: Poisson request stream")
@@ -99,7 +114,7 @@ def file_hash(*paths):
 def traffic_from_profile(kernel_src_hash):
     """HBM bytes per launch of the dominant kernel from the committed PMC
     summary, only if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "gemm_f64_propensity_mkl_d1038_traffic.json")
+    path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -162,42 +177,92 @@ def main():
     dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")  # noqa
     z, u = wl.chain_randoms(spec.D, max(args.ess_moves, 1) + 1, seed=args.seed)
     q0 = np.zeros(spec.D)
-    S = rmhmc.State(model, dev(q0), dev(np.zeros(spec.D)), cfg.alpha)
-    S.draw_momentum(dev(z[0]))
+    q0_dev, p0_dev, z0_dev = dev(q0), dev(np.zeros(spec.D)), dev(z[0])
+
+    def fresh_state():
+        st = rmhmc.State(model, q0_dev, p0_dev, cfg.alpha)
+        st.draw_momentum(z0_dev)
+        return st
+
     log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)  # noqa: E731
+    S = fresh_state()
     log(f"state ready D={spec.D}")
     for k in range(args.warmup):
         S.step(cfg.eps, cfg.n_fixed_point)
         torch.cuda.synchronize()
         log(f"warmup step {k} done")
+    S.close()
 
-    if not args.no_timing:
-        rmhmc.timing_enable((DOMINANT,))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        S.step(cfg.eps, cfg.n_fixed_point)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    log(f"timed {args.steps} steps in {t1 - t0:.3f} s")
-    st_stats = S.stats()
-    elapsed = t1 - t0
+    def timed_steps(n):
+        """n leapfrogs in trajectories of at most args.traj steps; returns the
+        seconds spent in the steps and the summed eigensolver counters."""
+        total, done, eig_calls, sweeps = 0.0, 0, 0, 0
+        while done < n:
+            st = fresh_state()
+            base = st.stats()
+            b = min(args.traj, n - done)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            for _ in range(b):
+                st.step(cfg.eps, cfg.n_fixed_point)
+            torch.cuda.synchronize()
+            total += time.perf_counter() - ta
+            done += b
+            s1 = st.stats()
+            eig_calls += s1.eig_calls - base.eig_calls
+            sweeps += s1.sweeps - base.sweeps
+            st.close()
+        return total, eig_calls, sweeps
+
+    if args.calib_copy_mb > 0:
+        n = int(args.calib_copy_mb * 1e6 / 8)
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {8 * n} bytes done")
+        del a, b
+    elapsed, eig_calls, sweeps = timed_steps(args.steps)
+    log(f"timed {args.steps} steps in {elapsed:.3f} s")
     value = args.steps / elapsed
 
     roofline = None
+    roofline_gemm = None
     if not args.no_timing:
+        # per-kernel HIP events on the launch stream, over the same number of
+        # further steps (kept out of the timed region above)
+        # one trajectory, its state created before the events are switched on
+        n_inst = min(args.steps, args.traj)
+        st = fresh_state()
+        torch.cuda.synchronize()
+        rmhmc.timing_enable((DOMINANT, GEMM))
+        ta = time.perf_counter()
+        for _ in range(n_inst):
+            st.step(cfg.eps, cfg.n_fixed_point)
+        torch.cuda.synchronize()
+        elapsed_inst = time.perf_counter() - ta
+        st.close()
+        log(f"instrumented {n_inst} steps in {elapsed_inst:.3f} s")
         n, ms, flops, byts = rmhmc.timing_read(DOMINANT)
+        gn, gms, gflops, _ = rmhmc.timing_read(GEMM)
         rmhmc.timing_enable(())
         if n > 0 and ms > 0:
-            achieved = flops / (ms * 1e-3) / 1e12
-            src_hash = file_hash("paper_2511_06407_amd/csrc/gemm.hip")
-            roofline = {"bound": "mfma", "kernel": "gemm_kernel<double> (v_mfma_f64_16x16x4f64)",
-                        "achieved": round(achieved, 3), "peak": PEAK["f64_tflops"],
-                        "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64_tflops"], 4),
-                        "traffic": traffic_from_profile(src_hash),
+            achieved = byts / (ms * 1e-3) / 1e9
+            roofline = {"bound": "hbm", "kernel": DOMINANT_KERNEL,
+                        "achieved": round(achieved, 1), "peak": PEAK["hbm_gbs"],
+                        "unit": "GB/s", "frac": round(achieved / PEAK["hbm_gbs"], 4),
+                        "traffic": traffic_from_profile(file_hash(*TRAFFIC_SOURCES)),
                         "launches": n, "avg_launch_us": round(ms * 1e3 / n, 2),
+                        "algorithmic_bytes_per_launch": byts / n,
                         "algorithmic_flops_per_launch": flops / n,
-                        "kernel_time_share": round(ms * 1e-3 / elapsed, 3)}
+                        "kernel_time_share": round(ms * 1e-3 / elapsed_inst, 3)}
+        if gn > 0 and gms > 0:
+            ga = gflops / (gms * 1e-3) / 1e12
+            roofline_gemm = {"bound": "mfma", "kernel": "gemm_kernel<double> (v_mfma_f64_16x16x4f64)",
+                             "achieved": round(ga, 3), "peak": PEAK["f64_tflops"], "unit": "TFLOP/s",
+                             "frac": round(ga / PEAK["f64_tflops"], 4), "launches": gn,
+                             "avg_launch_us": round(gms * 1e3 / gn, 2),
+                             "kernel_time_share": round(gms * 1e-3 / elapsed_inst, 3)}
 
     ess_block = None
     if args.ess_moves > 0:
@@ -227,10 +292,11 @@ def main():
            "config": {"workload": args.workload, "D": spec.D, "N": spec.N, "P": spec.P,
                       "eps": cfg.eps, "n_fixed_point": cfg.n_fixed_point, "alpha": cfg.alpha,
                       "precision": args.precision, "parallelism": "single GPU"},
-           "roofline": roofline}
-    out["eig"] = {"eig_calls": st_stats.eig_calls, "sweeps": st_stats.sweeps,
-                  "sweeps_per_eig": st_stats.sweeps / max(st_stats.eig_calls, 1),
-                  "note": "counted since state creation (static first solve included)"}
+           "roofline": roofline, "roofline_gemm_f64": roofline_gemm}
+    out["eig"] = {"eig_calls": eig_calls, "sweeps": sweeps,
+                  "sweeps_per_eig": sweeps / max(eig_calls, 1),
+                  "note": "warm-started solves in the timed steps"}
+    out["config"]["trajectory_leapfrogs"] = args.traj
     if ess_block is not None:
         out["ess"] = ess_block
     if not args.no_cpu_baseline:

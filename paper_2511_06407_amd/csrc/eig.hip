@@ -368,17 +368,20 @@ __device__ __forceinline__ void jacobi_psi_tile(int Dp, int round, int k, double
 // of the previous round (Vpsi), four 32 x 32 tiles per workgroup.  The Psi
 // update does not feed the next solve, so it runs beside it on the CUs the
 // few solve workgroups leave idle.
+// MAX_INNER (inner sweeps per subproblem) is a template parameter, so warm
+// starts (1) and static solves (JACOBI_INNER_STATIC) are separate kernels.
+template <int MAX_INNER>
 __global__ __launch_bounds__(256) void jacobi_round_kernel(int Dp, int solve_round, int nsolve,
                                                            const double* __restrict__ M,
                                                            double* __restrict__ Vsolve,
                                                            const double* __restrict__ ctrl,
-                                                           int max_inner, int psi_round, int npsi,
+                                                           int psi_round, int npsi,
                                                            double* __restrict__ Psi,
                                                            const double* __restrict__ Vpsi) {
   if ((int)blockIdx.x < nsolve) {
     // ctrl[1]: converged flag (uniform over the workgroup)
     if (ctrl[1] != 0.0) return;
-    jacobi_solve_block<JSB>(Dp, solve_round, blockIdx.x, M, Vsolve, max_inner);
+    jacobi_solve_block<JSB>(Dp, solve_round, blockIdx.x, M, Vsolve, MAX_INNER);
     return;
   }
   __shared__ double Xs[4][JSB][JSB + 1];
@@ -666,29 +669,38 @@ void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, i
     double* Vb[2] = {w.V, w.V + (long)ns * JSB * JSB};
     const double solve_flops = (double)ns * (JSB - 1) * (JHB * JHB * 24.0 + JSB * JHB * 6.0);
     const double sb3 = (double)JSB * JSB * JSB;
+    RM_REQUIRE(max_inner == JACOBI_INNER_DYNAMIC || max_inner == JACOBI_INNER_STATIC,
+               "softabs_eig: unsupported number of inner sweeps");
+    auto round_kernel = max_inner == JACOBI_INNER_DYNAMIC
+                            ? jacobi_round_kernel<JACOBI_INNER_DYNAMIC>
+                            : jacobi_round_kernel<JACOBI_INNER_STATIC>;
     int slot = timing_begin(TK_JACOBI_SOLVE, st);
-    hipLaunchKernelGGL(jacobi_round_kernel, dim3(ns), dim3(256), 0, st, Dp, 0, ns,
-                       (const double*)Min, Vb[0], (const double*)w.ctrl, max_inner, 0, 0, w.Psi,
-                       (const double*)Vb[1]);
+    hipLaunchKernelGGL(round_kernel, dim3(ns), dim3(256), 0, st, Dp, 0, ns, (const double*)Min,
+                       Vb[0], (const double*)w.ctrl, 0, 0, w.Psi, (const double*)Vb[1]);
     RM_CHECK_LAUNCH();
-    timing_end(slot, st, solve_flops, 2.0 * ns * JSB * JSB * sizeof(double));
+    // algorithmic bytes: subproblems read, rotations written
+    const double vset = (double)ns * JSB * JSB * sizeof(double);
+    timing_end(slot, st, solve_flops, 2.0 * vset);
     for (int r = 0; r < nb - 1; ++r) {
       slot = timing_begin(TK_JACOBI_APPLY, st);
       hipLaunchKernelGGL(jacobi_apply_m_kernel, dim3(cdiv(ntri, 4)), dim3(256), 0, st, Dp, r,
                          (const double*)Min, Mout, (const double*)Vb[r & 1],
                          (const double*)w.ctrl);
       RM_CHECK_LAUNCH();
-      timing_end(slot, st, 4.0 * sb3 * ntri, 3.0 * (double)Dp * Dp * sizeof(double));
+      // upper tiles read, all of M written, rotations read once
+      timing_end(slot, st, 4.0 * sb3 * ntri,
+                 ((double)ntri * JSB * JSB + (double)Dp * Dp) * sizeof(double) + vset);
       std::swap(Min, Mout);
       const bool more = r + 1 < nb - 1;
       slot = timing_begin(TK_JACOBI_SOLVE, st);
-      hipLaunchKernelGGL(jacobi_round_kernel, dim3((more ? ns : 0) + cdiv(npsi, 4)), dim3(256), 0,
-                         st, Dp, r + 1, more ? ns : 0, (const double*)Min, Vb[(r + 1) & 1],
-                         (const double*)w.ctrl, max_inner, r, npsi, w.Psi,
-                         (const double*)Vb[r & 1]);
+      hipLaunchKernelGGL(round_kernel, dim3((more ? ns : 0) + cdiv(npsi, 4)), dim3(256), 0, st,
+                         Dp, r + 1, more ? ns : 0, (const double*)Min, Vb[(r + 1) & 1],
+                         (const double*)w.ctrl, r, npsi, w.Psi, (const double*)Vb[r & 1]);
       RM_CHECK_LAUNCH();
+      // Psi read and written once, the previous rotations read once, and
+      // (solve part) subproblems read and rotations written
       timing_end(slot, st, (more ? solve_flops : 0.0) + 2.0 * sb3 * npsi,
-                 2.0 * (double)Dp * Dp * sizeof(double));
+                 2.0 * (double)Dp * Dp * sizeof(double) + vset + (more ? 2.0 * vset : 0.0));
     }
     ++sw;
     hipLaunchKernelGGL(offnorm_kernel, dim3(nparts), dim3(256), 0, st, Dp, (const double*)Min, w.part);
