@@ -22,9 +22,23 @@
 namespace rmhmc {
 namespace {
 
+constexpr int JSB = 32, JHB = 16;   // subproblem size of the block Jacobi and its block width
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ int rr_player(int r, int k, int n) {
   // round r of a round-robin over n players: player at seat k (seat 0 fixed)
   return k == 0 ? 0 : 1 + ((k - 1 + r) % (n - 1));
+}
+
+// Hand LDS data between lanes of one wave: every LDS access of this wave
+// before the call is ordered before every access after it.  The hardware
+// runs a wave's LDS instructions in order, but without this the compiler may
+// move an access past another one it can prove is to a different address
+// for the same lane, which breaks data exchange between lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // rr_player over the SB local indices of a subproblem, branch-free:
@@ -56,6 +70,109 @@ __device__ __forceinline__ int vfrag_index(int cb, int kq, int lane) {
   return cb * 16 * SB + kq * 64 + lane;
 }
 
+// Round-r position of block X: its slot and its half (0: first 16 columns).
+__device__ __forceinline__ void rr_locate(int X, int r, int nb, int& slot, int& half) {
+  const int m = nb - 1;
+  const int k = X == 0 ? 0 : 1 + (((X - 1 - r) % m) + m) % m;   // seat of X
+  if (k < nb / 2) { slot = k; half = 0; } else { slot = nb - 1 - k; half = 1; }
+}
+
+// The subproblem of `slot` in round `round` >= 1 assembled from the previous
+// round's matrix Mprev and rotations Vprev, without waiting for the full M
+// update: with its blocks I', J' at (slot A, half hA) and (B, hB) of the
+// previous round and V~_X = V_X[:, 16 h_X ..] (32 x 16),
+//   S = [V~_A' Mprev[A,A] V~_A, V~_A' Mprev[A,B] V~_B; (.)', V~_B' Mprev[B,B] V~_B].
+// Waves 0..2 form the three distinct 16 x 16 blocks on the matrix cores
+// (T = Mprev tile x V~_Y, then V~_X' T).  The tiles are staged in T0..T2
+// (scratch of the caller) and S is written to Sout with the diagonal blocks
+// symmetrised.  All threads of the workgroup call this.
+__device__ __forceinline__ void jacobi_compose_subproblem(
+    int Dp, int round, int slot, const double* __restrict__ Mprev,
+    const double* __restrict__ Vprev, double (*T0)[JSB + 1], double (*T1)[JSB + 1],
+    double (*T2)[JSB + 1], double (*Tw)[JSB][17], double (*Sout)[JSB + 1]) {
+  const int nb = Dp / JHB;
+  const int tid = threadIdx.x, lane = tid & 63, lm = lane & 15, lk = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int Ip = rr_player(round, slot, nb), Jp = rr_player(round, nb - 1 - slot, nb);
+  int sA, hA, sB, hB;
+  rr_locate(Ip, round - 1, nb, sA, hA);
+  rr_locate(Jp, round - 1, nb, sB, hB);
+  const SlotCols<JHB> ca = slot_cols<JHB>(round - 1, sA, nb), cb = slot_cols<JHB>(round - 1, sB, nb);
+  // the three tiles Mprev[A,A], Mprev[A,B], Mprev[B,B]: 12 loads per thread, issued together
+  double ld[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    const int t = i / 4, e = tid + 256 * (i % 4), x = e % JSB, y = e / JSB;
+    const SlotCols<JHB>& cr = t == 2 ? cb : ca;
+    const SlotCols<JHB>& cc = t == 0 ? ca : cb;
+    ld[i] = Mprev[cr.col(x) + (long)cc.col(y) * Dp];
+  }
+  // this wave's rotation halves (w = 0: (A, A), 1: (A, B), 2: (B, B))
+  const int sX = w == 2 ? sB : sA, hX = w == 2 ? hB : hA;
+  const int sY = w == 0 ? sA : sB, hY = w == 0 ? hA : hB;
+  double fx[JSB / 4], fy[JSB / 4];
+  if (w < 3) {
+    const double* VX = Vprev + (long)sX * JSB * JSB + hX * (JSB / 4) * 64;
+    const double* VY = Vprev + (long)sY * JSB * JSB + hY * (JSB / 4) * 64;
+#pragma unroll
+    for (int kq = 0; kq < JSB / 4; ++kq) {
+      fx[kq] = VX[kq * 64 + lane];
+      fy[kq] = VY[kq * 64 + lane];
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);   // keep every load issued before the first use
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    const int t = i / 4, e = tid + 256 * (i % 4), x = e % JSB, y = e / JSB;
+    double(*T)[JSB + 1] = t == 0 ? T0 : (t == 1 ? T1 : T2);
+    T[x][y] = ld[i];
+  }
+  __syncthreads();
+  d4 s2 = d4{0, 0, 0, 0};
+  if (w < 3) {
+    double(*Mt)[JSB + 1] = w == 0 ? T0 : (w == 1 ? T1 : T2);
+    // T = Mt V~_Y (32 x 16): two row tiles
+    d4 t1[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
+#pragma unroll
+    for (int kq = 0; kq < JSB / 4; ++kq)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+        t1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(fy[kq], Mt[16 * t + lm][4 * kq + lk], t1[t], 0, 0, 0);
+    double(*Tt)[17] = Tw[w];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Tt[16 * t + lm][lk + 4 * r] = t1[t][r];
+    wave_lds_sync();   // T is read back by other lanes
+    // S_XY = V~_X' T (16 x 16); A(m, k) = V~_X(k, m) is this lane's fragment
+#pragma unroll
+    for (int kq = 0; kq < JSB / 4; ++kq)
+      s2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Tt[4 * kq + lk][lm], fx[kq], s2, 0, 0, 0);
+  }
+  __syncthreads();   // every wave is done with T0..T2
+  if (w < 3) {
+    // lane, register r hold S_XY(m = lm, n = lk + 4 r)
+    const int r0 = w == 2 ? JHB : 0, c0 = w == 0 ? 0 : JHB;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      Sout[r0 + lm][c0 + lk + 4 * r] = s2[r];
+      if (w == 1) Sout[c0 + lk + 4 * r][r0 + lm] = s2[r];
+    }
+  }
+  __syncthreads();
+  // symmetrise the two diagonal blocks
+  for (int e = tid; e < 2 * JHB * JHB; e += 256) {
+    const int b = e / (JHB * JHB), x = (e % (JHB * JHB)) % JHB, y = (e % (JHB * JHB)) / JHB;
+    if (x < y) {
+      const int o = b * JHB;
+      const double v = 0.5 * (Sout[o + x][o + y] + Sout[o + y][o + x]);
+      Sout[o + x][o + y] = v;
+      Sout[o + y][o + x] = v;
+    }
+  }
+  __syncthreads();
+}
+
 // One workgroup diagonalises the SB x SB subproblem of its slot with an inner
 // cyclic Jacobi (round-robin over SB indices, SB/2 disjoint rotations a round,
 // at most max_inner sweeps) and writes the accumulated rotation V.
@@ -63,43 +180,57 @@ __device__ __forceinline__ int vfrag_index(int cb, int kq, int lane) {
 // Every wave computes the round's SB/2 rotations itself (lane l holds pair
 // l mod SB/2; the computation is identical in every wave, so the decisions
 // taken from it are uniform over the workgroup) and publishes them to its own
-// LDS slot, which only that wave reads back (a wave's LDS operations complete
-// in order, so no barrier is needed).  S is double-buffered: a round reads one
+// LDS slot, which only that wave reads back (a wavefront-scope fence orders
+// the exchange; no workgroup barrier).  S is double-buffered: a round reads one
 // copy and writes the other, so one barrier per rotating round orders
 // everything.  Thread t updates the 2 x 2 blocks (u, v) = (t mod SB/2, ...)
 // of S, whose row pair u is the pair it computed itself, and SB/2 x SB / 256
 // (row, pair) entries of V.
-template <int SB>
+//
+// The subproblem is read from M directly when Vprev is null, else composed
+// from the previous round's M and rotations (see the round kernel).
 __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
                                                    const double* __restrict__ M,
+                                                   const double* __restrict__ Vprev,
                                                    double* __restrict__ Vbuf, int max_inner) {
+  constexpr int SB = JSB;
   constexpr int HB = SB / 2;                  // block width; also the number of pairs
   constexpr int NBLK = HB * HB / 256;         // S 2 x 2 blocks per thread
   constexpr int NVR = SB * HB / 256;          // V (row, pair) entries per thread
   static_assert(NBLK >= 1 && NVR >= 1, "subproblem too small for 256 threads");
   __shared__ double Sb[2][SB][SB + 1];
   __shared__ double V[SB][SB + 1];
-  __shared__ double2 cs[4][HB];   // per wave: (c, s) of the round's pairs
+  __shared__ double Tw[3][SB][17];  // per-wave intermediates of the composition
+  __shared__ double2 cs[4][HB];     // per wave: (c, s) of the round's pairs
   __shared__ double red[4];
   const int nb = Dp / HB;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const SlotCols<HB> sc = slot_cols<HB>(round, slot, nb);
   constexpr int NLD = SB * SB / 256;
-  double ld[NLD];
-#pragma unroll
-  for (int i = 0; i < NLD; ++i) {
-    const int e = tid + 256 * i, x = e % SB, y = e / SB;
-    ld[i] = M[sc.col(x) + (long)sc.col(y) * Dp];
-  }
   double ss = 0.0;
+  if (Vprev == nullptr) {
+    const SlotCols<HB> sc = slot_cols<HB>(round, slot, nb);
+    double ld[NLD];
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      const int e = tid + 256 * i, x = e % SB, y = e / SB;
+      ld[i] = M[sc.col(x) + (long)sc.col(y) * Dp];
+    }
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      const int e = tid + 256 * i, x = e % SB, y = e / SB;
+      Sb[0][x][y] = ld[i];
+    }
+  } else {
+    jacobi_compose_subproblem(Dp, round, slot, M, Vprev, Sb[0], Sb[1], V, Tw, Sb[0]);
+  }
 #pragma unroll
   for (int i = 0; i < NLD; ++i) {
     const int e = tid + 256 * i, x = e % SB, y = e / SB;
-    Sb[0][x][y] = ld[i];
+    const double v = Sb[0][x][y];
     V[x][y] = (x == y) ? 1.0 : 0.0;
-    ss += ld[i] * ld[i];
+    ss += v * v;
   }
   for (int o = 32; o > 0; o >>= 1) ss += __shfl_down(ss, o, 64);
   if (lane == 0) red[w] = ss;
@@ -140,6 +271,7 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
       // converge quadratically.
       significant = significant || (__ballot(fabs(t) > 1e-8) != 0);
       if (lane < HB) csw[u] = make_double2(c, sn);
+      wave_lds_sync();   // read back by other lanes of this wave
 
       // S' = J' S J by 2 x 2 blocks (u, v)
       double x[NBLK][4];
@@ -210,9 +342,7 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
   }
 }
 
-typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int JSB = 32, JHB = 16;   // subproblem size of the block Jacobi and its block width
 
 // C (32 x 32, one wave) = sum_k A(m, k) B(k, n) on v_mfma_f64_16x16x4f64:
 // 2 x 2 tiles, lane l, register r of tile (ti, tj) holding
@@ -283,26 +413,20 @@ __device__ __forceinline__ void tile32_to_lds(const double v[JSB * JSB / 64], do
   }
 }
 
-// M tiles of a round (one wave per 32 x 32 tile (P, R), P <= R, in row order,
-// four per workgroup): M_out[P,R] = V_P' M_in[P,R] V_R, stored with its mirror
+// M tile of a round (one wave per 32 x 32 tile (P, R), P <= R, tiles in row
+// order): M_out[P,R] = V_P' M_in[P,R] V_R, stored with its mirror
 // M_out[R,P] = M_out[P,R]' (M stays exactly symmetric; diagonal tiles are
-// symmetrised).  Every global load of a wave (its tile and both rotations in
-// their stored MFMA order) is issued before the first is used; each wave
-// stages its tile in its own LDS region and needs no barrier (a wave's LDS
-// operations complete in order).
-__global__ __launch_bounds__(256) void jacobi_apply_m_kernel(int Dp, int round,
-                                                             const double* __restrict__ Min,
-                                                             double* __restrict__ Mout,
-                                                             const double* __restrict__ Vbuf,
-                                                             const double* __restrict__ ctrl) {
-  if (ctrl[1] != 0.0) return;
-  __shared__ double Xs[4][JSB][JSB + 1];
-  const int nb = Dp / JHB, ns = nb / 2, ntri = ns * (ns + 1) / 2;
+// symmetrised).  Every global load of the wave (its tile and both rotations
+// in their stored MFMA order) is issued before the first is used; the wave
+// stages its tile in its own LDS region X, with wavefront-scope fences
+// between the lanes' writes and reads (no workgroup barrier).
+__device__ __forceinline__ void jacobi_m_tile(int Dp, int round, int tile,
+                                              const double* __restrict__ Min,
+                                              double* __restrict__ Mout,
+                                              const double* __restrict__ Vbuf,
+                                              double (*X)[JSB + 1]) {
+  const int nb = Dp / JHB, ns = nb / 2;
   const int lane = threadIdx.x & 63, lm = lane & 15, lk = lane >> 4;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  int tile = blockIdx.x * 4 + wave;
-  if (tile >= ntri) return;
-  double(*X)[JSB + 1] = Xs[wave];
   int P = 0, rowlen = ns;
   while (tile >= rowlen) { tile -= rowlen; ++P; --rowlen; }
   const int R = P + tile;
@@ -312,16 +436,23 @@ __global__ __launch_bounds__(256) void jacobi_apply_m_kernel(int Dp, int round,
   load_vfrag(Vbuf + (long)P * JSB * JSB, vp);
   load_vfrag(Vbuf + (long)R * JSB * JSB, vr);
   __builtin_amdgcn_sched_barrier(0);   // keep every load issued before the first use
+  // X is written and read by different lanes of this wave: order every
+  // hand-over (and every rewrite after reads) explicitly
   tile32_to_lds(tv, X);
+  wave_lds_sync();
   d4 acc[2][2];
   // Y = VP' X:  A(m, k) = VP(k, m)
   mm32_wave([&](int t, int kq) { return vp[kq][t]; },
             [&](int kq, int t) { return X[4 * kq + lk][16 * t + lm]; }, acc);
+  wave_lds_sync();
   mm32_to_lds(acc, X);
+  wave_lds_sync();
   // Z = Y VR
   mm32_wave([&](int t, int kq) { return X[16 * t + lm][4 * kq + lk]; },
             [&](int kq, int t) { return vr[kq][t]; }, acc);
+  wave_lds_sync();
   mm32_to_lds(acc, X);
+  wave_lds_sync();
   if (P == R) {
 #pragma unroll 4
     for (int e = lane; e < JSB * JSB; e += 64) {
@@ -352,10 +483,13 @@ __device__ __forceinline__ void jacobi_psi_tile(int Dp, int round, int k, double
   load_vfrag(Vbuf + (long)P * JSB * JSB, vp);
   __builtin_amdgcn_sched_barrier(0);   // keep every load issued before the first use
   tile32_to_lds(tv, X);
+  wave_lds_sync();
   d4 acc[2][2];
   mm32_wave([&](int t, int kq) { return X[16 * t + lm][4 * kq + lk]; },
             [&](int kq, int t) { return vp[kq][t]; }, acc);
+  wave_lds_sync();
   mm32_to_lds(acc, X);
+  wave_lds_sync();
 #pragma unroll 4
   for (int e = lane; e < JSB * JSB; e += 64) {
     const int x = e % JSB, y = e / JSB;
@@ -363,32 +497,45 @@ __device__ __forceinline__ void jacobi_psi_tile(int Dp, int round, int k, double
   }
 }
 
-// One launch per round: workgroups [0, nsolve) solve the subproblems of
-// round solve_round (writing Vsolve); the rest update Psi with the rotations
-// of the previous round (Vpsi), four 32 x 32 tiles per workgroup.  The Psi
-// update does not feed the next solve, so it runs beside it on the CUs the
-// few solve workgroups leave idle.
+// One launch per round r (apply_round = r >= 0):
+//   workgroups [0, nsolve)        solve the subproblems of round r + 1, each
+//                                 assembled from M_r (Min) and V_r (Vprev),
+//                                 writing V_{r+1} (Vnew);
+//   the next ceil(ntri / 4)       M_{r+1} = J_r' M_r J_r (Mout), one wave per tile;
+//   the rest                      Psi <- Psi J_r, one wave per 32 x 32 tile.
+// The three parts read M_r and V_r and write different buffers, so they run
+// side by side.  With apply_round < 0 the launch only solves round 0 from Min.
 // MAX_INNER (inner sweeps per subproblem) is a template parameter, so warm
 // starts (1) and static solves (JACOBI_INNER_STATIC) are separate kernels.
 template <int MAX_INNER>
-__global__ __launch_bounds__(256) void jacobi_round_kernel(int Dp, int solve_round, int nsolve,
-                                                           const double* __restrict__ M,
-                                                           double* __restrict__ Vsolve,
+__global__ __launch_bounds__(256) void jacobi_round_kernel(int Dp, int apply_round, int nsolve,
+                                                           const double* __restrict__ Min,
+                                                           double* __restrict__ Mout,
+                                                           const double* __restrict__ Vprev,
+                                                           double* __restrict__ Vnew,
                                                            const double* __restrict__ ctrl,
-                                                           int psi_round, int npsi,
-                                                           double* __restrict__ Psi,
-                                                           const double* __restrict__ Vpsi) {
-  if ((int)blockIdx.x < nsolve) {
+                                                           int ntri, int npsi,
+                                                           double* __restrict__ Psi) {
+  const int b = blockIdx.x;
+  if (b < nsolve) {
     // ctrl[1]: converged flag (uniform over the workgroup)
     if (ctrl[1] != 0.0) return;
-    jacobi_solve_block<JSB>(Dp, solve_round, blockIdx.x, M, Vsolve, MAX_INNER);
+    if (apply_round < 0)
+      jacobi_solve_block(Dp, 0, b, Min, nullptr, Vnew, MAX_INNER);
+    else
+      jacobi_solve_block(Dp, apply_round + 1, b, Min, Vprev, Vnew, MAX_INNER);
     return;
   }
   __shared__ double Xs[4][JSB][JSB + 1];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int k = ((int)blockIdx.x - nsolve) * 4 + wave;
-  if (k >= npsi) return;
-  jacobi_psi_tile(Dp, psi_round, k, Psi, Vpsi, Xs[wave]);
+  const int nmwg = (ntri + 3) / 4;
+  if (b < nsolve + nmwg) {
+    const int tile = (b - nsolve) * 4 + wave;
+    if (tile < ntri) jacobi_m_tile(Dp, apply_round, tile, Min, Mout, Vprev, Xs[wave]);
+    return;
+  }
+  const int k = (b - nsolve - nmwg) * 4 + wave;
+  if (k < npsi) jacobi_psi_tile(Dp, apply_round, k, Psi, Vprev, Xs[wave]);
 }
 
 // Per OFF_COLS-column chunk: off-diagonal squares, all squares, and the largest
@@ -662,45 +809,43 @@ void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, i
       throw Error(RMHMC_E_NONFINITE, "softabs_eig: non-finite entries in the matrix");
     if (w.ctrl_host[1] != 0.0) { conv = true; break; }
     if (sw >= max_sweeps) break;
-    // round r: solve (V[r & 1]), M tiles, then Psi tiles fused into the
-    // launch that solves round r + 1
-    const long ntri = (long)ns * (ns + 1) / 2;
+    // launch 0 solves round 0 from M; launch r + 1 applies round r to M and
+    // Psi and solves round r + 1 from M_r and V_r
+    const int ntri = ns * (ns + 1) / 2;
     const int npsi = (Dp / JSB) * ns;
     double* Vb[2] = {w.V, w.V + (long)ns * JSB * JSB};
     const double solve_flops = (double)ns * (JSB - 1) * (JHB * JHB * 24.0 + JSB * JHB * 6.0);
+    const double compose_flops = (double)ns * 3.0 * (2.0 * JSB * JSB * JHB + 2.0 * JHB * JSB * JHB);
     const double sb3 = (double)JSB * JSB * JSB;
+    const double vset = (double)ns * JSB * JSB * sizeof(double);
+    const double tile = (double)JSB * JSB * sizeof(double);
     RM_REQUIRE(max_inner == JACOBI_INNER_DYNAMIC || max_inner == JACOBI_INNER_STATIC,
                "softabs_eig: unsupported number of inner sweeps");
     auto round_kernel = max_inner == JACOBI_INNER_DYNAMIC
                             ? jacobi_round_kernel<JACOBI_INNER_DYNAMIC>
                             : jacobi_round_kernel<JACOBI_INNER_STATIC>;
     int slot = timing_begin(TK_JACOBI_SOLVE, st);
-    hipLaunchKernelGGL(round_kernel, dim3(ns), dim3(256), 0, st, Dp, 0, ns, (const double*)Min,
-                       Vb[0], (const double*)w.ctrl, 0, 0, w.Psi, (const double*)Vb[1]);
+    hipLaunchKernelGGL(round_kernel, dim3(ns), dim3(256), 0, st, Dp, -1, ns, (const double*)Min,
+                       Mout, (const double*)nullptr, Vb[0], (const double*)w.ctrl, 0, 0, w.Psi);
     RM_CHECK_LAUNCH();
     // algorithmic bytes: subproblems read, rotations written
-    const double vset = (double)ns * JSB * JSB * sizeof(double);
     timing_end(slot, st, solve_flops, 2.0 * vset);
     for (int r = 0; r < nb - 1; ++r) {
-      slot = timing_begin(TK_JACOBI_APPLY, st);
-      hipLaunchKernelGGL(jacobi_apply_m_kernel, dim3(cdiv(ntri, 4)), dim3(256), 0, st, Dp, r,
-                         (const double*)Min, Mout, (const double*)Vb[r & 1],
-                         (const double*)w.ctrl);
-      RM_CHECK_LAUNCH();
-      // upper tiles read, all of M written, rotations read once
-      timing_end(slot, st, 4.0 * sb3 * ntri,
-                 ((double)ntri * JSB * JSB + (double)Dp * Dp) * sizeof(double) + vset);
-      std::swap(Min, Mout);
       const bool more = r + 1 < nb - 1;
+      const int nsolve = more ? ns : 0;
       slot = timing_begin(TK_JACOBI_SOLVE, st);
-      hipLaunchKernelGGL(round_kernel, dim3((more ? ns : 0) + cdiv(npsi, 4)), dim3(256), 0, st,
-                         Dp, r + 1, more ? ns : 0, (const double*)Min, Vb[(r + 1) & 1],
-                         (const double*)w.ctrl, r, npsi, w.Psi, (const double*)Vb[r & 1]);
+      hipLaunchKernelGGL(round_kernel, dim3(nsolve + cdiv(ntri, 4) + cdiv(npsi, 4)), dim3(256), 0,
+                         st, Dp, r, nsolve, (const double*)Min, Mout, (const double*)Vb[r & 1],
+                         Vb[(r + 1) & 1], (const double*)w.ctrl, ntri, npsi, w.Psi);
       RM_CHECK_LAUNCH();
-      // Psi read and written once, the previous rotations read once, and
-      // (solve part) subproblems read and rotations written
-      timing_end(slot, st, (more ? solve_flops : 0.0) + 2.0 * sb3 * npsi,
-                 2.0 * (double)Dp * Dp * sizeof(double) + vset + (more ? 2.0 * vset : 0.0));
+      // algorithmic work: M update (upper tiles read, all of M written), Psi
+      // read and written, rotations V_r read once; solves: three tiles of
+      // M_r read per subproblem, V_{r+1} written
+      timing_end(slot, st,
+                 4.0 * sb3 * ntri + 2.0 * sb3 * npsi + (more ? solve_flops + compose_flops : 0.0),
+                 (double)ntri * tile + 3.0 * (double)Dp * Dp * sizeof(double) + vset +
+                     (more ? 3.0 * ns * tile + vset : 0.0));
+      std::swap(Min, Mout);
     }
     ++sw;
     hipLaunchKernelGGL(offnorm_kernel, dim3(nparts), dim3(256), 0, st, Dp, (const double*)Min, w.part);
