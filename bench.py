@@ -46,6 +46,10 @@ def parse():
                     help="skip the per-kernel event timing (use under a profiler)")
     ap.add_argument("--ess-moves", type=int, default=0,
                     help="also run a chain of this many moves and report ESS/s")
+    ap.add_argument("--ess-eps", type=float, default=0.0,
+                    help="step size of the ESS chain (default: the workload's)")
+    ap.add_argument("--ess-leapfrogs", type=int, default=0,
+                    help="leapfrogs per move of the ESS chain (default: the workload's)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--traj", type=int, default=5,
                     help="leapfrogs per trajectory: the state restarts from q0 with the same "
@@ -270,14 +274,17 @@ def main():
         nm = args.ess_moves
         torch.cuda.synchronize()
         c0 = time.perf_counter()
-        samples, logpost, acc, stats = model.chain(dev(q0), dev(z[:nm]), dev(u[:nm]), cfg.eps,
-                                                   cfg.n_leapfrog, cfg.n_fixed_point, cfg.alpha)
+        ess_eps = args.ess_eps if args.ess_eps > 0 else cfg.eps
+        ess_lf = args.ess_leapfrogs if args.ess_leapfrogs > 0 else cfg.n_leapfrog
+        samples, logpost, acc, stats = model.chain(dev(q0), dev(z[:nm]), dev(u[:nm]), ess_eps,
+                                                   ess_lf, cfg.n_fixed_point, cfg.alpha)
         torch.cuda.synchronize()
         c1 = time.perf_counter()
         burn = nm // 4
         es = ess_summary(samples.cpu().numpy()[burn:], logpost.cpu().numpy()[burn:])
         kept_time = (c1 - c0) * (nm - burn) / nm
-        ess_block = {"moves": nm, "burn_in": burn, "accept_rate": float(acc.float().mean()),
+        ess_block = {"moves": nm, "burn_in": burn, "eps": ess_eps, "leapfrogs_per_move": ess_lf,
+                     "failures": stats.failures, "accept_rate": float(acc.float().mean()),
                      "ess_min": es["min"], "ess_median": es["median"], "ess_logpost": es["logpost"],
                      "ess_min_per_sec": es["min"] / kept_time,
                      "ess_logpost_per_sec": es["logpost"] / kept_time,
