@@ -64,7 +64,9 @@ def rand_q(spec, seed, scale=0.4):
 
 # ---------------------------------------------------------------- GEMM
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("shape", [(64, 64, 64), (70, 45, 33), (1, 130, 17), (257, 3, 300), (128, 96, 1)])
+# (2050, 4100, 21): a large product, ragged in every dimension
+@pytest.mark.parametrize("shape", [(64, 64, 64), (70, 45, 33), (1, 130, 17), (257, 3, 300), (128, 96, 1),
+                                   (2050, 4100, 21)])
 @pytest.mark.parametrize("tA,tB", [(0, 0), (0, 1), (1, 0), (1, 1)])
 def test_gemm(rm, dtype, shape, tA, tB):
     m, n, k = shape
@@ -247,6 +249,36 @@ def test_metric_grad_parity(rm, name):
         record("metric_grad", model=name, alpha=alpha, dHdq=e_dq, dHdp=e_dp, ham=e_h, floor=fl)
         tol = max(BAR, 10 * fl)
         assert e_dq < tol and e_dp < tol and e_h < tol
+
+
+def test_full_size_hessian_and_metric_grad(rm):
+    """The benchmarked workload itself (D = 1038: N = 1024, P = 14, jitter
+    1e-6): U, grad U and H, then dH/dq, dH/dp and the Hamiltonian for the
+    reference eigen-state, against the reference and its own floor (the
+    reference with the data points reordered)."""
+    spec, cfg = wl.workload("propensity_mkl_d1038")
+    q = rand_q(spec, 31, 0.1)
+    M = rm.Model(spec)
+    U, g, H = M.hessian(dev(q))
+    ref = omodel.hessian(spec, q)
+    fl_h = floor_hessian(spec, q, ref)
+    eU, eg, eH = rel(host(U), ref[0]), rel(host(g), ref[1]), rel(host(H), ref[2])
+    record("full_hessian", D=spec.D, U=eU, grad=eg, H=eH, floor=fl_h)
+    tol = max(BAR, 10 * fl_h)
+    assert eU < tol and eg < tol and eH < tol
+    st = oham.State(oham.GPTarget(spec), q, cfg.alpha)
+    p = omomentum(st, np.random.default_rng(32).standard_normal(spec.D))
+    dq, dp, ham = M.metric_grad(dev(q), dev(p), dev(st.eig["Psi"].T), dev(st.eig["lam"]), cfg.alpha)
+    ref_dq, ref_dp, ref_h = oham.grad_q(st, p), oham.grad_p(st, p), oham.hamiltonian(st, p)
+    s2, q2, full = permuted(spec, q)
+    st2 = oham.State(oham.GPTarget(s2), q2, cfg.alpha)
+    fl = max(rel(unpermute_vec(oham.grad_q(st2, p[full]), full), ref_dq),
+             rel(unpermute_vec(oham.grad_p(st2, p[full]), full), ref_dp),
+             rel(oham.hamiltonian(st2, p[full]), ref_h))
+    e_dq, e_dp, e_h = rel(host(dq), ref_dq), rel(host(dp), ref_dp), rel(host(ham), ref_h)
+    record("full_metric_grad", D=spec.D, dHdq=e_dq, dHdp=e_dp, ham=e_h, floor=fl)
+    tol = max(BAR, 10 * fl)
+    assert e_dq < tol and e_dp < tol and e_h < tol
 
 
 # ---------------------------------------------------------------- leapfrog
