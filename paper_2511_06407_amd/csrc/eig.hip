@@ -201,7 +201,7 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
   __shared__ double Sb[2][SB][SB + 1];
   __shared__ double V[SB][SB + 1];
   __shared__ double Tw[3][SB][17];  // per-wave intermediates of the composition
-  __shared__ double2 cs[4][HB];     // per wave: (c, s) of the round's pairs
+  __shared__ double2 cs[4][HB];     // per wave: (s, tau) of the round's pairs
   __shared__ double red[4];
   const int nb = Dp / HB;
   const int tid = threadIdx.x;
@@ -252,7 +252,13 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
       // rotation of pair u (the smaller angle, |angle| <= pi/4)
       const int pu = rr_local<SB>(ir, u), qu = rr_local<SB>(ir, SB - 1 - u);
       const double app = S[pu][pu], aqq = S[qu][qu], apq = S[pu][qu];
-      double c = 1.0, sn = 0.0, t = 0.0;
+      // The rotation is kept as (s, tau), tau = s / (1 + c) = tan(angle / 2),
+      // and applied as x' = x - s (y + tau x), y' = y + s (x - tau y): c
+      // never appears rounded.  With c = fl(1 / sqrt(1 + t^2)), every small
+      // angle (t^2 below the unit roundoff, where c rounds to 1) would grow
+      // both columns' norms by t^2, always upwards, and a warm-started solve
+      // applies thousands of such angles to each column.
+      double sn = 0.0, tau = 0.0, t = 0.0;
       const double apq2 = apq * apq;
       if (apq2 > fmax(thr2, 1e-30 * fabs(app * aqq))) {
         // t = sgn(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)), d = a_qq - a_pp
@@ -261,8 +267,9 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
         const double r2 = d * d + 4.0 * apq2;
         const double r = r2 * rsqrt(r2);
         t = (d >= 0.0 ? 2.0 : -2.0) * apq / (fabs(d) + r);
-        c = rsqrt(1.0 + t * t);
+        const double c = rsqrt(1.0 + t * t);
         sn = t * c;
+        tau = sn / (1.0 + c);
       }
       if (__ballot(t != 0.0) == 0) continue;   // no pair rotates: S and V stay
       // significant: an angle above 1e-8.  Inside a tight cluster the entries
@@ -270,7 +277,7 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
       // subproblem must still be diagonalised for the outer sweeps to
       // converge quadratically.
       significant = significant || (__ballot(fabs(t) > 1e-8) != 0);
-      if (lane < HB) csw[u] = make_double2(c, sn);
+      if (lane < HB) csw[u] = make_double2(sn, tau);
       wave_lds_sync();   // read back by other lanes of this wave
 
       // S' = J' S J by 2 x 2 blocks (u, v)
@@ -305,11 +312,13 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
       }
 #pragma unroll
       for (int j = 0; j < NBLK; ++j) {
-        const double cv = rv[j].x, sv = rv[j].y;
-        const double y11 = c * x[j][0] - sn * x[j][2], y12 = c * x[j][1] - sn * x[j][3];
-        const double y21 = sn * x[j][0] + c * x[j][2], y22 = sn * x[j][1] + c * x[j][3];
-        double z11 = cv * y11 - sv * y12, z12 = sv * y11 + cv * y12;
-        double z21 = cv * y21 - sv * y22, z22 = sv * y21 + cv * y22;
+        const double sv = rv[j].x, tv = rv[j].y;
+        const double y11 = x[j][0] - sn * (x[j][2] + tau * x[j][0]);
+        const double y12 = x[j][1] - sn * (x[j][3] + tau * x[j][1]);
+        const double y21 = x[j][2] + sn * (x[j][0] - tau * x[j][2]);
+        const double y22 = x[j][3] + sn * (x[j][1] - tau * x[j][3]);
+        double z11 = y11 - sv * (y12 + tv * y11), z12 = y12 + sv * (y11 - tv * y12);
+        double z21 = y21 - sv * (y22 + tv * y21), z22 = y22 + sv * (y21 - tv * y22);
         if ((tid + 256 * j) / HB == u && t != 0.0) {
           // the pair's own block: exact annihilation (Rutishauser update)
           z11 = x[j][0] - t * x[j][1];
@@ -324,8 +333,9 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
       }
 #pragma unroll
       for (int k = 0; k < NVR; ++k) {
-        V[row[k]][p2[k]] = r2v[k].x * vp[k] - r2v[k].y * vq[k];
-        V[row[k]][q2[k]] = r2v[k].y * vp[k] + r2v[k].x * vq[k];
+        const double s2 = r2v[k].x, t2 = r2v[k].y;
+        V[row[k]][p2[k]] = vp[k] - s2 * (vq[k] + t2 * vp[k]);
+        V[row[k]][q2[k]] = vq[k] + s2 * (vp[k] - t2 * vq[k]);
       }
       __syncthreads();
       cur ^= 1;
