@@ -261,15 +261,24 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
       double sn = 0.0, tau = 0.0, t = 0.0;
       const double apq2 = apq * apq;
       if (apq2 > fmax(thr2, 1e-30 * fabs(app * aqq))) {
-        // t = sgn(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)), d = a_qq - a_pp
-        // (sgn(0) = +1), with the root from one refined rsqrt
+        // The smaller angle with tan(2 angle) = 2 a_pq / d, d = a_qq - a_pp
+        // (sgn(0) = +1), from two rsqrt and one reciprocal, with no division
+        // on the chain: rho = 1 / sqrt(d^2 + 4 a_pq^2), cos^2 = (1 + |d| rho) / 2,
+        // sin = sgn(d) a_pq rho / cos, t = tan = sin / cos.  1 + c lies in
+        // [1 + 1/sqrt 2, 2], so the hardware reciprocal refined by two Newton
+        // steps is accurate to rounding.
         const double d = aqq - app;
-        const double r2 = d * d + 4.0 * apq2;
-        const double r = r2 * rsqrt(r2);
-        t = (d >= 0.0 ? 2.0 : -2.0) * apq / (fabs(d) + r);
-        const double c = rsqrt(1.0 + t * t);
-        sn = t * c;
-        tau = sn / (1.0 + c);
+        const double rho = rsqrt(d * d + 4.0 * apq2);
+        const double x = fma(0.5 * fabs(d), rho, 0.5);
+        const double ic = rsqrt(x);
+        const double c = x * ic;
+        sn = ((d >= 0.0 ? apq : -apq) * rho) * ic;
+        t = sn * ic;
+        const double y = 1.0 + c;
+        double ry = __builtin_amdgcn_rcp(y);
+        ry = fma(ry, fma(-y, ry, 1.0), ry);
+        ry = fma(ry, fma(-y, ry, 1.0), ry);
+        tau = sn * ry;
       }
       if (__ballot(t != 0.0) == 0) continue;   // no pair rotates: S and V stay
       // significant: an angle above 1e-8.  Inside a tight cluster the entries
@@ -794,6 +803,13 @@ void eig_workspace_sizes(int D, long* doubles) {
   *doubles = 3L * Dp * Dp + 2L * (nb / 2) * JSB * JSB + 3L * (Dp / OFF_COLS + 1) + 8;
 }
 
+// Unused dynamic LDS reserved by the update-and-solve launches: it lifts a
+// workgroup's LDS above half of the CU's 160 KB, so each CU holds one
+// workgroup.  The solves are a latency-bound chain of dependent FP64 steps;
+// without this, tile workgroups of the same launch share their CU and delay
+// the chain (measured: 1.5 us of a 29.9 us launch at Dp = 1088).
+constexpr int ROUND_LDS_RESERVE = 12288;
+
 void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, int* sweeps_out,
                 hipStream_t st) {
   // Input: w.M (Dp x Dp symmetric, padded) and w.Psi (Dp x Dp, padded with identity).
@@ -844,8 +860,8 @@ void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, i
       const bool more = r + 1 < nb - 1;
       const int nsolve = more ? ns : 0;
       slot = timing_begin(TK_JACOBI_SOLVE, st);
-      hipLaunchKernelGGL(round_kernel, dim3(nsolve + cdiv(ntri, 4) + cdiv(npsi, 4)), dim3(256), 0,
-                         st, Dp, r, nsolve, (const double*)Min, Mout, (const double*)Vb[r & 1],
+      hipLaunchKernelGGL(round_kernel, dim3(nsolve + cdiv(ntri, 4) + cdiv(npsi, 4)), dim3(256),
+                         ROUND_LDS_RESERVE, st, Dp, r, nsolve, (const double*)Min, Mout, (const double*)Vb[r & 1],
                          Vb[(r + 1) & 1], (const double*)w.ctrl, ntri, npsi, w.Psi);
       RM_CHECK_LAUNCH();
       // algorithmic work: M update (upper tiles read, all of M written), Psi
