@@ -126,7 +126,7 @@ __global__ void dHe_kernel(int P, const double* __restrict__ D1, const double* _
                            const double* __restrict__ D3, const double* __restrict__ t3,
                            const double* __restrict__ tB, const double* __restrict__ tau,
                            const int* __restrict__ pidx, const int* __restrict__ tidx,
-                           const int* __restrict__ yidx, int npairs, int nyy,
+                           const int* __restrict__ tauidx, int npairs,
                            double* __restrict__ dHe) {
   const int P2 = P * P, P3 = P2 * P;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < P3; e += gridDim.x * blockDim.x) {
@@ -138,7 +138,7 @@ __global__ void dHe_kernel(int P, const double* __restrict__ D1, const double* _
     if (plm >= 0) v += D3[n * npairs + plm] - 0.5 * tB[n * npairs + plm];
     const int t = tidx[(l * P + m) * P + n];
     if (t >= 0) v += t3[t];
-    v += tau[n + yidx[l * P + m] * P];
+    v += tau[tauidx[e]];
     dHe[e] = v;
   }
 }
@@ -236,8 +236,8 @@ struct Model {
   Tuple* pairs = nullptr;
   Tuple* triples = nullptr;
   int npairs = 0, ntriples = 0, nyy = 0;
-  std::vector<int> pidx_h, tidx_h, yidx_h;
-  int *pidx = nullptr, *tidx = nullptr, *yidx = nullptr;
+  std::vector<int> pidx_h, tidx_h, yidx_h, tauidx_h;
+  int *pidx = nullptr, *tidx = nullptr, *tauidx = nullptr;
   // scratch
   CholWork chol;
   EigWork eig;
@@ -318,11 +318,12 @@ std::unique_ptr<Point> new_point(Model& m) {
   p.phiK2 = pl.alloc<double>(std::max(m.npairs, 1));
   p.trAA = pl.alloc<double>(P * P);
   p.ak = pl.alloc<double>(P);
-  // pointer arrays for the Y_lm = A_l A_m batch (l <= m)
+  // pointer arrays for the Y_lm = A_l A_m batch (the formed pairs l <= m)
   std::vector<const double*> ya, yb;
   std::vector<double*> yc;
   for (int l = 0; l < m.P; ++l)
     for (int mm = l; mm < m.P; ++mm) {
+      if (m.yidx_h[l * m.P + mm] < 0) continue;
       ya.push_back(p.A + l * NN);
       yb.push_back(p.A + mm * NN);
       yc.push_back(m.prec == RMHMC_MIXED ? p.Yt
@@ -345,6 +346,7 @@ std::unique_ptr<Point> new_point(Model& m) {
     std::vector<float*> fc;
     for (int l = 0; l < m.P; ++l)
       for (int mm = l; mm < m.P; ++mm) {
+        if (m.yidx_h[l * m.P + mm] < 0) continue;
         fa.push_back(p.Af + l * NN);
         fb.push_back(p.Af + mm * NN);
         fc.push_back(p.Ytf + (long)m.yidx_h[l * m.P + mm] * NN);
@@ -505,7 +507,7 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
       g.batch = m.nyy;
       gemm(g, st);
     }
-    // tau[n, (l,m)] = tr(A_n A_l A_m) = <A_n, Y_lm'>
+    // tau[n, y] = tr(A_n A_l A_m) = <A_n, Y_lm'> for the formed pairs y = (l, m)
     gemm_tallk(P, m.nyy, NN, pt.A, NN, pt.Yt, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
   } else {
     {
@@ -559,7 +561,7 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
   hipLaunchKernelGGL(dHe_kernel, dim3(cdiv(P * P * P, 256)), dim3(256), 0, st, P,
                      (const double*)m.D1, (const double*)m.D2, (const double*)m.D3,
                      (const double*)m.t3, (const double*)m.tB, (const double*)m.tau,
-                     (const int*)m.pidx, (const int*)m.tidx, (const int*)m.yidx, m.npairs, m.nyy,
+                     (const int*)m.pidx, (const int*)m.tidx, (const int*)m.tauidx, m.npairs,
                      pt.dHe);
   RM_CHECK_LAUNCH();
   pt.have_pre = true;
@@ -711,16 +713,36 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
     if (kind == RMHMC_K_SE_ISO || kind == RMHMC_K_SE_ARD) return true;
     return a == b && b == c;
   };
+  // tau_nlm = tr(A_n A_l A_m) is symmetric in all three indices (the trace
+  // is cyclic, and transposing A_n A_l A_m with A_i = K^-1 K_i reverses the
+  // order), so Y_lm = A_l A_m is formed only for pairs within one half of
+  // the index range: of any three indices two share a half.  That is
+  // h(h+1)/2 + h'(h'+1)/2 products (56 for P = 14) instead of P(P+1)/2.
+  const int half = (P + 1) / 2;
+  int ny = 0;
+  for (int l = 0; l < P; ++l)
+    for (int mm = l; mm < P; ++mm)
+      if ((l < half) == (mm < half)) {
+        m.yidx_h[l * P + mm] = m.yidx_h[mm * P + l] = ny++;
+      }
+  m.nyy = ny;
+  m.tauidx_h.assign(P * P * P, -1);
+  for (int n = 0; n < P; ++n)
+    for (int l = 0; l < P; ++l)
+      for (int mm = 0; mm < P; ++mm) {
+        int& t = m.tauidx_h[(n * P + l) * P + mm];
+        if (m.yidx_h[l * P + mm] >= 0) t = n + P * m.yidx_h[l * P + mm];
+        else if (m.yidx_h[n * P + l] >= 0) t = mm + P * m.yidx_h[n * P + l];
+        else t = l + P * m.yidx_h[n * P + mm];
+        RM_REQUIRE(t >= 0 && t < P * m.nyy, "internal: tau index table");
+      }
   for (int l = 0; l < P; ++l)
     for (int mm = l; mm < P; ++mm) {
-      const int y = (int)(l * P - l * (l - 1) / 2 + (mm - l));
-      m.yidx_h[l * P + mm] = m.yidx_h[mm * P + l] = y;
       if (!nonzero(l, mm, mm)) continue;
       const int idx = (int)m.pairs_h.size();
       m.pairs_h.push_back({2, l, mm, 0});
       m.pidx_h[l * P + mm] = m.pidx_h[mm * P + l] = idx;
     }
-  m.nyy = P * (P + 1) / 2;
   for (int l = 0; l < P; ++l)
     for (int mm = l; mm < P; ++mm)
       for (int n = mm; n < P; ++n) {
@@ -749,10 +771,10 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   if (m.ntriples) RM_HIP(hipMemcpy(m.triples, m.triples_h.data(), m.ntriples * sizeof(Tuple), hipMemcpyHostToDevice));
   m.pidx = pl.alloc<int>(P * P);
   m.tidx = pl.alloc<int>(P * P * P);
-  m.yidx = pl.alloc<int>(P * P);
+  m.tauidx = pl.alloc<int>(P * P * P);
   RM_HIP(hipMemcpy(m.pidx, m.pidx_h.data(), P * P * sizeof(int), hipMemcpyHostToDevice));
   RM_HIP(hipMemcpy(m.tidx, m.tidx_h.data(), P * P * P * sizeof(int), hipMemcpyHostToDevice));
-  RM_HIP(hipMemcpy(m.yidx, m.yidx_h.data(), P * P * sizeof(int), hipMemcpyHostToDevice));
+  RM_HIP(hipMemcpy(m.tauidx, m.tauidx_h.data(), P * P * P * sizeof(int), hipMemcpyHostToDevice));
   // scratch
   m.chol.L = pl.alloc<double>(NN);
   m.chol.Linv = pl.alloc<double>(NN);

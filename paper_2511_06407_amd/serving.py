@@ -78,7 +78,9 @@ def footprint_bytes(N, P):
     D = N + P
     Dp = ((D + 63) // 64) * 64
     nn = N * N
-    point = (2 + 4 * P + P * (P + 1) // 2) * nn + 2 * Dp * Dp + (2 * P * P + 8) * N + P ** 3
+    h1, h2 = (P + 1) // 2, P // 2
+    ny = h1 * (h1 + 1) // 2 + h2 * (h2 + 1) // 2   # Y_lm products formed (pairs within a half)
+    point = (2 + 4 * P + ny) * nn + 2 * Dp * Dp + (2 * P * P + 8) * N + P ** 3
     # generated second derivatives of K: at most one per pair (l <= m), 64 at a time
     model_scratch = 3 * nn + 6 * Dp * Dp + min(P * (P + 1) // 2, 64) * nn
     return 8 * (4 * point + model_scratch)
