@@ -57,7 +57,25 @@ __global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
   const T* __restrict__ B = p.Bp ? p.Bp[batch] : p.B + (long)batch * p.sB;
   const long kbeg = (long)kc * p.kchunk;
   const long kend = min((long)p.k, kbeg + p.kchunk);
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  // XCD-aware tile order.  Workgroups are handed to the eight XCDs in
+  // turn, so workgroup ids j, j + 8, j + 16, ... of a batch item share an
+  // XCD and its L2.  Those ids get one compact block of tiles (a quarter of
+  // the row bands times half of the column bands) instead of two row bands
+  // against every column band, so each XCD streams less of A and B.  The
+  // map is a bijection whenever gx % 4 == 0 and gy % 2 == 0 (then gx * gy is
+  // a multiple of 8); other grids keep the plain order.
+  int bx = blockIdx.x, by = blockIdx.y;
+  {
+    const int gx = gridDim.x, gy = gridDim.y;
+    if (gx % 4 == 0 && gy % 2 == 0) {
+      const int lin = blockIdx.x + gx * blockIdx.y;
+      const int j = lin % 8, k = lin / 8;
+      const int rw = gx / 4, cw = gy / 2;
+      bx = (j % 4) * rw + k % rw;
+      by = (j / 4) * cw + k / rw;
+    }
+  }
+  const int m0 = bx * BM, n0 = by * BN;
   const int M = p.m, N = p.n;
   const long lda = p.lda, ldb = p.ldb;
 

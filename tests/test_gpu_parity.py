@@ -64,9 +64,10 @@ def rand_q(spec, seed, scale=0.4):
 
 # ---------------------------------------------------------------- GEMM
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-# (2050, 4100, 21): a large product, ragged in every dimension
+# (2050, 4100, 21): a large product, ragged in every dimension; (250, 120, 70):
+# a 4 x 2 tile grid, which takes the XCD-aware tile order, ragged in m and n
 @pytest.mark.parametrize("shape", [(64, 64, 64), (70, 45, 33), (1, 130, 17), (257, 3, 300), (128, 96, 1),
-                                   (2050, 4100, 21)])
+                                   (2050, 4100, 21), (250, 120, 70)])
 @pytest.mark.parametrize("tA,tB", [(0, 0), (0, 1), (1, 0), (1, 1)])
 def test_gemm(rm, dtype, shape, tA, tB):
     m, n, k = shape
