@@ -197,15 +197,27 @@ __global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
       }
 }
 
+// C = sum over the split-K partials.  One wave per output element: its
+// lanes take every 64th split and a shuffle tree adds the lane sums (a fixed
+// order, so the result is deterministic).  With a few hundred outputs and
+// hundreds of splits, a thread per output would leave the loads serial.
 template <typename T>
-__global__ void splitk_reduce(int m, int n, int splits, const T* __restrict__ part,
-                              double* __restrict__ C, long ldc) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)m * n) return;
+__global__ __launch_bounds__(256) void splitk_reduce(int m, int n, int splits,
+                                                     const T* __restrict__ part,
+                                                     double* __restrict__ C, long ldc) {
+  const long mn = (long)m * n;
+  const long idx = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   double s = 0;
-  for (int kc = 0; kc < splits; ++kc) s += (double)part[(long)kc * m * n + idx];
-  const int i = (int)(idx % m), j = (int)(idx / m);
-  C[i + (long)j * ldc] = s;
+  if (idx < mn) {
+#pragma unroll 4
+    for (int kc = lane; kc < splits; kc += 64) s += (double)part[(long)kc * mn + idx];
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0 && idx < mn) {
+    const int i = (int)(idx % m), j = (int)(idx / m);
+    C[i + (long)j * ldc] = s;
+  }
 }
 
 template <typename T>
@@ -255,7 +267,7 @@ void tallk_impl(int m, int n, long k, const T* A, long lda, const T* B, long ldb
   p.part = reinterpret_cast<T*>(work);
   launch(p, true, false, 1, st);
   const long mn = (long)m * n;
-  hipLaunchKernelGGL((splitk_reduce<T>), dim3(cdiv(mn, 256)), dim3(256), 0, st, m, n, sp,
+  hipLaunchKernelGGL((splitk_reduce<T>), dim3(cdiv(mn, 4)), dim3(256), 0, st, m, n, sp,
                      (const T*)p.part, C, ldc);
   RM_CHECK_LAUNCH();
 }
