@@ -89,6 +89,8 @@ void gemv_split(int m, int n, double alpha, const double* A, long lda, const dou
                 double beta, double* y, double* work, hipStream_t st);
 
 // out[b] = sum_ij A(i,j) * B_b(i,j) for an m x n A (lda) and B_b = B + b*sB (ldb).
+// `work` holds multi_dot_work(n) doubles; nb <= 32.
+inline long multi_dot_work(long n) { return n * 4 * 32; }
 void multi_dot(int m, int n, const double* A, long lda, const double* B, long ldb, long sB,
                int nb, double* out, double* work, hipStream_t st);
 

@@ -610,13 +610,21 @@ __global__ __launch_bounds__(256) void offnorm_kernel(int Dp, const double* __re
 // norm-wise test also held one sweep earlier (one polishing sweep at most).
 __global__ void offnorm_finish_kernel(int nparts, const double* __restrict__ part, double zeta,
                                       double* __restrict__ ctrl, int first) {
-  if (threadIdx.x != 0) return;
+  // One wave: lanes take every 64th partial, then a shuffle tree combines
+  // the lane sums and maxima in a fixed order.
+  const int lane = threadIdx.x;
   double off = 0.0, tot = 0.0, rel = 0.0;
-  for (int p = 0; p < nparts; ++p) {
+  for (int p = lane; p < nparts; p += 64) {
     off += part[3 * p];
     tot += part[3 * p + 1];
     rel = fmax(rel, part[3 * p + 2]);
   }
+  for (int o = 32; o > 0; o >>= 1) {
+    off += __shfl_xor(off, o, 64);
+    tot += __shfl_xor(tot, o, 64);
+    rel = fmax(rel, __shfl_xor(rel, o, 64));
+  }
+  if (lane != 0) return;
   const double nrm = sqrt(tot);
   if (first) ctrl[0] = nrm;
   const double r = nrm > 0.0 ? sqrt(off) / nrm : 0.0;

@@ -142,14 +142,18 @@ __global__ __launch_bounds__(256) void kd_wsum_kernel(ModelDev md, const double*
     part[((long)w * gridDim.x + blockIdx.x) * nt + t] = sh[0][t] + sh[1][t] + sh[2][t] + sh[3][t];
 }
 
-__global__ void kd_wsum_reduce(int nblk, int nt, int nw, const double* __restrict__ part,
-                               double* __restrict__ out) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nt * nw) return;
+// out[w * nt + t] = sum over the per-block partials.  One wave per output:
+// lanes take every 64th block and a shuffle tree adds the lane sums (a fixed
+// order, so the result is deterministic).
+__global__ __launch_bounds__(64) void kd_wsum_reduce(int nblk, int nt, const double* __restrict__ part,
+                                                     double* __restrict__ out) {
+  const int idx = blockIdx.x;
   const int w = idx / nt, t = idx % nt;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[((long)w * nblk + b) * nt + t];
-  out[idx] = s;
+#pragma unroll 4
+  for (int b = threadIdx.x; b < nblk; b += 64) s += part[((long)w * nblk + b) * nt + t];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (threadIdx.x == 0) out[idx] = s;
 }
 
 // Partial sums of y = dK_tuple x over the j chunk blockIdx.z.
@@ -295,7 +299,9 @@ static void kd_wsum_chunk(const ModelDev& md, const double* eta, const Tuple* tu
                           int nw, double* out, double* work, hipStream_t st) {
   if (nt <= 0 || nw <= 0) return;
   const long NN = (long)md.N * md.N;
-  int nblk = cdiv(NN, 256 * 16);
+  // Eight elements per thread: 512 workgroups at N = 1024, two waves per
+  // SIMD, which is what the kernel's register use allows.
+  int nblk = cdiv(NN, 256 * 8);
   if (nblk > 512) nblk = 512;
   if (nblk < 1) nblk = 1;
   const int slot = timing_begin(TK_KD_WSUM, st);
@@ -303,7 +309,7 @@ static void kd_wsum_chunk(const ModelDev& md, const double* eta, const Tuple* tu
                      Kinv, alpha, Wstack, work);
   RM_CHECK_LAUNCH();
   timing_end(slot, st, 2.0 * (double)NN * nt * nw, (double)NN * nw * sizeof(double));
-  hipLaunchKernelGGL(kd_wsum_reduce, dim3(cdiv(nt * nw, 256)), dim3(256), 0, st, nblk, nt, nw,
+  hipLaunchKernelGGL(kd_wsum_reduce, dim3(nt * nw), dim3(64), 0, st, nblk, nt,
                      (const double*)work, out);
   RM_CHECK_LAUNCH();
 }

@@ -161,35 +161,52 @@ __global__ __launch_bounds__(256) void gemv_t_kernel(int m, int n, double alpha,
 }
 
 // ---------------------------------------------------------------- multi-dot
+// out[b] = sum_ij A(i, j) B_b(i, j) for up to MD_MAX matrices B_b.  One
+// workgroup per column j; its 256 threads stride over the rows, so every
+// load is coalesced and a launch holds n workgroups (several per CU, enough
+// loads in flight to stream the nb + 1 matrices from HBM).  Each wave sums
+// its lanes with a shuffle tree and writes one partial per matrix:
+// part[(4 j + wave) * nb + b].
 constexpr int MD_MAX = 32;
-__global__ __launch_bounds__(256) void multi_dot_kernel(int m, int n, const double* A, long lda,
+constexpr int MD_WAVES = 4;
+__global__ __launch_bounds__(256) void multi_dot_kernel(int m, const double* A, long lda,
                                                         const double* B, long ldb, long sB,
-                                                        int nb, int cols_per_block, double* part) {
-  __shared__ double sh[256];
+                                                        int nb, double* part) {
   double acc[MD_MAX];
 #pragma unroll
   for (int b = 0; b < MD_MAX; ++b) acc[b] = 0;
-  const int c0 = blockIdx.x * cols_per_block;
-  const int c1 = min(n, c0 + cols_per_block);
-  for (int j = c0; j < c1; ++j)
-    for (int i = threadIdx.x; i < m; i += 256) {
-      const double a = A[i + (long)j * lda];
+  const int j = blockIdx.x;
+  for (int i = threadIdx.x; i < m; i += 256) {
+    const double a = A[i + (long)j * lda];
 #pragma unroll
-      for (int b = 0; b < MD_MAX; ++b)
-        if (b < nb) acc[b] += a * B[(long)b * sB + i + (long)j * ldb];
-    }
-  for (int b = 0; b < nb; ++b) {
-    double s = block_sum(acc[b], sh);
-    if (threadIdx.x == 0) part[(long)blockIdx.x * nb + b] = s;
+    for (int b = 0; b < MD_MAX; ++b)
+      if (b < nb) acc[b] += a * B[(long)b * sB + i + (long)j * ldb];
   }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double mine = 0;
+#pragma unroll
+  for (int b = 0; b < MD_MAX; ++b) {
+    if (b < nb) {
+      double s = acc[b];
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (lane == b) mine = s;
+    }
+  }
+  if (lane < nb) part[((long)j * MD_WAVES + wave) * nb + lane] = mine;
 }
 
-__global__ void reduce_parts_kernel(int nparts, int nb, const double* part, double* out) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
+// out[b] = sum over the partials of matrix b.  One wave per matrix: lanes
+// take every 64th partial and a shuffle tree adds the lane sums, so the
+// order is fixed and the result deterministic.
+__global__ __launch_bounds__(64) void reduce_parts_kernel(int nparts, int nb, const double* part,
+                                                          double* out) {
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
   double s = 0;
-  for (int p = 0; p < nparts; ++p) s += part[(long)p * nb + b];
-  out[b] = s;
+#pragma unroll 8
+  for (int p = lane; p < nparts; p += 64) s += part[(long)p * nb + b];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) out[b] = s;
 }
 
 // ---------------------------------------------------------------- Cholesky
@@ -370,12 +387,13 @@ void multi_dot(int m, int n, const double* A, long lda, const double* B, long ld
                int nb, double* out, double* work, hipStream_t st) {
   if (nb <= 0) return;
   RM_REQUIRE(nb <= MD_MAX, "multi_dot: too many matrices");
-  const int cpb = 4;
-  const int nblocks = cdiv(n, cpb);
-  hipLaunchKernelGGL(multi_dot_kernel, dim3(nblocks), dim3(256), 0, st, m, n, A, lda, B, ldb, sB,
-                     nb, cpb, work);
+  if (m <= 0 || n <= 0) {
+    fill(out, nb, 0.0, st);
+    return;
+  }
+  hipLaunchKernelGGL(multi_dot_kernel, dim3(n), dim3(256), 0, st, m, A, lda, B, ldb, sB, nb, work);
   RM_CHECK_LAUNCH();
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, st, nblocks, nb,
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(nb), dim3(64), 0, st, n * MD_WAVES, nb,
                      (const double*)work, out);
   RM_CHECK_LAUNCH();
 }

@@ -144,49 +144,67 @@ __global__ void dHe_kernel(int P, const double* __restrict__ D1, const double* _
 }
 
 // z = sum_lm W_lm (2 K_l a_m - K_lm alpha)
-__global__ void zvec_kernel(int N, int P, int Dp, const double* __restrict__ W,
-                            const double* __restrict__ c1a, const double* __restrict__ k2a,
-                            const int* __restrict__ pidx, double* __restrict__ z) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+// z_i = sum_lm W[eta_l, eta_m] (2 c1a_lm(i) - k2a_lm(i)).  A workgroup
+// covers 64 rows i; its 16 waves split the P^2 (l, m) terms and the wave
+// sums are added in a fixed order through LDS.
+constexpr int ZV_WAVES = 16;
+__global__ __launch_bounds__(64 * ZV_WAVES) void zvec_kernel(int N, int P, int Dp, const double* __restrict__ W,
+                                                          const double* __restrict__ c1a, const double* __restrict__ k2a,
+                                                          const int* __restrict__ pidx, double* __restrict__ z) {
+  __shared__ double sh[ZV_WAVES][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + tx;
   double s = 0.0;
-  for (int l = 0; l < P; ++l)
-    for (int m = 0; m < P; ++m) {
+  if (i < N) {
+    for (int k = ty; k < P * P; k += ZV_WAVES) {
+      const int l = k / P, m = k % P;
       const double wlm = W[(N + l) + (long)(N + m) * Dp];
-      double t = 2.0 * c1a[(long)(l * P + m) * N + i];
-      const int pi = pidx[l * P + m];
+      double t = 2.0 * c1a[(long)k * N + i];
+      const int pi = pidx[k];
       if (pi >= 0) t -= k2a[(long)pi * N + i];
       s += wlm * t;
     }
-  z[i] = s;
+  }
+  sh[ty][tx] = s;
+  __syncthreads();
+  if (ty == 0 && i < N) {
+    double r = 0.0;
+    for (int w = 0; w < ZV_WAVES; ++w) r += sh[w][tx];
+    z[i] = r;
+  }
 }
 
-// v = tr(W dH/dq) assembled from the pieces (f-part and eta-part).
+// v = tr(W dH/dq) for the latent coordinates i < N, assembled from the pieces.
 __global__ void contract_final_kernel(int N, int P, int Dp, double beta, const double* __restrict__ W,
                                       const double* __restrict__ lik, const double* __restrict__ Au,
-                                      const double* __restrict__ Kz, const double* __restrict__ wB,
-                                      const double* __restrict__ E1, const double* __restrict__ E2,
-                                      const double* __restrict__ dHe, const int* __restrict__ pidx,
-                                      int npairs, double* __restrict__ v) {
+                                      const double* __restrict__ Kz, double* __restrict__ v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int D = N + P;
-  if (i >= D) return;
-  if (i < N) {
-    double s = beta * W[i + (long)i * Dp] * lik[3 * N + i] + Kz[i];
-    for (int l = 0; l < P; ++l) s -= 2.0 * Au[(long)l * N + i];
-    v[i] = s;
-  } else {
-    const int n = i - N, P2 = P * P;
-    double s = -wB[n];
-    for (int l = 0; l < P; ++l) {
-      s += 2.0 * (E1[l * P2 + n * P + l] + E1[l * P2 + l * P + n]);
-      const int pln = pidx[l * P + n];
-      if (pln >= 0) s -= 2.0 * E2[l * npairs + pln];
-    }
-    for (int l = 0; l < P; ++l)
-      for (int m = 0; m < P; ++m) s += W[(N + l) + (long)(N + m) * Dp] * dHe[n * P2 + l * P + m];
-    v[i] = s;
+  if (i >= N) return;
+  double s = beta * W[i + (long)i * Dp] * lik[3 * N + i] + Kz[i];
+  for (int l = 0; l < P; ++l) s -= 2.0 * Au[(long)l * N + i];
+  v[i] = s;
+}
+
+// v = tr(W dH/dq) for the hyperparameter coordinate N + n: one wave per n,
+// lanes over the P^2 (l, m) terms, summed by a shuffle tree.
+__global__ __launch_bounds__(64) void contract_eta_kernel(int N, int P, int Dp, const double* __restrict__ W,
+                                                          const double* __restrict__ wB, const double* __restrict__ E1,
+                                                          const double* __restrict__ E2, const double* __restrict__ dHe,
+                                                          const int* __restrict__ pidx, int npairs,
+                                                          double* __restrict__ v) {
+  const int n = blockIdx.x, lane = threadIdx.x, P2 = P * P;
+  double s = 0.0;
+  for (int k = lane; k < P2; k += 64) {
+    const int l = k / P, m = k % P;
+    s += W[(N + l) + (long)(N + m) * Dp] * dHe[(long)n * P2 + k];
   }
+  for (int l = lane; l < P; l += 64) {
+    s += 2.0 * (E1[l * P2 + n * P + l] + E1[l * P2 + l * P + n]);
+    const int pln = pidx[l * P + n];
+    if (pln >= 0) s -= 2.0 * E2[l * npairs + pln];
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) v[N + n] = s - wB[n];
 }
 
 // H(q,p) = U + log|G|/2 + sum c^2/g / 2 + D log(2 pi)/2, c = Psi' p.
@@ -585,15 +603,19 @@ void contract(Model& m, Point& pt, const double* W, double* v, hipStream_t st) {
   gemv(N, N, 1.0, pt.Kinv, N, true, 0, m.Ku, N, 0.0, m.Au, N, P, st);     // A_l u_l = K^-1 K_l u_l
   pair_dots(N, m.u, N, P, pt.c1a, N, P * P, m.E1, st);
   pair_dots(N, m.u, N, P, pt.k2a, N, m.npairs, m.E2, st);
-  hipLaunchKernelGGL(zvec_kernel, dim3(cdiv(N, 256)), dim3(256), 0, st, N, P, Dp, W,
+  hipLaunchKernelGGL(zvec_kernel, dim3(cdiv(N, 64)), dim3(64 * ZV_WAVES), 0, st, N, P, Dp, W,
                      (const double*)pt.c1a, (const double*)pt.k2a, (const int*)m.pidx, m.z);
   RM_CHECK_LAUNCH();
   gemv(N, N, 1.0, pt.Kinv, N, true, 0, m.z, 0, 0.0, m.Kz, 0, 1, st);
-  hipLaunchKernelGGL(contract_final_kernel, dim3(cdiv(m.D, 256)), dim3(256), 0, st, N, P, Dp,
-                     m.beta, W, (const double*)pt.lik, (const double*)m.Au, (const double*)m.Kz,
-                     (const double*)m.wB, (const double*)m.E1, (const double*)m.E2,
-                     (const double*)pt.dHe, (const int*)m.pidx, m.npairs, v);
+  hipLaunchKernelGGL(contract_final_kernel, dim3(cdiv(N, 256)), dim3(256), 0, st, N, P, Dp,
+                     m.beta, W, (const double*)pt.lik, (const double*)m.Au, (const double*)m.Kz, v);
   RM_CHECK_LAUNCH();
+  if (P > 0) {
+    hipLaunchKernelGGL(contract_eta_kernel, dim3(P), dim3(64), 0, st, N, P, Dp, W,
+                       (const double*)m.wB, (const double*)m.E1, (const double*)m.E2,
+                       (const double*)pt.dHe, (const int*)m.pidx, m.npairs, v);
+    RM_CHECK_LAUNCH();
+  }
 }
 
 void compute_vW2(Model& m, Point& pt, hipStream_t st) {
@@ -793,7 +815,7 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   m.kdwork = pl.alloc<double>(512L * MAX_P * MAX_TUPLES + (long)MAX_P * std::max(m.ntriples, m.npairs) + 64);
   m.mvwork = pl.alloc<double>((long)KD_MV_SPLIT * std::min(m.npairs, MAX_TUPLES) * N + 64);
   m.ktbuf = pl.alloc<double>((long)std::min(m.npairs, MAX_TUPLES) * N * N + 64);
-  m.mdwork = pl.alloc<double>((long)(std::max<long>(N, Dp) / 4 + 2) * 32);
+  m.mdwork = pl.alloc<double>(multi_dot_work(std::max<long>(N, Dp)) + 64);
   m.W = pl.alloc<double>(Dp * Dp);
   m.Wt1 = pl.alloc<double>(Dp * Dp);
   m.Wt2 = pl.alloc<double>(Dp * Dp);
