@@ -72,6 +72,10 @@ void gemm(const Gemm<float>& g, hipStream_t st);
 // C (m x n) = op(A)' B over a very long inner dimension k, split across
 // workgroups and summed in a fixed order (deterministic).  A is k x m (lda),
 // B is k x n (ldb), both column-major.  `work` must hold splits*m*n values.
+// A single plain product (batch 1, alpha 1, beta 0, C only) with its k range
+// split over `splits` layers; `work` holds splits * m * n doubles.  Anything
+// else goes to gemm().
+void gemm_splitk(const Gemm<double>& g, double* work, int splits, hipStream_t st);
 void gemm_tallk(int m, int n, long k, const double* A, long lda, const double* B, long ldb,
                 double* C, long ldc, double* work, int splits, hipStream_t st);
 void gemm_tallk(int m, int n, long k, const float* A, long lda, const float* B, long ldb,
@@ -102,6 +106,8 @@ struct CholWork {
   double* tmp = nullptr;    // n x n
   double* diagLogs = nullptr;  // n
   int* info = nullptr;
+  double* split = nullptr;  // optional: nsplit * n * n partials for K^-1 = Linv' Linv
+  int nsplit = 0;
 };
 void chol_inverse(int n, const double* K, double* Kinv, double* logdet, CholWork& w,
                   double* redwork, hipStream_t st);

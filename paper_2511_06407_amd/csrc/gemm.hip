@@ -220,6 +220,20 @@ __global__ __launch_bounds__(256) void splitk_reduce(int m, int n, int splits,
   }
 }
 
+// C = sum over a few split-K partials, one thread per output element, the
+// splits added in order (deterministic).  For wide outputs with few splits.
+__global__ __launch_bounds__(256) void splitk_sum(int m, int n, int splits,
+                                                  const double* __restrict__ part,
+                                                  double* __restrict__ C, long ldc) {
+  const long mn = (long)m * n;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= mn) return;
+  double s = 0;
+  for (int kc = 0; kc < splits; ++kc) s += part[(long)kc * mn + idx];
+  const int i = (int)(idx % m), j = (int)(idx / m);
+  C[i + (long)j * ldc] = s;
+}
+
 template <typename T>
 void launch(const Params<T>& p, bool tA, bool tB, int batch, hipStream_t st) {
   dim3 grid(cdiv(p.m, BM), cdiv(p.n, BN), batch * p.ksplit);
@@ -272,10 +286,40 @@ void tallk_impl(int m, int n, long k, const T* A, long lda, const T* B, long ldb
   RM_CHECK_LAUNCH();
 }
 
+// One plain product C = op(A) op(B) with its k range split over `splits`
+// workgroup layers.  A single square product near 1000 has only a few
+// hundred 64 x 64 tiles, about one wave per SIMD; the layers multiply the
+// waves in flight, and a second pass adds them in order.
+void gemm_splitk_impl(const Gemm<double>& g, double* work, int splits, hipStream_t st) {
+  const bool plain = g.batch == 1 && g.alpha == 1.0 && g.beta == 0.0 && !g.C2 && !g.C2p &&
+                     !g.Ap && !g.Bp && !g.Cp && g.C && work;
+  if (!plain || splits <= 1 || g.k < 2 * BK * splits) {
+    gemm_impl(g, st);
+    return;
+  }
+  if (g.m <= 0 || g.n <= 0) return;
+  Params<double> p{};
+  p.m = g.m; p.n = g.n; p.k = g.k; p.alpha = 1; p.beta = 0;
+  p.A = g.A; p.lda = g.lda; p.B = g.B; p.ldb = g.ldb;
+  long chunk = ((long)g.k + splits - 1) / splits;
+  chunk = (chunk + BK - 1) / BK * BK;
+  const int sp = (int)(((long)g.k + chunk - 1) / chunk);
+  p.ksplit = sp; p.kchunk = chunk;
+  p.part = work;
+  launch(p, g.tA, g.tB, 1, st);
+  const long mn = (long)g.m * g.n;
+  hipLaunchKernelGGL(splitk_sum, dim3(cdiv(mn, 256)), dim3(256), 0, st, g.m, g.n, sp,
+                     (const double*)work, g.C, g.ldc);
+  RM_CHECK_LAUNCH();
+}
+
 }  // namespace
 
 void gemm(const Gemm<double>& g, hipStream_t st) { gemm_impl(g, st); }
 void gemm(const Gemm<float>& g, hipStream_t st) { gemm_impl(g, st); }
+void gemm_splitk(const Gemm<double>& g, double* work, int splits, hipStream_t st) {
+  gemm_splitk_impl(g, work, splits, st);
+}
 
 int tallk_splits(long k) {
   long s = k / 2048;

@@ -50,7 +50,7 @@ void kd_wsum_stack(const ModelDev& md, const double* eta, const Tuple* tuples, i
 // y[(x * nt + t) * N + i] = sum_j d K_tuple(i,j) x_x(j), for nx vectors x (stride N).
 // The j range is split over KD_MV_SPLIT workgroup columns; `work` holds
 // KD_MV_SPLIT * min(nt, MAX_TUPLES) * nx * N partial sums.
-constexpr int KD_MV_SPLIT = 16;
+constexpr int KD_MV_SPLIT = 32;
 void kd_matvec(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
                const double* x, int nx, double* y, double* work, hipStream_t st);
 

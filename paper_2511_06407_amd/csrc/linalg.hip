@@ -451,7 +451,7 @@ void chol_inverse(int n, const double* K, double* Kinv, double* logdet, CholWork
   c.A = w.Linv; c.lda = n; c.tA = true;
   c.B = w.Linv; c.ldb = n;
   c.C = Kinv; c.ldc = n;
-  gemm(c, st);
+  gemm_splitk(c, w.split, w.nsplit, st);
   symmetrize(n, Kinv, n, st);
   vsum(n, w.diagLogs, logdet, st);
   axpby(1, 0.0, logdet, 2.0, logdet, st);  // log|K| = 2 sum log L_ii

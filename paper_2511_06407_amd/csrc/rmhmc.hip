@@ -242,6 +242,10 @@ __global__ void any_nonfinite_kernel(long n, const double* __restrict__ x, int* 
 
 // ------------------------------------------------------------ model
 
+// k-range layers for the single Dp x Dp warm-start products: 17 x 17 tiles
+// at Dp = 1088 become 1156 workgroups, about four per CU.
+constexpr int GSPLIT = 4;
+
 struct Model {
   int N = 0, dx = 0, P = 0, D = 0, Dp = 0;
   int lik = 0;
@@ -260,6 +264,7 @@ struct Model {
   CholWork chol;
   EigWork eig;
   double *tallwork = nullptr, *kdwork = nullptr, *mdwork = nullptr;
+  double* gsplit = nullptr;   // split-K partials of the warm-start products (GSPLIT x Dp x Dp)
   double *mvwork = nullptr;   // column-split partials of kd_matvec
   double *ktbuf = nullptr;    // generated second derivatives of K (<= MAX_TUPLES x N*N)
   double *W = nullptr, *Wt1 = nullptr, *Wt2 = nullptr;
@@ -475,13 +480,13 @@ int compute_eig(Model& m, Point& pt, Point* warm, double alpha, double zeta, int
     g.A = pt.H; g.lda = Dp;
     g.B = warm->Psi; g.ldb = Dp;
     g.C = m.Wt1; g.ldc = Dp;
-    gemm(g, st);
+    gemm_splitk(g, m.gsplit, GSPLIT, st);
     Gemm<double> h;
     h.m = Dp; h.n = Dp; h.k = Dp;
     h.A = warm->Psi; h.lda = Dp; h.tA = true;
     h.B = m.Wt1; h.ldb = Dp;
     h.C = m.eig.M; h.ldc = Dp;
-    gemm(h, st);
+    gemm_splitk(h, m.gsplit, GSPLIT, st);
     symmetrize(Dp, m.eig.M, Dp, st);
     copy(m.eig.Psi, warm->Psi, (long)Dp * Dp, st);
     pt.updates_since_reorth = cnt;
@@ -816,6 +821,9 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   m.mvwork = pl.alloc<double>((long)KD_MV_SPLIT * std::min(m.npairs, MAX_TUPLES) * N + 64);
   m.ktbuf = pl.alloc<double>((long)std::min(m.npairs, MAX_TUPLES) * N * N + 64);
   m.mdwork = pl.alloc<double>(multi_dot_work(std::max<long>(N, Dp)) + 64);
+  m.gsplit = pl.alloc<double>((long)GSPLIT * Dp * Dp + 64);
+  m.chol.split = m.gsplit;   // same stream, never live at the same time
+  m.chol.nsplit = GSPLIT;
   m.W = pl.alloc<double>(Dp * Dp);
   m.Wt1 = pl.alloc<double>(Dp * Dp);
   m.Wt2 = pl.alloc<double>(Dp * Dp);
