@@ -112,8 +112,10 @@ __global__ __launch_bounds__(256) void gemv_n_kernel(int m, int n, double alpha,
   const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + r;
   double s = 0;
-  if (i < m)
+  if (i < m) {
+#pragma unroll 8
     for (int j = g; j < n; j += 4) s += A[i + (long)j * lda] * x[j];
+  }
   sh[g][r] = s;
   __syncthreads();
   if (g == 0 && i < m) {
@@ -132,6 +134,7 @@ __global__ __launch_bounds__(256) void gemv_n_split_kernel(int m, int n, const d
   const int c0 = blockIdx.y * chunk, c1 = min(n, c0 + chunk);
   if (i >= m) return;
   double s = 0.0;
+#pragma unroll 8
   for (int j = c0; j < c1; ++j) s += A[i + (long)j * lda] * x[j];
   part[(long)blockIdx.y * m + i] = s;
 }
@@ -155,6 +158,7 @@ __global__ __launch_bounds__(256) void gemv_t_kernel(int m, int n, double alpha,
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= n) return;
   double s = 0;
+#pragma unroll 8
   for (int i = lane; i < m; i += 64) s += A[i + (long)j * lda] * x[i];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) y[j] = alpha * s + (beta != 0.0 ? beta * y[j] : 0.0);
