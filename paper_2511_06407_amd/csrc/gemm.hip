@@ -229,6 +229,7 @@ __global__ __launch_bounds__(256) void splitk_sum(int m, int n, int splits,
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= mn) return;
   double s = 0;
+#pragma unroll 4
   for (int kc = 0; kc < splits; ++kc) s += part[(long)kc * mn + idx];
   const int i = (int)(idx % m), j = (int)(idx / m);
   C[i + (long)j * ldc] = s;

@@ -202,6 +202,7 @@ __global__ void kd_matvec_reduce(long n, int nsplit, const double* __restrict__ 
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   double s = 0.0;
+#pragma unroll 8
   for (int z = 0; z < nsplit; ++z) s += part[(long)z * n + e];
   y[e] = s;
 }

@@ -144,6 +144,7 @@ __global__ void gemv_reduce_kernel(int m, int nsplit, const double* part, double
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   double s = 0.0;
+#pragma unroll 8
   for (int c = 0; c < nsplit; ++c) s += part[(long)c * m + i];
   y[i] = alpha * s + (beta != 0.0 ? beta * y[i] : 0.0);
 }
