@@ -226,6 +226,18 @@ rmhmc_status rmhmc_gemm_f64(int m, int n, int k, double alpha, const double* A, 
 rmhmc_status rmhmc_gemm_f32(int m, int n, int k, float alpha, const float* A, int lda, int transA,
                             const float* B, int ldb, int transB, float beta, float* C, int ldc,
                             hipStream_t stream);
+/* C = op(A) op(B) for one product whose k range is split over `splits`
+ * (1..64) workgroup layers, then added layer by layer in a fixed order: the
+ * form used for the single D x D products of the eigen warm start and for
+ * K^-1 = L^-T L^-1, where 64 x 64 output tiles alone leave about one wave per
+ * SIMD.  A, B, C and `work` [device, caller-owned]; `work` holds
+ * splits * m * n doubles and is overwritten.  Products whose k range is
+ * shorter than 32 * splits take the unsplit kernel.  RMHMC_E_ARG for bad
+ * sizes, leading dimensions, NULL pointers or `splits`.  Asynchronous on
+ * `stream`. */
+rmhmc_status rmhmc_gemm_f64_splitk(int m, int n, int k, const double* A, int lda, int transA,
+                                   const double* B, int ldb, int transB, double* C, int ldc,
+                                   double* work, int splits, hipStream_t stream);
 
 /* Live per-kernel timing (instrumentation, off by default).  When enabled,
  * the launches of each kernel family below are bracketed by HIP events on

@@ -1196,6 +1196,24 @@ rmhmc_status rmhmc_gemm_f32(int m, int n, int k, float alpha, const float* A, in
                             hipStream_t st) {
   return gemm_entry<float>(m, n, k, alpha, A, lda, transA, B, ldb, transB, beta, C, ldc, st);
 }
+rmhmc_status rmhmc_gemm_f64_splitk(int m, int n, int k, const double* A, int lda, int transA,
+                                   const double* B, int ldb, int transB, double* C, int ldc,
+                                   double* work, int splits, hipStream_t st) {
+  return guard([&] {
+    RM_REQUIRE(m >= 0 && n >= 0 && k >= 0, "negative dimension");
+    RM_REQUIRE(A && B && C && work, "NULL matrix or workspace");
+    RM_REQUIRE(splits >= 1 && splits <= 64, "splits must be in [1, 64]");
+    RM_REQUIRE(lda >= std::max(1, transA ? k : m), "lda too small");
+    RM_REQUIRE(ldb >= std::max(1, transB ? n : k), "ldb too small");
+    RM_REQUIRE(ldc >= std::max(1, m), "ldc too small");
+    Gemm<double> g;
+    g.m = m; g.n = n; g.k = k;
+    g.A = A; g.lda = lda; g.tA = transA != 0;
+    g.B = B; g.ldb = ldb; g.tB = transB != 0;
+    g.C = C; g.ldc = ldc;
+    gemm_splitk(g, work, splits, st);
+  });
+}
 
 rmhmc_status rmhmc_model_create(const rmhmc_model_desc* desc, rmhmc_precision prec,
                                 rmhmc_model** out) {

@@ -28,7 +28,8 @@ FP64, MIXED = 0, 1
 EXPORTED = ["rmhmc_model_create", "rmhmc_model_dims", "rmhmc_model_destroy", "rmhmc_hessian",
             "rmhmc_softabs_eig", "rmhmc_metric_grad", "rmhmc_state_create", "rmhmc_state_get",
             "rmhmc_state_set_momentum", "rmhmc_state_destroy", "rmhmc_glf_step", "rmhmc_chain",
-            "rmhmc_gemm_f64", "rmhmc_gemm_f32", "rmhmc_last_error", "rmhmc_state_draw_momentum",
+            "rmhmc_gemm_f64", "rmhmc_gemm_f32", "rmhmc_gemm_f64_splitk", "rmhmc_last_error",
+            "rmhmc_state_draw_momentum",
             "rmhmc_timing_enable", "rmhmc_timing_read", "rmhmc_pool_create", "rmhmc_pool_submit",
             "rmhmc_pool_poll", "rmhmc_pool_destroy", "rmhmc_state_stats"]
 
@@ -84,6 +85,7 @@ _sig = {
     "rmhmc_glf_step": [_vp, _vp, _d, _i, _vp],
     "rmhmc_chain": [_vp, C.POINTER(ChainCfg), _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(ChainStats), _vp],
     "rmhmc_gemm_f64": [_i, _i, _i, _d, _vp, _i, _i, _vp, _i, _i, _d, _vp, _i, _vp],
+    "rmhmc_gemm_f64_splitk": [_i, _i, _i, _vp, _i, _i, _vp, _i, _i, _vp, _i, _vp, _i, _vp],
     "rmhmc_gemm_f32": [_i, _i, _i, C.c_float, _vp, _i, _i, _vp, _i, _i, C.c_float, _vp, _i, _vp],
 }
 for _name, _args in _sig.items():
@@ -142,6 +144,12 @@ def gemm_colmajor(m, n, k, A, lda, tA, B, ldb, tB, Cm, ldc, alpha=1.0, beta=0.0,
         f32 = torch.float32
         _check(_lib.rmhmc_gemm_f32(m, n, k, alpha, _ptr(A, f32), lda, int(tA), _ptr(B, f32), ldb,
                                    int(tB), beta, _ptr(Cm, f32), ldc, _stream(stream)))
+
+
+def gemm_splitk_colmajor(m, n, k, A, lda, tA, B, ldb, tB, Cm, ldc, work, splits, stream=None):
+    """C = op(A) op(B) in FP64 with the k range split over `splits` layers."""
+    _check(_lib.rmhmc_gemm_f64_splitk(m, n, k, _f64(A), lda, int(tA), _f64(B), ldb, int(tB),
+                                      _f64(Cm), ldc, _f64(work), splits, _stream(stream)))
 
 
 class Model:

@@ -98,6 +98,38 @@ def test_gemm(rm, dtype, shape, tA, tB):
     assert np.array_equal(host(Ct)[:, m:], Cm[:, m:].astype(np.float32 if dtype == "f32" else np.float64))
 
 
+# Split-K single products: (1088, 1088, 1088) is the eigen warm-start shape
+# (17 x 17 tiles, 4 layers of 272); (130, 77, 301) is ragged in every
+# dimension with a short last layer; (64, 40, 100) has k below 32 * splits and
+# takes the unsplit kernel.
+@pytest.mark.parametrize("shape,splits", [((1088, 1088, 1088), 4), ((130, 77, 301), 3),
+                                          ((64, 40, 100), 4), ((33, 65, 500), 1)])
+@pytest.mark.parametrize("tA,tB", [(0, 0), (1, 0), (0, 1)])
+def test_gemm_splitk(rm, shape, splits, tA, tB):
+    m, n, k = shape
+    rng = np.random.default_rng(m * 5 + n * 11 + k + splits)
+    ra, ca = (k, m) if tA else (m, k)
+    rb, cb = (n, k) if tB else (k, n)
+    lda, ldb, ldc = ra + 2, rb + 3, m + 1
+    A = rng.standard_normal((ca, lda))
+    B = rng.standard_normal((cb, ldb))
+    Cm = rng.standard_normal((n, ldc))
+    opA = A[:, :ra] if tA else A[:, :ra].T
+    opB = B[:, :rb] if tB else B[:, :rb].T
+    want = opA @ opB
+    At = torch.tensor(A, dtype=torch.float64, device="cuda")
+    Bt = torch.tensor(B, dtype=torch.float64, device="cuda")
+    Ct = torch.tensor(Cm, dtype=torch.float64, device="cuda")
+    work = torch.full((splits * m * n,), np.nan, dtype=torch.float64, device="cuda")
+    rm.gemm_splitk_colmajor(m, n, k, At, lda, tA, Bt, ldb, tB, Ct, ldc, work, splits)
+    got = host(Ct)[:, :m].T
+    err = rel(got, want)
+    record("gemm_splitk", shape=str(shape), splits=splits, tA=tA, tB=tB, err=err)
+    assert err < 1e-13
+    # padding rows of C untouched
+    assert np.array_equal(host(Ct)[:, m:], Cm[:, m:])
+
+
 # ---------------------------------------------------------------- Hessian
 def floor_hessian(spec, q, ref):
     s2, q2, full = permuted(spec, q)
