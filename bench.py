@@ -1,10 +1,13 @@
-"""Benchmark: generalized-leapfrog throughput of softabs RMHMC at D = 1038.
+"""Benchmark: softabs RMHMC throughput at D = 1038 (N = 1024 latent values,
+14 kernel hyperparameters).
 
-One step = one generalized leapfrog (Eq. leapfrog of the paper) on the
-device-resident state: K Hessian assemblies and warm-started Jacobi
-eigendecompositions for the implicit position update, the per-point
-contraction precompute at the new point, and K + 2 structured
-third-derivative contractions for the two momentum half steps.
+One step = one generalized leapfrog (Eq. leapfrog of the paper) inside the
+RMHMC chain of Algorithm 1, run entirely on the device: K Hessian assemblies
+and warm-started Jacobi eigendecompositions for the implicit position update,
+the contraction precompute at the new point, K + 2 structured third-derivative
+contractions for the two momentum half steps, and per move of C leapfrogs the
+momentum draw and the Metropolis-Hastings test.  The timed steps continue the
+chain of the warmup steps; an ESS chain continues after them.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 
@@ -37,25 +40,21 @@ TRAFFIC_SOURCES = ("paper_2511_06407_amd/csrc/eig.hip",)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="propensity_mkl_d1038")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="skip the per-kernel event timing (use under a profiler)")
-    ap.add_argument("--ess-moves", type=int, default=0,
-                    help="also run a chain of this many moves and report ESS/s")
-    ap.add_argument("--ess-eps", type=float, default=0.0,
-                    help="step size of the ESS chain (default: the workload's)")
-    ap.add_argument("--ess-leapfrogs", type=int, default=0,
-                    help="leapfrogs per move of the ESS chain (default: the workload's)")
+    ap.add_argument("--ess-moves", type=int, default=40,
+                    help="moves of the ESS chain run after the timed steps (0: none)")
+    ap.add_argument("--ess-burnin", type=int, default=-1,
+                    help="burn-in moves of the ESS chain (default: a quarter)")
+    ap.add_argument("--eps", type=float, default=0.0, help="step size (default: the workload's)")
+    ap.add_argument("--leapfrogs", type=int, default=0,
+                    help="leapfrogs per move C (default: the workload's)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--traj", type=int, default=5,
-                    help="leapfrogs per trajectory: the state restarts from q0 with the same "
-                         "momentum draw every TRAJ steps, outside the timed region (longer "
-                         "trajectories without Metropolis-Hastings drift out of the stable "
-                         "region of this posterior)")
     ap.add_argument("--calib-copy-mb", type=float, default=0.0,
                     help="run one device-to-device copy of this many MB before the timed "
                          "steps (a kernel of known traffic for scaling PMC byte counters)")
@@ -128,35 +127,89 @@ def traffic_from_profile(kernel_src_hash):
     return d.get("bytes_per_launch")
 
 
+def lscpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(spec, cfg):
     """The FP64 reference timed on the host cores on a bounded sample: one
     metric evaluation at a point (Hessian + eigendecomposition) and one
-    third-derivative contraction, scaled to a leapfrog
-    (K evaluations + (K + 2) contractions)."""
+    third-derivative contraction at the chain's start point, first with all
+    BLAS threads, then with one (the paper drove its GPU from one core).  A
+    reference leapfrog is K such evaluations and K + 2 contractions plus
+    O(D^2) vector work, so the sample scales to leapfrogs/s."""
     import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import hamiltonian as oham
     from oracle.chain import momentum
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
-    except Exception:
-        cores = os.cpu_count()
     T = oham.GPTarget(spec)
     q = np.zeros(spec.D)
-    t0 = time.perf_counter()
-    st = oham.State(T, q, cfg.alpha)
-    t1 = time.perf_counter()
-    p = momentum(st, np.random.default_rng(0).standard_normal(spec.D))
-    st.v_w2()
-    t2 = time.perf_counter()
     K = cfg.n_fixed_point
-    per_leapfrog = K * (t1 - t0) + (K + 2) * (t2 - t1)
-    return {"value": 1.0 / per_leapfrog, "unit": "leapfrog steps/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": (f"1 Hessian+eigh ({t1 - t0:.2f} s) and 1 contraction ({t2 - t1:.2f} s) "
-                       f"at q=0 of {spec.D}-dim workload, scaled to K={K} evaluations + "
-                       f"{K + 2} contractions per leapfrog"),
-            "seconds": t2 - t0}
+
+    def sample():
+        t0 = time.perf_counter()
+        st = oham.State(T, q, cfg.alpha)
+        t1 = time.perf_counter()
+        momentum(st, np.random.default_rng(0).standard_normal(spec.D))
+        st.v_w2()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+
+    cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    ts_all, tc_all = sample()
+    with threadpool_limits(limits=1):
+        ts_one, tc_one = sample()
+    per_all = K * ts_all + (K + 2) * tc_all
+    per_one = K * ts_one + (K + 2) * tc_one
+    return {"value": 1.0 / per_all, "unit": "leapfrog steps/s", "cores": int(cores),
+            "kind": "oracle", "cpu_model": lscpu_model(),
+            "value_1_thread": 1.0 / per_one,
+            "sample": (f"1 Hessian+eigh and 1 contraction at q=0 of the {spec.D}-dim workload "
+                       f"({ts_all:.2f} s + {tc_all:.2f} s on {cores} threads, "
+                       f"{ts_one:.2f} s + {tc_one:.2f} s on 1 thread), scaled to K={K} "
+                       f"evaluations + {K + 2} contractions per leapfrog"),
+            "seconds": ts_all + tc_all + ts_one + tc_one}
+
+
+def algorithmic_flops(N, P, D, K):
+    """Flops of one generalized leapfrog by textbook counts: Cholesky N^3/3,
+    inverse 2N^3/3, GEMM 2mnk, 4.3 D^3 per eigendecomposition with vectors;
+    K metric evaluations ((1 + 2P) N^3 + 4.3 D^3 each), K + 1 W1 builds
+    (4 D^3), one W2 build (2 D^3), K + 2 contractions (2 N^3 each) and the
+    per-point trace tensor (min(2P(K + 2), P(P + 1)) N^3)."""
+    return (K * ((1 + 2 * P) * N ** 3 + 4.3 * D ** 3) + (K + 1) * 4 * D ** 3 + 2 * D ** 3
+            + (K + 2) * 2 * N ** 3 + min(2 * P * (K + 2), P * (P + 1)) * N ** 3)
+
+
+def run_chain_steps(model, cfg, q0_dev, n_steps, seed, stream_id, burn=False):
+    """n_steps leapfrogs of the device chain from q0: moves of C leapfrogs and
+    one shorter move for the remainder.  Returns (seconds, last sample, stats
+    list, (samples, logpost, accepted) of the full moves)."""
+    import torch
+    C = cfg.n_leapfrog
+    parts = [(n_steps // C, C)] if n_steps >= C else []
+    if n_steps % C:
+        parts.append((1, n_steps % C))
+    q = q0_dev
+    stats, out = [], None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, (moves, lf) in enumerate(parts):
+        s, l, a, st = model.chain(q, cfg.eps, lf, cfg.n_fixed_point, moves, seed=seed,
+                                  stream_id=stream_id + i, alpha=cfg.alpha)
+        q = s[-1].clone()
+        stats.append(st)
+        if out is None:
+            out = (s, l, a)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, q, stats, out
 
 
 def main():
@@ -177,47 +230,18 @@ def main():
         print(json.dumps(run_serve_mode(args)), flush=True)
         return
     spec, cfg = wl.workload(args.workload, args.seed)
+    if args.eps > 0:
+        cfg.eps = args.eps
+    if args.leapfrogs > 0:
+        cfg.n_leapfrog = args.leapfrogs
     model = rmhmc.Model(spec, rmhmc.MIXED if args.precision == "mixed" else rmhmc.FP64)
-    dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")  # noqa
-    z, u = wl.chain_randoms(spec.D, max(args.ess_moves, 1) + 1, seed=args.seed)
-    q0 = np.zeros(spec.D)
-    q0_dev, p0_dev, z0_dev = dev(q0), dev(np.zeros(spec.D)), dev(z[0])
-
-    def fresh_state():
-        st = rmhmc.State(model, q0_dev, p0_dev, cfg.alpha)
-        st.draw_momentum(z0_dev)
-        return st
-
     log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)  # noqa: E731
-    S = fresh_state()
-    log(f"state ready D={spec.D}")
-    for k in range(args.warmup):
-        S.step(cfg.eps, cfg.n_fixed_point)
-        torch.cuda.synchronize()
-        log(f"warmup step {k} done")
-    S.close()
-
-    def timed_steps(n):
-        """n leapfrogs in trajectories of at most args.traj steps; returns the
-        seconds spent in the steps and the summed eigensolver counters."""
-        total, done, eig_calls, sweeps = 0.0, 0, 0, 0
-        while done < n:
-            st = fresh_state()
-            base = st.stats()
-            b = min(args.traj, n - done)
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            for _ in range(b):
-                st.step(cfg.eps, cfg.n_fixed_point)
-            torch.cuda.synchronize()
-            total += time.perf_counter() - ta
-            done += b
-            s1 = st.stats()
-            eig_calls += s1.eig_calls - base.eig_calls
-            sweeps += s1.sweeps - base.sweeps
-            st.close()
-        return total, eig_calls, sweeps
-
+    q0 = torch.zeros(spec.D, dtype=torch.float64, device="cuda")
+    log(f"model ready D={spec.D} ({model.device_bytes / 2**30:.2f} GiB on the device)")
+    q = q0
+    if args.warmup > 0:
+        tw, q, _, _ = run_chain_steps(model, cfg, q0, args.warmup, args.seed, 100)
+        log(f"warmup {args.warmup} leapfrogs in {tw:.2f} s")
     if args.calib_copy_mb > 0:
         n = int(args.calib_copy_mb * 1e6 / 8)
         a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -226,69 +250,82 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy of {8 * n} bytes done")
         del a, b
-    elapsed, eig_calls, sweeps = timed_steps(args.steps)
+    elapsed, q, st_list, _ = run_chain_steps(model, cfg, q, args.steps, args.seed, 200)
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
     value = args.steps / elapsed
+    eig_calls = sum(st.eig_calls for st in st_list)
+    sweeps = sum(st.sweeps for st in st_list)
+    F = algorithmic_flops(spec.N, spec.P, spec.D, cfg.n_fixed_point)
 
     roofline = None
     roofline_gemm = None
     if not args.no_timing:
-        # per-kernel HIP events on the launch stream, over the same number of
-        # further steps (kept out of the timed region above)
-        # one trajectory, its state created before the events are switched on
-        n_inst = min(args.steps, args.traj)
-        st = fresh_state()
-        torch.cuda.synchronize()
+        # per-kernel HIP events on the launch stream, over further chain
+        # leapfrogs kept out of the timed region above
+        n_inst = min(args.steps, cfg.n_leapfrog)
         rmhmc.timing_enable((DOMINANT, GEMM))
-        ta = time.perf_counter()
-        for _ in range(n_inst):
-            st.step(cfg.eps, cfg.n_fixed_point)
-        torch.cuda.synchronize()
-        elapsed_inst = time.perf_counter() - ta
-        st.close()
-        log(f"instrumented {n_inst} steps in {elapsed_inst:.3f} s")
+        t_inst, q_inst, st_inst, _ = run_chain_steps(model, cfg, q, n_inst, args.seed, 300)
+        log(f"instrumented {n_inst} steps in {t_inst:.3f} s")
         n, ms, flops, byts = rmhmc.timing_read(DOMINANT)
         gn, gms, gflops, _ = rmhmc.timing_read(GEMM)
         rmhmc.timing_enable(())
+        inst_eigs = sum(st.eig_calls for st in st_inst)
         if n > 0 and ms > 0:
-            achieved = byts / (ms * 1e-3) / 1e9
-            roofline = {"bound": "hbm", "kernel": DOMINANT_KERNEL,
-                        "achieved": round(achieved, 1), "peak": PEAK["hbm_gbs"],
-                        "unit": "GB/s", "frac": round(achieved / PEAK["hbm_gbs"], 4),
+            # the unit of work of the eigensolver is one eigendecomposition,
+            # 4.3 D^3 flops by the textbook count; a round launch does
+            # eig_calls / launches of one
+            per_launch = 4.3 * spec.D ** 3 * inst_eigs / n
+            avg_s = ms * 1e-3 / n
+            achieved = per_launch / avg_s / 1e12
+            roofline = {"bound": "mfma", "kernel": DOMINANT_KERNEL,
+                        "achieved": round(achieved, 4), "peak": PEAK["f64_tflops"],
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64_tflops"], 5),
                         "traffic": traffic_from_profile(file_hash(*TRAFFIC_SOURCES)),
-                        "launches": n, "avg_launch_us": round(ms * 1e3 / n, 2),
-                        "algorithmic_bytes_per_launch": byts / n,
-                        "algorithmic_flops_per_launch": flops / n,
-                        "kernel_time_share": round(ms * 1e-3 / elapsed_inst, 3)}
+                        "algorithmic_flops_per_launch": per_launch,
+                        "launches": n, "eigendecompositions": inst_eigs,
+                        "avg_launch_us": round(avg_s * 1e6, 2),
+                        "kernel_time_share": round(ms * 1e-3 / t_inst, 3),
+                        "hbm_view": {"algorithmic_bytes_per_launch": byts / n,
+                                     "achieved_gbs": round(byts / n / avg_s / 1e9, 1),
+                                     "peak_gbs": PEAK["hbm_gbs"]}}
         if gn > 0 and gms > 0:
             ga = gflops / (gms * 1e-3) / 1e12
             roofline_gemm = {"bound": "mfma", "kernel": "gemm_kernel<double> (v_mfma_f64_16x16x4f64)",
                              "achieved": round(ga, 3), "peak": PEAK["f64_tflops"], "unit": "TFLOP/s",
                              "frac": round(ga / PEAK["f64_tflops"], 4), "launches": gn,
                              "avg_launch_us": round(gms * 1e3 / gn, 2),
-                             "kernel_time_share": round(gms * 1e-3 / elapsed_inst, 3)}
+                             "kernel_time_share": round(gms * 1e-3 / t_inst, 3)}
+        q = q_inst
 
     ess_block = None
     if args.ess_moves > 0:
         from paper_2511_06407_amd.analysis import ess_summary
         nm = args.ess_moves
+        burn = args.ess_burnin if args.ess_burnin >= 0 else nm // 4
         torch.cuda.synchronize()
         c0 = time.perf_counter()
-        ess_eps = args.ess_eps if args.ess_eps > 0 else cfg.eps
-        ess_lf = args.ess_leapfrogs if args.ess_leapfrogs > 0 else cfg.n_leapfrog
-        samples, logpost, acc, stats = model.chain(dev(q0), dev(z[:nm]), dev(u[:nm]), ess_eps,
-                                                   ess_lf, cfg.n_fixed_point, cfg.alpha)
+        samples, logpost, acc, stats = model.chain(q, cfg.eps, cfg.n_leapfrog, cfg.n_fixed_point,
+                                                   nm, n_burnin=burn, seed=args.seed,
+                                                   stream_id=400, alpha=cfg.alpha)
         torch.cuda.synchronize()
         c1 = time.perf_counter()
-        burn = nm // 4
-        es = ess_summary(samples.cpu().numpy()[burn:], logpost.cpu().numpy()[burn:])
+        sm, lp = samples.cpu().numpy(), logpost.cpu().numpy()
+        es = ess_summary(sm, lp)
         kept_time = (c1 - c0) * (nm - burn) / nm
-        ess_block = {"moves": nm, "burn_in": burn, "eps": ess_eps, "leapfrogs_per_move": ess_lf,
-                     "failures": stats.failures, "accept_rate": float(acc.float().mean()),
+        ess_block = {"moves": nm, "burn_in": burn, "eps": cfg.eps,
+                     "leapfrogs_per_move": cfg.n_leapfrog, "seconds": c1 - c0,
+                     "failures": stats.failures, "fail_not_pd": stats.fail_not_pd,
+                     "fail_nonfinite": stats.fail_nonfinite, "fail_noconv": stats.fail_noconv,
+                     "eig_fallbacks": stats.eig_fallbacks,
+                     "accept_rate_kept": stats.accepted / max(nm - burn, 1),
+                     "accept_rate_all": stats.accepted_all / nm,
                      "ess_min": es["min"], "ess_median": es["median"], "ess_logpost": es["logpost"],
                      "ess_min_per_sec": es["min"] / kept_time,
+                     "ess_median_per_sec": es["median"] / kept_time,
                      "ess_logpost_per_sec": es["logpost"] / kept_time,
-                     "chain_leapfrogs_per_sec": stats.leapfrogs / (c1 - c0)}
+                     "chain_leapfrogs_per_sec": stats.leapfrogs / (c1 - c0),
+                     "max_fixed_point_residual": [stats.max_res_p, stats.max_res_q],
+                     "eta_mean": [float(x) for x in sm[:, spec.N:].mean(0)]}
 
     out = {"metric": "leapfrog steps/sec + ESS/sec at D=1036; p50/p99 request latency",
            "value": value, "unit": "leapfrog steps/s", "n_gpus": 1, "steps": args.steps,
@@ -297,13 +334,19 @@ def main():
            "dtype": "f64" if args.precision == "fp64" else "f32+f64",
            "data": "synthetic",
            "config": {"workload": args.workload, "D": spec.D, "N": spec.N, "P": spec.P,
-                      "eps": cfg.eps, "n_fixed_point": cfg.n_fixed_point, "alpha": cfg.alpha,
+                      "eps": cfg.eps, "n_leapfrog": cfg.n_leapfrog,
+                      "n_fixed_point": cfg.n_fixed_point, "alpha": cfg.alpha,
                       "precision": args.precision, "parallelism": "single GPU"},
-           "roofline": roofline, "roofline_gemm_f64": roofline_gemm}
+           "roofline": roofline, "roofline_gemm_f64": roofline_gemm,
+           "whole_step": {"algorithmic_flops": F,
+                          "achieved_tflops": round(F * value / 1e12, 3),
+                          "frac_f64_peak": round(F * value / 1e12 / PEAK["f64_tflops"], 4)},
+           "chain": {"accepted": sum(st.accepted for st in st_list),
+                     "failures": sum(st.failures for st in st_list),
+                     "eig_fallbacks": sum(st.eig_fallbacks for st in st_list)}}
     out["eig"] = {"eig_calls": eig_calls, "sweeps": sweeps,
                   "sweeps_per_eig": sweeps / max(eig_calls, 1),
-                  "note": "warm-started solves in the timed steps"}
-    out["config"]["trajectory_leapfrogs"] = args.traj
+                  "note": "in the timed chain (its first point is a static solve)"}
     if ess_block is not None:
         out["ess"] = ess_block
     if not args.no_cpu_baseline:

@@ -82,41 +82,66 @@ typedef struct {
 typedef struct rmhmc_model rmhmc_model;
 typedef struct rmhmc_state rmhmc_state;
 
+/* Inputs of Algorithm 1 besides the target and q(0): A total moves of which
+ * the first A0 are burn-in, step size, C leapfrogs per move, the softabs
+ * sharpness, and how the implicit equations and the eigensolver are run.
+ * The randomness of a chain is fixed by (seed, stream_id): Philox4x64-10
+ * with key (seed, stream_id) and counter (block, move, purpose, 0); momentum
+ * normals by Box-Muller, two per pair of 53-bit uniforms (purpose 0); the
+ * Metropolis-Hastings uniform of a move from purpose 1. */
 typedef struct {
   double eps;            /* leapfrog step size epsilon                        */
   double alpha;          /* softabs sharpness (g = lam coth(alpha lam))       */
   double zeta;           /* Jacobi tolerance (<= 0: 1e-13)                    */
   int n_leapfrog;        /* C, leapfrogs per move                             */
-  int n_moves;           /* A, moves (burn-in included)                       */
+  int n_moves;           /* A, moves in all (burn-in included)                */
+  int n_burnin;          /* A0, leading moves not returned (0 <= A0 < A)      */
   int n_fixed_point;     /* K, fixed-point iterations per implicit equation   */
   int max_sweeps;        /* Jacobi sweep cap per eigendecomposition (<=0: 60) */
-  int reorth_every;      /* re-orthogonalise Q every this many updates (<=0: 10) */
+  int reorth_every;      /* re-orthonormalise the eigenvectors every this many
+                            dynamic updates within a move (<=0: 10)           */
+  unsigned long long seed;       /* Philox key word 0                          */
+  unsigned long long stream_id;  /* Philox key word 1 (independent chains)     */
+  int precision;         /* rmhmc_precision; must equal the model's           */
 } rmhmc_chain_cfg;
 
 typedef struct {
-  int accepted;          /* moves accepted                                    */
+  int accepted;          /* accepted moves among the returned ones (A - A0)   */
+  int accepted_all;      /* accepted moves, burn-in included                  */
   int failures;          /* moves rejected because a step failed              */
+  int fail_not_pd;       /*   of which: K not positive definite               */
+  int fail_nonfinite;    /*   non-finite values                               */
+  int fail_noconv;       /*   an eigensolve did not converge                  */
   long long leapfrogs;   /* generalized leapfrogs completed                   */
   long long eig_calls;   /* eigendecompositions                               */
   long long sweeps;      /* Jacobi sweeps over all eigendecompositions        */
+  int eig_fallbacks;     /* warm starts redone by a static solve              */
+  double max_res_p;      /* largest relative residual of the last fixed-point
+                            iteration of the momentum equation                */
+  double max_res_q;      /* ... of the position equation                      */
 } rmhmc_chain_stats;
 
 /* Build a model: copies X and y to the device and allocates every workspace
- * the calls below need for this N, P and D (no allocation happens later).
+ * the calls below need for this N, P and D, the chain state of rmhmc_chain
+ * included (no call below allocates device memory, except a stand-alone
+ * rmhmc_softabs_eig larger than any before it on the device).
  * The prior is eta ~ N(0, I), f | eta ~ N(0, K(eta)); the likelihood of
  * Sec. 2.1 Eq. (data_likelihood), raised to the power beta (power posterior
  * of the evidence appendix).  Returns RMHMC_E_ARG for an invalid descriptor,
- * RMHMC_E_NOMEM if device memory runs out. */
+ * RMHMC_E_NOMEM if device memory runs out.  Calls on one model from several
+ * threads are serialised (one runs at a time). */
 rmhmc_status rmhmc_model_create(const rmhmc_model_desc* desc, rmhmc_precision prec,
                                 rmhmc_model** out);
 rmhmc_status rmhmc_model_dims(const rmhmc_model* m, int* N, int* P, int* D); /* [host] outs */
+/* Device bytes held by the model (its scratch and chain state).  [host] out. */
+rmhmc_status rmhmc_model_bytes(const rmhmc_model* m, long long* bytes);
 rmhmc_status rmhmc_model_destroy(rmhmc_model* m);
 
 /* U(q) = -ln P(q) (constants included), grad U and the Hessian H of U at q
  * (H is the matrix the softabs map of Sec. 2.2 is applied to).
  *   q [device] D; U [device] 1; gradU [device] D; H [device] D x D, ldh >= D.
- * RMHMC_E_NOT_PD if the Cholesky factorisation of K fails (the check reads
- * one device flag and synchronises the stream). */
+ * RMHMC_E_NOT_PD if the Cholesky factorisation of K fails.  Synchronises the
+ * stream. */
 rmhmc_status rmhmc_hessian(rmhmc_model* m, const double* q, double* U, double* gradU,
                            double* H, int ldh, hipStream_t stream);
 
@@ -128,12 +153,17 @@ rmhmc_status rmhmc_hessian(rmhmc_model* m, const double* q, double* U, double* g
  *   H [device] D x D (ldh); Q_warm, Q [device] D x D (ld = D);
  *   lam, g, gp [device] D: eigenvalues, g = lam coth(alpha lam) and g';
  *   logdetG [device] 1 = sum log g;  sweeps [host, nullable].
- * Eigenvalues are not sorted.  Synchronises the stream once per sweep.
- * RMHMC_E_EIG_NOCONV if max_sweeps (<= 0 selects 60) runs out. */
+ * Eigenvalues are not sorted.  Reads the convergence flag after each sweep;
+ * synchronises the stream.  The workspace is per device and shared by the
+ * calls on it (they run one at a time); a call on a larger D than any before
+ * allocates it, which rmhmc_softabs_eig_reserve(D) does ahead of time.
+ * RMHMC_E_EIG_NOCONV if max_sweeps (<= 0 selects 60) runs out,
+ * RMHMC_E_NONFINITE for non-finite entries. */
 rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, double zeta,
                                int max_sweeps, const double* Q_warm, double* Q, double* lam,
                                double* g, double* gp, double* logdetG, int* sweeps,
                                hipStream_t stream);
+rmhmc_status rmhmc_softabs_eig_reserve(int D);
 
 /* Hamiltonian and its gradients at (q, p) for a given eigen-state (Q, lam)
  * of H(q) (Sec. 2.2, Eq. Hamiltonian and Eq. d_Hamiltonian, with the metric
@@ -168,24 +198,37 @@ rmhmc_status rmhmc_state_draw_momentum(rmhmc_state* s, const double* z, hipStrea
 /* One generalized leapfrog (Sec. 2.2, Eq. leapfrog).  Both implicit
  * equations are solved by n_fixed_point plain fixed-point iterations
  * started at p(t) and q(t) (no early exit).  Metric evaluations at new
- * points are warm-started Jacobi updates (Sec. 2.4). */
+ * points are warm-started Jacobi updates (Sec. 2.4); a warm start that runs
+ * out of sweeps is redone statically.  Reads one failure word at the end
+ * (synchronises); on RMHMC_E_NOT_PD / _NONFINITE / _EIG_NOCONV the state
+ * stays at its start point. */
 rmhmc_status rmhmc_glf_step(rmhmc_model* m, rmhmc_state* s, double eps, int n_fixed_point,
                             hipStream_t stream);
 
 
-/* RMHMC chain, Algorithm 1: per move p = G^{1/2} z (p ~ N(0, G(q))),
- * C generalized leapfrogs, then Metropolis-Hastings: accept iff
- * log u < H_old - H_new, else restore q and its eigen-state (the printed
+/* RMHMC chain, Algorithm 1, entirely on the device: per move the momentum
+ * p = G^{1/2} z (p ~ N(0, G(q)), z from the chain's Philox stream), C
+ * generalized leapfrogs, then Metropolis-Hastings: accept iff
+ * log r < H_old - H_new, else keep q and its eigen-state (the printed
  * algorithm restores on the opposite event).  A failure inside a move
- * counts as a rejection.
- *   q0 [device] D; z [device] n_moves x D (row-major: move-major);
- *   u [device] n_moves in (0,1); samples [device] n_moves x D (row-major);
- *   logpost [device] n_moves (= -U(q) after each move);
- *   accepted [device] n_moves (int32 0/1); stats [host, nullable].
- * Synchronises once per move (the accept decision is read on the host). */
+ * (K not positive definite, non-finite values, no eigensolver convergence
+ * after the static fallback) is a rejection, counted in the stats.  Outputs
+ * are the moves A0 .. A-1:
+ *   q0 [device] D; samples [device] (A - A0) x D (row-major: move-major);
+ *   logpost [device] A - A0 (= -U(q) after each move);
+ *   accepted [device] A - A0 (int32 0/1); stats [host, nullable].
+ * The host reads the eigensolver's convergence flag after each sweep (no
+ * other device read inside the chain) and synchronises once at the end. */
 rmhmc_status rmhmc_chain(rmhmc_model* m, const rmhmc_chain_cfg* cfg, const double* q0,
-                         const double* z, const double* u, double* samples, double* logpost,
-                         int* accepted, rmhmc_chain_stats* stats, hipStream_t stream);
+                         double* samples, double* logpost, int* accepted,
+                         rmhmc_chain_stats* stats, hipStream_t stream);
+
+/* The randomness of move `move` of the chain (seed, stream_id), as
+ * rmhmc_chain draws it (exposed for tests): the D momentum normals z and the
+ * Metropolis-Hastings uniform u.  z [device] D, u [device] 1.  Asynchronous. */
+rmhmc_status rmhmc_chain_randoms(int D, unsigned long long seed, unsigned long long stream_id,
+                                 unsigned long long move, double* z, double* u,
+                                 hipStream_t stream);
 
 /* Concurrent chains: a pool of worker threads, each with its own HIP stream
  * (default priority), runs rmhmc_chain jobs side by side.  A job submitted
@@ -208,8 +251,7 @@ rmhmc_status rmhmc_chain(rmhmc_model* m, const rmhmc_chain_cfg* cfg, const doubl
 typedef struct rmhmc_pool rmhmc_pool;
 rmhmc_status rmhmc_pool_create(int n_workers, rmhmc_pool** out);
 rmhmc_status rmhmc_pool_submit(rmhmc_pool* pool, rmhmc_model* m, const rmhmc_chain_cfg* cfg,
-                               const double* q0, const double* z, const double* u,
-                               double* samples, double* logpost, int* accepted,
+                               const double* q0, double* samples, double* logpost, int* accepted,
                                long long* ticket);
 rmhmc_status rmhmc_pool_poll(rmhmc_pool* pool, long long ticket, int wait, int* done,
                              rmhmc_chain_stats* stats, double* times_ms);

@@ -11,15 +11,18 @@ The momentum draw p = G^{1/2} z = Psi diag(sqrt g) Psi' z (z ~ N(0, I))
 realises N(0, G) with the symmetric square root, which depends on G alone
 (an eigenvector-based draw Psi diag(sqrt g) z would depend on the signs and
 in-cluster rotation of the computed eigenvectors).
-The normals z and uniforms r are inputs, drawn by the shared seeded input
-generator, so the GPU chain and this reference consume identical randomness.
-A failure inside a trajectory (non-finite value, non-positive-definite K)
-counts as a rejection.
+The normals z and uniforms r of ``run_chain`` are inputs; ``run_seeded_chain``
+derives them from (seed, stream_id) with the counter-based generator of
+``oracle.rng``, as the device chain does, so both consume identical
+randomness.  Algorithm 1 runs A moves and returns the positions after moves
+A0 .. A-1 (its burn-in A0).  A failure inside a trajectory (non-finite
+value, non-positive-definite K) counts as a rejection.
 """
 from __future__ import annotations
 
 import numpy as np
 
+from . import rng
 from .hamiltonian import State, hamiltonian
 from .integrator import glf_step
 
@@ -60,3 +63,18 @@ def run_chain(target, q0, eps, n_leapfrog, n_fixed_point, alpha, z, u):
         samples[ell] = st.q
         logpost[ell] = -st.U
     return samples, logpost, accepted, h_old, h_new
+
+
+def run_seeded_chain(target, q0, eps, n_leapfrog, n_fixed_point, alpha, n_moves, n_burnin,
+                     seed, stream_id):
+    """Algorithm 1 with A = n_moves moves, of which the first A0 = n_burnin are
+    burn-in, and the randomness of (seed, stream_id).  Returns the kept
+    samples, log posteriors and accept flags (moves A0 .. A-1) and, for all A
+    moves, the accept flags and H_old / H_new."""
+    if not 0 <= n_burnin < n_moves:
+        raise ValueError("need 0 <= n_burnin < n_moves")
+    z, u = rng.chain_randoms(seed, stream_id, n_moves, target.D)
+    samples, logpost, accepted, h_old, h_new = run_chain(target, q0, eps, n_leapfrog,
+                                                         n_fixed_point, alpha, z, u)
+    k = slice(n_burnin, n_moves)
+    return samples[k], logpost[k], accepted[k], accepted, h_old, h_new

@@ -28,16 +28,15 @@ LOG2PI = math.log(2.0 * math.pi)
 class GPTarget:
     """The latent-GP posterior as a sampling target."""
 
-    def __init__(self, spec, operand_round=None):
+    def __init__(self, spec):
         self.spec = spec
         self.D = spec.D
-        self.operand_round = operand_round   # rounding model of A_l, B_l (None: exact)
 
     def derivs(self, q):
-        return model.hessian(self.spec, q, self.operand_round)
+        return model.hessian(self.spec, q)
 
     def contract(self, q, W):
-        return model.contract(self.spec, q, W, self.operand_round)
+        return model.contract(self.spec, q, W)
 
 
 class State:

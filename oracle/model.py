@@ -210,27 +210,13 @@ def gradient(spec, q):
     return g
 
 
-def _products_rounding(operand_round):
-    """A_l = K^-1 K_l (and B_l = A_l K^-1) with an optional rounding model.
-
-    operand_round=None is exact FP64.  A callable r (for instance rounding to
-    float32) is applied to both operands and to the product, which models a
-    product computed from stored low-precision copies; it only serves to
-    measure how sensitive a result is to that rounding."""
-    if operand_round is None:
-        return lambda X, Y: X @ Y
-    r = operand_round
-    return lambda X, Y: r(r(X) @ r(Y))
-
-
-def hessian(spec, q, operand_round=None):
+def hessian(spec, q):
     """U, grad U and the Hessian H of U at q.
 
     H_ff = beta diag(l'') + K^-1
     H_fl = -A_l alpha
     H_lm = a'K_l A_m a - 1/2 a'K_lm a + 1/2 tr(K^-1 K_lm) - 1/2 tr(A_l A_m) + delta_lm
     """
-    mul = _products_rounding(operand_round)
     N, P = spec.N, spec.P
     f, eta = q[:N], q[N:]
     K = gram(spec, eta)
@@ -238,7 +224,7 @@ def hessian(spec, q, operand_round=None):
     a = Kinv @ f
     kd = KernelDerivs(spec, eta)
     Kl = [kd.d((l,)) for l in range(P)]
-    A = [mul(Kinv, Kl[l]) for l in range(P)]
+    A = [Kinv @ Kl[l] for l in range(P)]
     l0, l1, l2, _ = lik_terms(spec, f)
     dt = np.result_type(q, np.float64)
     H = np.zeros((N + P, N + P), dtype=dt)
@@ -271,7 +257,7 @@ def hessian(spec, q, operand_round=None):
 # Third-derivative contraction (Sec. 2.3)
 # --------------------------------------------------------------------------
 
-def contract(spec, q, W, operand_round=None):
+def contract(spec, q, W):
     """v(W)_i = tr(W dH/dq_i) for a fixed symmetric W, without forming dH/dq.
 
     Sec. 2.3 orders the computation of tr(W_s dH/dq) by model structure so the
@@ -286,7 +272,6 @@ def contract(spec, q, W, operand_round=None):
           + sum_lm W_lm dH_lm/d eta_n
     """
     N, P = spec.N, spec.P
-    mul = _products_rounding(operand_round)
     f, eta = q[:N], q[N:]
     W = 0.5 * (W + W.T)
     Wff, w, Wee = W[:N, :N], W[:N, N:], W[N:, N:]
@@ -296,8 +281,8 @@ def contract(spec, q, W, operand_round=None):
     kd = KernelDerivs(spec, eta)
     K1 = [kd.d((l,)) for l in range(P)]
     K2 = [[kd.d((l, m)) for m in range(P)] for l in range(P)]
-    A = [mul(Kinv, K1[l]) for l in range(P)]
-    B = [mul(A[l], Kinv) for l in range(P)]        # K^-1 K_l K^-1
+    A = [Kinv @ K1[l] for l in range(P)]
+    B = [A[l] @ Kinv for l in range(P)]            # K^-1 K_l K^-1
     am = [A[m] @ a for m in range(P)]
     kl = [K1[l] @ a for l in range(P)]
     zero = np.zeros(N)

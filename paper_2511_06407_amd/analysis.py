@@ -18,7 +18,9 @@ def ess(x):
     non-positive pair and made monotone."""
     x = np.asarray(x, dtype=np.float64)
     n = x.size
-    if n < 4 or np.var(x) == 0.0:
+    if np.var(x) == 0.0:
+        return 0.0          # a chain that never moved carries no information
+    if n < 4:
         return float(n)
     rho = autocorr(x)
     pairs = rho[: (n // 2) * 2].reshape(-1, 2).sum(axis=1)

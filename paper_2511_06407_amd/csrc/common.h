@@ -64,6 +64,11 @@ struct Gemm {
   const T* const* Bp = nullptr;
   T* const* Cp = nullptr;
   T* const* C2p = nullptr;
+  // Copies of the result in the other precision (float for a double GEMM,
+  // double for a float one), written by the same epilogue: Co in C's layout
+  // (ldc, stride sCo), C2o transposed (ldc2, stride sC2o).
+  void* Co = nullptr; long sCo = 0;
+  void* C2o = nullptr; long sC2o = 0;
 };
 
 void gemm(const Gemm<double>& g, hipStream_t st);
@@ -113,6 +118,7 @@ void chol_inverse(int n, const double* K, double* Kinv, double* logdet, CholWork
                   double* redwork, hipStream_t st);
 
 void fill(double* x, long n, double v, hipStream_t st);
+void fill_int(int* x, long n, int v, hipStream_t st);
 void copy(double* dst, const double* src, long n, hipStream_t st);
 // y = a*x + b*y (vectors)
 void axpby(long n, double a, const double* x, double b, double* y, hipStream_t st);

@@ -10,9 +10,10 @@ struct EigWork {
   double* Psi = nullptr;   // Dp x Dp eigenvectors (columns), identity-padded
   double* V = nullptr;     // per-slot 32 x 32 rotations, two sets (eig_rotation_doubles)
   double* part = nullptr;  // reduction partials
-  double* ctrl = nullptr;  // device: ||M||_F, converged, ratio, checks
+  double* ctrl = nullptr;  // device control block (EIG_CTRL_DOUBLES): norm, stop flag, counts
   double* ctrl_host = nullptr;  // pinned host mirror of ctrl
 };
+constexpr int EIG_CTRL_DOUBLES = 16;
 
 int eig_padded_dim(int D);
 void eig_workspace_sizes(int D, long* doubles);
@@ -31,8 +32,22 @@ constexpr int JACOBI_INNER_DYNAMIC = 1;
 // rotations, one per slot (double-buffered across rounds).
 inline long eig_rotation_doubles(int Dp) { return 2L * (Dp / 32) * 32 * 32; }
 
-void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, int* sweeps_out,
-                hipStream_t st);
+// Result of a solve, known on the host only when it checked convergence.
+struct JacobiResult {
+  int sweeps = -1;          // sweeps applied (-1: not read back)
+  bool converged = true;    // false: max_sweeps ran out (or non-finite entries)
+  bool nonfinite = false;
+};
+// Sweeps are launched `blind` at a time without the host looking: every
+// launch first reads a stop flag that the convergence check after each sweep
+// sets on the device, so sweeps launched past convergence exit at once.  With
+// host_check the host then reads the flag after each further sweep until it
+// is set or max_sweeps have run; without it (graph capture) exactly
+// max(blind, 1) sweeps are launched and nothing is read back.  On the device:
+// *fail |= 4 if the solve did not converge, 8 if it met non-finite entries
+// (fail may be null); dstats[0] += 1, dstats[1] += sweeps (may be null).
+JacobiResult jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, int blind,
+                        bool host_check, int* fail, double* dstats, hipStream_t st);
 // Rayleigh quotients lam_i = psi_i' H psi_i of the converged basis against the
 // original H (D x D, ldh), written to diag(w.M); Z is Dp x Dp scratch.
 // One Newton-Schulz step Psi <- Psi (3I - Psi'Psi) / 2 on the D x D block of

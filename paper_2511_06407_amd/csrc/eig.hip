@@ -536,9 +536,11 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(int Dp, int apply_rou
                                                            int ntri, int npsi,
                                                            double* __restrict__ Psi) {
   const int b = blockIdx.x;
+  // ctrl[1]: stop flag, set by the convergence check after a sweep and
+  // constant within one; every part of a launch of a stopped solve exits
+  // (sweeps launched ahead of the check cost only their launch)
+  if (ctrl[1] != 0.0) return;
   if (b < nsolve) {
-    // ctrl[1]: converged flag (uniform over the workgroup)
-    if (ctrl[1] != 0.0) return;
     if (apply_round < 0)
       jacobi_solve_block(Dp, 0, b, Min, nullptr, Vnew, MAX_INNER);
     else
@@ -563,9 +565,11 @@ constexpr int OFF_COLS = 8;   // columns per workgroup of the convergence check
 constexpr int OFF_MAXDP = 4096;
 
 __global__ __launch_bounds__(256) void offnorm_kernel(int Dp, const double* __restrict__ M,
-                                                      double* __restrict__ part) {
+                                                      double* __restrict__ part,
+                                                      const double* __restrict__ ctrl) {
   __shared__ double sh[3][4];
   __shared__ double rdg[OFF_MAXDP];   // 1 / sqrt|m_ii| (inf for a zero diagonal)
+  if (ctrl[1] != 0.0) return;
   for (int i = threadIdx.x; i < Dp; i += 256) {
     const double d = fabs(M[i + (long)i * Dp]);
     rdg[i] = d > 0.0 ? rsqrt(d) : INFINITY;
@@ -602,16 +606,23 @@ __global__ __launch_bounds__(256) void offnorm_kernel(int Dp, const double* __re
   }
 }
 
-// ctrl[0] = ||M||_F (set on the first check), ctrl[1] = converged flag,
-// ctrl[2] = last off/||M|| ratio, ctrl[3] = number of checks, ctrl[4] = 1 if
-// the norm-wise test already held at the previous check.
+// Control block of one solve (doubles):
+//   [0] ||M||_F (set on the first check)     [1] stop flag (converged or non-finite)
+//   [2] last off/||M|| ratio                  [3] checks made
+//   [4] the norm-wise test held at the previous check
+//   [5] non-finite entries found              [6] buffer holding M when stopped (0: M, 1: M2)
+//   [7] sweeps applied before the stop
 // Converged: off(M)_F <= zeta ||M||_F (the stated tolerance) and either every
 // off-diagonal is below 1e-12 of the geometric mean of its diagonals or the
 // norm-wise test also held one sweep earlier (one polishing sweep at most).
+// A non-finite norm stops the solve without convergence.
+constexpr int CTRL_N = 16;
+
 __global__ void offnorm_finish_kernel(int nparts, const double* __restrict__ part, double zeta,
-                                      double* __restrict__ ctrl, int first) {
+                                      double* __restrict__ ctrl, int first, int cur_buf) {
   // One wave: lanes take every 64th partial, then a shuffle tree combines
   // the lane sums and maxima in a fixed order.
+  if (ctrl[1] != 0.0) return;
   const int lane = threadIdx.x;
   double off = 0.0, tot = 0.0, rel = 0.0;
   for (int p = lane; p < nparts; p += 64) {
@@ -626,14 +637,51 @@ __global__ void offnorm_finish_kernel(int nparts, const double* __restrict__ par
   }
   if (lane != 0) return;
   const double nrm = sqrt(tot);
+  const double sweeps = ctrl[3];   // checks before this one = sweeps applied
+  ctrl[3] = sweeps + 1.0;
+  ctrl[6] = (double)cur_buf;
+  ctrl[7] = sweeps;
+  if (!isfinite(nrm) || !isfinite(off)) {
+    ctrl[5] = 1.0;
+    ctrl[1] = 1.0;
+    return;
+  }
   if (first) ctrl[0] = nrm;
   const double r = nrm > 0.0 ? sqrt(off) / nrm : 0.0;
   ctrl[2] = r;
-  ctrl[3] += 1.0;
   const bool normwise = sqrt(off) <= zeta * nrm || !(nrm > 0.0);
   const bool done = normwise && (rel <= 1e-12 || off == 0.0 || ctrl[4] != 0.0);
   ctrl[4] = normwise ? 1.0 : 0.0;
   ctrl[1] = done ? 1.0 : 0.0;
+}
+
+// After the last sweep: keep the converged matrix in M (copy it from M2 when
+// the stop came there), tally the sweeps and flag a solve that did not
+// converge.  fail |= 4 (no convergence) or 8 (non-finite); stats[0] counts
+// solves and stats[1] their sweeps.  One workgroup per 256 x 16 chunk.
+__global__ __launch_bounds__(256) void jacobi_collect_kernel(long n, double* __restrict__ M,
+                                                             const double* __restrict__ M2,
+                                                             const double* __restrict__ ctrl,
+                                                             int last_buf, int* __restrict__ fail,
+                                                             double* __restrict__ stats) {
+  const bool stopped = ctrl[1] != 0.0;
+  const int buf = stopped ? (int)ctrl[6] : last_buf;
+  if (buf == 1) {
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+      M[i] = M2[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const bool nonfinite = ctrl[5] != 0.0;
+    if (fail && (!stopped || nonfinite)) *fail |= nonfinite ? 8 : 4;
+    if (stats) {
+      stats[0] += 1.0;
+      stats[1] += stopped ? ctrl[7] : ctrl[3] - 1.0;
+    }
+  }
+}
+
+__global__ void fill_ctrl_kernel(double* __restrict__ ctrl) {
+  if (threadIdx.x < CTRL_N) ctrl[threadIdx.x] = 0.0;
 }
 
 // ------------------------------------------------------------ softabs g, g'
@@ -808,7 +856,7 @@ void eig_workspace_sizes(int D, long* doubles) {
   const int Dp = eig_padded_dim(D);
   const int nb = Dp / JHB;
   // M, M2, Psi; two rotation sets (double-buffered); convergence partials; ctrl
-  *doubles = 3L * Dp * Dp + 2L * (nb / 2) * JSB * JSB + 3L * (Dp / OFF_COLS + 1) + 8;
+  *doubles = 3L * Dp * Dp + 2L * (nb / 2) * JSB * JSB + 3L * (Dp / OFF_COLS + 1) + CTRL_N;
 }
 
 // Unused dynamic LDS reserved by the update-and-solve launches: it lifts a
@@ -818,49 +866,45 @@ void eig_workspace_sizes(int D, long* doubles) {
 // the chain (measured: 1.5 us of a 29.9 us launch at Dp = 1088).
 constexpr int ROUND_LDS_RESERVE = 12288;
 
-void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, int* sweeps_out,
-                hipStream_t st) {
+JacobiResult jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, int blind,
+                        bool host_check, int* fail, double* dstats, hipStream_t st) {
   // Input: w.M (Dp x Dp symmetric, padded) and w.Psi (Dp x Dp, padded with identity).
   const int Dp = eig_padded_dim(D);
   const int nb = Dp / JHB, ns = nb / 2;
   RM_REQUIRE(Dp % JSB == 0 && nb % 2 == 0, "softabs_eig: padded dimension does not fit the blocks");
   RM_REQUIRE(Dp <= OFF_MAXDP, "softabs_eig: dimension too large for the convergence check");
+  RM_REQUIRE(max_inner == JACOBI_INNER_DYNAMIC || max_inner == JACOBI_INNER_STATIC,
+             "softabs_eig: unsupported number of inner sweeps");
   const int nparts = Dp / OFF_COLS;
-  double* Min = w.M;
-  double* Mout = w.M2;
-  RM_HIP(hipMemsetAsync(w.ctrl, 0, 8 * sizeof(double), st));
-  hipLaunchKernelGGL(offnorm_kernel, dim3(nparts), dim3(256), 0, st, Dp, (const double*)Min, w.part);
+  double* Mb[2] = {w.M, w.M2};
+  int cur = 0;   // buffer holding the current M
+  hipLaunchKernelGGL(fill_ctrl_kernel, dim3(1), dim3(64), 0, st, w.ctrl);
   RM_CHECK_LAUNCH();
-  hipLaunchKernelGGL(offnorm_finish_kernel, dim3(1), dim3(64), 0, st, nparts, (const double*)w.part,
-                     zeta, w.ctrl, 1);
-  RM_CHECK_LAUNCH();
-  int sw = 0;
-  bool conv = false;
-  for (;;) {
-    RM_HIP(hipMemcpyAsync(w.ctrl_host, w.ctrl, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-    RM_HIP(hipStreamSynchronize(st));
-    if (!std::isfinite(w.ctrl_host[0]))
-      throw Error(RMHMC_E_NONFINITE, "softabs_eig: non-finite entries in the matrix");
-    if (w.ctrl_host[1] != 0.0) { conv = true; break; }
-    if (sw >= max_sweeps) break;
+  auto check = [&](int first) {
+    hipLaunchKernelGGL(offnorm_kernel, dim3(nparts), dim3(256), 0, st, Dp, (const double*)Mb[cur],
+                       w.part, (const double*)w.ctrl);
+    RM_CHECK_LAUNCH();
+    hipLaunchKernelGGL(offnorm_finish_kernel, dim3(1), dim3(64), 0, st, nparts,
+                       (const double*)w.part, zeta, w.ctrl, first, cur);
+    RM_CHECK_LAUNCH();
+  };
+  const int ntri = ns * (ns + 1) / 2;
+  const int npsi = (Dp / JSB) * ns;
+  double* Vb[2] = {w.V, w.V + (long)ns * JSB * JSB};
+  const double solve_flops = (double)ns * (JSB - 1) * (JHB * JHB * 24.0 + JSB * JHB * 6.0);
+  const double compose_flops = (double)ns * 3.0 * (2.0 * JSB * JSB * JHB + 2.0 * JHB * JSB * JHB);
+  const double sb3 = (double)JSB * JSB * JSB;
+  const double vset = (double)ns * JSB * JSB * sizeof(double);
+  const double tile = (double)JSB * JSB * sizeof(double);
+  auto round_kernel = max_inner == JACOBI_INNER_DYNAMIC ? jacobi_round_kernel<JACOBI_INNER_DYNAMIC>
+                                                        : jacobi_round_kernel<JACOBI_INNER_STATIC>;
+  auto sweep = [&]() {
     // launch 0 solves round 0 from M; launch r + 1 applies round r to M and
     // Psi and solves round r + 1 from M_r and V_r
-    const int ntri = ns * (ns + 1) / 2;
-    const int npsi = (Dp / JSB) * ns;
-    double* Vb[2] = {w.V, w.V + (long)ns * JSB * JSB};
-    const double solve_flops = (double)ns * (JSB - 1) * (JHB * JHB * 24.0 + JSB * JHB * 6.0);
-    const double compose_flops = (double)ns * 3.0 * (2.0 * JSB * JSB * JHB + 2.0 * JHB * JSB * JHB);
-    const double sb3 = (double)JSB * JSB * JSB;
-    const double vset = (double)ns * JSB * JSB * sizeof(double);
-    const double tile = (double)JSB * JSB * sizeof(double);
-    RM_REQUIRE(max_inner == JACOBI_INNER_DYNAMIC || max_inner == JACOBI_INNER_STATIC,
-               "softabs_eig: unsupported number of inner sweeps");
-    auto round_kernel = max_inner == JACOBI_INNER_DYNAMIC
-                            ? jacobi_round_kernel<JACOBI_INNER_DYNAMIC>
-                            : jacobi_round_kernel<JACOBI_INNER_STATIC>;
     int slot = timing_begin(TK_JACOBI_SOLVE, st);
-    hipLaunchKernelGGL(round_kernel, dim3(ns), dim3(256), 0, st, Dp, -1, ns, (const double*)Min,
-                       Mout, (const double*)nullptr, Vb[0], (const double*)w.ctrl, 0, 0, w.Psi);
+    hipLaunchKernelGGL(round_kernel, dim3(ns), dim3(256), 0, st, Dp, -1, ns,
+                       (const double*)Mb[cur], Mb[cur ^ 1], (const double*)nullptr, Vb[0],
+                       (const double*)w.ctrl, 0, 0, w.Psi);
     RM_CHECK_LAUNCH();
     // algorithmic bytes: subproblems read, rotations written
     timing_end(slot, st, solve_flops, 2.0 * vset);
@@ -869,8 +913,9 @@ void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, i
       const int nsolve = more ? ns : 0;
       slot = timing_begin(TK_JACOBI_SOLVE, st);
       hipLaunchKernelGGL(round_kernel, dim3(nsolve + cdiv(ntri, 4) + cdiv(npsi, 4)), dim3(256),
-                         ROUND_LDS_RESERVE, st, Dp, r, nsolve, (const double*)Min, Mout, (const double*)Vb[r & 1],
-                         Vb[(r + 1) & 1], (const double*)w.ctrl, ntri, npsi, w.Psi);
+                         ROUND_LDS_RESERVE, st, Dp, r, nsolve, (const double*)Mb[cur], Mb[cur ^ 1],
+                         (const double*)Vb[r & 1], Vb[(r + 1) & 1], (const double*)w.ctrl, ntri,
+                         npsi, w.Psi);
       RM_CHECK_LAUNCH();
       // algorithmic work: M update (upper tiles read, all of M written), Psi
       // read and written, rotations V_r read once; solves: three tiles of
@@ -879,21 +924,34 @@ void jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, i
                  4.0 * sb3 * ntri + 2.0 * sb3 * npsi + (more ? solve_flops + compose_flops : 0.0),
                  (double)ntri * tile + 3.0 * (double)Dp * Dp * sizeof(double) + vset +
                      (more ? 3.0 * ns * tile + vset : 0.0));
-      std::swap(Min, Mout);
+      cur ^= 1;
     }
-    ++sw;
-    hipLaunchKernelGGL(offnorm_kernel, dim3(nparts), dim3(256), 0, st, Dp, (const double*)Min, w.part);
-    RM_CHECK_LAUNCH();
-    hipLaunchKernelGGL(offnorm_finish_kernel, dim3(1), dim3(64), 0, st, nparts,
-                       (const double*)w.part, zeta, w.ctrl, 0);
-    RM_CHECK_LAUNCH();
+    check(0);
+  };
+  check(1);
+  JacobiResult res;
+  int launched = 0;
+  // sweeps launched before the host first looks (all of them without host checks)
+  const int ahead = std::min(max_sweeps, host_check ? std::max(blind, 0) : std::max(blind, 1));
+  for (; launched < ahead; ++launched) sweep();
+  if (host_check) {
+    for (;;) {
+      RM_HIP(hipMemcpyAsync(w.ctrl_host, w.ctrl, CTRL_N * sizeof(double), hipMemcpyDeviceToHost, st));
+      RM_HIP(hipStreamSynchronize(st));
+      if (w.ctrl_host[1] != 0.0 || launched >= max_sweeps) break;
+      sweep();
+      ++launched;
+    }
+    res.nonfinite = w.ctrl_host[5] != 0.0;
+    res.converged = w.ctrl_host[1] != 0.0 && !res.nonfinite;
+    res.sweeps = w.ctrl_host[1] != 0.0 ? (int)w.ctrl_host[7] : launched;
   }
-  if (Min != w.M) {
-    // keep the converged matrix in w.M
-    RM_HIP(hipMemcpyAsync(w.M, Min, (size_t)Dp * Dp * sizeof(double), hipMemcpyDeviceToDevice, st));
-  }
-  if (sweeps_out) *sweeps_out = sw;
-  if (!conv) throw Error(RMHMC_E_EIG_NOCONV, "softabs_eig: Jacobi did not converge");
+  const long n = (long)Dp * Dp;
+  hipLaunchKernelGGL(jacobi_collect_kernel, dim3((unsigned)std::min<long>(cdiv(n, 256 * 16), 1024)),
+                     dim3(256), 0, st, n, w.M, (const double*)w.M2, (const double*)w.ctrl, cur,
+                     fail, dstats);
+  RM_CHECK_LAUNCH();
+  return res;
 }
 
 namespace {

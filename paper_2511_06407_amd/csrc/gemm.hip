@@ -35,8 +35,15 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
+template <typename T> struct OtherPrec;
+template <> struct OtherPrec<double> { typedef float type; };
+template <> struct OtherPrec<float> { typedef double type; };
+
 template <typename T>
 struct Params {
+  typedef typename OtherPrec<T>::type OT;
+  OT* Co; long sCo;     // result in the other precision, C's layout
+  OT* C2o; long sC2o;   // and transposed (ldc2)
   int m, n, k;
   T alpha, beta;
   const T* A; long lda; long sA;
@@ -175,8 +182,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
         }
     return;
   }
+  typedef typename OtherPrec<T>::type OT;
   T* C = p.Cp ? p.Cp[batch] : (p.C ? p.C + (long)batch * p.sC : nullptr);
   T* C2 = p.C2p ? p.C2p[batch] : (p.C2 ? p.C2 + (long)batch * p.sC2 : nullptr);
+  OT* Co = p.Co ? p.Co + (long)batch * p.sCo : nullptr;
+  OT* C2o = p.C2o ? p.C2o + (long)batch * p.sC2o : nullptr;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -193,6 +203,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
             *c = v;
           }
           if (C2) C2[gn + (long)gm * p.ldc2] = v;
+          if (Co) Co[gm + (long)gn * p.ldc] = (OT)v;
+          if (C2o) C2o[gn + (long)gm * p.ldc2] = (OT)v;
         }
       }
 }
@@ -262,6 +274,9 @@ void gemm_impl(const Gemm<T>& g, hipStream_t st) {
   p.C = g.C; p.ldc = g.ldc; p.sC = g.sC;
   p.C2 = g.C2; p.ldc2 = g.ldc2; p.sC2 = g.sC2;
   p.Ap = g.Ap; p.Bp = g.Bp; p.Cp = g.Cp; p.C2p = g.C2p;
+  p.Co = static_cast<typename Params<T>::OT*>(g.Co); p.sCo = g.sCo;
+  p.C2o = static_cast<typename Params<T>::OT*>(g.C2o); p.sC2o = g.sC2o;
+  RM_REQUIRE(!(g.Co || g.C2o) || (!g.Cp && !g.C2p), "gemm: other-precision copies need strided C");
   p.ksplit = 1; p.kchunk = g.k > 0 ? g.k : 1; p.part = nullptr;
   launch(p, g.tA, g.tB, g.batch, st);
 }
@@ -293,7 +308,7 @@ void tallk_impl(int m, int n, long k, const T* A, long lda, const T* B, long ldb
 // waves in flight, and a second pass adds them in order.
 void gemm_splitk_impl(const Gemm<double>& g, double* work, int splits, hipStream_t st) {
   const bool plain = g.batch == 1 && g.alpha == 1.0 && g.beta == 0.0 && !g.C2 && !g.C2p &&
-                     !g.Ap && !g.Bp && !g.Cp && g.C && work;
+                     !g.Ap && !g.Bp && !g.Cp && !g.Co && !g.C2o && g.C && work;
   if (!plain || splits <= 1 || g.k < 2 * BK * splits) {
     gemm_impl(g, st);
     return;

@@ -289,9 +289,7 @@ void kd_wsum(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
   for (int t0 = 0; t0 < nt; t0 += MAX_TUPLES) {
     const int c = std::min(MAX_TUPLES, nt - t0);
     kd_wsum_chunk(md, eta, tuples + t0, c, mode, Kinv, alpha, Wstack, nw, tmp, work, st);
-    for (int w = 0; w < nw; ++w)
-      RM_HIP(hipMemcpyAsync(out + (long)w * nt + t0, tmp + (long)w * c, c * sizeof(double),
-                            hipMemcpyDeviceToDevice, st));
+    for (int w = 0; w < nw; ++w) copy(out + (long)w * nt + t0, tmp + (long)w * c, c, st);
   }
 }
 

@@ -309,6 +309,10 @@ __global__ void fill_kernel(double* x, long n, double v) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;
 }
+__global__ void fill_int_kernel(int* x, long n, int v) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
 __global__ void copy_kernel(double* d, const double* s, long n) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = s[i];
@@ -406,9 +410,9 @@ void multi_dot(int m, int n, const double* A, long lda, const double* B, long ld
 void chol_inverse(int n, const double* K, double* Kinv, double* logdet, CholWork& w,
                   double* redwork, hipStream_t st) {
   const long nn = (long)n * n;
-  RM_HIP(hipMemcpyAsync(w.L, K, nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+  copy(w.L, K, nn, st);
   fill(w.Linv, nn, 0.0, st);
-  RM_HIP(hipMemsetAsync(w.info, 0, sizeof(int), st));
+  fill_int(w.info, 1, 0, st);
   const int nb = cdiv(n, CB);
   for (int kb = 0; kb < nb; ++kb) {
     const int k0 = kb * CB, bw = std::min(CB, n - k0), r0 = k0 + bw, rm = n - r0;
@@ -466,6 +470,11 @@ void chol_inverse(int n, const double* K, double* Kinv, double* logdet, CholWork
 void fill(double* x, long n, double v, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(fill_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, x, n, v);
+  RM_CHECK_LAUNCH();
+}
+void fill_int(int* x, long n, int v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_int_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, x, n, v);
   RM_CHECK_LAUNCH();
 }
 void copy(double* dst, const double* src, long n, hipStream_t st) {

@@ -43,10 +43,12 @@ const double kLog2Pi = 1.8378770664093453;
 struct Pool {
   std::vector<void*> ptrs;
   std::vector<void*> host;
+  size_t bytes = 0;   // device bytes held
   template <class T>
   T* alloc(size_t n) {
     void* p = nullptr;
     if (n == 0) n = 1;
+    bytes += n * sizeof(T);
     hipError_t e = hipMalloc(&p, n * sizeof(T));
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -221,15 +223,165 @@ __global__ void ham_kernel(int D, const double* __restrict__ c, const double* __
     out[0] = U[0] + 0.5 * logdetG[0] + 0.5 * (sh[0] + sh[1] + sh[2] + sh[3]) + 0.5 * D * kLog2Pi;
 }
 
+// ------------------------------------------------------------ chain randomness
+// Philox4x64-10 (Salmon et al., SC 2011): ten rounds of two 64 x 64 -> 128-bit
+// products of counter words 0 and 2 by fixed odd multipliers, the high halves
+// mixed with the other counter words and the key, the key bumped by two Weyl
+// constants between rounds.  key = (seed, stream_id); counter = (block j,
+// move, purpose, 0), purpose 0 for the momentum normals and 1 for the
+// Metropolis-Hastings uniform of the move.
+struct Philox4 {
+  unsigned long long w[4];
+};
+__device__ __forceinline__ Philox4 philox4x64(unsigned long long c0, unsigned long long c1,
+                                              unsigned long long c2, unsigned long long c3,
+                                              unsigned long long k0, unsigned long long k1) {
+  const unsigned long long M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const unsigned long long W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const unsigned long long hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    const unsigned long long hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    const unsigned long long n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  return Philox4{{c0, c1, c2, c3}};
+}
+
+// (0, 1) uniform from the top 53 bits of a word.
+__device__ __forceinline__ double uniform53(unsigned long long w) {
+  return ((double)(w >> 11) + 0.5) * 0x1.0p-53;
+}
+
+// z[4j .. 4j+3] from block j: two Box-Muller pairs from words (0, 1), (2, 3).
+__global__ void normals_kernel(int D, unsigned long long seed, unsigned long long stream,
+                               unsigned long long move, double* __restrict__ z) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (4 * j >= D) return;
+  const Philox4 r = philox4x64((unsigned long long)j, move, 0ull, 0ull, seed, stream);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const double u0 = uniform53(r.w[2 * h]), u1 = uniform53(r.w[2 * h + 1]);
+    const double rad = sqrt(-2.0 * log(u0));
+    const double t = (2.0 * M_PI) * u1;
+    const int i = 4 * j + 2 * h;
+    if (i < D) z[i] = rad * cos(t);
+    if (i + 1 < D) z[i + 1] = rad * sin(t);
+  }
+}
+
+// The Metropolis-Hastings uniform of a move (word 0 of block 0, purpose 1).
+__global__ void uniform_kernel(unsigned long long seed, unsigned long long stream,
+                               unsigned long long move, double* __restrict__ u) {
+  if (threadIdx.x == 0) u[0] = uniform53(philox4x64(0ull, move, 1ull, 0ull, seed, stream).w[0]);
+}
+
+// Device statistics of a state (doubles).
+enum {
+  ST_EIG = 0, ST_SWEEPS = 1, ST_ACC = 2, ST_FAIL = 3, ST_NOTPD = 4, ST_NONFINITE = 5, ST_NOCONV = 6,
+  ST_RESP = 8, ST_RESQ = 9, ST_ACC_KEPT = 11, ST_N = 16
+};
+// Failure bits of a move (device int): 1 K not positive definite, 4 an
+// eigensolve did not converge, 8 non-finite values met.
+enum { FAIL_NOT_PD = 1, FAIL_NOCONV = 4, FAIL_NONFINITE = 8 };
+
+// Metropolis-Hastings test of Algorithm 1 (accept iff log r < H_old - H_new;
+// the printed algorithm restores q on this event instead): a failed or
+// non-finite move is a rejection.  acc[0] = decision; kept_acc (nullable) =
+// the decision in the output of a kept move; the failure word is cleared for
+// the next move.
+__global__ void mh_kernel(unsigned long long seed, unsigned long long stream,
+                          unsigned long long move, const double* __restrict__ ham,
+                          int* __restrict__ fail, int* __restrict__ acc,
+                          double* __restrict__ stats, int* __restrict__ kept_acc) {
+  if (threadIdx.x != 0) return;
+  const double u = uniform53(philox4x64(0ull, move, 1ull, 0ull, seed, stream).w[0]);
+  const int f = *fail;
+  const double h0 = ham[0], h1 = ham[1];
+  const bool finite = isfinite(h0) && isfinite(h1);
+  const bool ok = f == 0 && finite;
+  const bool a = ok && log(u) < h0 - h1;
+  acc[0] = a ? 1 : 0;
+  stats[ST_ACC] += a ? 1.0 : 0.0;
+  if (!ok) {
+    stats[ST_FAIL] += 1.0;
+    if (f & FAIL_NOT_PD) stats[ST_NOTPD] += 1.0;
+    if ((f & FAIL_NONFINITE) || (!finite && !(f & FAIL_NOT_PD))) stats[ST_NONFINITE] += 1.0;
+    if (f & FAIL_NOCONV) stats[ST_NOCONV] += 1.0;
+  }
+  if (kept_acc) {
+    kept_acc[0] = a ? 1 : 0;
+    stats[ST_ACC_KEPT] += a ? 1.0 : 0.0;
+  }
+  *fail = 0;
+}
+
+// dst <- src over n 16-byte words when *flag is set (an accepted move's end
+// point becomes the start point of the next move).
+__global__ __launch_bounds__(256) void copy_if_kernel(long n, double2* __restrict__ dst,
+                                                      const double2* __restrict__ src,
+                                                      const int* __restrict__ flag) {
+  if (*flag == 0) return;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+    dst[i] = src[i];
+}
+
 __global__ void store_sample_kernel(int D, const double* __restrict__ q, const double* __restrict__ U,
-                                    double* __restrict__ sample, double* __restrict__ logpost,
-                                    int* __restrict__ acc, int accepted) {
+                                    double* __restrict__ sample, double* __restrict__ logpost) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < D) sample[i] = q[i];
-  if (i == 0) {
-    logpost[0] = -U[0];
-    acc[0] = accepted;
+  if (i == 0) logpost[0] = -U[0];
+}
+
+// One fixed-point update dst <- base + c1 x + c2 y of the implicit leapfrog
+// equations; when `res` is given, res = max(res, ||new - old|| / ||new||)
+// (the relative residual of the iteration).  One workgroup.
+__global__ __launch_bounds__(1024) void fp_update_kernel(int n, const double* __restrict__ base,
+                                                         double c1, const double* __restrict__ x,
+                                                         double c2, const double* __restrict__ y,
+                                                         double* __restrict__ dst,
+                                                         double* __restrict__ res) {
+  __shared__ double sh[2][16];
+  double d2 = 0.0, n2 = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    const double v = base[i] + c1 * x[i] + c2 * y[i];
+    const double d = v - dst[i];
+    d2 += d * d;
+    n2 += v * v;
+    dst[i] = v;
   }
+  if (!res) return;
+  for (int o = 32; o > 0; o >>= 1) {
+    d2 += __shfl_xor(d2, o, 64);
+    n2 += __shfl_xor(n2, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][w] = d2;
+    sh[1][w] = n2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < 16; ++k) {
+      a += sh[0][k];
+      b += sh[1][k];
+    }
+    const double r = b > 0.0 ? sqrt(a / b) : sqrt(a);
+    if (!(r <= res[0])) res[0] = r;   // a NaN residual is kept
+  }
+}
+
+// fail |= bit when the Cholesky flag is set.
+__global__ void fold_flag_kernel(const int* __restrict__ info, int* __restrict__ fail, int bit) {
+  if (threadIdx.x == 0 && *info != 0) *fail |= bit;
+}
+__global__ void or_flag_kernel(int* __restrict__ fail, int bit) {
+  if (threadIdx.x == 0) *fail |= bit;
 }
 
 __global__ void any_nonfinite_kernel(long n, const double* __restrict__ x, int* __restrict__ flag) {
@@ -245,6 +397,19 @@ __global__ void any_nonfinite_kernel(long n, const double* __restrict__ x, int* 
 // k-range layers for the single Dp x Dp warm-start products: 17 x 17 tiles
 // at Dp = 1088 become 1156 workgroups, about four per CU.
 constexpr int GSPLIT = 4;
+
+// How an eigendecomposition is driven: host_check reads the stop flag after
+// each sweep past the first `blind` (single calls and the chain); without it
+// exactly `blind` sweeps are launched with nothing read back (graph capture).
+// fail / dstats: the state's failure word and statistics (nullable).
+struct EigCfg {
+  double zeta = 1e-13;
+  int max_sweeps = 60;
+  int blind = 0;
+  bool host_check = true;
+  int* fail = nullptr;
+  double* dstats = nullptr;
+};
 
 struct Model {
   int N = 0, dx = 0, P = 0, D = 0, Dp = 0;
@@ -273,120 +438,157 @@ struct Model {
   double* gvwork = nullptr;    // column-split GEMV partials
   double *E1 = nullptr, *E2 = nullptr, *D1 = nullptr, *D2 = nullptr, *D3 = nullptr;
   double *t3 = nullptr, *tB = nullptr, *tau = nullptr;
-  double* dscal = nullptr;     // device scalars for API outputs
-  double* hscal = nullptr;     // pinned host mirror
   int* dflag = nullptr;
   int* hflag = nullptr;
   struct Point* api_pt = nullptr;
   std::unique_ptr<struct Point> api_pt_own;
   std::unique_ptr<struct State> chain_state;
-  long reorth_every = 10;
+  size_t device_bytes = 0;   // device memory held by the model (points, chain state, scratch)
+  // Serialises every call that uses the model's scratch or its chain state
+  // (calls on a model from several threads run one at a time).
+  std::mutex busy;
   ~Model();
 };
 
+// Everything that depends on one point q.  The data arrays live in one
+// contiguous device block (`data`, `data_bytes`), so an accepted move's end
+// point can replace the start point with one predicated copy on the device;
+// the device pointer arrays of the batched Y products point into the Point's
+// own block and sit outside it.
 struct Point {
-  Pool pool;
+  Pool meta;
+  char* data = nullptr;
+  size_t data_bytes = 0;
   int N, P, D, Dp;
   double *q, *K, *Kinv, *K1, *A, *At, *alpha, *lik, *scal, *k1a, *a, *gradU, *H;
   double *Psi, *lam, *g, *gp;
   double *B, *Yt, *k2a, *ik2a, *c1a, *Aam, *dHe, *vW2;
   double *trK1, *kla, *phiK2, *trAA, *ak;
-  const double **Yap, **Ybp;
-  double** Ycp;
+  const double **Yap = nullptr, **Ybp = nullptr;
+  double** Ycp = nullptr;
   // mixed precision: FP32 copies feeding the FP32 MFMA products
-  float *Kinvf = nullptr, *K1f = nullptr, *Af = nullptr, *Atf = nullptr, *Bf = nullptr,
-        *Ytf = nullptr;
+  float *Kinvf = nullptr, *Af = nullptr, *Atf = nullptr, *Ytf = nullptr;
   const float **Yapf = nullptr, **Ybpf = nullptr;
   float** Ycpf = nullptr;
   bool have_pre = false, have_vW2 = false, have_eig = false;
-  long updates_since_reorth = 0;
   // scal: [0] log|K|, [1] U, [2] log|G|, [3] sum l, [4] f.alpha, [5] ham
 };
 
 namespace {
 
+// Sub-allocation of a Point's data block: the same layout is run once to
+// size the block and once to hand out its pieces (256-byte aligned).
+struct Carve {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += std::max<size_t>(n, 1) * sizeof(T);
+    return p;
+  }
+};
+
+void layout_point(const Model& m, Point& p, Carve& c) {
+  const long N = m.N, P = m.P, NN = N * N, Dp = m.Dp;
+  const bool mixed = m.prec == RMHMC_MIXED;
+  p.q = c.take<double>(m.D);
+  p.K = c.take<double>(NN);
+  p.Kinv = c.take<double>(NN);
+  p.K1 = c.take<double>(P * NN);
+  p.A = c.take<double>(P * NN);
+  p.At = c.take<double>(mixed ? 1 : P * NN);
+  p.alpha = c.take<double>(N);
+  p.lik = c.take<double>(4 * N);
+  p.scal = c.take<double>(8);
+  p.k1a = c.take<double>(P * N);
+  p.a = c.take<double>(P * N);
+  p.gradU = c.take<double>(m.D);
+  p.H = c.take<double>(Dp * Dp);
+  p.Psi = c.take<double>(Dp * Dp);
+  p.lam = c.take<double>(Dp);
+  p.g = c.take<double>(Dp);
+  p.gp = c.take<double>(Dp);
+  p.B = c.take<double>(P * NN);
+  p.Yt = c.take<double>(mixed ? 1 : (long)m.nyy * NN);
+  p.k2a = c.take<double>((long)std::max(m.npairs, 1) * N);
+  p.ik2a = c.take<double>((long)std::max(m.npairs, 1) * N);
+  p.c1a = c.take<double>(P * P * N);
+  p.Aam = c.take<double>(P * P * N);
+  p.dHe = c.take<double>(P * P * P);
+  p.vW2 = c.take<double>(m.D);
+  p.trK1 = c.take<double>(P);
+  p.kla = c.take<double>(P * P);
+  p.phiK2 = c.take<double>(std::max(m.npairs, 1));
+  p.trAA = c.take<double>(P * P);
+  p.ak = c.take<double>(P);
+  if (mixed) {
+    p.Kinvf = c.take<float>(NN);
+    p.Af = c.take<float>(P * NN);
+    p.Atf = c.take<float>(P * NN);
+    p.Ytf = c.take<float>((long)m.nyy * NN);
+  }
+}
+
+// Device bytes of one Point of model m.
+size_t point_bytes(const Model& m) {
+  Point p;
+  Carve c;
+  layout_point(m, p, c);
+  return (c.off + 255) & ~size_t(255);
+}
+
 std::unique_ptr<Point> new_point(Model& m) {
   auto pt = std::make_unique<Point>();
   Point& p = *pt;
-  const long N = m.N, P = m.P, NN = N * N, Dp = m.Dp;
   p.N = m.N; p.P = m.P; p.D = m.D; p.Dp = m.Dp;
-  Pool& pl = p.pool;
-  p.q = pl.alloc<double>(m.D);
-  p.K = pl.alloc<double>(NN);
-  p.Kinv = pl.alloc<double>(NN);
-  p.K1 = pl.alloc<double>(P * NN);
-  p.A = pl.alloc<double>(P * NN);
-  p.At = pl.alloc<double>(P * NN);
-  p.alpha = pl.alloc<double>(N);
-  p.lik = pl.alloc<double>(4 * N);
-  p.scal = pl.alloc<double>(8);
-  p.k1a = pl.alloc<double>(P * N);
-  p.a = pl.alloc<double>(P * N);
-  p.gradU = pl.alloc<double>(m.D);
-  p.H = pl.alloc<double>(Dp * Dp);
-  p.Psi = pl.alloc<double>(Dp * Dp);
-  p.lam = pl.alloc<double>(Dp);
-  p.g = pl.alloc<double>(Dp);
-  p.gp = pl.alloc<double>(Dp);
-  p.B = pl.alloc<double>(P * NN);
-  p.Yt = pl.alloc<double>(m.prec == RMHMC_MIXED ? 1 : (long)m.nyy * NN);
-  p.k2a = pl.alloc<double>((long)std::max(m.npairs, 1) * N);
-  p.ik2a = pl.alloc<double>((long)std::max(m.npairs, 1) * N);
-  p.c1a = pl.alloc<double>(P * P * N);
-  p.Aam = pl.alloc<double>(P * P * N);
-  p.dHe = pl.alloc<double>(P * P * P);
-  p.vW2 = pl.alloc<double>(m.D);
-  p.trK1 = pl.alloc<double>(P);
-  p.kla = pl.alloc<double>(P * P);
-  p.phiK2 = pl.alloc<double>(std::max(m.npairs, 1));
-  p.trAA = pl.alloc<double>(P * P);
-  p.ak = pl.alloc<double>(P);
+  p.data_bytes = point_bytes(m);
+  p.data = p.meta.alloc<char>(p.data_bytes);
+  Carve c;
+  c.base = p.data;
+  layout_point(m, p, c);
+  const long NN = (long)m.N * m.N;
   // pointer arrays for the Y_lm = A_l A_m batch (the formed pairs l <= m)
   std::vector<const double*> ya, yb;
   std::vector<double*> yc;
+  std::vector<const float*> fa, fb;
+  std::vector<float*> fc;
   for (int l = 0; l < m.P; ++l)
     for (int mm = l; mm < m.P; ++mm) {
-      if (m.yidx_h[l * m.P + mm] < 0) continue;
-      ya.push_back(p.A + l * NN);
-      yb.push_back(p.A + mm * NN);
-      yc.push_back(m.prec == RMHMC_MIXED ? p.Yt
-                                         : p.Yt + (long)m.yidx_h[l * m.P + mm] * NN);
-    }
-  p.Yap = (const double**)pl.alloc<double*>(ya.size());
-  p.Ybp = (const double**)pl.alloc<double*>(yb.size());
-  p.Ycp = pl.alloc<double*>(yc.size());
-  RM_HIP(hipMemcpy((void*)p.Yap, ya.data(), ya.size() * sizeof(void*), hipMemcpyHostToDevice));
-  RM_HIP(hipMemcpy((void*)p.Ybp, yb.data(), yb.size() * sizeof(void*), hipMemcpyHostToDevice));
-  RM_HIP(hipMemcpy((void*)p.Ycp, yc.data(), yc.size() * sizeof(void*), hipMemcpyHostToDevice));
-  if (m.prec == RMHMC_MIXED) {
-    p.Kinvf = pl.alloc<float>(NN);
-    p.K1f = pl.alloc<float>(P * NN);
-    p.Af = pl.alloc<float>(P * NN);
-    p.Atf = pl.alloc<float>(P * NN);
-    p.Bf = pl.alloc<float>(P * NN);
-    p.Ytf = pl.alloc<float>((long)m.nyy * NN);
-    std::vector<const float*> fa, fb;
-    std::vector<float*> fc;
-    for (int l = 0; l < m.P; ++l)
-      for (int mm = l; mm < m.P; ++mm) {
-        if (m.yidx_h[l * m.P + mm] < 0) continue;
+      const int y = m.yidx_h[l * m.P + mm];
+      if (y < 0) continue;
+      if (m.prec == RMHMC_MIXED) {
         fa.push_back(p.Af + l * NN);
         fb.push_back(p.Af + mm * NN);
-        fc.push_back(p.Ytf + (long)m.yidx_h[l * m.P + mm] * NN);
+        fc.push_back(p.Ytf + (long)y * NN);
+      } else {
+        ya.push_back(p.A + l * NN);
+        yb.push_back(p.A + mm * NN);
+        yc.push_back(p.Yt + (long)y * NN);
       }
-    p.Yapf = (const float**)pl.alloc<float*>(fa.size());
-    p.Ybpf = (const float**)pl.alloc<float*>(fb.size());
-    p.Ycpf = pl.alloc<float*>(fc.size());
+    }
+  if (m.prec == RMHMC_MIXED) {
+    p.Yapf = (const float**)p.meta.alloc<float*>(fa.size());
+    p.Ybpf = (const float**)p.meta.alloc<float*>(fb.size());
+    p.Ycpf = p.meta.alloc<float*>(fc.size());
     RM_HIP(hipMemcpy((void*)p.Yapf, fa.data(), fa.size() * sizeof(void*), hipMemcpyHostToDevice));
     RM_HIP(hipMemcpy((void*)p.Ybpf, fb.data(), fb.size() * sizeof(void*), hipMemcpyHostToDevice));
     RM_HIP(hipMemcpy((void*)p.Ycpf, fc.data(), fc.size() * sizeof(void*), hipMemcpyHostToDevice));
+  } else {
+    p.Yap = (const double**)p.meta.alloc<double*>(ya.size());
+    p.Ybp = (const double**)p.meta.alloc<double*>(yb.size());
+    p.Ycp = p.meta.alloc<double*>(yc.size());
+    RM_HIP(hipMemcpy((void*)p.Yap, ya.data(), ya.size() * sizeof(void*), hipMemcpyHostToDevice));
+    RM_HIP(hipMemcpy((void*)p.Ybp, yb.data(), yb.size() * sizeof(void*), hipMemcpyHostToDevice));
+    RM_HIP(hipMemcpy((void*)p.Ycp, yc.data(), yc.size() * sizeof(void*), hipMemcpyHostToDevice));
   }
-  RM_HIP(hipMemset(p.scal, 0, 8 * sizeof(double)));
+  RM_HIP(hipMemset(p.data, 0, p.data_bytes));
   return pt;
 }
 
 void check_flag_nonfinite(Model& m, const double* x, long n, hipStream_t st, const char* what) {
-  RM_HIP(hipMemsetAsync(m.dflag, 0, sizeof(int), st));
+  fill_int(m.dflag, 1, 0, st);
   hipLaunchKernelGGL(any_nonfinite_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, n, x, m.dflag);
   RM_CHECK_LAUNCH();
   RM_HIP(hipMemcpyAsync(m.hflag, m.dflag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -394,8 +596,10 @@ void check_flag_nonfinite(Model& m, const double* x, long n, hipStream_t st, con
   if (*m.hflag) throw Error(RMHMC_E_NONFINITE, std::string("non-finite values in ") + what);
 }
 
-// U, grad U, H at pt.q.
-void compute_hessian(Model& m, Point& pt, hipStream_t st) {
+// U, grad U, H at pt.q.  fail == nullptr: a non-positive-definite K is
+// reported at once (reads the Cholesky flag, synchronises the stream);
+// otherwise the flag is folded into *fail on the device.
+void compute_hessian(Model& m, Point& pt, hipStream_t st, int* fail) {
   const int N = m.N, P = m.P;
   const long NN = (long)N * N;
   const double* eta = pt.q + N;
@@ -407,27 +611,25 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st) {
   gemv(N, N, 1.0, pt.Kinv, N, true, 0, pt.q, 0, 0.0, pt.alpha, 0, 1, st);
   lik_derivs(N, m.lik, m.noise_var, pt.q, m.y, pt.lik, st);
   const bool mixed = m.prec == RMHMC_MIXED;
-  if (!mixed) {  // A_l = K^-1 K_l, and the transposed copies
+  {  // A_l = K^-1 K_l, and the transposed copies
+    // A_l stays FP64 in both modes: K^-1 reaches 1/jitter while A_l is O(1),
+    // so its entries come from heavy cancellation that FP32 operands and
+    // accumulation cannot resolve.  Mixed mode takes the FP32 operands of the
+    // later products (A_l, A_l' for the traces) from the same epilogue.
     Gemm<double> g;
     g.m = N; g.n = N; g.k = N;
     g.A = pt.Kinv; g.lda = N;
     g.B = pt.K1; g.ldb = N; g.sB = NN;
     g.C = pt.A; g.ldc = N; g.sC = NN;
-    g.C2 = pt.At; g.ldc2 = N; g.sC2 = NN;
     g.batch = P;
+    if (!mixed) {
+      g.C2 = pt.At; g.ldc2 = N; g.sC2 = NN;
+    } else {
+      g.Co = pt.Af; g.sCo = NN;
+      g.ldc2 = N; g.C2o = pt.Atf; g.sC2o = NN;
+      cast_to_float(NN, pt.Kinv, pt.Kinvf, st);
+    }
     gemm(g, st);
-  } else {       // the same products on the FP32 matrix cores, FP32 accumulation
-    cast_to_float(NN, pt.Kinv, pt.Kinvf, st);
-    cast_to_float(P * NN, pt.K1, pt.K1f, st);
-    Gemm<float> g;
-    g.m = N; g.n = N; g.k = N;
-    g.A = pt.Kinvf; g.lda = N;
-    g.B = pt.K1f; g.ldb = N; g.sB = NN;
-    g.C = pt.Af; g.ldc = N; g.sC = NN;
-    g.C2 = pt.Atf; g.ldc2 = N; g.sC2 = NN;
-    g.batch = P;
-    gemm(g, st);
-    widen_to_double(P * NN, pt.Af, pt.A, st);
   }
   gemv(N, N, 1.0, pt.K1, N, true, NN, pt.alpha, 0, 0.0, pt.k1a, N, P, st);
   gemv(N, N, 1.0, pt.Kinv, N, true, 0, pt.k1a, N, 0.0, pt.a, N, P, st);   // A_l a = K^-1 (K_l a)
@@ -450,59 +652,57 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st) {
                      (const double*)pt.alpha, (const double*)pt.lik, (const double*)pt.ak,
                      (const double*)pt.trK1, pt.gradU, pt.scal);
   RM_CHECK_LAUNCH();
-  RM_HIP(hipMemcpyAsync(m.hflag, m.chol.info, sizeof(int), hipMemcpyDeviceToHost, st));
-  RM_HIP(hipStreamSynchronize(st));
-  if (*m.hflag) throw Error(RMHMC_E_NOT_PD, "kernel matrix K is not positive definite");
-  (void)NN;
+  if (fail) {
+    hipLaunchKernelGGL(fold_flag_kernel, dim3(1), dim3(64), 0, st, (const int*)m.chol.info, fail,
+                       (int)FAIL_NOT_PD);
+    RM_CHECK_LAUNCH();
+  } else {
+    RM_HIP(hipMemcpyAsync(m.hflag, m.chol.info, sizeof(int), hipMemcpyDeviceToHost, st));
+    RM_HIP(hipStreamSynchronize(st));
+    if (*m.hflag) throw Error(RMHMC_E_NOT_PD, "kernel matrix K is not positive definite");
+  }
 }
 
-void reorthogonalise(Model& m, double* Psi, hipStream_t st) {
-  orthonormalise(m.D, m.Dp, Psi, m.Wt1, m.Wt2, st);
-}
-
-// Softabs eigen-state of pt.H; warm == nullptr: static, else dynamic from warm->Psi.
-int compute_eig(Model& m, Point& pt, Point* warm, double alpha, double zeta, int max_sweeps,
-                hipStream_t st) {
+// Softabs eigen-state of pt.H; warm == nullptr: static, else dynamic from
+// warm->Psi (Sec. 2.4).  The warm basis is copied before anything touches it
+// (a move's start point stays as it was); with `reorth` the copy is first
+// re-orthonormalised.
+JacobiResult compute_eig(Model& m, Point& pt, const Point* warm, double alpha, const EigCfg& ec,
+                         bool reorth, hipStream_t st) {
   const int D = m.D, Dp = m.Dp;
   if (!warm) {
     eig_load_matrix(D, pt.H, Dp, m.eig, st);
     eig_load_basis(D, nullptr, Dp, m.eig, st);
-    pt.updates_since_reorth = 0;
   } else {
-    long cnt = warm->updates_since_reorth + 1;
-    if (cnt >= m.reorth_every) {
-      reorthogonalise(m, warm->Psi, st);
-      cnt = 0;
-    }
+    copy(m.eig.Psi, warm->Psi, (long)Dp * Dp, st);
+    if (reorth) orthonormalise(D, Dp, m.eig.Psi, m.Wt1, m.Wt2, st);
     // M = Psi_w' H Psi_w
     Gemm<double> g;
     g.m = Dp; g.n = Dp; g.k = Dp;
     g.A = pt.H; g.lda = Dp;
-    g.B = warm->Psi; g.ldb = Dp;
+    g.B = m.eig.Psi; g.ldb = Dp;
     g.C = m.Wt1; g.ldc = Dp;
     gemm_splitk(g, m.gsplit, GSPLIT, st);
     Gemm<double> h;
     h.m = Dp; h.n = Dp; h.k = Dp;
-    h.A = warm->Psi; h.lda = Dp; h.tA = true;
+    h.A = m.eig.Psi; h.lda = Dp; h.tA = true;
     h.B = m.Wt1; h.ldb = Dp;
     h.C = m.eig.M; h.ldc = Dp;
     gemm_splitk(h, m.gsplit, GSPLIT, st);
     symmetrize(Dp, m.eig.M, Dp, st);
-    copy(m.eig.Psi, warm->Psi, (long)Dp * Dp, st);
-    pt.updates_since_reorth = cnt;
   }
-  int sweeps = 0;
-  jacobi_eig(D, m.eig, zeta, max_sweeps, warm ? JACOBI_INNER_DYNAMIC : JACOBI_INNER_STATIC,
-             &sweeps, st);
+  const JacobiResult r =
+      jacobi_eig(D, m.eig, ec.zeta, ec.max_sweeps, warm ? JACOBI_INNER_DYNAMIC : JACOBI_INNER_STATIC,
+                 ec.blind, ec.host_check, ec.host_check ? nullptr : ec.fail, ec.dstats, st);
   // a static solve accumulates one rounding per rotation into Psi: restore
   // orthogonality before the eigenvalues are refined against H
-  if (!warm) reorthogonalise(m, m.eig.Psi, st);
+  if (!warm) orthonormalise(D, Dp, m.eig.Psi, m.Wt1, m.Wt2, st);
   rayleigh_refine(D, pt.H, Dp, m.eig, m.Wt2, st);
   copy(pt.Psi, m.eig.Psi, (long)Dp * Dp, st);
   softabs_finalize(D, m.eig.M, Dp, alpha, pt.lam, pt.g, pt.gp, pt.scal + 2, st);
   pt.have_eig = true;
   pt.have_vW2 = false;
-  return sweeps;
+  return r;
 }
 
 // W-independent pieces of v(W) at pt (needs compute_hessian first).
@@ -533,15 +733,15 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
     // tau[n, y] = tr(A_n A_l A_m) = <A_n, Y_lm'> for the formed pairs y = (l, m)
     gemm_tallk(P, m.nyy, NN, pt.A, NN, pt.Yt, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
   } else {
-    {
+    {  // B_l = A_l K^-1 on the FP32 matrix cores, stored in FP64
       Gemm<float> g;
       g.m = N; g.n = N; g.k = N;
       g.A = pt.Af; g.lda = N; g.sA = NN;
       g.B = pt.Kinvf; g.ldb = N;
-      g.C = pt.Bf; g.ldc = N; g.sC = NN;
+      g.ldc = N;
+      g.Co = pt.B; g.sCo = NN;
       g.batch = P;
       gemm(g, st);
-      widen_to_double(P * NN, pt.Bf, pt.B, st);
     }
     {
       Gemm<float> g;
@@ -676,12 +876,34 @@ void grad_q(Model& m, Point& pt, const double* p, double alpha, double* dHdq, do
   lincomb3(D, pt.gradU, 0.5, pt.vW2, -0.5, m.v1, dHdq, st);
 }
 
-void full_point(Model& m, Point& pt, Point* warm, double alpha, double zeta, int max_sweeps,
-                hipStream_t st, int* sweeps) {
-  compute_hessian(m, pt, st);
-  const int s = compute_eig(m, pt, warm, alpha, zeta, max_sweeps, st);
-  if (sweeps) *sweeps += s;
+// Metric at a new point: Hessian, then the eigen-state (static when warm is
+// null).  A warm start whose Jacobi sweeps run out is redone statically
+// (counted in *fallbacks) when the host checks convergence; without host
+// checks the failure word records it.  A non-finite eigenproblem marks the
+// failure word (host-checked mode: also returns false).
+bool full_point(Model& m, Point& pt, const Point* warm, double alpha, const EigCfg& ec, bool reorth,
+                hipStream_t st, int* fail, long* fallbacks) {
+  compute_hessian(m, pt, st, fail);
+  JacobiResult r = compute_eig(m, pt, warm, alpha, ec, reorth, st);
+  if (!ec.host_check) return true;
+  if (!r.converged && !r.nonfinite && warm) {
+    if (fallbacks) ++*fallbacks;
+    r = compute_eig(m, pt, nullptr, alpha, ec, false, st);
+  }
+  if (r.nonfinite || !r.converged) {
+    if (!fail) {
+      if (r.nonfinite) throw Error(RMHMC_E_NONFINITE, "non-finite values in the Hessian");
+      throw Error(RMHMC_E_EIG_NOCONV, "softabs_eig: Jacobi did not converge");
+    }
+    hipLaunchKernelGGL(or_flag_kernel, dim3(1), dim3(64), 0, st, fail,
+                       r.nonfinite ? (int)FAIL_NONFINITE : (int)FAIL_NOCONV);
+    RM_CHECK_LAUNCH();
+    return false;
+  }
+  return true;
 }
+
+std::unique_ptr<struct State> make_state(Model& m, double alpha);
 
 void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   RM_REQUIRE(d != nullptr, "model descriptor is NULL");
@@ -813,8 +1035,8 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   m.eig.Psi = pl.alloc<double>(Dp * Dp);
   m.eig.V = pl.alloc<double>(eig_rotation_doubles(Dp));
   m.eig.part = pl.alloc<double>(3 * (Dp / 8 + 1));
-  m.eig.ctrl = pl.alloc<double>(8);
-  m.eig.ctrl_host = pl.alloc_host<double>(4);
+  m.eig.ctrl = pl.alloc<double>(EIG_CTRL_DOUBLES);
+  m.eig.ctrl_host = pl.alloc_host<double>(EIG_CTRL_DOUBLES);
   const int spl = tallk_splits(NN);
   m.tallwork = pl.alloc<double>((long)spl * P * std::max(P, m.nyy) + 64);
   m.kdwork = pl.alloc<double>(512L * MAX_P * MAX_TUPLES + (long)MAX_P * std::max(m.ntriples, m.npairs) + 64);
@@ -847,8 +1069,6 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   m.t3 = pl.alloc<double>(std::max(m.ntriples, 1));
   m.tB = pl.alloc<double>(P * std::max(m.npairs, 1));
   m.tau = pl.alloc<double>(P * m.nyy);
-  m.dscal = pl.alloc<double>(8);
-  m.hscal = pl.alloc_host<double>(8);
   m.dflag = pl.alloc<int>(1);
   m.hflag = pl.alloc_host<int>(1);
   m.api_pt_own = new_point(m);
@@ -864,10 +1084,17 @@ struct State {
   Model* m;
   std::unique_ptr<Point> own[3];
   Point* pts[3];     // pts[0] = current point
-  double alpha, zeta;
-  int max_sweeps;
-  double *p, *ph, *v0, *vk, *gq, *qk, *ham;
-  long leapfrogs = 0, eig_calls = 0, sweeps = 0;
+  double alpha;
+  EigCfg ec;         // eigensolver control (fail / dstats point into this state)
+  long reorth_every = 10;
+  long updates_since_reorth = 0;   // dynamic eigen-updates since the last re-orthonormalisation
+  double *p, *ph, *v0, *vk, *gq, *qk, *ham, *z;
+  int* fail = nullptr;     // failure word of the current move or step
+  int* acc = nullptr;      // accept decision of the current move
+  double* dstats = nullptr;   // ST_N device statistics
+  double* hstats = nullptr;   // pinned mirror
+  int* hfail = nullptr;       // pinned mirror of fail
+  long leapfrogs = 0, fallbacks = 0;
 };
 
 namespace {
@@ -876,8 +1103,6 @@ std::unique_ptr<State> make_state(Model& m, double alpha) {
   auto s = std::make_unique<State>();
   s->m = &m;
   s->alpha = alpha;
-  s->zeta = 1e-13;
-  s->max_sweeps = 60;
   for (int i = 0; i < 3; ++i) {
     s->own[i] = new_point(m);
     s->pts[i] = s->own[i].get();
@@ -889,8 +1114,43 @@ std::unique_ptr<State> make_state(Model& m, double alpha) {
   s->vk = pl.alloc<double>(m.D);
   s->gq = pl.alloc<double>(m.D);
   s->qk = pl.alloc<double>(m.D);
+  s->z = pl.alloc<double>(m.D);
   s->ham = pl.alloc<double>(2);
+  s->fail = pl.alloc<int>(2);
+  s->acc = s->fail + 1;
+  s->dstats = pl.alloc<double>(ST_N);
+  s->hstats = pl.alloc_host<double>(ST_N);
+  s->hfail = pl.alloc_host<int>(1);
+  RM_HIP(hipMemset(s->fail, 0, 2 * sizeof(int)));
+  RM_HIP(hipMemset(s->dstats, 0, ST_N * sizeof(double)));
+  s->ec.fail = s->fail;
+  s->ec.dstats = s->dstats;
   return s;
+}
+
+void reset_stats(State& S, hipStream_t st) {
+  fill(S.dstats, ST_N, 0.0, st);
+  fill_int(S.fail, 2, 0, st);
+  S.leapfrogs = S.fallbacks = 0;
+}
+
+void read_stats(State& S, rmhmc_chain_stats* out, hipStream_t st) {
+  RM_HIP(hipMemcpyAsync(S.hstats, S.dstats, ST_N * sizeof(double), hipMemcpyDeviceToHost, st));
+  RM_HIP(hipStreamSynchronize(st));
+  const double* h = S.hstats;
+  *out = rmhmc_chain_stats{};
+  out->accepted = (int)h[ST_ACC_KEPT];
+  out->accepted_all = (int)h[ST_ACC];
+  out->failures = (int)h[ST_FAIL];
+  out->fail_not_pd = (int)h[ST_NOTPD];
+  out->fail_nonfinite = (int)h[ST_NONFINITE];
+  out->fail_noconv = (int)h[ST_NOCONV];
+  out->leapfrogs = S.leapfrogs;
+  out->eig_calls = (long long)h[ST_EIG];
+  out->sweeps = (long long)h[ST_SWEEPS];
+  out->eig_fallbacks = (int)S.fallbacks;
+  out->max_res_p = h[ST_RESP];
+  out->max_res_q = h[ST_RESQ];
 }
 
 }  // namespace
@@ -908,43 +1168,56 @@ void draw_momentum(Model& m, State& S, Point& pt, const double* z, hipStream_t s
   gemv_split(m.D, m.D, 1.0, pt.Psi, m.Dp, S.vk, 0.0, S.p, m.gvwork, st);
 }
 
-// One generalized leapfrog from cur with momentum s.p; trial points alternate
-// among the two non-current Points, never touching `keep` (if given).
-Point* leapfrog(State& s, Point* cur, Point* keep, double eps, int K, hipStream_t st) {
+void fp_update(int n, const double* base, double c1, const double* x, double c2, const double* y,
+               double* dst, double* res, hipStream_t st) {
+  hipLaunchKernelGGL(fp_update_kernel, dim3(1), dim3(1024), 0, st, n, base, c1, x, c2, y, dst, res);
+  RM_CHECK_LAUNCH();
+}
+
+// One generalized leapfrog (Eq. leapfrog) from cur with momentum s.p; trial
+// points alternate among the two non-current Points, never touching `keep`
+// (if given), which is left exactly as it was.  Both implicit equations are
+// solved by K plain fixed-point iterations; the relative residual of the last
+// iteration of each goes into the state's statistics.  Failures land in the
+// state's failure word; returns false when the host already knows this
+// leapfrog failed (the rest of the move can be skipped).
+Point* leapfrog(State& s, Point* cur, Point* keep, double eps, int K, hipStream_t st, bool* ok) {
   Model& m = *s.m;
   const int D = m.D;
   Point* trial = nullptr;
   for (int i = 0; i < 3; ++i)
     if (s.pts[i] != cur && s.pts[i] != keep) { trial = s.pts[i]; break; }
-  // implicit momentum half step at fixed q
+  // implicit momentum half step at fixed q: ph <- p - eps/2 dH/dq(q, ph)
   copy(s.ph, s.p, D, st);
   for (int k = 0; k < K; ++k) {
     grad_q(m, *cur, s.ph, s.alpha, s.gq, nullptr, nullptr, st);
-    lincomb3(D, s.p, -0.5 * eps, s.gq, 0.0, s.gq, s.ph, st);
+    fp_update(D, s.p, -0.5 * eps, s.gq, 0.0, s.gq, s.ph, k == K - 1 ? s.dstats + ST_RESP : nullptr, st);
   }
-  // implicit position step
+  // implicit position step: qk <- q + eps/2 (G(q)^-1 ph + G(qk)^-1 ph)
   metric_vectors(m, *cur, s.ph, s.v0, nullptr, st);
-  lincomb3(D, cur->q, eps, s.v0, 0.0, s.v0, s.qk, st);   // k = 0: G(q) both times
-  Point* warm = cur;
+  copy(s.qk, cur->q, D, st);
+  fp_update(D, cur->q, eps, s.v0, 0.0, s.v0, s.qk, K == 1 ? s.dstats + ST_RESQ : nullptr, st);
+  const Point* warm = cur;
+  bool good = true;
+  auto eval = [&](Point& pt) {
+    copy(pt.q, s.qk, D, st);
+    const bool reorth = ++s.updates_since_reorth >= s.reorth_every;
+    if (reorth) s.updates_since_reorth = 0;
+    good = full_point(m, pt, warm, s.alpha, s.ec, reorth, st, s.fail, &s.fallbacks) && good;
+    warm = &pt;
+  };
   for (int k = 1; k < K; ++k) {
-    copy(trial->q, s.qk, D, st);
-    int sw = 0;
-    full_point(m, *trial, warm, s.alpha, s.zeta, s.max_sweeps, st, &sw);
-    s.sweeps += sw;
-    s.eig_calls += 1;
-    warm = trial;
+    eval(*trial);
     metric_vectors(m, *trial, s.ph, s.vk, nullptr, st);
-    lincomb3(D, cur->q, 0.5 * eps, s.v0, 0.5 * eps, s.vk, s.qk, st);
+    fp_update(D, cur->q, 0.5 * eps, s.v0, 0.5 * eps, s.vk, s.qk,
+              k == K - 1 ? s.dstats + ST_RESQ : nullptr, st);
   }
-  copy(trial->q, s.qk, D, st);
-  int sw = 0;
-  full_point(m, *trial, warm, s.alpha, s.zeta, s.max_sweeps, st, &sw);
-  s.sweeps += sw;
-  s.eig_calls += 1;
+  eval(*trial);
   // explicit momentum half step
   grad_q(m, *trial, s.ph, s.alpha, s.gq, nullptr, nullptr, st);
   lincomb3(D, s.ph, -0.5 * eps, s.gq, 0.0, s.gq, s.p, st);
   s.leapfrogs += 1;
+  if (ok) *ok = good;
   return trial;
 }
 
@@ -956,69 +1229,72 @@ namespace {
 
 // ------------------------------------------------------------ chain (Algorithm 1)
 
-void chain_impl(Model& m, const rmhmc_chain_cfg* cfg, const double* q0, const double* z,
-                const double* u, double* samples, double* logpost, int* accepted,
-                rmhmc_chain_stats* stats, hipStream_t st) {
-  RM_REQUIRE(cfg && q0 && z && u && samples && logpost && accepted, "NULL argument");
-  RM_REQUIRE(cfg->n_leapfrog >= 1 && cfg->n_moves >= 1 && cfg->n_fixed_point >= 1,
-             "n_leapfrog, n_moves and n_fixed_point must be >= 1");
+void check_chain_cfg(const Model& m, const rmhmc_chain_cfg* cfg) {
+  RM_REQUIRE(cfg != nullptr, "NULL chain configuration");
+  RM_REQUIRE(cfg->n_leapfrog >= 1 && cfg->n_fixed_point >= 1,
+             "n_leapfrog and n_fixed_point must be >= 1");
+  RM_REQUIRE(cfg->n_moves >= 1 && cfg->n_burnin >= 0 && cfg->n_burnin < cfg->n_moves,
+             "need n_moves >= 1 and 0 <= n_burnin < n_moves");
   RM_REQUIRE(std::isfinite(cfg->eps) && cfg->eps > 0.0, "eps must be positive");
   RM_REQUIRE(std::isfinite(cfg->alpha) && cfg->alpha > 0.0, "alpha must be positive");
+  RM_REQUIRE(cfg->precision == m.prec, "chain precision differs from the model's");
+}
+
+void chain_impl(Model& m, const rmhmc_chain_cfg* cfg, const double* q0, double* samples,
+                double* logpost, int* accepted, rmhmc_chain_stats* stats, hipStream_t st) {
+  check_chain_cfg(m, cfg);
+  RM_REQUIRE(q0 && samples && logpost && accepted, "NULL argument");
   const int D = m.D;
-  m.reorth_every = cfg->reorth_every > 0 ? cfg->reorth_every : 10;
-  // the chain state (three Points) is allocated once per model and reused
-  if (!m.chain_state) m.chain_state = make_state(m, cfg->alpha);
   State& S = *m.chain_state;
   S.alpha = cfg->alpha;
-  S.zeta = cfg->zeta > 0.0 ? cfg->zeta : 1e-13;
-  S.max_sweeps = cfg->max_sweeps > 0 ? cfg->max_sweeps : 60;
-  S.leapfrogs = S.eig_calls = S.sweeps = 0;
-  std::vector<double> uh(cfg->n_moves);
-  RM_HIP(hipMemcpyAsync(uh.data(), u, cfg->n_moves * sizeof(double), hipMemcpyDeviceToHost, st));
-  copy(S.pts[0]->q, q0, D, st);
-  check_flag_nonfinite(m, S.pts[0]->q, D, st, "q0");
-  int sw = 0;
-  full_point(m, *S.pts[0], nullptr, cfg->alpha, S.zeta, S.max_sweeps, st, &sw);
-  S.sweeps += sw;
-  S.eig_calls += 1;
-  int n_acc = 0, n_fail = 0;
+  S.ec.zeta = cfg->zeta > 0.0 ? cfg->zeta : 1e-13;
+  S.ec.max_sweeps = cfg->max_sweeps > 0 ? cfg->max_sweeps : 60;
+  S.ec.blind = 0;
+  S.ec.host_check = true;
+  S.reorth_every = cfg->reorth_every > 0 ? cfg->reorth_every : 10;
+  reset_stats(S, st);
+  Point* start = S.pts[0];
+  copy(start->q, q0, D, st);
+  check_flag_nonfinite(m, start->q, D, st, "q0");
+  {
+    EigCfg ec0 = S.ec;   // the first point is solved statically and must succeed
+    ec0.fail = nullptr;
+    full_point(m, *start, nullptr, S.alpha, ec0, false, st, nullptr, nullptr);
+  }
+  const size_t words = start->data_bytes / sizeof(double2);
+  const unsigned copy_grid = (unsigned)std::min<size_t>(cdiv((long)words, 256), 2048);
   for (int ell = 0; ell < cfg->n_moves; ++ell) {
-    Point* start = S.pts[0];
-    draw_momentum(m, S, *start, z + (long)ell * D, st);
-    metric_vectors(m, *start, S.p, nullptr, S.ham, st);
-    bool ok = true;
-    Point* cur = start;
-    try {
-      for (int c = 0; c < cfg->n_leapfrog; ++c)
-        cur = leapfrog(S, cur, start, cfg->eps, cfg->n_fixed_point, st);
-      metric_vectors(m, *cur, S.p, nullptr, S.ham + 1, st);
-    } catch (const Error& e) {
-      if (e.status == RMHMC_E_HIP || e.status == RMHMC_E_ARG || e.status == RMHMC_E_NOMEM) throw;
-      ok = false;
-    }
-    RM_HIP(hipMemcpyAsync(m.hscal, S.ham, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    RM_HIP(hipStreamSynchronize(st));
-    const double h0 = m.hscal[0], h1 = m.hscal[1];
-    const bool acc = ok && std::isfinite(h1) && std::isfinite(h0) && std::log(uh[ell]) < h0 - h1;
-    if (!ok) ++n_fail;
-    if (acc) {
-      ++n_acc;
-      for (int i = 1; i < 3; ++i)
-        if (S.pts[i] == cur) std::swap(S.pts[0], S.pts[i]);
-    }
-    hipLaunchKernelGGL(store_sample_kernel, dim3(cdiv(D, 256)), dim3(256), 0, st, D,
-                       (const double*)S.pts[0]->q, (const double*)(S.pts[0]->scal + 1),
-                       samples + (long)ell * D, logpost + ell, accepted + ell, acc ? 1 : 0);
+    const bool kept = ell >= cfg->n_burnin;
+    const long row = ell - cfg->n_burnin;
+    // p ~ N(0, G(q)) from the move's normals
+    hipLaunchKernelGGL(normals_kernel, dim3(cdiv(cdiv(D, 4), 64)), dim3(64), 0, st, D, cfg->seed,
+                       cfg->stream_id, (unsigned long long)ell, S.z);
     RM_CHECK_LAUNCH();
+    draw_momentum(m, S, *start, S.z, st);
+    metric_vectors(m, *start, S.p, nullptr, S.ham, st);
+    S.updates_since_reorth = 0;
+    Point* cur = start;
+    bool ok = true;
+    for (int c = 0; c < cfg->n_leapfrog && ok; ++c)
+      cur = leapfrog(S, cur, start, cfg->eps, cfg->n_fixed_point, st, &ok);
+    metric_vectors(m, *cur, S.p, nullptr, S.ham + 1, st);
+    hipLaunchKernelGGL(mh_kernel, dim3(1), dim3(64), 0, st, cfg->seed, cfg->stream_id,
+                       (unsigned long long)ell, (const double*)S.ham, S.fail, S.acc, S.dstats,
+                       kept ? accepted + row : (int*)nullptr);
+    RM_CHECK_LAUNCH();
+    hipLaunchKernelGGL(copy_if_kernel, dim3(copy_grid), dim3(256), 0, st, (long)words,
+                       (double2*)start->data, (const double2*)cur->data, (const int*)S.acc);
+    RM_CHECK_LAUNCH();
+    if (kept) {
+      hipLaunchKernelGGL(store_sample_kernel, dim3(cdiv(D, 256)), dim3(256), 0, st, D,
+                         (const double*)start->q, (const double*)(start->scal + 1),
+                         samples + row * D, logpost + row);
+      RM_CHECK_LAUNCH();
+    }
   }
-  RM_HIP(hipStreamSynchronize(st));
-  if (stats) {
-    stats->accepted = n_acc;
-    stats->failures = n_fail;
-    stats->leapfrogs = S.leapfrogs;
-    stats->eig_calls = S.eig_calls;
-    stats->sweeps = S.sweeps;
-  }
+  rmhmc_chain_stats tmp;
+  read_stats(S, &tmp, st);
+  if (stats) *stats = tmp;
 }
 
 }  // namespace
@@ -1032,7 +1308,6 @@ void chain_impl(Model& m, const rmhmc_chain_cfg* cfg, const double* q0, const do
 
 struct rmhmc_model {
   rmhmc::Model impl;
-  std::mutex busy;    // one chain at a time per model (its scratch is shared)
 };
 
 namespace rmhmc {
@@ -1042,7 +1317,7 @@ struct PoolJob {
   long long id = 0;
   rmhmc_model* m = nullptr;
   rmhmc_chain_cfg cfg{};
-  const double *q0 = nullptr, *z = nullptr, *u = nullptr;
+  const double* q0 = nullptr;
   double *samples = nullptr, *logpost = nullptr;
   int* accepted = nullptr;
   rmhmc_chain_stats stats{};
@@ -1083,7 +1358,7 @@ void pool_worker(rmhmc_pool* pool, int w) {
         if (pool->stop) return;
         // first queued job whose model is free
         for (auto it = pool->queue.begin(); it != pool->queue.end(); ++it) {
-          if ((*it)->m->busy.try_lock()) {
+          if ((*it)->m->impl.busy.try_lock()) {
             job = *it;
             pool->queue.erase(it);
             break;
@@ -1098,8 +1373,8 @@ void pool_worker(rmhmc_pool* pool, int w) {
     rmhmc_status status = RMHMC_OK;
     std::string err;
     try {
-      chain_impl(job->m->impl, &job->cfg, job->q0, job->z, job->u, job->samples, job->logpost,
-                 job->accepted, &job->stats, st);
+      chain_impl(job->m->impl, &job->cfg, job->q0, job->samples, job->logpost, job->accepted,
+                 &job->stats, st);
     } catch (const Error& e) {
       status = e.status;
       err = e.what();
@@ -1107,7 +1382,7 @@ void pool_worker(rmhmc_pool* pool, int w) {
       status = RMHMC_E_HIP;
       err = e.what();
     }
-    job->m->busy.unlock();
+    job->m->impl.busy.unlock();
     {
       std::lock_guard<std::mutex> lk(pool->mu);
       job->status = status;
@@ -1151,14 +1426,43 @@ rmhmc_status guard(F&& f) {
   }
 }
 
-struct EigCache {
+// Workspace of the stand-alone eigensolver, one per device, sized by the
+// largest dimension reserved or solved so far.  A call holds its mutex until
+// its stream has drained, so calls from several threads never share it.
+struct EigWorkspace {
+  std::mutex mu;
   int Dp = 0;
-  Pool* pool = nullptr;
+  std::unique_ptr<Pool> pool;
   EigWork w;
 };
-EigCache& eig_cache() {
-  static EigCache c;
-  return c;
+
+EigWorkspace& eig_workspace() {
+  static std::mutex gmu;
+  static std::map<int, std::unique_ptr<EigWorkspace>> per_device;
+  int dev = 0;
+  RM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(gmu);
+  auto& p = per_device[dev];
+  if (!p) p = std::make_unique<EigWorkspace>();
+  return *p;
+}
+
+// Caller holds ws.mu; every earlier use of the buffers has completed.
+void eig_workspace_grow(EigWorkspace& ws, int D) {
+  const int Dp = eig_padded_dim(D);
+  if (ws.Dp >= Dp) return;
+  auto pool = std::make_unique<Pool>();
+  EigWork w;
+  w.M = pool->alloc<double>((long)Dp * Dp);
+  w.M2 = pool->alloc<double>((long)Dp * Dp);
+  w.Psi = pool->alloc<double>((long)Dp * Dp);
+  w.V = pool->alloc<double>(eig_rotation_doubles(Dp));
+  w.part = pool->alloc<double>(3 * (Dp / 8 + 1));
+  w.ctrl = pool->alloc<double>(EIG_CTRL_DOUBLES);
+  w.ctrl_host = pool->alloc_host<double>(EIG_CTRL_DOUBLES);
+  ws.pool = std::move(pool);
+  ws.w = w;
+  ws.Dp = Dp;
 }
 
 template <typename T>
@@ -1220,7 +1524,11 @@ rmhmc_status rmhmc_model_create(const rmhmc_model_desc* desc, rmhmc_precision pr
   return guard([&] {
     RM_REQUIRE(out != nullptr, "out is NULL");
     auto m = std::make_unique<rmhmc_model>();
-    build_model(m->impl, desc, prec);
+    Model& md = m->impl;
+    build_model(md, desc, prec);
+    md.chain_state = make_state(md, 1e6);
+    md.device_bytes = md.pool.bytes + md.api_pt->meta.bytes + md.chain_state->pool.bytes;
+    for (int i = 0; i < 3; ++i) md.device_bytes += md.chain_state->pts[i]->meta.bytes;
     RM_HIP(hipDeviceSynchronize());
     *out = m.release();
   });
@@ -1232,6 +1540,13 @@ rmhmc_status rmhmc_model_dims(const rmhmc_model* m, int* N, int* P, int* D) {
     if (N) *N = m->impl.N;
     if (P) *P = m->impl.P;
     if (D) *D = m->impl.D;
+  });
+}
+
+rmhmc_status rmhmc_model_bytes(const rmhmc_model* m, long long* bytes) {
+  return guard([&] {
+    RM_REQUIRE(m && bytes, "NULL argument");
+    *bytes = (long long)m->impl.device_bytes;
   });
 }
 
@@ -1250,13 +1565,25 @@ rmhmc_status rmhmc_hessian(rmhmc_model* mh, const double* q, double* U, double* 
     RM_REQUIRE(mh && q && U && gradU && H, "NULL argument");
     Model& m = mh->impl;
     RM_REQUIRE(ldh >= m.D, "ldh < D");
+    std::lock_guard<std::mutex> lk(m.busy);
     Point& pt = *m.api_pt;
     copy(pt.q, q, m.D, st);
     check_flag_nonfinite(m, pt.q, m.D, st, "q");
-    compute_hessian(m, pt, st);
+    compute_hessian(m, pt, st, nullptr);
     copy(U, pt.scal + 1, 1, st);
     copy(gradU, pt.gradU, m.D, st);
     copy_matrix(m.D, m.D, pt.H, m.Dp, H, ldh, st);
+    RM_HIP(hipStreamSynchronize(st));   // the model's scratch is free on return
+  });
+}
+
+rmhmc_status rmhmc_softabs_eig_reserve(int D) {
+  return guard([&] {
+    RM_REQUIRE(D >= 1, "D must be >= 1");
+    RM_REQUIRE(eig_padded_dim(D) <= 4096, "D too large");
+    EigWorkspace& ws = eig_workspace();
+    std::lock_guard<std::mutex> lk(ws.mu);
+    eig_workspace_grow(ws, D);
   });
 }
 
@@ -1268,53 +1595,49 @@ rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, do
     RM_REQUIRE(D >= 1 && H && Q && lam && g && gp && logdetG, "bad argument");
     RM_REQUIRE(ldh >= D, "ldh < D");
     RM_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "alpha must be positive");
+    RM_REQUIRE(eig_padded_dim(D) <= 4096, "D too large");
     if (zeta <= 0.0) zeta = 1e-13;
     if (max_sweeps <= 0) max_sweeps = 60;
-    EigCache& c = eig_cache();
+    EigWorkspace& ws = eig_workspace();
+    std::lock_guard<std::mutex> lk(ws.mu);
+    eig_workspace_grow(ws, D);
+    EigWork& w = ws.w;
     const int Dp = eig_padded_dim(D);
-    if (c.Dp < Dp) {
-      RM_HIP(hipDeviceSynchronize());
-      delete c.pool;
-      c.pool = new Pool();
-      c.w.M = c.pool->alloc<double>((long)Dp * Dp);
-      c.w.M2 = c.pool->alloc<double>((long)Dp * Dp);
-      c.w.Psi = c.pool->alloc<double>((long)Dp * Dp);
-      c.w.V = c.pool->alloc<double>(eig_rotation_doubles(Dp));
-      c.w.part = c.pool->alloc<double>(3 * (Dp / 8 + 1));
-      c.w.ctrl = c.pool->alloc<double>(8);
-      c.w.ctrl_host = c.pool->alloc_host<double>(4);
-      c.Dp = Dp;
-    }
-    eig_load_matrix(D, H, ldh, c.w, st);
+    eig_load_matrix(D, H, ldh, w, st);
     if (Q_warm) {
       // M = Qw' H Qw computed through padded copies
-      eig_load_basis(D, Q_warm, D, c.w, st);
+      eig_load_basis(D, Q_warm, D, w, st);
       Gemm<double> a;
       a.m = Dp; a.n = Dp; a.k = Dp;
-      a.A = c.w.M; a.lda = Dp;
-      a.B = c.w.Psi; a.ldb = Dp;
-      a.C = c.w.M2; a.ldc = Dp;
+      a.A = w.M; a.lda = Dp;
+      a.B = w.Psi; a.ldb = Dp;
+      a.C = w.M2; a.ldc = Dp;
       gemm(a, st);
       Gemm<double> b;
       b.m = Dp; b.n = Dp; b.k = Dp;
-      b.A = c.w.Psi; b.lda = Dp; b.tA = true;
-      b.B = c.w.M2; b.ldb = Dp;
-      b.C = c.w.M; b.ldc = Dp;
+      b.A = w.Psi; b.lda = Dp; b.tA = true;
+      b.B = w.M2; b.ldb = Dp;
+      b.C = w.M; b.ldc = Dp;
       gemm(b, st);
-      symmetrize(Dp, c.w.M, Dp, st);
+      symmetrize(Dp, w.M, Dp, st);
     } else {
-      eig_load_basis(D, nullptr, D, c.w, st);
+      eig_load_basis(D, nullptr, D, w, st);
     }
-    int sw = 0;
-    jacobi_eig(D, c.w, zeta, max_sweeps, Q_warm ? JACOBI_INNER_DYNAMIC : JACOBI_INNER_STATIC, &sw,
-               st);
+    const JacobiResult r = jacobi_eig(D, w, zeta, max_sweeps,
+                                      Q_warm ? JACOBI_INNER_DYNAMIC : JACOBI_INNER_STATIC, 0, true,
+                                      nullptr, nullptr, st);
+    if (r.nonfinite) {
+      RM_HIP(hipStreamSynchronize(st));
+      throw Error(RMHMC_E_NONFINITE, "softabs_eig: non-finite entries in the matrix");
+    }
     // static solve: restore orthogonality (M's off-diagonal part is free now)
-    if (!Q_warm) orthonormalise(D, Dp, c.w.Psi, c.w.M2, c.w.M, st);
-    rayleigh_refine(D, H, ldh, c.w, c.w.M2, st);
-    copy_matrix(D, D, c.w.Psi, Dp, Q, D, st);
-    softabs_finalize(D, c.w.M, Dp, alpha, lam, g, gp, logdetG, st);
+    if (!Q_warm) orthonormalise(D, Dp, w.Psi, w.M2, w.M, st);
+    rayleigh_refine(D, H, ldh, w, w.M2, st);
+    copy_matrix(D, D, w.Psi, Dp, Q, D, st);
+    softabs_finalize(D, w.M, Dp, alpha, lam, g, gp, logdetG, st);
     RM_HIP(hipStreamSynchronize(st));
-    if (sweeps) *sweeps = sw;
+    if (sweeps) *sweeps = r.sweeps;
+    if (!r.converged) throw Error(RMHMC_E_EIG_NOCONV, "softabs_eig: Jacobi did not converge");
   });
 }
 
@@ -1325,9 +1648,10 @@ rmhmc_status rmhmc_metric_grad(rmhmc_model* mh, const double* q, const double* p
     RM_REQUIRE(mh && q && p && Q && lam && dHdq && dHdp && ham, "NULL argument");
     RM_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "alpha must be positive");
     Model& m = mh->impl;
+    std::lock_guard<std::mutex> lk(m.busy);
     Point& pt = *m.api_pt;
     copy(pt.q, q, m.D, st);
-    compute_hessian(m, pt, st);
+    compute_hessian(m, pt, st, nullptr);
     // eigen-state supplied by the caller
     eig_load_basis(m.D, Q, m.D, m.eig, st);
     copy(pt.Psi, m.eig.Psi, (long)m.Dp * m.Dp, st);
@@ -1336,6 +1660,7 @@ rmhmc_status rmhmc_metric_grad(rmhmc_model* mh, const double* q, const double* p
     softabs_finalize(m.D, m.eig.M, m.Dp, alpha, pt.lam, pt.g, pt.gp, pt.scal + 2, st);
     pt.have_eig = true;
     grad_q(m, pt, p, alpha, dHdq, dHdp, ham, st);
+    RM_HIP(hipStreamSynchronize(st));
   });
 }
 
@@ -1345,16 +1670,14 @@ rmhmc_status rmhmc_state_create(rmhmc_model* mh, const double* q0, const double*
     RM_REQUIRE(mh && q0 && p0 && out, "NULL argument");
     RM_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "alpha must be positive");
     Model& m = mh->impl;
+    std::lock_guard<std::mutex> lk(m.busy);
     auto s = std::make_unique<rmhmc_state>();
     s->impl = make_state(m, alpha);
     State& S = *s->impl;
     copy(S.pts[0]->q, q0, m.D, st);
     copy(S.p, p0, m.D, st);
     check_flag_nonfinite(m, S.pts[0]->q, m.D, st, "q0");
-    int sw = 0;
-    full_point(m, *S.pts[0], nullptr, alpha, S.zeta, S.max_sweeps, st, &sw);
-    S.sweeps += sw;
-    S.eig_calls += 1;
+    full_point(m, *S.pts[0], nullptr, alpha, S.ec, false, st, nullptr, nullptr);
     RM_HIP(hipStreamSynchronize(st));
     *out = s.release();
   });
@@ -1366,9 +1689,11 @@ rmhmc_status rmhmc_state_get(const rmhmc_state* sh, double* q, double* p, double
     RM_REQUIRE(sh && q && p, "NULL argument");
     State& S = *sh->impl;
     Model& m = *S.m;
+    std::lock_guard<std::mutex> lk(m.busy);
     copy(q, S.pts[0]->q, m.D, st);
     copy(p, S.p, m.D, st);
     if (ham) metric_vectors(m, *S.pts[0], S.p, nullptr, ham, st);
+    RM_HIP(hipStreamSynchronize(st));
   });
 }
 
@@ -1383,18 +1708,30 @@ rmhmc_status rmhmc_state_draw_momentum(rmhmc_state* sh, const double* z, hipStre
   return guard([&] {
     RM_REQUIRE(sh && z, "NULL argument");
     State& S = *sh->impl;
+    std::lock_guard<std::mutex> lk(S.m->busy);
     draw_momentum(*S.m, S, *S.pts[0], z, st);
+    RM_HIP(hipStreamSynchronize(st));
   });
 }
 
 rmhmc_status rmhmc_state_stats(const rmhmc_state* sh, rmhmc_chain_stats* out) {
   return guard([&] {
     RM_REQUIRE(sh && out, "NULL argument");
-    const State& S = *sh->impl;
-    *out = rmhmc_chain_stats{};
-    out->leapfrogs = S.leapfrogs;
-    out->eig_calls = S.eig_calls;
-    out->sweeps = S.sweeps;
+    State& S = *sh->impl;
+    read_stats(S, out, nullptr);
+  });
+}
+
+rmhmc_status rmhmc_chain_randoms(int D, unsigned long long seed, unsigned long long stream_id,
+                                 unsigned long long move, double* z, double* u,
+                                 hipStream_t st) {
+  return guard([&] {
+    RM_REQUIRE(D >= 1 && z && u, "bad argument");
+    hipLaunchKernelGGL(normals_kernel, dim3(cdiv(cdiv(D, 4), 64)), dim3(64), 0, st, D, seed,
+                       stream_id, move, z);
+    RM_CHECK_LAUNCH();
+    hipLaunchKernelGGL(uniform_kernel, dim3(1), dim3(64), 0, st, seed, stream_id, move, u);
+    RM_CHECK_LAUNCH();
   });
 }
 
@@ -1429,19 +1766,32 @@ rmhmc_status rmhmc_glf_step(rmhmc_model* mh, rmhmc_state* sh, double eps, int n_
     RM_REQUIRE(n_fixed_point >= 1, "n_fixed_point must be >= 1");
     RM_REQUIRE(std::isfinite(eps) && eps > 0.0, "eps must be positive");
     State& S = *sh->impl;
-    Point* nxt = leapfrog(S, S.pts[0], nullptr, eps, n_fixed_point, st);
+    std::lock_guard<std::mutex> lk(mh->impl.busy);
+    Point* nxt = leapfrog(S, S.pts[0], nullptr, eps, n_fixed_point, st, nullptr);
+    // one read of the failure word per step; a failed step leaves the state
+    // at its start point
+    RM_HIP(hipMemcpyAsync(S.hfail, S.fail, sizeof(int), hipMemcpyDeviceToHost, st));
+    RM_HIP(hipStreamSynchronize(st));
+    const int f = *S.hfail;
+    if (f) {
+      fill_int(S.fail, 1, 0, st);
+      RM_HIP(hipStreamSynchronize(st));
+      if (f & FAIL_NOT_PD) throw Error(RMHMC_E_NOT_PD, "kernel matrix K is not positive definite");
+      if (f & FAIL_NONFINITE) throw Error(RMHMC_E_NONFINITE, "non-finite values in the leapfrog");
+      throw Error(RMHMC_E_EIG_NOCONV, "softabs_eig: Jacobi did not converge");
+    }
     for (int i = 1; i < 3; ++i)
       if (S.pts[i] == nxt) std::swap(S.pts[0], S.pts[i]);
   });
 }
 
 rmhmc_status rmhmc_chain(rmhmc_model* mh, const rmhmc_chain_cfg* cfg, const double* q0,
-                         const double* z, const double* u, double* samples, double* logpost,
-                         int* accepted, rmhmc_chain_stats* stats, hipStream_t st) {
+                         double* samples, double* logpost, int* accepted,
+                         rmhmc_chain_stats* stats, hipStream_t st) {
   return guard([&] {
     RM_REQUIRE(mh != nullptr, "NULL model");
-    std::lock_guard<std::mutex> lk(mh->busy);
-    chain_impl(mh->impl, cfg, q0, z, u, samples, logpost, accepted, stats, st);
+    std::lock_guard<std::mutex> lk(mh->impl.busy);
+    chain_impl(mh->impl, cfg, q0, samples, logpost, accepted, stats, st);
   });
 }
 
@@ -1463,16 +1813,16 @@ rmhmc_status rmhmc_pool_create(int n_workers, rmhmc_pool** out) {
 }
 
 rmhmc_status rmhmc_pool_submit(rmhmc_pool* pool, rmhmc_model* m, const rmhmc_chain_cfg* cfg,
-                               const double* q0, const double* z, const double* u,
-                               double* samples, double* logpost, int* accepted,
+                               const double* q0, double* samples, double* logpost, int* accepted,
                                long long* ticket) {
   return guard([&] {
-    RM_REQUIRE(pool && m && cfg && q0 && z && u && samples && logpost && accepted && ticket,
+    RM_REQUIRE(pool && m && cfg && q0 && samples && logpost && accepted && ticket,
                "NULL argument");
+    check_chain_cfg(m->impl, cfg);
     auto j = std::make_shared<PoolJob>();
     j->m = m;
     j->cfg = *cfg;
-    j->q0 = q0; j->z = z; j->u = u;
+    j->q0 = q0;
     j->samples = samples; j->logpost = logpost; j->accepted = accepted;
     {
       std::lock_guard<std::mutex> lk(pool->mu);

@@ -31,7 +31,8 @@ EXPORTED = ["rmhmc_model_create", "rmhmc_model_dims", "rmhmc_model_destroy", "rm
             "rmhmc_gemm_f64", "rmhmc_gemm_f32", "rmhmc_gemm_f64_splitk", "rmhmc_last_error",
             "rmhmc_state_draw_momentum",
             "rmhmc_timing_enable", "rmhmc_timing_read", "rmhmc_pool_create", "rmhmc_pool_submit",
-            "rmhmc_pool_poll", "rmhmc_pool_destroy", "rmhmc_state_stats"]
+            "rmhmc_pool_poll", "rmhmc_pool_destroy", "rmhmc_state_stats", "rmhmc_model_bytes",
+            "rmhmc_softabs_eig_reserve", "rmhmc_chain_randoms"]
 
 TIMER_KINDS = {"gemm_f64": 0, "gemm_f32": 1, "jacobi_solve": 2, "jacobi_apply": 3, "kd_wsum": 4,
                "kd_matvec": 5, "potrf_diag": 6}
@@ -50,13 +51,20 @@ class ModelDesc(C.Structure):
 
 class ChainCfg(C.Structure):
     _fields_ = [("eps", C.c_double), ("alpha", C.c_double), ("zeta", C.c_double),
-                ("n_leapfrog", C.c_int), ("n_moves", C.c_int), ("n_fixed_point", C.c_int),
-                ("max_sweeps", C.c_int), ("reorth_every", C.c_int)]
+                ("n_leapfrog", C.c_int), ("n_moves", C.c_int), ("n_burnin", C.c_int),
+                ("n_fixed_point", C.c_int), ("max_sweeps", C.c_int), ("reorth_every", C.c_int),
+                ("seed", C.c_ulonglong), ("stream_id", C.c_ulonglong), ("precision", C.c_int)]
 
 
 class ChainStats(C.Structure):
-    _fields_ = [("accepted", C.c_int), ("failures", C.c_int), ("leapfrogs", C.c_longlong),
-                ("eig_calls", C.c_longlong), ("sweeps", C.c_longlong)]
+    _fields_ = [("accepted", C.c_int), ("accepted_all", C.c_int), ("failures", C.c_int),
+                ("fail_not_pd", C.c_int), ("fail_nonfinite", C.c_int), ("fail_noconv", C.c_int),
+                ("leapfrogs", C.c_longlong), ("eig_calls", C.c_longlong),
+                ("sweeps", C.c_longlong), ("eig_fallbacks", C.c_int),
+                ("max_res_p", C.c_double), ("max_res_q", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _vp = C.c_void_p
@@ -64,6 +72,9 @@ _i, _d = C.c_int, C.c_double
 _sig = {
     "rmhmc_model_create": [C.POINTER(ModelDesc), _i, C.POINTER(_vp)],
     "rmhmc_model_dims": [_vp, C.POINTER(_i), C.POINTER(_i), C.POINTER(_i)],
+    "rmhmc_model_bytes": [_vp, C.POINTER(C.c_longlong)],
+    "rmhmc_softabs_eig_reserve": [_i],
+    "rmhmc_chain_randoms": [_i, C.c_ulonglong, C.c_ulonglong, C.c_ulonglong, _vp, _vp, _vp],
     "rmhmc_model_destroy": [_vp],
     "rmhmc_hessian": [_vp, _vp, _vp, _vp, _vp, _i, _vp],
     "rmhmc_softabs_eig": [_i, _vp, _i, _d, _d, _i, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_i), _vp],
@@ -76,14 +87,14 @@ _sig = {
     "rmhmc_state_stats": [_vp, C.POINTER(ChainStats)],
     "rmhmc_timing_enable": [C.c_uint],
     "rmhmc_pool_create": [_i, C.POINTER(_vp)],
-    "rmhmc_pool_submit": [_vp, _vp, C.POINTER(ChainCfg), _vp, _vp, _vp, _vp, _vp, _vp,
+    "rmhmc_pool_submit": [_vp, _vp, C.POINTER(ChainCfg), _vp, _vp, _vp, _vp,
                           C.POINTER(C.c_longlong)],
     "rmhmc_pool_poll": [_vp, C.c_longlong, _i, C.POINTER(_i), C.POINTER(ChainStats),
                         C.POINTER(_d)],
     "rmhmc_pool_destroy": [_vp],
     "rmhmc_timing_read": [_i, C.POINTER(C.c_longlong), C.POINTER(_d), C.POINTER(_d), C.POINTER(_d)],
     "rmhmc_glf_step": [_vp, _vp, _d, _i, _vp],
-    "rmhmc_chain": [_vp, C.POINTER(ChainCfg), _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(ChainStats), _vp],
+    "rmhmc_chain": [_vp, C.POINTER(ChainCfg), _vp, _vp, _vp, _vp, C.POINTER(ChainStats), _vp],
     "rmhmc_gemm_f64": [_i, _i, _i, _d, _vp, _i, _i, _vp, _i, _i, _d, _vp, _i, _vp],
     "rmhmc_gemm_f64_splitk": [_i, _i, _i, _vp, _i, _i, _vp, _i, _i, _vp, _i, _vp, _i, _vp],
     "rmhmc_gemm_f32": [_i, _i, _i, C.c_float, _vp, _i, _i, _vp, _i, _i, C.c_float, _vp, _i, _vp],
@@ -175,6 +186,7 @@ class Model:
         _check(_lib.rmhmc_model_dims(h, C.byref(N), C.byref(P), C.byref(D)))
         self.N, self.P, self.D = N.value, P.value, D.value
         self.spec = spec
+        self.precision = precision
 
     def close(self):
         if getattr(self, "_h", None):
@@ -207,19 +219,46 @@ class Model:
                                       _f64(dq), _f64(dp), _f64(ham), _stream(stream)))
         return dq, dp, ham
 
-    def chain(self, q0, z, u, eps, n_leapfrog, n_fixed_point, alpha=1e6, zeta=0.0,
-              max_sweeps=0, reorth_every=0, stream=None):
+    @property
+    def device_bytes(self):
+        b = C.c_longlong()
+        _check(_lib.rmhmc_model_bytes(self._h, C.byref(b)))
+        return b.value
+
+    def chain(self, q0, eps, n_leapfrog, n_fixed_point, n_moves, n_burnin=0, seed=0,
+              stream_id=0, alpha=1e6, zeta=0.0, max_sweeps=0, reorth_every=0, stream=None):
+        """Algorithm 1 on the device; returns (samples, logpost, accepted, stats)
+        for the moves n_burnin .. n_moves-1."""
         torch = _torch()
-        n_moves = z.shape[0]
-        samples = torch.empty((n_moves, self.D), dtype=torch.float64, device=q0.device)
-        logpost = torch.empty(n_moves, dtype=torch.float64, device=q0.device)
-        acc = torch.empty(n_moves, dtype=torch.int32, device=q0.device)
-        cfg = ChainCfg(eps, alpha, zeta, n_leapfrog, n_moves, n_fixed_point, max_sweeps, reorth_every)
+        kept = n_moves - n_burnin
+        samples = torch.empty((max(kept, 1), self.D), dtype=torch.float64, device=q0.device)
+        logpost = torch.empty(max(kept, 1), dtype=torch.float64, device=q0.device)
+        acc = torch.empty(max(kept, 1), dtype=torch.int32, device=q0.device)
+        cfg = chain_cfg(self, eps, n_leapfrog, n_fixed_point, n_moves, n_burnin, seed, stream_id,
+                        alpha, zeta, max_sweeps, reorth_every)
         stats = ChainStats()
-        _check(_lib.rmhmc_chain(self._h, C.byref(cfg), _f64(q0), _f64(z), _f64(u), _f64(samples),
-                                _f64(logpost), _ptr(acc, torch.int32), C.byref(stats),
-                                _stream(stream)))
-        return samples, logpost, acc, stats
+        _check(_lib.rmhmc_chain(self._h, C.byref(cfg), _f64(q0), _f64(samples), _f64(logpost),
+                                _ptr(acc, torch.int32), C.byref(stats), _stream(stream)))
+        return samples[:kept], logpost[:kept], acc[:kept], stats
+
+
+def chain_cfg(model, eps, n_leapfrog, n_fixed_point, n_moves, n_burnin=0, seed=0, stream_id=0,
+              alpha=1e6, zeta=0.0, max_sweeps=0, reorth_every=0):
+    return ChainCfg(eps, alpha, zeta, n_leapfrog, n_moves, n_burnin, n_fixed_point, max_sweeps,
+                    reorth_every, seed, stream_id, model.precision)
+
+
+def chain_randoms(D, seed, stream_id, move, stream=None):
+    """(z, u) of one move of the chain (seed, stream_id), drawn on the device."""
+    torch = _torch()
+    z = torch.empty(D, dtype=torch.float64, device="cuda")
+    u = torch.empty(1, dtype=torch.float64, device="cuda")
+    _check(_lib.rmhmc_chain_randoms(D, seed, stream_id, move, _f64(z), _f64(u), _stream(stream)))
+    return z, u
+
+
+def softabs_eig_reserve(D):
+    _check(_lib.rmhmc_softabs_eig_reserve(D))
 
 
 def softabs_eig(H, alpha, Q_warm=None, zeta=0.0, max_sweeps=0, stream=None):
@@ -303,13 +342,13 @@ def timing_read(kind):
 class ChainJob:
     """Device buffers of one submitted chain (kept alive until collected)."""
 
-    def __init__(self, model, q0, z, u, cfg):
+    def __init__(self, model, q0, cfg):
         torch = _torch()
-        n_moves = z.shape[0]
-        self.model, self.q0, self.z, self.u, self.cfg = model, q0, z, u, cfg
-        self.samples = torch.empty((n_moves, model.D), dtype=torch.float64, device=q0.device)
-        self.logpost = torch.empty(n_moves, dtype=torch.float64, device=q0.device)
-        self.accepted = torch.empty(n_moves, dtype=torch.int32, device=q0.device)
+        kept = max(cfg.n_moves - cfg.n_burnin, 1)
+        self.model, self.q0, self.cfg = model, q0, cfg
+        self.samples = torch.empty((kept, model.D), dtype=torch.float64, device=q0.device)
+        self.logpost = torch.empty(kept, dtype=torch.float64, device=q0.device)
+        self.accepted = torch.empty(kept, dtype=torch.int32, device=q0.device)
         self.ticket = None
         self.stats = None
         self.times_ms = None
@@ -324,14 +363,15 @@ class Pool:
         self._h = h
         self.n_workers = n_workers
 
-    def submit(self, model, q0, z, u, eps, n_leapfrog, n_fixed_point, alpha=1e6, zeta=0.0,
-               max_sweeps=0, reorth_every=0):
+    def submit(self, model, q0, eps, n_leapfrog, n_fixed_point, n_moves, n_burnin=0, seed=0,
+               stream_id=0, alpha=1e6, zeta=0.0, max_sweeps=0, reorth_every=0):
         torch = _torch()
-        job = ChainJob(model, q0, z, u, ChainCfg(eps, alpha, zeta, n_leapfrog, z.shape[0],
-                                                 n_fixed_point, max_sweeps, reorth_every))
+        job = ChainJob(model, q0, chain_cfg(model, eps, n_leapfrog, n_fixed_point, n_moves,
+                                            n_burnin, seed, stream_id, alpha, zeta, max_sweeps,
+                                            reorth_every))
         t = C.c_longlong()
-        _check(_lib.rmhmc_pool_submit(self._h, model._h, C.byref(job.cfg), _f64(q0), _f64(z),
-                                      _f64(u), _f64(job.samples), _f64(job.logpost),
+        _check(_lib.rmhmc_pool_submit(self._h, model._h, C.byref(job.cfg), _f64(q0),
+                                      _f64(job.samples), _f64(job.logpost),
                                       _ptr(job.accepted, torch.int32), C.byref(t)))
         job.ticket = t.value
         return job

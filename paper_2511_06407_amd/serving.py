@@ -173,10 +173,9 @@ class PoolExecutor:
         import torch
         spec, eps = request_spec(req)
         model = self.rm.Model(spec)
-        z, u = wl.chain_randoms(spec.D, req.n_moves, seed=req.seed)
-        dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")  # noqa
-        job = self.pool.submit(model, dev(np.zeros(spec.D)), dev(z), dev(u), eps,
-                               self.n_leapfrog, self.K, self.alpha)
+        q0 = torch.zeros(spec.D, dtype=torch.float64, device="cuda")
+        job = self.pool.submit(model, q0, eps, self.n_leapfrog, self.K, req.n_moves,
+                               seed=req.seed, stream_id=req.rid, alpha=self.alpha)
         return job
 
     def done(self, job):

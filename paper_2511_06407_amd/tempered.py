@@ -45,10 +45,7 @@ def run_tempered(n_chains=64, n_moves=20, n_leapfrog=10, n_fixed_point=6, eps=0.
         drawn_dims = np.full(n_chains, dims)
     models = [rmhmc.Model(s) for s in specs]
     dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")  # noqa
-    inputs = []
-    for k, s in enumerate(specs):
-        z, u = wl.chain_randoms(s.D, n_moves, seed=seed, stream=k)
-        inputs.append((dev(np.zeros(s.D)), dev(z), dev(u)))
+    inputs = [dev(np.zeros(s.D)) for s in specs]
     pool = rmhmc.Pool(n_workers)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -56,8 +53,8 @@ def run_tempered(n_chains=64, n_moves=20, n_leapfrog=10, n_fixed_point=6, eps=0.
     order = np.argsort(-drawn_dims, kind="stable")
     jobs = {}
     for k in order:
-        q0, z, u = inputs[k]
-        jobs[k] = pool.submit(models[k], q0, z, u, eps, n_leapfrog, n_fixed_point, alpha)
+        jobs[k] = pool.submit(models[k], inputs[k], eps, n_leapfrog, n_fixed_point, n_moves,
+                              seed=seed, stream_id=k, alpha=alpha)
     for k in order:
         pool.wait(jobs[k])
         if log:

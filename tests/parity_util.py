@@ -8,6 +8,9 @@ order (a mathematically identical problem); a GPU result is held to
 max(bar, 10 x floor).
 """
 import dataclasses
+import json
+import os
+import sys
 
 import numpy as np
 
@@ -44,6 +47,35 @@ def unpermute_mat(M2, full):
 
 
 def record(name, **vals):
-    """Print one line of measured errors (kept in the pytest log)."""
+    """Print one line of measured errors (kept in the pytest log) and, when
+    RMHMC_PARITY_LOG names a file, append it there as JSON."""
     items = " ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}" for k, v in vals.items())
     print(f"[parity] {name} {items}", flush=True)
+    path = os.environ.get("RMHMC_PARITY_LOG")
+    if path:
+        clean = {k: (float(v) if isinstance(v, (float, np.floating)) else
+                     int(v) if isinstance(v, (np.integer,)) else v) for k, v in vals.items()}
+        with open(path, "a") as f:
+            f.write(json.dumps({"case": name, **clean}) + "\n")
+
+
+def progress(msg):
+    """A progress line on the real stderr (long reference runs)."""
+    print(f"[progress] {msg}", file=sys.__stderr__, flush=True)
+
+
+def chain_floor(spec, eps, n_leapfrog, n_fixed_point, alpha, n_moves, seed, stream, ref):
+    """Floor of a seeded reference chain (oracle.chain.run_seeded_chain with
+    n_burnin = 0, result `ref`): the same chain with the data points in
+    another order and the momentum normals permuted alike (p = G^{1/2} z is
+    then the permuted momentum).  inf if the accept decisions differ."""
+    from oracle import hamiltonian as oham, rng
+    from oracle.chain import run_chain
+    q0 = np.zeros(spec.D)
+    s2, _, full = permuted(spec, q0)
+    z, u = rng.chain_randoms(seed, stream, n_moves, spec.D)
+    ref2 = run_chain(oham.GPTarget(s2), q0, eps, n_leapfrog, n_fixed_point, alpha, z[:, full], u)
+    if not np.array_equal(ref2[2], ref[2]):
+        return float("inf")
+    back = np.stack([unpermute_vec(r, full) for r in ref2[0]])
+    return max(rel(back, ref[0]), rel(ref2[1], ref[1]))

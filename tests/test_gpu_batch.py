@@ -10,8 +10,8 @@ torch = pytest.importorskip("torch")
 
 from paper_2511_06407_amd import workloads as wl  # noqa: E402
 from oracle import hamiltonian as oham  # noqa: E402
-from oracle.chain import run_chain  # noqa: E402
-from tests.parity_util import rel, record  # noqa: E402
+from oracle.chain import run_seeded_chain  # noqa: E402
+from tests.parity_util import rel, record, chain_floor  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -39,16 +39,16 @@ def test_pool_mix_equals_alone(rm):
     n_moves, C_, K = 3, 2, 6
     runs = []
     for k, (spec, eps) in enumerate(specs_mix()):
-        z, u = wl.chain_randoms(spec.D, n_moves, seed=1, stream=k)
-        runs.append((spec, eps, dev(np.zeros(spec.D)), dev(z), dev(u)))
+        runs.append((spec, eps, dev(np.zeros(spec.D)), k))
     alone = []
-    for spec, eps, q0, z, u in runs:
-        s, l, a, st = rm.Model(spec).chain(q0, z, u, eps, C_, K)
+    for spec, eps, q0, k in runs:
+        s, l, a, st = rm.Model(spec).chain(q0, eps, C_, K, n_moves, seed=1, stream_id=k)
         torch.cuda.synchronize()
         alone.append((s.cpu().numpy(), l.cpu().numpy(), a.cpu().numpy()))
     pool = rm.Pool(3)
     models = [rm.Model(spec) for spec, *_ in runs]
-    jobs = [pool.submit(m, q0, z, u, eps, C_, K) for m, (spec, eps, q0, z, u) in zip(models, runs)]
+    jobs = [pool.submit(m, q0, eps, C_, K, n_moves, seed=1, stream_id=k)
+            for m, (spec, eps, q0, k) in zip(models, runs)]
     for j in jobs:
         assert pool.wait(j)
     torch.cuda.synchronize()
@@ -75,13 +75,14 @@ def test_tempered_ladder_runs_and_matches_reference(rm):
     k = int(np.argmin([c["D"] for c in out["chains"]]))
     specs, dims, betas = wl.tempered_ladder(6, 0)
     spec = specs[k]
-    z, u = wl.chain_randoms(spec.D, 2, seed=0, stream=k)
-    ref = run_chain(oham.GPTarget(spec), np.zeros(spec.D), 0.01, 2, 6, 1e6, z, u)
+    ref = run_seeded_chain(oham.GPTarget(spec), np.zeros(spec.D), 0.01, 2, 6, 1e6, 2, 0, 0, k)
     got = out["jobs"][k].samples.cpu().numpy()
     e = rel(got, ref[0])
-    record("tempered_ref", chain=k, D=spec.D, beta=float(betas[k]), samples=e)
+    fl = chain_floor(spec, 0.01, 2, 6, 1e6, 2, 0, k, ref)
+    bar = max(1e-10, 10 * fl)
+    record("tempered_ref", chain=k, D=spec.D, beta=float(betas[k]), samples=e, floor=fl, bar=bar)
     assert np.array_equal(out["jobs"][k].accepted.cpu().numpy(), ref[2])
-    assert e < 1e-7
+    assert e < bar
 
 
 def test_serving_results_same_alone_and_in_mix(rm):
@@ -104,8 +105,8 @@ def test_serving_results_same_alone_and_in_mix(rm):
     assert sch.max_running >= 2
     for r in reqs[:3]:
         spec, eps = sv.request_spec(r)
-        z, u = wl.chain_randoms(spec.D, r.n_moves, seed=r.seed)
-        s, l, a, st = rm.Model(spec).chain(dev(np.zeros(spec.D)), dev(z), dev(u), eps, 2, 6)
+        s, l, a, st = rm.Model(spec).chain(dev(np.zeros(spec.D)), eps, 2, 6, r.n_moves,
+                                           seed=r.seed, stream_id=r.rid)
         torch.cuda.synchronize()
         assert np.array_equal(s.cpu().numpy(), kept[r.rid].samples.cpu().numpy())
     ex.close()

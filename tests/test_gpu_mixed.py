@@ -1,12 +1,13 @@
 """GPU mixed precision: FP32 MFMA products (A_l, B_l, Y_lm and the trace
 GEMMs) with FP64 Cholesky, eigensolver, softabs branch and log|G|.
 
-Bar: error against the FP64 reference below max(1e-4, 10 x floor), where the
-floor is how far the FP64 reference itself moves when its A_l = K^-1 K_l and
-B_l = A_l K^-1 are formed from float32-rounded operands and rounded to
-float32 (the rounding the mixed path applies).  On well-conditioned kernels
-the floor is far below 1e-4; with jitter 1e-6 K^-1 reaches 1e6 and the
-floor grows with it."""
+Bar: every output within 1e-4 of the FP64 reference, norm-wise.  On an
+ill-conditioned kernel matrix (jitter 1e-6) the bar is max(1e-4, 10 x floor),
+the floor being the FP64 reference's own disagreement with itself on the
+same problem with the data points reordered; the well-conditioned set
+(jitter 1e-2) is held to 1e-4 strictly.  Every measured error, floor and bar
+is recorded."""
+import concurrent.futures as cf
 import dataclasses
 
 import numpy as np
@@ -18,7 +19,7 @@ from paper_2511_06407_amd import workloads as wl  # noqa: E402
 from oracle import model as omodel, hamiltonian as oham  # noqa: E402
 from oracle.integrator import glf_step as oglf  # noqa: E402
 from oracle.chain import momentum as omomentum  # noqa: E402
-from tests.parity_util import rel, record  # noqa: E402
+from tests.parity_util import rel, record, permuted, unpermute_vec, unpermute_mat, progress  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 BAR_MIXED = 1e-4
@@ -42,47 +43,89 @@ def host(t):
 
 
 CASES = {
-    "mkl_d104": wl.propensity_mkl(90, seed=2)[0],
-    "mkl_d270": wl.propensity_mkl(256, seed=0)[0],
-    "c1_d34": wl.workload("gp_logistic_d34")[0],
+    "mkl_d104_wellcond": (dataclasses.replace(wl.propensity_mkl(90, seed=2)[0], jitter=1e-2), True),
+    "mkl_d104": (wl.propensity_mkl(90, seed=2)[0], False),
+    "mkl_d270": (wl.propensity_mkl(256, seed=0)[0], False),
+    "c1_d34": (wl.workload("gp_logistic_d34")[0], False),
 }
+
+
+def _reference(args):
+    """U, grad U, H, dH/dq, dH/dp and H(q,p) of the FP64 reference."""
+    spec, q, p, alpha = args
+    U, g, H = omodel.hessian(spec, q)
+    st = oham.State(oham.GPTarget(spec), q, alpha)
+    return U, g, H, oham.grad_q(st, p), oham.grad_p(st, p), oham.hamiltonian(st, p), st
+
+
+def check_mixed_point(rm, name, spec, q, alpha, strict):
+    st = oham.State(oham.GPTarget(spec), q, alpha)
+    p = omomentum(st, np.random.default_rng(4).standard_normal(spec.D))
+    s2, q2, full = permuted(spec, q)
+    with cf.ProcessPoolExecutor(2) as ex:
+        fa = ex.submit(_reference, (spec, q, p, alpha))
+        fb = ex.submit(_reference, (s2, q2, p[full], alpha))
+        ref, ref2 = fa.result(), fb.result()
+    st = ref[6]
+    M = rm.Model(spec, precision=rm.MIXED)
+    U, g, H = M.hessian(dev(q))
+    dq, dp, ham = M.metric_grad(dev(q), dev(p), dev(st.eig["Psi"].T), dev(st.eig["lam"]), alpha)
+    got = (host(U), host(g), host(H), host(dq), host(dp), host(ham))
+    names = ("U", "grad", "H", "dHdq", "dHdp", "ham")
+    unperm = (lambda x: x, lambda v: unpermute_vec(v, full), lambda A: unpermute_mat(A, full),
+              lambda v: unpermute_vec(v, full), lambda v: unpermute_vec(v, full), lambda x: x)
+    errs = {k: rel(got[i], ref[i]) for i, k in enumerate(names)}
+    fl = max(rel(unperm[i](ref2[i]), ref[i]) for i in range(6))
+    bar = BAR_MIXED if strict else max(BAR_MIXED, 10 * fl)
+    record("mixed", model=name, D=spec.D, jitter=spec.jitter, floor=fl, bar=bar, **errs)
+    for k, e in errs.items():
+        assert e < bar, (k, e, bar)
 
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_mixed_hessian_and_gradient(rm, name):
-    spec = CASES[name]
+    spec, strict = CASES[name]
     q = 0.2 * np.random.default_rng(3).standard_normal(spec.D)
-    M = rm.Model(spec, precision=rm.MIXED)
-    U, g, H = M.hessian(dev(q))
-    ref = omodel.hessian(spec, q)
-    eU, eg, eH = rel(host(U), ref[0]), rel(host(g), ref[1]), rel(host(H), ref[2])
-    T = oham.GPTarget(spec)
-    st = oham.State(T, q, 1e6)
-    p = omomentum(st, np.random.default_rng(4).standard_normal(spec.D))
-    dq, dp, ham = M.metric_grad(dev(q), dev(p), dev(st.eig["Psi"].T), dev(st.eig["lam"]), 1e6)
-    ref_dq = oham.grad_q(st, p)
-    e_dq = rel(host(dq), ref_dq)
-    e_h = rel(host(ham), oham.hamiltonian(st, p))
-    # floor: the reference with float32-rounded products, same eigen-state
-    f32 = lambda X: np.asarray(X, dtype=np.float32).astype(np.float64)   # noqa: E731
-    ref32 = omodel.hessian(spec, q, f32)
-    st32 = oham.State(oham.GPTarget(spec, f32), q, 1e6)
-    st32.eig = st.eig
-    fl = max(rel(ref32[2], ref[2]), rel(oham.grad_q(st32, p), ref_dq))
-    bar = max(BAR_MIXED, 10 * fl)
-    record("mixed", model=name, U=eU, grad=eg, H=eH, dHdq=e_dq, ham=e_h, floor=fl, bar=bar)
-    assert max(eU, eg, eH, e_dq, e_h) < bar
+    check_mixed_point(rm, name, spec, q, 1e6, strict)
 
 
-def test_mixed_leapfrog(rm):
-    spec = CASES["mkl_d104"]
-    q = 0.2 * np.random.default_rng(5).standard_normal(spec.D)
+@pytest.mark.timeout(900)
+def test_mixed_full_size(rm):
+    """The benchmarked workload (D = 1038, jitter 1e-6) in mixed precision."""
+    spec, cfg = wl.workload("propensity_mkl_d1038")
+    q = 0.05 * np.random.default_rng(31).standard_normal(spec.D)
+    check_mixed_point(rm, "propensity_mkl_d1038", spec, q, cfg.alpha, False)
+
+
+def _glf_ref(args):
+    spec, q, p, eps, K, alpha = args
+    st, pn = oglf(oham.State(oham.GPTarget(spec), q, alpha), p, eps, K)
+    return st.q, pn
+
+
+@pytest.mark.parametrize("name,eps", [("mkl_d104_wellcond", 0.003), ("mkl_d104", 0.003),
+                                      ("full_d1038", 0.003)])
+@pytest.mark.timeout(900)
+def test_mixed_leapfrog(rm, name, eps):
+    if name == "full_d1038":
+        spec, strict = wl.workload("propensity_mkl_d1038")[0], False
+        q = 0.05 * np.random.default_rng(5).standard_normal(spec.D)
+    else:
+        spec, strict = CASES[name]
+        q = 0.2 * np.random.default_rng(5).standard_normal(spec.D)
     st = oham.State(oham.GPTarget(spec), q, 1e6)
     p = omomentum(st, np.random.default_rng(6).standard_normal(spec.D))
     S = rm.State(rm.Model(spec, precision=rm.MIXED), dev(q), dev(p), 1e6)
-    S.step(0.003, 6)
-    ref_st, ref_p = oglf(st, p, 0.003, 6)
+    S.step(eps, 6)
     qg, pg, _ = S.get()
-    e_q, e_p = rel(host(qg), ref_st.q), rel(host(pg), ref_p)
-    record("mixed_glf", q=e_q, p=e_p)
-    assert e_q < BAR_MIXED and e_p < BAR_MIXED
+    progress(f"mixed leapfrog {name} on the GPU done; reference runs started")
+    s2, q2, full = permuted(spec, q)
+    with cf.ProcessPoolExecutor(2) as ex:
+        fa = ex.submit(_glf_ref, (spec, q, p, eps, 6, 1e6))
+        fb = ex.submit(_glf_ref, (s2, q2, p[full], eps, 6, 1e6))
+        (rq, rp), (q2n, p2n) = fa.result(), fb.result()
+    fl = max(rel(unpermute_vec(q2n, full), rq), rel(unpermute_vec(p2n, full), rp))
+    bar = BAR_MIXED if strict else max(BAR_MIXED, 10 * fl)
+    e_q, e_p = rel(host(qg), rq), rel(host(pg), rp)
+    record("mixed_glf", model=name, D=spec.D, q=e_q, p=e_p, floor=fl, bar=bar)
+    assert e_q < bar and e_p < bar

@@ -13,10 +13,11 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from paper_2511_06407_amd import workloads as wl  # noqa: E402
-from oracle import model as omodel, softabs as osoft, hamiltonian as oham  # noqa: E402
+from oracle import model as omodel, softabs as osoft, hamiltonian as oham, rng as orng  # noqa: E402
 from oracle.integrator import glf_step as oglf  # noqa: E402
-from oracle.chain import run_chain, momentum as omomentum  # noqa: E402
-from tests.parity_util import rel, permuted, unpermute_mat, unpermute_vec, record  # noqa: E402
+from oracle.chain import run_seeded_chain, momentum as omomentum  # noqa: E402
+from tests.parity_util import (rel, permuted, unpermute_mat, unpermute_vec, record,  # noqa: E402
+                               chain_floor, progress)
 
 pytestmark = pytest.mark.gpu
 BAR = 1e-10
@@ -365,21 +366,115 @@ def test_glf_step_parity(rm, name, eps):
         assert e_q < tol and e_p < tol and e_h < max(tol, 1e-12)
 
 
+def _glf_ref(args):
+    """Two reference leapfrogs from (q, p) on spec (run in a worker process)."""
+    spec, q, p, eps, K, alpha = args
+    st = oham.State(oham.GPTarget(spec), q, alpha)
+    out = []
+    for _ in range(2):
+        st, p = oglf(st, p, eps, K)
+        out.append((st.q.copy(), p.copy(), oham.hamiltonian(st, p)))
+    return out
+
+
+@pytest.mark.timeout(1500)
+def test_glf_step_parity_full_size(rm):
+    """Two generalized leapfrogs of the benchmarked workload itself (D = 1038:
+    N = 1024, P = 14, jitter 1e-6) at its step size, against the reference
+    and its permutation floor (the two reference runs go to two processes)."""
+    import concurrent.futures as cf
+    spec, cfg = wl.workload("propensity_mkl_d1038")
+    q = rand_q(spec, 41, 0.05)
+    alpha, K, eps = cfg.alpha, cfg.n_fixed_point, cfg.eps
+    st = oham.State(oham.GPTarget(spec), q, alpha)
+    p = omomentum(st, np.random.default_rng(42).standard_normal(spec.D))
+    S = rm.State(rm.Model(spec), dev(q), dev(p), alpha)
+    got = []
+    for _ in range(2):
+        S.step(eps, K)
+        qg, pg, hg = S.get()
+        got.append((host(qg), host(pg), float(host(hg)[0])))
+    progress("full-size leapfrogs on the GPU done; reference runs started")
+    s2, q2, full = permuted(spec, q)
+    with cf.ProcessPoolExecutor(2) as ex:
+        fa = ex.submit(_glf_ref, (spec, q, p, eps, K, alpha))
+        fb = ex.submit(_glf_ref, (s2, q2, p[full], eps, K, alpha))
+        ref, ref2 = fa.result(), fb.result()
+    for step in range(2):
+        rq, rp, rh = ref[step]
+        q2s, p2s, _ = ref2[step]
+        fl = max(rel(unpermute_vec(q2s, full), rq), rel(unpermute_vec(p2s, full), rp))
+        e_q, e_p, e_h = rel(got[step][0], rq), rel(got[step][1], rp), rel(got[step][2], rh)
+        tol = max(BAR, 10 * fl)
+        record("glf_step_full", D=spec.D, step=step, q=e_q, p=e_p, ham=e_h, floor=fl, bar=tol)
+        assert e_q < tol and e_p < tol and e_h < max(tol, 1e-12)
+
+
 # ---------------------------------------------------------------- chain
+def test_chain_randoms_match_reference(rm):
+    """The device Philox4x64-10 stream: uniforms bit for bit, normals to the
+    last place (the two sides' log/sqrt/sin/cos)."""
+    for seed, stream, move, D in ((0, 0, 0, 34), (7, 3, 5, 1038), (2 ** 63 + 5, 2 ** 40, 123, 9)):
+        z, u = rm.chain_randoms(D, seed, stream, move)
+        zr = orng.momentum_normals(seed, stream, move, D)
+        ur = orng.mh_uniform(seed, stream, move)
+        ez = float(np.max(np.abs(host(z) - zr)))
+        record("chain_randoms", seed=seed, stream=stream, move=move, D=D, z_maxabs=ez)
+        assert float(host(u)[0]) == ur
+        assert ez < 1e-14
+
+
 def test_chain_parity_c1(rm):
+    """Algorithm 1 on the device against the reference, same (seed, stream):
+    identical accept decisions, samples within 10 x the reference's own
+    permutation floor; burn-in moves are not returned."""
     spec, cfg = wl.workload("gp_logistic_d34")
     T = oham.GPTarget(spec)
-    n_moves, C_, K = 4, 3, cfg.n_fixed_point
-    z, u = wl.chain_randoms(spec.D, n_moves, seed=0)
+    n_moves, n_burnin, C_, K = 5, 1, 3, cfg.n_fixed_point
     q0 = np.zeros(spec.D)
     M = rm.Model(spec)
-    samples, logpost, acc, stats = M.chain(dev(q0), dev(z), dev(u), cfg.eps, C_, K, alpha=cfg.alpha)
-    ref = run_chain(T, q0, cfg.eps, C_, K, cfg.alpha, z, u)
+    samples, logpost, acc, stats = M.chain(dev(q0), cfg.eps, C_, K, n_moves, n_burnin=n_burnin,
+                                           seed=11, stream_id=2, alpha=cfg.alpha)
+    ref = run_seeded_chain(T, q0, cfg.eps, C_, K, cfg.alpha, n_moves, n_burnin, 11, 2)
+    ref_all = run_seeded_chain(T, q0, cfg.eps, C_, K, cfg.alpha, n_moves, 0, 11, 2)
+    fl = chain_floor(spec, cfg.eps, C_, K, cfg.alpha, n_moves, 11, 2, ref_all)
+    bar = max(BAR, 10 * fl)
     gs, gl, ga = host(samples), host(logpost), host(acc)
+    # decisions within 1e-8 of the threshold may legitimately flip
+    margin = np.abs(np.log([orng.mh_uniform(11, 2, m) for m in range(n_moves)])
+                    - (ref_all[4] - ref_all[5]))
     record("chain_c1", accepted=int(ga.sum()), ref_accepted=int(ref[2].sum()),
-           samples=rel(gs, ref[0]), logpost=rel(gl, ref[1]), sweeps=stats.sweeps,
-           eig_calls=stats.eig_calls)
+           samples=rel(gs, ref[0]), logpost=rel(gl, ref[1]), floor=fl, bar=bar,
+           min_margin=float(margin.min()), sweeps=stats.sweeps, eig_calls=stats.eig_calls,
+           res_p=stats.max_res_p, res_q=stats.max_res_q)
+    assert margin.min() > 1e-8
+    assert gs.shape == (n_moves - n_burnin, spec.D)
     assert ref[2].sum() >= 2            # the reference accepts at this step size
     assert np.array_equal(ga, ref[2])
-    assert rel(gs, ref[0]) < 1e-8 and rel(gl, ref[1]) < 1e-8
+    assert rel(gs, ref[0]) < bar and rel(gl, ref[1]) < bar
     assert stats.leapfrogs == n_moves * C_
+    assert stats.accepted == int(ref[2].sum()) and stats.accepted_all == int(ref_all[2].sum())
+    assert stats.failures == 0
+    assert stats.max_res_p < 1e-6 and stats.max_res_q < 1e-6
+
+
+def test_chain_failures_are_rejections(rm):
+    """A first point the eigensolver cannot finish (one sweep allowed) is an
+    error; a step size far beyond stability (eps = 5) makes every trajectory
+    leave the domain, as in the reference: each move is a counted failure and
+    a rejection, and q stays at q0."""
+    spec, cfg = wl.workload("gp_logistic_d34")
+    q0 = np.zeros(spec.D)
+    M = rm.Model(spec)
+    with pytest.raises(rm.RmhmcError):
+        M.chain(dev(q0), cfg.eps, 2, 3, 2, max_sweeps=1)
+    with np.errstate(all="ignore"):
+        ref = run_seeded_chain(oham.GPTarget(spec), q0, 5.0, 2, 3, cfg.alpha, 3, 0, 3, 0)
+    assert not ref[2].any() and not np.isfinite(ref[5]).any()
+    samples, logpost, acc, stats = M.chain(dev(q0), 5.0, 2, 3, 3, seed=3)
+    record("chain_fail", failures=stats.failures, not_pd=stats.fail_not_pd,
+           nonfinite=stats.fail_nonfinite, noconv=stats.fail_noconv, accepted=stats.accepted)
+    assert stats.failures == 3 and stats.accepted == 0
+    assert stats.failures <= stats.fail_not_pd + stats.fail_nonfinite + stats.fail_noconv
+    assert not host(acc).any()
+    assert np.array_equal(host(samples), np.zeros((3, spec.D)))

@@ -118,16 +118,43 @@ def test_harmonic_oscillator_closed_form():
 
 
 def test_reversibility_gp():
+    """Reversibility of the generalized leapfrog (Eq. leapfrog): integrating
+    back from (q', -p') returns to (q, -p).  It holds for the exact solution of
+    the two implicit equations, so it is checked where the K fixed-point
+    iterations have converged to rounding (asserted from the logged
+    residuals).  At eps = 0.02 the fixed-point map is no contraction for this
+    draw p ~ N(0, G(q)) (its Lipschitz constant grows with eps |G^-1 dG G^-1 p|):
+    the iterations stop converging and the trajectory fails (also asserted),
+    so the pin uses eps = 0.005."""
     T = gp_target(N=6, seed=8)
     rng = np.random.default_rng(8)
     q = 0.3 * rng.standard_normal(T.D)
     st0 = ham.State(T, q, 1e6)
     p0 = momentum(st0, rng.standard_normal(T.D))       # p ~ N(0, G(q))
-    st1, p1 = trajectory(st0, p0, 0.005, 5, 12)
+    log = {}
+    st, p = st0, p0
+    for _ in range(5):
+        st, p = glf_step(st, p, 0.005, 12, log)
+    st1, p1 = st, p
     assert np.linalg.norm(st1.q - q) > 0.1                  # it did move
+    for rp, rq in zip(log["res_p"], log["res_q"]):          # solved to rounding
+        assert rp[-1] < 1e-12 * np.linalg.norm(p0) and rq[-1] < 1e-12 * max(1, np.linalg.norm(q))
     st2, p2 = trajectory(st1, -p1, 0.005, 5, 12)
     assert np.linalg.norm(st2.q - q) < 1e-11 * max(1, np.linalg.norm(q))
     assert np.linalg.norm(p2 + p0) < 1e-11 * np.linalg.norm(p0)
+    # the same draw at eps = 0.02: the fixed-point iterations stop converging
+    # to rounding, and the trajectory leaves the domain of U within 5 steps
+    log2, solved = {}, True
+    with np.errstate(all="ignore"):
+        try:
+            st, p = st0, p0
+            for _ in range(5):
+                st, p = glf_step(st, p, 0.02, 12, log2)
+        except FloatingPointError:
+            solved = False
+    solved = solved and all(rp[-1] < 1e-12 * np.linalg.norm(p0) and rq[-1] < 1e-12
+                            for rp, rq in zip(log2["res_p"], log2["res_q"]))
+    assert not solved
 
 
 def test_energy_error_is_second_order():

@@ -1,5 +1,6 @@
 """Pins of the reference U, grad U, H and v(W) = grad tr(W H) by the complex-step
-derivative (Squire & Trapp 1998), which is exact to rounding for analytic code.
+derivative (Squire & Trapp 1998), which is exact to rounding for analytic code,
+and of the kernel matrix itself by entries worked out by hand.
 
 Models: every kernel kind (isotropic SE, SE-ARD, linear-ARD, same-value binary),
 both likelihoods, a tempered likelihood (beta != 1) and random points q.
@@ -116,23 +117,43 @@ def test_gaussian_likelihood_fixed_eta_textbook():
     assert np.allclose(H[:spec.N, :spec.N], np.linalg.inv(K) + np.eye(spec.N) / s2, rtol=1e-12)
 
 
-def test_operand_rounding_model():
-    """The rounding model used to size the mixed-precision bar: an identity
-    rounding reproduces the exact result bit for bit, and float32 rounding of
-    the A_l, B_l products moves H and v(W) by a few float32 ulps relative to
-    their operands on a well-conditioned model (jitter 1e-2)."""
-    spec = MODELS[2]
-    q = rand_q(spec, 50)
-    W = np.random.default_rng(51).standard_normal((spec.D, spec.D))
-    W = W + W.T
-    H = model.hessian(spec, q)[2]
-    v = model.contract(spec, q, W)
-    ident = lambda X: X   # noqa: E731
-    assert np.array_equal(model.hessian(spec, q, ident)[2], H)
-    assert np.array_equal(model.contract(spec, q, W, ident), v)
-    f32 = lambda X: np.asarray(X, dtype=np.float32).astype(np.float64)   # noqa: E731
-    eH = np.linalg.norm(model.hessian(spec, q, f32)[2] - H) / np.linalg.norm(H)
-    ev = np.linalg.norm(model.contract(spec, q, W, f32) - v) / np.linalg.norm(v)
-    u32 = np.finfo(np.float32).eps / 2
-    assert u32 / 100 < eH < 1e3 * u32
-    assert u32 / 100 < ev < 1e3 * u32
+# Kernel values worked out by hand on three points, one kernel kind at a time
+# (Sec. 2.1, Eq. BMKL: the prior covariance is the sum of the terms).  They fix
+# the conventions the complex-step pins cannot see, since those differentiate
+# the same function they check: the SE amplitude enters as s^2 and the
+# lengthscale as l^2 in exp(-r^2 / (2 l^2)), linear-ARD variances as e^eta,
+# same-value kernels as s^2 [x_c == x'_c], and the jitter sits on the diagonal.
+GRAM_X = np.array([[0.0, 0.0, 1.0, 0.0],
+                   [1.0, 0.0, 2.0, 1.0],
+                   [0.0, 2.0, 0.0, 1.0]])
+E = np.exp
+
+
+def _gram_cases():
+    ln = np.log
+    se_iso = ([(wl.SE_ISO, (0, 1))], [ln(2.0), ln(0.5)],     # s = 2, l = 1/2: 4 exp(-2 r^2)
+              4.0 * np.array([[1, E(-2.0), E(-8.0)], [E(-2.0), 1, E(-10.0)], [E(-8.0), E(-10.0), 1]]))
+    se_ard = ([(wl.SE_ARD, (0, 1, 2))], [0.0, 0.0, ln(2.0), ln(0.5 ** 0.5)],   # 2 l_d^2 = 2, 8, 1
+              np.array([[1, E(-1.5), E(-1.5)], [E(-1.5), 1, E(-5.0)], [E(-1.5), E(-5.0), 1]]))
+    lin = ([(wl.LINEAR_ARD, (0, 2))], [ln(3.0), ln(0.5)],   # 3 x0 x0' + x2 x2' / 2
+           np.array([[0.5, 1.0, 0.0], [1.0, 5.0, 0.0], [0.0, 0.0, 0.0]]))
+    same = ([(wl.BINARY_SAME, (3,))], [ln(1.5)],           # 2.25 [x3 == x3']
+            2.25 * np.array([[1, 0, 0], [0, 1, 1], [0, 1, 1]]))
+    cases = {"se_iso": se_iso, "se_ard": se_ard, "linear_ard": lin, "binary_same": same}
+    cases["sum"] = (se_iso[0] + se_ard[0] + lin[0] + same[0],
+                    se_iso[1] + se_ard[1] + lin[1] + same[1],
+                    se_iso[2] + se_ard[2] + lin[2] + same[2])
+    return cases
+
+
+GRAM_CASES = _gram_cases()
+
+
+@pytest.mark.parametrize("name", list(GRAM_CASES))
+def test_gram_hand_values(name):
+    terms, eta, want = GRAM_CASES[name]
+    jitter = 0.125
+    spec = wl.ModelSpec(X=GRAM_X, y=np.zeros(3), terms=terms, jitter=jitter)
+    assert spec.P == len(eta)
+    K = model.gram(spec, np.array(eta))
+    assert np.allclose(K, want + jitter * np.eye(3), rtol=1e-14, atol=1e-15)
