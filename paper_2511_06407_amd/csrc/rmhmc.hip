@@ -467,7 +467,7 @@ struct Point {
   const double **Yap = nullptr, **Ybp = nullptr;
   double** Ycp = nullptr;
   // mixed precision: FP32 copies feeding the FP32 MFMA products
-  float *Kinvf = nullptr, *Af = nullptr, *Atf = nullptr, *Ytf = nullptr;
+  float *Af = nullptr, *Atf = nullptr, *Ytf = nullptr;
   const float **Yapf = nullptr, **Ybpf = nullptr;
   float** Ycpf = nullptr;
   bool have_pre = false, have_vW2 = false, have_eig = false;
@@ -524,7 +524,6 @@ void layout_point(const Model& m, Point& p, Carve& c) {
   p.trAA = c.take<double>(P * P);
   p.ak = c.take<double>(P);
   if (mixed) {
-    p.Kinvf = c.take<float>(NN);
     p.Af = c.take<float>(P * NN);
     p.Atf = c.take<float>(P * NN);
     p.Ytf = c.take<float>((long)m.nyy * NN);
@@ -627,7 +626,6 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st, int* fail) {
     } else {
       g.Co = pt.Af; g.sCo = NN;
       g.ldc2 = N; g.C2o = pt.Atf; g.sC2o = NN;
-      cast_to_float(NN, pt.Kinv, pt.Kinvf, st);
     }
     gemm(g, st);
   }
@@ -733,13 +731,13 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
     // tau[n, y] = tr(A_n A_l A_m) = <A_n, Y_lm'> for the formed pairs y = (l, m)
     gemm_tallk(P, m.nyy, NN, pt.A, NN, pt.Yt, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
   } else {
-    {  // B_l = A_l K^-1 on the FP32 matrix cores, stored in FP64
-      Gemm<float> g;
+    {  // B_l = A_l K^-1 in FP64: the product of an O(1) matrix with K^-1
+       // (entries up to 1/jitter) cancels as heavily as A_l does
+      Gemm<double> g;
       g.m = N; g.n = N; g.k = N;
-      g.A = pt.Af; g.lda = N; g.sA = NN;
-      g.B = pt.Kinvf; g.ldb = N;
-      g.ldc = N;
-      g.Co = pt.B; g.sCo = NN;
+      g.A = pt.A; g.lda = N; g.sA = NN;
+      g.B = pt.Kinv; g.ldb = N;
+      g.C = pt.B; g.ldc = N; g.sC = NN;
       g.batch = P;
       gemm(g, st);
     }

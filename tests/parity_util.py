@@ -79,3 +79,53 @@ def chain_floor(spec, eps, n_leapfrog, n_fixed_point, alpha, n_moves, seed, stre
         return float("inf")
     back = np.stack([unpermute_vec(r, full) for r in ref2[0]])
     return max(rel(back, ref[0]), rel(ref2[1], ref[1]))
+
+
+def _limited(args):
+    """Run fn(*fargs) in a worker process with `threads` BLAS threads."""
+    fn, fargs, threads = args
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=threads):
+        return fn(*fargs)
+
+
+def run_parallel(jobs, label):
+    """Run [(fn, args), ...] in fresh worker processes (spawned, so nothing of
+    the parent's GPU or thread state is inherited), the host cores split
+    between them; prints a progress line every 20 s while they run.  fn must
+    be importable (module level)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    cores = max(1, (os.cpu_count() or 2) // len(jobs))
+    ctx = mp.get_context("spawn")
+    with cf.ProcessPoolExecutor(len(jobs), mp_context=ctx) as ex:
+        futs = [ex.submit(_limited, (fn, args, cores)) for fn, args in jobs]
+        waited = 0
+        while True:
+            done, pending = cf.wait(futs, timeout=20)
+            if not pending:
+                break
+            waited += 20
+            progress(f"{label}: {len(pending)} reference run(s) still going after {waited} s")
+        return [f.result() for f in futs]
+
+
+def ref_glf(spec, q, p, eps, K, alpha, steps):
+    """`steps` generalized leapfrogs of the reference from (q, p): [(q, p, H)]."""
+    from oracle import hamiltonian as oham
+    from oracle.integrator import glf_step
+    st = oham.State(oham.GPTarget(spec), q, alpha)
+    out = []
+    for _ in range(steps):
+        st, p = glf_step(st, p, eps, K)
+        out.append((st.q.copy(), p.copy(), oham.hamiltonian(st, p)))
+    return out
+
+
+def ref_point(spec, q, p, alpha):
+    """U, grad U, H, dH/dq, dH/dp, H(q,p) and the eigen-state of the reference."""
+    from oracle import model as omodel, hamiltonian as oham
+    U, g, H = omodel.hessian(spec, q)
+    st = oham.State(oham.GPTarget(spec), q, alpha)
+    return (U, g, H, oham.grad_q(st, p), oham.grad_p(st, p), oham.hamiltonian(st, p),
+            {"Psi": st.eig["Psi"], "lam": st.eig["lam"]})

@@ -17,7 +17,7 @@ from oracle import model as omodel, softabs as osoft, hamiltonian as oham, rng a
 from oracle.integrator import glf_step as oglf  # noqa: E402
 from oracle.chain import run_seeded_chain, momentum as omomentum  # noqa: E402
 from tests.parity_util import (rel, permuted, unpermute_mat, unpermute_vec, record,  # noqa: E402
-                               chain_floor, progress)
+                               chain_floor, progress, run_parallel, ref_glf)
 
 pytestmark = pytest.mark.gpu
 BAR = 1e-10
@@ -366,23 +366,11 @@ def test_glf_step_parity(rm, name, eps):
         assert e_q < tol and e_p < tol and e_h < max(tol, 1e-12)
 
 
-def _glf_ref(args):
-    """Two reference leapfrogs from (q, p) on spec (run in a worker process)."""
-    spec, q, p, eps, K, alpha = args
-    st = oham.State(oham.GPTarget(spec), q, alpha)
-    out = []
-    for _ in range(2):
-        st, p = oglf(st, p, eps, K)
-        out.append((st.q.copy(), p.copy(), oham.hamiltonian(st, p)))
-    return out
-
-
 @pytest.mark.timeout(1500)
 def test_glf_step_parity_full_size(rm):
     """Two generalized leapfrogs of the benchmarked workload itself (D = 1038:
     N = 1024, P = 14, jitter 1e-6) at its step size, against the reference
     and its permutation floor (the two reference runs go to two processes)."""
-    import concurrent.futures as cf
     spec, cfg = wl.workload("propensity_mkl_d1038")
     q = rand_q(spec, 41, 0.05)
     alpha, K, eps = cfg.alpha, cfg.n_fixed_point, cfg.eps
@@ -396,10 +384,8 @@ def test_glf_step_parity_full_size(rm):
         got.append((host(qg), host(pg), float(host(hg)[0])))
     progress("full-size leapfrogs on the GPU done; reference runs started")
     s2, q2, full = permuted(spec, q)
-    with cf.ProcessPoolExecutor(2) as ex:
-        fa = ex.submit(_glf_ref, (spec, q, p, eps, K, alpha))
-        fb = ex.submit(_glf_ref, (s2, q2, p[full], eps, K, alpha))
-        ref, ref2 = fa.result(), fb.result()
+    ref, ref2 = run_parallel([(ref_glf, (spec, q, p, eps, K, alpha, 2)),
+                              (ref_glf, (s2, q2, p[full], eps, K, alpha, 2))], "full-size glf")
     for step in range(2):
         rq, rp, rh = ref[step]
         q2s, p2s, _ = ref2[step]
