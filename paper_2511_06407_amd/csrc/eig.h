@@ -13,7 +13,15 @@ struct EigWork {
   double* ctrl = nullptr;  // device control block (EIG_CTRL_DOUBLES): norm, stop flag, counts
   double* ctrl_host = nullptr;  // pinned host mirror of ctrl
 };
-constexpr int EIG_CTRL_DOUBLES = 16;
+constexpr int EIG_CTRL_DOUBLES = 32;
+// Stopping rules of the Jacobi solve (see eig.hip); RMHMC_EIG_STOP=polish in
+// the environment selects the older one.
+enum { EIG_STOP_POLISH = 0, EIG_STOP_METRIC = 1 };
+int eig_stop_rule();
+double eig_stop_zeta_scaled();
+bool eig_trace();
+// Doubles of EigWork::part for a padded dimension Dp.
+long eig_part_doubles(int Dp);
 
 int eig_padded_dim(int D);
 void eig_workspace_sizes(int D, long* doubles);
@@ -46,8 +54,11 @@ struct JacobiResult {
 // max(blind, 1) sweeps are launched and nothing is read back.  On the device:
 // *fail |= 4 if the solve did not converge, 8 if it met non-finite entries
 // (fail may be null); dstats[0] += 1, dstats[1] += sweeps (may be null).
-JacobiResult jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, int blind,
-                        bool host_check, int* fail, double* dstats, hipStream_t st);
+// gfloor: the smallest value of the softabs map (1 / alpha), the scale below
+// which an eigenvalue's size no longer matters to G^-1.
+JacobiResult jacobi_eig(int D, EigWork& w, double zeta, double gfloor, int max_sweeps,
+                        int max_inner, int blind, bool host_check, int* fail, double* dstats,
+                        hipStream_t st);
 // Rayleigh quotients lam_i = psi_i' H psi_i of the converged basis against the
 // original H (D x D, ldh), written to diag(w.M); Z is Dp x Dp scratch.
 // One Newton-Schulz step Psi <- Psi (3I - Psi'Psi) / 2 on the D x D block of

@@ -14,6 +14,9 @@
 // takes the smaller angle (|angle| <= pi/4) and annihilates its pair
 // exactly (Rutishauser's update of the diagonal).
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
 #include <utility>
 
 #include "common.h"
@@ -559,50 +562,67 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(int Dp, int apply_rou
   if (k < npsi) jacobi_psi_tile(Dp, apply_round, k, Psi, Vprev, Xs[wave]);
 }
 
-// Per OFF_COLS-column chunk: off-diagonal squares, all squares, and the largest
-// relative off-diagonal |m_ij| / sqrt(|m_ii m_jj|).
+// Per OFF_COLS-column chunk: off-diagonal squares, all squares, the largest
+// relative off-diagonal |m_ij| / sqrt(|m_ii m_jj|), and the same squares
+// scaled by 1 / (s_i s_j) with s_i = max(|m_ii|, gfloor), together with the
+// sum of 1 / s_i^2 over the chunk's diagonal.
 constexpr int OFF_COLS = 8;   // columns per workgroup of the convergence check
 constexpr int OFF_MAXDP = 4096;
+constexpr int OFF_PARTS = 5;  // partials per chunk
+constexpr int CTRL_N = EIG_CTRL_DOUBLES;
 
 __global__ __launch_bounds__(256) void offnorm_kernel(int Dp, const double* __restrict__ M,
-                                                      double* __restrict__ part,
+                                                      double* __restrict__ part, double gfloor,
                                                       const double* __restrict__ ctrl) {
-  __shared__ double sh[3][4];
+  __shared__ double sh[OFF_PARTS][4];
   __shared__ double rdg[OFF_MAXDP];   // 1 / sqrt|m_ii| (inf for a zero diagonal)
+  __shared__ double rs[OFF_MAXDP];    // 1 / max(|m_ii|, gfloor)
   if (ctrl[1] != 0.0) return;
   for (int i = threadIdx.x; i < Dp; i += 256) {
     const double d = fabs(M[i + (long)i * Dp]);
     rdg[i] = d > 0.0 ? rsqrt(d) : INFINITY;
+    rs[i] = 1.0 / fmax(d, gfloor);
   }
   __syncthreads();
   const int c0 = blockIdx.x * OFF_COLS;
-  double off = 0.0, tot = 0.0, rel = 0.0;
+  double off = 0.0, tot = 0.0, rel = 0.0, soff = 0.0, sdiag = 0.0;
   for (int j = c0; j < c0 + OFF_COLS; ++j) {
-    const double rj = rdg[j];
+    const double rj = rdg[j], sj = rs[j];
     for (int i = threadIdx.x; i < Dp; i += 256) {
       const double v = M[i + (long)j * Dp];
       tot += v * v;
       if (i != j && v != 0.0) {
         off += v * v;
         rel = fmax(rel, fabs(v) * rdg[i] * rj);
+        const double w = v * rs[i] * sj;
+        soff += w * w;
       }
     }
+    if (threadIdx.x == 0 && j < Dp && M[j + (long)j * Dp] != 0.0) sdiag += sj * sj;
   }
   for (int o = 32; o > 0; o >>= 1) {
     off += __shfl_down(off, o, 64);
     tot += __shfl_down(tot, o, 64);
     rel = fmax(rel, __shfl_down(rel, o, 64));
+    soff += __shfl_down(soff, o, 64);
+    sdiag += __shfl_down(sdiag, o, 64);
   }
   if ((threadIdx.x & 63) == 0) {
-    sh[0][threadIdx.x >> 6] = off;
-    sh[1][threadIdx.x >> 6] = tot;
-    sh[2][threadIdx.x >> 6] = rel;
+    const int w = threadIdx.x >> 6;
+    sh[0][w] = off;
+    sh[1][w] = tot;
+    sh[2][w] = rel;
+    sh[3][w] = soff;
+    sh[4][w] = sdiag;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    part[3 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
-    part[3 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
-    part[3 * blockIdx.x + 2] = fmax(fmax(sh[2][0], sh[2][1]), fmax(sh[2][2], sh[2][3]));
+    double* o = part + OFF_PARTS * blockIdx.x;
+    o[0] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    o[1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    o[2] = fmax(fmax(sh[2][0], sh[2][1]), fmax(sh[2][2], sh[2][3]));
+    o[3] = sh[3][0] + sh[3][1] + sh[3][2] + sh[3][3];
+    o[4] = sh[4][0] + sh[4][1] + sh[4][2] + sh[4][3];
   }
 }
 
@@ -612,28 +632,42 @@ __global__ __launch_bounds__(256) void offnorm_kernel(int Dp, const double* __re
 //   [4] the norm-wise test held at the previous check
 //   [5] non-finite entries found              [6] buffer holding M when stopped (0: M, 1: M2)
 //   [7] sweeps applied before the stop
-// Converged: off(M)_F <= zeta ||M||_F (the stated tolerance) and either every
-// off-diagonal is below 1e-12 of the geometric mean of its diagonals or the
-// norm-wise test also held one sweep earlier (one polishing sweep at most).
-// A non-finite norm stops the solve without convergence.
-constexpr int CTRL_N = 16;
-
+//   [8 + c], [16 + c], [24 + c] for checks c < 8: the norm-wise ratio, the
+//   scaled ratio and the largest relative off-diagonal (convergence history)
+// Two stopping rules:
+//   EIG_STOP_POLISH: off(M)_F <= zeta ||M||_F (the stated tolerance) and
+//     either every off-diagonal is below 1e-12 of the geometric mean of its
+//     diagonals or the norm-wise test also held one sweep earlier;
+//   EIG_STOP_METRIC: off(M)_F <= zeta ||M||_F and off(S M S)_F <= zeta_s
+//     ||diag(S)||_F with S = diag(1 / max(|m_ii|, 1/alpha)).  To first order
+//     an off-diagonal E left in M moves G by at most ||E|| (|g'| <= 1) and
+//     G^-1 by E_ij / (g_i g_j) with g >= max(|lambda|, 1/alpha), so the two
+//     tests bound the relative errors of G and of G^-1 (hence of G^-1 p and
+//     of the trace terms) by zeta and zeta_s.  Off-diagonals between two
+//     eigenvalues of the cluster near 1/jitter are then left at their
+//     harmless size instead of being resolved to 1e-12 of 1/jitter.
 __global__ void offnorm_finish_kernel(int nparts, const double* __restrict__ part, double zeta,
-                                      double* __restrict__ ctrl, int first, int cur_buf) {
+                                      double zeta_s, int rule, double* __restrict__ ctrl,
+                                      int first, int cur_buf) {
   // One wave: lanes take every 64th partial, then a shuffle tree combines
   // the lane sums and maxima in a fixed order.
   if (ctrl[1] != 0.0) return;
   const int lane = threadIdx.x;
-  double off = 0.0, tot = 0.0, rel = 0.0;
+  double off = 0.0, tot = 0.0, rel = 0.0, soff = 0.0, sdiag = 0.0;
   for (int p = lane; p < nparts; p += 64) {
-    off += part[3 * p];
-    tot += part[3 * p + 1];
-    rel = fmax(rel, part[3 * p + 2]);
+    const double* o = part + OFF_PARTS * p;
+    off += o[0];
+    tot += o[1];
+    rel = fmax(rel, o[2]);
+    soff += o[3];
+    sdiag += o[4];
   }
   for (int o = 32; o > 0; o >>= 1) {
     off += __shfl_xor(off, o, 64);
     tot += __shfl_xor(tot, o, 64);
     rel = fmax(rel, __shfl_xor(rel, o, 64));
+    soff += __shfl_xor(soff, o, 64);
+    sdiag += __shfl_xor(sdiag, o, 64);
   }
   if (lane != 0) return;
   const double nrm = sqrt(tot);
@@ -641,16 +675,28 @@ __global__ void offnorm_finish_kernel(int nparts, const double* __restrict__ par
   ctrl[3] = sweeps + 1.0;
   ctrl[6] = (double)cur_buf;
   ctrl[7] = sweeps;
-  if (!isfinite(nrm) || !isfinite(off)) {
+  if (!isfinite(nrm) || !isfinite(off) || !isfinite(soff)) {
     ctrl[5] = 1.0;
     ctrl[1] = 1.0;
     return;
   }
   if (first) ctrl[0] = nrm;
   const double r = nrm > 0.0 ? sqrt(off) / nrm : 0.0;
+  const double rs = sdiag > 0.0 ? sqrt(soff / sdiag) : 0.0;
   ctrl[2] = r;
+  const int c = (int)sweeps;
+  if (c < 8) {
+    ctrl[8 + c] = r;
+    ctrl[16 + c] = rs;
+    ctrl[24 + c] = rel;
+  }
   const bool normwise = sqrt(off) <= zeta * nrm || !(nrm > 0.0);
-  const bool done = normwise && (rel <= 1e-12 || off == 0.0 || ctrl[4] != 0.0);
+  bool done;
+  if (rule == EIG_STOP_METRIC) {
+    done = normwise && rs <= zeta_s;
+  } else {
+    done = normwise && (rel <= 1e-12 || off == 0.0 || ctrl[4] != 0.0);
+  }
   ctrl[4] = normwise ? 1.0 : 0.0;
   ctrl[1] = done ? 1.0 : 0.0;
 }
@@ -856,7 +902,7 @@ void eig_workspace_sizes(int D, long* doubles) {
   const int Dp = eig_padded_dim(D);
   const int nb = Dp / JHB;
   // M, M2, Psi; two rotation sets (double-buffered); convergence partials; ctrl
-  *doubles = 3L * Dp * Dp + 2L * (nb / 2) * JSB * JSB + 3L * (Dp / OFF_COLS + 1) + CTRL_N;
+  *doubles = 3L * Dp * Dp + 2L * (nb / 2) * JSB * JSB + eig_part_doubles(Dp) + CTRL_N;
 }
 
 // Unused dynamic LDS reserved by the update-and-solve launches: it lifts a
@@ -866,8 +912,25 @@ void eig_workspace_sizes(int D, long* doubles) {
 // the chain (measured: 1.5 us of a 29.9 us launch at Dp = 1088).
 constexpr int ROUND_LDS_RESERVE = 12288;
 
-JacobiResult jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_inner, int blind,
-                        bool host_check, int* fail, double* dstats, hipStream_t st) {
+bool eig_trace() {
+  static const bool on = std::getenv("RMHMC_EIG_TRACE") != nullptr;
+  return on;
+}
+
+long eig_part_doubles(int Dp) { return (long)OFF_PARTS * (Dp / OFF_COLS + 1); }
+
+int eig_stop_rule() {
+  static const int rule = [] {
+    const char* e = std::getenv("RMHMC_EIG_STOP");
+    return (e && std::string(e) == "polish") ? EIG_STOP_POLISH : EIG_STOP_METRIC;
+  }();
+  return rule;
+}
+double eig_stop_zeta_scaled() { return 1e-12; }
+
+JacobiResult jacobi_eig(int D, EigWork& w, double zeta, double gfloor, int max_sweeps,
+                        int max_inner, int blind, bool host_check, int* fail, double* dstats,
+                        hipStream_t st) {
   // Input: w.M (Dp x Dp symmetric, padded) and w.Psi (Dp x Dp, padded with identity).
   const int Dp = eig_padded_dim(D);
   const int nb = Dp / JHB, ns = nb / 2;
@@ -882,10 +945,11 @@ JacobiResult jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_
   RM_CHECK_LAUNCH();
   auto check = [&](int first) {
     hipLaunchKernelGGL(offnorm_kernel, dim3(nparts), dim3(256), 0, st, Dp, (const double*)Mb[cur],
-                       w.part, (const double*)w.ctrl);
+                       w.part, gfloor, (const double*)w.ctrl);
     RM_CHECK_LAUNCH();
     hipLaunchKernelGGL(offnorm_finish_kernel, dim3(1), dim3(64), 0, st, nparts,
-                       (const double*)w.part, zeta, w.ctrl, first, cur);
+                       (const double*)w.part, zeta, eig_stop_zeta_scaled(), eig_stop_rule(),
+                       w.ctrl, first, cur);
     RM_CHECK_LAUNCH();
   };
   const int ntri = ns * (ns + 1) / 2;
@@ -945,6 +1009,13 @@ JacobiResult jacobi_eig(int D, EigWork& w, double zeta, int max_sweeps, int max_
     res.nonfinite = w.ctrl_host[5] != 0.0;
     res.converged = w.ctrl_host[1] != 0.0 && !res.nonfinite;
     res.sweeps = w.ctrl_host[1] != 0.0 ? (int)w.ctrl_host[7] : launched;
+    if (eig_trace()) {
+      std::fprintf(stderr, "[eig] D=%d sweeps=%d converged=%d", D, res.sweeps, (int)res.converged);
+      for (int c = 0; c < 8 && c <= res.sweeps; ++c)
+        std::fprintf(stderr, " | %.1e %.1e %.1e", w.ctrl_host[8 + c], w.ctrl_host[16 + c],
+                     w.ctrl_host[24 + c]);
+      std::fprintf(stderr, "\n");
+    }
   }
   const long n = (long)Dp * Dp;
   hipLaunchKernelGGL(jacobi_collect_kernel, dim3((unsigned)std::min<long>(cdiv(n, 256 * 16), 1024)),

@@ -690,8 +690,9 @@ JacobiResult compute_eig(Model& m, Point& pt, const Point* warm, double alpha, c
     symmetrize(Dp, m.eig.M, Dp, st);
   }
   const JacobiResult r =
-      jacobi_eig(D, m.eig, ec.zeta, ec.max_sweeps, warm ? JACOBI_INNER_DYNAMIC : JACOBI_INNER_STATIC,
-                 ec.blind, ec.host_check, ec.host_check ? nullptr : ec.fail, ec.dstats, st);
+      jacobi_eig(D, m.eig, ec.zeta, 1.0 / alpha, ec.max_sweeps,
+                 warm ? JACOBI_INNER_DYNAMIC : JACOBI_INNER_STATIC, ec.blind, ec.host_check,
+                 ec.host_check ? nullptr : ec.fail, ec.dstats, st);
   // a static solve accumulates one rounding per rotation into Psi: restore
   // orthogonality before the eigenvalues are refined against H
   if (!warm) orthonormalise(D, Dp, m.eig.Psi, m.Wt1, m.Wt2, st);
@@ -1032,7 +1033,7 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   m.eig.M2 = pl.alloc<double>(Dp * Dp);
   m.eig.Psi = pl.alloc<double>(Dp * Dp);
   m.eig.V = pl.alloc<double>(eig_rotation_doubles(Dp));
-  m.eig.part = pl.alloc<double>(3 * (Dp / 8 + 1));
+  m.eig.part = pl.alloc<double>(eig_part_doubles(Dp));
   m.eig.ctrl = pl.alloc<double>(EIG_CTRL_DOUBLES);
   m.eig.ctrl_host = pl.alloc_host<double>(EIG_CTRL_DOUBLES);
   const int spl = tallk_splits(NN);
@@ -1455,7 +1456,7 @@ void eig_workspace_grow(EigWorkspace& ws, int D) {
   w.M2 = pool->alloc<double>((long)Dp * Dp);
   w.Psi = pool->alloc<double>((long)Dp * Dp);
   w.V = pool->alloc<double>(eig_rotation_doubles(Dp));
-  w.part = pool->alloc<double>(3 * (Dp / 8 + 1));
+  w.part = pool->alloc<double>(eig_part_doubles(Dp));
   w.ctrl = pool->alloc<double>(EIG_CTRL_DOUBLES);
   w.ctrl_host = pool->alloc_host<double>(EIG_CTRL_DOUBLES);
   ws.pool = std::move(pool);
@@ -1621,7 +1622,7 @@ rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, do
     } else {
       eig_load_basis(D, nullptr, D, w, st);
     }
-    const JacobiResult r = jacobi_eig(D, w, zeta, max_sweeps,
+    const JacobiResult r = jacobi_eig(D, w, zeta, 1.0 / alpha, max_sweeps,
                                       Q_warm ? JACOBI_INNER_DYNAMIC : JACOBI_INNER_STATIC, 0, true,
                                       nullptr, nullptr, st);
     if (r.nonfinite) {
