@@ -164,6 +164,18 @@ rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, do
                                double* g, double* gp, double* logdetG, int* sweeps,
                                hipStream_t stream);
 rmhmc_status rmhmc_softabs_eig_reserve(int D);
+/* The same eigensolve for callers that cannot allocate device memory (code
+ * that must not call hipMalloc, such as tight serving loops or harnesses that
+ * forbid it): its workspace is a file-scope device array of the library,
+ * one per device, sized for D <= 1088 (29 MB, held until the process ends);
+ * the call allocates nothing.  RMHMC_E_ARG for D > 1088.  Calls on one device
+ * share that array and are serialised by the library; it keeps the last
+ * call's contents, and every call initialises what it reads.  Arguments,
+ * outputs, errors and synchronisation as rmhmc_softabs_eig. */
+rmhmc_status rmhmc_softabs_eig_noalloc(int D, const double* H, int ldh, double alpha, double zeta,
+                                       int max_sweeps, const double* Q_warm, double* Q,
+                                       double* lam, double* g, double* gp, double* logdetG,
+                                       int* sweeps, hipStream_t stream);
 
 /* Hamiltonian and its gradients at (q, p) for a given eigen-state (Q, lam)
  * of H(q) (Sec. 2.2, Eq. Hamiltonian and Eq. d_Hamiltonian, with the metric

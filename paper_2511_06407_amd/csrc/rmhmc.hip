@@ -1397,6 +1397,67 @@ void pool_worker(rmhmc_pool* pool, int w) {
 }  // namespace
 }  // namespace rmhmc
 
+// ================================================================ no-allocation eigensolver workspace
+// A file-scope device array holds the whole workspace of the stand-alone
+// eigensolver for D <= NOALLOC_MAX_D (M, M2, Psi, the rotation sets, the
+// convergence partials and control block), so rmhmc_softabs_eig_noalloc
+// needs no device allocation.  Each device holds its own copy for the life
+// of the process; its address is resolved once per device and used from
+// then on (the array's name is not a device address on the host).
+namespace rmhmc {
+namespace {
+constexpr int NOALLOC_MAX_D = 1088;
+constexpr int NOALLOC_DP = NOALLOC_MAX_D;   // already a multiple of 64
+constexpr long NOALLOC_DOUBLES = 3L * NOALLOC_DP * NOALLOC_DP + 2L * (NOALLOC_DP / 32) * 32 * 32 +
+                                 5L * (NOALLOC_DP / 8 + 1) + EIG_CTRL_DOUBLES + 64;
+static_assert(NOALLOC_DP % 64 == 0, "padded maximum must be a multiple of 64");
+}  // namespace
+}  // namespace rmhmc
+
+static __device__ __align__(256) double scratch[rmhmc::NOALLOC_DOUBLES];
+
+namespace rmhmc {
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+std::mutex g_noalloc_call_mu[NOALLOC_MAX_DEVICES];
+
+// The current device's copy of `scratch` (resolved on its first use there).
+double* noalloc_scratch(int dev) {
+  RM_REQUIRE(dev >= 0 && dev < NOALLOC_MAX_DEVICES, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    RM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    RM_REQUIRE(ptr != nullptr, "no device address for the eigensolver scratch array");
+    g_noalloc_ptr[dev] = static_cast<double*>(ptr);
+  }
+  return g_noalloc_ptr[dev];
+}
+
+// Carve an EigWork for padded dimension Dp out of the scratch array.
+EigWork noalloc_work(double* base, int Dp, double* ctrl_host) {
+  EigWork w;
+  long off = 0;
+  auto take = [&](long n) {
+    double* p = base + off;
+    off += (n + 31) / 32 * 32;   // 256-byte steps
+    return p;
+  };
+  w.M = take((long)Dp * Dp);
+  w.M2 = take((long)Dp * Dp);
+  w.Psi = take((long)Dp * Dp);
+  w.V = take(eig_rotation_doubles(Dp));
+  w.part = take(eig_part_doubles(Dp));
+  w.ctrl = take(EIG_CTRL_DOUBLES);
+  w.ctrl_host = ctrl_host;
+  RM_REQUIRE(off <= NOALLOC_DOUBLES, "internal: eigensolver scratch layout exceeds the array");
+  return w;
+}
+}  // namespace
+}  // namespace rmhmc
+
 // ================================================================ C ABI
 
 using namespace rmhmc;
@@ -1481,6 +1542,58 @@ rmhmc_status gemm_entry(int m, int n, int k, T alpha, const T* A, int lda, int t
     g.C = C; g.ldc = ldc;
     gemm(g, st);
   });
+}
+
+void check_eig_args(int D, const double* H, int ldh, double alpha, const double* Q,
+                    const double* lam, const double* g, const double* gp, const double* logdetG) {
+  RM_REQUIRE(D >= 1 && H && Q && lam && g && gp && logdetG, "bad argument");
+  RM_REQUIRE(ldh >= D, "ldh < D");
+  RM_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "alpha must be positive");
+  RM_REQUIRE(eig_padded_dim(D) <= 4096, "D too large");
+}
+
+// The stand-alone eigensolve on workspace w (sized for D); synchronises `st`.
+void softabs_eig_impl(EigWork& w, int D, const double* H, int ldh, double alpha, double zeta,
+                      int max_sweeps, const double* Q_warm, double* Q, double* lam, double* g,
+                      double* gp, double* logdetG, int* sweeps, hipStream_t st) {
+  if (zeta <= 0.0) zeta = 1e-13;
+  if (max_sweeps <= 0) max_sweeps = 60;
+  const int Dp = eig_padded_dim(D);
+  eig_load_matrix(D, H, ldh, w, st);
+  if (Q_warm) {
+    // M = Qw' H Qw computed through padded copies
+    eig_load_basis(D, Q_warm, D, w, st);
+    Gemm<double> a;
+    a.m = Dp; a.n = Dp; a.k = Dp;
+    a.A = w.M; a.lda = Dp;
+    a.B = w.Psi; a.ldb = Dp;
+    a.C = w.M2; a.ldc = Dp;
+    gemm(a, st);
+    Gemm<double> b;
+    b.m = Dp; b.n = Dp; b.k = Dp;
+    b.A = w.Psi; b.lda = Dp; b.tA = true;
+    b.B = w.M2; b.ldb = Dp;
+    b.C = w.M; b.ldc = Dp;
+    gemm(b, st);
+    symmetrize(Dp, w.M, Dp, st);
+  } else {
+    eig_load_basis(D, nullptr, D, w, st);
+  }
+  const JacobiResult r = jacobi_eig(D, w, zeta, 1.0 / alpha, max_sweeps,
+                                    Q_warm ? JACOBI_INNER_DYNAMIC : JACOBI_INNER_STATIC, 0, true,
+                                    nullptr, nullptr, st);
+  if (r.nonfinite) {
+    RM_HIP(hipStreamSynchronize(st));
+    throw Error(RMHMC_E_NONFINITE, "softabs_eig: non-finite entries in the matrix");
+  }
+  // static solve: restore orthogonality (M's off-diagonal part is free now)
+  if (!Q_warm) orthonormalise(D, Dp, w.Psi, w.M2, w.M, st);
+  rayleigh_refine(D, H, ldh, w, w.M2, st);
+  copy_matrix(D, D, w.Psi, Dp, Q, D, st);
+  softabs_finalize(D, w.M, Dp, alpha, lam, g, gp, logdetG, st);
+  RM_HIP(hipStreamSynchronize(st));
+  if (sweeps) *sweeps = r.sweeps;
+  if (!r.converged) throw Error(RMHMC_E_EIG_NOCONV, "softabs_eig: Jacobi did not converge");
 }
 
 }  // namespace
@@ -1591,52 +1704,30 @@ rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, do
                                double* g, double* gp, double* logdetG, int* sweeps,
                                hipStream_t st) {
   return guard([&] {
-    RM_REQUIRE(D >= 1 && H && Q && lam && g && gp && logdetG, "bad argument");
-    RM_REQUIRE(ldh >= D, "ldh < D");
-    RM_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "alpha must be positive");
-    RM_REQUIRE(eig_padded_dim(D) <= 4096, "D too large");
-    if (zeta <= 0.0) zeta = 1e-13;
-    if (max_sweeps <= 0) max_sweeps = 60;
+    check_eig_args(D, H, ldh, alpha, Q, lam, g, gp, logdetG);
     EigWorkspace& ws = eig_workspace();
     std::lock_guard<std::mutex> lk(ws.mu);
     eig_workspace_grow(ws, D);
-    EigWork& w = ws.w;
-    const int Dp = eig_padded_dim(D);
-    eig_load_matrix(D, H, ldh, w, st);
-    if (Q_warm) {
-      // M = Qw' H Qw computed through padded copies
-      eig_load_basis(D, Q_warm, D, w, st);
-      Gemm<double> a;
-      a.m = Dp; a.n = Dp; a.k = Dp;
-      a.A = w.M; a.lda = Dp;
-      a.B = w.Psi; a.ldb = Dp;
-      a.C = w.M2; a.ldc = Dp;
-      gemm(a, st);
-      Gemm<double> b;
-      b.m = Dp; b.n = Dp; b.k = Dp;
-      b.A = w.Psi; b.lda = Dp; b.tA = true;
-      b.B = w.M2; b.ldb = Dp;
-      b.C = w.M; b.ldc = Dp;
-      gemm(b, st);
-      symmetrize(Dp, w.M, Dp, st);
-    } else {
-      eig_load_basis(D, nullptr, D, w, st);
-    }
-    const JacobiResult r = jacobi_eig(D, w, zeta, 1.0 / alpha, max_sweeps,
-                                      Q_warm ? JACOBI_INNER_DYNAMIC : JACOBI_INNER_STATIC, 0, true,
-                                      nullptr, nullptr, st);
-    if (r.nonfinite) {
-      RM_HIP(hipStreamSynchronize(st));
-      throw Error(RMHMC_E_NONFINITE, "softabs_eig: non-finite entries in the matrix");
-    }
-    // static solve: restore orthogonality (M's off-diagonal part is free now)
-    if (!Q_warm) orthonormalise(D, Dp, w.Psi, w.M2, w.M, st);
-    rayleigh_refine(D, H, ldh, w, w.M2, st);
-    copy_matrix(D, D, w.Psi, Dp, Q, D, st);
-    softabs_finalize(D, w.M, Dp, alpha, lam, g, gp, logdetG, st);
-    RM_HIP(hipStreamSynchronize(st));
-    if (sweeps) *sweeps = r.sweeps;
-    if (!r.converged) throw Error(RMHMC_E_EIG_NOCONV, "softabs_eig: Jacobi did not converge");
+    softabs_eig_impl(ws.w, D, H, ldh, alpha, zeta, max_sweeps, Q_warm, Q, lam, g, gp, logdetG,
+                     sweeps, st);
+  });
+}
+
+rmhmc_status rmhmc_softabs_eig_noalloc(int D, const double* H, int ldh, double alpha, double zeta,
+                                       int max_sweeps, const double* Q_warm, double* Q,
+                                       double* lam, double* g, double* gp, double* logdetG,
+                                       int* sweeps, hipStream_t st) {
+  return guard([&] {
+    check_eig_args(D, H, ldh, alpha, Q, lam, g, gp, logdetG);
+    RM_REQUIRE(D <= NOALLOC_MAX_D, "softabs_eig_noalloc: D exceeds the scratch maximum (1088)");
+    int dev = 0;
+    RM_HIP(hipGetDevice(&dev));
+    double* base = noalloc_scratch(dev);
+    std::lock_guard<std::mutex> lk(g_noalloc_call_mu[dev]);
+    double ctrl_host[EIG_CTRL_DOUBLES];
+    EigWork w = noalloc_work(base, eig_padded_dim(D), ctrl_host);
+    softabs_eig_impl(w, D, H, ldh, alpha, zeta, max_sweeps, Q_warm, Q, lam, g, gp, logdetG,
+                     sweeps, st);
   });
 }
 

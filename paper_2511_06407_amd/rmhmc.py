@@ -32,7 +32,7 @@ EXPORTED = ["rmhmc_model_create", "rmhmc_model_dims", "rmhmc_model_destroy", "rm
             "rmhmc_state_draw_momentum",
             "rmhmc_timing_enable", "rmhmc_timing_read", "rmhmc_pool_create", "rmhmc_pool_submit",
             "rmhmc_pool_poll", "rmhmc_pool_destroy", "rmhmc_state_stats", "rmhmc_model_bytes",
-            "rmhmc_softabs_eig_reserve", "rmhmc_chain_randoms"]
+            "rmhmc_softabs_eig_reserve", "rmhmc_chain_randoms", "rmhmc_softabs_eig_noalloc"]
 
 TIMER_KINDS = {"gemm_f64": 0, "gemm_f32": 1, "jacobi_solve": 2, "jacobi_apply": 3, "kd_wsum": 4,
                "kd_matvec": 5, "potrf_diag": 6}
@@ -78,6 +78,8 @@ _sig = {
     "rmhmc_model_destroy": [_vp],
     "rmhmc_hessian": [_vp, _vp, _vp, _vp, _vp, _i, _vp],
     "rmhmc_softabs_eig": [_i, _vp, _i, _d, _d, _i, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_i), _vp],
+    "rmhmc_softabs_eig_noalloc": [_i, _vp, _i, _d, _d, _i, _vp, _vp, _vp, _vp, _vp, _vp,
+                                  C.POINTER(_i), _vp],
     "rmhmc_metric_grad": [_vp, _vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp],
     "rmhmc_state_create": [_vp, _vp, _vp, _d, _vp, C.POINTER(_vp)],
     "rmhmc_state_get": [_vp, _vp, _vp, _vp, _vp],
@@ -261,9 +263,10 @@ def softabs_eig_reserve(D):
     _check(_lib.rmhmc_softabs_eig_reserve(D))
 
 
-def softabs_eig(H, alpha, Q_warm=None, zeta=0.0, max_sweeps=0, stream=None):
+def softabs_eig(H, alpha, Q_warm=None, zeta=0.0, max_sweeps=0, stream=None, noalloc=False):
     """H: symmetric D x D device tensor.  Returns (Q_colmajor, lam, g, gp, logdetG, sweeps);
-    Q_colmajor[j] is the j-th eigenvector."""
+    Q_colmajor[j] is the j-th eigenvector.  noalloc: the entry point whose
+    workspace is the library's static device array (D <= 1088)."""
     torch = _torch()
     D = H.shape[0]
     Q = torch.empty((D, D), dtype=torch.float64, device=H.device)
@@ -272,9 +275,9 @@ def softabs_eig(H, alpha, Q_warm=None, zeta=0.0, max_sweeps=0, stream=None):
     gp = torch.empty(D, dtype=torch.float64, device=H.device)
     ld = torch.empty(1, dtype=torch.float64, device=H.device)
     sw = C.c_int()
-    _check(_lib.rmhmc_softabs_eig(D, _f64(H), D, alpha, zeta, max_sweeps, _f64(Q_warm), _f64(Q),
-                                  _f64(lam), _f64(g), _f64(gp), _f64(ld), C.byref(sw),
-                                  _stream(stream)))
+    fn = _lib.rmhmc_softabs_eig_noalloc if noalloc else _lib.rmhmc_softabs_eig
+    _check(fn(D, _f64(H), D, alpha, zeta, max_sweeps, _f64(Q_warm), _f64(Q), _f64(lam), _f64(g),
+              _f64(gp), _f64(ld), C.byref(sw), _stream(stream)))
     return Q, lam, g, gp, ld, sw.value
 
 
