@@ -63,7 +63,9 @@ def parse():
                          "chains of uneven D on the worker pool; serve: Poisson request stream")
     ap.add_argument("--chains", type=int, default=64)
     ap.add_argument("--moves", type=int, default=4, help="moves per chain (tempered mode)")
-    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--workers", type=int, default=8, help="streams (graph) or workers (pool)")
+    ap.add_argument("--engine", choices=["graph", "pool"], default="graph",
+                    help="tempered mode: graph-captured batch or eager worker pool")
     ap.add_argument("--rate", type=float, default=20.0, help="requests/s (serve mode)")
     ap.add_argument("--duration", type=float, default=3.0, help="arrival window in s (serve)")
     ap.add_argument("--max-moves", type=int, default=4, help="moves per request (serve)")
@@ -75,14 +77,17 @@ def run_tempered_mode(args):
     from paper_2511_06407_amd.tempered import run_tempered
     log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)  # noqa: E731
     out = run_tempered(n_chains=args.chains, n_moves=args.moves, n_leapfrog=10, n_fixed_point=6,
-                       eps=0.01, n_workers=args.workers, seed=args.seed, log=log)
+                       eps=0.01, n_workers=args.workers, seed=args.seed, log=log,
+                       engine=args.engine)
     dims = [c["D"] for c in out["chains"]]
     return {"metric": "tempered chains: aggregate chain-leapfrogs/s", "value": out["chain_leapfrogs_per_s"],
             "unit": "chain-leapfrogs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
-            "data": "synthetic", "wall_s": out["wall_s"],
+            "data": "synthetic", "wall_s": out["wall_s"], "setup_s": out["setup_s"],
             "config": {"workload": f"{args.chains} power-posterior chains, beta_k=(k/{args.chains - 1})^5, "
                                    "D from {66,130,258,514}", "moves": args.moves, "n_leapfrog": 10,
-                       "workers": args.workers, "dims": dims},
+                       "workers": args.workers, "engine": args.engine, "dims": dims},
+            "shapes": {str(c["D"]): c["shape"] for c in out["chains"]},
+            "fail_noconv": sum(c["fail_noconv"] for c in out["chains"]),
             "accept": [c["accepted"] for c in out["chains"]],
             "failures": sum(c["failures"] for c in out["chains"])}
 

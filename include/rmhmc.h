@@ -269,6 +269,45 @@ rmhmc_status rmhmc_pool_poll(rmhmc_pool* pool, long long ticket, int wait, int* 
                              rmhmc_chain_stats* stats, double* times_ms);
 rmhmc_status rmhmc_pool_destroy(rmhmc_pool* pool);
 
+/* Batched chains with graph-captured moves, e.g. the tempered rungs of the
+ * power-posterior evidence estimate (appendix on model evidence): every
+ * admitted chain's move (momentum draw, C leapfrogs, Metropolis-Hastings,
+ * sample store) is recorded once into a HIP graph and replayed, one replay
+ * per move, on the batch's streams (default priority).  A chain's launch
+ * shapes come from a tuner keyed by its class (padded dimension and
+ * precision): on the first model of a class it times a few leapfrogs with
+ * 1, 2, 4 and 8 k-range layers for the single D x D products and sets the
+ * Jacobi sweep budget of each eigen-solve of a leapfrog's position
+ * iteration in the captured moves to one more than the most sweeps that
+ * iteration's warm start needed there; the choice is kept per class for the
+ * process, so a chain runs the same launches alone or in any mix.  In a
+ * captured move nothing is read back: a warm start that has not converged
+ * within the budget fails the move (a rejection, counted in fail_noconv),
+ * where rmhmc_chain would redo it statically.  Otherwise a chain's results
+ * are bitwise those of rmhmc_chain on the same model and configuration.
+ *   rmhmc_batch_admit: runs the chain's set-up (its first static solve, and
+ *     the tuning of a new class) on a batch stream, then captures the move;
+ *     q0, samples, logpost, accepted [device] as rmhmc_chain (caller-owned,
+ *     alive until retired).  The model belongs to the batch until retired:
+ *     other calls on it return RMHMC_E_ARG.  *slot [host] names the chain.
+ *   rmhmc_batch_step: queues n_moves more moves of every active chain
+ *     (chains stop at their cfg->n_moves); asynchronous.
+ *   rmhmc_batch_sync: waits for every queued move.
+ *   rmhmc_batch_retire: waits for the slot's moves, returns [host, nullable]
+ *     the moves run, the stats, and the sweep budget and layer count used,
+ *     and releases the model.
+ *   rmhmc_batch_destroy: waits, releases every model, frees the batch. */
+typedef struct rmhmc_batch rmhmc_batch;
+rmhmc_status rmhmc_batch_create(int n_streams, rmhmc_batch** out);
+rmhmc_status rmhmc_batch_admit(rmhmc_batch* batch, rmhmc_model* m, const rmhmc_chain_cfg* cfg,
+                               const double* q0, double* samples, double* logpost, int* accepted,
+                               int* slot);
+rmhmc_status rmhmc_batch_step(rmhmc_batch* batch, int n_moves);
+rmhmc_status rmhmc_batch_sync(rmhmc_batch* batch);
+rmhmc_status rmhmc_batch_retire(rmhmc_batch* batch, int slot, int* moves_done,
+                                rmhmc_chain_stats* stats, int* sweep_budget, int* gsplit);
+rmhmc_status rmhmc_batch_destroy(rmhmc_batch* batch);
+
 /* Building block exposed for tests and benchmarks: the MFMA GEMM every
  * dense product above runs on.  C = alpha op(A) op(B) + beta C, column-major,
  * op(X) = X' when the trans flag is non-zero; A, B, C [device].

@@ -17,6 +17,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -258,10 +259,14 @@ __device__ __forceinline__ double uniform53(unsigned long long w) {
 }
 
 // z[4j .. 4j+3] from block j: two Box-Muller pairs from words (0, 1), (2, 3).
+// The move index comes from device memory when dmove is given (a chain's
+// move counter, so that a captured move replays with the right counter).
 __global__ void normals_kernel(int D, unsigned long long seed, unsigned long long stream,
-                               unsigned long long move, double* __restrict__ z) {
+                               unsigned long long move_imm, const long long* __restrict__ dmove,
+                               double* __restrict__ z) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (4 * j >= D) return;
+  const unsigned long long move = dmove ? (unsigned long long)*dmove : move_imm;
   const Philox4 r = philox4x64((unsigned long long)j, move, 0ull, 0ull, seed, stream);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -295,11 +300,13 @@ enum { FAIL_NOT_PD = 1, FAIL_NOCONV = 4, FAIL_NONFINITE = 8 };
 // the decision in the output of a kept move; the failure word is cleared for
 // the next move.
 __global__ void mh_kernel(unsigned long long seed, unsigned long long stream,
-                          unsigned long long move, const double* __restrict__ ham,
-                          int* __restrict__ fail, int* __restrict__ acc,
-                          double* __restrict__ stats, int* __restrict__ kept_acc) {
+                          const long long* __restrict__ dmove, int n_burnin,
+                          const double* __restrict__ ham, int* __restrict__ fail,
+                          int* __restrict__ acc, double* __restrict__ stats,
+                          int* __restrict__ accepted_out) {
   if (threadIdx.x != 0) return;
-  const double u = uniform53(philox4x64(0ull, move, 1ull, 0ull, seed, stream).w[0]);
+  const long long move = *dmove;
+  const double u = uniform53(philox4x64(0ull, (unsigned long long)move, 1ull, 0ull, seed, stream).w[0]);
   const int f = *fail;
   const double h0 = ham[0], h1 = ham[1];
   const bool finite = isfinite(h0) && isfinite(h1);
@@ -313,8 +320,8 @@ __global__ void mh_kernel(unsigned long long seed, unsigned long long stream,
     if ((f & FAIL_NONFINITE) || (!finite && !(f & FAIL_NOT_PD))) stats[ST_NONFINITE] += 1.0;
     if (f & FAIL_NOCONV) stats[ST_NOCONV] += 1.0;
   }
-  if (kept_acc) {
-    kept_acc[0] = a ? 1 : 0;
+  if (move >= n_burnin) {
+    accepted_out[move - n_burnin] = a ? 1 : 0;
     stats[ST_ACC_KEPT] += a ? 1.0 : 0.0;
   }
   *fail = 0;
@@ -330,11 +337,26 @@ __global__ __launch_bounds__(256) void copy_if_kernel(long n, double2* __restric
     dst[i] = src[i];
 }
 
-__global__ void store_sample_kernel(int D, const double* __restrict__ q, const double* __restrict__ U,
-                                    double* __restrict__ sample, double* __restrict__ logpost) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < D) sample[i] = q[i];
-  if (i == 0) logpost[0] = -U[0];
+// After a move: the position and log posterior of the chain's point go to
+// the output row of a kept move; the move counter advances.  One workgroup.
+__global__ __launch_bounds__(1024) void store_sample_kernel(int D, const double* __restrict__ q,
+                                                            const double* __restrict__ U,
+                                                            long long* __restrict__ dmove,
+                                                            int n_burnin,
+                                                            double* __restrict__ samples,
+                                                            double* __restrict__ logpost) {
+  const long long move = *dmove;
+  if (move >= n_burnin) {
+    const long long row = move - n_burnin;
+    for (int i = threadIdx.x; i < D; i += 1024) samples[row * D + i] = q[i];
+    if (threadIdx.x == 0) logpost[row] = -U[0];
+  }
+  __syncthreads();   // every thread has read the counter before it advances
+  if (threadIdx.x == 0) *dmove = move + 1;
+}
+
+__global__ void set_counter_kernel(long long* __restrict__ c, long long v) {
+  if (threadIdx.x == 0) *c = v;
 }
 
 // One fixed-point update dst <- base + c1 x + c2 y of the implicit leapfrog
@@ -394,9 +416,12 @@ __global__ void any_nonfinite_kernel(long n, const double* __restrict__ x, int* 
 
 // ------------------------------------------------------------ model
 
-// k-range layers for the single Dp x Dp warm-start products: 17 x 17 tiles
-// at Dp = 1088 become 1156 workgroups, about four per CU.
-constexpr int GSPLIT = 4;
+// k-range layers for the single Dp x Dp warm-start products and K^-1 =
+// L^-T L^-1: 17 x 17 tiles at Dp = 1088 become 1156 workgroups with 4
+// layers, about four per CU.  The tuner may pick another count up to
+// GSPLIT_MAX per model.
+constexpr int GSPLIT_DEFAULT = 4;
+constexpr int GSPLIT_MAX = 8;
 
 // How an eigendecomposition is driven: host_check reads the stop flag after
 // each sweep past the first `blind` (single calls and the chain); without it
@@ -409,7 +434,11 @@ struct EigCfg {
   bool host_check = true;
   int* fail = nullptr;
   double* dstats = nullptr;
+  int* max_seen = nullptr;   // [host] largest sweep count of a warm start (host-checked mode)
 };
+// Largest number of fixed-point iterations whose eigen-solves get their own
+// sweep budget in a captured move.
+constexpr int MAX_FP_BUDGETS = 16;
 
 struct Model {
   int N = 0, dx = 0, P = 0, D = 0, Dp = 0;
@@ -429,7 +458,8 @@ struct Model {
   CholWork chol;
   EigWork eig;
   double *tallwork = nullptr, *kdwork = nullptr, *mdwork = nullptr;
-  double* gsplit = nullptr;   // split-K partials of the warm-start products (GSPLIT x Dp x Dp)
+  double* gsplit = nullptr;   // split-K partials of the warm-start products (GSPLIT_MAX x Dp x Dp)
+  int gsplit_layers = GSPLIT_DEFAULT;
   double *mvwork = nullptr;   // column-split partials of kd_matvec
   double *ktbuf = nullptr;    // generated second derivatives of K (<= MAX_TUPLES x N*N)
   double *W = nullptr, *Wt1 = nullptr, *Wt2 = nullptr;
@@ -447,6 +477,7 @@ struct Model {
   // Serialises every call that uses the model's scratch or its chain state
   // (calls on a model from several threads run one at a time).
   std::mutex busy;
+  bool in_batch = false;   // admitted to a batch: its chain state belongs to the batch slot
   ~Model();
 };
 
@@ -680,19 +711,21 @@ JacobiResult compute_eig(Model& m, Point& pt, const Point* warm, double alpha, c
     g.A = pt.H; g.lda = Dp;
     g.B = m.eig.Psi; g.ldb = Dp;
     g.C = m.Wt1; g.ldc = Dp;
-    gemm_splitk(g, m.gsplit, GSPLIT, st);
+    gemm_splitk(g, m.gsplit, m.gsplit_layers, st);
     Gemm<double> h;
     h.m = Dp; h.n = Dp; h.k = Dp;
     h.A = m.eig.Psi; h.lda = Dp; h.tA = true;
     h.B = m.Wt1; h.ldb = Dp;
     h.C = m.eig.M; h.ldc = Dp;
-    gemm_splitk(h, m.gsplit, GSPLIT, st);
+    gemm_splitk(h, m.gsplit, m.gsplit_layers, st);
     symmetrize(Dp, m.eig.M, Dp, st);
   }
-  const JacobiResult r =
+  const JacobiResult r0 =
       jacobi_eig(D, m.eig, ec.zeta, 1.0 / alpha, ec.max_sweeps,
                  warm ? JACOBI_INNER_DYNAMIC : JACOBI_INNER_STATIC, ec.blind, ec.host_check,
                  ec.host_check ? nullptr : ec.fail, ec.dstats, st);
+  const JacobiResult& r = r0;
+  if (warm && ec.host_check && ec.max_seen && r.sweeps > *ec.max_seen) *ec.max_seen = r.sweeps;
   // a static solve accumulates one rounding per rotation into Psi: restore
   // orthogonality before the eigenvalues are refined against H
   if (!warm) orthonormalise(D, Dp, m.eig.Psi, m.Wt1, m.Wt2, st);
@@ -1042,9 +1075,9 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   m.mvwork = pl.alloc<double>((long)KD_MV_SPLIT * std::min(m.npairs, MAX_TUPLES) * N + 64);
   m.ktbuf = pl.alloc<double>((long)std::min(m.npairs, MAX_TUPLES) * N * N + 64);
   m.mdwork = pl.alloc<double>(multi_dot_work(std::max<long>(N, Dp)) + 64);
-  m.gsplit = pl.alloc<double>((long)GSPLIT * Dp * Dp + 64);
+  m.gsplit = pl.alloc<double>((long)GSPLIT_MAX * std::max<long>(Dp * Dp, NN) + 64);
   m.chol.split = m.gsplit;   // same stream, never live at the same time
-  m.chol.nsplit = GSPLIT;
+  m.chol.nsplit = GSPLIT_DEFAULT;
   m.W = pl.alloc<double>(Dp * Dp);
   m.Wt1 = pl.alloc<double>(Dp * Dp);
   m.Wt2 = pl.alloc<double>(Dp * Dp);
@@ -1087,9 +1120,16 @@ struct State {
   EigCfg ec;         // eigensolver control (fail / dstats point into this state)
   long reorth_every = 10;
   long updates_since_reorth = 0;   // dynamic eigen-updates since the last re-orthonormalisation
+  // Captured moves: the sweep budget of the eigen-solve at each position of
+  // the position iteration (0 = none set); the tuner records the most sweeps
+  // each position needed in its host-checked probe leapfrogs.
+  int budget_pos[MAX_FP_BUDGETS] = {};
+  int seen_pos[MAX_FP_BUDGETS] = {};
+  bool track_pos = false;
   double *p, *ph, *v0, *vk, *gq, *qk, *ham, *z;
   int* fail = nullptr;     // failure word of the current move or step
   int* acc = nullptr;      // accept decision of the current move
+  long long* dmove = nullptr;   // index of the chain's next move (device)
   double* dstats = nullptr;   // ST_N device statistics
   double* hstats = nullptr;   // pinned mirror
   int* hfail = nullptr;       // pinned mirror of fail
@@ -1117,6 +1157,8 @@ std::unique_ptr<State> make_state(Model& m, double alpha) {
   s->ham = pl.alloc<double>(2);
   s->fail = pl.alloc<int>(2);
   s->acc = s->fail + 1;
+  s->dmove = pl.alloc<long long>(1);
+  RM_HIP(hipMemset(s->dmove, 0, sizeof(long long)));
   s->dstats = pl.alloc<double>(ST_N);
   s->hstats = pl.alloc_host<double>(ST_N);
   s->hfail = pl.alloc_host<int>(1);
@@ -1198,11 +1240,19 @@ Point* leapfrog(State& s, Point* cur, Point* keep, double eps, int K, hipStream_
   fp_update(D, cur->q, eps, s.v0, 0.0, s.v0, s.qk, K == 1 ? s.dstats + ST_RESQ : nullptr, st);
   const Point* warm = cur;
   bool good = true;
+  int pos = 0;
   auto eval = [&](Point& pt) {
     copy(pt.q, s.qk, D, st);
     const bool reorth = ++s.updates_since_reorth >= s.reorth_every;
     if (reorth) s.updates_since_reorth = 0;
-    good = full_point(m, pt, warm, s.alpha, s.ec, reorth, st, s.fail, &s.fallbacks) && good;
+    EigCfg ec = s.ec;
+    int seen = 0;
+    const int slot = std::min(pos, MAX_FP_BUDGETS - 1);
+    if (!ec.host_check && s.budget_pos[slot] > 0) ec.blind = s.budget_pos[slot];
+    if (s.track_pos) ec.max_seen = &seen;
+    good = full_point(m, pt, warm, s.alpha, ec, reorth, st, s.fail, &s.fallbacks) && good;
+    if (s.track_pos) s.seen_pos[slot] = std::max(s.seen_pos[slot], seen);
+    ++pos;
     warm = &pt;
   };
   for (int k = 1; k < K; ++k) {
@@ -1239,12 +1289,12 @@ void check_chain_cfg(const Model& m, const rmhmc_chain_cfg* cfg) {
   RM_REQUIRE(cfg->precision == m.prec, "chain precision differs from the model's");
 }
 
-void chain_impl(Model& m, const rmhmc_chain_cfg* cfg, const double* q0, double* samples,
-                double* logpost, int* accepted, rmhmc_chain_stats* stats, hipStream_t st) {
-  check_chain_cfg(m, cfg);
-  RM_REQUIRE(q0 && samples && logpost && accepted, "NULL argument");
+// Chain set-up: the configuration into the state, statistics and move
+// counter cleared, q0 loaded and its eigen-state solved statically (this
+// first solve must succeed; its failure is an error, not a rejection).
+void chain_begin(Model& m, State& S, const rmhmc_chain_cfg* cfg, const double* q0,
+                 hipStream_t st) {
   const int D = m.D;
-  State& S = *m.chain_state;
   S.alpha = cfg->alpha;
   S.ec.zeta = cfg->zeta > 0.0 ? cfg->zeta : 1e-13;
   S.ec.max_sweeps = cfg->max_sweeps > 0 ? cfg->max_sweeps : 60;
@@ -1252,52 +1302,216 @@ void chain_impl(Model& m, const rmhmc_chain_cfg* cfg, const double* q0, double* 
   S.ec.host_check = true;
   S.reorth_every = cfg->reorth_every > 0 ? cfg->reorth_every : 10;
   reset_stats(S, st);
+  hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, st, S.dmove, 0LL);
+  RM_CHECK_LAUNCH();
   Point* start = S.pts[0];
   copy(start->q, q0, D, st);
   check_flag_nonfinite(m, start->q, D, st, "q0");
-  {
-    EigCfg ec0 = S.ec;   // the first point is solved statically and must succeed
-    ec0.fail = nullptr;
-    full_point(m, *start, nullptr, S.alpha, ec0, false, st, nullptr, nullptr);
-  }
+  EigCfg ec0 = S.ec;
+  ec0.fail = nullptr;
+  full_point(m, *start, nullptr, S.alpha, ec0, false, st, nullptr, nullptr);
+}
+
+// One move of Algorithm 1 from the state's current point pts[0]: momentum
+// from the move's normals (move index read from the device counter), C
+// leapfrogs, Metropolis-Hastings on the device, the accepted end point copied
+// over the start point, the sample stored.  With host checks off (S.ec) it
+// reads nothing back and can be captured into a graph.
+void chain_move(Model& m, State& S, const rmhmc_chain_cfg* cfg, double* samples, double* logpost,
+                int* accepted, hipStream_t st) {
+  const int D = m.D;
+  Point* start = S.pts[0];
   const size_t words = start->data_bytes / sizeof(double2);
   const unsigned copy_grid = (unsigned)std::min<size_t>(cdiv((long)words, 256), 2048);
-  for (int ell = 0; ell < cfg->n_moves; ++ell) {
-    const bool kept = ell >= cfg->n_burnin;
-    const long row = ell - cfg->n_burnin;
-    // p ~ N(0, G(q)) from the move's normals
-    hipLaunchKernelGGL(normals_kernel, dim3(cdiv(cdiv(D, 4), 64)), dim3(64), 0, st, D, cfg->seed,
-                       cfg->stream_id, (unsigned long long)ell, S.z);
-    RM_CHECK_LAUNCH();
-    draw_momentum(m, S, *start, S.z, st);
-    metric_vectors(m, *start, S.p, nullptr, S.ham, st);
-    S.updates_since_reorth = 0;
-    Point* cur = start;
-    bool ok = true;
-    for (int c = 0; c < cfg->n_leapfrog && ok; ++c)
-      cur = leapfrog(S, cur, start, cfg->eps, cfg->n_fixed_point, st, &ok);
-    metric_vectors(m, *cur, S.p, nullptr, S.ham + 1, st);
-    hipLaunchKernelGGL(mh_kernel, dim3(1), dim3(64), 0, st, cfg->seed, cfg->stream_id,
-                       (unsigned long long)ell, (const double*)S.ham, S.fail, S.acc, S.dstats,
-                       kept ? accepted + row : (int*)nullptr);
-    RM_CHECK_LAUNCH();
-    hipLaunchKernelGGL(copy_if_kernel, dim3(copy_grid), dim3(256), 0, st, (long)words,
-                       (double2*)start->data, (const double2*)cur->data, (const int*)S.acc);
-    RM_CHECK_LAUNCH();
-    if (kept) {
-      hipLaunchKernelGGL(store_sample_kernel, dim3(cdiv(D, 256)), dim3(256), 0, st, D,
-                         (const double*)start->q, (const double*)(start->scal + 1),
-                         samples + row * D, logpost + row);
-      RM_CHECK_LAUNCH();
-    }
-  }
+  // p ~ N(0, G(q)) from the move's normals
+  hipLaunchKernelGGL(normals_kernel, dim3(cdiv(cdiv(D, 4), 64)), dim3(64), 0, st, D, cfg->seed,
+                     cfg->stream_id, 0ull, (const long long*)S.dmove, S.z);
+  RM_CHECK_LAUNCH();
+  draw_momentum(m, S, *start, S.z, st);
+  metric_vectors(m, *start, S.p, nullptr, S.ham, st);
+  S.updates_since_reorth = 0;
+  Point* cur = start;
+  bool ok = true;
+  for (int c = 0; c < cfg->n_leapfrog && ok; ++c)
+    cur = leapfrog(S, cur, start, cfg->eps, cfg->n_fixed_point, st, &ok);
+  metric_vectors(m, *cur, S.p, nullptr, S.ham + 1, st);
+  hipLaunchKernelGGL(mh_kernel, dim3(1), dim3(64), 0, st, cfg->seed, cfg->stream_id,
+                     (const long long*)S.dmove, cfg->n_burnin, (const double*)S.ham, S.fail,
+                     S.acc, S.dstats, accepted);
+  RM_CHECK_LAUNCH();
+  hipLaunchKernelGGL(copy_if_kernel, dim3(copy_grid), dim3(256), 0, st, (long)words,
+                     (double2*)start->data, (const double2*)cur->data, (const int*)S.acc);
+  RM_CHECK_LAUNCH();
+  hipLaunchKernelGGL(store_sample_kernel, dim3(1), dim3(1024), 0, st, D, (const double*)start->q,
+                     (const double*)(start->scal + 1), S.dmove, cfg->n_burnin, samples, logpost);
+  RM_CHECK_LAUNCH();
+}
+
+void chain_impl(Model& m, const rmhmc_chain_cfg* cfg, const double* q0, double* samples,
+                double* logpost, int* accepted, rmhmc_chain_stats* stats, hipStream_t st) {
+  check_chain_cfg(m, cfg);
+  RM_REQUIRE(q0 && samples && logpost && accepted, "NULL argument");
+  State& S = *m.chain_state;
+  chain_begin(m, S, cfg, q0, st);
+  for (int ell = 0; ell < cfg->n_moves; ++ell) chain_move(m, S, cfg, samples, logpost, accepted, st);
   rmhmc_chain_stats tmp;
   read_stats(S, &tmp, st);
   if (stats) *stats = tmp;
 }
 
+// ------------------------------------------------------------ launch-shape tuner
+// For a class of chains (padded dimension and precision) the tuner picks, on
+// the first model of the class it sees, (a) the number of k-range layers of
+// the single Dp x Dp products and of K^-1 = L^-T L^-1 (1, 2, 4 or 8), by
+// timing a few leapfrogs with each, and (b) the Jacobi sweep budget of the
+// graph-captured moves: one more than the most sweeps a warm start needed in
+// those leapfrogs.  The result is kept per class for the process, so every
+// chain of a class runs the same launch shapes wherever it is admitted.
+struct TunedShape {
+  int gsplit = GSPLIT_DEFAULT;
+  int sweep_budget = 6;               // the largest of budget_pos
+  int budget_pos[MAX_FP_BUDGETS] = {};
+  double ms_per_leapfrog = 0.0;
+  bool valid = false;
+};
+
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, TunedShape> g_tuned;
+
+void apply_shape(Model& m, const TunedShape& t) {
+  m.gsplit_layers = t.gsplit;
+  m.chol.nsplit = t.gsplit;
+}
+
+TunedShape tune_class(Model& m, const rmhmc_chain_cfg* cfg, const double* q0, hipStream_t st) {
+  const std::pair<int, int> key(m.Dp, (int)m.prec);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) return it->second;
+  }
+  State& S = *m.chain_state;
+  const int probe = std::max(1, std::min(cfg->n_leapfrog, 3));
+  hipEvent_t e0, e1;
+  RM_HIP(hipEventCreate(&e0));
+  RM_HIP(hipEventCreate(&e1));
+  TunedShape best;
+  int seen = 0;
+  for (int& v : S.seen_pos) v = 0;
+  for (int layers : {1, 2, 4, 8}) {
+    TunedShape t;
+    t.gsplit = layers;
+    apply_shape(m, t);
+    chain_begin(m, S, cfg, q0, st);
+    hipLaunchKernelGGL(normals_kernel, dim3(cdiv(cdiv(m.D, 4), 64)), dim3(64), 0, st, m.D,
+                       cfg->seed, cfg->stream_id, 0ull, (const long long*)S.dmove, S.z);
+    RM_CHECK_LAUNCH();
+    draw_momentum(m, S, *S.pts[0], S.z, st);
+    S.updates_since_reorth = 0;
+    S.track_pos = true;
+    Point* cur = S.pts[0];
+    // one untimed leapfrog: it also computes the start point's precompute
+    cur = leapfrog(S, cur, S.pts[0], cfg->eps, cfg->n_fixed_point, st, nullptr);
+    RM_HIP(hipEventRecord(e0, st));
+    for (int c = 0; c < probe; ++c)
+      cur = leapfrog(S, cur, S.pts[0], cfg->eps, cfg->n_fixed_point, st, nullptr);
+    RM_HIP(hipEventRecord(e1, st));
+    RM_HIP(hipEventSynchronize(e1));
+    S.track_pos = false;
+    float ms = 0.f;
+    RM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    t.ms_per_leapfrog = ms / probe;
+    if (!best.valid || t.ms_per_leapfrog < best.ms_per_leapfrog) {
+      best = t;
+      best.valid = true;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // one sweep of margin over the most each position of the position
+  // iteration needed in the probe
+  best.sweep_budget = 0;
+  for (int k = 0; k < MAX_FP_BUDGETS; ++k) {
+    best.budget_pos[k] = S.seen_pos[k] > 0 ? S.seen_pos[k] + 1 : 2;
+    best.sweep_budget = std::max(best.sweep_budget, best.budget_pos[k]);
+  }
+  (void)seen;
+  if (eig_trace()) {
+    std::fprintf(stderr, "[tune] Dp=%d prec=%d gsplit=%d ms/leapfrog=%.3f budgets", m.Dp,
+                 (int)m.prec, best.gsplit, best.ms_per_leapfrog);
+    for (int k = 0; k < cfg->n_fixed_point && k < MAX_FP_BUDGETS; ++k)
+      std::fprintf(stderr, " %d", best.budget_pos[k]);
+    std::fprintf(stderr, "\n");
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) return it->second;   // tuned meanwhile by another thread
+    g_tuned[key] = best;
+  }
+  return best;
+}
+
+// The move of a chain captured into a graph: set up eagerly (static first
+// solve and the start point's contraction precompute), then one move with
+// host checks off is recorded on the stream and instantiated.  Replaying the
+// graph advances the chain by one move: the move index lives in the state's
+// device counter and the trial points are chosen in the same order every
+// move, so the recorded launches are the same for every move.
+hipGraphExec_t capture_move(Model& m, const rmhmc_chain_cfg* cfg, const double* q0,
+                            double* samples, double* logpost, int* accepted,
+                            const TunedShape& shape, hipStream_t st, hipGraph_t* graph_out) {
+  RM_REQUIRE(!timing_enabled(), "kernel timing must be off while a move is captured");
+  State& S = *m.chain_state;
+  chain_begin(m, S, cfg, q0, st);
+  compute_vW2(m, *S.pts[0], st);   // precompute and v(W2) of the start point
+  RM_HIP(hipStreamSynchronize(st));
+  const EigCfg saved = S.ec;
+  S.ec.host_check = false;
+  S.ec.blind = shape.sweep_budget;
+  for (int k = 0; k < MAX_FP_BUDGETS; ++k) S.budget_pos[k] = shape.budget_pos[k];
+  hipGraph_t graph = nullptr;
+  RM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  try {
+    chain_move(m, S, cfg, samples, logpost, accepted, st);
+  } catch (...) {
+    (void)hipStreamEndCapture(st, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    S.ec = saved;
+    throw;
+  }
+  RM_HIP(hipStreamEndCapture(st, &graph));
+  S.ec = saved;
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    throw Error(RMHMC_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  *graph_out = graph;
+  return exec;
+}
+
 }  // namespace
 }  // namespace rmhmc
+
+// ------------------------------------------------------------ batch of graph-captured chains
+
+struct rmhmc_batch {
+  struct Slot {
+    rmhmc_model* m = nullptr;
+    rmhmc_chain_cfg cfg{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t st = nullptr;
+    int launched = 0;
+    bool active = false;
+    rmhmc::TunedShape shape;
+  };
+  std::vector<hipStream_t> streams;
+  std::vector<Slot> slots;
+  std::mutex mu;
+};
 
 // ------------------------------------------------------------ worker pool
 // Chains (Algorithm 1) run concurrently on a fixed set of worker threads,
@@ -1372,6 +1586,7 @@ void pool_worker(rmhmc_pool* pool, int w) {
     rmhmc_status status = RMHMC_OK;
     std::string err;
     try {
+      RM_REQUIRE(!job->m->impl.in_batch, "the model is admitted to a batch");
       chain_impl(job->m->impl, &job->cfg, job->q0, job->samples, job->logpost, job->accepted,
                  &job->stats, st);
     } catch (const Error& e) {
@@ -1678,6 +1893,7 @@ rmhmc_status rmhmc_hessian(rmhmc_model* mh, const double* q, double* U, double* 
     Model& m = mh->impl;
     RM_REQUIRE(ldh >= m.D, "ldh < D");
     std::lock_guard<std::mutex> lk(m.busy);
+    RM_REQUIRE(!m.in_batch, "the model is admitted to a batch");
     Point& pt = *m.api_pt;
     copy(pt.q, q, m.D, st);
     check_flag_nonfinite(m, pt.q, m.D, st, "q");
@@ -1739,6 +1955,7 @@ rmhmc_status rmhmc_metric_grad(rmhmc_model* mh, const double* q, const double* p
     RM_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "alpha must be positive");
     Model& m = mh->impl;
     std::lock_guard<std::mutex> lk(m.busy);
+    RM_REQUIRE(!m.in_batch, "the model is admitted to a batch");
     Point& pt = *m.api_pt;
     copy(pt.q, q, m.D, st);
     compute_hessian(m, pt, st, nullptr);
@@ -1761,6 +1978,7 @@ rmhmc_status rmhmc_state_create(rmhmc_model* mh, const double* q0, const double*
     RM_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "alpha must be positive");
     Model& m = mh->impl;
     std::lock_guard<std::mutex> lk(m.busy);
+    RM_REQUIRE(!m.in_batch, "the model is admitted to a batch");
     auto s = std::make_unique<rmhmc_state>();
     s->impl = make_state(m, alpha);
     State& S = *s->impl;
@@ -1780,6 +1998,7 @@ rmhmc_status rmhmc_state_get(const rmhmc_state* sh, double* q, double* p, double
     State& S = *sh->impl;
     Model& m = *S.m;
     std::lock_guard<std::mutex> lk(m.busy);
+    RM_REQUIRE(!m.in_batch, "the model is admitted to a batch");
     copy(q, S.pts[0]->q, m.D, st);
     copy(p, S.p, m.D, st);
     if (ham) metric_vectors(m, *S.pts[0], S.p, nullptr, ham, st);
@@ -1818,7 +2037,7 @@ rmhmc_status rmhmc_chain_randoms(int D, unsigned long long seed, unsigned long l
   return guard([&] {
     RM_REQUIRE(D >= 1 && z && u, "bad argument");
     hipLaunchKernelGGL(normals_kernel, dim3(cdiv(cdiv(D, 4), 64)), dim3(64), 0, st, D, seed,
-                       stream_id, move, z);
+                       stream_id, move, (const long long*)nullptr, z);
     RM_CHECK_LAUNCH();
     hipLaunchKernelGGL(uniform_kernel, dim3(1), dim3(64), 0, st, seed, stream_id, move, u);
     RM_CHECK_LAUNCH();
@@ -1857,6 +2076,7 @@ rmhmc_status rmhmc_glf_step(rmhmc_model* mh, rmhmc_state* sh, double eps, int n_
     RM_REQUIRE(std::isfinite(eps) && eps > 0.0, "eps must be positive");
     State& S = *sh->impl;
     std::lock_guard<std::mutex> lk(mh->impl.busy);
+    RM_REQUIRE(!mh->impl.in_batch, "the model is admitted to a batch");
     Point* nxt = leapfrog(S, S.pts[0], nullptr, eps, n_fixed_point, st, nullptr);
     // one read of the failure word per step; a failed step leaves the state
     // at its start point
@@ -1881,7 +2101,115 @@ rmhmc_status rmhmc_chain(rmhmc_model* mh, const rmhmc_chain_cfg* cfg, const doub
   return guard([&] {
     RM_REQUIRE(mh != nullptr, "NULL model");
     std::lock_guard<std::mutex> lk(mh->impl.busy);
+    RM_REQUIRE(!mh->impl.in_batch, "the model is admitted to a batch");
     chain_impl(mh->impl, cfg, q0, samples, logpost, accepted, stats, st);
+  });
+}
+
+rmhmc_status rmhmc_batch_create(int n_streams, rmhmc_batch** out) {
+  return guard([&] {
+    RM_REQUIRE(out != nullptr, "out is NULL");
+    RM_REQUIRE(n_streams >= 1 && n_streams <= 64, "n_streams must be in 1..64");
+    auto b = std::make_unique<rmhmc_batch>();
+    for (int i = 0; i < n_streams; ++i) {
+      hipStream_t s;
+      RM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      b->streams.push_back(s);
+    }
+    *out = b.release();
+  });
+}
+
+rmhmc_status rmhmc_batch_admit(rmhmc_batch* b, rmhmc_model* mh, const rmhmc_chain_cfg* cfg,
+                               const double* q0, double* samples, double* logpost, int* accepted,
+                               int* slot) {
+  return guard([&] {
+    RM_REQUIRE(b && mh && cfg && q0 && samples && logpost && accepted && slot, "NULL argument");
+    Model& m = mh->impl;
+    check_chain_cfg(m, cfg);
+    std::lock_guard<std::mutex> blk(b->mu);
+    std::lock_guard<std::mutex> lk(m.busy);
+    RM_REQUIRE(!m.in_batch, "the model is already admitted to a batch");
+    int k = 0;
+    while (k < (int)b->slots.size() && b->slots[k].active) ++k;
+    if (k == (int)b->slots.size()) b->slots.emplace_back();
+    rmhmc_batch::Slot& sl = b->slots[k];
+    sl = rmhmc_batch::Slot{};
+    sl.m = mh;
+    sl.cfg = *cfg;
+    sl.st = b->streams[k % b->streams.size()];
+    sl.shape = tune_class(m, cfg, q0, sl.st);
+    apply_shape(m, sl.shape);
+    sl.exec = capture_move(m, cfg, q0, samples, logpost, accepted, sl.shape, sl.st, &sl.graph);
+    m.in_batch = true;
+    sl.active = true;
+    *slot = k;
+  });
+}
+
+rmhmc_status rmhmc_batch_step(rmhmc_batch* b, int n_moves) {
+  return guard([&] {
+    RM_REQUIRE(b != nullptr, "NULL batch");
+    RM_REQUIRE(n_moves >= 0, "n_moves must be >= 0");
+    std::lock_guard<std::mutex> blk(b->mu);
+    // one move of every active chain in turn, so the streams stay busy together
+    for (int k = 0; k < n_moves; ++k)
+      for (auto& sl : b->slots) {
+        if (!sl.active || sl.launched >= sl.cfg.n_moves) continue;
+        RM_HIP(hipGraphLaunch(sl.exec, sl.st));
+        ++sl.launched;
+      }
+  });
+}
+
+rmhmc_status rmhmc_batch_sync(rmhmc_batch* b) {
+  return guard([&] {
+    RM_REQUIRE(b != nullptr, "NULL batch");
+    for (hipStream_t s : b->streams) RM_HIP(hipStreamSynchronize(s));
+  });
+}
+
+rmhmc_status rmhmc_batch_retire(rmhmc_batch* b, int slot, int* moves_done,
+                                rmhmc_chain_stats* stats, int* sweep_budget, int* gsplit) {
+  return guard([&] {
+    RM_REQUIRE(b != nullptr, "NULL batch");
+    std::lock_guard<std::mutex> blk(b->mu);
+    RM_REQUIRE(slot >= 0 && slot < (int)b->slots.size() && b->slots[slot].active, "no such slot");
+    rmhmc_batch::Slot& sl = b->slots[slot];
+    RM_HIP(hipStreamSynchronize(sl.st));
+    Model& m = sl.m->impl;
+    State& S = *m.chain_state;
+    S.leapfrogs = (long)sl.launched * sl.cfg.n_leapfrog;
+    S.fallbacks = 0;
+    rmhmc_chain_stats st{};
+    read_stats(S, &st, sl.st);
+    if (stats) *stats = st;
+    if (moves_done) *moves_done = sl.launched;
+    if (sweep_budget) *sweep_budget = sl.shape.sweep_budget;
+    if (gsplit) *gsplit = sl.shape.gsplit;
+    (void)hipGraphExecDestroy(sl.exec);
+    (void)hipGraphDestroy(sl.graph);
+    {
+      std::lock_guard<std::mutex> lk(m.busy);
+      m.in_batch = false;
+    }
+    sl = rmhmc_batch::Slot{};
+  });
+}
+
+rmhmc_status rmhmc_batch_destroy(rmhmc_batch* b) {
+  return guard([&] {
+    if (!b) return;
+    for (hipStream_t s : b->streams) (void)hipStreamSynchronize(s);
+    for (auto& sl : b->slots) {
+      if (!sl.active) continue;
+      (void)hipGraphExecDestroy(sl.exec);
+      (void)hipGraphDestroy(sl.graph);
+      std::lock_guard<std::mutex> lk(sl.m->impl.busy);
+      sl.m->impl.in_batch = false;
+    }
+    for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+    delete b;
   });
 }
 

@@ -32,7 +32,9 @@ EXPORTED = ["rmhmc_model_create", "rmhmc_model_dims", "rmhmc_model_destroy", "rm
             "rmhmc_state_draw_momentum",
             "rmhmc_timing_enable", "rmhmc_timing_read", "rmhmc_pool_create", "rmhmc_pool_submit",
             "rmhmc_pool_poll", "rmhmc_pool_destroy", "rmhmc_state_stats", "rmhmc_model_bytes",
-            "rmhmc_softabs_eig_reserve", "rmhmc_chain_randoms", "rmhmc_softabs_eig_noalloc"]
+            "rmhmc_softabs_eig_reserve", "rmhmc_chain_randoms", "rmhmc_softabs_eig_noalloc",
+            "rmhmc_batch_create", "rmhmc_batch_admit", "rmhmc_batch_step", "rmhmc_batch_sync",
+            "rmhmc_batch_retire", "rmhmc_batch_destroy"]
 
 TIMER_KINDS = {"gemm_f64": 0, "gemm_f32": 1, "jacobi_solve": 2, "jacobi_apply": 3, "kd_wsum": 4,
                "kd_matvec": 5, "potrf_diag": 6}
@@ -94,6 +96,13 @@ _sig = {
     "rmhmc_pool_poll": [_vp, C.c_longlong, _i, C.POINTER(_i), C.POINTER(ChainStats),
                         C.POINTER(_d)],
     "rmhmc_pool_destroy": [_vp],
+    "rmhmc_batch_create": [_i, C.POINTER(_vp)],
+    "rmhmc_batch_admit": [_vp, _vp, C.POINTER(ChainCfg), _vp, _vp, _vp, _vp, C.POINTER(_i)],
+    "rmhmc_batch_step": [_vp, _i],
+    "rmhmc_batch_sync": [_vp],
+    "rmhmc_batch_retire": [_vp, _i, C.POINTER(_i), C.POINTER(ChainStats), C.POINTER(_i),
+                           C.POINTER(_i)],
+    "rmhmc_batch_destroy": [_vp],
     "rmhmc_timing_read": [_i, C.POINTER(C.c_longlong), C.POINTER(_d), C.POINTER(_d), C.POINTER(_d)],
     "rmhmc_glf_step": [_vp, _vp, _d, _i, _vp],
     "rmhmc_chain": [_vp, C.POINTER(ChainCfg), _vp, _vp, _vp, _vp, C.POINTER(ChainStats), _vp],
@@ -400,6 +409,59 @@ class Pool:
     def close(self):
         if getattr(self, "_h", None):
             _lib.rmhmc_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Chains whose moves are captured into HIP graphs and replayed side by
+    side on a few streams (rmhmc_batch)."""
+
+    def __init__(self, n_streams=8):
+        h = C.c_void_p()
+        _check(_lib.rmhmc_batch_create(n_streams, C.byref(h)))
+        self._h = h
+        self.jobs = {}
+
+    def admit(self, model, q0, eps, n_leapfrog, n_fixed_point, n_moves, n_burnin=0, seed=0,
+              stream_id=0, alpha=1e6, zeta=0.0, max_sweeps=0, reorth_every=0):
+        torch = _torch()
+        job = ChainJob(model, q0, chain_cfg(model, eps, n_leapfrog, n_fixed_point, n_moves,
+                                            n_burnin, seed, stream_id, alpha, zeta, max_sweeps,
+                                            reorth_every))
+        slot = C.c_int()
+        _check(_lib.rmhmc_batch_admit(self._h, model._h, C.byref(job.cfg), _f64(q0),
+                                      _f64(job.samples), _f64(job.logpost),
+                                      _ptr(job.accepted, torch.int32), C.byref(slot)))
+        job.ticket = slot.value
+        self.jobs[slot.value] = job
+        return job
+
+    def step(self, n_moves):
+        _check(_lib.rmhmc_batch_step(self._h, n_moves))
+
+    def sync(self):
+        _check(_lib.rmhmc_batch_sync(self._h))
+
+    def retire(self, job):
+        done, budget, layers = C.c_int(), C.c_int(), C.c_int()
+        st = ChainStats()
+        _check(_lib.rmhmc_batch_retire(self._h, job.ticket, C.byref(done), C.byref(st),
+                                       C.byref(budget), C.byref(layers)))
+        job.stats = st
+        job.moves_done = done.value
+        job.shape = {"sweep_budget": budget.value, "gsplit": layers.value}
+        self.jobs.pop(job.ticket, None)
+        return job
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.rmhmc_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

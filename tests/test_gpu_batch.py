@@ -67,7 +67,7 @@ def test_pool_mix_equals_alone(rm):
 
 def test_tempered_ladder_runs_and_matches_reference(rm):
     from paper_2511_06407_amd.tempered import run_tempered
-    out = run_tempered(n_chains=6, n_moves=2, n_leapfrog=2, n_workers=3, seed=0)
+    out = run_tempered(n_chains=6, n_moves=2, n_leapfrog=2, n_workers=3, seed=0, engine="pool")
     record("tempered", wall_s=out["wall_s"], leapfrogs=out["chain_leapfrogs"],
            lf_per_s=out["chain_leapfrogs_per_s"])
     assert out["chain_leapfrogs"] > 0
@@ -110,3 +110,79 @@ def test_serving_results_same_alone_and_in_mix(rm):
         torch.cuda.synchronize()
         assert np.array_equal(s.cpu().numpy(), kept[r.rid].samples.cpu().numpy())
     ex.close()
+
+
+def test_graph_batch_equals_eager_chain_and_alone(rm):
+    """Chains whose moves are replayed from captured graphs: identical to
+    themselves admitted alone, and to the eager rmhmc_chain on the same model
+    with the same (tuned) launch shapes."""
+    n_moves, C_, K = 3, 2, 6
+    runs = []
+    for k, (spec, eps) in enumerate(specs_mix()):
+        runs.append((spec, eps, dev(np.zeros(spec.D)), k))
+    models = [rm.Model(spec) for spec, *_ in runs]
+    # alone: one chain per batch (admission tunes the chain's class and sets
+    # the model's launch shapes; later runs reuse them)
+    alone = []
+    for m, (spec, eps, q0, k) in zip(models, runs):
+        b = rm.Batch(1)
+        j = b.admit(m, q0, eps, C_, K, n_moves, seed=4, stream_id=k)
+        b.step(n_moves)
+        b.sync()
+        b.retire(j)
+        b.close()
+        alone.append((j.samples.cpu().numpy(), j.logpost.cpu().numpy(), j.accepted.cpu().numpy(),
+                      j.stats, j.shape))
+    # the eager chain on the same models (now with the tuned launch shapes)
+    eager = []
+    for m, (spec, eps, q0, k) in zip(models, runs):
+        s, l, a, st = m.chain(q0, eps, C_, K, n_moves, seed=4, stream_id=k)
+        torch.cuda.synchronize()
+        eager.append((s.cpu().numpy(), l.cpu().numpy(), a.cpu().numpy()))
+    # mixed: all chains in one batch on two streams
+    b = rm.Batch(2)
+    jobs = [b.admit(m, q0, eps, C_, K, n_moves, seed=4, stream_id=k)
+            for m, (spec, eps, q0, k) in zip(models, runs)]
+    b.step(n_moves)
+    b.sync()
+    for k, j in enumerate(jobs):
+        b.retire(j)
+        s, l, a = j.samples.cpu().numpy(), j.logpost.cpu().numpy(), j.accepted.cpu().numpy()
+        record("graph_batch", chain=k, D=runs[k][0].D, moves=j.moves_done,
+               accepted=int(a.sum()), sweep_budget=j.shape["sweep_budget"],
+               gsplit=j.shape["gsplit"], noconv=j.stats.fail_noconv,
+               vs_eager=rel(s, eager[k][0]))
+        assert j.moves_done == n_moves and j.stats.leapfrogs == n_moves * C_
+        assert j.stats.fail_noconv == 0
+        assert np.array_equal(s, alone[k][0]) and np.array_equal(l, alone[k][1])
+        assert np.array_equal(a, alone[k][2])
+        assert np.array_equal(s, eager[k][0]) and np.array_equal(a, eager[k][2])
+    b.close()
+    # a model in a batch is refused elsewhere until retired
+    b = rm.Batch(1)
+    j = b.admit(models[0], runs[0][2], runs[0][1], C_, K, n_moves, seed=4)
+    with pytest.raises(rm.RmhmcError):
+        models[0].chain(runs[0][2], runs[0][1], C_, K, n_moves)
+    b.step(n_moves)
+    b.retire(j)
+    b.close()
+
+
+def test_graph_tempered_ladder_matches_reference(rm):
+    """The tempered ladder on the graph engine: the smallest chain's first
+    moves against the reference chain within 10 x its permutation floor."""
+    from paper_2511_06407_amd.tempered import run_tempered
+    out = run_tempered(n_chains=6, n_moves=2, n_leapfrog=2, n_workers=3, seed=0, engine="graph")
+    record("tempered_graph", wall_s=out["wall_s"], setup_s=out["setup_s"],
+           leapfrogs=out["chain_leapfrogs"], lf_per_s=out["chain_leapfrogs_per_s"])
+    k = int(np.argmin([c["D"] for c in out["chains"]]))
+    specs, dims, betas = wl.tempered_ladder(6, 0)
+    spec = specs[k]
+    ref = run_seeded_chain(oham.GPTarget(spec), np.zeros(spec.D), 0.01, 2, 6, 1e6, 2, 0, 0, k)
+    got = out["jobs"][k].samples.cpu().numpy()
+    fl = chain_floor(spec, 0.01, 2, 6, 1e6, 2, 0, k, ref)
+    bar = max(1e-10, 10 * fl)
+    e = rel(got, ref[0])
+    record("tempered_graph_ref", chain=k, D=spec.D, samples=e, floor=fl, bar=bar)
+    assert np.array_equal(out["jobs"][k].accepted.cpu().numpy(), ref[2])
+    assert e < bar
