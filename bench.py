@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--chains", type=int, default=64)
     ap.add_argument("--moves", type=int, default=4, help="moves per chain (tempered mode)")
     ap.add_argument("--workers", type=int, default=8, help="streams (graph) or workers (pool)")
-    ap.add_argument("--engine", choices=["graph", "pool"], default="graph",
+    ap.add_argument("--engine", choices=["graph", "pool"], default="pool",
                     help="tempered mode: graph-captured batch or eager worker pool")
     ap.add_argument("--rate", type=float, default=20.0, help="requests/s (serve mode)")
     ap.add_argument("--duration", type=float, default=3.0, help="arrival window in s (serve)")

@@ -44,6 +44,14 @@ typedef enum {
 
 typedef enum { RMHMC_FP64 = 0, RMHMC_MIXED = 1 } rmhmc_precision;
 
+/* The soft-absolute map of the metric, G = sum g(lam) psi psi' (Sec. 2.2):
+ *   RMHMC_SOFTABS_COTH  g = lam coth(alpha lam), the form the paper names
+ *                       after earlier software (Sec. 2.5);
+ *   RMHMC_SOFTABS_SQRT  g = sqrt(kappa^2 + lam^2), kappa = 1 / alpha, the form
+ *                       the paper's own runs use (Sec. 2.5, kappa = 1).
+ * Both stay above 1 / alpha (= kappa) and approach |lam| for large |lam|. */
+typedef enum { RMHMC_SOFTABS_COTH = 0, RMHMC_SOFTABS_SQRT = 1 } rmhmc_softabs;
+
 typedef enum { RMHMC_LIK_BERNOULLI_LOGIT = 0, RMHMC_LIK_GAUSSIAN = 1 } rmhmc_lik;
 
 /* Kernel terms of the multiple-kernel prior f ~ GP(0, sum_c k_c) (Sec. 2.1,
@@ -91,7 +99,8 @@ typedef struct rmhmc_state rmhmc_state;
  * Metropolis-Hastings uniform of a move from purpose 1. */
 typedef struct {
   double eps;            /* leapfrog step size epsilon                        */
-  double alpha;          /* softabs sharpness (g = lam coth(alpha lam))       */
+  double alpha;          /* softabs sharpness (coth: g = lam coth(alpha lam);
+                            sqrt: kappa = 1 / alpha)                          */
   double zeta;           /* Jacobi tolerance (<= 0: 1e-13)                    */
   int n_leapfrog;        /* C, leapfrogs per move                             */
   int n_moves;           /* A, moves in all (burn-in included)                */
@@ -103,6 +112,7 @@ typedef struct {
   unsigned long long seed;       /* Philox key word 0                          */
   unsigned long long stream_id;  /* Philox key word 1 (independent chains)     */
   int precision;         /* rmhmc_precision; must equal the model's           */
+  int softabs;           /* rmhmc_softabs: the map g of the metric            */
 } rmhmc_chain_cfg;
 
 typedef struct {
@@ -136,6 +146,14 @@ rmhmc_status rmhmc_model_dims(const rmhmc_model* m, int* N, int* P, int* D); /* 
 /* Device bytes held by the model (its scratch and chain state).  [host] out. */
 rmhmc_status rmhmc_model_bytes(const rmhmc_model* m, long long* bytes);
 rmhmc_status rmhmc_model_destroy(rmhmc_model* m);
+/* The inverse temperature tau of the power posterior P(X|f)^tau prior(f, eta)
+ * (appendix on model evidence): the likelihood of later calls is raised to
+ * beta.  A host-side setting; no device work. */
+rmhmc_status rmhmc_model_set_beta(rmhmc_model* m, double beta);
+/* ln P(X | f) at q = (f, eta) (Sec. 2.1, Eq. data_likelihood; no tempering),
+ * the integrand of the thermodynamic evidence estimate.  q [device] D,
+ * ll [device] 1.  Synchronises the stream. */
+rmhmc_status rmhmc_log_likelihood(rmhmc_model* m, const double* q, double* ll, hipStream_t stream);
 
 /* U(q) = -ln P(q) (constants included), grad U and the Hessian H of U at q
  * (H is the matrix the softabs map of Sec. 2.2 is applied to).
@@ -151,7 +169,8 @@ rmhmc_status rmhmc_hessian(rmhmc_model* m, const double* q, double* U, double* g
  * Jacobi on Q_warm' H Q_warm, then Q = Q_warm * (its rotations).  Stops when
  * off(M)_F <= zeta ||M||_F (zeta <= 0 selects 1e-13).
  *   H [device] D x D (ldh); Q_warm, Q [device] D x D (ld = D);
- *   lam, g, gp [device] D: eigenvalues, g = lam coth(alpha lam) and g';
+ *   softabs: the map g (rmhmc_softabs) with parameter alpha;
+ *   lam, g, gp [device] D: eigenvalues, g(lam) and g'(lam);
  *   logdetG [device] 1 = sum log g;  sweeps [host, nullable].
  * Eigenvalues are not sorted.  Reads the convergence flag after each sweep;
  * synchronises the stream.  The workspace is per device and shared by the
@@ -159,9 +178,9 @@ rmhmc_status rmhmc_hessian(rmhmc_model* m, const double* q, double* U, double* g
  * allocates it, which rmhmc_softabs_eig_reserve(D) does ahead of time.
  * RMHMC_E_EIG_NOCONV if max_sweeps (<= 0 selects 60) runs out,
  * RMHMC_E_NONFINITE for non-finite entries. */
-rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, double zeta,
-                               int max_sweeps, const double* Q_warm, double* Q, double* lam,
-                               double* g, double* gp, double* logdetG, int* sweeps,
+rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, int softabs,
+                               double zeta, int max_sweeps, const double* Q_warm, double* Q,
+                               double* lam, double* g, double* gp, double* logdetG, int* sweeps,
                                hipStream_t stream);
 rmhmc_status rmhmc_softabs_eig_reserve(int D);
 /* The same eigensolve for callers that cannot allocate device memory (code
@@ -172,10 +191,11 @@ rmhmc_status rmhmc_softabs_eig_reserve(int D);
  * share that array and are serialised by the library; it keeps the last
  * call's contents, and every call initialises what it reads.  Arguments,
  * outputs, errors and synchronisation as rmhmc_softabs_eig. */
-rmhmc_status rmhmc_softabs_eig_noalloc(int D, const double* H, int ldh, double alpha, double zeta,
-                                       int max_sweeps, const double* Q_warm, double* Q,
-                                       double* lam, double* g, double* gp, double* logdetG,
-                                       int* sweeps, hipStream_t stream);
+rmhmc_status rmhmc_softabs_eig_noalloc(int D, const double* H, int ldh, double alpha,
+                                       int softabs, double zeta, int max_sweeps,
+                                       const double* Q_warm, double* Q, double* lam, double* g,
+                                       double* gp, double* logdetG, int* sweeps,
+                                       hipStream_t stream);
 
 /* Hamiltonian and its gradients at (q, p) for a given eigen-state (Q, lam)
  * of H(q) (Sec. 2.2, Eq. Hamiltonian and Eq. d_Hamiltonian, with the metric
@@ -184,16 +204,19 @@ rmhmc_status rmhmc_softabs_eig_noalloc(int D, const double* H, int ldh, double a
  * where the traces use the cached W1, W2 of Eq. (Betancourt_formula) and the
  * structure-ordered contraction of Sec. 2.3.
  *   q, p [device] D; Q [device] D x D (ld D); lam [device] D;
+ *   alpha, softabs: the softabs map (rmhmc_softabs);
  *   dHdq, dHdp [device] D; ham [device] 1. */
 rmhmc_status rmhmc_metric_grad(rmhmc_model* m, const double* q, const double* p,
-                               const double* Q, const double* lam, double alpha,
+                               const double* Q, const double* lam, double alpha, int softabs,
                                double* dHdq, double* dHdp, double* ham, hipStream_t stream);
 
 /* Device-resident integrator state (q, p, eigen-state and per-point caches).
- * q0, p0 [device] D.  The first eigendecomposition is static; later ones
- * are warm-started (Sec. 2.4).  Synchronises `stream`. */
+ * q0, p0 [device] D; alpha, softabs: the softabs map.  The first
+ * eigendecomposition is static; later ones are warm-started (Sec. 2.4).
+ * Synchronises `stream`. */
 rmhmc_status rmhmc_state_create(rmhmc_model* m, const double* q0, const double* p0,
-                                double alpha, hipStream_t stream, rmhmc_state** out);
+                                double alpha, int softabs, hipStream_t stream,
+                                rmhmc_state** out);
 rmhmc_status rmhmc_state_get(const rmhmc_state* s, double* q, double* p, double* ham,
                              hipStream_t stream);   /* [device] outs, ham nullable */
 rmhmc_status rmhmc_state_set_momentum(rmhmc_state* s, const double* p, hipStream_t stream);

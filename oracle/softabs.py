@@ -1,5 +1,6 @@
-"""Soft-absolute metric: g(lambda) = lambda coth(alpha lambda), its derivative,
-the divided-difference matrix T and the cached products W1, W2.  FP64.
+"""Soft-absolute metric: g(lambda) = lambda coth(alpha lambda) or
+g(lambda) = sqrt(kappa^2 + lambda^2), its derivative, the divided-difference
+matrix T and the cached products W1, W2.  FP64.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -16,6 +17,11 @@ Paper anchors
     |x| >= 20         : h = |x|, h' = sign x (coth 20 - 1 < 2^-53)
     |x| <  0.5        : Taylor series of x coth x (radius pi), 12 terms
     otherwise         : h = x / tanh x, h' = (sinh(2x)/2 - x) / sinh(x)^2.
+* The form the paper's own runs use (Sec. 2.5): g = sqrt(kappa^2 + lambda^2),
+  g' = lambda / g, and the divided difference written without cancellation,
+  (g_j - g_l) / (lambda_j - lambda_l) = (lambda_j + lambda_l) / (g_j + g_l)
+  (multiply by g_j + g_l and use g^2 = kappa^2 + lambda^2).  It is selected
+  by passing SqrtMap(kappa) wherever `alpha` is taken.
 """
 from __future__ import annotations
 
@@ -106,13 +112,40 @@ def h3(x):
     return out
 
 
+class SqrtMap:
+    """g(lambda) = sqrt(kappa^2 + lambda^2) (Sec. 2.5, kappa = 1 there)."""
+
+    def __init__(self, kappa=1.0):
+        self.kappa = float(kappa)
+
+    def g_gprime(self, lam):
+        lam = np.asarray(lam, dtype=np.float64)
+        g = np.sqrt(self.kappa ** 2 + lam * lam)
+        return g, lam / g
+
+    def divided_differences(self, lam):
+        lam = np.asarray(lam, dtype=np.float64)
+        g, gp = self.g_gprime(lam)
+        T = (lam[:, None] + lam[None, :]) / (g[:, None] + g[None, :])
+        np.fill_diagonal(T, gp)
+        return T
+
+
 def g_gprime(lam, alpha):
-    """g(lambda) = lambda coth(alpha lambda) and g'(lambda)."""
+    """g(lambda) = lambda coth(alpha lambda) and g'(lambda) (or the SqrtMap's)."""
+    if isinstance(alpha, SqrtMap):
+        return alpha.g_gprime(lam)
     x = alpha * np.asarray(lam, dtype=np.float64)
     return h(x) / alpha, h1(x)
 
 
 def divided_differences(lam, alpha):
+    if isinstance(alpha, SqrtMap):
+        return alpha.divided_differences(lam)
+    return _coth_divided_differences(lam, alpha)
+
+
+def _coth_divided_differences(lam, alpha):
     """T_jl = (g_j - g_l)/(lam_j - lam_l), T_jj = g'(lam_j)  (Eq. d3_transform).
 
     Near-equal pairs (|alpha (lam_j - lam_l)| < 1e-3) use the midpoint

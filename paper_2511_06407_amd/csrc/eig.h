@@ -67,10 +67,11 @@ JacobiResult jacobi_eig(int D, EigWork& w, double zeta, double gfloor, int max_s
 void orthonormalise(int D, int Dp, double* Psi, double* T1, double* T2, hipStream_t st);
 
 void rayleigh_refine(int D, const double* H, long ldh, EigWork& w, double* Z, hipStream_t st);
-void softabs_finalize(int D, const double* M, long ldm, double alpha, double* lam, double* g,
-                      double* gp, double* logdetG, hipStream_t st);
+// lam = diag(M); g, g' and log|G| of the softabs map `kind` (rmhmc_softabs).
+void softabs_finalize(int D, const double* M, long ldm, double alpha, int kind, double* lam,
+                      double* g, double* gp, double* logdetG, hipStream_t st);
 // M1(j,k) = T_jk b_j b_k with T the divided differences of g.
-void t_bb(int D, const double* lam, const double* b, double alpha, double* M1, long ld,
+void t_bb(int D, const double* lam, const double* b, double alpha, int kind, double* M1, long ld,
           hipStream_t st);
 // B(:, j) = A(:, j) * num[j] / den[j]  (either may be null)
 void scale_cols(int m, int n, const double* A, long lda, const double* num, const double* den,

@@ -790,7 +790,18 @@ __device__ double h3(double x) {
 
 }  // namespace
 
-__device__ double divided_difference(double lj, double ll, double alpha) {
+// The softabs map (rmhmc_softabs): g = lam coth(alpha lam) (COTH) or
+// g = sqrt(kappa^2 + lam^2) with kappa = 1 / alpha (SQRT, the form of the
+// paper's own runs, Sec. 2.5).  For SQRT, g' = lam / g and the divided
+// difference (g_j - g_l) / (lam_j - lam_l) equals (lam_j + lam_l) / (g_j + g_l),
+// which has no cancellation.
+__device__ __forceinline__ double sqrt_g(double l, double alpha) {
+  const double kappa = 1.0 / alpha;
+  return sqrt(fma(l, l, kappa * kappa));
+}
+
+__device__ double divided_difference(double lj, double ll, double alpha, int kind) {
+  if (kind == RMHMC_SOFTABS_SQRT) return (lj + ll) / (sqrt_g(lj, alpha) + sqrt_g(ll, alpha));
   const double xj = alpha * lj, xl = alpha * ll;
   if (fabs(xj) >= 20.0 && fabs(xl) >= 20.0) {
     if ((xj > 0) == (xl > 0)) return xj > 0 ? 1.0 : -1.0;
@@ -807,7 +818,7 @@ __device__ double divided_difference(double lj, double ll, double alpha) {
 namespace {
 
 __global__ __launch_bounds__(256) void softabs_finalize_kernel(int D, const double* __restrict__ M,
-                                                               long ldm, double alpha,
+                                                               long ldm, double alpha, int kind,
                                                                double* __restrict__ lam,
                                                                double* __restrict__ g,
                                                                double* __restrict__ gp,
@@ -816,11 +827,18 @@ __global__ __launch_bounds__(256) void softabs_finalize_kernel(int D, const doub
   double s = 0.0;
   for (int i = threadIdx.x; i < D; i += 256) {
     const double l = M[i + (long)i * ldm];
-    const double x = alpha * l;
-    const double gi = h0(x) / alpha;
+    double gi, gpi;
+    if (kind == RMHMC_SOFTABS_SQRT) {
+      gi = sqrt_g(l, alpha);
+      gpi = l / gi;
+    } else {
+      const double x = alpha * l;
+      gi = h0(x) / alpha;
+      gpi = h1(x);
+    }
     lam[i] = l;
     g[i] = gi;
-    gp[i] = h1(x);
+    gp[i] = gpi;
     s += log(gi);
   }
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
@@ -831,11 +849,15 @@ __global__ __launch_bounds__(256) void softabs_finalize_kernel(int D, const doub
 
 // M1(j,k) = T_jk b_j b_k  (T from Eq. d3_transform), D x D with ld.
 __global__ void t_bb_kernel(int D, const double* __restrict__ lam, const double* __restrict__ b,
-                            double alpha, double* __restrict__ M1, long ld) {
+                            double alpha, int kind, double* __restrict__ M1, long ld) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)D * D) return;
   const int j = (int)(e % D), k = (int)(e / D);
-  const double t = (j == k) ? h1(alpha * lam[j]) : divided_difference(lam[j], lam[k], alpha);
+  double t;
+  if (j == k)
+    t = kind == RMHMC_SOFTABS_SQRT ? lam[j] / sqrt_g(lam[j], alpha) : h1(alpha * lam[j]);
+  else
+    t = divided_difference(lam[j], lam[k], alpha, kind);
   M1[j + (long)k * ld] = t * b[j] * b[k];
 }
 
@@ -1082,17 +1104,18 @@ void rayleigh_refine(int D, const double* H, long ldh, EigWork& w, double* Z, hi
   RM_CHECK_LAUNCH();
 }
 
-void softabs_finalize(int D, const double* M, long ldm, double alpha, double* lam, double* g,
-                      double* gp, double* logdetG, hipStream_t st) {
-  hipLaunchKernelGGL(softabs_finalize_kernel, dim3(1), dim3(256), 0, st, D, M, ldm, alpha, lam, g,
-                     gp, logdetG);
+void softabs_finalize(int D, const double* M, long ldm, double alpha, int kind, double* lam,
+                      double* g, double* gp, double* logdetG, hipStream_t st) {
+  hipLaunchKernelGGL(softabs_finalize_kernel, dim3(1), dim3(256), 0, st, D, M, ldm, alpha, kind,
+                     lam, g, gp, logdetG);
   RM_CHECK_LAUNCH();
 }
 
-void t_bb(int D, const double* lam, const double* b, double alpha, double* M1, long ld,
+void t_bb(int D, const double* lam, const double* b, double alpha, int kind, double* M1, long ld,
           hipStream_t st) {
   const long n = (long)D * D;
-  hipLaunchKernelGGL(t_bb_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, D, lam, b, alpha, M1, ld);
+  hipLaunchKernelGGL(t_bb_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, D, lam, b, alpha, kind, M1,
+                     ld);
   RM_CHECK_LAUNCH();
 }
 

@@ -435,6 +435,7 @@ struct EigCfg {
   int* fail = nullptr;
   double* dstats = nullptr;
   int* max_seen = nullptr;   // [host] largest sweep count of a warm start (host-checked mode)
+  int softabs = RMHMC_SOFTABS_COTH;   // the map g of the metric (rmhmc_softabs)
 };
 // Largest number of fixed-point iterations whose eigen-solves get their own
 // sweep budget in a captured move.
@@ -731,7 +732,7 @@ JacobiResult compute_eig(Model& m, Point& pt, const Point* warm, double alpha, c
   if (!warm) orthonormalise(D, Dp, m.eig.Psi, m.Wt1, m.Wt2, st);
   rayleigh_refine(D, pt.H, Dp, m.eig, m.Wt2, st);
   copy(pt.Psi, m.eig.Psi, (long)Dp * Dp, st);
-  softabs_finalize(D, m.eig.M, Dp, alpha, pt.lam, pt.g, pt.gp, pt.scal + 2, st);
+  softabs_finalize(D, m.eig.M, Dp, alpha, ec.softabs, pt.lam, pt.g, pt.gp, pt.scal + 2, st);
   pt.have_eig = true;
   pt.have_vW2 = false;
   return r;
@@ -885,13 +886,13 @@ void metric_vectors(Model& m, Point& pt, const double* p, double* dHdp, double* 
 }
 
 // dH/dq = grad U + v(W2)/2 - v(W1)/2 at pt for momentum p.  Also dH/dp, ham.
-void grad_q(Model& m, Point& pt, const double* p, double alpha, double* dHdq, double* dHdp,
-            double* ham, hipStream_t st) {
+void grad_q(Model& m, Point& pt, const double* p, double alpha, int kind, double* dHdq,
+            double* dHdp, double* ham, hipStream_t st) {
   const int D = m.D, Dp = m.Dp;
   compute_vW2(m, pt, st);
   metric_vectors(m, pt, p, dHdp, ham, st);
   fill(m.W, (long)Dp * Dp, 0.0, st);
-  t_bb(D, pt.lam, m.vb, alpha, m.Wt1, Dp, st);             // T o b b'
+  t_bb(D, pt.lam, m.vb, alpha, kind, m.Wt1, Dp, st);       // T o b b'
   Gemm<double> g;                                            // Wt2 = (T o bb') Psi'
   g.m = D; g.n = D; g.k = D;
   g.A = m.Wt1; g.lda = Dp;
@@ -1231,7 +1232,7 @@ Point* leapfrog(State& s, Point* cur, Point* keep, double eps, int K, hipStream_
   // implicit momentum half step at fixed q: ph <- p - eps/2 dH/dq(q, ph)
   copy(s.ph, s.p, D, st);
   for (int k = 0; k < K; ++k) {
-    grad_q(m, *cur, s.ph, s.alpha, s.gq, nullptr, nullptr, st);
+    grad_q(m, *cur, s.ph, s.alpha, s.ec.softabs, s.gq, nullptr, nullptr, st);
     fp_update(D, s.p, -0.5 * eps, s.gq, 0.0, s.gq, s.ph, k == K - 1 ? s.dstats + ST_RESP : nullptr, st);
   }
   // implicit position step: qk <- q + eps/2 (G(q)^-1 ph + G(qk)^-1 ph)
@@ -1263,7 +1264,7 @@ Point* leapfrog(State& s, Point* cur, Point* keep, double eps, int K, hipStream_
   }
   eval(*trial);
   // explicit momentum half step
-  grad_q(m, *trial, s.ph, s.alpha, s.gq, nullptr, nullptr, st);
+  grad_q(m, *trial, s.ph, s.alpha, s.ec.softabs, s.gq, nullptr, nullptr, st);
   lincomb3(D, s.ph, -0.5 * eps, s.gq, 0.0, s.gq, s.p, st);
   s.leapfrogs += 1;
   if (ok) *ok = good;
@@ -1287,6 +1288,8 @@ void check_chain_cfg(const Model& m, const rmhmc_chain_cfg* cfg) {
   RM_REQUIRE(std::isfinite(cfg->eps) && cfg->eps > 0.0, "eps must be positive");
   RM_REQUIRE(std::isfinite(cfg->alpha) && cfg->alpha > 0.0, "alpha must be positive");
   RM_REQUIRE(cfg->precision == m.prec, "chain precision differs from the model's");
+  RM_REQUIRE(cfg->softabs == RMHMC_SOFTABS_COTH || cfg->softabs == RMHMC_SOFTABS_SQRT,
+             "unknown softabs map");
 }
 
 // Chain set-up: the configuration into the state, statistics and move
@@ -1296,6 +1299,7 @@ void chain_begin(Model& m, State& S, const rmhmc_chain_cfg* cfg, const double* q
                  hipStream_t st) {
   const int D = m.D;
   S.alpha = cfg->alpha;
+  S.ec.softabs = cfg->softabs;
   S.ec.zeta = cfg->zeta > 0.0 ? cfg->zeta : 1e-13;
   S.ec.max_sweeps = cfg->max_sweeps > 0 ? cfg->max_sweeps : 60;
   S.ec.blind = 0;
@@ -1759,8 +1763,9 @@ rmhmc_status gemm_entry(int m, int n, int k, T alpha, const T* A, int lda, int t
   });
 }
 
-void check_eig_args(int D, const double* H, int ldh, double alpha, const double* Q,
+void check_eig_args(int D, const double* H, int ldh, double alpha, int softabs, const double* Q,
                     const double* lam, const double* g, const double* gp, const double* logdetG) {
+  RM_REQUIRE(softabs == RMHMC_SOFTABS_COTH || softabs == RMHMC_SOFTABS_SQRT, "unknown softabs map");
   RM_REQUIRE(D >= 1 && H && Q && lam && g && gp && logdetG, "bad argument");
   RM_REQUIRE(ldh >= D, "ldh < D");
   RM_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "alpha must be positive");
@@ -1768,7 +1773,8 @@ void check_eig_args(int D, const double* H, int ldh, double alpha, const double*
 }
 
 // The stand-alone eigensolve on workspace w (sized for D); synchronises `st`.
-void softabs_eig_impl(EigWork& w, int D, const double* H, int ldh, double alpha, double zeta,
+void softabs_eig_impl(EigWork& w, int D, const double* H, int ldh, double alpha, int softabs,
+                      double zeta,
                       int max_sweeps, const double* Q_warm, double* Q, double* lam, double* g,
                       double* gp, double* logdetG, int* sweeps, hipStream_t st) {
   if (zeta <= 0.0) zeta = 1e-13;
@@ -1805,7 +1811,7 @@ void softabs_eig_impl(EigWork& w, int D, const double* H, int ldh, double alpha,
   if (!Q_warm) orthonormalise(D, Dp, w.Psi, w.M2, w.M, st);
   rayleigh_refine(D, H, ldh, w, w.M2, st);
   copy_matrix(D, D, w.Psi, Dp, Q, D, st);
-  softabs_finalize(D, w.M, Dp, alpha, lam, g, gp, logdetG, st);
+  softabs_finalize(D, w.M, Dp, alpha, softabs, lam, g, gp, logdetG, st);
   RM_HIP(hipStreamSynchronize(st));
   if (sweeps) *sweeps = r.sweeps;
   if (!r.converged) throw Error(RMHMC_E_EIG_NOCONV, "softabs_eig: Jacobi did not converge");
@@ -1877,6 +1883,31 @@ rmhmc_status rmhmc_model_bytes(const rmhmc_model* m, long long* bytes) {
   });
 }
 
+rmhmc_status rmhmc_model_set_beta(rmhmc_model* mh, double beta) {
+  return guard([&] {
+    RM_REQUIRE(mh != nullptr, "model is NULL");
+    RM_REQUIRE(beta >= 0.0 && std::isfinite(beta), "beta must be finite and >= 0");
+    Model& m = mh->impl;
+    std::lock_guard<std::mutex> lk(m.busy);
+    RM_REQUIRE(!m.in_batch, "the model is admitted to a batch");
+    m.beta = beta;
+  });
+}
+
+rmhmc_status rmhmc_log_likelihood(rmhmc_model* mh, const double* q, double* ll, hipStream_t st) {
+  return guard([&] {
+    RM_REQUIRE(mh && q && ll, "NULL argument");
+    Model& m = mh->impl;
+    std::lock_guard<std::mutex> lk(m.busy);
+    RM_REQUIRE(!m.in_batch, "the model is admitted to a batch");
+    Point& pt = *m.api_pt;
+    lik_derivs(m.N, m.lik, m.noise_var, q, m.y, pt.lik, st);   // l_i = -ln P(X_i | f_i)
+    vsum(m.N, pt.lik, ll, st);
+    axpby(1, 0.0, ll, -1.0, ll, st);
+    RM_HIP(hipStreamSynchronize(st));
+  });
+}
+
 rmhmc_status rmhmc_model_destroy(rmhmc_model* m) {
   return guard([&] {
     if (m) {
@@ -1915,26 +1946,27 @@ rmhmc_status rmhmc_softabs_eig_reserve(int D) {
   });
 }
 
-rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, double zeta,
-                               int max_sweeps, const double* Q_warm, double* Q, double* lam,
-                               double* g, double* gp, double* logdetG, int* sweeps,
+rmhmc_status rmhmc_softabs_eig(int D, const double* H, int ldh, double alpha, int softabs,
+                               double zeta, int max_sweeps, const double* Q_warm, double* Q,
+                               double* lam, double* g, double* gp, double* logdetG, int* sweeps,
                                hipStream_t st) {
   return guard([&] {
-    check_eig_args(D, H, ldh, alpha, Q, lam, g, gp, logdetG);
+    check_eig_args(D, H, ldh, alpha, softabs, Q, lam, g, gp, logdetG);
     EigWorkspace& ws = eig_workspace();
     std::lock_guard<std::mutex> lk(ws.mu);
     eig_workspace_grow(ws, D);
-    softabs_eig_impl(ws.w, D, H, ldh, alpha, zeta, max_sweeps, Q_warm, Q, lam, g, gp, logdetG,
-                     sweeps, st);
+    softabs_eig_impl(ws.w, D, H, ldh, alpha, softabs, zeta, max_sweeps, Q_warm, Q, lam, g, gp,
+                     logdetG, sweeps, st);
   });
 }
 
-rmhmc_status rmhmc_softabs_eig_noalloc(int D, const double* H, int ldh, double alpha, double zeta,
-                                       int max_sweeps, const double* Q_warm, double* Q,
-                                       double* lam, double* g, double* gp, double* logdetG,
-                                       int* sweeps, hipStream_t st) {
+rmhmc_status rmhmc_softabs_eig_noalloc(int D, const double* H, int ldh, double alpha,
+                                       int softabs, double zeta, int max_sweeps,
+                                       const double* Q_warm, double* Q, double* lam, double* g,
+                                       double* gp, double* logdetG, int* sweeps,
+                                       hipStream_t st) {
   return guard([&] {
-    check_eig_args(D, H, ldh, alpha, Q, lam, g, gp, logdetG);
+    check_eig_args(D, H, ldh, alpha, softabs, Q, lam, g, gp, logdetG);
     RM_REQUIRE(D <= NOALLOC_MAX_D, "softabs_eig_noalloc: D exceeds the scratch maximum (1088)");
     int dev = 0;
     RM_HIP(hipGetDevice(&dev));
@@ -1942,14 +1974,14 @@ rmhmc_status rmhmc_softabs_eig_noalloc(int D, const double* H, int ldh, double a
     std::lock_guard<std::mutex> lk(g_noalloc_call_mu[dev]);
     double ctrl_host[EIG_CTRL_DOUBLES];
     EigWork w = noalloc_work(base, eig_padded_dim(D), ctrl_host);
-    softabs_eig_impl(w, D, H, ldh, alpha, zeta, max_sweeps, Q_warm, Q, lam, g, gp, logdetG,
-                     sweeps, st);
+    softabs_eig_impl(w, D, H, ldh, alpha, softabs, zeta, max_sweeps, Q_warm, Q, lam, g, gp,
+                     logdetG, sweeps, st);
   });
 }
 
 rmhmc_status rmhmc_metric_grad(rmhmc_model* mh, const double* q, const double* p, const double* Q,
-                               const double* lam, double alpha, double* dHdq, double* dHdp,
-                               double* ham, hipStream_t st) {
+                               const double* lam, double alpha, int softabs, double* dHdq,
+                               double* dHdp, double* ham, hipStream_t st) {
   return guard([&] {
     RM_REQUIRE(mh && q && p && Q && lam && dHdq && dHdp && ham, "NULL argument");
     RM_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "alpha must be positive");
@@ -1964,15 +1996,17 @@ rmhmc_status rmhmc_metric_grad(rmhmc_model* mh, const double* q, const double* p
     copy(pt.Psi, m.eig.Psi, (long)m.Dp * m.Dp, st);
     fill(m.eig.M, (long)m.Dp * m.Dp, 0.0, st);
     copy_matrix(1, m.D, lam, 1, m.eig.M, m.Dp + 1, st);   // diag(lam)
-    softabs_finalize(m.D, m.eig.M, m.Dp, alpha, pt.lam, pt.g, pt.gp, pt.scal + 2, st);
+    RM_REQUIRE(softabs == RMHMC_SOFTABS_COTH || softabs == RMHMC_SOFTABS_SQRT,
+               "unknown softabs map");
+    softabs_finalize(m.D, m.eig.M, m.Dp, alpha, softabs, pt.lam, pt.g, pt.gp, pt.scal + 2, st);
     pt.have_eig = true;
-    grad_q(m, pt, p, alpha, dHdq, dHdp, ham, st);
+    grad_q(m, pt, p, alpha, softabs, dHdq, dHdp, ham, st);
     RM_HIP(hipStreamSynchronize(st));
   });
 }
 
 rmhmc_status rmhmc_state_create(rmhmc_model* mh, const double* q0, const double* p0, double alpha,
-                                hipStream_t st, rmhmc_state** out) {
+                                int softabs, hipStream_t st, rmhmc_state** out) {
   return guard([&] {
     RM_REQUIRE(mh && q0 && p0 && out, "NULL argument");
     RM_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "alpha must be positive");
@@ -1980,8 +2014,11 @@ rmhmc_status rmhmc_state_create(rmhmc_model* mh, const double* q0, const double*
     std::lock_guard<std::mutex> lk(m.busy);
     RM_REQUIRE(!m.in_batch, "the model is admitted to a batch");
     auto s = std::make_unique<rmhmc_state>();
+    RM_REQUIRE(softabs == RMHMC_SOFTABS_COTH || softabs == RMHMC_SOFTABS_SQRT,
+               "unknown softabs map");
     s->impl = make_state(m, alpha);
     State& S = *s->impl;
+    S.ec.softabs = softabs;
     copy(S.pts[0]->q, q0, m.D, st);
     copy(S.p, p0, m.D, st);
     check_flag_nonfinite(m, S.pts[0]->q, m.D, st, "q0");

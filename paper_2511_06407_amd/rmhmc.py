@@ -24,6 +24,7 @@ _lib = C.CDLL(LIB_PATH)
 MAX_TERM_COLS = 8
 OK, E_ARG, E_NOT_PD, E_EIG_NOCONV, E_NONFINITE, E_NOMEM, E_HIP = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
+SOFTABS_COTH, SOFTABS_SQRT = 0, 1
 
 EXPORTED = ["rmhmc_model_create", "rmhmc_model_dims", "rmhmc_model_destroy", "rmhmc_hessian",
             "rmhmc_softabs_eig", "rmhmc_metric_grad", "rmhmc_state_create", "rmhmc_state_get",
@@ -34,7 +35,8 @@ EXPORTED = ["rmhmc_model_create", "rmhmc_model_dims", "rmhmc_model_destroy", "rm
             "rmhmc_pool_poll", "rmhmc_pool_destroy", "rmhmc_state_stats", "rmhmc_model_bytes",
             "rmhmc_softabs_eig_reserve", "rmhmc_chain_randoms", "rmhmc_softabs_eig_noalloc",
             "rmhmc_batch_create", "rmhmc_batch_admit", "rmhmc_batch_step", "rmhmc_batch_sync",
-            "rmhmc_batch_retire", "rmhmc_batch_destroy"]
+            "rmhmc_batch_retire", "rmhmc_batch_destroy", "rmhmc_model_set_beta",
+            "rmhmc_log_likelihood"]
 
 TIMER_KINDS = {"gemm_f64": 0, "gemm_f32": 1, "jacobi_solve": 2, "jacobi_apply": 3, "kd_wsum": 4,
                "kd_matvec": 5, "potrf_diag": 6}
@@ -55,7 +57,8 @@ class ChainCfg(C.Structure):
     _fields_ = [("eps", C.c_double), ("alpha", C.c_double), ("zeta", C.c_double),
                 ("n_leapfrog", C.c_int), ("n_moves", C.c_int), ("n_burnin", C.c_int),
                 ("n_fixed_point", C.c_int), ("max_sweeps", C.c_int), ("reorth_every", C.c_int),
-                ("seed", C.c_ulonglong), ("stream_id", C.c_ulonglong), ("precision", C.c_int)]
+                ("seed", C.c_ulonglong), ("stream_id", C.c_ulonglong), ("precision", C.c_int),
+                ("softabs", C.c_int)]
 
 
 class ChainStats(C.Structure):
@@ -75,15 +78,18 @@ _sig = {
     "rmhmc_model_create": [C.POINTER(ModelDesc), _i, C.POINTER(_vp)],
     "rmhmc_model_dims": [_vp, C.POINTER(_i), C.POINTER(_i), C.POINTER(_i)],
     "rmhmc_model_bytes": [_vp, C.POINTER(C.c_longlong)],
+    "rmhmc_model_set_beta": [_vp, _d],
+    "rmhmc_log_likelihood": [_vp, _vp, _vp, _vp],
     "rmhmc_softabs_eig_reserve": [_i],
     "rmhmc_chain_randoms": [_i, C.c_ulonglong, C.c_ulonglong, C.c_ulonglong, _vp, _vp, _vp],
     "rmhmc_model_destroy": [_vp],
     "rmhmc_hessian": [_vp, _vp, _vp, _vp, _vp, _i, _vp],
-    "rmhmc_softabs_eig": [_i, _vp, _i, _d, _d, _i, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_i), _vp],
-    "rmhmc_softabs_eig_noalloc": [_i, _vp, _i, _d, _d, _i, _vp, _vp, _vp, _vp, _vp, _vp,
+    "rmhmc_softabs_eig": [_i, _vp, _i, _d, _i, _d, _i, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_i),
+                          _vp],
+    "rmhmc_softabs_eig_noalloc": [_i, _vp, _i, _d, _i, _d, _i, _vp, _vp, _vp, _vp, _vp, _vp,
                                   C.POINTER(_i), _vp],
-    "rmhmc_metric_grad": [_vp, _vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp],
-    "rmhmc_state_create": [_vp, _vp, _vp, _d, _vp, C.POINTER(_vp)],
+    "rmhmc_metric_grad": [_vp, _vp, _vp, _vp, _vp, _d, _i, _vp, _vp, _vp, _vp],
+    "rmhmc_state_create": [_vp, _vp, _vp, _d, _i, _vp, C.POINTER(_vp)],
     "rmhmc_state_get": [_vp, _vp, _vp, _vp, _vp],
     "rmhmc_state_set_momentum": [_vp, _vp, _vp],
     "rmhmc_state_destroy": [_vp],
@@ -219,7 +225,7 @@ class Model:
         # H is symmetric, so the row-major view equals the column-major matrix
         return U, g, H
 
-    def metric_grad(self, q, p, Q, lam, alpha, stream=None):
+    def metric_grad(self, q, p, Q, lam, alpha, stream=None, softabs=SOFTABS_COTH):
         """Q: device tensor whose column-major layout holds the eigenvectors,
         i.e. Q_t[j, i] = Q(i, j) (pass Q.T.contiguous() of a row-major matrix)."""
         torch = _torch()
@@ -227,8 +233,19 @@ class Model:
         dp = torch.empty(self.D, dtype=torch.float64, device=q.device)
         ham = torch.empty(1, dtype=torch.float64, device=q.device)
         _check(_lib.rmhmc_metric_grad(self._h, _f64(q), _f64(p), _f64(Q), _f64(lam), alpha,
-                                      _f64(dq), _f64(dp), _f64(ham), _stream(stream)))
+                                      softabs, _f64(dq), _f64(dp), _f64(ham), _stream(stream)))
         return dq, dp, ham
+
+    def set_beta(self, beta):
+        """Inverse temperature of the power posterior for later calls."""
+        _check(_lib.rmhmc_model_set_beta(self._h, float(beta)))
+
+    def log_likelihood(self, q, stream=None):
+        """ln P(X | f) at q, as a device scalar."""
+        torch = _torch()
+        ll = torch.empty(1, dtype=torch.float64, device=q.device)
+        _check(_lib.rmhmc_log_likelihood(self._h, _f64(q), _f64(ll), _stream(stream)))
+        return ll
 
     @property
     def device_bytes(self):
@@ -237,7 +254,8 @@ class Model:
         return b.value
 
     def chain(self, q0, eps, n_leapfrog, n_fixed_point, n_moves, n_burnin=0, seed=0,
-              stream_id=0, alpha=1e6, zeta=0.0, max_sweeps=0, reorth_every=0, stream=None):
+              stream_id=0, alpha=1e6, zeta=0.0, max_sweeps=0, reorth_every=0, stream=None,
+              softabs=SOFTABS_COTH):
         """Algorithm 1 on the device; returns (samples, logpost, accepted, stats)
         for the moves n_burnin .. n_moves-1."""
         torch = _torch()
@@ -246,7 +264,7 @@ class Model:
         logpost = torch.empty(max(kept, 1), dtype=torch.float64, device=q0.device)
         acc = torch.empty(max(kept, 1), dtype=torch.int32, device=q0.device)
         cfg = chain_cfg(self, eps, n_leapfrog, n_fixed_point, n_moves, n_burnin, seed, stream_id,
-                        alpha, zeta, max_sweeps, reorth_every)
+                        alpha, zeta, max_sweeps, reorth_every, softabs)
         stats = ChainStats()
         _check(_lib.rmhmc_chain(self._h, C.byref(cfg), _f64(q0), _f64(samples), _f64(logpost),
                                 _ptr(acc, torch.int32), C.byref(stats), _stream(stream)))
@@ -254,9 +272,9 @@ class Model:
 
 
 def chain_cfg(model, eps, n_leapfrog, n_fixed_point, n_moves, n_burnin=0, seed=0, stream_id=0,
-              alpha=1e6, zeta=0.0, max_sweeps=0, reorth_every=0):
+              alpha=1e6, zeta=0.0, max_sweeps=0, reorth_every=0, softabs=SOFTABS_COTH):
     return ChainCfg(eps, alpha, zeta, n_leapfrog, n_moves, n_burnin, n_fixed_point, max_sweeps,
-                    reorth_every, seed, stream_id, model.precision)
+                    reorth_every, seed, stream_id, model.precision, softabs)
 
 
 def chain_randoms(D, seed, stream_id, move, stream=None):
@@ -272,7 +290,8 @@ def softabs_eig_reserve(D):
     _check(_lib.rmhmc_softabs_eig_reserve(D))
 
 
-def softabs_eig(H, alpha, Q_warm=None, zeta=0.0, max_sweeps=0, stream=None, noalloc=False):
+def softabs_eig(H, alpha, Q_warm=None, zeta=0.0, max_sweeps=0, stream=None, noalloc=False,
+                softabs=SOFTABS_COTH):
     """H: symmetric D x D device tensor.  Returns (Q_colmajor, lam, g, gp, logdetG, sweeps);
     Q_colmajor[j] is the j-th eigenvector.  noalloc: the entry point whose
     workspace is the library's static device array (D <= 1088)."""
@@ -285,18 +304,18 @@ def softabs_eig(H, alpha, Q_warm=None, zeta=0.0, max_sweeps=0, stream=None, noal
     ld = torch.empty(1, dtype=torch.float64, device=H.device)
     sw = C.c_int()
     fn = _lib.rmhmc_softabs_eig_noalloc if noalloc else _lib.rmhmc_softabs_eig
-    _check(fn(D, _f64(H), D, alpha, zeta, max_sweeps, _f64(Q_warm), _f64(Q), _f64(lam), _f64(g),
-              _f64(gp), _f64(ld), C.byref(sw), _stream(stream)))
+    _check(fn(D, _f64(H), D, alpha, softabs, zeta, max_sweeps, _f64(Q_warm), _f64(Q), _f64(lam),
+              _f64(g), _f64(gp), _f64(ld), C.byref(sw), _stream(stream)))
     return Q, lam, g, gp, ld, sw.value
 
 
 class State:
     """Device-resident integrator state (rmhmc_state)."""
 
-    def __init__(self, model: Model, q0, p0, alpha=1e6, stream=None):
+    def __init__(self, model: Model, q0, p0, alpha=1e6, stream=None, softabs=SOFTABS_COTH):
         h = C.c_void_p()
-        _check(_lib.rmhmc_state_create(model._h, _f64(q0), _f64(p0), alpha, _stream(stream),
-                                       C.byref(h)))
+        _check(_lib.rmhmc_state_create(model._h, _f64(q0), _f64(p0), alpha, softabs,
+                                       _stream(stream), C.byref(h)))
         self._h, self.model = h, model
 
     def step(self, eps, n_fixed_point, stream=None):

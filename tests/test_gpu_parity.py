@@ -189,12 +189,16 @@ def test_softabs_eig_static(rm, case):
     check_static_eig(rm, case, H, alpha)
 
 
-def check_static_eig(rm, case, H, alpha, Q_warm=None):
+def check_static_eig(rm, case, H, alpha, Q_warm=None, sqrt_map=False):
     """Solve H with the GPU eigensolver (cold, or warm-started from the rows
     of Q_warm) and hold the result to the bars below against the reference
-    eigendecomposition; returns the sweep count."""
+    eigendecomposition; returns the sweep count.  With sqrt_map the softabs
+    map is g = sqrt(kappa^2 + lambda^2), kappa = 1/alpha."""
     D = H.shape[0]
-    Qt, lam, g, gp, ld, sweeps = rm.softabs_eig(dev(H), alpha, Q_warm=Q_warm)
+    kind = rm.SOFTABS_SQRT if sqrt_map else rm.SOFTABS_COTH
+    Qt, lam, g, gp, ld, sweeps = rm.softabs_eig(dev(H), alpha, Q_warm=Q_warm, softabs=kind)
+    if sqrt_map:
+        alpha = osoft.SqrtMap(1.0 / alpha)
     Q = host(Qt)
     lam, g, gp, ld = host(lam), host(g), host(gp), float(host(ld)[0])
     ref = osoft.softabs_eig(H, alpha)
@@ -219,7 +223,7 @@ def check_static_eig(rm, case, H, alpha, Q_warm=None):
     fl_ld = rel(ref2["logdetG"], ref["logdetG"])
     fl_gip = rel(osoft.ginv_p(ref2, p), osoft.ginv_p(ref, p))
     fl_G = rel(osoft.metric(ref2), Gr)
-    record("eig_static", case=case, sweeps=sweeps, lam=e_lam, G=e_G, logdetG=e_ld, Ginvp=e_gip,
+    record("eig_sqrt" if sqrt_map else "eig_static", case=case, sweeps=sweeps, lam=e_lam, G=e_G, logdetG=e_ld, Ginvp=e_gip,
            orth=orth, resid=resid, g=e_g, gp=e_gp, floor_logdetG=fl_ld, floor_Ginvp=fl_gip)
     assert e_g < 1e-14 and e_gp < 1e-14
     # backward error at working accuracy: orthogonality and residual ~ sqrt(D) u
@@ -464,3 +468,72 @@ def test_chain_failures_are_rejections(rm):
     assert stats.failures <= stats.fail_not_pd + stats.fail_nonfinite + stats.fail_noconv
     assert not host(acc).any()
     assert np.array_equal(host(samples), np.zeros((3, spec.D)))
+
+
+# ---------------------------------------------------------------- g = sqrt(kappa^2 + lambda^2)
+SQRT = osoft.SqrtMap(1.0)   # kappa = 1 (alpha = 1), the paper's own softabs
+
+
+@pytest.mark.parametrize("case", ["c1_hessian", "cluster_130"])
+def test_softabs_eig_sqrt_map(rm, case):
+    """The eigensolver with the sqrt map, held to the bars of the coth cases
+    (G^-1 p against the reference's own spread under a permutation)."""
+    if case == "c1_hessian":
+        spec = MODELS["c1_d34"]
+        H = omodel.hessian(spec, rand_q(spec, 5))[2]
+    else:
+        H = cluster_matrix(130, 4)
+    check_static_eig(rm, case, 0.5 * (H + H.T), 1.0, sqrt_map=True)
+
+
+@pytest.mark.parametrize("name", ["c1_d34", "mkl_d104_wellcond", "mkl_d104"])
+def test_metric_grad_and_glf_sqrt_map(rm, name):
+    spec = MODELS[name]
+    T = oham.GPTarget(spec)
+    q = rand_q(spec, 13, 0.3)
+    st = oham.State(T, q, SQRT)
+    p = omomentum(st, np.random.default_rng(14).standard_normal(spec.D))
+    M = rm.Model(spec)
+    dq, dp, ham = M.metric_grad(dev(q), dev(p), dev(st.eig["Psi"].T), dev(st.eig["lam"]), 1.0,
+                                softabs=rm.SOFTABS_SQRT)
+    ref = (oham.grad_q(st, p), oham.grad_p(st, p), oham.hamiltonian(st, p))
+    s2, q2, full = permuted(spec, q)
+    st2 = oham.State(oham.GPTarget(s2), q2, SQRT)
+    fl = max(rel(unpermute_vec(oham.grad_q(st2, p[full]), full), ref[0]),
+             rel(unpermute_vec(oham.grad_p(st2, p[full]), full), ref[1]),
+             rel(oham.hamiltonian(st2, p[full]), ref[2]))
+    e_dq, e_dp, e_h = rel(host(dq), ref[0]), rel(host(dp), ref[1]), rel(host(ham), ref[2])
+    tol = max(BAR, 10 * fl)
+    record("metric_grad_sqrt", model=name, dHdq=e_dq, dHdp=e_dp, ham=e_h, floor=fl, bar=tol)
+    assert e_dq < tol and e_dp < tol and e_h < tol
+    # one generalized leapfrog with the same map
+    eps = 0.01
+    S = rm.State(M, dev(q), dev(p), 1.0, softabs=rm.SOFTABS_SQRT)
+    S.step(eps, 6)
+    qg, pg, _ = S.get()
+    rst, rp = oglf(st, p, eps, 6)
+    st2n, p2n = oglf(st2, p[full], eps, 6)
+    fl = max(rel(unpermute_vec(st2n.q, full), rst.q), rel(unpermute_vec(p2n, full), rp))
+    tol = max(BAR, 10 * fl)
+    e_q, e_p = rel(host(qg), rst.q), rel(host(pg), rp)
+    record("glf_sqrt", model=name, q=e_q, p=e_p, floor=fl, bar=tol)
+    assert e_q < tol and e_p < tol
+
+
+def test_chain_sqrt_map_c1(rm):
+    """The seeded device chain with the paper's softabs map against the
+    reference chain: identical decisions, samples within the floor bar."""
+    spec, cfg = wl.workload("gp_logistic_d34")
+    T = oham.GPTarget(spec)
+    n_moves, C_, K, eps = 4, 3, 6, 0.02
+    q0 = np.zeros(spec.D)
+    s, l, a, stats = rm.Model(spec).chain(dev(q0), eps, C_, K, n_moves, seed=21, stream_id=1,
+                                          alpha=1.0, softabs=rm.SOFTABS_SQRT)
+    ref = run_seeded_chain(T, q0, eps, C_, K, SQRT, n_moves, 0, 21, 1)
+    fl = chain_floor(spec, eps, C_, K, SQRT, n_moves, 21, 1, ref)
+    bar = max(BAR, 10 * fl)
+    gs, ga = host(s), host(a)
+    record("chain_sqrt", accepted=int(ga.sum()), ref_accepted=int(ref[2].sum()),
+           samples=rel(gs, ref[0]), floor=fl, bar=bar, failures=stats.failures)
+    assert np.array_equal(ga, ref[2]) and ref[2].sum() >= 2
+    assert rel(gs, ref[0]) < bar

@@ -91,3 +91,75 @@ def test_w_matrices_are_the_two_traces(alpha):
         fd = (4 * d2 - d1) / 3
         got = want_sign * np.sum(W * E)
         assert abs(got - fd) < 1e-6 * max(1.0, abs(fd))
+
+
+# ---------------------------------------------------------------- g = sqrt(kappa^2 + lambda^2)
+def test_sqrt_map_values_and_divided_differences_mpmath():
+    """g, g' and the cancellation-free divided difference (lambda_j + lambda_l)
+    / (g_j + g_l) against 50-digit evaluation of (g_j - g_l) / (lambda_j -
+    lambda_l), including near-equal pairs where the direct quotient cancels."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    sq = softabs.SqrtMap(1.0)
+    lam = np.array([-30.0, -1.0, -1e-3, 0.0, 2e-9, 0.7, 0.7 + 1e-12, 5.0, 1e4])
+    g, gp = sq.g_gprime(lam)
+    T = sq.divided_differences(lam)
+    for i, a in enumerate(lam):
+        ga = mp.sqrt(1 + mp.mpf(a) ** 2)
+        assert abs(g[i] - float(ga)) <= 1e-15 * float(ga)
+        assert abs(gp[i] - float(mp.mpf(a) / ga)) <= 1e-15
+        for j, b in enumerate(lam):
+            if i == j:
+                want = mp.mpf(a) / ga
+            else:
+                gb = mp.sqrt(1 + mp.mpf(b) ** 2)
+                want = (ga - gb) / (mp.mpf(a) - mp.mpf(b))
+            assert abs(T[i, j] - float(want)) <= 4e-16 * max(1.0, abs(float(want))), (a, b)
+
+
+def test_sqrt_map_diagonal_closed_form_and_daleckii_krein():
+    """On a diagonal H the metric is diag(sqrt(1 + H_ii^2)); on a full H the
+    derivative of G = g(H) along a symmetric E is Psi (T o Psi'E Psi) Psi'
+    (central differences of the matrix function)."""
+    sq = softabs.SqrtMap(1.0)
+    d = np.array([-2.0, 0.0, 0.3, 4.0])
+    eig = softabs.softabs_eig(np.diag(d), sq)
+    assert np.allclose(softabs.metric(eig), np.diag(np.sqrt(1 + d * d)), rtol=1e-14, atol=1e-15)
+    assert np.isclose(eig["logdetG"], np.sum(np.log(np.sqrt(1 + d * d))), rtol=1e-14)
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((6, 6))
+    H = A + A.T
+    E = rng.standard_normal((6, 6))
+    E = E + E.T
+    e0 = softabs.softabs_eig(H, sq)
+    T = sq.divided_differences(e0["lam"])
+    Psi = e0["Psi"]
+    dG = Psi @ (T * (Psi.T @ E @ Psi)) @ Psi.T
+    h = 1e-5
+    fd = (softabs.metric(softabs.softabs_eig(H + h * E, sq))
+          - softabs.metric(softabs.softabs_eig(H - h * E, sq))) / (2 * h)
+    assert np.linalg.norm(dG - fd) / np.linalg.norm(fd) < 1e-8
+
+
+def test_sqrt_map_hamiltonian_gradient_finite_differences():
+    """dH/dq with the sqrt softabs against Richardson central differences of
+    the Hamiltonian (Eq. d_Hamiltonian with the derived signs)."""
+    import dataclasses
+    from paper_2511_06407_amd import workloads as wl
+    from oracle import hamiltonian as ham
+    spec, _, _ = wl.gp_logistic_2d(6, 3)
+    T = ham.GPTarget(dataclasses.replace(spec, jitter=1e-2))
+    sq = softabs.SqrtMap(1.0)
+    rng = np.random.default_rng(2)
+    q = 0.4 * rng.standard_normal(T.D)
+    p = rng.standard_normal(T.D)
+    st = ham.State(T, q, sq)
+    got = ham.grad_q(st, p)
+    E = np.eye(T.D)
+
+    def cd(hh):
+        return np.array([(ham.hamiltonian(ham.State(T, q + hh * E[i], sq), p)
+                          - ham.hamiltonian(ham.State(T, q - hh * E[i], sq), p)) / (2 * hh)
+                         for i in range(T.D)])
+    fd = (4 * cd(5e-4) - cd(1e-3)) / 3
+    assert np.linalg.norm(got - fd) / np.linalg.norm(fd) < 1e-8
