@@ -66,9 +66,11 @@ def parse():
     ap.add_argument("--workers", type=int, default=8, help="streams (graph) or workers (pool)")
     ap.add_argument("--engine", choices=["graph", "pool"], default="pool",
                     help="tempered mode: graph-captured batch or eager worker pool")
-    ap.add_argument("--rate", type=float, default=20.0, help="requests/s (serve mode)")
-    ap.add_argument("--duration", type=float, default=3.0, help="arrival window in s (serve)")
-    ap.add_argument("--max-moves", type=int, default=4, help="moves per request (serve)")
+    ap.add_argument("--rate", type=float, default=2.0, help="requests/s (serving)")
+    ap.add_argument("--duration", type=float, default=10.0,
+                    help="arrival window in s (serving; 0 leaves the serving block out)")
+    ap.add_argument("--moves-scale", type=float, default=0.01,
+                    help="fraction of the serving mix's 200..2000 moves per request")
     ap.add_argument("--hbm-gb", type=float, default=200.0, help="admission budget (serve)")
     return ap.parse_args()
 
@@ -92,22 +94,30 @@ def run_tempered_mode(args):
             "failures": sum(c["failures"] for c in out["chains"])}
 
 
+def serving_block(rate, window_s, moves_scale, workers, hbm_gb, seed):
+    """Requests of the serving mix (D log-uniform on [34, 1038], GP-logistic
+    or multiple-kernel) arriving as a Poisson stream, with the move counts
+    scaled by moves_scale; latencies and the backlog as measured."""
+    from paper_2511_06407_amd.serve_bench import run_rate
+    lo = max(1, int(round(200 * moves_scale)))
+    hi = max(lo, int(round(2000 * moves_scale)))
+    out = run_rate(rate, window_s, (lo, hi), workers, 32, hbm_gb, seed)
+    out["moves_scale"] = moves_scale
+    out["note"] = ("requests of the serving mix with 1/{:g} of its move counts; a sustainable "
+                   "rate r here is r x {:g} requests/s at full length".format(1 / moves_scale,
+                                                                              moves_scale))
+    return out
+
+
 def run_serve_mode(args):
-    from paper_2511_06407_amd import serving as sv
-    reqs = sv.make_requests(args.rate, args.duration, moves=(1, args.max_moves), seed=args.seed)
-    ex = sv.PoolExecutor(n_workers=args.workers, n_leapfrog=10)
-    sch = sv.Scheduler(ex, args.hbm_gb * 1e9, args.workers)
-    t0 = time.perf_counter()
-    sch.run(reqs)
-    wall = time.perf_counter() - t0
-    ex.close()
-    summ = sv.summarize(reqs, wall)
+    summ = serving_block(args.rate, args.duration, args.moves_scale, args.workers, args.hbm_gb,
+                         args.seed)
     return {"metric": "serving: p50/p99 request latency", "value": summ["p99_latency_s"],
             "unit": "s (p99 latency)", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
-            "data": "synthetic", **summ, "max_running": sch.max_running,
+            "data": "synthetic", **summ,
             "config": {"workload": "Poisson arrivals, D log-uniform in [34,1038], GP-logistic or "
                                    "multiple-kernel", "rate_per_s": args.rate,
-                       "duration_s": args.duration, "moves": [1, args.max_moves],
+                       "duration_s": args.duration, "moves_scale": args.moves_scale,
                        "workers": args.workers, "hbm_budget_gb": args.hbm_gb}}
 
 
@@ -359,6 +369,13 @@ def main():
                   "note": "in the timed chain (its first point is a static solve)"}
     if ess_block is not None:
         out["ess"] = ess_block
+    if args.duration > 0:
+        model.close()
+        log(f"serving: {args.rate} requests/s for {args.duration} s")
+        out["serving"] = serving_block(args.rate, args.duration, args.moves_scale, args.workers,
+                                       args.hbm_gb, args.seed)
+        log(f"serving: p50 {out['serving']['p50_latency_s']:.2f} s "
+            f"p99 {out['serving']['p99_latency_s']:.2f} s")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, cfg)
     print(json.dumps(out), flush=True)

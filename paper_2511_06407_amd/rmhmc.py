@@ -19,6 +19,12 @@ LIB_PATH = os.path.join(_HERE, "librmhmc.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2511_06407_amd.build`")
+# torch ships its own HIP runtime under the same soname (libamdhip64.so.7)
+# as the one the library links against; whichever is loaded first serves the
+# whole process.  Loading torch first makes its runtime the shared one, so
+# its tensors and streams are valid in the library (loaded the other way
+# round, torch finds no GPU).
+import torch  # noqa: E402,F401
 _lib = C.CDLL(LIB_PATH)
 
 MAX_TERM_COLS = 8
