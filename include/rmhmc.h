@@ -358,8 +358,9 @@ rmhmc_status rmhmc_gemm_f64_splitk(int m, int n, int k, const double* A, int lda
 /* Live per-kernel timing (instrumentation, off by default).  When enabled,
  * the launches of each kernel family below are bracketed by HIP events on
  * their own stream and their algorithmic work is tallied:
- *   0 FP64 MFMA GEMM, 1 FP32 MFMA GEMM, 2 Jacobi subproblem solve,
- *   3 Jacobi rotation apply, 4 kernel-derivative weighted sums,
+ *   0 FP64 MFMA GEMM, 1 FP32 MFMA GEMM, 2 Jacobi round launches of
+ *   warm-started solves (one event pair per sweep, counted per launch),
+ *   3 the same for static solves, 4 kernel-derivative weighted sums,
  *   5 kernel-derivative mat-vec, 6 Cholesky diagonal block.
  * rmhmc_timing_enable(mask) clears the tallies and times the families whose
  * bit (1 << family) is set, 0 switches timing off (synchronises the device);

@@ -39,12 +39,14 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 // HIP events on the launch stream and record the algorithmic flops / bytes
 // of that launch; rmhmc_timing_read() sums them per kernel family.
 enum TimerKind {
-  TK_GEMM_F64 = 0, TK_GEMM_F32, TK_JACOBI_SOLVE, TK_JACOBI_APPLY, TK_KD_WSUM, TK_KD_MATVEC,
+  TK_GEMM_F64 = 0, TK_GEMM_F32, TK_JACOBI_DYNAMIC, TK_JACOBI_STATIC, TK_KD_WSUM, TK_KD_MATVEC,
   TK_POTRF, TK_COUNT
 };
 bool timing_enabled();
 int timing_begin(int kind, hipStream_t st);
-void timing_end(int slot, hipStream_t st, double flops, double bytes);
+// flops and bytes are the algorithmic work of everything between begin and
+// end, which may be several back-to-back launches of one kernel family
+void timing_end(int slot, hipStream_t st, double flops, double bytes, long long launches = 1);
 
 // ------------------------------------------------------------------ GEMM
 // C = alpha * op(A) op(B) + beta * C, column-major.  op(A) is m x k, op(B)

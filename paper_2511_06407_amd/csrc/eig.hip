@@ -986,18 +986,20 @@ JacobiResult jacobi_eig(int D, EigWork& w, double zeta, double gfloor, int max_s
                                                         : jacobi_round_kernel<JACOBI_INNER_STATIC>;
   auto sweep = [&]() {
     // launch 0 solves round 0 from M; launch r + 1 applies round r to M and
-    // Psi and solves round r + 1 from M_r and V_r
-    int slot = timing_begin(TK_JACOBI_SOLVE, st);
+    // Psi and solves round r + 1 from M_r and V_r.  One event pair brackets
+    // the sweep's nb back-to-back launches, so the per-launch average carries
+    // no event overhead of its own.
+    const int slot =
+        timing_begin(max_inner == JACOBI_INNER_DYNAMIC ? TK_JACOBI_DYNAMIC : TK_JACOBI_STATIC, st);
     hipLaunchKernelGGL(round_kernel, dim3(ns), dim3(256), 0, st, Dp, -1, ns,
                        (const double*)Mb[cur], Mb[cur ^ 1], (const double*)nullptr, Vb[0],
                        (const double*)w.ctrl, 0, 0, w.Psi);
     RM_CHECK_LAUNCH();
     // algorithmic bytes: subproblems read, rotations written
-    timing_end(slot, st, solve_flops, 2.0 * vset);
+    double flops = solve_flops, bytes = 2.0 * vset;
     for (int r = 0; r < nb - 1; ++r) {
       const bool more = r + 1 < nb - 1;
       const int nsolve = more ? ns : 0;
-      slot = timing_begin(TK_JACOBI_SOLVE, st);
       hipLaunchKernelGGL(round_kernel, dim3(nsolve + cdiv(ntri, 4) + cdiv(npsi, 4)), dim3(256),
                          ROUND_LDS_RESERVE, st, Dp, r, nsolve, (const double*)Mb[cur], Mb[cur ^ 1],
                          (const double*)Vb[r & 1], Vb[(r + 1) & 1], (const double*)w.ctrl, ntri,
@@ -1006,12 +1008,12 @@ JacobiResult jacobi_eig(int D, EigWork& w, double zeta, double gfloor, int max_s
       // algorithmic work: M update (upper tiles read, all of M written), Psi
       // read and written, rotations V_r read once; solves: three tiles of
       // M_r read per subproblem, V_{r+1} written
-      timing_end(slot, st,
-                 4.0 * sb3 * ntri + 2.0 * sb3 * npsi + (more ? solve_flops + compose_flops : 0.0),
-                 (double)ntri * tile + 3.0 * (double)Dp * Dp * sizeof(double) + vset +
-                     (more ? 3.0 * ns * tile + vset : 0.0));
+      flops += 4.0 * sb3 * ntri + 2.0 * sb3 * npsi + (more ? solve_flops + compose_flops : 0.0);
+      bytes += (double)ntri * tile + 3.0 * (double)Dp * Dp * sizeof(double) + vset +
+               (more ? 3.0 * ns * tile + vset : 0.0);
       cur ^= 1;
     }
+    timing_end(slot, st, flops, bytes, nb);
     check(0);
   };
   check(1);

@@ -16,6 +16,7 @@ struct TRec {
   int kind;
   hipEvent_t a, b;
   double flops, bytes;
+  long long launches;   // back-to-back launches of the kind between a and b
 };
 std::mutex g_tmu;
 unsigned g_tmask = 0;
@@ -38,19 +39,20 @@ bool timing_enabled() { return g_tmask != 0; }
 int timing_begin(int kind, hipStream_t st) {
   if (!((g_tmask >> kind) & 1u)) return -1;
   std::lock_guard<std::mutex> lk(g_tmu);
-  TRec r{kind, take_event(), take_event(), 0.0, 0.0};
+  TRec r{kind, take_event(), take_event(), 0.0, 0.0, 1};
   RM_HIP(hipEventRecord(r.a, st));
   g_recs.push_back(r);
   return (int)g_recs.size() - 1;
 }
 
-void timing_end(int slot, hipStream_t st, double flops, double bytes) {
+void timing_end(int slot, hipStream_t st, double flops, double bytes, long long launches) {
   if (slot < 0) return;
   std::lock_guard<std::mutex> lk(g_tmu);
   TRec& r = g_recs[slot];
   RM_HIP(hipEventRecord(r.b, st));
   r.flops = flops;
   r.bytes = bytes;
+  r.launches = launches;
 }
 
 void timing_set(unsigned mask) {
@@ -72,7 +74,7 @@ void timing_read(int kind, long long* launches, double* ms, double* flops, doubl
     RM_HIP(hipEventSynchronize(r.b));
     float e = 0.f;
     RM_HIP(hipEventElapsedTime(&e, r.a, r.b));
-    ++n;
+    n += r.launches;
     t += e;
     f += r.flops;
     b += r.bytes;

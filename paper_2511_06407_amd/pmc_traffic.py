@@ -25,8 +25,12 @@ def read(path):
 
 
 def calibration(rows, calib_bytes):
-    """Counter KiB of the largest copy dispatch (the calibration copy)."""
-    copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"] or "copy" in r["Kernel_Name"].lower()]
+    """Counter KiB of the calibration copy: the largest dispatch of the
+    runtime's device-to-device copy kernel (the program's own copy kernels,
+    such as the chain's accept copy, are not of known size)."""
+    copies = [r for r in rows if "__amd_rocclr_copyBuffer" in r["Kernel_Name"]]
+    if not copies:
+        raise SystemExit("no __amd_rocclr_copyBuffer dispatch: run the program with its calibration copy")
     best = max(copies, key=lambda r: float(r["Counter_Value"]))
     kib = float(best["Counter_Value"])
     return calib_bytes / (kib * 1024.0), kib

@@ -44,7 +44,7 @@ EXPORTED = ["rmhmc_model_create", "rmhmc_model_dims", "rmhmc_model_destroy", "rm
             "rmhmc_batch_retire", "rmhmc_batch_destroy", "rmhmc_model_set_beta",
             "rmhmc_log_likelihood"]
 
-TIMER_KINDS = {"gemm_f64": 0, "gemm_f32": 1, "jacobi_solve": 2, "jacobi_apply": 3, "kd_wsum": 4,
+TIMER_KINDS = {"gemm_f64": 0, "gemm_f32": 1, "jacobi_round": 2, "jacobi_round_static": 3, "kd_wsum": 4,
                "kd_matvec": 5, "potrf_diag": 6}
 
 
