@@ -52,7 +52,19 @@ typedef enum { RMHMC_FP64 = 0, RMHMC_MIXED = 1 } rmhmc_precision;
  * Both stay above 1 / alpha (= kappa) and approach |lam| for large |lam|. */
 typedef enum { RMHMC_SOFTABS_COTH = 0, RMHMC_SOFTABS_SQRT = 1 } rmhmc_softabs;
 
-typedef enum { RMHMC_LIK_BERNOULLI_LOGIT = 0, RMHMC_LIK_GAUSSIAN = 1 } rmhmc_lik;
+/* Per-record likelihoods (Sec. 2.1, Eq. data_likelihood):
+ *   BERNOULLI_LOGIT  y in {0,1}, P(y = 1) = sigmoid(f);
+ *   GAUSSIAN         y ~ N(f, noise_var);
+ *   GAUSSIAN_MV      Example 1 of Sec. 2.1 (Eq. mvmodel), two latent
+ *                    functions: y ~ N(f1, delta + exp f2).  The N latent
+ *                    points are the R = N / 2 records twice, f1 first, then
+ *                    f2 (n_fns = 2, see rmhmc_model_desc); y has N
+ *                    entries, the R targets first (the rest are unused). */
+typedef enum {
+  RMHMC_LIK_BERNOULLI_LOGIT = 0,
+  RMHMC_LIK_GAUSSIAN = 1,
+  RMHMC_LIK_GAUSSIAN_MV = 2
+} rmhmc_lik;
 
 /* Kernel terms of the multiple-kernel prior f ~ GP(0, sum_c k_c) (Sec. 2.1,
  * Eq. BMKL).  Parameters are consumed in term order:
@@ -73,6 +85,10 @@ typedef struct {
   int kind;                          /* rmhmc_kernel_kind                  */
   int ncols;                         /* 1..RMHMC_MAX_TERM_COLS              */
   int cols[RMHMC_MAX_TERM_COLS];     /* covariate columns used by the term  */
+  int fn;                            /* with n_fns = 2: the latent function
+                                        (0 or 1) whose prior the term is
+                                        part of, -1 for all points; ignored
+                                        otherwise                           */
 } rmhmc_kernel_term;
 
 typedef struct {
@@ -85,6 +101,15 @@ typedef struct {
   const rmhmc_kernel_term* terms; /* [host] nterms entries                     */
   double jitter;             /* fixed diagonal added to K (> 0)                */
   double beta;               /* inverse temperature on the likelihood, >= 0   */
+  int n_fns;                 /* latent functions J: 0 or 1, or 2 with
+                                GAUSSIAN_MV (each f_j has its own GP prior,
+                                Sec. 2.1 Eq. BMKL: a term acts only between
+                                two points of its function, so K is block
+                                diagonal)                                     */
+  int fn_col;                /* n_fns = 2: column of X holding each point's
+                                function index (0 for the first R rows, 1
+                                for the last R)                               */
+  double delta;              /* GAUSSIAN_MV: the fixed variance floor (> 0)  */
 } rmhmc_model_desc;
 
 typedef struct rmhmc_model rmhmc_model;

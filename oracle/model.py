@@ -29,7 +29,7 @@ import math
 import numpy as np
 
 from paper_2511_06407_amd.workloads import (SE_ISO, SE_ARD, LINEAR_ARD, BINARY_SAME,
-                                            LIK_BERNOULLI_LOGIT, LIK_GAUSSIAN,
+                                            LIK_BERNOULLI_LOGIT, LIK_GAUSSIAN, LIK_GAUSSIAN_MV,
                                             term_nparams)
 
 LOG2PI = math.log(2.0 * math.pi)
@@ -47,6 +47,15 @@ def _term_layout(spec):
         out.append((kind, cols, i, n))
         i += n
     return out
+
+
+def _term_mask(spec, t):
+    """1 where term t acts: between two points of its latent function (Sec.
+    2.1: each f_j has its own GP prior), everywhere for untagged terms."""
+    if not spec.term_fns or spec.term_fns[t] < 0:
+        return 1.0
+    on = spec.X[:, spec.fn_col] == spec.term_fns[t]
+    return (on[:, None] & on[None, :]).astype(np.float64)
 
 
 def _se_pieces(spec, eta, cols, i0, kind):
@@ -74,18 +83,21 @@ def _se_pieces(spec, eta, cols, i0, kind):
 
 
 def gram(spec, eta):
-    """K(eta) = sum of kernel terms + jitter I (Sec. 2.1, Eq. BMKL)."""
+    """K(eta) = sum of kernel terms + jitter I (Sec. 2.1, Eq. BMKL); a term
+    tagged with a latent function acts only within that function's block."""
     N = spec.N
     K = spec.jitter * np.eye(N, dtype=np.result_type(eta, np.float64))
-    for kind, cols, i0, n in _term_layout(spec):
+    for t, (kind, cols, i0, n) in enumerate(_term_layout(spec)):
         if kind in (SE_ISO, SE_ARD):
-            K = K + _se_pieces(spec, eta, cols, i0, kind)[0]
+            Kt = _se_pieces(spec, eta, cols, i0, kind)[0]
         elif kind == LINEAR_ARD:
+            Kt = 0.0
             for j, c in enumerate(cols):
-                K = K + np.exp(eta[i0 + j]) * np.outer(spec.X[:, c], spec.X[:, c])
+                Kt = Kt + np.exp(eta[i0 + j]) * np.outer(spec.X[:, c], spec.X[:, c])
         elif kind == BINARY_SAME:
             c = cols[0]
-            K = K + np.exp(2.0 * eta[i0]) * (spec.X[:, c, None] == spec.X[None, :, c])
+            Kt = np.exp(2.0 * eta[i0]) * (spec.X[:, c, None] == spec.X[None, :, c])
+        K = K + _term_mask(spec, t) * Kt
     return K
 
 
@@ -121,6 +133,10 @@ class KernelDerivs:
         terms = {self.owner[i][0] for i in idx}
         if len(terms) != 1:
             return None
+        out = self._d(idx)
+        return None if out is None else _term_mask(self.spec, self.owner[idx[0]][0]) * out
+
+    def _d(self, idx):
         t, kind, cols, i0, _ = self.owner[idx[0]]
         loc = [i - i0 for i in idx]
         if kind in (SE_ISO, SE_ARD):
@@ -173,6 +189,74 @@ def lik_terms(spec, f):
     raise ValueError(spec.lik)
 
 
+def mv_value(spec, f):
+    """Per-record negative log likelihood of the mean/variance model (Sec.
+    2.1, Eq. mvmodel): y_i ~ N(f1_i, delta + exp f2_i), with f = (f1, f2)."""
+    R = spec.N // 2
+    a, b, y = f[:R], f[R:], spec.y[:R]
+    v = spec.delta + np.exp(b)
+    return 0.5 * (y - a) ** 2 / v + 0.5 * np.log(2.0 * np.pi * v)
+
+
+def mv_partials(spec, f):
+    """Partial derivatives of mv_value in (a, b) = (f1_i, f2_i), up to third
+    order, from l = r^2 / (2v) + ln(2 pi v) / 2 with r = a - y, v = delta + e,
+    e = exp(b), dv/db = e:
+      l_a = r/v, l_aa = 1/v, l_aaa = 0, l_ab = -r e / v^2, l_aab = -e / v^2,
+      l_b = (e/v - r^2 e / v^2) / 2, l_abb = -r e (v - 2e) / v^3,
+      l_bb = (delta e / v^2 - r^2 e (v - 2e) / v^3) / 2,
+      l_bbb = (delta e (v - 2e) / v^3 - r^2 (e/v^2 - 6 e^2/v^3 + 6 e^3/v^4)) / 2."""
+    R = spec.N // 2
+    a, b, y = f[:R], f[R:], spec.y[:R]
+    e = np.exp(b)
+    v = spec.delta + e
+    r = a - y
+    dl = spec.delta
+    return {
+        "a": r / v, "b": 0.5 * (e / v - r * r * e / v ** 2),
+        "aa": 1.0 / v, "ab": -r * e / v ** 2,
+        "bb": 0.5 * (dl * e / v ** 2 - r * r * e * (v - 2.0 * e) / v ** 3),
+        "aaa": np.zeros_like(v), "aab": -e / v ** 2,
+        "abb": -r * e * (v - 2.0 * e) / v ** 3,
+        "bbb": 0.5 * (dl * e * (v - 2.0 * e) / v ** 3
+                      - r * r * (e / v ** 2 - 6.0 * e * e / v ** 3 + 6.0 * e ** 3 / v ** 4)),
+    }
+
+
+def lik_parts(spec, f):
+    """The likelihood in the latent coordinates: (sum_i l_i, gradient,
+    Hessian, v3) with v3(W)_k = sum_mn W_mn d^3 L / df_k df_m df_n.  The
+    single-function likelihoods are diagonal in the points; the mean/variance
+    model couples the two functions' values at each record (a 2 x 2 block per
+    record: Sec. 2.3's per-sample structure with J = 2)."""
+    if spec.lik != LIK_GAUSSIAN_MV:
+        l0, l1, l2, l3 = lik_terms(spec, f)
+        return np.sum(l0), l1, np.diag(l2), lambda W: np.diag(W) * l3
+    R = spec.N // 2
+    d = mv_partials(spec, f)
+    g = np.concatenate([d["a"], d["b"]])
+    H = np.zeros((spec.N, spec.N), dtype=np.result_type(f, np.float64))
+    i = np.arange(R)
+    H[i, i] = d["aa"]
+    H[R + i, R + i] = d["bb"]
+    H[i, R + i] = d["ab"]
+    H[R + i, i] = d["ab"]
+
+    def v3(W):
+        w11, w22 = np.diag(W)[:R], np.diag(W)[R:]
+        w12 = 0.5 * (W[i, R + i] + W[R + i, i])
+        return np.concatenate([w11 * d["aaa"] + 2.0 * w12 * d["aab"] + w22 * d["abb"],
+                               w11 * d["aab"] + 2.0 * w12 * d["abb"] + w22 * d["bbb"]])
+    return np.sum(mv_value(spec, f)), g, H, v3
+
+
+def lik_sum(spec, f):
+    """-ln P(X | f): the sum of the per-record negative log likelihoods."""
+    if spec.lik == LIK_GAUSSIAN_MV:
+        return np.sum(mv_value(spec, f))
+    return np.sum(lik_terms(spec, f)[0])
+
+
 # --------------------------------------------------------------------------
 # U, grad U, H
 # --------------------------------------------------------------------------
@@ -189,8 +273,7 @@ def neg_log_post(spec, q):
     a = np.linalg.solve(K, f)
     sign, logabs = np.linalg.slogdet(K)
     logdet = logabs + np.log(sign) if np.iscomplexobj(K) else logabs
-    l0 = lik_terms(spec, f)[0]
-    return (spec.beta * np.sum(l0) + 0.5 * f @ a + 0.5 * logdet + 0.5 * eta @ eta
+    return (spec.beta * lik_sum(spec, f) + 0.5 * f @ a + 0.5 * logdet + 0.5 * eta @ eta
             + 0.5 * (N + P) * LOG2PI)
 
 
@@ -203,7 +286,7 @@ def gradient(spec, q):
     a = Kinv @ f
     kd = KernelDerivs(spec, eta)
     g = np.empty(N + P, dtype=np.result_type(q, np.float64))
-    g[:N] = spec.beta * lik_terms(spec, f)[1] + a
+    g[:N] = spec.beta * lik_parts(spec, f)[1] + a
     for l in range(P):
         Kl = kd.d((l,))
         g[N + l] = -0.5 * a @ (Kl @ a) + 0.5 * np.sum(Kinv * Kl) + eta[l]
@@ -213,7 +296,7 @@ def gradient(spec, q):
 def hessian(spec, q):
     """U, grad U and the Hessian H of U at q.
 
-    H_ff = beta diag(l'') + K^-1
+    H_ff = beta L'' + K^-1   (L'' = diag(l'') for one latent function)
     H_fl = -A_l alpha
     H_lm = a'K_l A_m a - 1/2 a'K_lm a + 1/2 tr(K^-1 K_lm) - 1/2 tr(A_l A_m) + delta_lm
     """
@@ -225,10 +308,10 @@ def hessian(spec, q):
     kd = KernelDerivs(spec, eta)
     Kl = [kd.d((l,)) for l in range(P)]
     A = [Kinv @ Kl[l] for l in range(P)]
-    l0, l1, l2, _ = lik_terms(spec, f)
+    lsum, l1, Hl, _ = lik_parts(spec, f)
     dt = np.result_type(q, np.float64)
     H = np.zeros((N + P, N + P), dtype=dt)
-    H[:N, :N] = 0.5 * (Kinv + Kinv.T) + np.diag(spec.beta * l2)
+    H[:N, :N] = 0.5 * (Kinv + Kinv.T) + spec.beta * Hl
     for l in range(P):
         col = -(A[l] @ a)
         H[:N, N + l] = col
@@ -244,7 +327,7 @@ def hessian(spec, q):
             H[N + m, N + l] = v
     sign, logabs = np.linalg.slogdet(K)
     logdet = logabs + np.log(sign) if np.iscomplexobj(K) else logabs
-    U = (spec.beta * np.sum(l0) + 0.5 * f @ a + 0.5 * logdet + 0.5 * eta @ eta
+    U = (spec.beta * lsum + 0.5 * f @ a + 0.5 * logdet + 0.5 * eta @ eta
          + 0.5 * (N + P) * LOG2PI)
     grad = np.empty(N + P, dtype=dt)
     grad[:N] = spec.beta * l1 + a
@@ -266,7 +349,7 @@ def contract(spec, q, W):
     blocks (omitted in the paper's display) are written out here in full.
     With w_l = W[f, eta_l], u_l = K^-1 w_l, a_m = A_m alpha, k_l = K_l alpha:
 
-    v_f = beta diag(W_ff) l''' - 2 sum_l A_l u_l
+    v_f = beta v3(W_ff) - 2 sum_l A_l u_l   (v3 = diag(W_ff) l''' for one function)
           + K^-1 [ 2 sum_lm W_lm K_l a_m - sum_lm W_lm K_lm alpha ]
     v_n = -tr(K^-1 W_ff K^-1 K_n) + 2 sum_l [u_l'K_n a_l + u_l'K_l a_n - u_l'K_ln alpha]
           + sum_lm W_lm dH_lm/d eta_n
@@ -290,11 +373,11 @@ def contract(spec, q, W):
     ik2a = [[Kinv @ k2a[l][m] for m in range(P)] for l in range(P)]
     Aam = [[A[l] @ am[m] for m in range(P)] for l in range(P)]
     u = [Kinv @ w[:, l] for l in range(P)]
-    l3 = lik_terms(spec, f)[3]
+    v3 = lik_parts(spec, f)[3]
 
     v = np.zeros(N + P)
     # f-part
-    vf = spec.beta * np.diag(Wff) * l3
+    vf = spec.beta * v3(Wff)
     for l in range(P):
         vf = vf - 2.0 * (A[l] @ u[l])
     z = np.zeros(N)

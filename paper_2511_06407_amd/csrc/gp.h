@@ -13,6 +13,7 @@ constexpr int MAX_TUPLES = 64;
 struct TermDev {
   int kind, ncols, p0, np;
   int cols[RMHMC_MAX_TERM_COLS];
+  int fn;               // latent function the term belongs to (-1: all points)
 };
 
 // Everything a kernel needs to evaluate K(eta) and its derivatives at (i, j).
@@ -20,6 +21,7 @@ struct ModelDev {
   int N, dx, P, nterms;
   double jitter;
   const double* X;     // dx x N: X[c * N + i]
+  int fn_col;          // column of X with each point's latent function, -1: one function
   TermDev terms[MAX_TERMS];
   int param_term[MAX_P];
 };
@@ -54,9 +56,15 @@ constexpr int KD_MV_SPLIT = 32;
 void kd_matvec(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
                const double* x, int nx, double* y, double* work, hipStream_t st);
 
-// l, l', l'', l''' of the per-sample negative log likelihood: out[0..4N).
-void lik_derivs(int N, int lik, double noise_var, const double* f, const double* y, double* out,
-                hipStream_t st);
+// Likelihood derivatives in the latent coordinates, out[0..LIK_SLOTS * N):
+//   [0, N)   l_i (per record; zero at the second function's points)
+//   [N, 2N)  gradient;  [2N, 3N) diagonal of the Hessian;
+//   [3N, 4N) diagonal third derivatives d^3 L / df_k^3;
+// and, for the mean/variance model (R = N / 2 records, a = f1_i, b = f2_i):
+//   [4N, 4N+R) l_ab, [4N+R, 5N) l_aab, [5N, 5N+R) l_abb, [5N+R, 6N) zero.
+constexpr int LIK_SLOTS = 6;
+void lik_derivs(int N, int lik, double noise_var, double delta, const double* f, const double* y,
+                double* out, hipStream_t st);
 
 // out[a * ny + b] = x_a . y_b  (length n, x stride sx, y stride sy)
 void pair_dots(int n, const double* x, long sx, int nx, const double* y, long sy, int ny,

@@ -23,6 +23,16 @@ __device__ __forceinline__ void term_eval(const ModelDev& md, const double* __re
   const TermDev& T = md.terms[t];
   const double* X = md.X;
   const int N = md.N;
+  if (T.fn >= 0) {
+    // a term of one latent function's prior acts only between its points:
+    // the term and every derivative of it vanish elsewhere
+    const double* F = X + (long)md.fn_col * N;
+    if (F[i] != (double)T.fn || F[j] != (double)T.fn) {
+      tv.Kt = 0.0;
+      for (int c = 0; c < RMHMC_MAX_TERM_COLS; ++c) tv.u[c] = 0.0;
+      return;
+    }
+  }
   if (T.kind == RMHMC_K_SE_ISO) {
     double r2 = 0.0;
     for (int c = 0; c < T.ncols; ++c) {
@@ -224,6 +234,32 @@ __global__ __launch_bounds__(256) void kd_gen_kernel(ModelDev md, const double* 
   }
 }
 
+// Mean/variance model (Sec. 2.1, Eq. mvmodel), one thread per record:
+// l = r^2 / (2v) + ln(2 pi v) / 2 with r = a - y, v = delta + e, e = exp(b),
+// differentiated in a = f1_i and b = f2_i (dv/db = e).
+__global__ void lik_mv_kernel(int R, double delta, const double* __restrict__ f,
+                              const double* __restrict__ y, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= R) return;
+  const long N = 2L * R;
+  const double a = f[i], b = f[R + i];
+  const double e = exp(b), v = delta + e, r = a - y[i];
+  const double iv = 1.0 / v, iv2 = iv * iv, iv3 = iv2 * iv, r2 = r * r;
+  out[i] = 0.5 * r2 * iv + 0.5 * log(2.0 * M_PI * v);
+  out[R + i] = 0.0;
+  out[N + i] = r * iv;                                               // l_a
+  out[N + R + i] = 0.5 * (e * iv - r2 * e * iv2);                    // l_b
+  out[2 * N + i] = iv;                                               // l_aa
+  out[2 * N + R + i] = 0.5 * (delta * e * iv2 - r2 * e * (v - 2.0 * e) * iv3);   // l_bb
+  out[3 * N + i] = 0.0;                                              // l_aaa
+  out[3 * N + R + i] = 0.5 * (delta * e * (v - 2.0 * e) * iv3 -
+                              r2 * (e * iv2 - 6.0 * e * e * iv3 + 6.0 * e * e * e * iv3 * iv));  // l_bbb
+  out[4 * N + i] = -r * e * iv2;                                     // l_ab
+  out[4 * N + R + i] = -e * iv2;                                     // l_aab
+  out[5 * N + i] = -r * e * (v - 2.0 * e) * iv3;                     // l_abb
+  out[5 * N + R + i] = 0.0;
+}
+
 __global__ void lik_kernel(int N, int lik, double noise_var, const double* __restrict__ f,
                            const double* __restrict__ y, double* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -354,9 +390,15 @@ void kd_wsum_stack(const ModelDev& md, const double* eta, const Tuple* tuples, i
   }
 }
 
-void lik_derivs(int N, int lik, double noise_var, const double* f, const double* y, double* out,
-                hipStream_t st) {
-  hipLaunchKernelGGL(lik_kernel, dim3(cdiv(N, 256)), dim3(256), 0, st, N, lik, noise_var, f, y, out);
+void lik_derivs(int N, int lik, double noise_var, double delta, const double* f, const double* y,
+                double* out, hipStream_t st) {
+  if (lik == RMHMC_LIK_GAUSSIAN_MV) {
+    const int R = N / 2;
+    hipLaunchKernelGGL(lik_mv_kernel, dim3(cdiv(R, 256)), dim3(256), 0, st, R, delta, f, y, out);
+  } else {
+    hipLaunchKernelGGL(lik_kernel, dim3(cdiv(N, 256)), dim3(256), 0, st, N, lik, noise_var, f, y,
+                       out);
+  }
   RM_CHECK_LAUNCH();
 }
 

@@ -216,6 +216,56 @@ __global__ __launch_bounds__(64) void reduce_parts_kernel(int nparts, int nb, co
   if (lane == 0) out[b] = s;
 }
 
+// Panel of the blocked Cholesky factorisation: P = B L_kk^-T for the rows
+// below the diagonal block, i.e. the triangular solve X L_kk' = B, in place.
+// One lane per row: x_c = (b_c - sum_{j<c} x_j L_kk[c][j]) / L_kk[c][c] by
+// forward substitution, which is backward stable; multiplying B by the
+// explicit inverse of L_kk instead loses accuracy in proportion to cond(L_kk)
+// (measured 13x on a 1024-point kernel matrix with jitter 1e-6).  L_kk and
+// the reciprocals of its diagonal sit in LDS and are read at the same address
+// by every lane; x stays in registers; the sums run over four interleaved
+// partial sums.
+__global__ __launch_bounds__(256) void trsm_panel_kernel(int n, int k0, int bw, int r0,
+                                                         double* __restrict__ L) {
+  __shared__ double sL[CB * CB];
+  __shared__ double rd[CB];
+  const double* Dk = L + k0 + (long)k0 * n;
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    const int r = e / CB, c = e % CB;
+    sL[e] = (r < bw && c <= r) ? Dk[r + (long)c * n] : 0.0;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < CB; c += blockDim.x) rd[c] = c < bw ? 1.0 / sL[c * CB + c] : 0.0;
+  __syncthreads();
+  const int row = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  double* B = L + row + (long)k0 * n;   // element c of this row at B[c * n]
+  double x[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) x[c] = c < bw ? B[(long)c * n] : 0.0;
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    if (c < bw) {
+      const double* Lc = sL + c * CB;
+      double s0 = x[c], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int j = 0;
+#pragma unroll
+      for (; j + 3 < c; j += 4) {
+        s0 -= Lc[j] * x[j];
+        s1 -= Lc[j + 1] * x[j + 1];
+        s2 -= Lc[j + 2] * x[j + 2];
+        s3 -= Lc[j + 3] * x[j + 3];
+      }
+#pragma unroll
+      for (; j < c; ++j) s0 -= Lc[j] * x[j];
+      x[c] = ((s0 + s1) + (s2 + s3)) * rd[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CB; ++c)
+    if (c < bw) B[(long)c * n] = x[c];
+}
+
 // ---------------------------------------------------------------- Cholesky
 // Factor one CB x CB diagonal block and invert its triangle in one workgroup.
 //
@@ -422,14 +472,10 @@ void chol_inverse(int n, const double* K, double* Kinv, double* logdet, CholWork
                        w.diagLogs, w.info);
     RM_CHECK_LAUNCH();
     if (rm <= 0) break;
-    // panel: tmp = L[r0:, k0:k0+bw] * Linv_kk'
-    Gemm<double> g;
-    g.m = rm; g.n = bw; g.k = bw;
-    g.A = w.L + r0 + (long)k0 * n; g.lda = n;
-    g.B = w.Linv + k0 + (long)k0 * n; g.ldb = n; g.tB = true;
-    g.C = w.tmp + r0 + (long)k0 * n; g.ldc = n;
-    gemm(g, st);
-    copy_matrix(rm, bw, w.tmp + r0 + (long)k0 * n, n, w.L + r0 + (long)k0 * n, n, st);
+    // panel: L[r0:, k0:k0+bw] <- L[r0:, k0:k0+bw] L_kk^-T by substitution
+    hipLaunchKernelGGL(trsm_panel_kernel, dim3(cdiv(rm, 256)), dim3(256), 0, st, n, k0, bw, r0,
+                       w.L);
+    RM_CHECK_LAUNCH();
     // trailing: L[r0:, r0:] -= P P'
     Gemm<double> t;
     t.m = rm; t.n = rm; t.k = bw; t.alpha = -1.0; t.beta = 1.0;

@@ -74,9 +74,11 @@ struct Pool {
 
 // ------------------------------------------------------------ small kernels
 
-// H (Dp x Dp, padded with zeros): H_ff = K^-1 + beta diag(l''), H_fl = -A_l alpha,
+// H (Dp x Dp, padded with zeros): H_ff = K^-1 + beta L'', H_fl = -A_l alpha,
 // H_lm = k_l.a_m + <Phi, K_lm> - tr(A_l A_m)/2 + delta_lm (symmetrised).
-__global__ void assemble_H_kernel(int N, int P, int Dp, double beta, const double* __restrict__ Kinv,
+// L'' is diag(l'') for one latent function; with two (R > 0 records, the
+// mean/variance model) each record also couples f1_i and f2_i = f_(R+i).
+__global__ void assemble_H_kernel(int N, int P, int Dp, int R, double beta, const double* __restrict__ Kinv,
                                   const double* __restrict__ lik, const double* __restrict__ a,
                                   const double* __restrict__ kla, const double* __restrict__ phiK2,
                                   const double* __restrict__ trAA, const int* __restrict__ pidx,
@@ -89,6 +91,7 @@ __global__ void assemble_H_kernel(int N, int P, int Dp, double beta, const doubl
   if (i < N && j < N) {
     v = Kinv[i + (long)j * N];
     if (i == j) v += beta * lik[2 * N + i];
+    if (R > 0 && (i - j == R || j - i == R)) v += beta * lik[4 * N + min(i, j)];
   } else if (i < N && j < D) {
     v = -a[(long)(j - N) * N + i];
   } else if (j < N && i < D) {
@@ -178,12 +181,28 @@ __global__ __launch_bounds__(64 * ZV_WAVES) void zvec_kernel(int N, int P, int D
 }
 
 // v = tr(W dH/dq) for the latent coordinates i < N, assembled from the pieces.
-__global__ void contract_final_kernel(int N, int P, int Dp, double beta, const double* __restrict__ W,
+// The likelihood part is sum_mn W_mn d^3 L / df_i df_m df_n: W_ii l'''_i for
+// one latent function; with two (R > 0), per record (a, b) = (f1_r, f2_r):
+//   v_a = W_aa l_aaa + 2 W_ab l_aab + W_bb l_abb,
+//   v_b = W_aa l_aab + 2 W_ab l_abb + W_bb l_bbb.
+__global__ void contract_final_kernel(int N, int P, int Dp, int R, double beta,
+                                      const double* __restrict__ W,
                                       const double* __restrict__ lik, const double* __restrict__ Au,
                                       const double* __restrict__ Kz, double* __restrict__ v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  double s = beta * W[i + (long)i * Dp] * lik[3 * N + i] + Kz[i];
+  double t3;
+  if (R > 0) {
+    const int r = i < R ? i : i - R;
+    const double waa = W[r + (long)r * Dp], wbb = W[(r + R) + (long)(r + R) * Dp];
+    const double wab = 0.5 * (W[r + (long)(r + R) * Dp] + W[(r + R) + (long)r * Dp]);
+    const double laab = lik[4 * N + R + r], labb = lik[5 * N + r];
+    t3 = i < R ? waa * lik[3 * N + r] + 2.0 * wab * laab + wbb * labb
+               : waa * laab + 2.0 * wab * labb + wbb * lik[3 * N + R + r];
+  } else {
+    t3 = W[i + (long)i * Dp] * lik[3 * N + i];
+  }
+  double s = beta * t3 + Kz[i];
   for (int l = 0; l < P; ++l) s -= 2.0 * Au[(long)l * N + i];
   v[i] = s;
 }
@@ -444,7 +463,8 @@ constexpr int MAX_FP_BUDGETS = 16;
 struct Model {
   int N = 0, dx = 0, P = 0, D = 0, Dp = 0;
   int lik = 0;
-  double noise_var = 1.0, jitter = 1e-6, beta = 1.0;
+  int R = 0;            // records of the mean/variance model (two latent functions), else 0
+  double noise_var = 1.0, jitter = 1e-6, beta = 1.0, delta = 0.0;
   rmhmc_precision prec = RMHMC_FP64;
   ModelDev md{};
   Pool pool;
@@ -532,7 +552,7 @@ void layout_point(const Model& m, Point& p, Carve& c) {
   p.A = c.take<double>(P * NN);
   p.At = c.take<double>(mixed ? 1 : P * NN);
   p.alpha = c.take<double>(N);
-  p.lik = c.take<double>(4 * N);
+  p.lik = c.take<double>((long)LIK_SLOTS * N);
   p.scal = c.take<double>(8);
   p.k1a = c.take<double>(P * N);
   p.a = c.take<double>(P * N);
@@ -640,7 +660,7 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st, int* fail) {
   // K^-1 and K_l are symmetric: A x = A' x, and the column-dot kernel is the
   // well-parallelised one
   gemv(N, N, 1.0, pt.Kinv, N, true, 0, pt.q, 0, 0.0, pt.alpha, 0, 1, st);
-  lik_derivs(N, m.lik, m.noise_var, pt.q, m.y, pt.lik, st);
+  lik_derivs(N, m.lik, m.noise_var, m.delta, pt.q, m.y, pt.lik, st);
   const bool mixed = m.prec == RMHMC_MIXED;
   {  // A_l = K^-1 K_l, and the transposed copies
     // A_l stays FP64 in both modes: K^-1 reaches 1/jitter while A_l is O(1),
@@ -674,7 +694,7 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st, int* fail) {
   vsum(N, pt.lik, pt.scal + 3, st);
   vdot(N, pt.q, pt.alpha, pt.scal + 4, st);
   hipLaunchKernelGGL(assemble_H_kernel, dim3(cdiv((long)m.Dp * m.Dp, 256)), dim3(256), 0, st, N, P,
-                     m.Dp, m.beta, (const double*)pt.Kinv, (const double*)pt.lik,
+                     m.Dp, m.R, m.beta, (const double*)pt.Kinv, (const double*)pt.lik,
                      (const double*)pt.a, (const double*)pt.kla, (const double*)pt.phiK2,
                      (const double*)pt.trAA, (const int*)m.pidx, pt.H);
   RM_CHECK_LAUNCH();
@@ -846,7 +866,7 @@ void contract(Model& m, Point& pt, const double* W, double* v, hipStream_t st) {
   RM_CHECK_LAUNCH();
   gemv(N, N, 1.0, pt.Kinv, N, true, 0, m.z, 0, 0.0, m.Kz, 0, 1, st);
   hipLaunchKernelGGL(contract_final_kernel, dim3(cdiv(N, 256)), dim3(256), 0, st, N, P, Dp,
-                     m.beta, W, (const double*)pt.lik, (const double*)m.Au, (const double*)m.Kz, v);
+                     m.R, m.beta, W, (const double*)pt.lik, (const double*)m.Au, (const double*)m.Kz, v);
   RM_CHECK_LAUNCH();
   if (P > 0) {
     hipLaunchKernelGGL(contract_eta_kernel, dim3(P), dim3(64), 0, st, N, P, Dp, W,
@@ -945,14 +965,31 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   RM_REQUIRE(d->nterms >= 1 && d->nterms <= MAX_TERMS && d->terms, "1..8 kernel terms required");
   RM_REQUIRE(d->jitter > 0.0 && std::isfinite(d->jitter), "jitter must be positive");
   RM_REQUIRE(d->beta >= 0.0 && std::isfinite(d->beta), "beta must be finite and >= 0");
-  RM_REQUIRE(d->lik == RMHMC_LIK_BERNOULLI_LOGIT || d->lik == RMHMC_LIK_GAUSSIAN, "unknown likelihood");
+  RM_REQUIRE(d->lik == RMHMC_LIK_BERNOULLI_LOGIT || d->lik == RMHMC_LIK_GAUSSIAN ||
+                 d->lik == RMHMC_LIK_GAUSSIAN_MV,
+             "unknown likelihood");
   if (d->lik == RMHMC_LIK_GAUSSIAN) RM_REQUIRE(d->noise_var > 0.0, "noise_var must be positive");
   RM_REQUIRE(prec == RMHMC_FP64 || prec == RMHMC_MIXED, "unknown precision");
+  const bool two = d->n_fns == 2;
+  RM_REQUIRE(d->n_fns >= 0 && d->n_fns <= 2, "n_fns must be 0, 1 or 2");
+  RM_REQUIRE(two == (d->lik == RMHMC_LIK_GAUSSIAN_MV),
+             "two latent functions go with the mean/variance likelihood and only with it");
+  if (two) {
+    RM_REQUIRE(d->N % 2 == 0, "two latent functions need N = 2R points");
+    RM_REQUIRE(d->fn_col >= 0 && d->fn_col < d->dx, "fn_col out of range");
+    RM_REQUIRE(d->delta > 0.0 && std::isfinite(d->delta), "delta must be positive");
+    for (int i = 0; i < d->N; ++i)
+      RM_REQUIRE(d->X[(long)i * d->dx + d->fn_col] == (i < d->N / 2 ? 0.0 : 1.0),
+                 "the function column must be 0 for the first R points and 1 for the last R");
+  }
   m.N = d->N; m.dx = d->dx; m.lik = d->lik; m.noise_var = d->noise_var;
   m.jitter = d->jitter; m.beta = d->beta; m.prec = prec;
+  m.R = two ? d->N / 2 : 0;
+  m.delta = two ? d->delta : 0.0;
   int P = 0;
   ModelDev& md = m.md;
   md.N = m.N; md.dx = m.dx; md.nterms = d->nterms; md.jitter = d->jitter;
+  md.fn_col = two ? d->fn_col : -1;
   for (int t = 0; t < d->nterms; ++t) {
     const rmhmc_kernel_term& tt = d->terms[t];
     RM_REQUIRE(tt.ncols >= 1 && tt.ncols <= RMHMC_MAX_TERM_COLS, "term ncols out of range");
@@ -969,8 +1006,10 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
         break;
       default: throw Error(RMHMC_E_ARG, "unknown kernel kind");
     }
+    if (two) RM_REQUIRE(tt.fn >= -1 && tt.fn <= 1, "term fn must be -1, 0 or 1");
     TermDev& T = md.terms[t];
     T.kind = tt.kind; T.ncols = tt.ncols; T.p0 = P; T.np = np;
+    T.fn = two ? tt.fn : -1;
     for (int c = 0; c < RMHMC_MAX_TERM_COLS; ++c) T.cols[c] = c < tt.ncols ? tt.cols[c] : 0;
     RM_REQUIRE(P + np <= MAX_P, "too many hyperparameters");
     for (int a = 0; a < np; ++a) md.param_term[P + a] = t;
@@ -1901,7 +1940,7 @@ rmhmc_status rmhmc_log_likelihood(rmhmc_model* mh, const double* q, double* ll, 
     std::lock_guard<std::mutex> lk(m.busy);
     RM_REQUIRE(!m.in_batch, "the model is admitted to a batch");
     Point& pt = *m.api_pt;
-    lik_derivs(m.N, m.lik, m.noise_var, q, m.y, pt.lik, st);   // l_i = -ln P(X_i | f_i)
+    lik_derivs(m.N, m.lik, m.noise_var, m.delta, q, m.y, pt.lik, st);   // l_i = -ln P(X_i | f_i)
     vsum(m.N, pt.lik, ll, st);
     axpby(1, 0.0, ll, -1.0, ll, st);
     RM_HIP(hipStreamSynchronize(st));

@@ -49,14 +49,16 @@ TIMER_KINDS = {"gemm_f64": 0, "gemm_f32": 1, "jacobi_round": 2, "jacobi_round_st
 
 
 class KernelTerm(C.Structure):
-    _fields_ = [("kind", C.c_int), ("ncols", C.c_int), ("cols", C.c_int * MAX_TERM_COLS)]
+    _fields_ = [("kind", C.c_int), ("ncols", C.c_int), ("cols", C.c_int * MAX_TERM_COLS),
+                ("fn", C.c_int)]
 
 
 class ModelDesc(C.Structure):
     _fields_ = [("N", C.c_int), ("dx", C.c_int), ("X", C.POINTER(C.c_double)),
                 ("y", C.POINTER(C.c_double)), ("lik", C.c_int), ("noise_var", C.c_double),
                 ("nterms", C.c_int), ("terms", C.POINTER(KernelTerm)), ("jitter", C.c_double),
-                ("beta", C.c_double)]
+                ("beta", C.c_double), ("n_fns", C.c_int), ("fn_col", C.c_int),
+                ("delta", C.c_double)]
 
 
 class ChainCfg(C.Structure):
@@ -194,6 +196,7 @@ class Model:
         for t, (kind, cols) in enumerate(spec.terms):
             terms[t].kind = kind
             terms[t].ncols = len(cols)
+            terms[t].fn = spec.term_fns[t] if spec.term_fns else -1
             for c, col in enumerate(cols):
                 terms[t].cols[c] = col
         X = np.ascontiguousarray(spec.X, dtype=np.float64)
@@ -201,7 +204,8 @@ class Model:
         self._keep = (X, y, terms)
         desc = ModelDesc(spec.N, spec.dx, X.ctypes.data_as(C.POINTER(C.c_double)),
                          y.ctypes.data_as(C.POINTER(C.c_double)), spec.lik, spec.noise_var,
-                         len(spec.terms), terms, spec.jitter, spec.beta)
+                         len(spec.terms), terms, spec.jitter, spec.beta,
+                         2 if spec.lik == wl.LIK_GAUSSIAN_MV else 1, spec.fn_col, spec.delta)
         h = C.c_void_p()
         _check(_lib.rmhmc_model_create(C.byref(desc), precision, C.byref(h)))
         self._h = h

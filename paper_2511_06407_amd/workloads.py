@@ -23,7 +23,13 @@ parameterisation the paper's Discussion attributes to earlier work):
     BINARY_SAME(col):  s^2 [x_c == x'_c],               eta = (log s,)
 * Priors: eta ~ N(0, I); f | eta ~ N(0, K(eta)).
 * Likelihood: Bernoulli-logit (y in {0,1}) scaled by an inverse temperature
-  beta (power posterior), or Gaussian with known noise variance (tests only).
+  beta (power posterior), Gaussian with known noise variance (tests), or the
+  mean/variance model of Sec. 2.1 Example 1 (J = 2 latent functions).
+* Several latent functions (J = 2): the latent points are stacked, function
+  by function (f_1 at the R records, then f_2 at the same records); the
+  column fn_col of X holds each point's function index, and a kernel term
+  with term_fns[t] = j acts only between two points of function j, so K is
+  block diagonal, one block per function with its own hyperparameters.
 """
 from __future__ import annotations
 
@@ -40,6 +46,7 @@ BINARY_SAME = 3
 
 LIK_BERNOULLI_LOGIT = 0
 LIK_GAUSSIAN = 1
+LIK_GAUSSIAN_MV = 2     # Example 1 of Sec. 2.1: mean f_1, variance delta + exp(f_2)
 
 KIND_NAMES = {SE_ISO: "se_iso", SE_ARD: "se_ard", LINEAR_ARD: "linear_ard",
               BINARY_SAME: "binary_same"}
@@ -69,6 +76,9 @@ class ModelSpec:
     noise_var: float = 1.0            # Gaussian likelihood only
     jitter: float = 1e-6
     beta: float = 1.0                 # inverse temperature on the likelihood
+    delta: float = 0.0                # variance floor of the mean/variance model
+    fn_col: int = -1                # column of X with each point's function index
+    term_fns: Tuple[int, ...] = ()  # function index of each term (-1: all points)
 
     def __post_init__(self):
         self.X = np.ascontiguousarray(np.asarray(self.X, dtype=np.float64))
@@ -81,6 +91,15 @@ class ModelSpec:
             for c in cols:
                 if not 0 <= c < self.X.shape[1]:
                     raise ValueError("kernel column out of range")
+        self.term_fns = tuple(int(t) for t in self.term_fns)
+        if self.term_fns and len(self.term_fns) != len(self.terms):
+            raise ValueError("term_fns needs one entry per kernel term")
+        if self.term_fns and not 0 <= self.fn_col < self.X.shape[1]:
+            raise ValueError("term_fns needs a task column")
+        if self.lik == LIK_GAUSSIAN_MV:
+            if self.X.shape[0] % 2 or self.delta <= 0.0 or self.fn_col < 0:
+                raise ValueError("the mean/variance model needs 2R stacked points, delta > 0 "
+                                 "and a task column")
 
     @property
     def N(self) -> int:
@@ -89,6 +108,11 @@ class ModelSpec:
     @property
     def dx(self) -> int:
         return self.X.shape[1]
+
+    @property
+    def n_records(self) -> int:
+        """Data records: N, or N / 2 for the two stacked latent functions."""
+        return self.N // 2 if self.lik == LIK_GAUSSIAN_MV else self.N
 
     @property
     def P(self) -> int:
@@ -178,6 +202,28 @@ def gaussian_gp(N: int, noise_var: float = 0.1, seed: int = 0):
     return spec, eta_true, f_true
 
 
+def mean_variance(R: int, seed: int = 0, delta: float = 0.01):
+    """Example 1 of Sec. 2.1: y_i = f_1(x_i) + e_i, e_i ~ N(0, delta + exp f_2(x_i)),
+    with R records of two covariates x ~ N(0, I_2); f_1 ~ GP(SE-ARD) and
+    f_2 ~ GP(SE-iso), each with its own hyperparameters (P = 3 + 2).  The
+    latent points are stacked (f_1 at the R records, then f_2), D = 2R + 5."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((R, 2))
+    X = np.zeros((2 * R, 3))
+    X[:R, :2] = x
+    X[R:, :2] = x
+    X[R:, 2] = 1.0
+    t1, t2 = [(SE_ARD, (0, 1))], [(SE_ISO, (0, 1))]
+    eta1 = rng.standard_normal(term_nparams(*t1[0]))
+    eta2 = rng.standard_normal(term_nparams(*t2[0]))
+    f1 = np.linalg.cholesky(_gram_for_data(x, t1, eta1, 1e-6)) @ rng.standard_normal(R)
+    f2 = np.linalg.cholesky(_gram_for_data(x, t2, eta2, 1e-6)) @ rng.standard_normal(R)
+    y = f1 + np.sqrt(delta + np.exp(f2)) * rng.standard_normal(R)
+    spec = ModelSpec(X=X, y=np.concatenate([y, y]), terms=t1 + t2, lik=LIK_GAUSSIAN_MV,
+                     delta=delta, fn_col=2, term_fns=(0, 1))
+    return spec, np.concatenate([eta1, eta2]), np.concatenate([f1, f2])
+
+
 @dataclasses.dataclass
 class ChainSettings:
     eps: float
@@ -220,6 +266,11 @@ def workload(name: str, seed: int = 0):
                                    n_samples=1000, n_burnin=334)
     if name == "propensity_mkl_d1038":
         spec, _, _ = propensity_mkl(1024, seed)
+        return spec, ChainSettings(eps=0.001, n_leapfrog=20, n_fixed_point=6,
+                                   n_samples=200, n_burnin=67)
+    if name == "mean_variance_d1029":
+        # Example 1 of Sec. 2.1 at R = 512 records: 1024 latent values + 5
+        spec, _, _ = mean_variance(512, seed)
         return spec, ChainSettings(eps=0.001, n_leapfrog=20, n_fixed_point=6,
                                    n_samples=200, n_burnin=67)
     raise KeyError(name)

@@ -27,7 +27,13 @@ def rel(x, y):
 def permuted(spec, q, seed=123):
     """(spec', q', index map) with the data points in another order."""
     rng = np.random.default_rng(seed)
-    p = rng.permutation(spec.N)
+    if spec.n_records != spec.N:
+        # two latent functions stacked record by record: permute the records
+        # and keep each function's block in place
+        r = rng.permutation(spec.n_records)
+        p = np.concatenate([r, spec.n_records + r])
+    else:
+        p = rng.permutation(spec.N)
     s2 = dataclasses.replace(spec, X=spec.X[p], y=spec.y[p])
     full = np.concatenate([p, spec.N + np.arange(spec.P)])
     q2 = q[full]

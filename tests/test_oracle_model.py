@@ -3,7 +3,8 @@ derivative (Squire & Trapp 1998), which is exact to rounding for analytic code,
 and of the kernel matrix itself by entries worked out by hand.
 
 Models: every kernel kind (isotropic SE, SE-ARD, linear-ARD, same-value binary),
-both likelihoods, a tempered likelihood (beta != 1) and random points q.
+every likelihood (the mean/variance model of two latent functions included),
+a tempered likelihood (beta != 1) and random points q.
 Jitter 1e-2 keeps K well conditioned so the bar can be near machine precision.
 """
 import dataclasses
@@ -22,8 +23,9 @@ def small_models():
     b, _, _ = wl.gp_logistic_ard4(9, seed=2)
     c, _, _ = wl.propensity_mkl(12, seed=3)
     d, _, _ = wl.gaussian_gp(8, noise_var=0.3, seed=4)
+    e, _, _ = wl.mean_variance(6, seed=5, delta=0.05)
     out = []
-    for s, beta in ((a, 0.7), (b, 1.0), (c, 0.35), (d, 1.0)):
+    for s, beta in ((a, 0.7), (b, 1.0), (c, 0.35), (d, 1.0), (e, 0.8)):
         out.append(dataclasses.replace(s, jitter=1e-2, beta=beta))
     return out
 
@@ -157,3 +159,33 @@ def test_gram_hand_values(name):
     assert spec.P == len(eta)
     K = model.gram(spec, np.array(eta))
     assert np.allclose(K, want + jitter * np.eye(3), rtol=1e-14, atol=1e-15)
+
+
+def test_mean_variance_likelihood_is_the_normal_density():
+    """Sec. 2.1 Example 1: the per-record term is -ln N(y; f1, delta + exp f2),
+    checked against scipy's normal log density."""
+    from scipy.stats import norm
+    spec, _, _ = wl.mean_variance(7, seed=3, delta=0.02)
+    f = 0.8 * np.random.default_rng(1).standard_normal(spec.N)
+    R = spec.n_records
+    want = -norm.logpdf(spec.y[:R], loc=f[:R], scale=np.sqrt(0.02 + np.exp(f[R:])))
+    assert np.allclose(model.mv_value(spec, f), want, rtol=1e-14, atol=1e-14)
+    assert abs(model.lik_sum(spec, f) - want.sum()) < 1e-12 * abs(want.sum())
+
+
+def test_mean_variance_prior_is_block_diagonal():
+    """Each latent function has its own GP prior (Sec. 2.1): the stacked K is
+    blockdiag(K1(eta_1), K2(eta_2)) + jitter, with K_j the Gram matrix of
+    term j alone on the records' covariates."""
+    spec, _, _ = wl.mean_variance(5, seed=2)
+    eta = np.random.default_rng(0).standard_normal(spec.P)
+    R = spec.n_records
+    x = spec.X[:R, :2]
+    (k1, c1), (k2, c2) = spec.terms
+    n1 = wl.term_nparams(k1, c1)
+    s1 = wl.ModelSpec(X=x, y=np.zeros(R), terms=[(k1, c1)], jitter=spec.jitter)
+    s2 = wl.ModelSpec(X=x, y=np.zeros(R), terms=[(k2, c2)], jitter=spec.jitter)
+    K = model.gram(spec, eta)
+    assert np.array_equal(K[:R, R:], np.zeros((R, R))) and np.array_equal(K[R:, :R], np.zeros((R, R)))
+    assert np.allclose(K[:R, :R], model.gram(s1, eta[:n1]), rtol=1e-15, atol=0)
+    assert np.allclose(K[R:, R:], model.gram(s2, eta[n1:]), rtol=1e-15, atol=0)
