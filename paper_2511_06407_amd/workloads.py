@@ -224,6 +224,84 @@ def mean_variance(R: int, seed: int = 0, delta: float = 0.01):
     return spec, np.concatenate([eta1, eta2]), np.concatenate([f1, f2])
 
 
+BASIS_GAUSS = 0    # a one-dimensional Gaussian kernel, M sinusoidal features
+BASIS_LINEAR = 1   # a linear kernel, one feature (the covariate itself)
+
+
+@dataclasses.dataclass
+class BasisSpec:
+    """The paper's reduced-rank basis model (Sec. 2.1, Eqs. BMKL,
+    Solin_representation and hpar_prior; features in the appendix on the
+    reduced-rank representation), one latent function (J = 1):
+        f(x_i) = sum_k sum_m a_km phi_km(x_ik) + b,
+        a_km ~ N(0, c_g V_m(sigma_g)) (Gaussian-kernel covariates),
+        a_k  ~ N(0, c_l)              (linear-kernel covariates, phi = x),
+        b ~ N(0, bias_var), c_g, sigma_g, c_l ~ InvGamma(alpha, beta).
+    q = (a in covariate order, b, c_g, sigma_g, c_l): the hyperparameters are
+    sampled on their own scale (positive), as the paper writes them."""
+    X: np.ndarray                     # N x dx covariates
+    y: np.ndarray                     # N labels {0,1} (logit) or targets (Gaussian)
+    kinds: Tuple[int, ...]            # BASIS_GAUSS / BASIS_LINEAR per covariate
+    M: int = 30                       # features per Gaussian-kernel covariate
+    L: float = 8.0                    # domain half-width [-L, L]
+    bias_var: float = 1.0             # Sigma
+    ig_alpha: Tuple[float, float, float] = (2.0, 2.0, 2.0)   # (c_g, sigma_g, c_l)
+    ig_beta: Tuple[float, float, float] = (2.0, 2.0, 2.0)
+    lik: int = LIK_BERNOULLI_LOGIT
+    noise_var: float = 1.0
+    beta: float = 1.0                 # inverse temperature on the likelihood
+
+    def __post_init__(self):
+        self.X = np.ascontiguousarray(np.asarray(self.X, dtype=np.float64))
+        self.y = np.ascontiguousarray(np.asarray(self.y, dtype=np.float64))
+        self.kinds = tuple(int(k) for k in self.kinds)
+        if self.X.ndim != 2 or len(self.kinds) != self.X.shape[1]:
+            raise ValueError("one kernel kind per covariate")
+        if self.lik not in (LIK_BERNOULLI_LOGIT, LIK_GAUSSIAN):
+            raise ValueError("the basis model takes the logit or Gaussian likelihood")
+
+    @property
+    def N(self) -> int:
+        return self.X.shape[0]
+
+    @property
+    def dx(self) -> int:
+        return self.X.shape[1]
+
+    @property
+    def n_features(self) -> int:
+        return sum(self.M if k == BASIS_GAUSS else 1 for k in self.kinds)
+
+    @property
+    def P(self) -> int:
+        return 3
+
+    @property
+    def D(self) -> int:
+        return self.n_features + 1 + 3
+
+
+def basis_logistic(D_in: int, N: int = 500, seed: int = 0, M: int = 30, L: float = 8.0):
+    """The simulated logistic-regression data of Sec. 2.5: x ~ N(0, 1)^D_in;
+    f* = sum_k sum_m a*_km sin(pi m (x_k + L) / 2L) + b* with b* = -0.5,
+    a*_km ~ N(0, c* / m) for 4 <= m <= 16 and 0 otherwise, c* set so that the
+    empirical SD of f* is 1.5; labels 1 with probability sigmoid(f*).  The
+    model: a Gaussian kernel with M features per covariate (d = M D_in + 4),
+    alpha_theta = beta_theta = 2 for every hyperparameter, Sigma = 1."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((N, D_in))
+    m = np.arange(1, M + 1)
+    z = rng.standard_normal((D_in, M)) / np.sqrt(m)
+    z[:, (m < 4) | (m > 16)] = 0.0
+    feats = np.sin(np.pi * m[None, None, :] * (X[:, :, None] + L) / (2.0 * L))   # N x D_in x M
+    g = np.einsum("nkm,km->n", feats, z)
+    c_star = (1.5 / np.std(g)) ** 2
+    f = np.sqrt(c_star) * g - 0.5
+    y = (rng.uniform(size=N) < 1.0 / (1.0 + np.exp(-f))).astype(np.float64)
+    spec = BasisSpec(X=X, y=y, kinds=(BASIS_GAUSS,) * D_in, M=M, L=L)
+    return spec, f
+
+
 @dataclasses.dataclass
 class ChainSettings:
     eps: float
@@ -268,6 +346,11 @@ def workload(name: str, seed: int = 0):
         spec, _, _ = propensity_mkl(1024, seed)
         return spec, ChainSettings(eps=0.001, n_leapfrog=20, n_fixed_point=6,
                                    n_samples=200, n_burnin=67)
+    if name in ("basis_logistic_d34", "basis_logistic_d484"):
+        # the paper's own model and data recipe (Sec. 2.5): C = 100, eps = 1e-3
+        spec, _ = basis_logistic(1 if name.endswith("d34") else 16, seed=seed)
+        return spec, ChainSettings(eps=0.001, n_leapfrog=100, n_fixed_point=6,
+                                   n_samples=9600 - 2400, n_burnin=2400, alpha=1.0)
     if name == "mean_variance_d1029":
         # Example 1 of Sec. 2.1 at R = 512 records: 1024 latent values + 5
         spec, _, _ = mean_variance(512, seed)
