@@ -180,6 +180,38 @@ rmhmc_status rmhmc_model_set_beta(rmhmc_model* m, double beta);
  * ll [device] 1.  Synchronises the stream. */
 rmhmc_status rmhmc_log_likelihood(rmhmc_model* m, const double* q, double* ll, hipStream_t stream);
 
+/* The paper's own model, the reduced-rank basis form of Sec. 2.1 (Eqs. BMKL,
+ * Solin_representation and hpar_prior; features in the appendix on the
+ * reduced-rank representation), one latent function:
+ *   f(x_i) = sum_k sum_m a_km phi_m(x_ik) + b,
+ *   Gaussian-kernel covariate k: phi_m(x) = sin(pi m (x + L) / (2L)),
+ *     m = 1..M, a_km ~ N(0, c_g V_m(sigma_g)),
+ *     V_m(sigma) = sqrt(pi sigma) exp(-pi^2 m^2 sigma / (16 L^2)) (the
+ *     spectral density of exp(-r^2 / sigma) at the m-th frequency);
+ *   linear-kernel covariate k: one feature x_k, a_k ~ N(0, c_l);
+ *   b ~ N(0, bias_var); c_g, sigma_g, c_l ~ InvGamma(ig_alpha[h], ig_beta[h]).
+ * q = (a in covariate order, b, c_g, sigma_g, c_l): D = F + 4 with F the
+ * number of features; the hyperparameters are sampled on their own (positive)
+ * scale, and a trajectory that takes one to zero or below fails (a rejection
+ * in rmhmc_chain).  The likelihood is BERNOULLI_LOGIT or GAUSSIAN, raised to
+ * beta.  Every call below that takes an rmhmc_model works on it
+ * (FP64 only); rmhmc_model_dims reports N = records and P = 3. */
+typedef enum { RMHMC_BASIS_GAUSS = 0, RMHMC_BASIS_LINEAR = 1 } rmhmc_basis_kind;
+typedef struct {
+  int N, dx;                 /* records, covariates                            */
+  const double* X;           /* [host] N x dx, row-major                       */
+  const double* y;           /* [host] N labels {0,1} (logit) or targets       */
+  int lik;                   /* rmhmc_lik: BERNOULLI_LOGIT or GAUSSIAN         */
+  double noise_var;          /* Gaussian likelihood only                       */
+  const int* kinds;          /* [host] dx entries of rmhmc_basis_kind          */
+  int M;                     /* features per Gaussian-kernel covariate (>= 1)  */
+  double L;                  /* half-width of the domain [-L, L] (> 0)         */
+  double bias_var;           /* Sigma, the prior variance of b (> 0)           */
+  double ig_alpha[3], ig_beta[3];  /* InvGamma of (c_g, sigma_g, c_l) (> 0)    */
+  double beta;               /* inverse temperature on the likelihood, >= 0   */
+} rmhmc_basis_desc;
+rmhmc_status rmhmc_basis_model_create(const rmhmc_basis_desc* desc, rmhmc_model** out);
+
 /* U(q) = -ln P(q) (constants included), grad U and the Hessian H of U at q
  * (H is the matrix the softabs map of Sec. 2.2 is applied to).
  *   q [device] D; U [device] 1; gradU [device] D; H [device] D x D, ldh >= D.

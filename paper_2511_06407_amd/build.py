@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "librmhmc.so")
-SOURCES = ["gemm.hip", "linalg.hip", "gp.hip", "eig.hip", "rmhmc.hip"]
+SOURCES = ["gemm.hip", "linalg.hip", "gp.hip", "basis.hip", "eig.hip", "rmhmc.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17",
          # keep the compiler from emitting packed FP32 arithmetic
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

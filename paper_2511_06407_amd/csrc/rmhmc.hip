@@ -27,6 +27,7 @@
 #include <thread>
 #include <vector>
 
+#include "basis.h"
 #include "common.h"
 #include "eig.h"
 #include "gp.h"
@@ -464,6 +465,10 @@ struct Model {
   int N = 0, dx = 0, P = 0, D = 0, Dp = 0;
   int lik = 0;
   int R = 0;            // records of the mean/variance model (two latent functions), else 0
+  // the reduced-rank basis model (q = (a, b, c_g, sigma_g, c_l); N = records)
+  bool basis = false;
+  BasisDev bd;
+  double* bwork = nullptr;   // N x (F + 1) + N
   double noise_var = 1.0, jitter = 1e-6, beta = 1.0, delta = 0.0;
   rmhmc_precision prec = RMHMC_FP64;
   ModelDev md{};
@@ -545,6 +550,21 @@ struct Carve {
 void layout_point(const Model& m, Point& p, Carve& c) {
   const long N = m.N, P = m.P, NN = N * N, Dp = m.Dp;
   const bool mixed = m.prec == RMHMC_MIXED;
+  if (m.basis) {
+    // f in alpha; the latent model's K-derived caches are not used
+    p.q = c.take<double>(m.D);
+    p.alpha = c.take<double>(N);
+    p.lik = c.take<double>((long)LIK_SLOTS * N);
+    p.scal = c.take<double>(8);
+    p.gradU = c.take<double>(m.D);
+    p.H = c.take<double>(Dp * Dp);
+    p.Psi = c.take<double>(Dp * Dp);
+    p.lam = c.take<double>(Dp);
+    p.g = c.take<double>(Dp);
+    p.gp = c.take<double>(Dp);
+    p.vW2 = c.take<double>(m.D);
+    return;
+  }
   p.q = c.take<double>(m.D);
   p.K = c.take<double>(NN);
   p.Kinv = c.take<double>(NN);
@@ -599,6 +619,10 @@ std::unique_ptr<Point> new_point(Model& m) {
   Carve c;
   c.base = p.data;
   layout_point(m, p, c);
+  if (m.basis) {
+    RM_HIP(hipMemset(p.data, 0, p.data_bytes));
+    return pt;
+  }
   const long NN = (long)m.N * m.N;
   // pointer arrays for the Y_lm = A_l A_m batch (the formed pairs l <= m)
   std::vector<const double*> ya, yb;
@@ -651,6 +675,15 @@ void check_flag_nonfinite(Model& m, const double* x, long n, hipStream_t st, con
 // reported at once (reads the Cholesky flag, synchronises the stream);
 // otherwise the flag is folded into *fail on the device.
 void compute_hessian(Model& m, Point& pt, hipStream_t st, int* fail) {
+  if (m.basis) {
+    // no factorisation can fail here: a hyperparameter outside (0, inf)
+    // leaves non-finite values, which the eigensolver reports
+    pt.have_pre = pt.have_vW2 = pt.have_eig = false;
+    basis_hessian(m.bd, m.lik, m.noise_var, m.beta, m.y, pt.q, pt.alpha, pt.lik, pt.H, m.Dp,
+                  pt.gradU, pt.scal, m.bwork, st);
+    (void)fail;
+    return;
+  }
   const int N = m.N, P = m.P;
   const long NN = (long)N * N;
   const double* eta = pt.q + N;
@@ -760,7 +793,7 @@ JacobiResult compute_eig(Model& m, Point& pt, const Point* warm, double alpha, c
 
 // W-independent pieces of v(W) at pt (needs compute_hessian first).
 void compute_precompute(Model& m, Point& pt, hipStream_t st) {
-  if (pt.have_pre) return;
+  if (pt.have_pre || m.basis) return;
   const int N = m.N, P = m.P;
   const long NN = (long)N * N;
   const double* eta = pt.q + N;
@@ -845,6 +878,10 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
 
 // v = tr(W dH/dq_i) for a symmetric W (Dp x Dp, ld Dp).
 void contract(Model& m, Point& pt, const double* W, double* v, hipStream_t st) {
+  if (m.basis) {
+    basis_contract(m.bd, m.beta, pt.q, pt.lik, W, m.Dp, v, m.bwork, st);
+    return;
+  }
   compute_precompute(m, pt, st);
   const int N = m.N, P = m.P, Dp = m.Dp;
   const long NN = (long)N * N;
@@ -1143,6 +1180,92 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   m.tau = pl.alloc<double>(P * m.nyy);
   m.dflag = pl.alloc<int>(1);
   m.hflag = pl.alloc_host<int>(1);
+  m.api_pt_own = new_point(m);
+  m.api_pt = m.api_pt_own.get();
+}
+
+// The reduced-rank basis model (Sec. 2.1; features in the appendix on the
+// reduced-rank representation): features on the device, FP64 throughout.
+void build_basis_model(Model& m, const rmhmc_basis_desc* d) {
+  RM_REQUIRE(d != nullptr, "basis descriptor is NULL");
+  RM_REQUIRE(d->N >= 1 && d->dx >= 1 && d->X && d->y && d->kinds, "need N >= 1, dx >= 1, X, y, kinds");
+  RM_REQUIRE(d->lik == RMHMC_LIK_BERNOULLI_LOGIT || d->lik == RMHMC_LIK_GAUSSIAN,
+             "the basis model takes the logit or Gaussian likelihood");
+  if (d->lik == RMHMC_LIK_GAUSSIAN) RM_REQUIRE(d->noise_var > 0.0, "noise_var must be positive");
+  RM_REQUIRE(d->M >= 1 && d->L > 0.0 && d->bias_var > 0.0, "need M >= 1, L > 0, bias_var > 0");
+  RM_REQUIRE(d->beta >= 0.0 && std::isfinite(d->beta), "beta must be finite and >= 0");
+  for (int h = 0; h < 3; ++h)
+    RM_REQUIRE(d->ig_alpha[h] > 0.0 && d->ig_beta[h] > 0.0, "inverse-Gamma parameters must be positive");
+  std::vector<int> col, freq, kind;
+  for (int c = 0; c < d->dx; ++c) {
+    RM_REQUIRE(d->kinds[c] == RMHMC_BASIS_GAUSS || d->kinds[c] == RMHMC_BASIS_LINEAR,
+               "unknown basis kernel kind");
+    const int nf = d->kinds[c] == RMHMC_BASIS_GAUSS ? d->M : 1;
+    for (int mm = 1; mm <= nf; ++mm) {
+      col.push_back(c);
+      freq.push_back(d->kinds[c] == RMHMC_BASIS_GAUSS ? mm : 0);
+      kind.push_back(d->kinds[c] == RMHMC_BASIS_GAUSS ? 0 : 1);
+    }
+  }
+  const int F = (int)col.size();
+  for (long i = 0; i < (long)d->N * d->dx; ++i)
+    RM_REQUIRE(std::isfinite(d->X[i]), "X contains a non-finite value");
+  for (int i = 0; i < d->N; ++i) RM_REQUIRE(std::isfinite(d->y[i]), "y contains a non-finite value");
+  m.basis = true;
+  m.N = d->N; m.dx = d->dx; m.lik = d->lik; m.noise_var = d->noise_var;
+  m.beta = d->beta; m.prec = RMHMC_FP64;
+  m.P = 3;
+  m.D = F + 4;
+  m.Dp = eig_padded_dim(m.D);
+  BasisDev& bd = m.bd;
+  bd.N = m.N; bd.F = F; bd.Fa = F + 1;
+  bd.bias_var = d->bias_var;
+  for (int h = 0; h < 3; ++h) {
+    bd.ig_a[h] = d->ig_alpha[h];
+    bd.ig_b[h] = d->ig_beta[h];
+  }
+  Pool& pl = m.pool;
+  const long N = m.N, Dp = m.Dp;
+  std::vector<double> Xc((size_t)m.dx * m.N), kap(F);
+  for (int i = 0; i < m.N; ++i)
+    for (int c = 0; c < m.dx; ++c) Xc[(size_t)c * m.N + i] = d->X[(size_t)i * m.dx + c];
+  for (int j = 0; j < F; ++j)
+    kap[j] = kind[j] == 0 ? M_PI * M_PI * freq[j] * freq[j] / (16.0 * d->L * d->L) : 0.0;
+  double* Xd = pl.alloc<double>(Xc.size());
+  int* cold = pl.alloc<int>(F);
+  int* freqd = pl.alloc<int>(F);
+  bd.kind = pl.alloc<int>(F);
+  bd.kappa = pl.alloc<double>(F);
+  bd.Phi = pl.alloc<double>(N * bd.Fa);
+  RM_HIP(hipMemcpy(Xd, Xc.data(), Xc.size() * sizeof(double), hipMemcpyHostToDevice));
+  RM_HIP(hipMemcpy(cold, col.data(), F * sizeof(int), hipMemcpyHostToDevice));
+  RM_HIP(hipMemcpy(freqd, freq.data(), F * sizeof(int), hipMemcpyHostToDevice));
+  RM_HIP(hipMemcpy(bd.kind, kind.data(), F * sizeof(int), hipMemcpyHostToDevice));
+  RM_HIP(hipMemcpy(bd.kappa, kap.data(), F * sizeof(double), hipMemcpyHostToDevice));
+  basis_features(bd, Xd, cold, freqd, d->L, nullptr);
+  m.y = pl.alloc<double>(N);
+  RM_HIP(hipMemcpy(m.y, d->y, N * sizeof(double), hipMemcpyHostToDevice));
+  m.bwork = pl.alloc<double>(N * bd.Fa + N + 64);
+  m.eig.M = pl.alloc<double>(Dp * Dp);
+  m.eig.M2 = pl.alloc<double>(Dp * Dp);
+  m.eig.Psi = pl.alloc<double>(Dp * Dp);
+  m.eig.V = pl.alloc<double>(eig_rotation_doubles(Dp));
+  m.eig.part = pl.alloc<double>(eig_part_doubles(Dp));
+  m.eig.ctrl = pl.alloc<double>(EIG_CTRL_DOUBLES);
+  m.eig.ctrl_host = pl.alloc_host<double>(EIG_CTRL_DOUBLES);
+  m.gsplit = pl.alloc<double>((long)GSPLIT_MAX * Dp * Dp + 64);
+  m.W = pl.alloc<double>(Dp * Dp);
+  m.Wt1 = pl.alloc<double>(Dp * Dp);
+  m.Wt2 = pl.alloc<double>(Dp * Dp);
+  m.vc = pl.alloc<double>(Dp);
+  m.vb = pl.alloc<double>(Dp);
+  m.vtmp = pl.alloc<double>(Dp);
+  m.vtmp2 = pl.alloc<double>(Dp);
+  m.v1 = pl.alloc<double>(Dp);
+  m.gvwork = pl.alloc<double>(64L * Dp);
+  m.dflag = pl.alloc<int>(1);
+  m.hflag = pl.alloc_host<int>(1);
+  RM_HIP(hipDeviceSynchronize());
   m.api_pt_own = new_point(m);
   m.api_pt = m.api_pt_own.get();
 }
@@ -1906,6 +2029,20 @@ rmhmc_status rmhmc_model_create(const rmhmc_model_desc* desc, rmhmc_precision pr
   });
 }
 
+rmhmc_status rmhmc_basis_model_create(const rmhmc_basis_desc* desc, rmhmc_model** out) {
+  return guard([&] {
+    RM_REQUIRE(out != nullptr, "out is NULL");
+    auto m = std::make_unique<rmhmc_model>();
+    Model& md = m->impl;
+    build_basis_model(md, desc);
+    md.chain_state = make_state(md, 1.0);
+    md.device_bytes = md.pool.bytes + md.api_pt->meta.bytes + md.chain_state->pool.bytes;
+    for (int i = 0; i < 3; ++i) md.device_bytes += md.chain_state->pts[i]->meta.bytes;
+    RM_HIP(hipDeviceSynchronize());
+    *out = m.release();
+  });
+}
+
 rmhmc_status rmhmc_model_dims(const rmhmc_model* m, int* N, int* P, int* D) {
   return guard([&] {
     RM_REQUIRE(m != nullptr, "model is NULL");
@@ -1940,7 +2077,12 @@ rmhmc_status rmhmc_log_likelihood(rmhmc_model* mh, const double* q, double* ll, 
     std::lock_guard<std::mutex> lk(m.busy);
     RM_REQUIRE(!m.in_batch, "the model is admitted to a batch");
     Point& pt = *m.api_pt;
-    lik_derivs(m.N, m.lik, m.noise_var, m.delta, q, m.y, pt.lik, st);   // l_i = -ln P(X_i | f_i)
+    const double* f = q;
+    if (m.basis) {   // f = Phi (a, b)
+      gemv(m.N, m.bd.Fa, 1.0, m.bd.Phi, m.N, false, 0, q, 0, 0.0, pt.alpha, 0, 1, st);
+      f = pt.alpha;
+    }
+    lik_derivs(m.N, m.lik, m.noise_var, m.delta, f, m.y, pt.lik, st);   // l_i = -ln P(X_i | f_i)
     vsum(m.N, pt.lik, ll, st);
     axpby(1, 0.0, ll, -1.0, ll, st);
     RM_HIP(hipStreamSynchronize(st));

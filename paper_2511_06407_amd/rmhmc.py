@@ -42,7 +42,7 @@ EXPORTED = ["rmhmc_model_create", "rmhmc_model_dims", "rmhmc_model_destroy", "rm
             "rmhmc_softabs_eig_reserve", "rmhmc_chain_randoms", "rmhmc_softabs_eig_noalloc",
             "rmhmc_batch_create", "rmhmc_batch_admit", "rmhmc_batch_step", "rmhmc_batch_sync",
             "rmhmc_batch_retire", "rmhmc_batch_destroy", "rmhmc_model_set_beta",
-            "rmhmc_log_likelihood"]
+            "rmhmc_log_likelihood", "rmhmc_basis_model_create"]
 
 TIMER_KINDS = {"gemm_f64": 0, "gemm_f32": 1, "jacobi_round": 2, "jacobi_round_static": 3, "kd_wsum": 4,
                "kd_matvec": 5, "potrf_diag": 6}
@@ -59,6 +59,14 @@ class ModelDesc(C.Structure):
                 ("nterms", C.c_int), ("terms", C.POINTER(KernelTerm)), ("jitter", C.c_double),
                 ("beta", C.c_double), ("n_fns", C.c_int), ("fn_col", C.c_int),
                 ("delta", C.c_double)]
+
+
+class BasisDesc(C.Structure):
+    _fields_ = [("N", C.c_int), ("dx", C.c_int), ("X", C.POINTER(C.c_double)),
+                ("y", C.POINTER(C.c_double)), ("lik", C.c_int), ("noise_var", C.c_double),
+                ("kinds", C.POINTER(C.c_int)), ("M", C.c_int), ("L", C.c_double),
+                ("bias_var", C.c_double), ("ig_alpha", C.c_double * 3), ("ig_beta", C.c_double * 3),
+                ("beta", C.c_double)]
 
 
 class ChainCfg(C.Structure):
@@ -279,6 +287,29 @@ class Model:
         _check(_lib.rmhmc_chain(self._h, C.byref(cfg), _f64(q0), _f64(samples), _f64(logpost),
                                 _ptr(acc, torch.int32), C.byref(stats), _stream(stream)))
         return samples[:kept], logpost[:kept], acc[:kept], stats
+
+
+class BasisModel(Model):
+    """The paper's reduced-rank basis model resident on the device
+    (rmhmc_basis_model_create); every Model method applies."""
+
+    def __init__(self, spec: wl.BasisSpec):
+        X = np.ascontiguousarray(spec.X, dtype=np.float64)
+        y = np.ascontiguousarray(spec.y, dtype=np.float64)
+        kinds = (C.c_int * spec.dx)(*spec.kinds)
+        self._keep = (X, y, kinds)
+        desc = BasisDesc(spec.N, spec.dx, X.ctypes.data_as(C.POINTER(C.c_double)),
+                         y.ctypes.data_as(C.POINTER(C.c_double)), spec.lik, spec.noise_var,
+                         kinds, spec.M, spec.L, spec.bias_var, (C.c_double * 3)(*spec.ig_alpha),
+                         (C.c_double * 3)(*spec.ig_beta), spec.beta)
+        h = C.c_void_p()
+        _check(_lib.rmhmc_basis_model_create(C.byref(desc), C.byref(h)))
+        self._h = h
+        N, P, D = C.c_int(), C.c_int(), C.c_int()
+        _check(_lib.rmhmc_model_dims(h, C.byref(N), C.byref(P), C.byref(D)))
+        self.N, self.P, self.D = N.value, P.value, D.value
+        self.spec = spec
+        self.precision = FP64
 
 
 def chain_cfg(model, eps, n_leapfrog, n_fixed_point, n_moves, n_burnin=0, seed=0, stream_id=0,

@@ -269,6 +269,10 @@ class BasisSpec:
         return self.X.shape[1]
 
     @property
+    def n_records(self) -> int:
+        return self.N
+
+    @property
     def n_features(self) -> int:
         return sum(self.M if k == BASIS_GAUSS else 1 for k in self.kinds)
 

@@ -135,3 +135,15 @@ def ref_point(spec, q, p, alpha):
     st = oham.State(oham.GPTarget(spec), q, alpha)
     return (U, g, H, oham.grad_q(st, p), oham.grad_p(st, p), oham.hamiltonian(st, p),
             {"Psi": st.eig["Psi"], "lam": st.eig["lam"]})
+
+
+def ref_glf_basis(spec, q, p, eps, K, steps):
+    """As ref_glf for the reduced-rank basis model with g = sqrt(1 + lambda^2)."""
+    from oracle import basis, hamiltonian as oham, softabs
+    from oracle.integrator import glf_step
+    st = oham.State(basis.BasisTarget(spec), q, softabs.SqrtMap(1.0))
+    out = []
+    for _ in range(steps):
+        st, p = glf_step(st, p, eps, K)
+        out.append((st.q.copy(), p.copy(), oham.hamiltonian(st, p)))
+    return out
