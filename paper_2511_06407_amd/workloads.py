@@ -314,6 +314,7 @@ class ChainSettings:
     n_samples: int        # kept moves
     n_burnin: int         # A0
     alpha: float = 1e6
+    sqrt_map: bool = False   # softabs g = sqrt(kappa^2 + lambda^2), kappa = 1/alpha
 
     @property
     def n_moves(self) -> int:
@@ -336,6 +337,15 @@ class ChainSettings:
 EPS_STATED = {"gp_logistic_d34": 0.1, "gp_logistic_ard_d261": 0.05, "propensity_mkl_d1038": 0.05}
 
 
+def start_point(spec):
+    """The chains' start: q = 0 for the latent models; a = 0, b = 0 and every
+    hyperparameter 1 for the basis model (as the paper starts, Sec. 2.5)."""
+    q = np.zeros(spec.D)
+    if isinstance(spec, BasisSpec):
+        q[-3:] = 1.0
+    return q
+
+
 def workload(name: str, seed: int = 0):
     """Return (spec, settings) for a named workload."""
     if name == "gp_logistic_d34":
@@ -354,7 +364,8 @@ def workload(name: str, seed: int = 0):
         # the paper's own model and data recipe (Sec. 2.5): C = 100, eps = 1e-3
         spec, _ = basis_logistic(1 if name.endswith("d34") else 16, seed=seed)
         return spec, ChainSettings(eps=0.001, n_leapfrog=100, n_fixed_point=6,
-                                   n_samples=9600 - 2400, n_burnin=2400, alpha=1.0)
+                                   n_samples=9600 - 2400, n_burnin=2400, alpha=1.0,
+                                   sqrt_map=True)
     if name == "mean_variance_d1029":
         # Example 1 of Sec. 2.1 at R = 512 records: 1024 latent values + 5
         spec, _, _ = mean_variance(512, seed)
