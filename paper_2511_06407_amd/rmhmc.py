@@ -436,11 +436,12 @@ class Pool:
         self.n_workers = n_workers
 
     def submit(self, model, q0, eps, n_leapfrog, n_fixed_point, n_moves, n_burnin=0, seed=0,
-               stream_id=0, alpha=1e6, zeta=0.0, max_sweeps=0, reorth_every=0):
+               stream_id=0, alpha=1e6, zeta=0.0, max_sweeps=0, reorth_every=0,
+               softabs=SOFTABS_COTH):
         torch = _torch()
         job = ChainJob(model, q0, chain_cfg(model, eps, n_leapfrog, n_fixed_point, n_moves,
                                             n_burnin, seed, stream_id, alpha, zeta, max_sweeps,
-                                            reorth_every))
+                                            reorth_every, softabs))
         t = C.c_longlong()
         _check(_lib.rmhmc_pool_submit(self._h, model._h, C.byref(job.cfg), _f64(q0),
                                       _f64(job.samples), _f64(job.logpost),
@@ -489,11 +490,12 @@ class Batch:
         self.jobs = {}
 
     def admit(self, model, q0, eps, n_leapfrog, n_fixed_point, n_moves, n_burnin=0, seed=0,
-              stream_id=0, alpha=1e6, zeta=0.0, max_sweeps=0, reorth_every=0):
+              stream_id=0, alpha=1e6, zeta=0.0, max_sweeps=0, reorth_every=0,
+              softabs=SOFTABS_COTH):
         torch = _torch()
         job = ChainJob(model, q0, chain_cfg(model, eps, n_leapfrog, n_fixed_point, n_moves,
                                             n_burnin, seed, stream_id, alpha, zeta, max_sweeps,
-                                            reorth_every))
+                                            reorth_every, softabs))
         slot = C.c_int()
         _check(_lib.rmhmc_batch_admit(self._h, model._h, C.byref(job.cfg), _f64(q0),
                                       _f64(job.samples), _f64(job.logpost),
