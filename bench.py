@@ -91,12 +91,15 @@ def parse():
 def run_tempered_mode(args):
     from paper_2511_06407_amd.tempered import run_tempered
     log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)  # noqa: E731
+    from paper_2511_06407_amd import rmhmc
     out = run_tempered(n_chains=args.chains, n_moves=args.moves, n_leapfrog=10, n_fixed_point=6,
                        eps=0.01, n_workers=args.workers, seed=args.seed, log=log,
-                       engine=args.engine)
+                       engine=args.engine,
+                       precision=rmhmc.MIXED if args.precision == "mixed" else rmhmc.FP64)
     dims = [c["D"] for c in out["chains"]]
     return {"metric": "tempered chains: aggregate chain-leapfrogs/s", "value": out["chain_leapfrogs_per_s"],
-            "unit": "chain-leapfrogs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+            "unit": "chain-leapfrogs/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f64" if args.precision == "fp64" else "f32+f64",
             "data": "synthetic", "wall_s": out["wall_s"], "setup_s": out["setup_s"],
             "config": {"workload": f"{args.chains} power-posterior chains, beta_k=(k/{args.chains - 1})^5, "
                                    "D from {66,130,258,514}", "moves": args.moves, "n_leapfrog": 10,
@@ -107,15 +110,18 @@ def run_tempered_mode(args):
             "failures": sum(c["failures"] for c in out["chains"])}
 
 
-def serving_block(rate, window_s, moves_scale, workers, hbm_gb, seed):
+def serving_block(rate, window_s, moves_scale, workers, hbm_gb, seed, precision="fp64"):
     """Requests of the serving mix (D log-uniform on [34, 1038], GP-logistic
     or multiple-kernel) arriving as a Poisson stream, with the move counts
     scaled by moves_scale; latencies and the backlog as measured."""
     from paper_2511_06407_amd.serve_bench import run_rate
     lo = max(1, int(round(200 * moves_scale)))
     hi = max(lo, int(round(2000 * moves_scale)))
-    out = run_rate(rate, window_s, (lo, hi), workers, 32, hbm_gb, seed)
+    from paper_2511_06407_amd import rmhmc
+    out = run_rate(rate, window_s, (lo, hi), workers, 32, hbm_gb, seed,
+                   precision=rmhmc.MIXED if precision == "mixed" else rmhmc.FP64)
     out["moves_scale"] = moves_scale
+    out["precision"] = precision
     out["note"] = ("requests of the serving mix with 1/{:g} of its move counts; a sustainable "
                    "rate r here is r x {:g} requests/s at full length".format(1 / moves_scale,
                                                                               moves_scale))
@@ -124,9 +130,10 @@ def serving_block(rate, window_s, moves_scale, workers, hbm_gb, seed):
 
 def run_serve_mode(args):
     summ = serving_block(args.rate, args.duration, args.moves_scale, args.workers, args.hbm_gb,
-                         args.seed)
+                         args.seed, args.precision)
     return {"metric": "serving: p50/p99 request latency", "value": summ["p99_latency_s"],
-            "unit": "s (p99 latency)", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
+            "unit": "s (p99 latency)", "n_gpus": 1, "higher_is_better": False,
+            "dtype": "f64" if args.precision == "fp64" else "f32+f64",
             "data": "synthetic", **summ,
             "config": {"workload": "Poisson arrivals, D log-uniform in [34,1038], GP-logistic or "
                                    "multiple-kernel", "rate_per_s": args.rate,
@@ -411,7 +418,7 @@ def main():
         model.close()
         log(f"serving: {args.rate} requests/s for {args.duration} s")
         out["serving"] = serving_block(args.rate, args.duration, args.moves_scale, args.workers,
-                                       args.hbm_gb, args.seed)
+                                       args.hbm_gb, args.seed, args.precision)
         log(f"serving: p50 {out['serving']['p50_latency_s']:.2f} s "
             f"p99 {out['serving']['p99_latency_s']:.2f} s")
     if args.workload in PAPER_CONTEXT:

@@ -27,11 +27,12 @@ import numpy as np
 from . import serving as sv
 
 
-def run_rate(rate, window_s, moves, n_workers, n_slots, budget_gb, seed, n_leapfrog=10):
+def run_rate(rate, window_s, moves, n_workers, n_slots, budget_gb, seed, n_leapfrog=10,
+             precision=None):
     reqs = sv.make_requests(rate, window_s, moves=moves, seed=seed)
     if not reqs:
         return None
-    ex = sv.PoolExecutor(n_workers=n_workers, n_leapfrog=n_leapfrog)
+    ex = sv.PoolExecutor(n_workers=n_workers, n_leapfrog=n_leapfrog, precision=precision)
     sch = sv.Scheduler(ex, hbm_budget_bytes=budget_gb * 1e9, n_slots=n_slots)
     t0 = time.perf_counter()
     sch.run(reqs)

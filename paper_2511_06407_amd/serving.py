@@ -182,16 +182,17 @@ class PoolExecutor:
     """Runs requests on the HIP worker pool; the model and its chain state
     live on the device from admission to release."""
 
-    def __init__(self, n_workers=4, n_leapfrog=10, n_fixed_point=6, alpha=1e6):
+    def __init__(self, n_workers=4, n_leapfrog=10, n_fixed_point=6, alpha=1e6, precision=None):
         from . import rmhmc
         self.rm = rmhmc
         self.pool = rmhmc.Pool(n_workers)
         self.n_leapfrog, self.K, self.alpha = n_leapfrog, n_fixed_point, alpha
+        self.precision = rmhmc.FP64 if precision is None else precision
 
     def start(self, req: Request):
         import torch
         spec, eps = request_spec(req)
-        model = self.rm.Model(spec)
+        model = self.rm.Model(spec, self.precision)
         q0 = torch.zeros(spec.D, dtype=torch.float64, device="cuda")
         job = self.pool.submit(model, q0, eps, self.n_leapfrog, self.K, req.n_moves,
                                seed=req.seed, stream_id=req.rid, alpha=self.alpha)

@@ -36,7 +36,8 @@ def trapezoid_log_evidence(betas, mean_loglik):
 
 
 def run_tempered(n_chains=64, n_moves=20, n_leapfrog=10, n_fixed_point=6, eps=0.01,
-                 alpha=1e6, n_workers=8, seed=0, dims=None, log=None, engine="graph"):
+                 alpha=1e6, n_workers=8, seed=0, dims=None, log=None, engine="graph",
+                 precision=None):
     """Run the ladder; returns per-chain results and throughput.  The timed
     region is the moves themselves (set-up, tuning and capture excluded)."""
     import torch
@@ -47,7 +48,8 @@ def run_tempered(n_chains=64, n_moves=20, n_leapfrog=10, n_fixed_point=6, eps=0.
         base, _, _ = wl.gp_logistic_2d(dims - 2, seed)
         specs = [dataclasses.replace(base, beta=float(b)) for b in betas]
         drawn_dims = np.full(n_chains, dims)
-    models = [rmhmc.Model(s) for s in specs]
+    prec = rmhmc.FP64 if precision is None else precision
+    models = [rmhmc.Model(s, prec) for s in specs]
     dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")  # noqa
     inputs = [dev(np.zeros(s.D)) for s in specs]
     # largest chains first: they bound the makespan
