@@ -56,9 +56,11 @@ struct JacobiResult {
 // (fail may be null); dstats[0] += 1, dstats[1] += sweeps (may be null).
 // gfloor: the smallest value of the softabs map (1 / alpha), the scale below
 // which an eigenvalue's size no longer matters to G^-1.
+// zeta_s: the tolerance of the scaled test of the metric stopping rule
+// (<= 0: eig_stop_zeta_scaled()).
 JacobiResult jacobi_eig(int D, EigWork& w, double zeta, double gfloor, int max_sweeps,
                         int max_inner, int blind, bool host_check, int* fail, double* dstats,
-                        hipStream_t st);
+                        hipStream_t st, double zeta_s = -1.0);
 // Rayleigh quotients lam_i = psi_i' H psi_i of the converged basis against the
 // original H (D x D, ldh), written to diag(w.M); Z is Dp x Dp scratch.
 // One Newton-Schulz step Psi <- Psi (3I - Psi'Psi) / 2 on the D x D block of

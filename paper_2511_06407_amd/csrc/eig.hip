@@ -952,7 +952,8 @@ double eig_stop_zeta_scaled() { return 1e-12; }
 
 JacobiResult jacobi_eig(int D, EigWork& w, double zeta, double gfloor, int max_sweeps,
                         int max_inner, int blind, bool host_check, int* fail, double* dstats,
-                        hipStream_t st) {
+                        hipStream_t st, double zeta_s) {
+  if (!(zeta_s > 0.0)) zeta_s = eig_stop_zeta_scaled();
   // Input: w.M (Dp x Dp symmetric, padded) and w.Psi (Dp x Dp, padded with identity).
   const int Dp = eig_padded_dim(D);
   const int nb = Dp / JHB, ns = nb / 2;
@@ -970,7 +971,7 @@ JacobiResult jacobi_eig(int D, EigWork& w, double zeta, double gfloor, int max_s
                        w.part, gfloor, (const double*)w.ctrl);
     RM_CHECK_LAUNCH();
     hipLaunchKernelGGL(offnorm_finish_kernel, dim3(1), dim3(64), 0, st, nparts,
-                       (const double*)w.part, zeta, eig_stop_zeta_scaled(), eig_stop_rule(),
+                       (const double*)w.part, zeta, zeta_s, eig_stop_rule(),
                        w.ctrl, first, cur);
     RM_CHECK_LAUNCH();
   };
