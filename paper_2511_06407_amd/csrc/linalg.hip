@@ -269,29 +269,20 @@ __global__ __launch_bounds__(256) void trsm_panel_kernel(int n, int k0, int bw, 
 }
 
 // ---------------------------------------------------------------- Cholesky
-// Factor one CB x CB diagonal block and invert its triangle in one workgroup.
-//
-// Factorisation (right-looking, unscaled columns): thread (row i = lane,
-// wave g) keeps S[i][k] for k = g + 4m in registers.  At step j the wave
-// owning column j publishes it to LDS (double-buffered, one barrier per
-// column) and every thread applies S_ik -= (S_ij / d_j) S_kj to its k > j.
-// Then L_ij = S_ij / sqrt(d_j), L_jj = sqrt(d_j).  Padding rows/columns of a
-// partial block start as the identity, so they factor trivially.
-//
-// Inverse: wave 0, one lane per column c, right-looking forward
-// substitution: once X[r][c] is final (scaled by 1/L[r][r]) it is removed
-// from every later row, a[i] -= L[i][r] X[r][c], so the updates of a step are
-// independent of each other.  a stays in registers; L is read from LDS at
-// the same address in every lane.
+// Factor one CB x CB diagonal block in one workgroup (right-looking,
+// unscaled columns): thread (row i = lane, wave g) keeps S[i][k] for
+// k = g + 4m in registers.  At step j the wave owning column j publishes it
+// to LDS (double-buffered, one barrier per column) and every thread applies
+// S_ik -= (S_ij / d_j) S_kj to its k > j.  Then L_ij = S_ij / sqrt(d_j),
+// L_jj = sqrt(d_j).  Padding rows/columns of a partial block start as the
+// identity, so they factor trivially.  The inverse of the triangle is not
+// needed until the factorisation is complete and is formed afterwards for
+// every diagonal block at once (trtri_diag_kernel), off this chain.
 __global__ __launch_bounds__(256) void potrf_diag_kernel(int n, int k0, double* L, long ldl,
-                                                         double* Linv, double* diagLogs,
-                                                         int* info) {
+                                                         double* diagLogs, int* info) {
   constexpr int NM = CB / 4;
   __shared__ double col[2][CB];
   __shared__ double dg[CB];
-  __shared__ double Ls[CB][CB + 1];
-  __shared__ double Xs[CB][CB + 1];
-  __shared__ double rl[CB];   // 1 / L[k][k]
   const int w = min(CB, n - k0);
   const int tid = threadIdx.x;
   const int i = tid & (CB - 1);
@@ -321,10 +312,36 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int n, int k0, double* 
 #pragma unroll
   for (int m = 0; m < NM; ++m) {
     const int k = g + 4 * m;
-    const double dk = dg[k];
-    Ls[i][k] = i > k ? sv[m] * rsqrt(dk) : (i == k ? sqrt(dk) : 0.0);
+    if (i < w && k < w) {
+      const double dk = dg[k];
+      L[(k0 + i) + (long)(k0 + k) * ldl] = i > k ? sv[m] * rsqrt(dk) : (i == k ? sqrt(dk) : 0.0);
+    }
   }
-  if (tid < CB) rl[tid] = rsqrt(dg[tid]);
+  if (tid < w) diagLogs[k0 + tid] = 0.5 * log(dg[tid]);
+  if (tid == 0 && bad) *info = k0 + 1;
+}
+
+// Inverse of every diagonal block's triangle (one workgroup per block):
+// wave 0, one lane per column c, right-looking forward substitution: once
+// X[r][c] is final (scaled by 1/L[r][r]) it is removed from every later row,
+// a[i] -= L[i][r] X[r][c], so the updates of a step are independent of each
+// other.  a stays in registers; L is read from LDS at the same address in
+// every lane.
+__global__ __launch_bounds__(256) void trtri_diag_kernel(int n, const double* __restrict__ L,
+                                                         long ldl, double* __restrict__ Linv) {
+  __shared__ double Ls[CB][CB + 1];
+  __shared__ double Xs[CB][CB + 1];
+  __shared__ double rl[CB];   // 1 / L[k][k]
+  const int k0 = blockIdx.x * CB;
+  const int w = min(CB, n - k0);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int r = e % CB, c = e / CB;
+    Ls[r][c] = (r < w && c < w) ? (r >= c ? L[(k0 + r) + (long)(k0 + c) * ldl] : 0.0)
+                                : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (tid < CB) rl[tid] = 1.0 / Ls[tid][tid];
   __syncthreads();
   if (tid < CB) {
     const int c = tid;
@@ -343,13 +360,8 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int n, int k0, double* 
   __syncthreads();
   for (int e = tid; e < CB * CB; e += 256) {
     const int r = e % CB, c = e / CB;
-    if (r < w && c < w) {
-      L[(k0 + r) + (long)(k0 + c) * ldl] = Ls[r][c];
-      Linv[(k0 + r) + (long)(k0 + c) * ldl] = Xs[r][c];
-    }
+    if (r < w && c < w) Linv[(k0 + r) + (long)(k0 + c) * ldl] = Xs[r][c];
   }
-  if (tid < w) diagLogs[k0 + tid] = log(Ls[tid][tid]);
-  if (tid == 0 && bad) *info = k0 + 1;
 }
 
 __global__ void zero_upper_kernel(int n, double* A, long lda) {
@@ -470,7 +482,7 @@ void chol_inverse(int n, const double* K, double* Kinv, double* logdet, CholWork
   const int nb = cdiv(n, CB);
   for (int kb = 0; kb < nb; ++kb) {
     const int k0 = kb * CB, bw = std::min(CB, n - k0), r0 = k0 + bw, rm = n - r0;
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, n, k0, w.L, (long)n, w.Linv,
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, n, k0, w.L, (long)n,
                        w.diagLogs, w.info);
     RM_CHECK_LAUNCH();
     if (rm <= 0) break;
@@ -487,6 +499,9 @@ void chol_inverse(int n, const double* K, double* Kinv, double* logdet, CholWork
     gemm(t, st);
   }
   hipLaunchKernelGGL(zero_upper_kernel, dim3(cdiv(nn, 256)), dim3(256), 0, st, n, w.L, (long)n);
+  RM_CHECK_LAUNCH();
+  hipLaunchKernelGGL(trtri_diag_kernel, dim3(nb), dim3(256), 0, st, n, (const double*)w.L, (long)n,
+                     w.Linv);
   RM_CHECK_LAUNCH();
   // Linv block rows: Linv[i, :i] = -Linv_ii (L[i, :i] Linv[:i, :i])
   for (int ib = 1; ib < nb; ++ib) {
