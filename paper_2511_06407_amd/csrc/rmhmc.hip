@@ -933,7 +933,7 @@ void compute_vW2(Model& m, Point& pt, hipStream_t st) {
   g.A = m.Wt1; g.lda = Dp;
   g.B = pt.Psi; g.ldb = Dp; g.tB = true;
   g.C = m.W; g.ldc = Dp;
-  gemm(g, st);
+  gemm_splitk(g, m.gsplit, m.gsplit_layers, st);
   contract(m, pt, m.W, pt.vW2, st);
   pt.have_vW2 = true;
 }
@@ -960,18 +960,20 @@ void grad_q(Model& m, Point& pt, const double* p, double alpha, int kind, double
   metric_vectors(m, pt, p, dHdp, ham, st);
   fill(m.W, (long)Dp * Dp, 0.0, st);
   t_bb(D, pt.lam, m.vb, alpha, kind, m.Wt1, Dp, st);       // T o b b'
+  // the D x D products leave about one wave per SIMD with 64 x 64 tiles:
+  // their k range is split over the model's layers, as for the warm start
   Gemm<double> g;                                            // Wt2 = (T o bb') Psi'
   g.m = D; g.n = D; g.k = D;
   g.A = m.Wt1; g.lda = Dp;
   g.B = pt.Psi; g.ldb = Dp; g.tB = true;
   g.C = m.Wt2; g.ldc = Dp;
-  gemm(g, st);
+  gemm_splitk(g, m.gsplit, m.gsplit_layers, st);
   Gemm<double> h;                                            // W1 = Psi Wt2
   h.m = D; h.n = D; h.k = D;
   h.A = pt.Psi; h.lda = Dp;
   h.B = m.Wt2; h.ldb = Dp;
   h.C = m.W; h.ldc = Dp;
-  gemm(h, st);
+  gemm_splitk(h, m.gsplit, m.gsplit_layers, st);
   contract(m, pt, m.W, m.v1, st);
   lincomb3(D, pt.gradU, 0.5, pt.vW2, -0.5, m.v1, dHdq, st);
 }
