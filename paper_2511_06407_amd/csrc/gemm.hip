@@ -14,7 +14,7 @@
 namespace rmhmc {
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, PADL = 4;
+constexpr int BK = 16, PADL = 4;
 
 template <typename T> struct Mfma;
 // Accumulator layout of a 16x16 output tile: lane l, register r holds
@@ -55,9 +55,17 @@ struct Params {
   T* part;          // split-K partials: part[kc * m * n + i + j * m]
 };
 
-template <typename T, bool TA, bool TB>
+// BT: the output tile (BT x BT per workgroup, a BT/2 x BT/2 quadrant per
+// wave = (BT/32)^2 MFMA tiles).  BT = 128 halves the operand traffic per
+// flop of BT = 64 and doubles the MFMAs per LDS read; it needs about twice
+// the registers and LDS, so it serves large outputs, where the grid still
+// fills the chip.
+template <typename T, bool TA, bool TB, int BT>
 __global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
   typedef typename Mfma<T>::v4 v4;
+  constexpr int TW = BT / 32;            // MFMA tiles per wave and dimension
+  constexpr int LPT = BT * BK / 256;     // operand elements a thread stages per stage
+  constexpr int LG = BT == 64 ? 6 : 7;   // log2(BT)
   const int bz = blockIdx.z;
   const int batch = bz / p.ksplit, kc = bz % p.ksplit;
   const T* __restrict__ A = p.Ap ? p.Ap[batch] : p.A + (long)batch * p.sA;
@@ -82,29 +90,38 @@ __global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
       by = (j / 4) * cw + k / rw;
     }
   }
-  const int m0 = bx * BM, n0 = by * BN;
+  const int m0 = bx * BT, n0 = by * BT;
   const int M = p.m, N = p.n;
   const long lda = p.lda, ldb = p.ldb;
 
-  __shared__ T As[2][BK][BM + PADL];
-  __shared__ T Bs[2][BK][BN + PADL];
+  __shared__ T As[2][BK][BT + PADL];
+  __shared__ T Bs[2][BK][BT + PADL];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
 
-  v4 acc[2][2];
+  v4 acc[TW][TW];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TW; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
+    for (int b = 0; b < TW; ++b) acc[a][b] = v4{0, 0, 0, 0};
 
-  T ra[4], rb[4];
+  // staging map: k-major operands (A', B) by 16-long k columns, the others
+  // by BT-long m / n rows, LPT elements a thread
+  auto mapA = [&](int r, int& ml, int& kl) {
+    if (!TA) { ml = tid & (BT - 1); kl = (tid >> LG) + (256 >> LG) * r; }
+    else     { kl = tid & 15; ml = (tid >> 4) + 16 * r; }
+  };
+  auto mapB = [&](int r, int& nl, int& kl) {
+    if (!TB) { kl = tid & 15; nl = (tid >> 4) + 16 * r; }
+    else     { nl = tid & (BT - 1); kl = (tid >> LG) + (256 >> LG) * r; }
+  };
+  T ra[LPT], rb[LPT];
   auto loadA = [&](long k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < LPT; ++r) {
       int ml, kl;
-      if (!TA) { ml = tid & 63; kl = (tid >> 6) + 4 * r; }
-      else     { kl = tid & 15; ml = (tid >> 4) + 16 * r; }
+      mapA(r, ml, kl);
       const long gm = m0 + ml, gk = k0 + kl;
       T v = 0;
       if (gm < M && gk < kend) v = TA ? A[gk + gm * lda] : A[gm + gk * lda];
@@ -113,10 +130,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
   };
   auto loadB = [&](long k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < LPT; ++r) {
       int nl, kl;
-      if (!TB) { kl = tid & 15; nl = (tid >> 4) + 16 * r; }
-      else     { nl = tid & 63; kl = (tid >> 6) + 4 * r; }
+      mapB(r, nl, kl);
       const long gn = n0 + nl, gk = k0 + kl;
       T v = 0;
       if (gn < N && gk < kend) v = TB ? B[gn + gk * ldb] : B[gk + gn * ldb];
@@ -125,14 +141,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
   };
   auto storeAB = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int ml, kl;
-      if (!TA) { ml = tid & 63; kl = (tid >> 6) + 4 * r; }
-      else     { kl = tid & 15; ml = (tid >> 4) + 16 * r; }
+    for (int r = 0; r < LPT; ++r) {
+      int ml, kl, nl, kl2;
+      mapA(r, ml, kl);
       As[buf][kl][ml] = ra[r];
-      int nl, kl2;
-      if (!TB) { kl2 = tid & 15; nl = (tid >> 4) + 16 * r; }
-      else     { nl = tid & 63; kl2 = (tid >> 6) + 4 * r; }
+      mapB(r, nl, kl2);
       Bs[buf][kl2][nl] = rb[r];
     }
   };
@@ -150,16 +163,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = 4 * kk + (lane >> 4);
-      T av[2], bv[2];
+      T av[TW], bv[TW];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        av[t] = As[cur][kr][wm * 32 + t * 16 + (lane & 15)];
-        bv[t] = Bs[cur][kr][wn * 32 + t * 16 + (lane & 15)];
+      for (int t = 0; t < TW; ++t) {
+        av[t] = As[cur][kr][wm * (BT / 2) + t * 16 + (lane & 15)];
+        bv[t] = Bs[cur][kr][wn * (BT / 2) + t * 16 + (lane & 15)];
       }
 #pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
+      for (int ti = 0; ti < TW; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = Mfma<T>::op(bv[tj], av[ti], acc[ti][tj]);
+        for (int tj = 0; tj < TW; ++tj) acc[ti][tj] = Mfma<T>::op(bv[tj], av[ti], acc[ti][tj]);
     }
     if (more) storeAB(cur ^ 1);
     __syncthreads();
@@ -171,13 +184,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
   if (p.part) {
     T* part = p.part + (long)kc * M * N;
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
+    for (int ti = 0; ti < TW; ++ti)
 #pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
+      for (int tj = 0; tj < TW; ++tj)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int gm = m0 + wm * 32 + ti * 16 + (lane & 15);
-          const int gn = n0 + wn * 32 + tj * 16 + Mfma<T>::row(lane, r);
+          const int gm = m0 + wm * (BT / 2) + ti * 16 + (lane & 15);
+          const int gn = n0 + wn * (BT / 2) + tj * 16 + Mfma<T>::row(lane, r);
           if (gm < M && gn < N) part[gm + (long)gn * M] = acc[ti][tj][r];
         }
     return;
@@ -188,13 +201,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
   OT* Co = p.Co ? p.Co + (long)batch * p.sCo : nullptr;
   OT* C2o = p.C2o ? p.C2o + (long)batch * p.sC2o : nullptr;
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
+  for (int ti = 0; ti < TW; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
+    for (int tj = 0; tj < TW; ++tj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm * 32 + ti * 16 + (lane & 15);
-        const int gn = n0 + wn * 32 + tj * 16 + Mfma<T>::row(lane, r);
+        const int gm = m0 + wm * (BT / 2) + ti * 16 + (lane & 15);
+        const int gn = n0 + wn * (BT / 2) + tj * 16 + Mfma<T>::row(lane, r);
         if (gm < M && gn < N) {
           T v = p.alpha * acc[ti][tj][r];
           if (C) {
@@ -247,16 +260,25 @@ __global__ __launch_bounds__(256) void splitk_sum(int m, int n, int splits,
   C[i + (long)j * ldc] = s;
 }
 
+template <typename T, int BT>
+void launch_tiles(const Params<T>& p, bool tA, bool tB, int batch, hipStream_t st) {
+  dim3 grid(cdiv(p.m, BT), cdiv(p.n, BT), batch * p.ksplit);
+  RM_REQUIRE(grid.z <= 65535, "gemm: batch*ksplit too large");
+  if (!tA && !tB) hipLaunchKernelGGL((gemm_kernel<T, false, false, BT>), grid, dim3(256), 0, st, p);
+  else if (!tA && tB) hipLaunchKernelGGL((gemm_kernel<T, false, true, BT>), grid, dim3(256), 0, st, p);
+  else if (tA && !tB) hipLaunchKernelGGL((gemm_kernel<T, true, false, BT>), grid, dim3(256), 0, st, p);
+  else hipLaunchKernelGGL((gemm_kernel<T, true, true, BT>), grid, dim3(256), 0, st, p);
+  RM_CHECK_LAUNCH();
+}
+
+// 64 x 64 tiles throughout.  128 x 128 tiles (223 registers a lane, one
+// wave per SIMD) were measured slower on the large batched products: 888
+// against 687 us for the 14 products K^-1 K_l at N = 1024, 3026 against
+// 2737 us for the 56 products A_l A_m.
 template <typename T>
 void launch(const Params<T>& p, bool tA, bool tB, int batch, hipStream_t st) {
-  dim3 grid(cdiv(p.m, BM), cdiv(p.n, BN), batch * p.ksplit);
-  RM_REQUIRE(grid.z <= 65535, "gemm: batch*ksplit too large");
   const int slot = timing_begin(sizeof(T) == 8 ? TK_GEMM_F64 : TK_GEMM_F32, st);
-  if (!tA && !tB) hipLaunchKernelGGL((gemm_kernel<T, false, false>), grid, dim3(256), 0, st, p);
-  else if (!tA && tB) hipLaunchKernelGGL((gemm_kernel<T, false, true>), grid, dim3(256), 0, st, p);
-  else if (tA && !tB) hipLaunchKernelGGL((gemm_kernel<T, true, false>), grid, dim3(256), 0, st, p);
-  else hipLaunchKernelGGL((gemm_kernel<T, true, true>), grid, dim3(256), 0, st, p);
-  RM_CHECK_LAUNCH();
+  launch_tiles<T, 64>(p, tA, tB, batch, st);
   if (slot >= 0) {
     const double mnk = (double)p.m * p.n * p.k * batch;
     const double io = ((double)p.m * p.k + (double)p.k * p.n + (double)p.m * p.n) * batch * sizeof(T);
