@@ -6,7 +6,8 @@
 // nb = Dp/16 column blocks play a round-robin tournament, nb-1 rounds per
 // sweep.  In a round every pair of blocks (I, J) forms a 32 x 32 symmetric
 // subproblem that one workgroup diagonalises in LDS with an inner cyclic
-// Jacobi (its own round-robin over 32 indices); the resulting 32 x 32
+// Jacobi (its own round-robin over 32 indices; warm starts rotate only the
+// pairs between the two blocks in most rounds); the resulting 32 x 32
 // rotations are then applied to M (one wave per 32 x 32 tile on the FP64
 // matrix cores, double-buffered M) and to the columns of Psi (fused into
 // the next round's solve launch).  Padding rows/columns are zero and never
@@ -26,6 +27,13 @@ namespace rmhmc {
 namespace {
 
 constexpr int JSB = 32, JHB = 16;   // subproblem size of the block Jacobi and its block width
+// Warm-started solves: a full inner sweep (all pairs of the subproblem) in
+// every JACOBI_FULL_PERIOD-th round of an outer sweep, only the pairs between
+// the two blocks in the others.  Measured on the Hessians of the D = 1038
+// model warm-started from a nearby point, the outer sweeps converge as with a
+// full inner sweep in every round (also at a period of 16; a full sweep in
+// the first round alone converges more slowly).
+constexpr int JACOBI_FULL_PERIOD = 8;
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int rr_player(int r, int k, int n) {
@@ -50,6 +58,22 @@ template <int SB>
 __device__ __forceinline__ int rr_local(int r, int k) {
   const int x = k - 1 + r;
   return k == 0 ? 0 : 1 + (x >= SB - 1 ? x - (SB - 1) : x);
+}
+
+// Pair u of inner round ir.  Full rounds: the round-robin over all SB local
+// indices (SB - 1 rounds cover every pair).  Cross rounds: u in the first
+// block against HB + (u + ir) mod HB in the second (HB rounds cover the HB^2
+// pairs between the two blocks and none inside one).
+template <int SB>
+__device__ __forceinline__ void inner_pair(bool cross, int ir, int u, int& p, int& q) {
+  constexpr int HB = SB / 2;
+  if (cross) {
+    p = u;
+    q = HB + ((u + ir) & (HB - 1));
+  } else {
+    p = rr_local<SB>(ir, u);
+    q = rr_local<SB>(ir, SB - 1 - u);
+  }
 }
 
 // The SB global indices of a slot in a round: local x < HB in block I,
@@ -192,10 +216,16 @@ __device__ __forceinline__ void jacobi_compose_subproblem(
 //
 // The subproblem is read from M directly when Vprev is null, else composed
 // from the previous round's M and rotations (see the round kernel).
+//
+// cross: one sweep of cross rounds only (pairs between the two blocks).  Each
+// block comes from a subproblem that the previous round rotated, so the
+// coupling inside a block is what that solve left; a later full round removes
+// it, and every pair of indices still meets once per outer sweep.
 __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
                                                    const double* __restrict__ M,
                                                    const double* __restrict__ Vprev,
-                                                   double* __restrict__ Vbuf, int max_inner) {
+                                                   double* __restrict__ Vbuf, int max_inner,
+                                                   bool cross) {
   constexpr int SB = JSB;
   constexpr int HB = SB / 2;                  // block width; also the number of pairs
   constexpr int NBLK = HB * HB / 256;         // S 2 x 2 blocks per thread
@@ -247,14 +277,39 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
   const int u = tid % HB;
   double2* const csw = cs[w];
   int cur = 0;
+  const int n_inner = cross ? HB : SB - 1;
   for (int sweep = 0; sweep < max_inner; ++sweep) {
     bool significant = false;
-    for (int ir = 0; ir < SB - 1; ++ir) {
+    for (int ir = 0; ir < n_inner; ++ir) {
       double(*S)[SB + 1] = Sb[cur];
       double(*T)[SB + 1] = Sb[cur ^ 1];
       // rotation of pair u (the smaller angle, |angle| <= pi/4)
-      const int pu = rr_local<SB>(ir, u), qu = rr_local<SB>(ir, SB - 1 - u);
+      int pu, qu;
+      inner_pair<SB>(cross, ir, u, pu, qu);
       const double app = S[pu][pu], aqq = S[qu][qu], apq = S[pu][qu];
+      // this thread's 2 x 2 blocks of S and entries of V, read before the
+      // rotations are known so that the reads overlap their arithmetic
+      double x[NBLK][4];
+      int pv[NBLK], qv[NBLK];
+#pragma unroll
+      for (int j = 0; j < NBLK; ++j) {
+        const int v = (tid + 256 * j) / HB;
+        inner_pair<SB>(cross, ir, v, pv[j], qv[j]);
+        x[j][0] = S[pu][pv[j]];
+        x[j][1] = S[pu][qv[j]];
+        x[j][2] = S[qu][pv[j]];
+        x[j][3] = S[qu][qv[j]];
+      }
+      double vp[NVR], vq[NVR];
+      int p2[NVR], q2[NVR], row[NVR];
+#pragma unroll
+      for (int k = 0; k < NVR; ++k) {
+        const int e = tid + 256 * k;
+        row[k] = e % SB;
+        inner_pair<SB>(cross, ir, e / SB, p2[k], q2[k]);
+        vp[k] = V[row[k]][p2[k]];
+        vq[k] = V[row[k]][q2[k]];
+      }
       // The rotation is kept as (s, tau), tau = s / (1 + c) = tan(angle / 2),
       // and applied as x' = x - s (y + tau x), y' = y + s (x - tau y): c
       // never appears rounded.  With c = fl(1 / sqrt(1 + t^2)), every small
@@ -292,36 +347,12 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
       if (lane < HB) csw[u] = make_double2(sn, tau);
       wave_lds_sync();   // read back by other lanes of this wave
 
-      // S' = J' S J by 2 x 2 blocks (u, v)
-      double x[NBLK][4];
-      int pv[NBLK], qv[NBLK];
-      double2 rv[NBLK];
+      // S' = J' S J by 2 x 2 blocks (u, v); V <- V J by entries (row, pair)
+      double2 rv[NBLK], r2v[NVR];
 #pragma unroll
-      for (int j = 0; j < NBLK; ++j) {
-        const int v = (tid + 256 * j) / HB;
-        pv[j] = rr_local<SB>(ir, v);
-        qv[j] = rr_local<SB>(ir, SB - 1 - v);
-        rv[j] = csw[v];
-        x[j][0] = S[pu][pv[j]];
-        x[j][1] = S[pu][qv[j]];
-        x[j][2] = S[qu][pv[j]];
-        x[j][3] = S[qu][qv[j]];
-      }
-      // V <- V J: entries (row, pair u2)
-      double vp[NVR], vq[NVR];
-      double2 r2v[NVR];
-      int p2[NVR], q2[NVR], row[NVR];
+      for (int j = 0; j < NBLK; ++j) rv[j] = csw[(tid + 256 * j) / HB];
 #pragma unroll
-      for (int k = 0; k < NVR; ++k) {
-        const int e = tid + 256 * k;
-        const int u2 = e / SB;
-        row[k] = e % SB;
-        p2[k] = rr_local<SB>(ir, u2);
-        q2[k] = rr_local<SB>(ir, SB - 1 - u2);
-        r2v[k] = csw[u2];
-        vp[k] = V[row[k]][p2[k]];
-        vq[k] = V[row[k]][q2[k]];
-      }
+      for (int k = 0; k < NVR; ++k) r2v[k] = csw[(tid + 256 * k) / SB];
 #pragma unroll
       for (int j = 0; j < NBLK; ++j) {
         const double sv = rv[j].x, tv = rv[j].y;
@@ -544,10 +575,14 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(int Dp, int apply_rou
   // (sweeps launched ahead of the check cost only their launch)
   if (ctrl[1] != 0.0) return;
   if (b < nsolve) {
+    // warm starts run the full inner sweep every JACOBI_FULL_PERIOD-th round
+    // and cross rounds in between; static solves always run full sweeps
+    const int round = apply_round + 1;
+    const bool cross = MAX_INNER == JACOBI_INNER_DYNAMIC && round % JACOBI_FULL_PERIOD != 0;
     if (apply_round < 0)
-      jacobi_solve_block(Dp, 0, b, Min, nullptr, Vnew, MAX_INNER);
+      jacobi_solve_block(Dp, 0, b, Min, nullptr, Vnew, MAX_INNER, false);
     else
-      jacobi_solve_block(Dp, apply_round + 1, b, Min, Vprev, Vnew, MAX_INNER);
+      jacobi_solve_block(Dp, round, b, Min, Vprev, Vnew, MAX_INNER, cross);
     return;
   }
   __shared__ double Xs[4][JSB][JSB + 1];
@@ -978,7 +1013,12 @@ JacobiResult jacobi_eig(int D, EigWork& w, double zeta, double gfloor, int max_s
   const int ntri = ns * (ns + 1) / 2;
   const int npsi = (Dp / JSB) * ns;
   double* Vb[2] = {w.V, w.V + (long)ns * JSB * JSB};
-  const double solve_flops = (double)ns * (JSB - 1) * (JHB * JHB * 24.0 + JSB * JHB * 6.0);
+  // per inner round of a subproblem; rounds per solve: JSB - 1 (full), JHB (cross)
+  const double inner_flops = (double)ns * (JHB * JHB * 24.0 + JSB * JHB * 6.0);
+  auto solve_flops = [&](int round) {
+    const bool cross = max_inner == JACOBI_INNER_DYNAMIC && round % JACOBI_FULL_PERIOD != 0;
+    return inner_flops * (cross ? JHB : JSB - 1);
+  };
   const double compose_flops = (double)ns * 3.0 * (2.0 * JSB * JSB * JHB + 2.0 * JHB * JSB * JHB);
   const double sb3 = (double)JSB * JSB * JSB;
   const double vset = (double)ns * JSB * JSB * sizeof(double);
@@ -997,7 +1037,7 @@ JacobiResult jacobi_eig(int D, EigWork& w, double zeta, double gfloor, int max_s
                        (const double*)w.ctrl, 0, 0, w.Psi);
     RM_CHECK_LAUNCH();
     // algorithmic bytes: subproblems read, rotations written
-    double flops = solve_flops, bytes = 2.0 * vset;
+    double flops = solve_flops(0), bytes = 2.0 * vset;
     for (int r = 0; r < nb - 1; ++r) {
       const bool more = r + 1 < nb - 1;
       const int nsolve = more ? ns : 0;
@@ -1009,7 +1049,7 @@ JacobiResult jacobi_eig(int D, EigWork& w, double zeta, double gfloor, int max_s
       // algorithmic work: M update (upper tiles read, all of M written), Psi
       // read and written, rotations V_r read once; solves: three tiles of
       // M_r read per subproblem, V_{r+1} written
-      flops += 4.0 * sb3 * ntri + 2.0 * sb3 * npsi + (more ? solve_flops + compose_flops : 0.0);
+      flops += 4.0 * sb3 * ntri + 2.0 * sb3 * npsi + (more ? solve_flops(r + 1) + compose_flops : 0.0);
       bytes += (double)ntri * tile + 3.0 * (double)Dp * Dp * sizeof(double) + vset +
                (more ? 3.0 * ns * tile + vset : 0.0);
       cur ^= 1;
