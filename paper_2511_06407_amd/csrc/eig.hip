@@ -111,12 +111,14 @@ __device__ __forceinline__ void rr_locate(int X, int r, int nb, int& slot, int& 
 //   S = [V~_A' Mprev[A,A] V~_A, V~_A' Mprev[A,B] V~_B; (.)', V~_B' Mprev[B,B] V~_B].
 // Waves 0..2 form the three distinct 16 x 16 blocks on the matrix cores
 // (T = Mprev tile x V~_Y, then V~_X' T).  The tiles are staged in T0..T2
-// (scratch of the caller) and S is written to Sout with the diagonal blocks
-// symmetrised.  All threads of the workgroup call this.
+// (scratch of the caller) and S is written to Sout, each diagonal block from
+// its upper triangle (so S is exactly symmetric).  T2 is then set to the
+// identity and red[w] receives this wave's part of ||S||_F^2.  All threads of
+// the workgroup call this; it ends with a barrier.
 __device__ __forceinline__ void jacobi_compose_subproblem(
     int Dp, int round, int slot, const double* __restrict__ Mprev,
     const double* __restrict__ Vprev, double (*T0)[JSB + 1], double (*T1)[JSB + 1],
-    double (*T2)[JSB + 1], double (*Tw)[JSB][17], double (*Sout)[JSB + 1]) {
+    double (*T2)[JSB + 1], double (*Tw)[JSB][17], double (*Sout)[JSB + 1], double* red) {
   const int nb = Dp / JHB;
   const int tid = threadIdx.x, lane = tid & 63, lm = lane & 15, lk = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -177,26 +179,28 @@ __device__ __forceinline__ void jacobi_compose_subproblem(
       s2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Tt[4 * kq + lk][lm], fx[kq], s2, 0, 0, 0);
   }
   __syncthreads();   // every wave is done with T0..T2
+  double ss = 0.0;
   if (w < 3) {
     // lane, register r hold S_XY(m = lm, n = lk + 4 r)
     const int r0 = w == 2 ? JHB : 0, c0 = w == 0 ? 0 : JHB;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      Sout[r0 + lm][c0 + lk + 4 * r] = s2[r];
-      if (w == 1) Sout[c0 + lk + 4 * r][r0 + lm] = s2[r];
+      const int n = lk + 4 * r;
+      const double v = s2[r];
+      if (w == 1 || lm <= n) {
+        Sout[r0 + lm][c0 + n] = v;
+        Sout[c0 + n][r0 + lm] = v;
+        ss += (w != 1 && lm == n) ? v * v : 2.0 * v * v;
+      }
     }
   }
-  __syncthreads();
-  // symmetrise the two diagonal blocks
-  for (int e = tid; e < 2 * JHB * JHB; e += 256) {
-    const int b = e / (JHB * JHB), x = (e % (JHB * JHB)) % JHB, y = (e % (JHB * JHB)) / JHB;
-    if (x < y) {
-      const int o = b * JHB;
-      const double v = 0.5 * (Sout[o + x][o + y] + Sout[o + y][o + x]);
-      Sout[o + x][o + y] = v;
-      Sout[o + y][o + x] = v;
-    }
+#pragma unroll
+  for (int i = 0; i < JSB * JSB / 256; ++i) {
+    const int e = tid + 256 * i, x = e % JSB, y = e / JSB;
+    T2[x][y] = (x == y) ? 1.0 : 0.0;
   }
+  for (int o = 32; o > 0; o >>= 1) ss += __shfl_down(ss, o, 64);
+  if (lane == 0) red[w] = ss;
   __syncthreads();
 }
 
@@ -206,16 +210,17 @@ __device__ __forceinline__ void jacobi_compose_subproblem(
 //
 // Every wave computes the round's SB/2 rotations itself (lane l holds pair
 // l mod SB/2; the computation is identical in every wave, so the decisions
-// taken from it are uniform over the workgroup) and publishes them to its own
-// LDS slot, which only that wave reads back (a wavefront-scope fence orders
-// the exchange; no workgroup barrier).  S is double-buffered: a round reads one
+// taken from it are uniform over the workgroup).  S is double-buffered: a round reads one
 // copy and writes the other, so one barrier per rotating round orders
 // everything.  Thread t updates the 2 x 2 blocks (u, v) = (t mod SB/2, ...)
-// of S, whose row pair u is the pair it computed itself, and SB/2 x SB / 256
-// (row, pair) entries of V.
+// of S, whose row pair u is the pair it computed itself, and the entries
+// (v, u) and (v + SB/2, u) of V, so V only needs its own rotation; the
+// rotation of column pair v comes from lane v of the wave by a shuffle.
 //
 // The subproblem is read from M directly when Vprev is null, else composed
-// from the previous round's M and rotations (see the round kernel).
+// from the previous round's M and rotations (see the round kernel).  A solve
+// whose stop flag (ctrl[1]) is set returns once the subproblem is loaded: the
+// flag is read together with the subproblem instead of before it.
 //
 // cross: one sweep of cross rounds only (pairs between the two blocks).  Each
 // block comes from a subproblem that the previous round rotated, so the
@@ -225,23 +230,21 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
                                                    const double* __restrict__ M,
                                                    const double* __restrict__ Vprev,
                                                    double* __restrict__ Vbuf, int max_inner,
-                                                   bool cross) {
+                                                   bool cross, const double* __restrict__ ctrl) {
   constexpr int SB = JSB;
   constexpr int HB = SB / 2;                  // block width; also the number of pairs
-  constexpr int NBLK = HB * HB / 256;         // S 2 x 2 blocks per thread
-  constexpr int NVR = SB * HB / 256;          // V (row, pair) entries per thread
-  static_assert(NBLK >= 1 && NVR >= 1, "subproblem too small for 256 threads");
+  // one 2 x 2 block of S and two entries of V per thread
+  static_assert(HB * HB == 256, "the thread mapping needs a 32 x 32 subproblem");
   __shared__ double Sb[2][SB][SB + 1];
   __shared__ double V[SB][SB + 1];
   __shared__ double Tw[3][SB][17];  // per-wave intermediates of the composition
-  __shared__ double2 cs[4][HB];     // per wave: (s, tau) of the round's pairs
   __shared__ double red[4];
+  const double stop = ctrl[1];
   const int nb = Dp / HB;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   constexpr int NLD = SB * SB / 256;
-  double ss = 0.0;
   if (Vprev == nullptr) {
     const SlotCols<HB> sc = slot_cols<HB>(round, slot, nb);
     double ld[NLD];
@@ -250,32 +253,28 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
       const int e = tid + 256 * i, x = e % SB, y = e / SB;
       ld[i] = M[sc.col(x) + (long)sc.col(y) * Dp];
     }
+    double ss = 0.0;
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
       const int e = tid + 256 * i, x = e % SB, y = e / SB;
       Sb[0][x][y] = ld[i];
+      V[x][y] = (x == y) ? 1.0 : 0.0;
+      ss += ld[i] * ld[i];
     }
+    for (int o = 32; o > 0; o >>= 1) ss += __shfl_down(ss, o, 64);
+    if (lane == 0) red[w] = ss;
+    __syncthreads();
   } else {
-    jacobi_compose_subproblem(Dp, round, slot, M, Vprev, Sb[0], Sb[1], V, Tw, Sb[0]);
+    jacobi_compose_subproblem(Dp, round, slot, M, Vprev, Sb[0], Sb[1], V, Tw, Sb[0], red);
   }
-#pragma unroll
-  for (int i = 0; i < NLD; ++i) {
-    const int e = tid + 256 * i, x = e % SB, y = e / SB;
-    const double v = Sb[0][x][y];
-    V[x][y] = (x == y) ? 1.0 : 0.0;
-    ss += v * v;
-  }
-  for (int o = 32; o > 0; o >>= 1) ss += __shfl_down(ss, o, 64);
-  if (lane == 0) red[w] = ss;
-  __syncthreads();
+  if (stop != 0.0) return;   // uniform: every thread of the workgroup returns
   // Skip a rotation when |a_pq| <= 1e-15 sqrt(|a_pp a_qq|) (relative
   // criterion, so eigenvectors of small eigenvalues stay accurate next to
   // large ones), with an absolute floor of 1e-30 ||S||_F; entries below
   // 1e-150 never rotate, so every square below stays a normal number.
   const double thr = fmax(1e-30 * sqrt(red[0] + red[1] + red[2] + red[3]), 1e-150);
   const double thr2 = thr * thr;
-  const int u = tid % HB;
-  double2* const csw = cs[w];
+  const int u = tid % HB, v = tid / HB;
   int cur = 0;
   const int n_inner = cross ? HB : SB - 1;
   for (int sweep = 0; sweep < max_inner; ++sweep) {
@@ -287,29 +286,12 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
       int pu, qu;
       inner_pair<SB>(cross, ir, u, pu, qu);
       const double app = S[pu][pu], aqq = S[qu][qu], apq = S[pu][qu];
-      // this thread's 2 x 2 blocks of S and entries of V, read before the
+      // this thread's 2 x 2 block of S and entries of V, read before the
       // rotations are known so that the reads overlap their arithmetic
-      double x[NBLK][4];
-      int pv[NBLK], qv[NBLK];
-#pragma unroll
-      for (int j = 0; j < NBLK; ++j) {
-        const int v = (tid + 256 * j) / HB;
-        inner_pair<SB>(cross, ir, v, pv[j], qv[j]);
-        x[j][0] = S[pu][pv[j]];
-        x[j][1] = S[pu][qv[j]];
-        x[j][2] = S[qu][pv[j]];
-        x[j][3] = S[qu][qv[j]];
-      }
-      double vp[NVR], vq[NVR];
-      int p2[NVR], q2[NVR], row[NVR];
-#pragma unroll
-      for (int k = 0; k < NVR; ++k) {
-        const int e = tid + 256 * k;
-        row[k] = e % SB;
-        inner_pair<SB>(cross, ir, e / SB, p2[k], q2[k]);
-        vp[k] = V[row[k]][p2[k]];
-        vq[k] = V[row[k]][q2[k]];
-      }
+      int pv, qv;
+      inner_pair<SB>(cross, ir, v, pv, qv);
+      const double x0 = S[pu][pv], x1 = S[pu][qv], x2 = S[qu][pv], x3 = S[qu][qv];
+      const double vp0 = V[v][pu], vq0 = V[v][qu], vp1 = V[v + HB][pu], vq1 = V[v + HB][qu];
       // The rotation is kept as (s, tau), tau = s / (1 + c) = tan(angle / 2),
       // and applied as x' = x - s (y + tau x), y' = y + s (x - tau y): c
       // never appears rounded.  With c = fl(1 / sqrt(1 + t^2)), every small
@@ -344,42 +326,32 @@ __device__ __forceinline__ void jacobi_solve_block(int Dp, int round, int slot,
       // subproblem must still be diagonalised for the outer sweeps to
       // converge quadratically.
       significant = significant || (__ballot(fabs(t) > 1e-8) != 0);
-      if (lane < HB) csw[u] = make_double2(sn, tau);
-      wave_lds_sync();   // read back by other lanes of this wave
+      // the rotation of column pair v: lane v of this wave computed it
+      const double sv = __shfl(sn, v, 64), tv = __shfl(tau, v, 64);
 
-      // S' = J' S J by 2 x 2 blocks (u, v); V <- V J by entries (row, pair)
-      double2 rv[NBLK], r2v[NVR];
-#pragma unroll
-      for (int j = 0; j < NBLK; ++j) rv[j] = csw[(tid + 256 * j) / HB];
-#pragma unroll
-      for (int k = 0; k < NVR; ++k) r2v[k] = csw[(tid + 256 * k) / SB];
-#pragma unroll
-      for (int j = 0; j < NBLK; ++j) {
-        const double sv = rv[j].x, tv = rv[j].y;
-        const double y11 = x[j][0] - sn * (x[j][2] + tau * x[j][0]);
-        const double y12 = x[j][1] - sn * (x[j][3] + tau * x[j][1]);
-        const double y21 = x[j][2] + sn * (x[j][0] - tau * x[j][2]);
-        const double y22 = x[j][3] + sn * (x[j][1] - tau * x[j][3]);
-        double z11 = y11 - sv * (y12 + tv * y11), z12 = y12 + sv * (y11 - tv * y12);
-        double z21 = y21 - sv * (y22 + tv * y21), z22 = y22 + sv * (y21 - tv * y22);
-        if ((tid + 256 * j) / HB == u && t != 0.0) {
-          // the pair's own block: exact annihilation (Rutishauser update)
-          z11 = x[j][0] - t * x[j][1];
-          z22 = x[j][3] + t * x[j][1];
-          z12 = 0.0;
-          z21 = 0.0;
-        }
-        T[pu][pv[j]] = z11;
-        T[pu][qv[j]] = z12;
-        T[qu][pv[j]] = z21;
-        T[qu][qv[j]] = z22;
+      // S' = J' S J on the 2 x 2 block (u, v)
+      const double y11 = x0 - sn * (x2 + tau * x0);
+      const double y12 = x1 - sn * (x3 + tau * x1);
+      const double y21 = x2 + sn * (x0 - tau * x2);
+      const double y22 = x3 + sn * (x1 - tau * x3);
+      double z11 = y11 - sv * (y12 + tv * y11), z12 = y12 + sv * (y11 - tv * y12);
+      double z21 = y21 - sv * (y22 + tv * y21), z22 = y22 + sv * (y21 - tv * y22);
+      if (v == u && t != 0.0) {
+        // the pair's own block: exact annihilation (Rutishauser update)
+        z11 = x0 - t * x1;
+        z22 = x3 + t * x1;
+        z12 = 0.0;
+        z21 = 0.0;
       }
-#pragma unroll
-      for (int k = 0; k < NVR; ++k) {
-        const double s2 = r2v[k].x, t2 = r2v[k].y;
-        V[row[k]][p2[k]] = vp[k] - s2 * (vq[k] + t2 * vp[k]);
-        V[row[k]][q2[k]] = vq[k] + s2 * (vp[k] - t2 * vq[k]);
-      }
+      T[pu][pv] = z11;
+      T[pu][qv] = z12;
+      T[qu][pv] = z21;
+      T[qu][qv] = z22;
+      // V <- V J: rows v and v + HB of the columns of pair u
+      V[v][pu] = vp0 - sn * (vq0 + tau * vp0);
+      V[v][qu] = vq0 + sn * (vp0 - tau * vq0);
+      V[v + HB][pu] = vp1 - sn * (vq1 + tau * vp1);
+      V[v + HB][qu] = vq1 + sn * (vp1 - tau * vq1);
       __syncthreads();
       cur ^= 1;
     }
@@ -572,19 +544,20 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(int Dp, int apply_rou
   const int b = blockIdx.x;
   // ctrl[1]: stop flag, set by the convergence check after a sweep and
   // constant within one; every part of a launch of a stopped solve exits
-  // (sweeps launched ahead of the check cost only their launch)
-  if (ctrl[1] != 0.0) return;
+  // (sweeps launched ahead of the check cost only their launch and the
+  // subproblem loads)
   if (b < nsolve) {
     // warm starts run the full inner sweep every JACOBI_FULL_PERIOD-th round
     // and cross rounds in between; static solves always run full sweeps
     const int round = apply_round + 1;
     const bool cross = MAX_INNER == JACOBI_INNER_DYNAMIC && round % JACOBI_FULL_PERIOD != 0;
     if (apply_round < 0)
-      jacobi_solve_block(Dp, 0, b, Min, nullptr, Vnew, MAX_INNER, false);
+      jacobi_solve_block(Dp, 0, b, Min, nullptr, Vnew, MAX_INNER, false, ctrl);
     else
-      jacobi_solve_block(Dp, round, b, Min, Vprev, Vnew, MAX_INNER, cross);
+      jacobi_solve_block(Dp, round, b, Min, Vprev, Vnew, MAX_INNER, cross, ctrl);
     return;
   }
+  if (ctrl[1] != 0.0) return;
   __shared__ double Xs[4][JSB][JSB + 1];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nmwg = (ntri + 3) / 4;
