@@ -503,21 +503,36 @@ void chol_inverse(int n, const double* K, double* Kinv, double* logdet, CholWork
   hipLaunchKernelGGL(trtri_diag_kernel, dim3(nb), dim3(256), 0, st, n, (const double*)w.L, (long)n,
                      w.Linv);
   RM_CHECK_LAUNCH();
-  // Linv block rows: Linv[i, :i] = -Linv_ii (L[i, :i] Linv[:i, :i])
-  for (int ib = 1; ib < nb; ++ib) {
-    const int i0 = ib * CB, bw = std::min(CB, n - i0);
-    Gemm<double> a;
-    a.m = bw; a.n = i0; a.k = i0;
-    a.A = w.L + i0; a.lda = n;
-    a.B = w.Linv; a.ldb = n;
-    a.C = w.tmp + i0; a.ldc = n;
-    gemm(a, st);
-    Gemm<double> b;
-    b.m = bw; b.n = i0; b.k = bw; b.alpha = -1.0;
-    b.A = w.Linv + i0 + (long)i0 * n; b.lda = n;
-    b.B = w.tmp + i0; b.ldb = n;
-    b.C = w.Linv + i0; b.ldc = n;
-    gemm(b, st);
+  // Linv by doubling: for two inverted diagonal blocks X11 = L11^-1 (s x s)
+  // and X22 = L22^-1 (s2 x s2, s2 <= s) of [L11 0; L21 L22], the block below
+  // X11 is X21 = -X22 (L21 X11).  Level s pairs the blocks starting at
+  // multiples of 2s; those pairs are independent and lie at a constant
+  // stride 2s(n + 1) along the diagonal, so each level is two batched
+  // products (plus a ragged last pair when n is not a power-of-two multiple
+  // of CB).
+  for (int s = CB; s < n; s *= 2) {
+    const int full = n / (2 * s);                  // pairs with s2 = s
+    const long stride = 2L * s * (n + 1);
+    auto level = [&](int b0, int s2, int batch) {
+      const long off21 = (b0 + s) + (long)b0 * n;
+      Gemm<double> a;                                // T = L21 X11
+      a.m = s2; a.n = s; a.k = s;
+      a.A = w.L + off21; a.lda = n; a.sA = stride;
+      a.B = w.Linv + b0 + (long)b0 * n; a.ldb = n; a.sB = stride;
+      a.C = w.tmp + off21; a.ldc = n; a.sC = stride;
+      a.batch = batch;
+      gemm(a, st);
+      Gemm<double> b;                                // X21 = -X22 T
+      b.m = s2; b.n = s; b.k = s2; b.alpha = -1.0;
+      b.A = w.Linv + (b0 + s) + (long)(b0 + s) * n; b.lda = n; b.sA = stride;
+      b.B = w.tmp + off21; b.ldb = n; b.sB = stride;
+      b.C = w.Linv + off21; b.ldc = n; b.sC = stride;
+      b.batch = batch;
+      gemm(b, st);
+    };
+    if (full > 0) level(0, s, full);
+    const int b0 = full * 2 * s;
+    if (b0 + s < n) level(b0, n - b0 - s, 1);
   }
   // K^-1 = Linv' Linv
   Gemm<double> c;
