@@ -71,6 +71,8 @@ struct Gemm {
   // (ldc, stride sCo), C2o transposed (ldc2, stride sC2o).
   void* Co = nullptr; long sCo = 0;
   void* C2o = nullptr; long sC2o = 0;
+  // pointer-array batches: Co per batch item (C's layout, ldc)
+  void* const* Cop = nullptr;
 };
 
 void gemm(const Gemm<double>& g, hipStream_t st);

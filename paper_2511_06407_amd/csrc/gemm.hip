@@ -51,6 +51,7 @@ struct Params {
   T* C; long ldc; long sC;
   T* C2; long ldc2; long sC2;
   const T* const* Ap; const T* const* Bp; T* const* Cp; T* const* C2p;
+  OT* const* Cop;       // per batch item: Co (pointer-array batches)
   int ksplit; long kchunk;
   T* part;          // split-K partials: part[kc * m * n + i + j * m]
 };
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
   typedef typename OtherPrec<T>::type OT;
   T* C = p.Cp ? p.Cp[batch] : (p.C ? p.C + (long)batch * p.sC : nullptr);
   T* C2 = p.C2p ? p.C2p[batch] : (p.C2 ? p.C2 + (long)batch * p.sC2 : nullptr);
-  OT* Co = p.Co ? p.Co + (long)batch * p.sCo : nullptr;
+  OT* Co = p.Cop ? p.Cop[batch] : (p.Co ? p.Co + (long)batch * p.sCo : nullptr);
   OT* C2o = p.C2o ? p.C2o + (long)batch * p.sC2o : nullptr;
 #pragma unroll
   for (int ti = 0; ti < TW; ++ti)
@@ -298,6 +299,7 @@ void gemm_impl(const Gemm<T>& g, hipStream_t st) {
   p.Ap = g.Ap; p.Bp = g.Bp; p.Cp = g.Cp; p.C2p = g.C2p;
   p.Co = static_cast<typename Params<T>::OT*>(g.Co); p.sCo = g.sCo;
   p.C2o = static_cast<typename Params<T>::OT*>(g.C2o); p.sC2o = g.sC2o;
+  p.Cop = reinterpret_cast<typename Params<T>::OT* const*>(g.Cop);
   RM_REQUIRE(!(g.Co || g.C2o) || (!g.Cp && !g.C2p), "gemm: other-precision copies need strided C");
   p.ksplit = 1; p.kchunk = g.k > 0 ? g.k : 1; p.part = nullptr;
   launch(p, g.tA, g.tB, g.batch, st);
@@ -330,7 +332,7 @@ void tallk_impl(int m, int n, long k, const T* A, long lda, const T* B, long ldb
 // waves in flight, and a second pass adds them in order.
 void gemm_splitk_impl(const Gemm<double>& g, double* work, int splits, hipStream_t st) {
   const bool plain = g.batch == 1 && g.alpha == 1.0 && g.beta == 0.0 && !g.C2 && !g.C2p &&
-                     !g.Ap && !g.Bp && !g.Cp && !g.Co && !g.C2o && g.C && work;
+                     !g.Ap && !g.Bp && !g.Cp && !g.Co && !g.C2o && !g.Cop && g.C && work;
   if (!plain || splits <= 1 || g.k < 2 * BK * splits) {
     gemm_impl(g, st);
     return;

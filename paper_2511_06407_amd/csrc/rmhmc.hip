@@ -25,6 +25,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "basis.h"
@@ -79,6 +80,23 @@ struct Pool {
 // H_lm = k_l.a_m + <Phi, K_lm> - tr(A_l A_m)/2 + delta_lm (symmetrised).
 // L'' is diag(l'') for one latent function; with two (R > 0 records, the
 // mean/variance model) each record also couples f1_i and f2_i = f_(R+i).
+// Same-value terms with at most this many distinct values take the
+// low-rank form of their derivative.
+constexpr int LR_MAX_RANK = 4;
+
+// UU[:, ncol + k] = UU[:, k] c_s(eta) for the columns k of slot s = k / rl:
+// c = exp(eta_l) (linear-ARD), 2 exp(2 eta_l) (same-value).
+__global__ void lr_scale_kernel(int N, int ncol, int rl, double* __restrict__ UU,
+                                const int* __restrict__ lr_param, const int* __restrict__ lr_kind,
+                                const double* __restrict__ eta) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)N * ncol) return;
+  const int sl = (int)(e / N) / rl;
+  const double h = eta[lr_param[sl]];
+  const double c = lr_kind[sl] ? 2.0 * exp(2.0 * h) : exp(h);
+  UU[(long)ncol * N + e] = UU[e] * c;
+}
+
 __global__ void assemble_H_kernel(int N, int P, int Dp, int R, double beta, const double* __restrict__ Kinv,
                                   const double* __restrict__ lik, const double* __restrict__ a,
                                   const double* __restrict__ kla, const double* __restrict__ phiK2,
@@ -504,6 +522,20 @@ struct Model {
   double* gvwork = nullptr;    // column-split GEMV partials
   double *E1 = nullptr, *E2 = nullptr, *D1 = nullptr, *D2 = nullptr, *D3 = nullptr;
   double *t3 = nullptr, *tB = nullptr, *tau = nullptr;
+  // Low-rank hyperparameter derivatives.  A linear-ARD parameter's K_l is
+  // exp(eta_l) x x' (rank one) and a same-value term's is 2 exp(2 eta_l)
+  // times the indicator of equal values (one column per distinct value), so
+  // K_l = U_l c_l(eta) U_l' with U_l of rl columns (zero-padded).  Such
+  // parameters (slots, in parameter order) take their A_l = K^-1 K_l,
+  // B_l = A_l K^-1 and Y products from thin factors instead of N^3 products.
+  int nlr = 0, rl = 0;
+  std::vector<int> lr_slot_h;                  // per parameter: slot, -1: full rank
+  std::vector<std::pair<int, int>> runs_h;     // consecutive parameters of one class: (first, count)
+  int *lr_param = nullptr, *lr_kind = nullptr; // per slot: parameter; 0: c = e^eta, 1: c = 2 e^(2 eta)
+  double* UU = nullptr;                        // N x 2 nlr rl: [U | U C] (C set per point)
+  double* Gy = nullptr;                        // (nyl + nyr) x N x rl: thin Y factors
+  // formed Y pairs l <= m: both full rank; l low rank; only m low rank
+  int nyf = 0, nyl = 0, nyr = 0;
   int* dflag = nullptr;
   int* hflag = nullptr;
   struct Point* api_pt = nullptr;
@@ -533,6 +565,15 @@ struct Point {
   double *trK1, *kla, *phiK2, *trAA, *ak;
   const double **Yap = nullptr, **Ybp = nullptr;
   double** Ycp = nullptr;
+  // low-rank parameters: ZZ = [K^-1 U | K^-1 U C] (N x 2 nlr rl), and the
+  // pointer arrays of the thin Y products (first factors with l low rank,
+  // with only m low rank, then the outer products)
+  double* ZZ = nullptr;
+  const double **YLa = nullptr, **YLb = nullptr, **YRa = nullptr, **YRb = nullptr;
+  double **YLc = nullptr, **YRc = nullptr;
+  const double **Y2a = nullptr, **Y2b = nullptr;
+  double** Y2c = nullptr;
+  float** Y2cf = nullptr;
   // mixed precision: FP32 copies feeding the FP32 MFMA products
   float *Af = nullptr, *Atf = nullptr, *Ytf = nullptr;
   const float **Yapf = nullptr, **Ybpf = nullptr;
@@ -605,6 +646,7 @@ void layout_point(const Model& m, Point& p, Carve& c) {
   p.phiK2 = c.take<double>(std::max(m.npairs, 1));
   p.trAA = c.take<double>(P * P);
   p.ak = c.take<double>(P);
+  p.ZZ = c.take<double>(N * 2L * m.nlr * m.rl);
   if (mixed) {
     p.Af = c.take<float>(P * NN);
     p.Atf = c.take<float>(P * NN);
@@ -634,15 +676,47 @@ std::unique_ptr<Point> new_point(Model& m) {
     return pt;
   }
   const long NN = (long)m.N * m.N;
-  // pointer arrays for the Y_lm = A_l A_m batch (the formed pairs l <= m)
+  // pointer arrays for the Y_lm = A_l A_m products (the formed pairs l <= m):
+  // both factors full rank in one batch; with a low-rank factor, thin
+  // products through G (N x rl):
+  //   l low rank:       G = A_m' U_l,    Y' = G Zc_l'
+  //   only m low rank:  G = A_l Zc_m,    Y' = U_m G'
+  // with Zc = K^-1 U C, so that A_l = Zc_l U_l' for a low-rank l
   std::vector<const double*> ya, yb;
   std::vector<double*> yc;
   std::vector<const float*> fa, fb;
   std::vector<float*> fc;
+  std::vector<const double*> la, lb, ra, rb, a2l, b2l, a2r, b2r;
+  std::vector<double*> lc, rc, c2l, c2r;
+  std::vector<float*> c2lf, c2rf;
+  const long ncol = (long)m.nlr * m.rl;
   for (int l = 0; l < m.P; ++l)
     for (int mm = l; mm < m.P; ++mm) {
       const int y = m.yidx_h[l * m.P + mm];
       if (y < 0) continue;
+      const int sl = m.lr_slot_h[l], sm = m.lr_slot_h[mm];
+      if (sl >= 0 || sm >= 0) {
+        const bool caseL = sl >= 0;
+        double* G = m.Gy + (long)(caseL ? la.size() : m.nyl + ra.size()) * m.N * m.rl;
+        if (caseL) {
+          la.push_back(p.A + mm * NN);
+          lb.push_back(m.UU + (long)sl * m.rl * m.N);
+          lc.push_back(G);
+          a2l.push_back(G);
+          b2l.push_back(p.ZZ + (ncol + (long)sl * m.rl) * m.N);
+          c2l.push_back(p.Yt + (long)y * NN);
+          c2lf.push_back(p.Ytf ? p.Ytf + (long)y * NN : nullptr);
+        } else {
+          ra.push_back(p.A + l * NN);
+          rb.push_back(p.ZZ + (ncol + (long)sm * m.rl) * m.N);
+          rc.push_back(G);
+          a2r.push_back(m.UU + (long)sm * m.rl * m.N);
+          b2r.push_back(G);
+          c2r.push_back(p.Yt + (long)y * NN);
+          c2rf.push_back(p.Ytf ? p.Ytf + (long)y * NN : nullptr);
+        }
+        continue;
+      }
       if (m.prec == RMHMC_MIXED) {
         fa.push_back(p.Af + l * NN);
         fb.push_back(p.Af + mm * NN);
@@ -667,6 +741,25 @@ std::unique_ptr<Point> new_point(Model& m) {
     RM_HIP(hipMemcpy((void*)p.Yap, ya.data(), ya.size() * sizeof(void*), hipMemcpyHostToDevice));
     RM_HIP(hipMemcpy((void*)p.Ybp, yb.data(), yb.size() * sizeof(void*), hipMemcpyHostToDevice));
     RM_HIP(hipMemcpy((void*)p.Ycp, yc.data(), yc.size() * sizeof(void*), hipMemcpyHostToDevice));
+  }
+  RM_REQUIRE((int)la.size() == m.nyl && (int)ra.size() == m.nyr, "internal: low-rank Y pairs");
+  if (m.nyl + m.nyr > 0) {
+    auto upload = [&](auto& v) {
+      using E = typename std::decay_t<decltype(v)>::value_type;
+      E* d = p.meta.alloc<E>(std::max<size_t>(v.size(), 1));
+      if (!v.empty()) RM_HIP(hipMemcpy((void*)d, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice));
+      return d;
+    };
+    p.YLa = upload(la); p.YLb = upload(lb); p.YLc = upload(lc);
+    p.YRa = upload(ra); p.YRb = upload(rb); p.YRc = upload(rc);
+    // the outer products of both cases run as one batch
+    a2l.insert(a2l.end(), a2r.begin(), a2r.end());
+    b2l.insert(b2l.end(), b2r.begin(), b2r.end());
+    c2l.insert(c2l.end(), c2r.begin(), c2r.end());
+    c2lf.insert(c2lf.end(), c2rf.begin(), c2rf.end());
+    p.Y2a = upload(a2l); p.Y2b = upload(b2l);
+    if (m.prec == RMHMC_MIXED) p.Y2cf = upload(c2lf);
+    else p.Y2c = upload(c2l);
   }
   RM_HIP(hipMemset(p.data, 0, p.data_bytes));
   return pt;
@@ -705,22 +798,42 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st, int* fail) {
   gemv(N, N, 1.0, pt.Kinv, N, true, 0, pt.q, 0, 0.0, pt.alpha, 0, 1, st);
   lik_derivs(N, m.lik, m.noise_var, m.delta, pt.q, m.y, pt.lik, st);
   const bool mixed = m.prec == RMHMC_MIXED;
-  {  // A_l = K^-1 K_l, and the transposed copies
+  const long ncol = (long)m.nlr * m.rl;
+  if (m.nlr > 0) {  // [Z | Zc] = K^-1 [U | U C]
+    hipLaunchKernelGGL(lr_scale_kernel, dim3(cdiv((long)N * ncol, 256)), dim3(256), 0, st, N,
+                       (int)ncol, m.rl, m.UU, (const int*)m.lr_param, (const int*)m.lr_kind, eta);
+    RM_CHECK_LAUNCH();
+    Gemm<double> z;
+    z.m = N; z.n = (int)(2 * ncol); z.k = N;
+    z.A = pt.Kinv; z.lda = N;
+    z.B = m.UU; z.ldb = N;
+    z.C = pt.ZZ; z.ldc = N;
+    gemm(z, st);
+  }
+  for (const auto& run : m.runs_h) {  // A_l = K^-1 K_l, and the transposed copies
     // A_l stays FP64 in both modes: K^-1 reaches 1/jitter while A_l is O(1),
     // so its entries come from heavy cancellation that FP32 operands and
     // accumulation cannot resolve.  Mixed mode takes the FP32 operands of the
     // later products (A_l, A_l' for the traces) from the same epilogue.
+    const int l0 = run.first, s0 = m.lr_slot_h[l0];
     Gemm<double> g;
-    g.m = N; g.n = N; g.k = N;
-    g.A = pt.Kinv; g.lda = N;
-    g.B = pt.K1; g.ldb = N; g.sB = NN;
-    g.C = pt.A; g.ldc = N; g.sC = NN;
-    g.batch = P;
+    g.m = N; g.n = N;
+    if (s0 < 0) {
+      g.k = N;
+      g.A = pt.Kinv; g.lda = N;
+      g.B = pt.K1 + l0 * NN; g.ldb = N; g.sB = NN;
+    } else {  // A_l = Zc_l U_l'
+      g.k = m.rl;
+      g.A = pt.ZZ + (ncol + (long)s0 * m.rl) * N; g.lda = N; g.sA = (long)m.rl * N;
+      g.B = m.UU + (long)s0 * m.rl * N; g.ldb = N; g.tB = true; g.sB = (long)m.rl * N;
+    }
+    g.C = pt.A + l0 * NN; g.ldc = N; g.sC = NN;
+    g.batch = run.second;
     if (!mixed) {
-      g.C2 = pt.At; g.ldc2 = N; g.sC2 = NN;
+      g.C2 = pt.At + l0 * NN; g.ldc2 = N; g.sC2 = NN;
     } else {
-      g.Co = pt.Af; g.sCo = NN;
-      g.ldc2 = N; g.C2o = pt.Atf; g.sC2o = NN;
+      g.Co = pt.Af + l0 * NN; g.sCo = NN;
+      g.ldc2 = N; g.C2o = pt.Atf + l0 * NN; g.sC2o = NN;
     }
     gemm(g, st);
   }
@@ -807,49 +920,84 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
   const int N = m.N, P = m.P;
   const long NN = (long)N * N;
   const double* eta = pt.q + N;
-  if (m.prec != RMHMC_MIXED) {
-    {  // B_l = A_l K^-1
-      Gemm<double> g;
-      g.m = N; g.n = N; g.k = N;
-      g.A = pt.A; g.lda = N; g.sA = NN;
+  const bool mixed = m.prec == RMHMC_MIXED;
+  const long ncol = (long)m.nlr * m.rl;
+  // B_l = A_l K^-1, FP64 in both modes: the product of an O(1) matrix with
+  // K^-1 (entries up to 1/jitter) cancels as heavily as A_l does.  For a
+  // low-rank l, B_l = K^-1 U_l C_l U_l' K^-1 = Zc_l Z_l'.
+  for (const auto& run : m.runs_h) {
+    const int l0 = run.first, s0 = m.lr_slot_h[l0];
+    Gemm<double> g;
+    g.m = N; g.n = N;
+    if (s0 < 0) {
+      g.k = N;
+      g.A = pt.A + l0 * NN; g.lda = N; g.sA = NN;
       g.B = pt.Kinv; g.ldb = N;
-      g.C = pt.B; g.ldc = N; g.sC = NN;
-      g.batch = P;
-      gemm(g, st);
+    } else {
+      g.k = m.rl;
+      g.A = pt.ZZ + (ncol + (long)s0 * m.rl) * N; g.lda = N; g.sA = (long)m.rl * N;
+      g.B = pt.ZZ + (long)s0 * m.rl * N; g.ldb = N; g.tB = true; g.sB = (long)m.rl * N;
     }
-    {  // Y_lm = A_l A_m (l <= m), stored transposed
+    g.C = pt.B + l0 * NN; g.ldc = N; g.sC = NN;
+    g.batch = run.second;
+    gemm(g, st);
+  }
+  // Y_lm = A_l A_m (formed pairs l <= m), stored transposed: pairs of two
+  // full-rank parameters by N^3 products (FP32 operands in mixed mode),
+  // the others by the thin products (FP64, rounded to FP32 in mixed mode)
+  if (m.nyf > 0) {
+    if (!mixed) {
       Gemm<double> g;
       g.m = N; g.n = N; g.k = N;
       g.Ap = pt.Yap; g.lda = N;
       g.Bp = pt.Ybp; g.ldb = N;
       g.C2p = pt.Ycp; g.ldc2 = N;
-      g.batch = m.nyy;
+      g.batch = m.nyf;
       gemm(g, st);
-    }
-    // tau[n, y] = tr(A_n A_l A_m) = <A_n, Y_lm'> for the formed pairs y = (l, m)
-    gemm_tallk(P, m.nyy, NN, pt.A, NN, pt.Yt, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
-  } else {
-    {  // B_l = A_l K^-1 in FP64: the product of an O(1) matrix with K^-1
-       // (entries up to 1/jitter) cancels as heavily as A_l does
-      Gemm<double> g;
-      g.m = N; g.n = N; g.k = N;
-      g.A = pt.A; g.lda = N; g.sA = NN;
-      g.B = pt.Kinv; g.ldb = N;
-      g.C = pt.B; g.ldc = N; g.sC = NN;
-      g.batch = P;
-      gemm(g, st);
-    }
-    {
+    } else {
       Gemm<float> g;
       g.m = N; g.n = N; g.k = N;
       g.Ap = pt.Yapf; g.lda = N;
       g.Bp = pt.Ybpf; g.ldb = N;
       g.C2p = pt.Ycpf; g.ldc2 = N;
-      g.batch = m.nyy;
+      g.batch = m.nyf;
       gemm(g, st);
     }
-    gemm_tallk(P, m.nyy, NN, pt.Af, NN, pt.Ytf, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
   }
+  if (m.nyl > 0) {  // G = A_m' U_l
+    Gemm<double> g;
+    g.m = N; g.n = m.rl; g.k = N;
+    g.Ap = pt.YLa; g.lda = N; g.tA = true;
+    g.Bp = pt.YLb; g.ldb = N;
+    g.Cp = pt.YLc; g.ldc = N;
+    g.batch = m.nyl;
+    gemm(g, st);
+  }
+  if (m.nyr > 0) {  // G = A_l Zc_m
+    Gemm<double> g;
+    g.m = N; g.n = m.rl; g.k = N;
+    g.Ap = pt.YRa; g.lda = N;
+    g.Bp = pt.YRb; g.ldb = N;
+    g.Cp = pt.YRc; g.ldc = N;
+    g.batch = m.nyr;
+    gemm(g, st);
+  }
+  if (m.nyl + m.nyr > 0) {  // Y' = G Zc_l' (l low rank), U_m G' (only m low rank)
+    Gemm<double> g;
+    g.m = N; g.n = N; g.k = m.rl;
+    g.Ap = pt.Y2a; g.lda = N;
+    g.Bp = pt.Y2b; g.ldb = N; g.tB = true;
+    g.ldc = N;
+    if (!mixed) g.Cp = pt.Y2c;
+    else g.Cop = reinterpret_cast<void* const*>(pt.Y2cf);
+    g.batch = m.nyl + m.nyr;
+    gemm(g, st);
+  }
+  // tau[n, y] = tr(A_n A_l A_m) = <A_n, Y_lm'> for the formed pairs y = (l, m)
+  if (!mixed)
+    gemm_tallk(P, m.nyy, NN, pt.A, NN, pt.Yt, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
+  else
+    gemm_tallk(P, m.nyy, NN, pt.Af, NN, pt.Ytf, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
   kd_matvec(m.md, eta, m.pairs, m.npairs, pt.alpha, 1, pt.k2a, m.mvwork, st);
   {
     Gemm<double> g;  // ik2a = K^-1 [K_lm alpha]
@@ -1083,17 +1231,72 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
     if (kind == RMHMC_K_SE_ISO || kind == RMHMC_K_SE_ARD) return true;
     return a == b && b == c;
   };
+  // low-rank derivatives: U columns per slot (parameter order)
+  m.lr_slot_h.assign(P, -1);
+  std::vector<std::vector<std::vector<double>>> lr_cols;
+  std::vector<int> lr_param_h, lr_kind_h;
+  for (int t = 0; t < md.nterms; ++t) {
+    const TermDev& T = md.terms[t];
+    auto xv = [&](int i, int c) { return d->X[(long)i * m.dx + c]; };
+    auto in_fn = [&](int i) { return T.fn < 0 || xv(i, md.fn_col) == (double)T.fn; };
+    if (T.kind == RMHMC_K_LINEAR_ARD) {
+      for (int a = 0; a < T.np; ++a) {
+        std::vector<double> u(m.N);
+        for (int i = 0; i < m.N; ++i) u[i] = in_fn(i) ? xv(i, T.cols[a]) : 0.0;
+        m.lr_slot_h[T.p0 + a] = (int)lr_cols.size();
+        lr_cols.push_back({u});
+        lr_param_h.push_back(T.p0 + a);
+        lr_kind_h.push_back(0);
+      }
+    } else if (T.kind == RMHMC_K_BINARY_SAME) {
+      std::vector<double> vals;
+      for (int i = 0; i < m.N && (int)vals.size() <= LR_MAX_RANK; ++i)
+        if (in_fn(i) && std::find(vals.begin(), vals.end(), xv(i, T.cols[0])) == vals.end())
+          vals.push_back(xv(i, T.cols[0]));
+      if ((int)vals.size() <= LR_MAX_RANK) {
+        std::vector<std::vector<double>> us;
+        for (double v : vals) {
+          std::vector<double> u(m.N);
+          for (int i = 0; i < m.N; ++i) u[i] = (in_fn(i) && xv(i, T.cols[0]) == v) ? 1.0 : 0.0;
+          us.push_back(u);
+        }
+        m.lr_slot_h[T.p0] = (int)lr_cols.size();
+        lr_cols.push_back(us);
+        lr_param_h.push_back(T.p0);
+        lr_kind_h.push_back(1);
+      }
+    }
+  }
+  m.nlr = (int)lr_cols.size();
+  m.rl = 0;
+  for (auto& c : lr_cols) m.rl = std::max(m.rl, (int)c.size());
+  for (int l = 0; l < P;) {
+    int e = l + 1;
+    while (e < P && (m.lr_slot_h[e] >= 0) == (m.lr_slot_h[l] >= 0)) ++e;
+    m.runs_h.push_back({l, e - l});
+    l = e;
+  }
   // tau_nlm = tr(A_n A_l A_m) is symmetric in all three indices (the trace
   // is cyclic, and transposing A_n A_l A_m with A_i = K^-1 K_i reverses the
-  // order), so Y_lm = A_l A_m is formed only for pairs within one half of
-  // the index range: of any three indices two share a half.  That is
-  // h(h+1)/2 + h'(h'+1)/2 products (56 for P = 14) instead of P(P+1)/2.
-  const int half = (P + 1) / 2;
+  // order), so Y_lm = A_l A_m is formed only for pairs within one of two
+  // sides of a split of the parameters: of any three indices two share a
+  // side.  The full-rank parameters alternate between the sides (and so do
+  // the low-rank ones), so the N^3 products (pairs of two full-rank
+  // parameters) split evenly: 12 of them for 6 full-rank parameters.
+  std::vector<int> side(P);
+  {
+    int nf = 0, nl = 0;
+    for (int l = 0; l < P; ++l) side[l] = (m.lr_slot_h[l] < 0 ? nf++ : nl++) & 1;
+  }
   int ny = 0;
+  m.nyf = m.nyl = m.nyr = 0;
   for (int l = 0; l < P; ++l)
     for (int mm = l; mm < P; ++mm)
-      if ((l < half) == (mm < half)) {
+      if (side[l] == side[mm]) {
         m.yidx_h[l * P + mm] = m.yidx_h[mm * P + l] = ny++;
+        if (m.lr_slot_h[l] >= 0) ++m.nyl;
+        else if (m.lr_slot_h[mm] >= 0) ++m.nyr;
+        else ++m.nyf;
       }
   m.nyy = ny;
   m.tauidx_h.assign(P * P * P, -1);
@@ -1145,6 +1348,20 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   RM_HIP(hipMemcpy(m.pidx, m.pidx_h.data(), P * P * sizeof(int), hipMemcpyHostToDevice));
   RM_HIP(hipMemcpy(m.tidx, m.tidx_h.data(), P * P * P * sizeof(int), hipMemcpyHostToDevice));
   RM_HIP(hipMemcpy(m.tauidx, m.tauidx_h.data(), P * P * P * sizeof(int), hipMemcpyHostToDevice));
+  if (m.nlr > 0) {
+    const long ncol = (long)m.nlr * m.rl;
+    std::vector<double> U((size_t)(N * ncol), 0.0);
+    for (int sl = 0; sl < m.nlr; ++sl)
+      for (size_t c = 0; c < lr_cols[sl].size(); ++c)
+        std::copy(lr_cols[sl][c].begin(), lr_cols[sl][c].end(), U.begin() + (sl * m.rl + c) * N);
+    m.UU = pl.alloc<double>(2 * N * ncol);
+    RM_HIP(hipMemcpy(m.UU, U.data(), U.size() * sizeof(double), hipMemcpyHostToDevice));
+    m.lr_param = pl.alloc<int>(m.nlr);
+    m.lr_kind = pl.alloc<int>(m.nlr);
+    RM_HIP(hipMemcpy(m.lr_param, lr_param_h.data(), m.nlr * sizeof(int), hipMemcpyHostToDevice));
+    RM_HIP(hipMemcpy(m.lr_kind, lr_kind_h.data(), m.nlr * sizeof(int), hipMemcpyHostToDevice));
+    m.Gy = pl.alloc<double>(std::max(1L, (long)(m.nyl + m.nyr) * N * m.rl));
+  }
   // scratch
   m.chol.L = pl.alloc<double>(NN);
   m.chol.Linv = pl.alloc<double>(NN);
