@@ -411,6 +411,26 @@ rmhmc_status rmhmc_gemm_f32(int m, int n, int k, float alpha, const float* A, in
 rmhmc_status rmhmc_gemm_f64_splitk(int m, int n, int k, const double* A, int lda, int transA,
                                    const double* B, int ldb, int transB, double* C, int ldc,
                                    double* work, int splits, hipStream_t stream);
+/* C (m x n, FP64, ld ldc) = A' B over a long inner dimension k, where A and
+ * B hold m and n columns of length k (column i of A at A + i * lda): the
+ * form of the traces tr(X Y) = <X, Y'> of products of N x N matrices
+ * (k = N^2) in the Hessian's hyperparameter block and the third-derivative
+ * tensor (Sec. 2.3).  With m <= 16, n <= 64, lda and ldb multiples of 4 and
+ * A, B aligned to four elements, a streaming kernel reads each operand once
+ * (one 16 x 16 MFMA tile per 16 columns of C); other shapes take the tiled
+ * kernel with the k range split into layers.  The k range is cut into at
+ * most `splits` (1..1024) chunks whose partials are added in a fixed order.
+ * A, B, C and `work` [device, caller-owned]; `work` holds splits * m * n
+ * elements of the operand type and is overwritten.  The _f32 form takes
+ * FP32 operands (FP32 products and chunk sums, FP64 total).  RMHMC_E_ARG for
+ * bad sizes, leading dimensions, NULL pointers or `splits`.  Asynchronous on
+ * `stream`. */
+rmhmc_status rmhmc_gemm_tallk_f64(int m, int n, long k, const double* A, long lda,
+                                  const double* B, long ldb, double* C, int ldc, double* work,
+                                  int splits, hipStream_t stream);
+rmhmc_status rmhmc_gemm_tallk_f32(int m, int n, long k, const float* A, long lda, const float* B,
+                                  long ldb, double* C, int ldc, float* work, int splits,
+                                  hipStream_t stream);
 
 /* Live per-kernel timing (instrumentation, off by default).  When enabled,
  * the launches of each kernel family below are bracketed by HIP events on

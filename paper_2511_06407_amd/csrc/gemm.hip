@@ -246,6 +246,78 @@ __global__ __launch_bounds__(256) void splitk_reduce(int m, int n, int splits,
   }
 }
 
+// Tall-k products with a small output (m <= 16, n <= 16 NT): partials of
+// C = A' B over one k chunk per workgroup, for the traces of products of
+// N x N matrices (k = N^2).  One 16 x 16 MFMA tile per 16 output columns, no
+// LDS staging: lane l streams four consecutive k of operand row l mod 16
+// (one 16- or 32-byte load), and the four MFMAs of a 16-long k step take one
+// of those k each, so that each chunk of A and B is read once.  The waves
+// take interleaved 16-long steps of the chunk; their sums are added in a
+// fixed order (deterministic).  Partials as the tiled kernel's split-K:
+// part[kc * m * n + i + j * m].
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void tallk_small_kernel(int m, int n, long k,
+                                                          const T* __restrict__ A, long lda,
+                                                          const T* __restrict__ B, long ldb,
+                                                          long kchunk, T* __restrict__ part) {
+  typedef typename Mfma<T>::v4 v4;
+  typedef T t4 __attribute__((ext_vector_type(4)));
+  __shared__ v4 red[3][NT][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, q = lane >> 4;
+  const long kbeg = (long)blockIdx.x * kchunk, kend = min(k, kbeg + kchunk);
+  v4 acc[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) acc[j] = v4{0, 0, 0, 0};
+  const bool am = r16 < m;
+  const T* Ar = A + (long)(am ? r16 : 0) * lda;
+  const T* Br[NT];
+  bool bn[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    bn[j] = 16 * j + r16 < n;
+    Br[j] = B + (long)(bn[j] ? 16 * j + r16 : 0) * ldb;
+  }
+  long k0 = kbeg + 16L * wave;
+  for (; k0 + 16 <= kend; k0 += 64) {
+    const long kk = k0 + 4 * q;
+    const t4 a = am ? *reinterpret_cast<const t4*>(Ar + kk) : t4{0, 0, 0, 0};
+    t4 b[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) b[j] = bn[j] ? *reinterpret_cast<const t4*>(Br[j] + kk) : t4{0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[j] = Mfma<T>::op(b[j][t], a[t], acc[j]);
+  }
+  if (k0 < kend) {   // a last step shorter than 16
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const long kt = k0 + 4 * q + t;
+      const bool in = kt < kend;
+      const T a = (am && in) ? Ar[kt] : T(0);
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[j] = Mfma<T>::op((bn[j] && in) ? Br[j][kt] : T(0), a, acc[j]);
+    }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int j = 0; j < NT; ++j) red[wave - 1][j][lane] = acc[j];
+  }
+  __syncthreads();
+  if (wave > 0) return;
+  T* out = part + (long)blockIdx.x * m * n;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const v4 s = ((acc[j] + red[0][j][lane]) + red[1][j][lane]) + red[2][j][lane];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int jn = 16 * j + Mfma<T>::row(lane, r);
+      if (am && jn < n) out[r16 + (long)jn * m] = s[r];
+    }
+  }
+}
+
 // C = sum over a few split-K partials, one thread per output element, the
 // splits added in order (deterministic).  For wide outputs with few splits.
 __global__ __launch_bounds__(256) void splitk_sum(int m, int n, int splits,
@@ -309,6 +381,30 @@ template <typename T>
 void tallk_impl(int m, int n, long k, const T* A, long lda, const T* B, long ldb, double* C,
                 long ldc, double* work, int splits, hipStream_t st) {
   if (m <= 0 || n <= 0) return;
+  const uintptr_t align = 4 * sizeof(T);
+  if (m <= 16 && n <= 64 && lda % 4 == 0 && ldb % 4 == 0 && (uintptr_t)A % align == 0 &&
+      (uintptr_t)B % align == 0) {
+    // small output: the streaming kernel, k chunks of a multiple of 64
+    long chunk = ((k + splits - 1) / splits + 63) / 64 * 64;
+    if (chunk < 64) chunk = 64;
+    const int sp = (int)((k + chunk - 1) / chunk);
+    T* part = reinterpret_cast<T*>(work);
+    const int nt = cdiv(n, 16);
+    const int slot = timing_begin(sizeof(T) == 8 ? TK_GEMM_F64 : TK_GEMM_F32, st);
+    if (nt == 1)
+      hipLaunchKernelGGL((tallk_small_kernel<T, 1>), dim3(sp), dim3(256), 0, st, m, n, k, A, lda, B, ldb, chunk, part);
+    else if (nt == 2)
+      hipLaunchKernelGGL((tallk_small_kernel<T, 2>), dim3(sp), dim3(256), 0, st, m, n, k, A, lda, B, ldb, chunk, part);
+    else
+      hipLaunchKernelGGL((tallk_small_kernel<T, 4>), dim3(sp), dim3(256), 0, st, m, n, k, A, lda, B, ldb, chunk, part);
+    RM_CHECK_LAUNCH();
+    if (slot >= 0) timing_end(slot, st, 2.0 * m * n * (double)k, (double)(m + n) * k * sizeof(T));
+    const long mn = (long)m * n;
+    hipLaunchKernelGGL((splitk_reduce<T>), dim3(cdiv(mn, 4)), dim3(256), 0, st, m, n, sp,
+                       (const T*)part, C, ldc);
+    RM_CHECK_LAUNCH();
+    return;
+  }
   Params<T> p{};
   p.m = m; p.n = n; p.k = (int)k; p.alpha = 1; p.beta = 0;
   RM_REQUIRE(k < (1L << 31), "gemm_tallk: k too large");

@@ -662,6 +662,17 @@ size_t point_bytes(const Model& m) {
   return (c.off + 255) & ~size_t(255);
 }
 
+// A product with a thin output (a few 64 x 64 tiles) over a long k range
+// leaves most of the chip idle: its k range is split over up to 16 layers of
+// workgroups (partials in the model's split-K space, added in order).
+void thin_gemm(Model& m, const Gemm<double>& g, hipStream_t st) {
+  const long tiles = (long)cdiv(g.m, 64) * cdiv(g.n, 64);
+  const long room = (long)GSPLIT_MAX * std::max<long>((long)m.Dp * m.Dp, (long)m.N * m.N) /
+                    std::max<long>(1, (long)g.m * g.n);
+  const int sp = (int)std::max<long>(1, std::min<long>({16L, 256 / std::max(tiles, 1L), room}));
+  gemm_splitk(g, m.gsplit, sp, st);
+}
+
 std::unique_ptr<Point> new_point(Model& m) {
   auto pt = std::make_unique<Point>();
   Point& p = *pt;
@@ -808,7 +819,7 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st, int* fail) {
     z.A = pt.Kinv; z.lda = N;
     z.B = m.UU; z.ldb = N;
     z.C = pt.ZZ; z.ldc = N;
-    gemm(z, st);
+    thin_gemm(m, z, st);
   }
   for (const auto& run : m.runs_h) {  // A_l = K^-1 K_l, and the transposed copies
     // A_l stays FP64 in both modes: K^-1 reaches 1/jitter while A_l is O(1),
@@ -1005,7 +1016,7 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
     g.A = pt.Kinv; g.lda = N;
     g.B = pt.k2a; g.ldb = N;
     g.C = pt.ik2a; g.ldc = N;
-    gemm(g, st);
+    thin_gemm(m, g, st);
   }
   {
     Gemm<double> g;  // c1a[l] = K_l [a_0 .. a_P-1]
@@ -1050,7 +1061,7 @@ void contract(Model& m, Point& pt, const double* W, double* v, hipStream_t st) {
     g.A = pt.Kinv; g.lda = N;
     g.B = W + (long)N * Dp; g.ldb = Dp;
     g.C = m.u; g.ldc = N;
-    gemm(g, st);
+    thin_gemm(m, g, st);
   }
   gemv(N, N, 1.0, pt.K1, N, true, NN, m.u, N, 0.0, m.Ku, N, P, st);      // K_l u_l
   gemv(N, N, 1.0, pt.Kinv, N, true, 0, m.Ku, N, 0.0, m.Au, N, P, st);     // A_l u_l = K^-1 K_l u_l
@@ -2214,6 +2225,20 @@ void softabs_eig_impl(EigWork& w, int D, const double* H, int ldh, double alpha,
 
 }  // namespace
 
+template <typename T>
+rmhmc_status tallk_entry(int m, int n, long k, const T* A, long lda, const T* B, long ldb,
+                         double* C, int ldc, T* work, int splits, hipStream_t st) {
+  return guard([&] {
+    RM_REQUIRE(m >= 0 && n >= 0 && k >= 0, "negative dimension");
+    RM_REQUIRE(A && B && C && work, "NULL matrix or workspace");
+    RM_REQUIRE(splits >= 1 && splits <= 1024, "splits must be in [1, 1024]");
+    RM_REQUIRE(k < (1L << 31), "k too large");
+    RM_REQUIRE(lda >= std::max(1L, k) && ldb >= std::max(1L, k), "lda or ldb too small");
+    RM_REQUIRE(ldc >= std::max(1, m), "ldc too small");
+    gemm_tallk(m, n, k, A, lda, B, ldb, C, ldc, reinterpret_cast<double*>(work), splits, st);
+  });
+}
+
 extern "C" {
 
 const char* rmhmc_last_error(void) { return g_last_error.c_str(); }
@@ -2245,6 +2270,17 @@ rmhmc_status rmhmc_gemm_f64_splitk(int m, int n, int k, const double* A, int lda
     g.C = C; g.ldc = ldc;
     gemm_splitk(g, work, splits, st);
   });
+}
+
+rmhmc_status rmhmc_gemm_tallk_f64(int m, int n, long k, const double* A, long lda,
+                                  const double* B, long ldb, double* C, int ldc, double* work,
+                                  int splits, hipStream_t st) {
+  return tallk_entry<double>(m, n, k, A, lda, B, ldb, C, ldc, work, splits, st);
+}
+rmhmc_status rmhmc_gemm_tallk_f32(int m, int n, long k, const float* A, long lda, const float* B,
+                                  long ldb, double* C, int ldc, float* work, int splits,
+                                  hipStream_t st) {
+  return tallk_entry<float>(m, n, k, A, lda, B, ldb, C, ldc, work, splits, st);
 }
 
 rmhmc_status rmhmc_model_create(const rmhmc_model_desc* desc, rmhmc_precision prec,

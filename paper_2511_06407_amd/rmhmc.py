@@ -42,7 +42,8 @@ EXPORTED = ["rmhmc_model_create", "rmhmc_model_dims", "rmhmc_model_destroy", "rm
             "rmhmc_softabs_eig_reserve", "rmhmc_chain_randoms", "rmhmc_softabs_eig_noalloc",
             "rmhmc_batch_create", "rmhmc_batch_admit", "rmhmc_batch_step", "rmhmc_batch_sync",
             "rmhmc_batch_retire", "rmhmc_batch_destroy", "rmhmc_model_set_beta",
-            "rmhmc_log_likelihood", "rmhmc_basis_model_create"]
+            "rmhmc_log_likelihood", "rmhmc_basis_model_create", "rmhmc_gemm_tallk_f64",
+            "rmhmc_gemm_tallk_f32"]
 
 TIMER_KINDS = {"gemm_f64": 0, "gemm_f32": 1, "jacobi_round": 2, "jacobi_round_static": 3, "kd_wsum": 4,
                "kd_matvec": 5, "potrf_diag": 6}
@@ -131,6 +132,8 @@ _sig = {
     "rmhmc_gemm_f64": [_i, _i, _i, _d, _vp, _i, _i, _vp, _i, _i, _d, _vp, _i, _vp],
     "rmhmc_gemm_f64_splitk": [_i, _i, _i, _vp, _i, _i, _vp, _i, _i, _vp, _i, _vp, _i, _vp],
     "rmhmc_gemm_f32": [_i, _i, _i, C.c_float, _vp, _i, _i, _vp, _i, _i, C.c_float, _vp, _i, _vp],
+    "rmhmc_gemm_tallk_f64": [_i, _i, C.c_long, _vp, C.c_long, _vp, C.c_long, _vp, _i, _vp, _i, _vp],
+    "rmhmc_gemm_tallk_f32": [_i, _i, C.c_long, _vp, C.c_long, _vp, C.c_long, _vp, _i, _vp, _i, _vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -194,6 +197,19 @@ def gemm_splitk_colmajor(m, n, k, A, lda, tA, B, ldb, tB, Cm, ldc, work, splits,
     """C = op(A) op(B) in FP64 with the k range split over `splits` layers."""
     _check(_lib.rmhmc_gemm_f64_splitk(m, n, k, _f64(A), lda, int(tA), _f64(B), ldb, int(tB),
                                       _f64(Cm), ldc, _f64(work), splits, _stream(stream)))
+
+
+def gemm_tallk(m, n, k, A, lda, B, ldb, Cm, ldc, work, splits, stream=None):
+    """C (FP64) = A' B over a long k: A, B hold m and n columns of length k
+    (FP64 or FP32 operands, `work` of the operand type)."""
+    torch = _torch()
+    if A.dtype == torch.float64:
+        _check(_lib.rmhmc_gemm_tallk_f64(m, n, k, _f64(A), lda, _f64(B), ldb, _f64(Cm), ldc,
+                                         _f64(work), splits, _stream(stream)))
+    else:
+        f32 = torch.float32
+        _check(_lib.rmhmc_gemm_tallk_f32(m, n, k, _ptr(A, f32), lda, _ptr(B, f32), ldb, _f64(Cm),
+                                         ldc, _ptr(work, f32), splits, _stream(stream)))
 
 
 class Model:

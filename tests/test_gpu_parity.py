@@ -131,6 +131,37 @@ def test_gemm_splitk(rm, shape, splits, tA, tB):
     assert np.array_equal(host(Ct)[:, m:], Cm[:, m:])
 
 
+# Tall-k products C = A' B (the trace form): (14, 56) and (14, 14) are the
+# trace shapes at P = 14 (four and one 16-column tiles), (16, 17) two tiles;
+# odd k leaves a last step shorter than 16 in the last chunk; (20, 30) has
+# more than 16 rows and an odd leading dimension takes the tiled kernel.
+@pytest.mark.parametrize("m,n,k,pad,splits", [(14, 56, 40007, 0, 64), (14, 14, 65536, 0, 512),
+                                              (16, 17, 3003, 4, 7), (5, 64, 999, 0, 3),
+                                              (20, 30, 5000, 0, 16), (14, 20, 4001, 1, 8)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gemm_tallk(rm, m, n, k, pad, splits, dtype):
+    rng = np.random.default_rng(m * 7 + n * 13 + k + pad)
+    ld = k + pad
+    A = rng.standard_normal((m, ld))
+    B = rng.standard_normal((n, ld))
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":
+        A, B = A.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64)
+    want = A[:, :k] @ B[:, :k].T
+    At = torch.tensor(A, dtype=tdt, device="cuda")
+    Bt = torch.tensor(B, dtype=tdt, device="cuda")
+    Ct = torch.full((n, m + 2), np.nan, dtype=torch.float64, device="cuda")
+    work = torch.full((splits * m * n,), np.nan, dtype=tdt, device="cuda")
+    rm.gemm_tallk(m, n, k, At, ld, Bt, ld, Ct, m + 2, work, splits)
+    got = host(Ct)[:, :m].T
+    err = rel(got, want)
+    record("gemm_tallk", m=m, n=n, k=k, pad=pad, splits=splits, dtype=dtype, err=err)
+    # FP32: products rounded to FP32 and summed in FP32 within 16-long steps
+    # and chunks of at most k / splits terms
+    assert err < (1e-13 if dtype == "f64" else 1e-5)
+    assert np.all(np.isnan(host(Ct)[:, m:]))
+
+
 # ---------------------------------------------------------------- Hessian
 def floor_hessian(spec, q, ref):
     s2, q2, full = permuted(spec, q)
