@@ -278,8 +278,12 @@ __global__ __launch_bounds__(256) void trsm_panel_kernel(int n, int k0, int bw, 
 // identity, so they factor trivially.  The inverse of the triangle is not
 // needed until the factorisation is complete and is formed afterwards for
 // every diagonal block at once (trtri_diag_kernel), off this chain.
-__global__ __launch_bounds__(256) void potrf_diag_kernel(int n, int k0, double* L, long ldl,
-                                                         double* diagLogs, int* info) {
+// (The block comes from registers: potrf_block is shared with the fused
+// trailing update below, which factors the next diagonal block in place.)
+// All 256 threads call it; sv[m] = S[i][g + 4m] on entry, only the lower
+// triangle of S is used.
+__device__ __forceinline__ void potrf_block(int n, int k0, double (&sv)[CB / 4], double* L,
+                                            long ldl, double* diagLogs, int* info) {
   constexpr int NM = CB / 4;
   __shared__ double col[2][CB];
   __shared__ double dg[CB];
@@ -288,12 +292,6 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int n, int k0, double* 
   const int i = tid & (CB - 1);
   const int g = __builtin_amdgcn_readfirstlane(tid >> 6);
   __builtin_assume(g >= 0 && g < 4);
-  double sv[NM];
-#pragma unroll
-  for (int m = 0; m < NM; ++m) {
-    const int k = g + 4 * m;
-    sv[m] = (i < w && k < w) ? L[(k0 + i) + (long)(k0 + k) * ldl] : (i == k ? 1.0 : 0.0);
-  }
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < CB; ++j) {
@@ -319,6 +317,114 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int n, int k0, double* 
   }
   if (tid < w) diagLogs[k0 + tid] = 0.5 * log(dg[tid]);
   if (tid == 0 && bad) *info = k0 + 1;
+}
+
+__global__ __launch_bounds__(256) void potrf_diag_kernel(int n, int k0, double* L, long ldl,
+                                                         double* diagLogs, int* info) {
+  constexpr int NM = CB / 4;
+  const int w = min(CB, n - k0);
+  const int i = threadIdx.x & (CB - 1);
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double sv[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    const int k = g + 4 * m;
+    sv[m] = (i < w && k < w) ? L[(k0 + i) + (long)(k0 + k) * ldl] : (i == k ? 1.0 : 0.0);
+  }
+  potrf_block(n, k0, sv, L, ldl, diagLogs, info);
+}
+
+// Trailing update of the blocked Cholesky after the panel of block k0:
+// S[r0:, r0:] -= P P' (P = L[r0:, k0:k0+CB], solved), lower 64 x 64 tiles
+// only (the upper triangle of L is cleared at the end), one workgroup per
+// tile (I >= J) on v_mfma_f64_16x16x4f64 (a 32 x 32 quadrant per wave, both
+// 64 x 64 panel pieces in LDS).  Workgroup 0 owns the next diagonal block:
+// it keeps its updated tile on chip and factors it at once (potrf_block),
+// so the factorisation of block r0 needs no launch of its own.
+__global__ __launch_bounds__(256) void chol_update_kernel(int n, int k0, double* L,
+                                                          double* diagLogs, int* info) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int PAD = 4;
+  __shared__ double Ps[2][CB][CB + PAD];   // Ps[0][k][m] = P[64 I + m][k], Ps[1]: P_J
+  const int r0 = k0 + CB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  // tile (I, J), I >= J, from the workgroup index b = I (I + 1) / 2 + J
+  const int b = blockIdx.x;
+  int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= b) ++I;
+  while (I * (I + 1) / 2 > b) --I;
+  const int J = b - I * (I + 1) / 2;
+  const int ri = r0 + CB * I, rj = r0 + CB * J;
+  // P pieces: rows ri.. and rj.., columns k0..k0+63 (coalesced down columns)
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int m = e % CB, k = e / CB;
+    const double* Pc = L + (long)(k0 + k) * n;
+    Ps[0][k][m] = ri + m < n ? Pc[ri + m] : 0.0;
+    Ps[1][k][m] = rj + m < n ? Pc[rj + m] : 0.0;
+  }
+  __syncthreads();
+  d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = d4{0, 0, 0, 0};
+#pragma unroll 4
+  for (int kq = 0; kq < CB / 4; ++kq) {
+    const int kr = 4 * kq + (lane >> 4);
+    double av[2], bv[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      av[t] = Ps[0][kr][wm * 32 + t * 16 + (lane & 15)];
+      bv[t] = Ps[1][kr][wn * 32 + t * 16 + (lane & 15)];
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
+  }
+  // acc[ti][tj][r] = (P_I P_J')(m, c), m = wm 32 + ti 16 + lane % 16,
+  // c = wn 32 + tj 16 + lane / 16 + 4 r
+  if (b != 0) {
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gm = ri + wm * 32 + ti * 16 + (lane & 15);
+          const int gc = rj + wn * 32 + tj * 16 + (lane >> 4) + 4 * r;
+          if (gm < n && gc < n) L[gm + (long)gc * n] -= acc[ti][tj][r];
+        }
+    return;
+  }
+  // workgroup 0: the next diagonal block, updated on chip, then factored
+  double (*S)[CB + PAD] = Ps[0];
+  __syncthreads();   // every wave is done reading Ps
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = wm * 32 + ti * 16 + (lane & 15);
+        const int c = wn * 32 + tj * 16 + (lane >> 4) + 4 * r;
+        const double v = (r0 + m < n && r0 + c < n) ? L[(r0 + m) + (long)(r0 + c) * n] : 0.0;
+        S[m][c] = v - acc[ti][tj][r];
+      }
+  __syncthreads();
+  constexpr int NM = CB / 4;
+  const int w = min(CB, n - r0);
+  const int i = tid & (CB - 1);
+  const int g = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double sv[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    const int k = g + 4 * m;
+    sv[m] = (i < w && k < w) ? S[i][k] : (i == k ? 1.0 : 0.0);
+  }
+  potrf_block(n, r0, sv, L, (long)n, diagLogs, info);
 }
 
 // Inverse of every diagonal block's triangle (one workgroup per block):
@@ -480,23 +586,22 @@ void chol_inverse(int n, const double* K, double* Kinv, double* logdet, CholWork
   fill(w.Linv, nn, 0.0, st);
   fill_int(w.info, 1, 0, st);
   const int nb = cdiv(n, CB);
-  for (int kb = 0; kb < nb; ++kb) {
-    const int k0 = kb * CB, bw = std::min(CB, n - k0), r0 = k0 + bw, rm = n - r0;
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, n, k0, w.L, (long)n,
-                       w.diagLogs, w.info);
-    RM_CHECK_LAUNCH();
-    if (rm <= 0) break;
-    // panel: L[r0:, k0:k0+bw] <- L[r0:, k0:k0+bw] L_kk^-T by substitution
-    hipLaunchKernelGGL(trsm_panel_kernel, dim3(cdiv(rm, 256)), dim3(256), 0, st, n, k0, bw, r0,
+  // block 0 on its own; every later diagonal block is factored by the
+  // trailing update that precedes it (chol_update_kernel, workgroup 0)
+  hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, n, 0, w.L, (long)n, w.diagLogs,
+                     w.info);
+  RM_CHECK_LAUNCH();
+  for (int kb = 0; kb + 1 < nb; ++kb) {
+    const int k0 = kb * CB, r0 = k0 + CB, rm = n - r0;
+    // panel: L[r0:, k0:k0+CB] <- L[r0:, k0:k0+CB] L_kk^-T by substitution
+    hipLaunchKernelGGL(trsm_panel_kernel, dim3(cdiv(rm, 256)), dim3(256), 0, st, n, k0, CB, r0,
                        w.L);
     RM_CHECK_LAUNCH();
-    // trailing: L[r0:, r0:] -= P P'
-    Gemm<double> t;
-    t.m = rm; t.n = rm; t.k = bw; t.alpha = -1.0; t.beta = 1.0;
-    t.A = w.L + r0 + (long)k0 * n; t.lda = n;
-    t.B = w.L + r0 + (long)k0 * n; t.ldb = n; t.tB = true;
-    t.C = w.L + r0 + (long)r0 * n; t.ldc = n;
-    gemm(t, st);
+    // trailing: L[r0:, r0:] -= P P' (lower tiles), then block r0 factored
+    const int T = cdiv(rm, CB);
+    hipLaunchKernelGGL(chol_update_kernel, dim3(T * (T + 1) / 2), dim3(256), 0, st, n, k0, w.L,
+                       w.diagLogs, w.info);
+    RM_CHECK_LAUNCH();
   }
   hipLaunchKernelGGL(zero_upper_kernel, dim3(cdiv(nn, 256)), dim3(256), 0, st, n, w.L, (long)n);
   RM_CHECK_LAUNCH();
