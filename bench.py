@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--workers", type=int, default=8, help="streams (graph) or workers (pool)")
     ap.add_argument("--engine", choices=["graph", "pool"], default="pool",
                     help="tempered mode: graph-captured batch or eager worker pool")
-    ap.add_argument("--rate", type=float, default=2.0, help="requests/s (serving)")
+    ap.add_argument("--rate", type=float, default=4.0, help="requests/s (serving)")
     ap.add_argument("--duration", type=float, default=10.0,
                     help="arrival window in s (serving; 0 leaves the serving block out)")
     ap.add_argument("--moves-scale", type=float, default=0.01,
