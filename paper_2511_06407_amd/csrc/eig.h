@@ -66,9 +66,12 @@ JacobiResult jacobi_eig(int D, EigWork& w, double zeta, double gfloor, int max_s
 // One Newton-Schulz step Psi <- Psi (3I - Psi'Psi) / 2 on the D x D block of
 // a Dp-strided basis: removes the rounding drift from orthogonality to second
 // order.  T1, T2: Dp x Dp scratch.
-void orthonormalise(int D, int Dp, double* Psi, double* T1, double* T2, hipStream_t st);
+// (split: optional split-K partials, nsplit x D x D, for the D x D products)
+void orthonormalise(int D, int Dp, double* Psi, double* T1, double* T2, hipStream_t st,
+                    double* split = nullptr, int nsplit = 1);
 
-void rayleigh_refine(int D, const double* H, long ldh, EigWork& w, double* Z, hipStream_t st);
+void rayleigh_refine(int D, const double* H, long ldh, EigWork& w, double* Z, hipStream_t st,
+                     double* split = nullptr, int nsplit = 1);
 // lam = diag(M); g, g' and log|G| of the softabs map `kind` (rmhmc_softabs).
 void softabs_finalize(int D, const double* M, long ldm, double alpha, int kind, double* lam,
                       double* g, double* gp, double* logdetG, hipStream_t st);

@@ -1077,13 +1077,14 @@ __global__ void ns_coeff_kernel(int D, int Dp, double* __restrict__ G) {
 }
 }  // namespace
 
-void orthonormalise(int D, int Dp, double* Psi, double* T1, double* T2, hipStream_t st) {
+void orthonormalise(int D, int Dp, double* Psi, double* T1, double* T2, hipStream_t st,
+                    double* split, int nsplit) {
   Gemm<double> g;
   g.m = D; g.n = D; g.k = D;
   g.A = Psi; g.lda = Dp; g.tA = true;
   g.B = Psi; g.ldb = Dp;
   g.C = T1; g.ldc = Dp;
-  gemm(g, st);
+  gemm_splitk(g, split, split ? nsplit : 1, st);
   hipLaunchKernelGGL(ns_coeff_kernel, dim3(cdiv((long)D * D, 256)), dim3(256), 0, st, D, Dp, T1);
   RM_CHECK_LAUNCH();
   Gemm<double> h;
@@ -1091,7 +1092,7 @@ void orthonormalise(int D, int Dp, double* Psi, double* T1, double* T2, hipStrea
   h.A = Psi; h.lda = Dp;
   h.B = T1; h.ldb = Dp;
   h.C = T2; h.ldc = Dp;
-  gemm(h, st);
+  gemm_splitk(h, split, split ? nsplit : 1, st);
   copy_matrix(D, D, T2, Dp, Psi, Dp, st);
 }
 
@@ -1109,7 +1110,8 @@ void eig_load_basis(int D, const double* Q, long ldq, EigWork& w, hipStream_t st
   RM_CHECK_LAUNCH();
 }
 
-void rayleigh_refine(int D, const double* H, long ldh, EigWork& w, double* Z, hipStream_t st) {
+void rayleigh_refine(int D, const double* H, long ldh, EigWork& w, double* Z, hipStream_t st,
+                     double* split, int nsplit) {
   // Z = H Psi on the leading D x D block, then diag(M) <- column dots
   const int Dp = eig_padded_dim(D);
   Gemm<double> g;
@@ -1117,7 +1119,7 @@ void rayleigh_refine(int D, const double* H, long ldh, EigWork& w, double* Z, hi
   g.A = H; g.lda = ldh;
   g.B = w.Psi; g.ldb = Dp;
   g.C = Z; g.ldc = Dp;
-  gemm(g, st);
+  gemm_splitk(g, split, split ? nsplit : 1, st);
   hipLaunchKernelGGL(rayleigh_kernel, dim3(D), dim3(256), 0, st, D, Dp, (const double*)w.Psi,
                      (const double*)Z, w.M);
   RM_CHECK_LAUNCH();

@@ -892,7 +892,7 @@ JacobiResult compute_eig(Model& m, Point& pt, const Point* warm, double alpha, c
     eig_load_basis(D, nullptr, Dp, m.eig, st);
   } else {
     copy(m.eig.Psi, warm->Psi, (long)Dp * Dp, st);
-    if (reorth) orthonormalise(D, Dp, m.eig.Psi, m.Wt1, m.Wt2, st);
+    if (reorth) orthonormalise(D, Dp, m.eig.Psi, m.Wt1, m.Wt2, st, m.gsplit, m.gsplit_layers);
     // M = Psi_w' H Psi_w
     Gemm<double> g;
     g.m = Dp; g.n = Dp; g.k = Dp;
@@ -916,8 +916,8 @@ JacobiResult compute_eig(Model& m, Point& pt, const Point* warm, double alpha, c
   if (warm && ec.host_check && ec.max_seen && r.sweeps > *ec.max_seen) *ec.max_seen = r.sweeps;
   // a static solve accumulates one rounding per rotation into Psi: restore
   // orthogonality before the eigenvalues are refined against H
-  if (!warm) orthonormalise(D, Dp, m.eig.Psi, m.Wt1, m.Wt2, st);
-  rayleigh_refine(D, pt.H, Dp, m.eig, m.Wt2, st);
+  if (!warm) orthonormalise(D, Dp, m.eig.Psi, m.Wt1, m.Wt2, st, m.gsplit, m.gsplit_layers);
+  rayleigh_refine(D, pt.H, Dp, m.eig, m.Wt2, st, m.gsplit, m.gsplit_layers);
   copy(pt.Psi, m.eig.Psi, (long)Dp * Dp, st);
   softabs_finalize(D, m.eig.M, Dp, alpha, ec.softabs, pt.lam, pt.g, pt.gp, pt.scal + 2, st);
   pt.have_eig = true;
