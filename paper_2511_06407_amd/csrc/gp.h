@@ -37,9 +37,11 @@ void kgen(const ModelDev& md, const double* eta, double* K, double* K1, hipStrea
 // out[w * nt + t] = sum_ij Wgt_w(i,j) * d^ord K / d eta_tuple(i,j).
 // mode 0: one weight Phi = (K^-1 - alpha alpha')/2 built from Kinv and alpha;
 // mode 1: nw weights from a stack (stride N*N).
-void kd_wsum(const ModelDev& md, const double* eta, const Tuple* tuples, int nt, int mode,
-             const double* Kinv, const double* alpha, const double* Wstack, int nw, double* out,
-             double* work, hipStream_t st);
+// tuples: on the device; tuples_h: the same list on the host (its terms set
+// the passes).
+void kd_wsum(const ModelDev& md, const double* eta, const Tuple* tuples, const Tuple* tuples_h,
+             int nt, int mode, const double* Kinv, const double* alpha, const double* Wstack,
+             int nw, double* out, double* work, hipStream_t st);
 
 // out[w * nt + t] = sum_ij W_w(i,j) * d^ord K / d eta_tuple(i,j) for nw weights
 // from a stack (stride N*N): the tuple derivatives are generated once into

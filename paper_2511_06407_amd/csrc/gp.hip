@@ -18,47 +18,68 @@ struct TermVals {
   double u[RMHMC_MAX_TERM_COLS];
 };
 
+// Every loop below runs over compile-time bounds and every array is indexed
+// by compile-time indices or through select(), so the per-element values
+// stay in registers (a runtime index into a register array puts it in
+// scratch memory, one memory round trip per access).
+template <int NS>
+__device__ __forceinline__ double select(const double (&v)[NS], int k) {
+  double r = 0.0;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) r = (q == k) ? v[q] : r;
+  return r;
+}
+
 __device__ __forceinline__ void term_eval(const ModelDev& md, const double* __restrict__ eta,
                                           int t, int i, int j, TermVals& tv) {
   const TermDev& T = md.terms[t];
   const double* X = md.X;
   const int N = md.N;
+  tv.Kt = 0.0;
+#pragma unroll
+  for (int c = 0; c < RMHMC_MAX_TERM_COLS; ++c) tv.u[c] = 0.0;
   if (T.fn >= 0) {
     // a term of one latent function's prior acts only between its points:
     // the term and every derivative of it vanish elsewhere
     const double* F = X + (long)md.fn_col * N;
-    if (F[i] != (double)T.fn || F[j] != (double)T.fn) {
-      tv.Kt = 0.0;
-      for (int c = 0; c < RMHMC_MAX_TERM_COLS; ++c) tv.u[c] = 0.0;
-      return;
-    }
+    if (F[i] != (double)T.fn || F[j] != (double)T.fn) return;
   }
   if (T.kind == RMHMC_K_SE_ISO) {
     double r2 = 0.0;
-    for (int c = 0; c < T.ncols; ++c) {
-      const double d = X[(long)T.cols[c] * N + i] - X[(long)T.cols[c] * N + j];
-      r2 += d * d;
+#pragma unroll
+    for (int c = 0; c < RMHMC_MAX_TERM_COLS; ++c) {
+      if (c < T.ncols) {
+        const double d = X[(long)T.cols[c] * N + i] - X[(long)T.cols[c] * N + j];
+        r2 += d * d;
+      }
     }
     const double u = r2 * exp(-2.0 * eta[T.p0 + 1]);
     tv.u[0] = u;
     tv.Kt = exp(2.0 * eta[T.p0] - 0.5 * u);
   } else if (T.kind == RMHMC_K_SE_ARD) {
     double su = 0.0;
-    for (int c = 0; c < T.ncols; ++c) {
-      const double d = X[(long)T.cols[c] * N + i] - X[(long)T.cols[c] * N + j];
-      const double u = d * d * exp(-2.0 * eta[T.p0 + 1 + c]);
-      tv.u[c] = u;
-      su += u;
+#pragma unroll
+    for (int c = 0; c < RMHMC_MAX_TERM_COLS; ++c) {
+      if (c < T.ncols) {
+        const double d = X[(long)T.cols[c] * N + i] - X[(long)T.cols[c] * N + j];
+        const double u = d * d * exp(-2.0 * eta[T.p0 + 1 + c]);
+        tv.u[c] = u;
+        su += u;
+      }
     }
     tv.Kt = exp(2.0 * eta[T.p0] - 0.5 * su);
   } else if (T.kind == RMHMC_K_LINEAR_ARD) {
-    double s = 0.0;
-    for (int c = 0; c < T.ncols; ++c) {
-      const double v = exp(eta[T.p0 + c]) * X[(long)T.cols[c] * N + i] * X[(long)T.cols[c] * N + j];
-      tv.u[c] = v;
-      s += v;
+    double s2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < RMHMC_MAX_TERM_COLS; ++c) {
+      if (c < T.ncols) {
+        const double v =
+            exp(eta[T.p0 + c]) * X[(long)T.cols[c] * N + i] * X[(long)T.cols[c] * N + j];
+        tv.u[c] = v;
+        s2 += v;
+      }
     }
-    tv.Kt = s;
+    tv.Kt = s2;
   } else {  // RMHMC_K_BINARY_SAME
     const long c = T.cols[0];
     tv.Kt = (X[c * N + i] == X[c * N + j]) ? exp(2.0 * eta[T.p0]) : 0.0;
@@ -70,26 +91,44 @@ __device__ __forceinline__ void term_eval(const ModelDev& md, const double* __re
 __device__ __forceinline__ double term_deriv(const TermDev& T, const TermVals& tv, int ord, int a,
                                              int b, int c) {
   if (T.kind == RMHMC_K_SE_ISO || T.kind == RMHMC_K_SE_ARD) {
-    auto c1 = [&](int x) { return x == 0 ? 2.0 : tv.u[x - 1]; };
-    auto c2 = [&](int x, int y) { return (x == y && x > 0) ? -2.0 * tv.u[x - 1] : 0.0; };
+    auto c1 = [&](int x) { return x == 0 ? 2.0 : select(tv.u, x - 1); };
+    auto c2 = [&](int x, int y) { return (x == y && x > 0) ? -2.0 * select(tv.u, x - 1) : 0.0; };
     if (ord == 1) return tv.Kt * c1(a);
     if (ord == 2) return tv.Kt * (c1(a) * c1(b) + c2(a, b));
-    const double c3 = (a == b && b == c && a > 0) ? 4.0 * tv.u[a - 1] : 0.0;
+    const double c3 = (a == b && b == c && a > 0) ? 4.0 * select(tv.u, a - 1) : 0.0;
     return tv.Kt * (c1(a) * c1(b) * c1(c) + c2(a, b) * c1(c) + c2(a, c) * c1(b) +
                     c2(b, c) * c1(a) + c3);
   }
   if (T.kind == RMHMC_K_LINEAR_ARD) {
     if (ord >= 2 && a != b) return 0.0;
     if (ord == 3 && a != c) return 0.0;
-    return tv.u[a];
+    return select(tv.u, a);
   }
   return (ord == 1 ? 2.0 : (ord == 2 ? 4.0 : 8.0)) * tv.Kt;
 }
 
-__device__ __forceinline__ double tuple_val(const ModelDev& md, const TermVals* tv, const Tuple& tp) {
-  const int t = md.param_term[tp.l];
-  const int p0 = md.terms[t].p0;
-  return term_deriv(md.terms[t], tv[t], tp.ord, tp.l - p0, tp.m - p0, tp.n - p0);
+// The derivative of a tuple at one element.  The tuple (and so its term) is
+// the same in every lane; the term is picked by an unrolled comparison so
+// that tv is only indexed at compile time.
+__device__ __forceinline__ double tuple_val(const ModelDev& md, const TermVals (&tv)[MAX_TERMS],
+                                            const Tuple& tp) {
+  const int t = __builtin_amdgcn_readfirstlane(md.param_term[tp.l]);
+  double v = 0.0;
+#pragma unroll
+  for (int tt = 0; tt < MAX_TERMS; ++tt) {
+    if (tt == t) {
+      const int p0 = md.terms[tt].p0;
+      v = term_deriv(md.terms[tt], tv[tt], tp.ord, tp.l - p0, tp.m - p0, tp.n - p0);
+    }
+  }
+  return v;
+}
+
+__device__ __forceinline__ void eval_terms(const ModelDev& md, const double* __restrict__ eta, int i,
+                                           int j, TermVals (&tv)[MAX_TERMS]) {
+#pragma unroll
+  for (int t = 0; t < MAX_TERMS; ++t)
+    if (t < md.nterms) term_eval(md, eta, t, i, j, tv[t]);
 }
 
 __global__ __launch_bounds__(256) void kgen_kernel(ModelDev md, const double* __restrict__ eta,
@@ -99,12 +138,17 @@ __global__ __launch_bounds__(256) void kgen_kernel(ModelDev md, const double* __
   if (e >= NN) return;
   const int i = (int)(e % md.N), j = (int)(e / md.N);
   double k = (i == j) ? md.jitter : 0.0;
-  for (int t = 0; t < md.nterms; ++t) {
-    TermVals tv;
-    term_eval(md, eta, t, i, j, tv);
-    k += tv.Kt;
-    const TermDev& T = md.terms[t];
-    for (int a = 0; a < T.np; ++a) K1[(long)(T.p0 + a) * NN + e] = term_deriv(T, tv, 1, a, 0, 0);
+#pragma unroll
+  for (int t = 0; t < MAX_TERMS; ++t) {
+    if (t < md.nterms) {
+      TermVals tv;
+      term_eval(md, eta, t, i, j, tv);
+      k += tv.Kt;
+      const TermDev& T = md.terms[t];
+#pragma unroll
+      for (int a = 0; a < RMHMC_MAX_TERM_COLS + 1; ++a)
+        if (a < T.np) K1[(long)(T.p0 + a) * NN + e] = term_deriv(T, tv, 1, a, 0, 0);
+    }
   }
   K[e] = k;
 }
@@ -114,42 +158,112 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void kd_wsum_kernel(ModelDev md, const double* __restrict__ eta,
-                                                      const Tuple* __restrict__ tuples, int nt,
-                                                      int mode, const double* __restrict__ Kinv,
-                                                      const double* __restrict__ alpha,
-                                                      const double* __restrict__ Wstack,
-                                                      double* __restrict__ part) {
-  __shared__ double sh[4][MAX_TUPLES];
-  __shared__ Tuple stup[MAX_TUPLES];
+// The kernel-derivative sums by passes: a pass is up to KD_PASS tuples of
+// one kernel term (the tuples of a term are consecutive), and workgroup
+// layer blockIdx.z takes one pass, so every element evaluates that term
+// only.  The term's derivative factors go to a per-thread LDS column (SE
+// kinds: c_0 = 2, c_x = u_(x-1), so that dK = K (c_a c_b c_c + ...) with
+// the second-order factors -2 c_x on the diagonal; linear-ARD: u_x), from
+// which each tuple reads the factors of its indices, which are the same in
+// every lane: the accumulators stay in registers and the code has one
+// branch per term kind, outside the element loop.
+constexpr int KD_PASS = 16;
+constexpr int KD_MAX_PASSES = 16;
+struct KdPasses {
+  int n;
+  int term[KD_MAX_PASSES], t0[KD_MAX_PASSES], cnt[KD_MAX_PASSES];
+};
+
+__global__ __launch_bounds__(256) void kd_wsum_pass_kernel(ModelDev md, const double* __restrict__ eta,
+                                                           const Tuple* __restrict__ tuples, int nt,
+                                                           KdPasses ps, int mode,
+                                                           const double* __restrict__ Kinv,
+                                                           const double* __restrict__ alpha,
+                                                           const double* __restrict__ Wstack,
+                                                           double* __restrict__ part) {
+  constexpr int NC = RMHMC_MAX_TERM_COLS + 1;
+  __shared__ double cv[NC][256];
+  __shared__ double sh[4][KD_PASS];
   const long NN = (long)md.N * md.N;
-  const int w = blockIdx.y;
-  for (int t = threadIdx.x; t < nt; t += blockDim.x) stup[t] = tuples[t];
-  __syncthreads();
-  double acc[MAX_TUPLES];
+  const int w = blockIdx.y, pz = blockIdx.z;
+  const int t = __builtin_amdgcn_readfirstlane(ps.term[pz]);
+  const int t0 = __builtin_amdgcn_readfirstlane(ps.t0[pz]);
+  const int nl = __builtin_amdgcn_readfirstlane(ps.cnt[pz]);
+  const int kind = __builtin_amdgcn_readfirstlane(md.terms[t].kind);
+  const int p0 = __builtin_amdgcn_readfirstlane(md.terms[t].p0);
+  int ord[KD_PASS], ia[KD_PASS], ib[KD_PASS], ic[KD_PASS];
 #pragma unroll
-  for (int t = 0; t < MAX_TUPLES; ++t) acc[t] = 0.0;
+  for (int k = 0; k < KD_PASS; ++k) {
+    const Tuple tp = tuples[t0 + (k < nl ? k : 0)];
+    ord[k] = __builtin_amdgcn_readfirstlane(tp.ord);
+    ia[k] = __builtin_amdgcn_readfirstlane(tp.l - p0);
+    ib[k] = __builtin_amdgcn_readfirstlane(tp.ord >= 2 ? tp.m - p0 : 0);
+    ic[k] = __builtin_amdgcn_readfirstlane(tp.ord >= 3 ? tp.n - p0 : 0);
+  }
+  double acc[KD_PASS];
+#pragma unroll
+  for (int k = 0; k < KD_PASS; ++k) acc[k] = 0.0;
+  const int tid = threadIdx.x;
+  const bool se = kind == RMHMC_K_SE_ISO || kind == RMHMC_K_SE_ARD;
   const long stride = (long)gridDim.x * blockDim.x;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < NN; e += stride) {
+  for (long e = (long)blockIdx.x * blockDim.x + tid; e < NN; e += stride) {
     const int i = (int)(e % md.N), j = (int)(e / md.N);
     const double wgt = mode == 0 ? 0.5 * (Kinv[e] - alpha[i] * alpha[j]) : Wstack[(long)w * NN + e];
-    TermVals tv[MAX_TERMS];
-    for (int t = 0; t < md.nterms; ++t) term_eval(md, eta, t, i, j, tv[t]);
+    TermVals tv;
+    term_eval(md, eta, t, i, j, tv);
+    if (se) {
+      cv[0][tid] = 2.0;
 #pragma unroll
-    for (int t = 0; t < MAX_TUPLES; ++t)
-      if (t < nt) acc[t] += wgt * tuple_val(md, tv, stup[t]);
+      for (int c = 0; c < RMHMC_MAX_TERM_COLS; ++c) cv[1 + c][tid] = tv.u[c];
+      const double wk = wgt * tv.Kt;
+#pragma unroll
+      for (int k = 0; k < KD_PASS; ++k) {
+        if (k < nl) {
+          const int a = ia[k], b = ib[k], c = ic[k];
+          const double ca = cv[a][tid];
+          double d = ca;
+          if (ord[k] >= 2) {
+            const double cb = cv[b][tid];
+            const double c2ab = (a == b && a > 0) ? -2.0 * ca : 0.0;
+            if (ord[k] == 2) {
+              d = ca * cb + c2ab;
+            } else {
+              const double cc = cv[c][tid];
+              const double c2ac = (a == c && a > 0) ? -2.0 * ca : 0.0;
+              const double c2bc = (b == c && b > 0) ? -2.0 * cb : 0.0;
+              const double c3 = (a == b && b == c && a > 0) ? 4.0 * ca : 0.0;
+              d = ca * cb * cc + c2ab * cc + c2ac * cb + c2bc * ca + c3;
+            }
+          }
+          acc[k] += wk * d;
+        }
+      }
+    } else if (kind == RMHMC_K_LINEAR_ARD) {
+#pragma unroll
+      for (int c = 0; c < RMHMC_MAX_TERM_COLS; ++c) cv[c][tid] = tv.u[c];
+#pragma unroll
+      for (int k = 0; k < KD_PASS; ++k) {
+        const bool nz = ord[k] == 1 || (ia[k] == ib[k] && (ord[k] == 2 || ia[k] == ic[k]));
+        if (k < nl && nz) acc[k] += wgt * cv[ia[k]][tid];
+      }
+    } else {  // same-value term: d^ord K = 2^ord K
+      const double wk = wgt * tv.Kt;
+#pragma unroll
+      for (int k = 0; k < KD_PASS; ++k)
+        if (k < nl) acc[k] += wk * (ord[k] == 1 ? 2.0 : (ord[k] == 2 ? 4.0 : 8.0));
+    }
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
-  for (int t = 0; t < MAX_TUPLES; ++t) {
-    if (t < nt) {
-      const double s = wave_sum(acc[t]);
-      if (lane == 0) sh[wave][t] = s;
+  for (int k = 0; k < KD_PASS; ++k) {
+    if (k < nl) {
+      const double sk = wave_sum(acc[k]);
+      if (lane == 0) sh[wave][k] = sk;
     }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < nt; t += blockDim.x)
-    part[((long)w * gridDim.x + blockIdx.x) * nt + t] = sh[0][t] + sh[1][t] + sh[2][t] + sh[3][t];
+  for (int k = tid; k < nl; k += blockDim.x)
+    part[((long)w * gridDim.x + blockIdx.x) * nt + t0 + k] = sh[0][k] + sh[1][k] + sh[2][k] + sh[3][k];
 }
 
 // out[w * nt + t] = sum over the per-block partials.  One wave per output:
@@ -187,7 +301,7 @@ __global__ __launch_bounds__(256) void kd_matvec_kernel(ModelDev md, const doubl
   if (i < N) {
     for (int j = j0 + g; j < j1; j += 4) {
       TermVals tv[MAX_TERMS];
-      for (int t = 0; t < md.nterms; ++t) term_eval(md, eta, t, i, j, tv[t]);
+      eval_terms(md, eta, i, j, tv);
       const double xj = xv[j];
 #pragma unroll
       for (int t = 0; t < MAX_TUPLES; ++t)
@@ -229,7 +343,7 @@ __global__ __launch_bounds__(256) void kd_gen_kernel(ModelDev md, const double* 
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < NN; e += stride) {
     const int i = (int)(e % md.N), j = (int)(e / md.N);
     TermVals tv[MAX_TERMS];
-    for (int t = 0; t < md.nterms; ++t) term_eval(md, eta, t, i, j, tv[t]);
+    eval_terms(md, eta, i, j, tv);
     for (int t = 0; t < nt; ++t) KT[(long)t * NN + e] = tuple_val(md, tv, stup[t]);
   }
 }
@@ -309,39 +423,54 @@ void kgen(const ModelDev& md, const double* eta, double* K, double* K1, hipStrea
   RM_CHECK_LAUNCH();
 }
 
-static void kd_wsum_chunk(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
-                          int mode, const double* Kinv, const double* alpha, const double* Wstack,
-                          int nw, double* out, double* work, hipStream_t st);
+static void kd_wsum_chunk(const ModelDev& md, const double* eta, const Tuple* tuples,
+                          const Tuple* tuples_h, int nt, int mode, const double* Kinv,
+                          const double* alpha, const double* Wstack, int nw, double* out,
+                          double* work, hipStream_t st);
 
-void kd_wsum(const ModelDev& md, const double* eta, const Tuple* tuples, int nt, int mode,
-             const double* Kinv, const double* alpha, const double* Wstack, int nw, double* out,
-             double* work, hipStream_t st) {
+void kd_wsum(const ModelDev& md, const double* eta, const Tuple* tuples, const Tuple* tuples_h,
+             int nt, int mode, const double* Kinv, const double* alpha, const double* Wstack,
+             int nw, double* out, double* work, hipStream_t st) {
   // out is nw x nt (row w); chunks of at most MAX_TUPLES tuples write their columns
   if (nt <= MAX_TUPLES) {
-    kd_wsum_chunk(md, eta, tuples, nt, mode, Kinv, alpha, Wstack, nw, out, work, st);
+    kd_wsum_chunk(md, eta, tuples, tuples_h, nt, mode, Kinv, alpha, Wstack, nw, out, work, st);
     return;
   }
   double* tmp = work + 512L * MAX_P * MAX_TUPLES;
   for (int t0 = 0; t0 < nt; t0 += MAX_TUPLES) {
     const int c = std::min(MAX_TUPLES, nt - t0);
-    kd_wsum_chunk(md, eta, tuples + t0, c, mode, Kinv, alpha, Wstack, nw, tmp, work, st);
+    kd_wsum_chunk(md, eta, tuples + t0, tuples_h + t0, c, mode, Kinv, alpha, Wstack, nw, tmp,
+                  work, st);
     for (int w = 0; w < nw; ++w) copy(out + (long)w * nt + t0, tmp + (long)w * c, c, st);
   }
 }
 
-static void kd_wsum_chunk(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
-                          int mode, const double* Kinv, const double* alpha, const double* Wstack,
-                          int nw, double* out, double* work, hipStream_t st) {
+static void kd_wsum_chunk(const ModelDev& md, const double* eta, const Tuple* tuples,
+                          const Tuple* tuples_h, int nt, int mode, const double* Kinv,
+                          const double* alpha, const double* Wstack, int nw, double* out,
+                          double* work, hipStream_t st) {
   if (nt <= 0 || nw <= 0) return;
   const long NN = (long)md.N * md.N;
-  // Eight elements per thread: 512 workgroups at N = 1024, two waves per
-  // SIMD, which is what the kernel's register use allows.
-  int nblk = cdiv(NN, 256 * 8);
+  // passes: runs of consecutive tuples of one term, at most KD_PASS each
+  KdPasses ps{};
+  for (int k = 0; k < nt;) {
+    const int t = md.param_term[tuples_h[k].l];
+    int e = k + 1;
+    while (e < nt && e - k < KD_PASS && md.param_term[tuples_h[e].l] == t) ++e;
+    RM_REQUIRE(ps.n < KD_MAX_PASSES, "kd_wsum: too many passes");
+    ps.term[ps.n] = t;
+    ps.t0[ps.n] = k;
+    ps.cnt[ps.n] = e - k;
+    ++ps.n;
+    k = e;
+  }
+  // sixteen elements per thread at N = 1024 (256 workgroups per pass)
+  int nblk = cdiv(NN, 256 * 16);
   if (nblk > 512) nblk = 512;
   if (nblk < 1) nblk = 1;
   const int slot = timing_begin(TK_KD_WSUM, st);
-  hipLaunchKernelGGL(kd_wsum_kernel, dim3(nblk, nw), dim3(256), 0, st, md, eta, tuples, nt, mode,
-                     Kinv, alpha, Wstack, work);
+  hipLaunchKernelGGL(kd_wsum_pass_kernel, dim3(nblk, nw, ps.n), dim3(256), 0, st, md, eta, tuples,
+                     nt, ps, mode, Kinv, alpha, Wstack, work);
   RM_CHECK_LAUNCH();
   timing_end(slot, st, 2.0 * (double)NN * nt * nw, (double)NN * nw * sizeof(double));
   hipLaunchKernelGGL(kd_wsum_reduce, dim3(nt * nw), dim3(64), 0, st, nblk, nt,

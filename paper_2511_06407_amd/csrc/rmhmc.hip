@@ -853,7 +853,8 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st, int* fail) {
   multi_dot(N, N, pt.Kinv, N, pt.K1, N, NN, P, pt.trK1, m.mdwork, st);
   pair_dots(N, pt.k1a, N, P, pt.a, N, P, pt.kla, st);
   pair_dots(N, pt.alpha, 0, 1, pt.k1a, N, P, pt.ak, st);
-  kd_wsum(m.md, eta, m.pairs, m.npairs, 0, pt.Kinv, pt.alpha, nullptr, 1, pt.phiK2, m.kdwork, st);
+  kd_wsum(m.md, eta, m.pairs, m.pairs_h.data(), m.npairs, 0, pt.Kinv, pt.alpha, nullptr, 1,
+          pt.phiK2, m.kdwork, st);
   if (!mixed)
     gemm_tallk(P, P, NN, pt.A, NN, pt.At, NN, pt.trAA, P, m.tallwork, tallk_splits(NN), st);
   else
@@ -1032,7 +1033,8 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
     gemm(h, st);
   }
   kd_wsum_stack(m.md, eta, m.pairs, m.npairs, pt.B, P, m.tB, m.ktbuf, m.tallwork, st);
-  kd_wsum(m.md, eta, m.triples, m.ntriples, 0, pt.Kinv, pt.alpha, nullptr, 1, m.t3, m.kdwork, st);
+  kd_wsum(m.md, eta, m.triples, m.triples_h.data(), m.ntriples, 0, pt.Kinv, pt.alpha, nullptr, 1,
+          m.t3, m.kdwork, st);
   pair_dots(N, pt.k1a, N, P, pt.Aam, N, P * P, m.D1, st);
   pair_dots(N, pt.k2a, N, m.npairs, pt.a, N, P, m.D2, st);
   pair_dots(N, pt.k1a, N, P, pt.ik2a, N, m.npairs, m.D3, st);
