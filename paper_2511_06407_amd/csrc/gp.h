@@ -47,16 +47,16 @@ void kd_wsum(const ModelDev& md, const double* eta, const Tuple* tuples, const T
 // from a stack (stride N*N): the tuple derivatives are generated once into
 // KT (at most MAX_TUPLES x N*N values) and contracted with every weight by a
 // deterministic tall-K GEMM (`tallwork`: tallk_splits(N*N) * MAX_TUPLES * nw).
-void kd_wsum_stack(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
-                   const double* Wstack, int nw, double* out, double* KT, double* tallwork,
-                   hipStream_t st);
+void kd_wsum_stack(const ModelDev& md, const double* eta, const Tuple* tuples,
+                   const Tuple* tuples_h, int nt, const double* Wstack, int nw, double* out,
+                   double* KT, double* tallwork, hipStream_t st);
 
 // y[(x * nt + t) * N + i] = sum_j d K_tuple(i,j) x_x(j), for nx vectors x (stride N).
 // The j range is split over KD_MV_SPLIT workgroup columns; `work` holds
 // KD_MV_SPLIT * min(nt, MAX_TUPLES) * nx * N partial sums.
 constexpr int KD_MV_SPLIT = 32;
-void kd_matvec(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
-               const double* x, int nx, double* y, double* work, hipStream_t st);
+void kd_matvec(const ModelDev& md, const double* eta, const Tuple* tuples, const Tuple* tuples_h,
+               int nt, const double* x, int nx, double* y, double* work, hipStream_t st);
 
 // Likelihood derivatives in the latent coordinates, out[0..LIK_SLOTS * N):
 //   [0, N)   l_i (per record; zero at the second function's points)

@@ -107,30 +107,6 @@ __device__ __forceinline__ double term_deriv(const TermDev& T, const TermVals& t
   return (ord == 1 ? 2.0 : (ord == 2 ? 4.0 : 8.0)) * tv.Kt;
 }
 
-// The derivative of a tuple at one element.  The tuple (and so its term) is
-// the same in every lane; the term is picked by an unrolled comparison so
-// that tv is only indexed at compile time.
-__device__ __forceinline__ double tuple_val(const ModelDev& md, const TermVals (&tv)[MAX_TERMS],
-                                            const Tuple& tp) {
-  const int t = __builtin_amdgcn_readfirstlane(md.param_term[tp.l]);
-  double v = 0.0;
-#pragma unroll
-  for (int tt = 0; tt < MAX_TERMS; ++tt) {
-    if (tt == t) {
-      const int p0 = md.terms[tt].p0;
-      v = term_deriv(md.terms[tt], tv[tt], tp.ord, tp.l - p0, tp.m - p0, tp.n - p0);
-    }
-  }
-  return v;
-}
-
-__device__ __forceinline__ void eval_terms(const ModelDev& md, const double* __restrict__ eta, int i,
-                                           int j, TermVals (&tv)[MAX_TERMS]) {
-#pragma unroll
-  for (int t = 0; t < MAX_TERMS; ++t)
-    if (t < md.nterms) term_eval(md, eta, t, i, j, tv[t]);
-}
-
 __global__ __launch_bounds__(256) void kgen_kernel(ModelDev md, const double* __restrict__ eta,
                                                    double* __restrict__ K, double* __restrict__ K1) {
   const long NN = (long)md.N * md.N;
@@ -174,6 +150,95 @@ struct KdPasses {
   int term[KD_MAX_PASSES], t0[KD_MAX_PASSES], cnt[KD_MAX_PASSES];
 };
 
+// The pass's tuples as local indices of its term (the same in every lane).
+struct PassTuples {
+  int t, nl, kind;
+  int ord[KD_PASS], ia[KD_PASS], ib[KD_PASS], ic[KD_PASS];
+};
+
+__device__ __forceinline__ void load_pass(const ModelDev& md, const Tuple* __restrict__ tuples,
+                                          const KdPasses& ps, int pz, PassTuples& P) {
+  P.t = __builtin_amdgcn_readfirstlane(ps.term[pz]);
+  const int t0 = __builtin_amdgcn_readfirstlane(ps.t0[pz]);
+  P.nl = __builtin_amdgcn_readfirstlane(ps.cnt[pz]);
+  P.kind = __builtin_amdgcn_readfirstlane(md.terms[P.t].kind);
+  const int p0 = __builtin_amdgcn_readfirstlane(md.terms[P.t].p0);
+#pragma unroll
+  for (int k = 0; k < KD_PASS; ++k) {
+    const Tuple tp = tuples[t0 + (k < P.nl ? k : 0)];
+    P.ord[k] = __builtin_amdgcn_readfirstlane(tp.ord);
+    P.ia[k] = __builtin_amdgcn_readfirstlane(tp.l - p0);
+    P.ib[k] = __builtin_amdgcn_readfirstlane(tp.ord >= 2 ? tp.m - p0 : 0);
+    P.ic[k] = __builtin_amdgcn_readfirstlane(tp.ord >= 3 ? tp.n - p0 : 0);
+  }
+}
+
+// acc[k] += wgt * (d^ord K / d eta_tuple k)(i, j) from the pass term's
+// values tv at (i, j); cv is the LDS block of per-thread factor columns.
+__device__ __forceinline__ void pass_accumulate(const PassTuples& P, const TermVals& tv, double wgt,
+                                                double (*cv)[256], int tid,
+                                                double (&acc)[KD_PASS]) {
+  if (P.kind == RMHMC_K_SE_ISO || P.kind == RMHMC_K_SE_ARD) {
+    cv[0][tid] = 2.0;
+#pragma unroll
+    for (int c = 0; c < RMHMC_MAX_TERM_COLS; ++c) cv[1 + c][tid] = tv.u[c];
+    const double wk = wgt * tv.Kt;
+#pragma unroll
+    for (int k = 0; k < KD_PASS; ++k) {
+      if (k < P.nl) {
+        const int a = P.ia[k], b = P.ib[k], c = P.ic[k];
+        const double ca = cv[a][tid];
+        double d = ca;
+        if (P.ord[k] >= 2) {
+          const double cb = cv[b][tid];
+          const double c2ab = (a == b && a > 0) ? -2.0 * ca : 0.0;
+          if (P.ord[k] == 2) {
+            d = ca * cb + c2ab;
+          } else {
+            const double cc = cv[c][tid];
+            const double c2ac = (a == c && a > 0) ? -2.0 * ca : 0.0;
+            const double c2bc = (b == c && b > 0) ? -2.0 * cb : 0.0;
+            const double c3 = (a == b && b == c && a > 0) ? 4.0 * ca : 0.0;
+            d = ca * cb * cc + c2ab * cc + c2ac * cb + c2bc * ca + c3;
+          }
+        }
+        acc[k] += wk * d;
+      }
+    }
+  } else if (P.kind == RMHMC_K_LINEAR_ARD) {
+#pragma unroll
+    for (int c = 0; c < RMHMC_MAX_TERM_COLS; ++c) cv[c][tid] = tv.u[c];
+#pragma unroll
+    for (int k = 0; k < KD_PASS; ++k) {
+      const bool nz = P.ord[k] == 1 || (P.ia[k] == P.ib[k] && (P.ord[k] == 2 || P.ia[k] == P.ic[k]));
+      if (k < P.nl && nz) acc[k] += wgt * cv[P.ia[k]][tid];
+    }
+  } else {  // same-value term: d^ord K = 2^ord K
+    const double wk = wgt * tv.Kt;
+#pragma unroll
+    for (int k = 0; k < KD_PASS; ++k)
+      if (k < P.nl) acc[k] += wk * (P.ord[k] == 1 ? 2.0 : (P.ord[k] == 2 ? 4.0 : 8.0));
+  }
+}
+
+// Passes of a host tuple list: runs of consecutive tuples of one term, at
+// most KD_PASS each.
+KdPasses make_passes(const ModelDev& md, const Tuple* tuples_h, int nt) {
+  KdPasses ps{};
+  for (int k = 0; k < nt;) {
+    const int t = md.param_term[tuples_h[k].l];
+    int e = k + 1;
+    while (e < nt && e - k < KD_PASS && md.param_term[tuples_h[e].l] == t) ++e;
+    RM_REQUIRE(ps.n < KD_MAX_PASSES, "kernel-derivative passes: too many");
+    ps.term[ps.n] = t;
+    ps.t0[ps.n] = k;
+    ps.cnt[ps.n] = e - k;
+    ++ps.n;
+    k = e;
+  }
+  return ps;
+}
+
 __global__ __launch_bounds__(256) void kd_wsum_pass_kernel(ModelDev md, const double* __restrict__ eta,
                                                            const Tuple* __restrict__ tuples, int nt,
                                                            KdPasses ps, int mode,
@@ -185,84 +250,32 @@ __global__ __launch_bounds__(256) void kd_wsum_pass_kernel(ModelDev md, const do
   __shared__ double cv[NC][256];
   __shared__ double sh[4][KD_PASS];
   const long NN = (long)md.N * md.N;
-  const int w = blockIdx.y, pz = blockIdx.z;
-  const int t = __builtin_amdgcn_readfirstlane(ps.term[pz]);
-  const int t0 = __builtin_amdgcn_readfirstlane(ps.t0[pz]);
-  const int nl = __builtin_amdgcn_readfirstlane(ps.cnt[pz]);
-  const int kind = __builtin_amdgcn_readfirstlane(md.terms[t].kind);
-  const int p0 = __builtin_amdgcn_readfirstlane(md.terms[t].p0);
-  int ord[KD_PASS], ia[KD_PASS], ib[KD_PASS], ic[KD_PASS];
-#pragma unroll
-  for (int k = 0; k < KD_PASS; ++k) {
-    const Tuple tp = tuples[t0 + (k < nl ? k : 0)];
-    ord[k] = __builtin_amdgcn_readfirstlane(tp.ord);
-    ia[k] = __builtin_amdgcn_readfirstlane(tp.l - p0);
-    ib[k] = __builtin_amdgcn_readfirstlane(tp.ord >= 2 ? tp.m - p0 : 0);
-    ic[k] = __builtin_amdgcn_readfirstlane(tp.ord >= 3 ? tp.n - p0 : 0);
-  }
+  const int w = blockIdx.y;
+  PassTuples P;
+  load_pass(md, tuples, ps, blockIdx.z, P);
   double acc[KD_PASS];
 #pragma unroll
   for (int k = 0; k < KD_PASS; ++k) acc[k] = 0.0;
   const int tid = threadIdx.x;
-  const bool se = kind == RMHMC_K_SE_ISO || kind == RMHMC_K_SE_ARD;
   const long stride = (long)gridDim.x * blockDim.x;
   for (long e = (long)blockIdx.x * blockDim.x + tid; e < NN; e += stride) {
     const int i = (int)(e % md.N), j = (int)(e / md.N);
     const double wgt = mode == 0 ? 0.5 * (Kinv[e] - alpha[i] * alpha[j]) : Wstack[(long)w * NN + e];
     TermVals tv;
-    term_eval(md, eta, t, i, j, tv);
-    if (se) {
-      cv[0][tid] = 2.0;
-#pragma unroll
-      for (int c = 0; c < RMHMC_MAX_TERM_COLS; ++c) cv[1 + c][tid] = tv.u[c];
-      const double wk = wgt * tv.Kt;
-#pragma unroll
-      for (int k = 0; k < KD_PASS; ++k) {
-        if (k < nl) {
-          const int a = ia[k], b = ib[k], c = ic[k];
-          const double ca = cv[a][tid];
-          double d = ca;
-          if (ord[k] >= 2) {
-            const double cb = cv[b][tid];
-            const double c2ab = (a == b && a > 0) ? -2.0 * ca : 0.0;
-            if (ord[k] == 2) {
-              d = ca * cb + c2ab;
-            } else {
-              const double cc = cv[c][tid];
-              const double c2ac = (a == c && a > 0) ? -2.0 * ca : 0.0;
-              const double c2bc = (b == c && b > 0) ? -2.0 * cb : 0.0;
-              const double c3 = (a == b && b == c && a > 0) ? 4.0 * ca : 0.0;
-              d = ca * cb * cc + c2ab * cc + c2ac * cb + c2bc * ca + c3;
-            }
-          }
-          acc[k] += wk * d;
-        }
-      }
-    } else if (kind == RMHMC_K_LINEAR_ARD) {
-#pragma unroll
-      for (int c = 0; c < RMHMC_MAX_TERM_COLS; ++c) cv[c][tid] = tv.u[c];
-#pragma unroll
-      for (int k = 0; k < KD_PASS; ++k) {
-        const bool nz = ord[k] == 1 || (ia[k] == ib[k] && (ord[k] == 2 || ia[k] == ic[k]));
-        if (k < nl && nz) acc[k] += wgt * cv[ia[k]][tid];
-      }
-    } else {  // same-value term: d^ord K = 2^ord K
-      const double wk = wgt * tv.Kt;
-#pragma unroll
-      for (int k = 0; k < KD_PASS; ++k)
-        if (k < nl) acc[k] += wk * (ord[k] == 1 ? 2.0 : (ord[k] == 2 ? 4.0 : 8.0));
-    }
+    term_eval(md, eta, P.t, i, j, tv);
+    pass_accumulate(P, tv, wgt, cv, tid, acc);
   }
   const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
   for (int k = 0; k < KD_PASS; ++k) {
-    if (k < nl) {
+    if (k < P.nl) {
       const double sk = wave_sum(acc[k]);
       if (lane == 0) sh[wave][k] = sk;
     }
   }
   __syncthreads();
-  for (int k = tid; k < nl; k += blockDim.x)
+  const int t0 = ps.t0[blockIdx.z];
+  for (int k = tid; k < P.nl; k += blockDim.x)
     part[((long)w * gridDim.x + blockIdx.x) * nt + t0 + k] = sh[0][k] + sh[1][k] + sh[2][k] + sh[3][k];
 }
 
@@ -280,43 +293,45 @@ __global__ __launch_bounds__(64) void kd_wsum_reduce(int nblk, int nt, const dou
   if (threadIdx.x == 0) out[idx] = s;
 }
 
-// Partial sums of y = dK_tuple x over the j chunk blockIdx.z.
-__global__ __launch_bounds__(256) void kd_matvec_kernel(ModelDev md, const double* __restrict__ eta,
-                                                        const Tuple* __restrict__ tuples, int nt,
-                                                        const double* __restrict__ x, int nx,
-                                                        int jchunk, double* __restrict__ part) {
-  __shared__ double sh[4][64];
-  __shared__ Tuple stup[MAX_TUPLES];
-  for (int t = threadIdx.x; t < nt; t += blockDim.x) stup[t] = tuples[t];
-  __syncthreads();
+// Partial sums of y = dK_tuple x over one j chunk, by passes:
+// blockIdx.z = pass * nsplit + chunk.  Thread (row lane, wave g) takes every
+// fourth j of the chunk; the four waves' sums are added in LDS in a fixed
+// order.
+__global__ __launch_bounds__(256) void kd_matvec_pass_kernel(ModelDev md, const double* __restrict__ eta,
+                                                             const Tuple* __restrict__ tuples, int nt,
+                                                             KdPasses ps, const double* __restrict__ x,
+                                                             int nx, int jchunk, int nsplit,
+                                                             double* __restrict__ part) {
+  constexpr int NC = RMHMC_MAX_TERM_COLS + 1;
+  __shared__ double cv[NC][256];
+  __shared__ double sh[4][KD_PASS][64];
   const int N = md.N;
-  const int xi = blockIdx.y, jz = blockIdx.z;
+  const int xi = blockIdx.y, pz = blockIdx.z / nsplit, jz = blockIdx.z % nsplit;
+  PassTuples P;
+  load_pass(md, tuples, ps, pz, P);
   const double* xv = x + (long)xi * N;
-  const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
   const int i = blockIdx.x * 64 + r;
   const int j0 = jz * jchunk, j1 = min(N, j0 + jchunk);
-  double acc[MAX_TUPLES];
+  double acc[KD_PASS];
 #pragma unroll
-  for (int t = 0; t < MAX_TUPLES; ++t) acc[t] = 0.0;
+  for (int k = 0; k < KD_PASS; ++k) acc[k] = 0.0;
   if (i < N) {
     for (int j = j0 + g; j < j1; j += 4) {
-      TermVals tv[MAX_TERMS];
-      eval_terms(md, eta, i, j, tv);
-      const double xj = xv[j];
-#pragma unroll
-      for (int t = 0; t < MAX_TUPLES; ++t)
-        if (t < nt) acc[t] += tuple_val(md, tv, stup[t]) * xj;
+      TermVals tv;
+      term_eval(md, eta, P.t, i, j, tv);
+      pass_accumulate(P, tv, xv[j], cv, tid, acc);
     }
   }
 #pragma unroll
-  for (int t = 0; t < MAX_TUPLES; ++t) {
-    if (t < nt) {
-      sh[g][r] = acc[t];
-      __syncthreads();
-      if (g == 0 && i < N)
-        part[(((long)jz * nx + xi) * nt + t) * N + i] = sh[0][r] + sh[1][r] + sh[2][r] + sh[3][r];
-      __syncthreads();
-    }
+  for (int k = 0; k < KD_PASS; ++k) sh[g][k][r] = acc[k];
+  __syncthreads();
+  const int t0 = ps.t0[pz];
+  for (int e = tid; e < P.nl * 64; e += 256) {
+    const int k = e / 64, rr = e % 64, ii = blockIdx.x * 64 + rr;
+    if (ii < N)
+      part[(((long)jz * nx + xi) * nt + t0 + k) * N + ii] =
+          sh[0][k][rr] + sh[1][k][rr] + sh[2][k][rr] + sh[3][k][rr];
   }
 }
 
@@ -332,19 +347,29 @@ __global__ void kd_matvec_reduce(long n, int nsplit, const double* __restrict__ 
 }
 
 // KT[t * NN + e] = d^ord K / d eta_tuple at element e = i + j N.
-__global__ __launch_bounds__(256) void kd_gen_kernel(ModelDev md, const double* __restrict__ eta,
-                                                     const Tuple* __restrict__ tuples, int nt,
-                                                     double* __restrict__ KT) {
-  __shared__ Tuple stup[MAX_TUPLES];
-  for (int t = threadIdx.x; t < nt; t += blockDim.x) stup[t] = tuples[t];
-  __syncthreads();
+// The tuple derivatives themselves, KT[t * NN + e], by passes (blockIdx.y).
+__global__ __launch_bounds__(256) void kd_gen_pass_kernel(ModelDev md, const double* __restrict__ eta,
+                                                          const Tuple* __restrict__ tuples,
+                                                          KdPasses ps, double* __restrict__ KT) {
+  constexpr int NC = RMHMC_MAX_TERM_COLS + 1;
+  __shared__ double cv[NC][256];
+  PassTuples P;
+  load_pass(md, tuples, ps, blockIdx.y, P);
+  const int t0 = ps.t0[blockIdx.y];
   const long NN = (long)md.N * md.N;
+  const int tid = threadIdx.x;
   const long stride = (long)gridDim.x * blockDim.x;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < NN; e += stride) {
+  for (long e = (long)blockIdx.x * blockDim.x + tid; e < NN; e += stride) {
     const int i = (int)(e % md.N), j = (int)(e / md.N);
-    TermVals tv[MAX_TERMS];
-    eval_terms(md, eta, i, j, tv);
-    for (int t = 0; t < nt; ++t) KT[(long)t * NN + e] = tuple_val(md, tv, stup[t]);
+    TermVals tv;
+    term_eval(md, eta, P.t, i, j, tv);
+    double acc[KD_PASS];
+#pragma unroll
+    for (int k = 0; k < KD_PASS; ++k) acc[k] = 0.0;
+    pass_accumulate(P, tv, 1.0, cv, tid, acc);
+#pragma unroll
+    for (int k = 0; k < KD_PASS; ++k)
+      if (k < P.nl) KT[(long)(t0 + k) * NN + e] = acc[k];
   }
 }
 
@@ -451,19 +476,7 @@ static void kd_wsum_chunk(const ModelDev& md, const double* eta, const Tuple* tu
                           double* work, hipStream_t st) {
   if (nt <= 0 || nw <= 0) return;
   const long NN = (long)md.N * md.N;
-  // passes: runs of consecutive tuples of one term, at most KD_PASS each
-  KdPasses ps{};
-  for (int k = 0; k < nt;) {
-    const int t = md.param_term[tuples_h[k].l];
-    int e = k + 1;
-    while (e < nt && e - k < KD_PASS && md.param_term[tuples_h[e].l] == t) ++e;
-    RM_REQUIRE(ps.n < KD_MAX_PASSES, "kd_wsum: too many passes");
-    ps.term[ps.n] = t;
-    ps.t0[ps.n] = k;
-    ps.cnt[ps.n] = e - k;
-    ++ps.n;
-    k = e;
-  }
+  const KdPasses ps = make_passes(md, tuples_h, nt);
   // sixteen elements per thread at N = 1024 (256 workgroups per pass)
   int nblk = cdiv(NN, 256 * 16);
   if (nblk > 512) nblk = 512;
@@ -478,23 +491,24 @@ static void kd_wsum_chunk(const ModelDev& md, const double* eta, const Tuple* tu
   RM_CHECK_LAUNCH();
 }
 
-void kd_matvec(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
-               const double* x, int nx, double* y, double* work, hipStream_t st) {
+void kd_matvec(const ModelDev& md, const double* eta, const Tuple* tuples, const Tuple* tuples_h,
+               int nt, const double* x, int nx, double* y, double* work, hipStream_t st) {
   if (nt <= 0 || nx <= 0) return;
   RM_REQUIRE(nt <= MAX_TUPLES || nx == 1, "kd_matvec: chunked tuples need a single vector");
   if (nt > MAX_TUPLES) {
     for (int t0 = 0; t0 < nt; t0 += MAX_TUPLES)
-      kd_matvec(md, eta, tuples + t0, std::min(MAX_TUPLES, nt - t0), x, 1, y + (long)t0 * md.N,
-                work, st);
+      kd_matvec(md, eta, tuples + t0, tuples_h + t0, std::min(MAX_TUPLES, nt - t0), x, 1,
+                y + (long)t0 * md.N, work, st);
     return;
   }
   const int N = md.N;
   const int jchunk = cdiv(N, KD_MV_SPLIT);
   const int nsplit = cdiv(N, jchunk);
   const long n = (long)nt * nx * N;
+  const KdPasses ps = make_passes(md, tuples_h, nt);
   const int slot = timing_begin(TK_KD_MATVEC, st);
-  hipLaunchKernelGGL(kd_matvec_kernel, dim3(cdiv(N, 64), nx, nsplit), dim3(256), 0, st, md, eta,
-                     tuples, nt, x, nx, jchunk, work);
+  hipLaunchKernelGGL(kd_matvec_pass_kernel, dim3(cdiv(N, 64), nx, nsplit * ps.n), dim3(256), 0, st,
+                     md, eta, tuples, nt, ps, x, nx, jchunk, nsplit, work);
   RM_CHECK_LAUNCH();
   hipLaunchKernelGGL(kd_matvec_reduce, dim3(cdiv(n, 256)), dim3(256), 0, st, n, nsplit,
                      (const double*)work, y);
@@ -502,16 +516,18 @@ void kd_matvec(const ModelDev& md, const double* eta, const Tuple* tuples, int n
   timing_end(slot, st, 2.0 * (double)N * N * nt * nx, (double)N * nx * (1.0 + nt) * sizeof(double));
 }
 
-void kd_wsum_stack(const ModelDev& md, const double* eta, const Tuple* tuples, int nt,
-                   const double* Wstack, int nw, double* out, double* KT, double* tallwork,
-                   hipStream_t st) {
+void kd_wsum_stack(const ModelDev& md, const double* eta, const Tuple* tuples,
+                   const Tuple* tuples_h, int nt, const double* Wstack, int nw, double* out,
+                   double* KT, double* tallwork, hipStream_t st) {
   if (nt <= 0 || nw <= 0) return;
   const long NN = (long)md.N * md.N;
   const int nblk = std::max(1, std::min(2048, cdiv(NN, 256 * 4)));
   for (int t0 = 0; t0 < nt; t0 += MAX_TUPLES) {
     const int c = std::min(MAX_TUPLES, nt - t0);
+    const KdPasses ps = make_passes(md, tuples_h + t0, c);
     const int slot = timing_begin(TK_KD_WSUM, st);
-    hipLaunchKernelGGL(kd_gen_kernel, dim3(nblk), dim3(256), 0, st, md, eta, tuples + t0, c, KT);
+    hipLaunchKernelGGL(kd_gen_pass_kernel, dim3(nblk, ps.n), dim3(256), 0, st, md, eta,
+                       tuples + t0, ps, KT);
     RM_CHECK_LAUNCH();
     timing_end(slot, st, 0.0, (double)NN * c * sizeof(double));
     // out(t, w) at out[w * nt + t]: C = KT' W with ldc = nt, columns offset by t0

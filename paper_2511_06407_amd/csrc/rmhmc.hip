@@ -1010,7 +1010,7 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
     gemm_tallk(P, m.nyy, NN, pt.A, NN, pt.Yt, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
   else
     gemm_tallk(P, m.nyy, NN, pt.Af, NN, pt.Ytf, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
-  kd_matvec(m.md, eta, m.pairs, m.npairs, pt.alpha, 1, pt.k2a, m.mvwork, st);
+  kd_matvec(m.md, eta, m.pairs, m.pairs_h.data(), m.npairs, pt.alpha, 1, pt.k2a, m.mvwork, st);
   {
     Gemm<double> g;  // ik2a = K^-1 [K_lm alpha]
     g.m = N; g.n = m.npairs; g.k = N;
@@ -1032,7 +1032,8 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
     h.C = pt.Aam;
     gemm(h, st);
   }
-  kd_wsum_stack(m.md, eta, m.pairs, m.npairs, pt.B, P, m.tB, m.ktbuf, m.tallwork, st);
+  kd_wsum_stack(m.md, eta, m.pairs, m.pairs_h.data(), m.npairs, pt.B, P, m.tB, m.ktbuf,
+                m.tallwork, st);
   kd_wsum(m.md, eta, m.triples, m.triples_h.data(), m.ntriples, 0, pt.Kinv, pt.alpha, nullptr, 1,
           m.t3, m.kdwork, st);
   pair_dots(N, pt.k1a, N, P, pt.Aam, N, P * P, m.D1, st);
