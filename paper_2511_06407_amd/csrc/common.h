@@ -81,9 +81,9 @@ void gemm(const Gemm<float>& g, hipStream_t st);
 // C (m x n) = op(A)' B over a very long inner dimension k, split across
 // workgroups and summed in a fixed order (deterministic).  A is k x m (lda),
 // B is k x n (ldb), both column-major.  `work` must hold splits*m*n values.
-// A single plain product (batch 1, alpha 1, beta 0, C only) with its k range
-// split over `splits` layers; `work` holds splits * m * n doubles.  Anything
-// else goes to gemm().
+// A plain product C = alpha op(A) op(B) (beta 0, C only; a strided batch
+// allowed) with its k range split over `splits` layers; `work` holds
+// batch * splits * m * n doubles.  Anything else goes to gemm().
 void gemm_splitk(const Gemm<double>& g, double* work, int splits, hipStream_t st);
 void gemm_tallk(int m, int n, long k, const double* A, long lda, const double* B, long ldb,
                 double* C, long ldc, double* work, int splits, hipStream_t st);

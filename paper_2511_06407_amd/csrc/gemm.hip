@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(Params<T> p) {
   // Epilogue.  acc[ti][tj][r] = C(m, n) with m = mbase + lane%16,
   // n = nbase + row(lane, r) (the MFMA row index is our n).
   if (p.part) {
-    T* part = p.part + (long)kc * M * N;
+    T* part = p.part + ((long)batch * p.ksplit + kc) * M * N;
 #pragma unroll
     for (int ti = 0; ti < TW; ++ti)
 #pragma unroll
@@ -320,17 +320,19 @@ __global__ __launch_bounds__(256) void tallk_small_kernel(int m, int n, long k,
 
 // C = sum over a few split-K partials, one thread per output element, the
 // splits added in order (deterministic).  For wide outputs with few splits.
-__global__ __launch_bounds__(256) void splitk_sum(int m, int n, int splits,
+// (blockIdx.y: batch item; its partials follow the previous item's.)
+__global__ __launch_bounds__(256) void splitk_sum(int m, int n, int splits, double alpha,
                                                   const double* __restrict__ part,
-                                                  double* __restrict__ C, long ldc) {
+                                                  double* __restrict__ C, long ldc, long sC) {
   const long mn = (long)m * n;
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= mn) return;
+  const double* pb = part + (long)blockIdx.y * splits * mn;
   double s = 0;
 #pragma unroll 4
-  for (int kc = 0; kc < splits; ++kc) s += part[(long)kc * mn + idx];
+  for (int kc = 0; kc < splits; ++kc) s += pb[(long)kc * mn + idx];
   const int i = (int)(idx % m), j = (int)(idx / m);
-  C[i + (long)j * ldc] = s;
+  C[(long)blockIdx.y * sC + i + (long)j * ldc] = alpha * s;
 }
 
 template <typename T, int BT>
@@ -422,13 +424,14 @@ void tallk_impl(int m, int n, long k, const T* A, long lda, const T* B, long ldb
   RM_CHECK_LAUNCH();
 }
 
-// One plain product C = op(A) op(B) with its k range split over `splits`
-// workgroup layers.  A single square product near 1000 has only a few
-// hundred 64 x 64 tiles, about one wave per SIMD; the layers multiply the
-// waves in flight, and a second pass adds them in order.
+// A plain product C = alpha op(A) op(B) (or a strided batch of them) with
+// its k range split over `splits` workgroup layers.  A single square
+// product near 1000 has only a few hundred 64 x 64 tiles, about one wave per
+// SIMD; the layers multiply the waves in flight, and a second pass adds them
+// in order.  work: batch * splits * m * n partials.
 void gemm_splitk_impl(const Gemm<double>& g, double* work, int splits, hipStream_t st) {
-  const bool plain = g.batch == 1 && g.alpha == 1.0 && g.beta == 0.0 && !g.C2 && !g.C2p &&
-                     !g.Ap && !g.Bp && !g.Cp && !g.Co && !g.C2o && !g.Cop && g.C && work;
+  const bool plain = g.batch >= 1 && g.beta == 0.0 && !g.C2 && !g.C2p && !g.Ap && !g.Bp &&
+                     !g.Cp && !g.Co && !g.C2o && !g.Cop && g.C && work;
   if (!plain || splits <= 1 || g.k < 2 * BK * splits) {
     gemm_impl(g, st);
     return;
@@ -436,16 +439,16 @@ void gemm_splitk_impl(const Gemm<double>& g, double* work, int splits, hipStream
   if (g.m <= 0 || g.n <= 0) return;
   Params<double> p{};
   p.m = g.m; p.n = g.n; p.k = g.k; p.alpha = 1; p.beta = 0;
-  p.A = g.A; p.lda = g.lda; p.B = g.B; p.ldb = g.ldb;
+  p.A = g.A; p.lda = g.lda; p.sA = g.sA; p.B = g.B; p.ldb = g.ldb; p.sB = g.sB;
   long chunk = ((long)g.k + splits - 1) / splits;
   chunk = (chunk + BK - 1) / BK * BK;
   const int sp = (int)(((long)g.k + chunk - 1) / chunk);
   p.ksplit = sp; p.kchunk = chunk;
   p.part = work;
-  launch(p, g.tA, g.tB, 1, st);
+  launch(p, g.tA, g.tB, g.batch, st);
   const long mn = (long)g.m * g.n;
-  hipLaunchKernelGGL(splitk_sum, dim3(cdiv(mn, 256)), dim3(256), 0, st, g.m, g.n, sp,
-                     (const double*)work, g.C, g.ldc);
+  hipLaunchKernelGGL(splitk_sum, dim3(cdiv(mn, 256), g.batch), dim3(256), 0, st, g.m, g.n, sp,
+                     g.alpha, (const double*)work, g.C, g.ldc, g.sC);
   RM_CHECK_LAUNCH();
 }
 

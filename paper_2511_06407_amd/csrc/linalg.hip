@@ -615,6 +615,16 @@ void chol_inverse(int n, const double* K, double* Kinv, double* logdet, CholWork
   // stride 2s(n + 1) along the diagonal, so each level is two batched
   // products (plus a ragged last pair when n is not a power-of-two multiple
   // of CB).
+  // the upper levels have few output tiles and a long k: split k so that
+  // about 256 workgroups run (partials in w.split, which holds at least
+  // GSPLIT_MAX n^2 doubles when present)
+  auto level_splits = [&](int m, int nn, int k, int batch) {
+    if (!w.split) return 1;
+    const long tiles = (long)cdiv(m, 64) * cdiv(nn, 64) * batch;
+    int sp = (int)std::max(1L, std::min(8L, 256 / std::max(tiles, 1L)));
+    while (sp > 1 && (long)k < 2L * 16 * sp) --sp;
+    return sp;
+  };
   for (int s = CB; s < n; s *= 2) {
     const int full = n / (2 * s);                  // pairs with s2 = s
     const long stride = 2L * s * (n + 1);
@@ -626,14 +636,14 @@ void chol_inverse(int n, const double* K, double* Kinv, double* logdet, CholWork
       a.B = w.Linv + b0 + (long)b0 * n; a.ldb = n; a.sB = stride;
       a.C = w.tmp + off21; a.ldc = n; a.sC = stride;
       a.batch = batch;
-      gemm(a, st);
+      gemm_splitk(a, w.split, level_splits(s2, s, s, batch), st);
       Gemm<double> b;                                // X21 = -X22 T
       b.m = s2; b.n = s; b.k = s2; b.alpha = -1.0;
       b.A = w.Linv + (b0 + s) + (long)(b0 + s) * n; b.lda = n; b.sA = stride;
       b.B = w.tmp + off21; b.ldb = n; b.sB = stride;
       b.C = w.Linv + off21; b.ldc = n; b.sC = stride;
       b.batch = batch;
-      gemm(b, st);
+      gemm_splitk(b, w.split, level_splits(s2, s, s2, batch), st);
     };
     if (full > 0) level(0, s, full);
     const int b0 = full * 2 * s;
