@@ -30,10 +30,11 @@ void eig_load_matrix(int D, const double* H, long ldh, EigWork& w, hipStream_t s
 // w.Psi = diag(Q, I) (Q == nullptr: identity).
 void eig_load_basis(int D, const double* Q, long ldq, EigWork& w, hipStream_t st);
 // Jacobi on w.M, rotations accumulated into w.Psi; converged matrix left in w.M.
-// max_inner: inner Jacobi sweeps per 64 x 64 subproblem and round.  A
-// warm-started matrix is nearly diagonal and one inner sweep per round is
-// fastest; a static solve from the identity converges in fewer outer sweeps
-// with up to JACOBI_INNER_STATIC.
+// max_inner names the solve: JACOBI_INNER_DYNAMIC for a warm start,
+// JACOBI_INNER_STATIC for a solve from the identity.  Both run one inner
+// sweep per round on the cross schedule (up to four inner sweeps per round
+// left a static solve at D = 1038 at the same 18 outer sweeps, 84 against
+// 22 ms); they are timed as separate kernel families.
 constexpr int JACOBI_INNER_STATIC = 4;
 constexpr int JACOBI_INNER_DYNAMIC = 1;
 // Doubles of EigWork::V for a padded dimension Dp: two sets of 32 x 32

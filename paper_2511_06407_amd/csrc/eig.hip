@@ -6,8 +6,8 @@
 // nb = Dp/16 column blocks play a round-robin tournament, nb-1 rounds per
 // sweep.  In a round every pair of blocks (I, J) forms a 32 x 32 symmetric
 // subproblem that one workgroup diagonalises in LDS with an inner cyclic
-// Jacobi (its own round-robin over 32 indices; warm starts rotate only the
-// pairs between the two blocks in most rounds); the resulting 32 x 32
+// Jacobi (its own round-robin over 32 indices; most rounds rotate only the
+// pairs between the two blocks); the resulting 32 x 32
 // rotations are then applied to M (one wave per 32 x 32 tile on the FP64
 // matrix cores, double-buffered M) and to the columns of Psi (fused into
 // the next round's solve launch).  Padding rows/columns are zero and never
@@ -27,12 +27,12 @@ namespace rmhmc {
 namespace {
 
 constexpr int JSB = 32, JHB = 16;   // subproblem size of the block Jacobi and its block width
-// Warm-started solves: a full inner sweep (all pairs of the subproblem) in
-// every JACOBI_FULL_PERIOD-th round of an outer sweep, only the pairs between
-// the two blocks in the others.  Measured on the Hessians of the D = 1038
-// model warm-started from a nearby point, the outer sweeps converge as with a
-// full inner sweep in every round (also at a period of 16; a full sweep in
-// the first round alone converges more slowly).
+// A full inner sweep (all pairs of the subproblem) in every
+// JACOBI_FULL_PERIOD-th round of an outer sweep, only the pairs between the
+// two blocks in the others.  Measured on the Hessians of the D = 1038 model,
+// warm-started from a nearby point and from the identity, the outer sweeps
+// converge as with a full inner sweep in every round (also at a period of
+// 16; a full sweep in the first round alone converges more slowly).
 constexpr int JACOBI_FULL_PERIOD = 8;
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -533,8 +533,7 @@ __device__ __forceinline__ void jacobi_psi_tile(int Dp, int round, int k, double
 //   the rest                      Psi <- Psi J_r, one wave per 32 x 32 tile.
 // The three parts read M_r and V_r and write different buffers, so they run
 // side by side.  With apply_round < 0 the launch only solves round 0 from Min.
-// MAX_INNER (inner sweeps per subproblem) is a template parameter, so warm
-// starts (1) and static solves (JACOBI_INNER_STATIC) are separate kernels.
+// MAX_INNER is the number of inner sweeps per subproblem (1 for every solve).
 template <int MAX_INNER>
 __global__ __launch_bounds__(256) void jacobi_round_kernel(int Dp, int apply_round, int nsolve,
                                                            const double* __restrict__ Min,
@@ -550,8 +549,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(int Dp, int apply_rou
   // (sweeps launched ahead of the check cost only their launch and the
   // subproblem loads)
   if (b < nsolve) {
-    // warm starts run the full inner sweep every JACOBI_FULL_PERIOD-th round
-    // and cross rounds in between; static solves always run full sweeps
+    // the full inner sweep every JACOBI_FULL_PERIOD-th round, cross rounds
+    // in between
     const int round = apply_round + 1;
     const bool cross = MAX_INNER == JACOBI_INNER_DYNAMIC && round % JACOBI_FULL_PERIOD != 0;
     if (apply_round < 0)
@@ -992,15 +991,16 @@ JacobiResult jacobi_eig(int D, EigWork& w, double zeta, double gfloor, int max_s
   // per inner round of a subproblem; rounds per solve: JSB - 1 (full), JHB (cross)
   const double inner_flops = (double)ns * (JHB * JHB * 24.0 + JSB * JHB * 6.0);
   auto solve_flops = [&](int round) {
-    const bool cross = max_inner == JACOBI_INNER_DYNAMIC && round % JACOBI_FULL_PERIOD != 0;
+    const bool cross = round % JACOBI_FULL_PERIOD != 0;
     return inner_flops * (cross ? JHB : JSB - 1);
   };
   const double compose_flops = (double)ns * 3.0 * (2.0 * JSB * JSB * JHB + 2.0 * JHB * JSB * JHB);
   const double sb3 = (double)JSB * JSB * JSB;
   const double vset = (double)ns * JSB * JSB * sizeof(double);
   const double tile = (double)JSB * JSB * sizeof(double);
-  auto round_kernel = max_inner == JACOBI_INNER_DYNAMIC ? jacobi_round_kernel<JACOBI_INNER_DYNAMIC>
-                                                        : jacobi_round_kernel<JACOBI_INNER_STATIC>;
+  // static and warm solves run the same rounds (one inner sweep, the cross
+  // schedule); max_inner only picks the timing family
+  auto round_kernel = jacobi_round_kernel<1>;
   auto sweep = [&]() {
     // launch 0 solves round 0 from M; launch r + 1 applies round r to M and
     // Psi and solves round r + 1 from M_r and V_r.  One event pair brackets
