@@ -512,6 +512,7 @@ struct Model {
   CholWork chol;
   EigWork eig;
   double *tallwork = nullptr, *kdwork = nullptr, *mdwork = nullptr;
+  long tallwork_n = 0;  // doubles of tallwork available to split partials
   double* gsplit = nullptr;   // split-K partials of the warm-start products (GSPLIT_MAX x Dp x Dp)
   int gsplit_layers = GSPLIT_DEFAULT;
   double *mvwork = nullptr;   // column-split partials of kd_matvec
@@ -660,6 +661,14 @@ size_t point_bytes(const Model& m) {
   Carve c;
   layout_point(m, p, c);
   return (c.off + 255) & ~size_t(255);
+}
+
+// The split partials of a rows x cols tall-K product over the N^2 elements
+// (tallk_splits(N^2) x rows x cols doubles), checked against the space held.
+double* tall_space(const Model& m, int rows, int cols) {
+  RM_REQUIRE((long)tallk_splits((long)m.N * m.N) * rows * cols <= m.tallwork_n,
+             "internal: tall-K workspace too small");
+  return m.tallwork;
 }
 
 // A product with a thin output (a few 64 x 64 tiles) over a long k range
@@ -856,9 +865,9 @@ void compute_hessian(Model& m, Point& pt, hipStream_t st, int* fail) {
   kd_wsum(m.md, eta, m.pairs, m.pairs_h.data(), m.npairs, 0, pt.Kinv, pt.alpha, nullptr, 1,
           pt.phiK2, m.kdwork, st);
   if (!mixed)
-    gemm_tallk(P, P, NN, pt.A, NN, pt.At, NN, pt.trAA, P, m.tallwork, tallk_splits(NN), st);
+    gemm_tallk(P, P, NN, pt.A, NN, pt.At, NN, pt.trAA, P, tall_space(m, P, P), tallk_splits(NN), st);
   else
-    gemm_tallk(P, P, NN, pt.Af, NN, pt.Atf, NN, pt.trAA, P, m.tallwork, tallk_splits(NN), st);
+    gemm_tallk(P, P, NN, pt.Af, NN, pt.Atf, NN, pt.trAA, P, tall_space(m, P, P), tallk_splits(NN), st);
   vsum(N, pt.lik, pt.scal + 3, st);
   vdot(N, pt.q, pt.alpha, pt.scal + 4, st);
   hipLaunchKernelGGL(assemble_H_kernel, dim3(cdiv((long)m.Dp * m.Dp, 256)), dim3(256), 0, st, N, P,
@@ -1007,9 +1016,9 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
   }
   // tau[n, y] = tr(A_n A_l A_m) = <A_n, Y_lm'> for the formed pairs y = (l, m)
   if (!mixed)
-    gemm_tallk(P, m.nyy, NN, pt.A, NN, pt.Yt, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
+    gemm_tallk(P, m.nyy, NN, pt.A, NN, pt.Yt, NN, m.tau, P, tall_space(m, P, m.nyy), tallk_splits(NN), st);
   else
-    gemm_tallk(P, m.nyy, NN, pt.Af, NN, pt.Ytf, NN, m.tau, P, m.tallwork, tallk_splits(NN), st);
+    gemm_tallk(P, m.nyy, NN, pt.Af, NN, pt.Ytf, NN, m.tau, P, tall_space(m, P, m.nyy), tallk_splits(NN), st);
   kd_matvec(m.md, eta, m.pairs, m.pairs_h.data(), m.npairs, pt.alpha, 1, pt.k2a, m.mvwork, st);
   {
     Gemm<double> g;  // ik2a = K^-1 [K_lm alpha]
@@ -1033,7 +1042,7 @@ void compute_precompute(Model& m, Point& pt, hipStream_t st) {
     gemm(h, st);
   }
   kd_wsum_stack(m.md, eta, m.pairs, m.pairs_h.data(), m.npairs, pt.B, P, m.tB, m.ktbuf,
-                m.tallwork, st);
+                tall_space(m, std::min(m.npairs, MAX_TUPLES), P), st);
   kd_wsum(m.md, eta, m.triples, m.triples_h.data(), m.ntriples, 0, pt.Kinv, pt.alpha, nullptr, 1,
           m.t3, m.kdwork, st);
   pair_dots(N, pt.k1a, N, P, pt.Aam, N, P * P, m.D1, st);
@@ -1390,7 +1399,12 @@ void build_model(Model& m, const rmhmc_model_desc* d, rmhmc_precision prec) {
   m.eig.ctrl = pl.alloc<double>(EIG_CTRL_DOUBLES);
   m.eig.ctrl_host = pl.alloc_host<double>(EIG_CTRL_DOUBLES);
   const int spl = tallk_splits(NN);
-  m.tallwork = pl.alloc<double>((long)spl * P * std::max(P, m.nyy) + 64);
+  // the tall-K products: P x P traces, P x nyy traces against the Y stack,
+  // and the second-derivative tuples (up to MAX_TUPLES at a time) against P
+  // weights
+  m.tallwork_n = (long)spl * std::max<long>((long)P * std::max(P, m.nyy),
+                                            (long)std::min(m.npairs, MAX_TUPLES) * P);
+  m.tallwork = pl.alloc<double>(m.tallwork_n + 64);
   m.kdwork = pl.alloc<double>(512L * MAX_P * MAX_TUPLES + (long)MAX_P * std::max(m.ntriples, m.npairs) + 64);
   m.mvwork = pl.alloc<double>((long)KD_MV_SPLIT * std::min(m.npairs, MAX_TUPLES) * N + 64);
   m.ktbuf = pl.alloc<double>((long)std::min(m.npairs, MAX_TUPLES) * N * N + 64);
