@@ -579,6 +579,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(int Dp, int apply_rou
 constexpr int OFF_COLS = 8;   // columns per workgroup of the convergence check
 constexpr int OFF_MAXDP = 4096;
 constexpr int OFF_PARTS = 5;  // partials per chunk
+constexpr int OFF_BATCH = 18; // loads in flight per thread
 constexpr int CTRL_N = EIG_CTRL_DOUBLES;
 
 __global__ __launch_bounds__(256) void offnorm_kernel(int Dp, const double* __restrict__ M,
@@ -588,27 +589,59 @@ __global__ __launch_bounds__(256) void offnorm_kernel(int Dp, const double* __re
   __shared__ double rdg[OFF_MAXDP];   // 1 / sqrt|m_ii| (inf for a zero diagonal)
   __shared__ double rs[OFF_MAXDP];    // 1 / max(|m_ii|, gfloor)
   if (ctrl[1] != 0.0) return;
-  for (int i = threadIdx.x; i < Dp; i += 256) {
-    const double d = fabs(M[i + (long)i * Dp]);
-    rdg[i] = d > 0.0 ? rsqrt(d) : INFINITY;
-    rs[i] = 1.0 / fmax(d, gfloor);
+  // every load of a thread is issued before the first is used: the diagonal
+  // (at most OFF_MAXDP / 256 entries a thread), then the chunk in batches of
+  // OFF_BATCH elements a thread (two batches at Dp = 1088)
+  {
+    constexpr int ND = OFF_MAXDP / 256;
+    double dv[ND];
+#pragma unroll
+    for (int t = 0; t < ND; ++t) {
+      const int i = threadIdx.x + 256 * t;
+      dv[t] = i < Dp ? M[i + (long)i * Dp] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < ND; ++t) {
+      const int i = threadIdx.x + 256 * t;
+      if (i < Dp) {
+        const double d = fabs(dv[t]);
+        rdg[i] = d > 0.0 ? rsqrt(d) : INFINITY;
+        rs[i] = 1.0 / fmax(d, gfloor);
+      }
+    }
   }
   __syncthreads();
   const int c0 = blockIdx.x * OFF_COLS;
+  // columns c0 .. c0 + OFF_COLS - 1 (ld Dp) are one contiguous range
+  const double* chunk = M + (long)c0 * Dp;
+  const int ne = OFF_COLS * Dp;
   double off = 0.0, tot = 0.0, rel = 0.0, soff = 0.0, sdiag = 0.0;
-  for (int j = c0; j < c0 + OFF_COLS; ++j) {
-    const double rj = rdg[j], sj = rs[j];
-    for (int i = threadIdx.x; i < Dp; i += 256) {
-      const double v = M[i + (long)j * Dp];
-      tot += v * v;
-      if (i != j && v != 0.0) {
-        off += v * v;
-        rel = fmax(rel, fabs(v) * rdg[i] * rj);
-        const double w = v * rs[i] * sj;
-        soff += w * w;
+  for (int e0 = 0; e0 < ne; e0 += 256 * OFF_BATCH) {
+    double v[OFF_BATCH];
+#pragma unroll
+    for (int t = 0; t < OFF_BATCH; ++t) {
+      const int e = e0 + threadIdx.x + 256 * t;
+      v[t] = e < ne ? chunk[e] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < OFF_BATCH; ++t) {
+      const int e = e0 + threadIdx.x + 256 * t;
+      if (e < ne) {
+        const int j = c0 + e / Dp, i = e - (j - c0) * Dp;
+        const double x = v[t];
+        tot += x * x;
+        if (i != j) {
+          if (x != 0.0) {
+            off += x * x;
+            rel = fmax(rel, fabs(x) * rdg[i] * rdg[j]);
+            const double w = x * rs[i] * rs[j];
+            soff += w * w;
+          }
+        } else if (x != 0.0) {
+          sdiag += rs[j] * rs[j];
+        }
       }
     }
-    if (threadIdx.x == 0 && j < Dp && M[j + (long)j * Dp] != 0.0) sdiag += sj * sj;
   }
   for (int o = 32; o > 0; o >>= 1) {
     off += __shfl_down(off, o, 64);

@@ -374,6 +374,32 @@ def test_full_size_hessian_and_metric_grad(rm):
     assert e_dq < tol and e_dp < tol and e_h < tol
 
 
+def test_metric_grad_two_parameter_se_n1000(rm):
+    """GP-logistic with an isotropic SE kernel (P = 2) at N = 1000, the
+    largest size of the serving mix: three second-derivative pairs against
+    two weights, so the tall-K contraction of the pairs writes more split
+    partials (splits x 3 x 2) than the P x P and P x n_Y trace products
+    (splits x 2 x 2).  dH/dq, dH/dp and H against the reference."""
+    spec, _, _ = wl.gp_logistic_2d(1000, seed=7)
+    q = rand_q(spec, 41, 0.1)
+    alpha = 1e6
+    st = oham.State(oham.GPTarget(spec), q, alpha)
+    p = omomentum(st, np.random.default_rng(42).standard_normal(spec.D))
+    M = rm.Model(spec)
+    dq, dp, ham = M.metric_grad(dev(q), dev(p), dev(st.eig["Psi"].T), dev(st.eig["lam"]), alpha)
+    ref_dq, ref_dp, ref_h = oham.grad_q(st, p), oham.grad_p(st, p), oham.hamiltonian(st, p)
+    s2, q2, full = permuted(spec, q)
+    st2 = oham.State(oham.GPTarget(s2), q2, alpha)
+    fl = max(rel(unpermute_vec(oham.grad_q(st2, p[full]), full), ref_dq),
+             rel(unpermute_vec(oham.grad_p(st2, p[full]), full), ref_dp),
+             rel(oham.hamiltonian(st2, p[full]), ref_h))
+    e_dq, e_dp, e_h = rel(host(dq), ref_dq), rel(host(dp), ref_dp), rel(host(ham), ref_h)
+    record("metric_grad", model="gp_logistic_n1000", alpha=alpha, dHdq=e_dq, dHdp=e_dp, ham=e_h,
+           floor=fl)
+    tol = max(BAR, 10 * fl)
+    assert e_dq < tol and e_dp < tol and e_h < tol
+
+
 # ---------------------------------------------------------------- leapfrog
 @pytest.mark.parametrize("name,eps", [("c1_d34", 0.01), ("mkl_d104_wellcond", 0.003),
                                       ("ard_d75_wellcond", 0.01)])
