@@ -173,6 +173,23 @@ __device__ __forceinline__ void load_pass(const ModelDev& md, const Tuple* __res
   }
 }
 
+// (i, j) of a grid-stride loop over the N x N elements e = i + j N, stepped
+// without a division per element: e advances by stride = sj N + si.
+struct ElemWalk {
+  int i, j, si, sj;
+  __device__ ElemWalk(long e, long stride, int N) {
+    j = (int)(e / N);
+    i = (int)(e - (long)j * N);
+    sj = (int)(stride / N);
+    si = (int)(stride - (long)sj * N);
+  }
+  __device__ __forceinline__ void step(int N) {
+    i += si;
+    j += sj;
+    if (i >= N) { i -= N; ++j; }
+  }
+};
+
 // acc[k] += wgt * (d^ord K / d eta_tuple k)(i, j) from the pass term's
 // values tv at (i, j); cv is the LDS block of per-thread factor columns.
 __device__ __forceinline__ void pass_accumulate(const PassTuples& P, const TermVals& tv, double wgt,
@@ -258,8 +275,10 @@ __global__ __launch_bounds__(256) void kd_wsum_pass_kernel(ModelDev md, const do
   for (int k = 0; k < KD_PASS; ++k) acc[k] = 0.0;
   const int tid = threadIdx.x;
   const long stride = (long)gridDim.x * blockDim.x;
-  for (long e = (long)blockIdx.x * blockDim.x + tid; e < NN; e += stride) {
-    const int i = (int)(e % md.N), j = (int)(e / md.N);
+  const long e0 = (long)blockIdx.x * blockDim.x + tid;
+  ElemWalk ij(e0, stride, md.N);
+  for (long e = e0; e < NN; e += stride, ij.step(md.N)) {
+    const int i = ij.i, j = ij.j;
     const double wgt = mode == 0 ? 0.5 * (Kinv[e] - alpha[i] * alpha[j]) : Wstack[(long)w * NN + e];
     TermVals tv;
     term_eval(md, eta, P.t, i, j, tv);
@@ -359,8 +378,10 @@ __global__ __launch_bounds__(256) void kd_gen_pass_kernel(ModelDev md, const dou
   const long NN = (long)md.N * md.N;
   const int tid = threadIdx.x;
   const long stride = (long)gridDim.x * blockDim.x;
-  for (long e = (long)blockIdx.x * blockDim.x + tid; e < NN; e += stride) {
-    const int i = (int)(e % md.N), j = (int)(e / md.N);
+  const long e0 = (long)blockIdx.x * blockDim.x + tid;
+  ElemWalk ij(e0, stride, md.N);
+  for (long e = e0; e < NN; e += stride, ij.step(md.N)) {
+    const int i = ij.i, j = ij.j;
     TermVals tv;
     term_eval(md, eta, P.t, i, j, tv);
     double acc[KD_PASS];

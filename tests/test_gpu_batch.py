@@ -112,6 +112,41 @@ def test_serving_results_same_alone_and_in_mix(rm):
     ex.close()
 
 
+def test_serving_largest_requests_same_alone_and_in_pool(rm):
+    """The serving mix's largest requests (D = 1038, both model kinds) run
+    side by side on the pool: every workspace at its largest size, and each
+    result bitwise that of the same request alone."""
+    from paper_2511_06407_amd import serving as sv
+    reqs = [sv.Request(0, 0.0, "gp_logistic", 1038, 1, seed=11),
+            sv.Request(1, 0.0, "mkl", 1038, 1, seed=12)]
+    C_, K = 2, 6
+    runs = []
+    for r in reqs:
+        spec, eps = sv.request_spec(r)
+        runs.append((spec, eps, dev(np.zeros(spec.D)), r))
+    alone = []
+    for spec, eps, q0, r in runs:
+        s, l, a, st = rm.Model(spec).chain(q0, eps, C_, K, r.n_moves, seed=r.seed,
+                                           stream_id=r.rid)
+        torch.cuda.synchronize()
+        alone.append((s.cpu().numpy(), l.cpu().numpy(), a.cpu().numpy()))
+    pool = rm.Pool(2)
+    models = [rm.Model(spec) for spec, *_ in runs]
+    jobs = [pool.submit(m, q0, eps, C_, K, r.n_moves, seed=r.seed, stream_id=r.rid)
+            for m, (spec, eps, q0, r) in zip(models, runs)]
+    for j in jobs:
+        assert pool.wait(j)
+    torch.cuda.synchronize()
+    for k, j in enumerate(jobs):
+        s, l, a = j.samples.cpu().numpy(), j.logpost.cpu().numpy(), j.accepted.cpu().numpy()
+        record("serving_largest", kind=reqs[k].kind, D=runs[k][0].D, samples=rel(s, alone[k][0]),
+               accepted=int(a.sum()))
+        assert np.all(np.isfinite(s))
+        assert np.array_equal(s, alone[k][0]) and np.array_equal(l, alone[k][1])
+        assert np.array_equal(a, alone[k][2])
+    pool.close()
+
+
 def test_graph_batch_equals_eager_chain_and_alone(rm):
     """Chains whose moves are replayed from captured graphs: identical to
     themselves admitted alone, and to the eager rmhmc_chain on the same model
