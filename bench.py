@@ -265,8 +265,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print("bench.py: this build runs on one GPU only; --gpus above 1 is not supported",
-              file=sys.stderr)
+        print("bench.py: the sampler runs on one GPU; --gpus above 1 is not supported "
+              "(chains and requests would be assigned to GPUs whole)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
