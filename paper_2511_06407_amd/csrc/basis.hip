@@ -44,14 +44,30 @@ __global__ void row_scale_kernel(int N, int Fa, double s, const double* __restri
 }
 
 // t_i = s * l'''_i * sum_j G[i + j N] Phi[i + j N]  (one thread per record)
-__global__ void rowdot_kernel(int N, int Fa, double s, const double* __restrict__ l3,
-                              const double* __restrict__ G, const double* __restrict__ Phi,
-                              double* __restrict__ t) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+// 64 rows per workgroup, their feature columns split over 16 phases (thread
+// (row r, phase g) takes columns g, g + 16, ...), the phases' sums added in
+// LDS in a fixed order: a few hundred rows still give every workgroup 16
+// waves with short loops.
+constexpr int RD_ROWS = 64, RD_PHASES = 16;
+__global__ __launch_bounds__(RD_ROWS * RD_PHASES) void rowdot_kernel(
+    int N, int Fa, double s, const double* __restrict__ l3, const double* __restrict__ G,
+    const double* __restrict__ Phi, double* __restrict__ t) {
+  __shared__ double sh[RD_PHASES][RD_ROWS];
+  const int r = threadIdx.x % RD_ROWS, g = threadIdx.x / RD_ROWS;
+  const int i = blockIdx.x * RD_ROWS + r;
   double acc = 0.0;
-  for (int j = 0; j < Fa; ++j) acc += G[i + (long)j * N] * Phi[i + (long)j * N];
-  t[i] = s * l3[i] * acc;
+  if (i < N) {
+#pragma unroll 4
+    for (int j = g; j < Fa; j += RD_PHASES) acc += G[i + (long)j * N] * Phi[i + (long)j * N];
+  }
+  sh[g][r] = acc;
+  __syncthreads();
+  if (g == 0 && i < N) {
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < RD_PHASES; ++q) sum += sh[q][r];
+    t[i] = s * l3[i] * sum;
+  }
 }
 
 // Derivatives of s_j = ln var_j in its hyperparameters: index (into q),
@@ -262,7 +278,8 @@ void basis_contract(const BasisDev& bd, double beta, const double* q, const doub
   g.B = W; g.ldb = Dp;
   g.C = G; g.ldc = N;
   gemm(g, st);
-  hipLaunchKernelGGL(rowdot_kernel, dim3(cdiv(N, 256)), dim3(256), 0, st, N, Fa, beta,
+  hipLaunchKernelGGL(rowdot_kernel, dim3(cdiv(N, RD_ROWS)), dim3(RD_ROWS * RD_PHASES), 0, st, N, Fa,
+                     beta,
                      (const double*)(likv + 3L * N), (const double*)G, (const double*)bd.Phi, t);
   RM_CHECK_LAUNCH();
   gemv(N, Fa, 1.0, bd.Phi, N, true, 0, t, 0, 0.0, v, 0, 1, st);   // v_ab = Phi' t
